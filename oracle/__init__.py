@@ -1,0 +1,211 @@
+"""FP64 CPU oracle for the DeGraF + robust local optical flow path -- TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import this package.
+It is a plain, slow, double-precision implementation written from the method's definitions
+(DeGraF-Flow, Section 2: "Point detection" with Eq. (1)-(2) and the centroid-selection rule;
+"Sparse point tracking" with the robust local flow reading documented in ``degraf_oracle.c``).
+It shares no code with the HIP library and never calls it.
+
+The C source is compiled with gcc into ``liboracle.so`` next to this file by :func:`build`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "degraf_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+ST_CONVERGED, ST_NOT_CONVERGED, ST_ILL_CONDITIONED, ST_OUT_OF_BOUNDS = 0, 1, 2, 3
+
+# Default tracker constants on the 0..255 intensity scale (same meaning as the library's
+# default options; the values are restated here, not imported).
+DEFAULTS = dict(sigma1=8.0, sigma2=32.0, eps_coarse=1e-2, eps_fine=1e-4, min_eig=1e-4 * 255.0 * 255.0)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C99, OpenMP for the loop over points)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-fopenmp", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64, f64 = ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    lib.or_detect_count.argtypes = [i32, i32, i32, i32]
+    lib.or_detect_count.restype = i64
+    lib.or_detect.argtypes = [P, i32, i32, i64, i32, i32, i32, P, P, P, i32]
+    lib.or_detect.restype = i64
+    lib.or_window_sums.argtypes = [P, i64, i32, i32, i32, i32, i32, P]
+    lib.or_window_sums.restype = None
+    lib.or_pyr_dims.argtypes = [i32, i32, i32, P]
+    lib.or_pyr_dims.restype = None
+    lib.or_pyr_down_u8.argtypes = [P, i32, i32, i64, P]
+    lib.or_pyr_down_u8.restype = i32
+    lib.or_pyr_down_f64.argtypes = [P, i32, i32, P]
+    lib.or_pyr_down_f64.restype = i32
+    lib.or_bilinear.argtypes = [P, i32, i32, f64, f64]
+    lib.or_bilinear.restype = f64
+    lib.or_psi.argtypes = [f64, f64, f64]
+    lib.or_psi.restype = f64
+    lib.or_dpsi.argtypes = [f64, f64, f64]
+    lib.or_dpsi.restype = f64
+    lib.or_track.argtypes = [P, P, i32, i32, i32, i64, P, i64, i32, i32, i32, f64, f64, f64, f64, f64,
+                             P, P, P, i32]
+    lib.or_track.restype = i32
+    lib.or_track_grad.argtypes = [P, P, i32, i32, P, i64, i32, f64, f64, P, P, P, P, P]
+    lib.or_track_grad.restype = i32
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def default_threads() -> int:
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def detect_count(W: int, H: int, window: int, stride: int) -> int:
+    return int(_load().or_detect_count(W, H, window, stride))
+
+
+def detect(img: np.ndarray, window: int, stride: int, m_mode: int = 0, threads: int | None = None):
+    """DeGraF key-points of a uint8 image.  Returns (points[N,2] float64 (x, y), sel[N] uint8,
+    response[N] float64)."""
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    H, W = img.shape
+    N = detect_count(W, H, window, stride)
+    pts = np.zeros((N, 2), np.float64)
+    sel = np.zeros(N, np.uint8)
+    resp = np.zeros(N, np.float64)
+    rc = _load().or_detect(_ptr(img), W, H, W, window, stride, m_mode, _ptr(pts), _ptr(sel), _ptr(resp),
+                           threads or default_threads())
+    if rc < 0:
+        raise ValueError(f"or_detect failed: {rc}")
+    return pts, sel, resp
+
+
+def window_sums(img: np.ndarray, x0: int, y0: int, w: int, h: int, m_mode: int = 0):
+    """Exact integer sums of one window (Eq. 1-2): (S_pos, sum i*I, sum j*I, S_neg,
+    sum i*(1+m-I), sum j*(1+m-I), m), i = row, j = column."""
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    H, W = img.shape
+    if not (0 <= x0 and 0 <= y0 and x0 + w <= W and y0 + h <= H):
+        raise ValueError("window outside the image")
+    out = np.zeros(7, np.int64)
+    _load().or_window_sums(_ptr(img), W, x0, y0, w, h, m_mode, _ptr(out))
+    return tuple(int(v) for v in out)
+
+
+def pyr_dims(W: int, H: int, levels: int):
+    d = np.zeros(2 * levels, np.int32)
+    _load().or_pyr_dims(W, H, levels, _ptr(d))
+    return [(int(d[2 * l]), int(d[2 * l + 1])) for l in range(levels)]
+
+
+def pyramid(img: np.ndarray, levels: int):
+    """List of pyramid levels: uint8 in -> uint8 levels; float in -> float64 levels."""
+    lib = _load()
+    out = []
+    if img.dtype == np.uint8:
+        cur = np.ascontiguousarray(img)
+        out.append(cur)
+        for _ in range(levels - 1):
+            H, W = cur.shape
+            nxt = np.zeros(((H + 1) // 2, (W + 1) // 2), np.uint8)
+            if lib.or_pyr_down_u8(_ptr(cur), W, H, W, _ptr(nxt)) != 0:
+                raise ValueError("or_pyr_down_u8 failed")
+            out.append(nxt)
+            cur = nxt
+    else:
+        cur = np.ascontiguousarray(img, dtype=np.float64)
+        out.append(cur)
+        for _ in range(levels - 1):
+            H, W = cur.shape
+            nxt = np.zeros(((H + 1) // 2, (W + 1) // 2), np.float64)
+            if lib.or_pyr_down_f64(_ptr(cur), W, H, _ptr(nxt)) != 0:
+                raise ValueError("or_pyr_down_f64 failed")
+            out.append(nxt)
+            cur = nxt
+    return out
+
+
+def bilinear(img: np.ndarray, x: float, y: float) -> float:
+    img = np.ascontiguousarray(img, dtype=np.float64)
+    H, W = img.shape
+    return float(_load().or_bilinear(_ptr(img), W, H, float(x), float(y)))
+
+
+def psi(r: float, sigma1: float, sigma2: float) -> float:
+    return float(_load().or_psi(float(r), float(sigma1), float(sigma2)))
+
+
+def dpsi(r: float, sigma1: float, sigma2: float) -> float:
+    return float(_load().or_dpsi(float(r), float(sigma1), float(sigma2)))
+
+
+def track(I0: np.ndarray, I1: np.ndarray, points: np.ndarray, levels: int, support: int, iters: int,
+          sigma1=DEFAULTS["sigma1"], sigma2=DEFAULTS["sigma2"], eps_coarse=DEFAULTS["eps_coarse"],
+          eps_fine=DEFAULTS["eps_fine"], min_eig=DEFAULTS["min_eig"], threads: int | None = None,
+          return_iters: bool = False):
+    """Track points from I0 to I1.  uint8 images use the uint8 pyramid; anything else is taken
+    as real-valued (float64).  Returns (flow[n,2] float64, status[n] uint8[, iters[n,L]])."""
+    if I0.shape != I1.shape:
+        raise ValueError("I0 and I1 must have the same shape")
+    if I0.dtype == np.uint8 and I1.dtype == np.uint8:
+        a0, a1, dt = np.ascontiguousarray(I0), np.ascontiguousarray(I1), 0
+    else:
+        a0 = np.ascontiguousarray(I0, dtype=np.float64)
+        a1 = np.ascontiguousarray(I1, dtype=np.float64)
+        dt = 1
+    H, W = a0.shape
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 2)
+    n = pts.shape[0]
+    flow = np.zeros((n, 2), np.float64)
+    st = np.zeros(n, np.uint8)
+    its = np.zeros((n, levels), np.int32) if return_iters else None
+    rc = _load().or_track(_ptr(a0), _ptr(a1), dt, W, H, W, _ptr(pts), n, levels, support, iters,
+                          sigma1, sigma2, eps_coarse, eps_fine, min_eig, _ptr(flow), _ptr(st), _ptr(its),
+                          threads or default_threads())
+    if rc != 0:
+        raise ValueError(f"or_track failed: {rc}")
+    if return_iters:
+        return flow, st, its
+    return flow, st
+
+
+def track_grad(I0: np.ndarray, I1: np.ndarray, points: np.ndarray, support: int, flow: np.ndarray,
+               status: np.ndarray, dflow: np.ndarray, sigma1=DEFAULTS["sigma1"], sigma2=DEFAULTS["sigma2"]):
+    """Implicit gradient (dL/dI0, dL/dI1) at the converged level-0 fixed point, for upstream
+    gradient dflow = dL/du (points with status != CONVERGED contribute nothing)."""
+    a0 = np.ascontiguousarray(I0, dtype=np.float64)
+    a1 = np.ascontiguousarray(I1, dtype=np.float64)
+    H, W = a0.shape
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 2)
+    fl = np.ascontiguousarray(flow, dtype=np.float64).reshape(-1, 2)
+    st = np.ascontiguousarray(status, dtype=np.uint8)
+    df = np.ascontiguousarray(dflow, dtype=np.float64).reshape(-1, 2)
+    dI0 = np.zeros((H, W), np.float64)
+    dI1 = np.zeros((H, W), np.float64)
+    rc = _load().or_track_grad(_ptr(a0), _ptr(a1), W, H, _ptr(pts), pts.shape[0], support, sigma1, sigma2,
+                               _ptr(fl), _ptr(st), _ptr(df), _ptr(dI0), _ptr(dI1))
+    if rc != 0:
+        raise ValueError(f"or_track_grad failed: {rc}")
+    return dI0, dI1

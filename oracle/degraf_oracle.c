@@ -1,0 +1,643 @@
+/*
+ * degraf_oracle.c -- plain FP64 CPU oracle for the DeGraF + robust local optical flow path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file exists so that the tests, the smoke check and the
+ * benchmark's CPU-baseline leg can compare the HIP library against a slow, obviously correct
+ * implementation written straight from the method's definitions.  No product code may link,
+ * load or call it, and it shares no code, header, table or helper with the HIP library.
+ *
+ * Sources of each computation (Stephenson, Breckon, Katramados, "DeGraF-Flow", 2019):
+ *   - Key-point detection: Section 2, "Point detection": sliding window with step delta,
+ *     Eq. (1) (positive centroid), Eq. (2) (negative centroid) and the rule after Eq. (2)
+ *     that keeps the centroid with the larger weight sum.
+ *   - Tracking: Section 2, "Sparse point tracking" (robust local optical flow, a Lucas-Kanade
+ *     derivative, Section 1).  The paper leaves the tracker's internals to its citation, so the
+ *     exact iteration below is the reading documented at each function: a coarse-to-fine
+ *     image pyramid and, per level, iteratively re-weighted Gauss-Newton on a 2x2 system under
+ *     a redescending robust norm.
+ *   - Gradient of the converged flow w.r.t. both images: implicit differentiation of the
+ *     level-0 fixed-point equation  F(u) = sum_k psi(r_k(u)) g_k = 0.
+ *
+ * Everything is double precision.  Loops follow the definitions one term at a time; the only
+ * parallelism is an OpenMP loop over independent windows or points.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_ERR_ARG (-1)
+#define OR_ERR_MEM (-2)
+
+#define OR_ST_CONVERGED 0
+#define OR_ST_NOT_CONVERGED 1
+#define OR_ST_ILL_CONDITIONED 2
+#define OR_ST_OUT_OF_BOUNDS 3
+
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* ------------------------------------------------------------------------------------------ */
+/* DeGraF detection (Section 2 "Point detection", Eq. 1-2)                                     */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Number of window positions.  Reading of "a sliding window is passed over the image with step
+ * delta": windows lie fully inside the image, origins at (kx*delta, ky*delta) from (0, 0). */
+int64_t or_detect_count(int W, int H, int win, int stride)
+{
+    if (win <= 0 || stride <= 0 || W < win || H < win) return 0;
+    return (int64_t)((W - win) / stride + 1) * (int64_t)((H - win) / stride + 1);
+}
+
+/*
+ * The two weighted sums of one w x h window at (x0, y0) (Eq. 1 and Eq. 2), as exact integers:
+ *   out[0] = S_pos = sum I,          out[1] = sum i*I (row),          out[2] = sum j*I (column)
+ *   out[3] = S_neg = sum (1+m-I),    out[4] = sum i*(1+m-I),          out[5] = sum j*(1+m-I)
+ *   out[6] = m
+ * m_mode 0: m is the window maximum (the subscript of max in Eq. 2);
+ * m_mode 1: m = 255 (the alternative reading of "normalised 1 -> 256").
+ */
+void or_window_sums(const uint8_t *img, int64_t pitch, int x0, int y0, int w, int h, int m_mode,
+                    int64_t out[7])
+{
+    int64_t m = 0;
+    for (int i = 0; i < h; ++i)
+        for (int j = 0; j < w; ++j) {
+            int64_t v = img[(int64_t)(y0 + i) * pitch + (x0 + j)];
+            if (v > m) m = v;
+        }
+    if (m_mode == 1) m = 255;
+    int64_t s_pos = 0, i_pos = 0, j_pos = 0;
+    int64_t s_neg = 0, i_neg = 0, j_neg = 0;
+    for (int i = 0; i < h; ++i)
+        for (int j = 0; j < w; ++j) {
+            int64_t v = img[(int64_t)(y0 + i) * pitch + (x0 + j)];
+            int64_t vn = 1 + m - v;
+            s_pos += v;
+            i_pos += (int64_t)i * v;
+            j_pos += (int64_t)j * v;
+            s_neg += vn;
+            i_neg += (int64_t)i * vn;
+            j_neg += (int64_t)j * vn;
+        }
+    out[0] = s_pos; out[1] = i_pos; out[2] = j_pos;
+    out[3] = s_neg; out[4] = i_neg; out[5] = j_neg;
+    out[6] = m;
+}
+
+/*
+ * One key-point per window, in row-major window order (window n = ky*nx + kx).
+ *   img      : uint8 grey image, row y at img + y*pitch
+ *   m_mode   : see or_window_sums
+ *   pts      : out [N][2] = (x, y), x = column, pixel centres at integer coordinates
+ *   sel      : out [N] (nullable) 1 when the negative centroid was kept
+ *   resp     : out [N] (nullable) |C_pos - C_neg|, with C_pos := window centre when S_pos = 0
+ * Returns N, or a negative code.
+ */
+int64_t or_detect(const uint8_t *img, int W, int H, int64_t pitch, int win, int stride, int m_mode,
+                  double *pts, uint8_t *sel, double *resp, int nthreads)
+{
+    if (!img || !pts || win <= 0 || stride <= 0 || W <= 0 || H <= 0 || pitch < W) return OR_ERR_ARG;
+    int64_t N = or_detect_count(W, H, win, stride);
+    if (N == 0) return 0;
+    const int nx = (W - win) / stride + 1;
+    const int w = win, h = win;
+    if (nthreads < 1) nthreads = 1;
+
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int64_t n = 0; n < N; ++n) {
+        const int kx = (int)(n % nx), ky = (int)(n / nx);
+        const int x0 = kx * stride, y0 = ky * stride;
+        int64_t S[7];
+        or_window_sums(img, pitch, x0, y0, w, h, m_mode, S);
+        const int64_t s_pos = S[0], s_neg = S[3];
+
+        /* Centroids as (column, row) offsets inside the window: Eq. (1) gives the row
+         * coordinate from sum i*I and the column coordinate from sum j*I. */
+        double cpos_x, cpos_y;
+        if (s_pos > 0) {
+            cpos_x = (double)S[2] / (double)s_pos;
+            cpos_y = (double)S[1] / (double)s_pos;
+        } else { /* all-black window: C_pos undefined; use the window centre for the response */
+            cpos_x = 0.5 * (w - 1);
+            cpos_y = 0.5 * (h - 1);
+        }
+        /* s_neg >= w*h >= 1 because every weight 1 + m - I is at least 1 */
+        double cneg_x = (double)S[5] / (double)s_neg;
+        double cneg_y = (double)S[4] / (double)s_neg;
+
+        /* Keep the centroid with the larger sum; a tie keeps the positive centroid. */
+        int neg = s_neg > s_pos;
+        pts[2 * n + 0] = (double)x0 + (neg ? cneg_x : cpos_x);
+        pts[2 * n + 1] = (double)y0 + (neg ? cneg_y : cpos_y);
+        if (sel) sel[n] = (uint8_t)neg;
+        if (resp) resp[n] = hypot(cpos_x - cneg_x, cpos_y - cneg_y);
+    }
+    return N;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Image pyramid (the tracker is pyramidal; the paper gives no filter, this is the reading)   */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Level l+1 has size ceil(W_l / 2) x ceil(H_l / 2); dims[2l] = W_l, dims[2l+1] = H_l. */
+void or_pyr_dims(int W, int H, int levels, int *dims)
+{
+    for (int l = 0; l < levels; ++l) {
+        dims[2 * l] = W;
+        dims[2 * l + 1] = H;
+        W = (W + 1) / 2;
+        H = (H + 1) / 2;
+    }
+}
+
+static const int k5[5] = {1, 4, 6, 4, 1};
+
+/* One reduction step on a uint8 image: full 5x5 binomial sum with replicated borders, sampled at
+ * even pixels, rounded half-up with integer arithmetic: (sum + 128) >> 8. */
+int or_pyr_down_u8(const uint8_t *src, int W, int H, int64_t pitch, uint8_t *dst)
+{
+    if (!src || !dst || W <= 0 || H <= 0 || pitch < W) return OR_ERR_ARG;
+    const int W2 = (W + 1) / 2, H2 = (H + 1) / 2;
+    for (int y = 0; y < H2; ++y)
+        for (int x = 0; x < W2; ++x) {
+            int64_t sum = 0;
+            for (int b = -2; b <= 2; ++b)
+                for (int a = -2; a <= 2; ++a) {
+                    int yy = clampi(2 * y + b, 0, H - 1), xx = clampi(2 * x + a, 0, W - 1);
+                    sum += (int64_t)k5[a + 2] * k5[b + 2] * src[(int64_t)yy * pitch + xx];
+                }
+            dst[(int64_t)y * W2 + x] = (uint8_t)((sum + 128) >> 8);
+        }
+    return OR_OK;
+}
+
+/* The same reduction on a real-valued image, exact division by 256 (no rounding). */
+int or_pyr_down_f64(const double *src, int W, int H, double *dst)
+{
+    if (!src || !dst || W <= 0 || H <= 0) return OR_ERR_ARG;
+    const int W2 = (W + 1) / 2, H2 = (H + 1) / 2;
+    for (int y = 0; y < H2; ++y)
+        for (int x = 0; x < W2; ++x) {
+            double sum = 0.0;
+            for (int b = -2; b <= 2; ++b)
+                for (int a = -2; a <= 2; ++a) {
+                    int yy = clampi(2 * y + b, 0, H - 1), xx = clampi(2 * x + a, 0, W - 1);
+                    sum += (double)(k5[a + 2] * k5[b + 2]) * src[(int64_t)yy * W + xx];
+                }
+            dst[(int64_t)y * W2 + x] = sum / 256.0;
+        }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Sampling helpers                                                                           */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Bilinear interpolation with each of the four taps clamped to the image (replicated border).
+ * Pixel centres are at integer coordinates.  Non-finite coordinates give NaN. */
+double or_bilinear(const double *I, int W, int H, double x, double y)
+{
+    if (!isfinite(x) || !isfinite(y)) return NAN;
+    double xf = floor(x), yf = floor(y);
+    double fx = x - xf, fy = y - yf;
+    /* Far outside the image every tap clamps to the border, so limiting the integer part first
+     * changes nothing and keeps the conversion to int defined. */
+    if (xf < -2.0) xf = -2.0;
+    if (xf > (double)W) xf = (double)W;
+    if (yf < -2.0) yf = -2.0;
+    if (yf > (double)H) yf = (double)H;
+    int x0 = (int)xf, y0 = (int)yf;
+    int xa = clampi(x0, 0, W - 1), xb = clampi(x0 + 1, 0, W - 1);
+    int ya = clampi(y0, 0, H - 1), yb = clampi(y0 + 1, 0, H - 1);
+    double i00 = I[(int64_t)ya * W + xa], i10 = I[(int64_t)ya * W + xb];
+    double i01 = I[(int64_t)yb * W + xa], i11 = I[(int64_t)yb * W + xb];
+    return (1.0 - fy) * ((1.0 - fx) * i00 + fx * i10) + fy * ((1.0 - fx) * i01 + fx * i11);
+}
+
+/* Central-difference image gradient on the integer grid with replicated border. */
+static void gradients(const double *I, int W, int H, double *gx, double *gy)
+{
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            int xl = clampi(x - 1, 0, W - 1), xr = clampi(x + 1, 0, W - 1);
+            int yu = clampi(y - 1, 0, H - 1), yd = clampi(y + 1, 0, H - 1);
+            gx[(int64_t)y * W + x] = 0.5 * (I[(int64_t)y * W + xr] - I[(int64_t)y * W + xl]);
+            gy[(int64_t)y * W + x] = 0.5 * (I[(int64_t)yd * W + x] - I[(int64_t)yu * W + x]);
+        }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Robust norm                                                                                */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Influence function of the robust norm: a continuous, piecewise-linear, redescending
+ * (Hampel-type) function with thresholds s1 <= s2 in intensity units:
+ *     psi(r) = r                                   |r| <= s1
+ *            = sign(r) * s1 * (s2 - |r|) / (s2 - s1)  s1 < |r| < s2
+ *            = 0                                   |r| >= s2
+ * s1 = s2 = +inf is the least-squares (plain Lucas-Kanade) limit. */
+double or_psi(double r, double s1, double s2)
+{
+    double a = fabs(r);
+    if (a <= s1) return r;
+    if (a >= s2) return 0.0;
+    return copysign(s1 * (s2 - a) / (s2 - s1), r);
+}
+
+/* Derivative of psi, band by band (used by the implicit gradient). */
+double or_dpsi(double r, double s1, double s2)
+{
+    double a = fabs(r);
+    if (a <= s1) return 1.0;
+    if (a >= s2) return 0.0;
+    return -s1 / (s2 - s1);
+}
+
+/* IRLS weight psi(r)/r, with the limit 1 at r = 0. */
+static double irls_weight(double r, double s1, double s2)
+{
+    if (r == 0.0) return 1.0;
+    return or_psi(r, s1, s2) / r;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Pyramids of both images as double arrays                                                   */
+/* ------------------------------------------------------------------------------------------ */
+
+typedef struct {
+    int levels;
+    int W[32], H[32];
+    double *img[32]; /* level images */
+    double *gx[32], *gy[32];
+} pyr_t;
+
+static void pyr_free(pyr_t *p)
+{
+    for (int l = 0; l < p->levels; ++l) {
+        free(p->img[l]);
+        free(p->gx[l]);
+        free(p->gy[l]);
+    }
+}
+
+/* dtype 0: uint8 input, levels are uint8 images (integer rounding), converted to double;
+ * dtype 1: double input, levels are exact double reductions. */
+static int pyr_build(pyr_t *p, const void *src, int dtype, int W, int H, int64_t pitch, int levels,
+                     int with_grad)
+{
+    memset(p, 0, sizeof(*p));
+    p->levels = levels;
+    int dims[64];
+    or_pyr_dims(W, H, levels, dims);
+    uint8_t *u8prev = NULL, *u8cur = NULL;
+    for (int l = 0; l < levels; ++l) {
+        int Wl = dims[2 * l], Hl = dims[2 * l + 1];
+        p->W[l] = Wl;
+        p->H[l] = Hl;
+        p->img[l] = (double *)malloc(sizeof(double) * (size_t)Wl * Hl);
+        if (!p->img[l]) return OR_ERR_MEM;
+        if (dtype == 0) {
+            if (l == 0) {
+                u8cur = (uint8_t *)malloc((size_t)Wl * Hl);
+                if (!u8cur) return OR_ERR_MEM;
+                for (int y = 0; y < Hl; ++y)
+                    memcpy(u8cur + (size_t)y * Wl, (const uint8_t *)src + (int64_t)y * pitch, (size_t)Wl);
+            } else {
+                u8cur = (uint8_t *)malloc((size_t)Wl * Hl);
+                if (!u8cur) return OR_ERR_MEM;
+                or_pyr_down_u8(u8prev, dims[2 * l - 2], dims[2 * l - 1], dims[2 * l - 2], u8cur);
+            }
+            for (int64_t i = 0; i < (int64_t)Wl * Hl; ++i) p->img[l][i] = (double)u8cur[i];
+            free(u8prev);
+            u8prev = u8cur;
+        } else {
+            if (l == 0) {
+                for (int y = 0; y < Hl; ++y)
+                    for (int x = 0; x < Wl; ++x)
+                        p->img[l][(int64_t)y * Wl + x] = ((const double *)src)[(int64_t)y * pitch + x];
+            } else {
+                or_pyr_down_f64(p->img[l - 1], dims[2 * l - 2], dims[2 * l - 1], p->img[l]);
+            }
+        }
+        if (with_grad) {
+            p->gx[l] = (double *)malloc(sizeof(double) * (size_t)Wl * Hl);
+            p->gy[l] = (double *)malloc(sizeof(double) * (size_t)Wl * Hl);
+            if (!p->gx[l] || !p->gy[l]) return OR_ERR_MEM;
+            gradients(p->img[l], Wl, Hl, p->gx[l], p->gy[l]);
+        }
+    }
+    free(u8prev);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Tracking                                                                                   */
+/* ------------------------------------------------------------------------------------------ */
+
+typedef struct {
+    double sigma1, sigma2;   /* robust-norm thresholds, intensity units */
+    double eps_coarse;       /* stop a level > 0 when |delta| < eps_coarse (px of that level) */
+    double eps_fine;         /* stop level 0 when |delta| < eps_fine */
+    double min_eig;          /* ill-conditioned when lambda_min(G0) / s^2 < min_eig */
+} or_opts;
+
+/*
+ * Track one point p (level-0 pixel coordinates) from I0 to I1.
+ * Reading of the robust local flow iteration (the paper cites it without restating it):
+ *   g = 0 at the coarsest level.  For l = L-1 .. 0, with p_l = p / 2^l and support offsets
+ *   k in [-r, r]^2 (s = 2r + 1):
+ *     T_k = B(I0_l, p_l + k), g_k = (B(Gx_l, p_l + k), B(Gy_l, p_l + k)), G0 = sum g_k g_k^T.
+ *     If lambda_min(G0)/s^2 < min_eig the point is ill-conditioned: u = 2^l g, stop.
+ *     d = 0; repeat up to iters times:
+ *        r_k = B(I1_l, p_l + k + g + d) - T_k,  w_k = psi(r_k)/r_k,
+ *        Gw = sum w_k g_k g_k^T,  b = -sum w_k r_k g_k,
+ *        if det Gw <= 1e-6 det G0 (or is not a number), use w = 1 for this step,
+ *        delta = Gw^-1 b,  d += delta,  stop the level when |delta|_2 < eps_l.
+ *     A non-finite delta ends the point (not converged).  For l > 0: g = 2 (g + d).
+ *   u = g + d.  Status: ill-conditioned, else not converged if level 0 did not stop on eps,
+ *   else out of bounds if p + u leaves [0, W-1] x [0, H-1], else converged.
+ * Points outside the image (or not finite) are out of bounds with u = 0.
+ */
+static void track_point(const pyr_t *P0, const pyr_t *P1, double px, double py, int L, int s,
+                        int iters, const or_opts *o, double *ux, double *uy, uint8_t *st,
+                        int32_t *it_count)
+{
+    const int r = s / 2;
+    const int W = P0->W[0], H = P0->H[0];
+    if (!(isfinite(px) && isfinite(py)) || px < 0.0 || py < 0.0 || px > W - 1 || py > H - 1) {
+        *ux = 0.0;
+        *uy = 0.0;
+        *st = OR_ST_OUT_OF_BOUNDS;
+        return;
+    }
+    const int npix = s * s;
+    double *T = (double *)malloc(sizeof(double) * npix);
+    double *gxk = (double *)malloc(sizeof(double) * npix);
+    double *gyk = (double *)malloc(sizeof(double) * npix);
+
+    double gX = 0.0, gY = 0.0; /* guess carried from the coarser level, in level-l pixels */
+    double dX = 0.0, dY = 0.0;
+    int conv = 0;
+    int status = -1;
+    for (int l = L - 1; l >= 0; --l) {
+        const double scale = ldexp(1.0, -l);
+        const double plx = px * scale, ply = py * scale;
+        const int Wl = P0->W[l], Hl = P0->H[l];
+
+        /* template and its gradient */
+        double a = 0.0, b = 0.0, c = 0.0; /* G0 = [[a, b], [b, c]] */
+        for (int ky = -r; ky <= r; ++ky)
+            for (int kx = -r; kx <= r; ++kx) {
+                int k = (ky + r) * s + (kx + r);
+                double x = plx + kx, y = ply + ky;
+                T[k] = or_bilinear(P0->img[l], Wl, Hl, x, y);
+                gxk[k] = or_bilinear(P0->gx[l], Wl, Hl, x, y);
+                gyk[k] = or_bilinear(P0->gy[l], Wl, Hl, x, y);
+                a += gxk[k] * gxk[k];
+                b += gxk[k] * gyk[k];
+                c += gyk[k] * gyk[k];
+            }
+        const double lam_min = 0.5 * (a + c) - sqrt(0.25 * (a - c) * (a - c) + b * b);
+        if (!(lam_min / (double)npix >= o->min_eig)) {
+            *ux = ldexp(gX, l);
+            *uy = ldexp(gY, l);
+            status = OR_ST_ILL_CONDITIONED;
+            break;
+        }
+        const double det0 = a * c - b * b;
+        const double eps = (l > 0) ? o->eps_coarse : o->eps_fine;
+
+        dX = 0.0;
+        dY = 0.0;
+        conv = 0;
+        int bad = 0;
+        int it = 0;
+        for (it = 1; it <= iters; ++it) {
+            double A = 0.0, B = 0.0, C = 0.0, bx = 0.0, by = 0.0;
+            for (int ky = -r; ky <= r; ++ky)
+                for (int kx = -r; kx <= r; ++kx) {
+                    int k = (ky + r) * s + (kx + r);
+                    double J = or_bilinear(P1->img[l], Wl, Hl, plx + kx + gX + dX, ply + ky + gY + dY);
+                    double res = J - T[k];
+                    double w = irls_weight(res, o->sigma1, o->sigma2);
+                    A += w * gxk[k] * gxk[k];
+                    B += w * gxk[k] * gyk[k];
+                    C += w * gyk[k] * gyk[k];
+                    bx -= w * res * gxk[k];
+                    by -= w * res * gyk[k];
+                }
+            double det = A * C - B * B;
+            if (!(det > 1e-6 * det0)) { /* too many down-weighted pixels: least-squares step */
+                A = a;
+                B = b;
+                C = c;
+                bx = 0.0;
+                by = 0.0;
+                for (int ky = -r; ky <= r; ++ky)
+                    for (int kx = -r; kx <= r; ++kx) {
+                        int k = (ky + r) * s + (kx + r);
+                        double J = or_bilinear(P1->img[l], Wl, Hl, plx + kx + gX + dX, ply + ky + gY + dY);
+                        double res = J - T[k];
+                        bx -= res * gxk[k];
+                        by -= res * gyk[k];
+                    }
+                det = det0;
+            }
+            double stepX = (C * bx - B * by) / det;
+            double stepY = (A * by - B * bx) / det;
+            if (!(isfinite(stepX) && isfinite(stepY))) {
+                bad = 1;
+                break;
+            }
+            dX += stepX;
+            dY += stepY;
+            if (sqrt(stepX * stepX + stepY * stepY) < eps) {
+                conv = 1;
+                break;
+            }
+        }
+        if (it_count) it_count[L - 1 - l] = (it > iters) ? iters : it;
+        if (bad) {
+            *ux = NAN;
+            *uy = NAN;
+            status = OR_ST_NOT_CONVERGED;
+            break;
+        }
+        if (l > 0) {
+            gX = 2.0 * (gX + dX);
+            gY = 2.0 * (gY + dY);
+        }
+    }
+    if (status < 0) {
+        *ux = gX + dX;
+        *uy = gY + dY;
+        if (!conv)
+            status = OR_ST_NOT_CONVERGED;
+        else {
+            double qx = px + *ux, qy = py + *uy;
+            status = (qx >= 0.0 && qy >= 0.0 && qx <= W - 1 && qy <= H - 1) ? OR_ST_CONVERGED
+                                                                            : OR_ST_OUT_OF_BOUNDS;
+        }
+    }
+    *st = (uint8_t)status;
+    free(T);
+    free(gxk);
+    free(gyk);
+}
+
+/*
+ * Track n points.  I0/I1: dtype 0 = uint8 (row pitch in bytes), 1 = double (pitch in elements).
+ * flow: out [n][2];  status: out [n];  iters_out: nullable [n][L], iterations run per level,
+ * coarsest level first (0 where the point stopped before reaching that level).
+ */
+int or_track(const void *I0, const void *I1, int dtype, int W, int H, int64_t pitch, const double *pts,
+             int64_t n, int levels, int support, int iters, double sigma1, double sigma2,
+             double eps_coarse, double eps_fine, double min_eig, double *flow, uint8_t *status,
+             int32_t *iters_out, int nthreads)
+{
+    if (!I0 || !I1 || (n > 0 && (!pts || !flow || !status))) return OR_ERR_ARG;
+    if (W <= 0 || H <= 0 || levels < 1 || levels > 16 || support < 1 || (support % 2) == 0 || iters < 1)
+        return OR_ERR_ARG;
+    if (dtype != 0 && dtype != 1) return OR_ERR_ARG;
+    if (nthreads < 1) nthreads = 1;
+    or_opts o = {sigma1, sigma2, eps_coarse, eps_fine, min_eig};
+    pyr_t P0, P1;
+    int rc0 = pyr_build(&P0, I0, dtype, W, H, pitch, levels, 1);
+    int rc1 = pyr_build(&P1, I1, dtype, W, H, pitch, levels, 0);
+    if (rc0 != OR_OK || rc1 != OR_OK) {
+        pyr_free(&P0);
+        pyr_free(&P1);
+        return OR_ERR_MEM;
+    }
+    if (iters_out) memset(iters_out, 0, sizeof(int32_t) * (size_t)n * levels);
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        track_point(&P0, &P1, pts[2 * i], pts[2 * i + 1], levels, support, iters, &o, &flow[2 * i],
+                    &flow[2 * i + 1], &status[i], iters_out ? &iters_out[i * levels] : NULL);
+    }
+    pyr_free(&P0);
+    pyr_free(&P1);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Gradient of the converged flow w.r.t. both images (implicit differentiation)               */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Bilinear taps: indices and weights of the four (clamped) samples, and the analytic derivative
+ * of the interpolant w.r.t. x and y inside the cell. */
+static void bilinear_taps(int W, int H, double x, double y, int64_t idx[4], double wt[4], int cx[4],
+                          int cy[4], double *fx_out, double *fy_out)
+{
+    double xf = floor(x), yf = floor(y);
+    double fx = x - xf, fy = y - yf;
+    if (xf < -2.0) xf = -2.0;
+    if (xf > (double)W) xf = (double)W;
+    if (yf < -2.0) yf = -2.0;
+    if (yf > (double)H) yf = (double)H;
+    int x0 = (int)xf, y0 = (int)yf;
+    int xa = clampi(x0, 0, W - 1), xb = clampi(x0 + 1, 0, W - 1);
+    int ya = clampi(y0, 0, H - 1), yb = clampi(y0 + 1, 0, H - 1);
+    cx[0] = xa; cy[0] = ya; wt[0] = (1.0 - fx) * (1.0 - fy);
+    cx[1] = xb; cy[1] = ya; wt[1] = fx * (1.0 - fy);
+    cx[2] = xa; cy[2] = yb; wt[2] = (1.0 - fx) * fy;
+    cx[3] = xb; cy[3] = yb; wt[3] = fx * fy;
+    for (int t = 0; t < 4; ++t) idx[t] = (int64_t)cy[t] * W + cx[t];
+    *fx_out = fx;
+    *fy_out = fy;
+}
+
+/*
+ * For every point with status CONVERGED, with upstream gradient lambda = dflow[i] (= dL/du):
+ *   J = dF/du = sum_k psi'(r_k) g_k (grad B(I1, p + k + u))^T        (2x2, not symmetric)
+ *   solve J^T mu = lambda
+ *   dL/dI1[q] = - sum_k psi'(r_k) (mu . g_k) beta_k(q)
+ *   dL/dI0[q] = + sum_k psi'(r_k) (mu . g_k) alpha_k(q) - sum_k psi(r_k) mu . dg_k/dI0[q]
+ * where alpha_k, beta_k are the bilinear tap weights of the template sample and of the I1
+ * sample, and g_k is the bilinear sample of the central-difference gradient image, so
+ * dg_k/dI0 is that difference stencil pushed through alpha_k.  Only the level-0 images
+ * enter: coarser levels decide which fixed point is reached but not its local dependence.
+ * Results are ADDED to dI0 and dI1 ([H][W] doubles).  I0, I1 are double images, pitch W.
+ */
+int or_track_grad(const double *I0, const double *I1, int W, int H, const double *pts, int64_t n, int support,
+                  double sigma1, double sigma2, const double *flow, const uint8_t *status,
+                  const double *dflow, double *dI0, double *dI1)
+{
+    if (!I0 || !I1 || W <= 0 || H <= 0 || support < 1 || (support % 2) == 0) return OR_ERR_ARG;
+    if (n > 0 && (!pts || !flow || !status || !dflow || !dI0 || !dI1)) return OR_ERR_ARG;
+    const int r = support / 2;
+    double *gx = (double *)malloc(sizeof(double) * (size_t)W * H);
+    double *gy = (double *)malloc(sizeof(double) * (size_t)W * H);
+    if (!gx || !gy) {
+        free(gx);
+        free(gy);
+        return OR_ERR_MEM;
+    }
+    gradients(I0, W, H, gx, gy);
+
+    for (int64_t i = 0; i < n; ++i) {
+        if (status[i] != OR_ST_CONVERGED) continue;
+        const double px = pts[2 * i], py = pts[2 * i + 1];
+        const double ux = flow[2 * i], uy = flow[2 * i + 1];
+
+        /* J = sum psi' g (grad J)^T */
+        double J00 = 0.0, J01 = 0.0, J10 = 0.0, J11 = 0.0;
+        for (int ky = -r; ky <= r; ++ky)
+            for (int kx = -r; kx <= r; ++kx) {
+                double x = px + kx, y = py + ky;
+                double T = or_bilinear(I0, W, H, x, y);
+                double g0 = or_bilinear(gx, W, H, x, y), g1 = or_bilinear(gy, W, H, x, y);
+                int64_t idx[4]; double wt[4]; int cx[4], cy[4]; double fx, fy;
+                bilinear_taps(W, H, x + ux, y + uy, idx, wt, cx, cy, &fx, &fy);
+                double Jv = wt[0] * I1[idx[0]] + wt[1] * I1[idx[1]] + wt[2] * I1[idx[2]] + wt[3] * I1[idx[3]];
+                double djx = (1.0 - fy) * (I1[idx[1]] - I1[idx[0]]) + fy * (I1[idx[3]] - I1[idx[2]]);
+                double djy = (1.0 - fx) * (I1[idx[2]] - I1[idx[0]]) + fx * (I1[idx[3]] - I1[idx[1]]);
+                double dp = or_dpsi(Jv - T, sigma1, sigma2);
+                J00 += dp * g0 * djx;
+                J01 += dp * g0 * djy;
+                J10 += dp * g1 * djx;
+                J11 += dp * g1 * djy;
+            }
+        /* J^T mu = lambda */
+        const double lx = dflow[2 * i], ly = dflow[2 * i + 1];
+        const double det = J00 * J11 - J01 * J10;
+        if (!(det != 0.0) || !isfinite(det)) continue;
+        /* J^T = [[J00, J10], [J01, J11]] */
+        const double mux = (J11 * lx - J10 * ly) / det;
+        const double muy = (J00 * ly - J01 * lx) / det;
+
+        for (int ky = -r; ky <= r; ++ky)
+            for (int kx = -r; kx <= r; ++kx) {
+                double x = px + kx, y = py + ky;
+                int64_t ia[4]; double wa[4]; int ax[4], ay[4]; double fxa, fya;
+                bilinear_taps(W, H, x, y, ia, wa, ax, ay, &fxa, &fya);
+                double T = wa[0] * I0[ia[0]] + wa[1] * I0[ia[1]] + wa[2] * I0[ia[2]] + wa[3] * I0[ia[3]];
+                double g0 = wa[0] * gx[ia[0]] + wa[1] * gx[ia[1]] + wa[2] * gx[ia[2]] + wa[3] * gx[ia[3]];
+                double g1 = wa[0] * gy[ia[0]] + wa[1] * gy[ia[1]] + wa[2] * gy[ia[2]] + wa[3] * gy[ia[3]];
+                int64_t ib[4]; double wb[4]; int bxx[4], byy[4]; double fxb, fyb;
+                bilinear_taps(W, H, x + ux, y + uy, ib, wb, bxx, byy, &fxb, &fyb);
+                double Jv = wb[0] * I1[ib[0]] + wb[1] * I1[ib[1]] + wb[2] * I1[ib[2]] + wb[3] * I1[ib[3]];
+                double res = Jv - T;
+                double ps = or_psi(res, sigma1, sigma2);
+                double dp = or_dpsi(res, sigma1, sigma2);
+                double mg = mux * g0 + muy * g1;
+                for (int t = 0; t < 4; ++t) {
+                    dI1[ib[t]] -= dp * mg * wb[t];
+                    dI0[ia[t]] += dp * mg * wa[t];
+                    /* g_k.x = sum_t alpha_t Gx[tap t], Gx[y][x] = (I0[y][x+1] - I0[y][x-1]) / 2 (clamped) */
+                    int xr = clampi(ax[t] + 1, 0, W - 1), xl = clampi(ax[t] - 1, 0, W - 1);
+                    int yd = clampi(ay[t] + 1, 0, H - 1), yu = clampi(ay[t] - 1, 0, H - 1);
+                    double cxw = -ps * mux * wa[t] * 0.5;
+                    double cyw = -ps * muy * wa[t] * 0.5;
+                    dI0[(int64_t)ay[t] * W + xr] += cxw;
+                    dI0[(int64_t)ay[t] * W + xl] -= cxw;
+                    dI0[(int64_t)yd * W + ax[t]] += cyw;
+                    dI0[(int64_t)yu * W + ax[t]] -= cyw;
+                }
+            }
+    }
+    free(gx);
+    free(gy);
+    return OR_OK;
+}

@@ -1,0 +1,280 @@
+"""Pins of the oracle's robust local optical flow tracker (DeGraF-Flow Section 2, "Sparse point
+tracking"; the tracker is a Lucas-Kanade derivative, Section 1) against exact recoveries,
+special cases, invariants and an independent least-squares pyramidal Lucas-Kanade."""
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import oracle
+from brute import lk_pyramidal
+from paper_1901_09971_amd import synth
+
+INF = float("inf")
+
+
+# ---------------------------------------------------------------------------------------------
+# robust norm and sampling
+# ---------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("s1,s2", [(8.0, 32.0), (1.0, 2.0), (5.0, 100.0)])
+def test_psi_shape(s1, s2):
+    # identity inside, zero outside, continuous at both thresholds, odd, linear in between
+    for r in np.linspace(-s1, s1, 11):
+        assert oracle.psi(r, s1, s2) == r
+    for r in (s2, s2 + 1, 10 * s2, -s2, -s2 - 3):
+        assert oracle.psi(r, s1, s2) == 0.0
+    e = 1e-9 * s2
+    assert abs(oracle.psi(s1 + e, s1, s2) - s1) < 1e-6
+    assert abs(oracle.psi(s2 - e, s1, s2)) < 1e-6
+    rs = np.linspace(s1 + 1e-3, s2 - 1e-3, 7)
+    vals = np.array([oracle.psi(r, s1, s2) for r in rs])
+    assert np.allclose(np.diff(vals) / np.diff(rs), -s1 / (s2 - s1), rtol=1e-9, atol=0)
+    for r in (0.3, s1 + 0.5, s2 - 0.1, 3 * s2):
+        assert oracle.psi(-r, s1, s2) == -oracle.psi(r, s1, s2)
+
+
+@pytest.mark.parametrize("s1,s2", [(8.0, 32.0), (2.0, 3.0)])
+def test_dpsi_is_derivative(s1, s2):
+    h = 1e-6
+    for r in (-40.0, -20.0, -5.0, -0.1, 0.0, 0.2, 4.0, 9.0, 20.0, 31.0, 33.0):
+        if min(abs(abs(r) - s1), abs(abs(r) - s2)) < 1e-3:
+            continue
+        fd = (oracle.psi(r + h, s1, s2) - oracle.psi(r - h, s1, s2)) / (2 * h)
+        assert abs(oracle.dpsi(r, s1, s2) - fd) < 1e-6
+
+
+def test_psi_least_squares_limit():
+    for r in (-1e6, -3.0, 0.0, 2.5, 1e9):
+        assert oracle.psi(r, INF, INF) == r
+
+
+def test_bilinear_exact_on_span_and_clamped():
+    H, W = 12, 15
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    f = lambda x, y: 3.0 - 0.7 * x + 1.1 * y + 0.25 * x * y
+    img = f(xx, yy)
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        x, y = rng.uniform(0, W - 1), rng.uniform(0, H - 1)
+        assert abs(oracle.bilinear(img, x, y) - f(x, y)) < 1e-12
+    # outside the image each tap clamps: equals the border value / border interpolation
+    assert oracle.bilinear(img, -5.0, 3.0) == img[3, 0]
+    assert oracle.bilinear(img, W + 7.5, H + 2.0) == img[H - 1, W - 1]
+    assert abs(oracle.bilinear(img, -3.0, 2.5) - 0.5 * (img[2, 0] + img[3, 0])) < 1e-12
+    assert np.isnan(oracle.bilinear(img, np.nan, 1.0))
+
+
+# ---------------------------------------------------------------------------------------------
+# tracking
+# ---------------------------------------------------------------------------------------------
+
+def _canvas_pair(W, H, t, seed=3, sigma=2.0, margin=24):
+    """I0 and I1(x, y) = I0(x - tx, y - ty) for integer t, both cut from one larger canvas, so
+    the shift is exact everywhere (no border effects)."""
+    rng = np.random.default_rng(seed)
+    C = synth.smoothed_noise(rng, W + 2 * margin, H + 2 * margin, sigma)
+    C = np.rint(C).astype(np.uint8)
+    tx, ty = t
+    I0 = C[margin:margin + H, margin:margin + W].copy()
+    I1 = C[margin - ty:margin - ty + H, margin - tx:margin - tx + W].copy()
+    return I0, I1
+
+
+def _interior_points(W, H, n, pad, seed=0):
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.uniform(pad, W - 1 - pad, n), rng.uniform(pad, H - 1 - pad, n)], 1)
+
+
+def test_zero_motion():
+    I0, _ = _canvas_pair(80, 60, (0, 0))
+    pts = _interior_points(80, 60, 50, 2)
+    flow, st, its = oracle.track(I0, I0, pts, 3, 9, 10, return_iters=True)
+    assert np.all(st == oracle.ST_CONVERGED)
+    assert np.all(flow == 0.0)
+    assert np.all(its == 1)
+
+
+@pytest.mark.parametrize("t", [(3, -2), (-1, 4), (0, 1)])
+def test_integer_translation_exact(t):
+    W, H = 96, 80
+    I0, I1 = _canvas_pair(W, H, t)
+    r = 4
+    pts = _interior_points(W, H, 60, r + 2 + max(abs(t[0]), abs(t[1])))
+    flow, st = oracle.track(I0, I1, pts, 3, 9, 100, eps_fine=1e-12)
+    ok = st == oracle.ST_CONVERGED
+    assert ok.mean() > 0.95
+    assert np.max(np.abs(flow[ok] - np.array(t, float))) < 1e-9
+
+
+def test_large_translation_needs_pyramid():
+    W, H = 160, 120
+    t = (13, -9)
+    I0, I1 = _canvas_pair(W, H, t, sigma=2.0, margin=30)
+    pts = _interior_points(W, H, 80, 4 + 2 + 13, seed=1)
+    flow, st = oracle.track(I0, I1, pts, 4, 9, 100, eps_fine=1e-12)
+    exact = (st == oracle.ST_CONVERGED) & np.all(np.abs(flow - np.array(t, float)) < 1e-9, axis=1)
+    assert exact.mean() > 0.9
+    flow1, st1 = oracle.track(I0, I1, pts, 1, 9, 100, eps_fine=1e-12)
+    exact1 = (st1 == oracle.ST_CONVERGED) & np.all(np.abs(flow1 - np.array(t, float)) < 1e-9, axis=1)
+    assert exact1.mean() < 0.5
+
+
+@pytest.mark.parametrize("t,levels", [((0.37, -0.61), 1), ((1.25, 0.8), 1), ((2.3, -1.7), 2)])
+def test_subpixel_translation_bilinear_span(t, levels):
+    # f = a + b x + c y + e x y: bilinear interpolation and central differences are exact on this
+    # span, so r_k(u) = f(q + u - t) - f(q) vanishes at u = t for interior supports.
+    W, H = 64, 56
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    f = lambda x, y: 20 + 0.5 * x + 0.3 * y + 0.05 * x * y
+    I0 = f(xx, yy)
+    I1 = f(xx - t[0], yy - t[1])
+    pts = _interior_points(W, H, 40, 4 + 2 + 3 * 2 ** (levels - 1), seed=2)
+    flow, st = oracle.track(I0, I1, pts, levels, 9, 100, eps_fine=1e-12, min_eig=0.0,
+                            sigma1=INF, sigma2=INF)
+    assert np.all(st == oracle.ST_CONVERGED)
+    assert np.max(np.abs(flow - np.array(t))) < 1e-9
+    # with the robust norm the residuals are zero at the solution too
+    flow2, st2 = oracle.track(I0, I1, pts, levels, 9, 100, eps_fine=1e-12, min_eig=0.0)
+    assert np.all(st2 == oracle.ST_CONVERGED)
+    assert np.max(np.abs(flow2 - np.array(t))) < 1e-9
+
+
+def test_occluder_rejected_by_robust_norm():
+    W, H = 96, 80
+    t = (2, 1)
+    I0, I1 = _canvas_pair(W, H, t, seed=4)
+    I1 = I1.astype(np.int32)
+    # occluder: a 4x9 block with residual magnitude 100 at u = t (>= sigma2 = 32)
+    py, px = 40, 48
+    blk = (slice(py + t[1] - 4, py + t[1]), slice(px + t[0] - 4, px + t[0] + 5))
+    I1[blk] = np.where(I1[blk] < 128, I1[blk] + 100, I1[blk] - 100)
+    I1 = I1.astype(np.uint8)
+    pts = np.array([[px + 0.3, py + 0.2], [px - 0.4, py + 0.45]])
+    flow, st = oracle.track(I0, I1, pts, 2, 9, 100, eps_fine=1e-12)
+    assert np.all(st == oracle.ST_CONVERGED)
+    assert np.max(np.abs(flow - np.array(t, float))) < 1e-9
+    flowL2, stL2 = oracle.track(I0, I1, pts, 2, 9, 100, eps_fine=1e-12, sigma1=INF, sigma2=INF)
+    assert np.all(np.linalg.norm(flowL2 - np.array(t, float), axis=1) > 1e-3)
+
+
+def _psi_np(r, s1, s2):
+    a = np.abs(r)
+    mid = np.sign(r) * s1 * (s2 - a) / (s2 - s1)
+    return np.where(a <= s1, r, np.where(a >= s2, 0.0, mid))
+
+
+def _fixed_point_residual(I0, I1, p, u, s, s1, s2):
+    """F(u) = sum_k psi(r_k) g_k, evaluated with scipy bilinear sampling."""
+    I0 = I0.astype(np.float64)
+    I1 = I1.astype(np.float64)
+    r = s // 2
+    ky, kx = np.mgrid[-r:r + 1, -r:r + 1].astype(np.float64)
+    X, Y = p[0] + kx.ravel(), p[1] + ky.ravel()
+    samp = lambda img, x, y: ndimage.map_coordinates(img, [y, x], order=1, mode="nearest")
+    gx = 0.5 * (np.concatenate([I0[:, 1:], I0[:, -1:]], 1) - np.concatenate([I0[:, :1], I0[:, :-1]], 1))
+    gy = 0.5 * (np.concatenate([I0[1:], I0[-1:]], 0) - np.concatenate([I0[:1], I0[:-1]], 0))
+    T = samp(I0, X, Y)
+    G = np.stack([samp(gx, X, Y), samp(gy, X, Y)], 1)
+    res = samp(I1, X + u[0], Y + u[1]) - T
+    ps = _psi_np(res, s1, s2)
+    return (ps[:, None] * G).sum(0), (np.abs(ps)[:, None] * np.abs(G)).sum(0)
+
+
+def test_mid_band_fixed_point():
+    # a block offset by +15 (between sigma1 = 8 and sigma2 = 32) moves the robust solution; the
+    # converged point must satisfy sum psi(r_k) g_k = 0 with the middle band active.
+    W, H = 96, 80
+    t = (1, -1)
+    I0, I1 = _canvas_pair(W, H, t, seed=9)
+    I1 = I1.astype(np.float64)
+    I1[35:44, 44:48] += 15.0
+    I0 = I0.astype(np.float64)
+    pts = np.array([[47.3, 40.6], [45.1, 38.2]])
+    flow, st = oracle.track(I0, I1, pts, 2, 9, 200, eps_fine=1e-13)
+    assert np.all(st == oracle.ST_CONVERGED)
+    for p, u in zip(pts, flow):
+        F, scale = _fixed_point_residual(I0, I1, p, u, 9, 8.0, 32.0)
+        assert np.all(np.abs(F) <= 1e-8 * scale)
+        assert np.linalg.norm(u - np.array(t, float)) > 1e-3  # the offset block moved it
+    # at the solution some residuals lie strictly inside the middle band
+    r = 4
+    ky, kx = np.mgrid[-r:r + 1, -r:r + 1]
+    p, u = pts[0], flow[0]
+    res = np.array([oracle.bilinear(I1, p[0] + a + u[0], p[1] + b + u[1]) - oracle.bilinear(I0, p[0] + a, p[1] + b)
+                    for a, b in zip(kx.ravel(), ky.ravel())])
+    assert np.any((np.abs(res) > 8.0) & (np.abs(res) < 32.0))
+
+
+def test_least_squares_limit_matches_textbook_lk():
+    I0, I1, _ = synth.noise_translation_pair(120, 90, seed=11, shift=(1.6, -2.4))
+    pts, _, _ = oracle.detect(I0, 9, 8)
+    flow, st = oracle.track(I0, I1, pts, 3, 9, 10, sigma1=INF, sigma2=INF, min_eig=0.0)
+    flow_b, conv_b = lk_pyramidal(I0, I1, pts, 3, 9, 10, 1e-2, 1e-4)
+    assert np.array_equal(st == oracle.ST_NOT_CONVERGED, ~conv_b) or \
+        np.mean((st == oracle.ST_NOT_CONVERGED) == ~conv_b) > 0.99
+    same = (st != oracle.ST_NOT_CONVERGED) == conv_b
+    assert np.max(np.abs(flow[same] - flow_b[same])) < 1e-9
+
+
+def test_transpose_symmetry():
+    I0, I1, _ = synth.noise_translation_pair(100, 100, seed=12, shift=(1.3, 2.1))
+    pts, _, _ = oracle.detect(I0, 9, 7)
+    flow, st = oracle.track(I0, I1, pts, 3, 9, 30)
+    flowT, stT = oracle.track(np.ascontiguousarray(I0.T), np.ascontiguousarray(I1.T), pts[:, ::-1], 3, 9, 30)
+    same = st == stT
+    assert same.mean() > 0.98
+    c = same & (st == oracle.ST_CONVERGED)
+    assert np.max(np.abs(flow[c] - flowT[c][:, ::-1])) < 1e-6
+
+
+def test_translation_config_sanity():
+    I0, I1, gt = synth.translation_256x128()
+    pts, _, _ = oracle.detect(I0, 9, 8)
+    assert len(pts) == 465
+    flow, st = oracle.track(I0, I1, pts, 3, 9, 10)
+    c = st == oracle.ST_CONVERGED
+    assert c.mean() > 0.95
+    assert np.median(np.linalg.norm(flow[c] - gt, axis=1)) < 0.1
+
+
+def test_ill_conditioned_constant_image():
+    I0 = np.full((40, 50), 100, np.uint8)
+    pts = _interior_points(50, 40, 10, 2)
+    flow, st = oracle.track(I0, I0, pts, 3, 9, 10)
+    assert np.all(st == oracle.ST_ILL_CONDITIONED)
+    assert np.all(flow == 0.0)
+
+
+def test_out_of_bounds_cases():
+    I0, I1 = _canvas_pair(60, 50, (2, 0))
+    pts = np.array([[-0.5, 10.0], [10.0, 49.5], [np.nan, 3.0], [59.0, 49.0], [58.7, 20.0]])
+    flow, st = oracle.track(I0, I1, pts, 2, 9, 50, eps_fine=1e-12)
+    assert list(st[:3]) == [oracle.ST_OUT_OF_BOUNDS] * 3
+    assert np.all(flow[:3] == 0.0)
+    # the last point moves by +2 in x and leaves the image
+    assert st[4] in (oracle.ST_OUT_OF_BOUNDS, oracle.ST_NOT_CONVERGED, oracle.ST_ILL_CONDITIONED)
+
+
+def test_nan_image_is_a_status_not_a_crash():
+    I0 = np.full((30, 30), 50.0)
+    I0 += np.random.default_rng(0).normal(0, 20, I0.shape)
+    I1 = I0.copy()
+    I1[10:20, 10:20] = np.nan
+    flow, st = oracle.track(I0, I1, np.array([[15.0, 15.0], [3.0, 3.0]]), 2, 5, 10, min_eig=0.0)
+    assert st[0] == oracle.ST_NOT_CONVERGED
+    assert st[1] in (oracle.ST_CONVERGED, oracle.ST_NOT_CONVERGED)
+
+
+def test_all_outliers_fall_back_to_least_squares():
+    # Low-contrast texture (values 100 +- 10) and a brightness offset of 60 on I1: every residual
+    # stays in [40, 80], beyond sigma2 = 32, wherever the tracker looks.  Every robust weight is
+    # then zero, each step takes the least-squares fallback, and the result must be identical to
+    # the least-squares tracker's.
+    I0, I1 = _canvas_pair(80, 64, (1, 0), seed=13)
+    I0 = 90.0 + I0.astype(np.float64) * (20.0 / 255.0)
+    I1 = 90.0 + I1.astype(np.float64) * (20.0 / 255.0) + 60.0
+    pts = _interior_points(80, 64, 20, 10, seed=3)
+    f_rob, s_rob = oracle.track(I0, I1, pts, 2, 9, 50, min_eig=0.0)
+    f_l2, s_l2 = oracle.track(I0, I1, pts, 2, 9, 50, min_eig=0.0, sigma1=INF, sigma2=INF)
+    assert np.array_equal(s_rob, s_l2)
+    assert np.array_equal(f_rob, f_l2)
