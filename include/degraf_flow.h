@@ -1,0 +1,159 @@
+/*
+ * degraf_flow.h -- C ABI of the MI355X (gfx950) DeGraF key-point detector and robust local
+ * optical flow tracker.
+ *
+ * Method: Stephenson, Breckon, Katramados, "DeGraF-Flow: Extending DeGraF Features for accurate
+ * and efficient sparse-to-dense optical flow estimation" (2019), Section 2: points are detected
+ * on a uniform grid of gradient centroids in the first frame ("Point detection", Eq. 1-2 and the
+ * selection rule) and tracked into the next frame with robust local optical flow ("Sparse point
+ * tracking").  The dense interpolation stage of that pipeline is not part of this library.
+ *
+ * Conventions shared by every call:
+ *   - Every data pointer is a DEVICE pointer owned by the caller.  The library never allocates
+ *     or frees caller memory; only a batch plan (dgf_batch_*) owns device memory, released by
+ *     dgf_batch_destroy.
+ *   - Every compute call is asynchronous on `stream` (a hipStream_t passed as void*, NULL = the
+ *     default stream), performs no host synchronisation and no device allocation.
+ *   - Return value: DGF_OK (0) or a negative DGF_ERR_* code.  Arguments are validated on the host
+ *     before anything is launched; on error nothing is launched and outputs are untouched.
+ *     Numerical trouble on the device (flat texture, divergence, non-finite pixels) is reported
+ *     per point through `status`, never as an error code.
+ *   - Coordinates: x = column, y = row, pixel centres at integer coordinates.  Points are float
+ *     pairs (x, y); flow[k] is the displacement u with I1(p_k + u) ~ I0(p_k).
+ *   - Images are row-major with a row pitch in bytes (pitch >= width * element size).
+ */
+#ifndef DEGRAF_FLOW_H
+#define DEGRAF_FLOW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------------------------------- */
+#define DGF_OK 0
+#define DGF_ERR_INVALID_ARG (-1) /* null pointer, bad size, bad dtype, bad pitch, ...          */
+#define DGF_ERR_CAPACITY (-2)    /* output capacity smaller than the number of results          */
+#define DGF_ERR_UNSUPPORTED (-3) /* valid request outside what this build implements          */
+#define DGF_ERR_HIP (-4)         /* a HIP runtime call or kernel launch failed                   */
+#define DGF_ERR_WORKSPACE (-5)   /* workspace null or smaller than dgf_track_workspace_bytes()   */
+
+/* ---- per-point tracking status ----------------------------------------------------------------- */
+#define DGF_ST_CONVERGED 0       /* level 0 stopped on the step-size test, p + u inside image    */
+#define DGF_ST_NOT_CONVERGED 1   /* level 0 ran out of iterations, or a step was not finite     */
+#define DGF_ST_ILL_CONDITIONED 2 /* lambda_min(G0) / s^2 < min_eig at some level                */
+#define DGF_ST_OUT_OF_BOUNDS 3   /* input point, or converged p + u, outside [0,W-1] x [0,H-1]  */
+
+/* ---- element types ------------------------------------------------------------------------------ */
+#define DGF_U8 0  /* uint8 grey levels 0..255 */
+#define DGF_F32 1 /* float, same 0..255 scale for the default tracker constants */
+
+#define DGF_MAX_LEVELS 12
+#define DGF_MAX_WINDOW 128
+#define DGF_MAX_SUPPORT 31
+
+typedef struct {
+    const void *data;    /* device pointer to row 0                                   */
+    int32_t width;       /* columns, >= 1                                             */
+    int32_t height;      /* rows, >= 1                                                */
+    int64_t pitch_bytes; /* bytes between consecutive rows, >= width * element size   */
+    int32_t dtype;       /* DGF_U8 or DGF_F32                                         */
+} dgf_image;
+
+/* Robust tracker constants.  The paper leaves the tracker's norm and stopping rule to its
+ * citation; this library uses a continuous, piecewise-linear redescending influence function
+ *   psi(r) = r (|r| <= sigma1),  sign(r) sigma1 (sigma2 - |r|) / (sigma2 - sigma1)
+ *            (sigma1 < |r| < sigma2),  0 (|r| >= sigma2)
+ * with iteratively re-weighted Gauss-Newton steps, w = psi(r) / r. */
+typedef struct {
+    float sigma1;     /* inner threshold, intensity units (default 8)                   */
+    float sigma2;     /* outer threshold, intensity units (default 32); both INFINITY
+                         gives plain least-squares pyramidal Lucas-Kanade                */
+    float eps_coarse; /* a level > 0 stops when |step|_2 < eps_coarse px (default 1e-2) */
+    float eps_fine;   /* level 0 stops when |step|_2 < eps_fine px (default 1e-4)       */
+    float min_eig;    /* ill-conditioned when lambda_min(G0)/s^2 < min_eig
+                         (default 1e-4 * 255^2)                                          */
+    int32_t flags;    /* reserved, must be 0                                            */
+} dgf_track_opts;
+
+/* ---- library ----------------------------------------------------------------------------------- */
+
+/* Static, NUL-terminated description of an error code (never NULL). */
+const char *dgf_strerror(int code);
+
+/* Library ABI version (major * 10000 + minor * 100 + patch). */
+int dgf_version(void);
+
+/* Fills *out with the default tracker constants listed in dgf_track_opts.  Returns DGF_OK, or
+ * DGF_ERR_INVALID_ARG for a null pointer. */
+int dgf_track_opts_default(dgf_track_opts *out);
+
+/* ---- DeGraF detection (Section 2 "Point detection", Eq. 1-2 and the selection rule) --------- */
+
+/* Number of key-points for a W x H image: one per window position, windows fully inside the
+ * image at origins (kx * stride, ky * stride):
+ *   N = (floor((W - window) / stride) + 1) * (floor((H - window) / stride) + 1), 0 if the image
+ * is smaller than the window.  Pure host function; returns -1 for window/stride < 1. */
+int64_t dgf_detect_count(int32_t width, int32_t height, int32_t window, int32_t stride);
+
+/* One key-point per window (square window x window), in row-major window order: point n belongs
+ * to window (n % nx, n / nx).  For each window the positive centroid (intensity-weighted mean
+ * position, Eq. 1) and the negative centroid (weights 1 + m - I with m the window maximum, Eq. 2)
+ * are formed; the key-point is the negative one when its weight sum is strictly larger, else the
+ * positive one.  Sums are exact integers; the final divisions are IEEE single precision.
+ *   I0       : DGF_U8 image (device)
+ *   window   : 1 .. DGF_MAX_WINDOW;  stride >= 1
+ *   points   : out, float[capacity][2] (x, y) in image pixels
+ *   sel      : out, nullable, uint8[capacity]: 1 when the negative centroid was kept
+ *   response : out, nullable, float[capacity]: |C_pos - C_neg| (C_pos := window centre for an
+ *              all-zero window)
+ *   capacity : number of points the outputs can hold; DGF_ERR_CAPACITY if smaller than
+ *              dgf_detect_count(...).  N = 0 launches nothing and returns DGF_OK. */
+int dgf_detect(const dgf_image *I0, int32_t window, int32_t stride, float *points, uint8_t *sel,
+               float *response, int64_t capacity, void *stream);
+
+/* ---- image pyramid (coarse-to-fine tracking) --------------------------------------------------- */
+
+/* Level l+1 is the 5-tap binomial [1 4 6 4 1]/16 smoothing of level l in both directions with
+ * replicated borders, sampled at even pixels: size ceil(W_l/2) x ceil(H_l/2), so a level-0
+ * point p sits at p / 2^l.  uint8 levels round half up exactly ((sum + 128) >> 8); float levels
+ * divide by 256.  Level 0 is the input image itself and is not copied.
+ *
+ * Layout of levels 1 .. levels-1 in `dst` (also used inside the track workspace): level l
+ * starts at byte offsets[l] and has row pitch pitches[l] bytes (offsets[0] = pitches[0] = 0).
+ * Returns the total number of bytes, or 0 for invalid arguments.  offsets/pitches nullable. */
+size_t dgf_pyramid_layout(int32_t width, int32_t height, int32_t levels, int32_t dtype,
+                          int64_t *offsets, int64_t *pitches);
+
+/* Builds levels 1 .. levels-1 of `src` into `dst` (device, dst_bytes >= dgf_pyramid_layout()). */
+int dgf_pyramid(const dgf_image *src, int32_t levels, void *dst, size_t dst_bytes, void *stream);
+
+/* ---- robust local optical flow tracking (Section 2 "Sparse point tracking") ------------------- */
+
+/* Workspace bytes needed by dgf_track for a pair of width x height images (both pyramids). */
+size_t dgf_track_workspace_bytes(int32_t width, int32_t height, int32_t levels, int32_t dtype);
+
+/* Tracks n points from I0 to I1 (same size and dtype).  For each point, coarse to fine over
+ * `levels` pyramid levels with a square support of `support` x `support` pixels (odd, 1 ..
+ * DGF_MAX_SUPPORT) centred on the point:
+ *   template T_k = bilinear(I0_l, p/2^l + k) and its gradient g_k (central differences,
+ *   bilinearly sampled); per iteration r_k = bilinear(I1_l, p/2^l + k + guess + d) - T_k,
+ *   w_k = psi(r_k)/r_k, step = (sum w g g^T)^-1 (-sum w r g)  (least-squares step if the
+ *   weighted matrix is near singular), at most `iters` iterations per level; the level's result
+ *   seeds the next finer level as 2 (guess + d).
+ *   points    : float[n][2] level-0 coordinates (device)
+ *   workspace : device, >= dgf_track_workspace_bytes(width, height, levels, dtype) bytes
+ *   flow      : out, float[n][2];   status : out, uint8[n] (DGF_ST_*)
+ *   iters_out : out, nullable, int32[n]: iterations run by the point summed over levels
+ *   opts      : nullable (defaults)
+ * n = 0 launches nothing. */
+int dgf_track(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
+              int32_t support, int32_t iters, const dgf_track_opts *opts, void *workspace,
+              size_t ws_bytes, float *flow, uint8_t *status, int32_t *iters_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DEGRAF_FLOW_H */

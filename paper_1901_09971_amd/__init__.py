@@ -1,1 +1,7 @@
-"""MI355X-native DeGraF key-point detection and robust local optical flow tracking."""
+"""MI355X-native DeGraF key-point detection and robust local optical flow tracking.
+
+The compute path is the gfx950 HIP library ``libdegraf_flow.so`` behind the C ABI in
+``include/degraf_flow.h``; this package only marshals tensors and streams into it.  Importing the
+package does not load the library; the first call does, and raises if it is not built.
+"""
+from .api import TrackOpts, detect, detect_count, pyramid, pyramid_layout, track, track_workspace_bytes  # noqa: F401

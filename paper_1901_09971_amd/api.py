@@ -1,0 +1,128 @@
+"""PyTorch-facing binding of the C ABI: tensors supply device memory and the current stream;
+every step of detection and tracking runs in the HIP library."""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import DGF_F32, DGF_U8, DgfImage, DgfTrackOpts, check, lib
+
+
+@dataclass
+class TrackOpts:
+    """Robust tracker constants (0..255 intensity scale); see dgf_track_opts in the C header."""
+    sigma1: float = 8.0
+    sigma2: float = 32.0
+    eps_coarse: float = 1e-2
+    eps_fine: float = 1e-4
+    min_eig: float = 1e-4 * 255.0 * 255.0
+
+    def to_c(self) -> DgfTrackOpts:
+        return DgfTrackOpts(self.sigma1, self.sigma2, self.eps_coarse, self.eps_fine, self.min_eig, 0)
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _image(t: torch.Tensor, name: str) -> DgfImage:
+    if not isinstance(t, torch.Tensor) or t.dim() != 2:
+        raise ValueError(f"{name}: expected a 2-D tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: expected a device (cuda) tensor")
+    if t.dtype == torch.uint8:
+        dt = DGF_U8
+    elif t.dtype == torch.float32:
+        dt = DGF_F32
+    else:
+        raise ValueError(f"{name}: dtype must be uint8 or float32")
+    if t.stride(1) != 1 or t.stride(0) < t.shape[1]:
+        raise ValueError(f"{name}: rows must be contiguous")
+    return DgfImage(t.data_ptr(), t.shape[1], t.shape[0], t.stride(0) * t.element_size(), dt)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def detect_count(width: int, height: int, window: int, stride: int) -> int:
+    return int(lib().dgf_detect_count(width, height, window, stride))
+
+
+def detect(frame: torch.Tensor, window: int, stride: int, return_sel: bool = False,
+           return_response: bool = False):
+    """DeGraF key-points of a uint8 frame: float32 [N, 2] (x, y) in row-major window order."""
+    img = _image(frame, "frame")
+    n = detect_count(img.width, img.height, window, stride)
+    if n < 0:
+        raise ValueError("window and stride must be >= 1")
+    pts = torch.empty((n, 2), dtype=torch.float32, device=frame.device)
+    sel = torch.empty(n, dtype=torch.uint8, device=frame.device) if return_sel else None
+    resp = torch.empty(n, dtype=torch.float32, device=frame.device) if return_response else None
+    check(lib().dgf_detect(ctypes.byref(img), window, stride, _ptr(pts), _ptr(sel), _ptr(resp), n, _stream()),
+          "dgf_detect")
+    out = [pts]
+    if return_sel:
+        out.append(sel)
+    if return_response:
+        out.append(resp)
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def pyramid_layout(width: int, height: int, levels: int, dtype: int):
+    off = (ctypes.c_int64 * _lib.DGF_MAX_LEVELS)()
+    pit = (ctypes.c_int64 * _lib.DGF_MAX_LEVELS)()
+    total = int(lib().dgf_pyramid_layout(width, height, levels, dtype, off, pit))
+    return total, list(off)[:levels], list(pit)[:levels]
+
+
+def pyramid(img: torch.Tensor, levels: int):
+    """Levels 0 .. levels-1 (level 0 is ``img``); coarser levels are views into one buffer."""
+    im = _image(img, "img")
+    total, off, pit = pyramid_layout(im.width, im.height, levels, im.dtype)
+    buf = torch.empty(max(total, 1), dtype=torch.uint8, device=img.device)
+    check(lib().dgf_pyramid(ctypes.byref(im), levels, _ptr(buf), total, _stream()), "dgf_pyramid")
+    out = [img]
+    W, H = im.width, im.height
+    esz = img.element_size()
+    for l in range(1, levels):
+        W, H = (W + 1) // 2, (H + 1) // 2
+        rows = buf[off[l]:off[l] + pit[l] * H].view(H, pit[l])
+        lvl = rows[:, :W * esz]
+        out.append(lvl if esz == 1 else lvl.contiguous().view(torch.float32))
+    return out
+
+
+def track_workspace_bytes(width: int, height: int, levels: int, dtype: int) -> int:
+    return int(lib().dgf_track_workspace_bytes(width, height, levels, dtype))
+
+
+def track(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, levels: int, support: int, iters: int,
+          opts: TrackOpts | None = None, return_iters: bool = False, workspace: torch.Tensor | None = None):
+    """Track ``points`` (float32 [n, 2] device) from I0 to I1.  Returns (flow float32 [n, 2],
+    status uint8 [n]) and optionally the per-point iteration count (int32 [n])."""
+    a, b = _image(I0, "I0"), _image(I1, "I1")
+    if points.dtype != torch.float32 or points.dim() != 2 or points.shape[1] != 2 or not points.is_cuda:
+        raise ValueError("points: expected a float32 [n, 2] device tensor")
+    points = points.contiguous()
+    n = points.shape[0]
+    ws_bytes = track_workspace_bytes(a.width, a.height, levels, a.dtype)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=I0.device)
+    flow = torch.empty((n, 2), dtype=torch.float32, device=I0.device)
+    status = torch.empty(n, dtype=torch.uint8, device=I0.device)
+    its = torch.empty(n, dtype=torch.int32, device=I0.device) if return_iters else None
+    o = (opts or TrackOpts()).to_c()
+    check(lib().dgf_track(ctypes.byref(a), ctypes.byref(b), _ptr(points), n, levels, support, iters,
+                          ctypes.byref(o), _ptr(workspace), workspace.numel(), _ptr(flow), _ptr(status), _ptr(its),
+                          _stream()), "dgf_track")
+    if return_iters:
+        return flow, status, its
+    return flow, status
+
+
+INF = math.inf

@@ -1,0 +1,187 @@
+// api.hip -- host side of the C ABI declared in include/degraf_flow.h: argument validation,
+// pyramid/workspace layout and kernel launches on the caller's stream.  No call here allocates
+// device memory or synchronises the host.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "dgf_internal.hpp"
+#include "dgf_tuning.hpp"
+
+using namespace dgf;
+
+namespace {
+
+int esize(int dtype) { return dtype == DGF_U8 ? 1 : (dtype == DGF_F32 ? 4 : 0); }
+
+bool image_ok(const dgf_image *im)
+{
+    if (!im || !im->data) return false;
+    if (im->width < 1 || im->height < 1) return false;
+    const int e = esize(im->dtype);
+    if (e == 0) return false;
+    if (im->pitch_bytes < (int64_t)im->width * e) return false;
+    if (im->dtype == DGF_F32 && ((uintptr_t)im->data % 4 != 0 || im->pitch_bytes % 4 != 0)) return false;
+    return true;
+}
+
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+int hip_rc(hipError_t e) { return e == hipSuccess ? DGF_OK : DGF_ERR_HIP; }
+
+} // namespace
+
+extern "C" {
+
+const char *dgf_strerror(int code)
+{
+    switch (code) {
+    case DGF_OK: return "ok";
+    case DGF_ERR_INVALID_ARG: return "invalid argument";
+    case DGF_ERR_CAPACITY: return "output capacity too small";
+    case DGF_ERR_UNSUPPORTED: return "unsupported configuration";
+    case DGF_ERR_HIP: return "HIP runtime error";
+    case DGF_ERR_WORKSPACE: return "workspace missing or too small";
+    default: return "unknown error";
+    }
+}
+
+int dgf_version(void) { return 100; }
+
+int dgf_track_opts_default(dgf_track_opts *o)
+{
+    if (!o) return DGF_ERR_INVALID_ARG;
+    o->sigma1 = 8.0f;
+    o->sigma2 = 32.0f;
+    o->eps_coarse = 1e-2f;
+    o->eps_fine = 1e-4f;
+    o->min_eig = 1e-4f * 255.0f * 255.0f;
+    o->flags = 0;
+    return DGF_OK;
+}
+
+int64_t dgf_detect_count(int32_t W, int32_t H, int32_t window, int32_t stride)
+{
+    if (window < 1 || stride < 1) return -1;
+    if (W < window || H < window) return 0;
+    return (int64_t)((W - window) / stride + 1) * (int64_t)((H - window) / stride + 1);
+}
+
+int dgf_detect(const dgf_image *I0, int32_t window, int32_t stride, float *points, uint8_t *sel, float *response,
+               int64_t capacity, void *stream)
+{
+    if (!image_ok(I0) || I0->dtype != DGF_U8) return DGF_ERR_INVALID_ARG;
+    if (window < 1 || window > DGF_MAX_WINDOW || stride < 1) return DGF_ERR_INVALID_ARG;
+    const int64_t N = dgf_detect_count(I0->width, I0->height, window, stride);
+    if (N == 0) return DGF_OK;
+    if (!points) return DGF_ERR_INVALID_ARG;
+    if (capacity < N) return DGF_ERR_CAPACITY;
+    return hip_rc(launch_detect((const uint8_t *)I0->data, I0->pitch_bytes, I0->width, I0->height, window, stride, points,
+                                sel, response, (hipStream_t)stream));
+}
+
+size_t dgf_pyramid_layout(int32_t W, int32_t H, int32_t levels, int32_t dtype, int64_t *offsets, int64_t *pitches)
+{
+    const int e = esize(dtype);
+    if (W < 1 || H < 1 || levels < 1 || levels > DGF_MAX_LEVELS || e == 0) return 0;
+    int64_t total = 0;
+    if (offsets) offsets[0] = 0;
+    if (pitches) pitches[0] = 0;
+    for (int l = 1; l < levels; ++l) {
+        W = (W + 1) / 2;
+        H = (H + 1) / 2;
+        const int64_t pitch = align_up((int64_t)W * e, 64);
+        total = align_up(total, 256);
+        if (offsets) offsets[l] = total;
+        if (pitches) pitches[l] = pitch;
+        total += pitch * H;
+    }
+    return (size_t)align_up(total, 256);
+}
+
+int dgf_pyramid(const dgf_image *src, int32_t levels, void *dst, size_t dst_bytes, void *stream)
+{
+    if (!image_ok(src) || levels < 1 || levels > DGF_MAX_LEVELS) return DGF_ERR_INVALID_ARG;
+    int64_t off[DGF_MAX_LEVELS], pitch[DGF_MAX_LEVELS];
+    const size_t need = dgf_pyramid_layout(src->width, src->height, levels, src->dtype, off, pitch);
+    if (levels == 1) return DGF_OK;
+    if (!dst || dst_bytes < need) return DGF_ERR_WORKSPACE;
+    const uint8_t *prev = (const uint8_t *)src->data;
+    int64_t prev_pitch = src->pitch_bytes;
+    int W = src->width, H = src->height;
+    for (int l = 1; l < levels; ++l) {
+        PyrJob j{prev, (uint8_t *)dst + off[l], prev_pitch, pitch[l], W, H};
+        const hipError_t e = launch_pyr_level(&j, 1, src->dtype, (hipStream_t)stream);
+        if (e != hipSuccess) return DGF_ERR_HIP;
+        prev = (const uint8_t *)dst + off[l];
+        prev_pitch = pitch[l];
+        W = (W + 1) / 2;
+        H = (H + 1) / 2;
+    }
+    return DGF_OK;
+}
+
+size_t dgf_track_workspace_bytes(int32_t W, int32_t H, int32_t levels, int32_t dtype)
+{
+    if (W < 1 || H < 1 || levels < 1 || levels > DGF_MAX_LEVELS || esize(dtype) == 0) return 0;
+    return 2 * dgf_pyramid_layout(W, H, levels, dtype, nullptr, nullptr) + 256;
+}
+
+int dgf_track(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
+              int32_t support, int32_t iters, const dgf_track_opts *opts, void *workspace, size_t ws_bytes,
+              float *flow, uint8_t *status, int32_t *iters_out, void *stream)
+{
+    if (!image_ok(I0) || !image_ok(I1)) return DGF_ERR_INVALID_ARG;
+    if (I0->width != I1->width || I0->height != I1->height || I0->dtype != I1->dtype) return DGF_ERR_INVALID_ARG;
+    if (levels < 1 || levels > DGF_MAX_LEVELS || iters < 1) return DGF_ERR_INVALID_ARG;
+    if (support < 1 || (support & 1) == 0 || support > DGF_MAX_SUPPORT) return DGF_ERR_INVALID_ARG;
+    if (n < 0) return DGF_ERR_INVALID_ARG;
+    if (n > 0 && (!points || !flow || !status)) return DGF_ERR_INVALID_ARG;
+    dgf_track_opts o;
+    if (opts) {
+        o = *opts;
+        if (o.flags != 0) return DGF_ERR_UNSUPPORTED;
+    } else {
+        dgf_track_opts_default(&o);
+    }
+    if (!(o.sigma1 >= 0.f) || !(o.sigma2 >= 0.f) || !(o.eps_coarse >= 0.f) || !(o.eps_fine >= 0.f) || isnan(o.min_eig))
+        return DGF_ERR_INVALID_ARG;
+    const size_t need = dgf_track_workspace_bytes(I0->width, I0->height, levels, I0->dtype);
+    if (levels > 1 && (!workspace || ws_bytes < need)) return DGF_ERR_WORKSPACE;
+    TrackTuning tune = tuning_for(support, levels, I0->dtype, n);
+    if (pick_ppl_max(support, tune.lpp) < 0) return DGF_ERR_UNSUPPORTED;
+    while (track_lds_bytes(support, tune) > kMaxLdsPerBlock && tune.wpb > 1) tune.wpb /= 2;
+    if (track_lds_bytes(support, tune) > kMaxLdsPerBlock) return DGF_ERR_UNSUPPORTED;
+    if (n == 0) return DGF_OK;
+
+    hipStream_t st = (hipStream_t)stream;
+    TrackParams P{};
+    int64_t off[DGF_MAX_LEVELS], pitch[DGF_MAX_LEVELS];
+    const size_t pyr_bytes = dgf_pyramid_layout(I0->width, I0->height, levels, I0->dtype, off, pitch);
+    uint8_t *ws0 = (uint8_t *)workspace;
+    uint8_t *ws1 = ws0 ? ws0 + pyr_bytes : nullptr;
+    P.lv[0] = LevelPair{(const uint8_t *)I0->data, (const uint8_t *)I1->data, I0->pitch_bytes, I1->pitch_bytes,
+                        I0->width, I0->height};
+    int W = I0->width, H = I0->height;
+    for (int l = 1; l < levels; ++l) {
+        PyrJob jobs[2] = {{P.lv[l - 1].p0, ws0 + off[l], P.lv[l - 1].pitch0, pitch[l], W, H},
+                          {P.lv[l - 1].p1, ws1 + off[l], P.lv[l - 1].pitch1, pitch[l], W, H}};
+        const hipError_t e = launch_pyr_level(jobs, 2, I0->dtype, st);
+        if (e != hipSuccess) return DGF_ERR_HIP;
+        W = (W + 1) / 2;
+        H = (H + 1) / 2;
+        P.lv[l] = LevelPair{ws0 + off[l], ws1 + off[l], pitch[l], pitch[l], W, H};
+    }
+    P.pts = points;
+    P.n = n;
+    P.flow = flow;
+    P.status = status;
+    P.iters_out = iters_out;
+    P.L = levels;
+    P.iters = iters;
+    fill_track_geometry(P, support, tune.margin, tune.lpp);
+    fill_track_constants(P, o, support);
+    return hip_rc(launch_track(P, tune, I0->dtype, st));
+}
+
+} // extern "C"

@@ -1,0 +1,126 @@
+// detect.hip -- DeGraF key-point detection on gfx950.
+//
+// One key-point per window of a uniform grid (DeGraF-Flow, Section 2 "Point detection"):
+// positive centroid from the intensity-weighted moments (Eq. 1), negative centroid from the
+// inverted weights 1 + m - I with m the window maximum (Eq. 2), and the centroid with the larger
+// weight sum is kept (strictly larger for the negative one).
+//
+// The image is read once from HBM: a workgroup owns a TX x TY block of windows, stages the
+// pixel rectangle they cover into LDS with coalesced row loads, and each lane then reduces its
+// own window from LDS.  Only the positive moments are accumulated; the negative ones follow
+// exactly from sum (1 + m - I) = (1 + m) w h - sum I (and likewise for the moments).
+#include "dgf_internal.hpp"
+
+namespace dgf {
+
+struct DetectOut {
+    float *pts;
+    uint8_t *sel;
+    float *resp;
+};
+
+__device__ __forceinline__ void finish_window(int S, int Mi, int Mj, int m, int win, int x0, int y0, int64_t n,
+                                              DetectOut o)
+{
+    const int wh = win * win;
+    const int mom = win * (win * (win - 1) / 2); // sum over the window of a row (or column) index
+    const int S_neg = (1 + m) * wh - S;
+    const int Mi_neg = (1 + m) * mom - Mi;
+    const int Mj_neg = (1 + m) * mom - Mj;
+    const bool neg = S_neg > S;
+    const float cnx = (float)Mj_neg / (float)S_neg, cny = (float)Mi_neg / (float)S_neg;
+    float cpx, cpy;
+    if (S > 0) {
+        cpx = (float)Mj / (float)S;
+        cpy = (float)Mi / (float)S;
+    } else {
+        cpx = 0.5f * (float)(win - 1);
+        cpy = cpx;
+    }
+    const float ox = neg ? cnx : cpx, oy = neg ? cny : cpy;
+    reinterpret_cast<float2 *>(o.pts)[n] = make_float2((float)x0 + ox, (float)y0 + oy);
+    if (o.sel) o.sel[n] = (uint8_t)neg;
+    if (o.resp) o.resp[n] = sqrtf((cpx - cnx) * (cpx - cnx) + (cpy - cny) * (cpy - cny));
+}
+
+// LDS-tiled form: TX x TY windows per workgroup, one lane per window.
+template <int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void k_detect_tiled(const uint8_t *__restrict__ img, int64_t pitch, int W, int H,
+                                                          int win, int stride, int nx, int ny, DetectOut o)
+{
+    extern __shared__ uint8_t tile[];
+    const int wx0 = blockIdx.x * TX, wy0 = blockIdx.y * TY;
+    const int ox = wx0 * stride, oy = wy0 * stride;
+    const int RW = (TX - 1) * stride + win, RH = (TY - 1) * stride + win;
+    const int rw = min(RW, W - ox), rh = min(RH, H - oy);
+    // coalesced staging: consecutive lanes read consecutive bytes of a row
+    for (int i = threadIdx.x; i < rw * rh; i += blockDim.x) {
+        const int y = i / rw, x = i - y * rw;
+        tile[y * RW + x] = img[(int64_t)(oy + y) * pitch + ox + x];
+    }
+    __syncthreads();
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int kx = wx0 + tx, ky = wy0 + ty;
+    if (kx >= nx || ky >= ny) return;
+    const uint8_t *w0 = tile + ty * stride * RW + tx * stride;
+    int S = 0, Mi = 0, Mj = 0, m = 0;
+    for (int i = 0; i < win; ++i) {
+        int rs = 0, rj = 0;
+        for (int j = 0; j < win; ++j) {
+            const int v = w0[i * RW + j];
+            rs += v;
+            rj += j * v;
+            m = max(m, v);
+        }
+        S += rs;
+        Mi += i * rs;
+        Mj += rj;
+    }
+    finish_window(S, Mi, Mj, m, win, kx * stride, ky * stride, (int64_t)ky * nx + kx, o);
+}
+
+// Direct form for windows too large to tile: one lane per window, reads through the cache.
+__global__ __launch_bounds__(256) void k_detect_direct(const uint8_t *__restrict__ img, int64_t pitch, int win,
+                                                        int stride, int nx, int64_t N, DetectOut o)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int kx = (int)(n % nx), ky = (int)(n / nx);
+    const int x0 = kx * stride, y0 = ky * stride;
+    int S = 0, Mi = 0, Mj = 0, m = 0;
+    for (int i = 0; i < win; ++i) {
+        const uint8_t *row = img + (int64_t)(y0 + i) * pitch + x0;
+        int rs = 0, rj = 0;
+        for (int j = 0; j < win; ++j) {
+            const int v = row[j];
+            rs += v;
+            rj += j * v;
+            m = max(m, v);
+        }
+        S += rs;
+        Mi += i * rs;
+        Mj += rj;
+    }
+    finish_window(S, Mi, Mj, m, win, x0, y0, n, o);
+}
+
+hipError_t launch_detect(const uint8_t *img, int64_t pitch, int W, int H, int win, int stride, float *pts,
+                         uint8_t *sel, float *resp, hipStream_t st)
+{
+    const int nx = (W - win) / stride + 1, ny = (H - win) / stride + 1;
+    DetectOut o{pts, sel, resp};
+    constexpr int TX = 16, TY = 16;
+    const int64_t RW = (int64_t)(TX - 1) * stride + win, RH = (int64_t)(TY - 1) * stride + win;
+    if (RW * RH <= 48 * 1024) {
+        dim3 grid((nx + TX - 1) / TX, (ny + TY - 1) / TY);
+        hipLaunchKernelGGL((k_detect_tiled<TX, TY>), grid, dim3(TX * TY), (size_t)(RW * RH), st, img, pitch, W, H, win,
+                           stride, nx, ny, o);
+    } else {
+        const int64_t N = (int64_t)nx * ny;
+        hipLaunchKernelGGL(k_detect_direct, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, img, pitch, win,
+                           stride, nx, N, o);
+    }
+    return hipGetLastError();
+}
+
+} // namespace dgf
