@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Throughput of the DeGraF detection + robust pyramidal tracking hot path on one MI355X.
+
+One step = DeGraF key-point detection on I0, the pyramids of both frames, and robust tracking of
+every detected point, on one 1242x375 driving-shaped uint8 pair (window 9, stride 5: 18,278
+points; 5 pyramid levels, 21x21 support, at most 20 iterations per level).  The frames are
+resident in device memory before the timed region; every step recomputes everything.
+
+Prints ONE JSON line.  ``value`` is tracked points per second over the timed steps.  The
+``roofline`` object describes the dominant kernel (the tracker): its algorithmic FP32 work per
+launch (24 flops per executed support-pixel iteration, counted from the per-point iteration
+numbers the kernel reports) over its average duration measured with HIP events on the stream it
+runs on.  ``cpu_baseline`` times the FP64 CPU oracle on the same pair on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "tracked points/sec (DeGraF+RLOF) @1242x375; batched vs plain frame-pairs/sec"
+FLOPS_PER_PIXEL_ITER = 24          # see the design doc: bilinear 7, residual 1, weight 3, psi 1, sums 12
+PEAK_FP32_VALU_TFLOPS = 78.6       # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, unpacked FP32
+PEAK_HBM_GBPS = 8000.0
+WORKLOAD = dict(name="driving_1242x375", W=1242, H=375, window=9, stride=5, levels=5, support=21, iters=20)
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "track_driving_1242x375_counters.md")
+TRACK_SOURCES = ["paper_1901_09971_amd/csrc/track.hip", "paper_1901_09971_amd/csrc/dgf_internal.hpp"]
+
+
+def track_source_sha() -> str:
+    h = hashlib.sha256()
+    for rel in TRACK_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic():
+    """HBM bytes per track launch from the committed rocprofv3 counter summary, or None when
+    the summary is missing or was taken on a different version of the kernel source."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    m = re.search(r"<!--\s*machine:\s*(\{.*?\})\s*-->", text, re.S)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("kernel_source_sha") != track_source_sha():
+        return None
+    return d
+
+
+def cpu_baseline(I0, I1, n_points, budget_s):
+    import oracle  # the CPU baseline leg is the only product-side user of the oracle
+    w = WORKLOAD
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    threads = min(int(os.environ.get("OMP_NUM_THREADS", cores)), cores)
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        pts, _, _ = oracle.detect(I0, w["window"], w["stride"], threads=threads)
+        oracle.track(I0, I1, pts, w["levels"], w["support"], w["iters"], threads=threads)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or reps >= 3:
+            break
+    return {"value": reps * n_points / el, "unit": "points/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} full pass(es) of detect+track of the {n_points}-point 1242x375 pair, FP64, "
+                      f"{el:.1f} s wall"}
+
+
+def copy_calibration(mib: int):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    n = mib * 1024 * 1024
+    a = torch.empty(n, dtype=torch.uint8, device="cuda").random_(0, 255)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 3}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget-s", type=float, default=12.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the tracker shards by pairs or point ranges with no "
+              "exchange in the forward pass, and this build runs on a single MI355X (use --gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration_mib:
+        copy_calibration(args.copy_calibration_mib)
+        return
+
+    import numpy as np
+    import torch
+
+    import paper_1901_09971_amd as dgf
+    from paper_1901_09971_amd import synth
+
+    w = WORKLOAD
+    I0n, I1n, _, _ = synth.driving_1242x375()
+    dev = torch.device("cuda", 0)
+    I0 = torch.from_numpy(I0n).to(dev)
+    I1 = torch.from_numpy(I1n).to(dev)
+    N = dgf.detect_count(w["W"], w["H"], w["window"], w["stride"])
+    pts = torch.empty((N, 2), dtype=torch.float32, device=dev)
+    flow = torch.empty((N, 2), dtype=torch.float32, device=dev)
+    status = torch.empty(N, dtype=torch.uint8, device=dev)
+    its = torch.empty(N, dtype=torch.int32, device=dev)
+    ws = torch.empty(dgf.track_workspace_bytes(w["W"], w["H"], w["levels"], 0), dtype=torch.uint8, device=dev)
+
+    def step(iters_out=None):
+        dgf.detect(I0, w["window"], w["stride"], out=pts)
+        dgf.track_pyramids(I0, I1, w["levels"], ws)
+        dgf.track_run(I0, I1, pts, w["levels"], w["support"], w["iters"], ws, flow, status, iters_out)
+
+    # work accounting (not timed): executed iterations of every point
+    step(its)
+    torch.cuda.synchronize()
+    it_total = int(its.to(torch.int64).sum().item())
+    pix_iters = it_total * w["support"] ** 2
+    st_counts = np.bincount(status.cpu().numpy(), minlength=4).tolist()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_host0 = time.perf_counter()
+    start.record()
+    for k in range(K):
+        e = ev[k]
+        e[0].record()
+        dgf.detect(I0, w["window"], w["stride"], out=pts)
+        e[1].record()
+        dgf.track_pyramids(I0, I1, w["levels"], ws)
+        e[2].record()
+        dgf.track_run(I0, I1, pts, w["levels"], w["support"], w["iters"], ws, flow, status)
+        e[3].record()
+    end.record()
+    torch.cuda.synchronize()
+    t_host = time.perf_counter() - t_host0
+    ms_total = start.elapsed_time(end)
+    ms_step = ms_total / K
+    t_detect = sum(e[0].elapsed_time(e[1]) for e in ev) / K
+    t_pyr = sum(e[1].elapsed_time(e[2]) for e in ev) / K
+    t_track = sum(e[2].elapsed_time(e[3]) for e in ev) / K
+
+    flops = pix_iters * FLOPS_PER_PIXEL_ITER
+    achieved = flops / (t_track * 1e-3) / 1e12
+    traffic = counter_traffic()
+    det_bytes = w["W"] * w["H"] + 8 * N
+    pyr_read = pyr_write = 0
+    Wl, Hl = w["W"], w["H"]
+    for _ in range(w["levels"] - 1):
+        pyr_read += 2 * Wl * Hl
+        Wl, Hl = (Wl + 1) // 2, (Hl + 1) // 2
+        pyr_write += 2 * Wl * Hl
+    out = {
+        "metric": METRIC,
+        "value": N / (ms_step * 1e-3),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "width": w["W"], "height": w["H"], "window": w["window"],
+                   "stride": w["stride"], "points": N, "levels": w["levels"], "support": w["support"],
+                   "max_iters": w["iters"], "input": "uint8 pair, layered affine motion up to 150 px"},
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_track",
+            "achieved": achieved,
+            "peak": PEAK_FP32_VALU_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VALU_TFLOPS,
+            "traffic": (traffic["fetch_bytes_per_launch"] + traffic["write_bytes_per_launch"]) if traffic else None,
+            "algorithmic_flops_per_launch": flops,
+            "pixel_iterations_per_launch": pix_iters,
+            "track_ms": t_track,
+        },
+        "kernels": {
+            "detect": {"ms": t_detect, "algorithmic_bytes": det_bytes,
+                       "hbm_frac": det_bytes / (t_detect * 1e-3) / (PEAK_HBM_GBPS * 1e9)},
+            "pyramids": {"ms": t_pyr, "launches": w["levels"] - 1, "algorithmic_bytes": pyr_read + pyr_write,
+                         "hbm_frac": (pyr_read + pyr_write) / (t_pyr * 1e-3) / (PEAK_HBM_GBPS * 1e9)},
+            "track": {"ms": t_track, "iterations": it_total, "status_counts": st_counts},
+        },
+        "host_wall_s": t_host,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(I0n, I1n, N, args.cpu_budget_s)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -153,6 +153,17 @@ int dgf_track(const dgf_image *I0, const dgf_image *I1, const float *points, int
               int32_t support, int32_t iters, const dgf_track_opts *opts, void *workspace,
               size_t ws_bytes, float *flow, uint8_t *status, int32_t *iters_out, void *stream);
 
+/* The two stages of dgf_track, for callers that time or reuse them separately:
+ * dgf_track_pyramids builds levels 1 .. levels-1 of both images into `workspace` (same layout
+ * and size as dgf_track uses); dgf_track_run then tracks on those pyramids without rebuilding
+ * them (the workspace must hold the pyramids of exactly these I0/I1 and levels).  Arguments
+ * and outputs as for dgf_track. */
+int dgf_track_pyramids(const dgf_image *I0, const dgf_image *I1, int32_t levels, void *workspace, size_t ws_bytes,
+                       void *stream);
+int dgf_track_run(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
+                  int32_t support, int32_t iters, const dgf_track_opts *opts, const void *workspace,
+                  size_t ws_bytes, float *flow, uint8_t *status, int32_t *iters_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -49,6 +49,8 @@ SIGNATURES = {
     "dgf_pyramid": (ctypes.c_int, [IMG, I32, P, SZ, P]),
     "dgf_track_workspace_bytes": (SZ, [I32, I32, I32, I32]),
     "dgf_track": (ctypes.c_int, [IMG, IMG, P, I64, I32, I32, I32, OPTS, P, SZ, P, P, P, P]),
+    "dgf_track_pyramids": (ctypes.c_int, [IMG, IMG, I32, P, SZ, P]),
+    "dgf_track_run": (ctypes.c_int, [IMG, IMG, P, I64, I32, I32, I32, OPTS, P, SZ, P, P, P, P]),
 }
 
 

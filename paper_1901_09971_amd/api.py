@@ -54,13 +54,19 @@ def detect_count(width: int, height: int, window: int, stride: int) -> int:
 
 
 def detect(frame: torch.Tensor, window: int, stride: int, return_sel: bool = False,
-           return_response: bool = False):
-    """DeGraF key-points of a uint8 frame: float32 [N, 2] (x, y) in row-major window order."""
+           return_response: bool = False, out: torch.Tensor | None = None):
+    """DeGraF key-points of a uint8 frame: float32 [N, 2] (x, y) in row-major window order.
+    ``out`` (float32 [N, 2] device) receives the points instead of a new tensor."""
     img = _image(frame, "frame")
     n = detect_count(img.width, img.height, window, stride)
     if n < 0:
         raise ValueError("window and stride must be >= 1")
-    pts = torch.empty((n, 2), dtype=torch.float32, device=frame.device)
+    if out is not None:
+        if out.shape != (n, 2) or out.dtype != torch.float32 or not out.is_contiguous():
+            raise ValueError("out: expected a contiguous float32 [N, 2] tensor")
+        pts = out
+    else:
+        pts = torch.empty((n, 2), dtype=torch.float32, device=frame.device)
     sel = torch.empty(n, dtype=torch.uint8, device=frame.device) if return_sel else None
     resp = torch.empty(n, dtype=torch.float32, device=frame.device) if return_response else None
     check(lib().dgf_detect(ctypes.byref(img), window, stride, _ptr(pts), _ptr(sel), _ptr(resp), n, _stream()),
@@ -123,6 +129,29 @@ def track(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, levels: int,
     if return_iters:
         return flow, status, its
     return flow, status
+
+
+def track_pyramids(I0: torch.Tensor, I1: torch.Tensor, levels: int, workspace: torch.Tensor) -> None:
+    """First stage of :func:`track`: build both pyramids into ``workspace`` (uint8 device
+    tensor of at least track_workspace_bytes(...) bytes)."""
+    a, b = _image(I0, "I0"), _image(I1, "I1")
+    check(lib().dgf_track_pyramids(ctypes.byref(a), ctypes.byref(b), levels, _ptr(workspace), workspace.numel(),
+                                   _stream()), "dgf_track_pyramids")
+
+
+def track_run(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, levels: int, support: int, iters: int,
+              workspace: torch.Tensor, flow: torch.Tensor, status: torch.Tensor, iters_out: torch.Tensor | None = None,
+              opts: TrackOpts | None = None) -> None:
+    """Second stage of :func:`track` on pyramids already built by :func:`track_pyramids`;
+    writes into the caller's ``flow`` (float32 [n, 2]) and ``status`` (uint8 [n])."""
+    a, b = _image(I0, "I0"), _image(I1, "I1")
+    n = points.shape[0]
+    if flow.shape != (n, 2) or flow.dtype != torch.float32 or status.shape != (n,) or status.dtype != torch.uint8:
+        raise ValueError("flow/status: wrong shape or dtype")
+    o = (opts or TrackOpts()).to_c()
+    check(lib().dgf_track_run(ctypes.byref(a), ctypes.byref(b), _ptr(points), n, levels, support, iters,
+                              ctypes.byref(o), _ptr(workspace), workspace.numel(), _ptr(flow), _ptr(status),
+                              _ptr(iters_out), _stream()), "dgf_track_run")
 
 
 INF = math.inf

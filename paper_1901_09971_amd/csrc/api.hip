@@ -127,13 +127,65 @@ size_t dgf_track_workspace_bytes(int32_t W, int32_t H, int32_t levels, int32_t d
     return 2 * dgf_pyramid_layout(W, H, levels, dtype, nullptr, nullptr) + 256;
 }
 
-int dgf_track(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
-              int32_t support, int32_t iters, const dgf_track_opts *opts, void *workspace, size_t ws_bytes,
-              float *flow, uint8_t *status, int32_t *iters_out, void *stream)
+namespace {
+
+int check_pair(const dgf_image *I0, const dgf_image *I1, int32_t levels)
 {
     if (!image_ok(I0) || !image_ok(I1)) return DGF_ERR_INVALID_ARG;
     if (I0->width != I1->width || I0->height != I1->height || I0->dtype != I1->dtype) return DGF_ERR_INVALID_ARG;
-    if (levels < 1 || levels > DGF_MAX_LEVELS || iters < 1) return DGF_ERR_INVALID_ARG;
+    if (levels < 1 || levels > DGF_MAX_LEVELS) return DGF_ERR_INVALID_ARG;
+    return DGF_OK;
+}
+
+// Level descriptors of both pyramids inside a track workspace (level 0 = the inputs).
+void pyramid_levels(const dgf_image *I0, const dgf_image *I1, int32_t levels, const void *workspace, LevelPair *lv,
+                    PyrJob *jobs /* nullable, [levels][2] */)
+{
+    int64_t off[DGF_MAX_LEVELS], pitch[DGF_MAX_LEVELS];
+    const size_t pyr_bytes = dgf_pyramid_layout(I0->width, I0->height, levels, I0->dtype, off, pitch);
+    uint8_t *ws0 = (uint8_t *)workspace;
+    uint8_t *ws1 = ws0 ? ws0 + pyr_bytes : nullptr;
+    lv[0] = LevelPair{(const uint8_t *)I0->data, (const uint8_t *)I1->data, I0->pitch_bytes, I1->pitch_bytes, I0->width,
+                      I0->height};
+    int W = I0->width, H = I0->height;
+    for (int l = 1; l < levels; ++l) {
+        if (jobs) {
+            jobs[2 * l] = PyrJob{lv[l - 1].p0, ws0 + off[l], lv[l - 1].pitch0, pitch[l], W, H};
+            jobs[2 * l + 1] = PyrJob{lv[l - 1].p1, ws1 + off[l], lv[l - 1].pitch1, pitch[l], W, H};
+        }
+        W = (W + 1) / 2;
+        H = (H + 1) / 2;
+        lv[l] = LevelPair{ws0 + off[l], ws1 + off[l], pitch[l], pitch[l], W, H};
+    }
+}
+
+} // namespace
+
+int dgf_track_pyramids(const dgf_image *I0, const dgf_image *I1, int32_t levels, void *workspace, size_t ws_bytes,
+                       void *stream)
+{
+    const int rc = check_pair(I0, I1, levels);
+    if (rc != DGF_OK) return rc;
+    if (levels == 1) return DGF_OK;
+    if (!workspace || ws_bytes < dgf_track_workspace_bytes(I0->width, I0->height, levels, I0->dtype))
+        return DGF_ERR_WORKSPACE;
+    LevelPair lv[DGF_MAX_LEVELS];
+    PyrJob jobs[2 * DGF_MAX_LEVELS];
+    pyramid_levels(I0, I1, levels, workspace, lv, jobs);
+    for (int l = 1; l < levels; ++l) {
+        const hipError_t e = launch_pyr_level(&jobs[2 * l], 2, I0->dtype, (hipStream_t)stream);
+        if (e != hipSuccess) return DGF_ERR_HIP;
+    }
+    return DGF_OK;
+}
+
+int dgf_track_run(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
+                  int32_t support, int32_t iters, const dgf_track_opts *opts, const void *workspace, size_t ws_bytes,
+                  float *flow, uint8_t *status, int32_t *iters_out, void *stream)
+{
+    int rc = check_pair(I0, I1, levels);
+    if (rc != DGF_OK) return rc;
+    if (iters < 1) return DGF_ERR_INVALID_ARG;
     if (support < 1 || (support & 1) == 0 || support > DGF_MAX_SUPPORT) return DGF_ERR_INVALID_ARG;
     if (n < 0) return DGF_ERR_INVALID_ARG;
     if (n > 0 && (!points || !flow || !status)) return DGF_ERR_INVALID_ARG;
@@ -146,32 +198,16 @@ int dgf_track(const dgf_image *I0, const dgf_image *I1, const float *points, int
     }
     if (!(o.sigma1 >= 0.f) || !(o.sigma2 >= 0.f) || !(o.eps_coarse >= 0.f) || !(o.eps_fine >= 0.f) || isnan(o.min_eig))
         return DGF_ERR_INVALID_ARG;
-    const size_t need = dgf_track_workspace_bytes(I0->width, I0->height, levels, I0->dtype);
-    if (levels > 1 && (!workspace || ws_bytes < need)) return DGF_ERR_WORKSPACE;
+    if (levels > 1 && (!workspace || ws_bytes < dgf_track_workspace_bytes(I0->width, I0->height, levels, I0->dtype)))
+        return DGF_ERR_WORKSPACE;
     TrackTuning tune = tuning_for(support, levels, I0->dtype, n);
     if (pick_ppl_max(support, tune.lpp) < 0) return DGF_ERR_UNSUPPORTED;
     while (track_lds_bytes(support, tune) > kMaxLdsPerBlock && tune.wpb > 1) tune.wpb /= 2;
     if (track_lds_bytes(support, tune) > kMaxLdsPerBlock) return DGF_ERR_UNSUPPORTED;
     if (n == 0) return DGF_OK;
 
-    hipStream_t st = (hipStream_t)stream;
     TrackParams P{};
-    int64_t off[DGF_MAX_LEVELS], pitch[DGF_MAX_LEVELS];
-    const size_t pyr_bytes = dgf_pyramid_layout(I0->width, I0->height, levels, I0->dtype, off, pitch);
-    uint8_t *ws0 = (uint8_t *)workspace;
-    uint8_t *ws1 = ws0 ? ws0 + pyr_bytes : nullptr;
-    P.lv[0] = LevelPair{(const uint8_t *)I0->data, (const uint8_t *)I1->data, I0->pitch_bytes, I1->pitch_bytes,
-                        I0->width, I0->height};
-    int W = I0->width, H = I0->height;
-    for (int l = 1; l < levels; ++l) {
-        PyrJob jobs[2] = {{P.lv[l - 1].p0, ws0 + off[l], P.lv[l - 1].pitch0, pitch[l], W, H},
-                          {P.lv[l - 1].p1, ws1 + off[l], P.lv[l - 1].pitch1, pitch[l], W, H}};
-        const hipError_t e = launch_pyr_level(jobs, 2, I0->dtype, st);
-        if (e != hipSuccess) return DGF_ERR_HIP;
-        W = (W + 1) / 2;
-        H = (H + 1) / 2;
-        P.lv[l] = LevelPair{ws0 + off[l], ws1 + off[l], pitch[l], pitch[l], W, H};
-    }
+    pyramid_levels(I0, I1, levels, workspace, P.lv, nullptr);
     P.pts = points;
     P.n = n;
     P.flow = flow;
@@ -181,7 +217,24 @@ int dgf_track(const dgf_image *I0, const dgf_image *I1, const float *points, int
     P.iters = iters;
     fill_track_geometry(P, support, tune.margin, tune.lpp);
     fill_track_constants(P, o, support);
-    return hip_rc(launch_track(P, tune, I0->dtype, st));
+    return hip_rc(launch_track(P, tune, I0->dtype, (hipStream_t)stream));
+}
+
+int dgf_track(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
+              int32_t support, int32_t iters, const dgf_track_opts *opts, void *workspace, size_t ws_bytes,
+              float *flow, uint8_t *status, int32_t *iters_out, void *stream)
+{
+    // validate everything first, so that an error launches nothing
+    int rc = dgf_track_run(I0, I1, points, 0, levels, support, iters, opts, workspace, ws_bytes, flow, status,
+                           iters_out, stream);
+    if (rc != DGF_OK) return rc;
+    if (n < 0) return DGF_ERR_INVALID_ARG;
+    if (n > 0 && (!points || !flow || !status)) return DGF_ERR_INVALID_ARG;
+    if (n == 0) return DGF_OK;
+    rc = dgf_track_pyramids(I0, I1, levels, workspace, ws_bytes, stream);
+    if (rc != DGF_OK) return rc;
+    return dgf_track_run(I0, I1, points, n, levels, support, iters, opts, workspace, ws_bytes, flow, status,
+                         iters_out, stream);
 }
 
 } // extern "C"

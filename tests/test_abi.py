@@ -1,0 +1,125 @@
+"""CPU checks of the C ABI: the library loads, exports every function the header declares, and
+its host-only entry points (sizes, layouts, defaults, argument validation that returns before
+any launch) behave as documented.  No compute call is made."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1901_09971_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER_DIR = os.path.join(ROOT, "include")
+
+
+def _declared():
+    names = set()
+    for f in os.listdir(HEADER_DIR):
+        if f.endswith(".h"):
+            text = open(os.path.join(HEADER_DIR, f)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(dgf_[a-z0-9_]+)\s*\(", text))
+    return names
+
+
+def test_header_declares_and_library_exports_everything():
+    declared = _declared()
+    assert "dgf_detect" in declared and "dgf_track" in declared
+    L = _lib.lib()
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\b(dgf_[a-z0-9_]+)\b", out))
+    assert declared <= exported
+    # the Python signature table covers exactly the declared functions
+    assert set(_lib.SIGNATURES) == declared
+
+
+def test_strerror_version_defaults():
+    L = _lib.lib()
+    for code in (0, -1, -2, -3, -4, -5, 17):
+        assert isinstance(L.dgf_strerror(code), bytes) and len(L.dgf_strerror(code)) > 0
+    assert L.dgf_version() >= 100
+    o = _lib.DgfTrackOpts()
+    assert L.dgf_track_opts_default(ctypes.byref(o)) == 0
+    assert (o.sigma1, o.sigma2) == (8.0, 32.0)
+    assert abs(o.eps_coarse - 1e-2) < 1e-9 and abs(o.eps_fine - 1e-4) < 1e-10
+    assert abs(o.min_eig - 6.5025) < 1e-4 and o.flags == 0
+    assert L.dgf_track_opts_default(None) == -1
+
+
+@pytest.mark.parametrize("W,H,w,d,n", [(256, 128, 9, 8, 465), (1242, 375, 9, 5, 18278), (1242, 375, 3, 9, 5796),
+                                       (2048, 1024, 9, 2, 518160), (8, 8, 9, 1, 0), (9, 9, 9, 4, 1)])
+def test_detect_count(W, H, w, d, n):
+    assert _lib.lib().dgf_detect_count(W, H, w, d) == n
+    assert _lib.lib().dgf_detect_count(W, H, 0, d) == -1
+
+
+def test_pyramid_layout_and_workspace():
+    L = _lib.lib()
+    off = (ctypes.c_int64 * 12)()
+    pit = (ctypes.c_int64 * 12)()
+    total = L.dgf_pyramid_layout(1242, 375, 5, 0, off, pit)
+    dims = [(621, 188), (311, 94), (156, 47), (78, 24)]
+    for l, (w, h) in enumerate(dims, start=1):
+        assert pit[l] >= w and pit[l] % 64 == 0 and off[l] % 256 == 0
+        if l > 1:
+            assert off[l] >= off[l - 1] + pit[l - 1] * dims[l - 2][1]
+    assert total >= off[4] + pit[4] * 24
+    assert L.dgf_pyramid_layout(1242, 375, 1, 0, None, None) == 0
+    assert L.dgf_pyramid_layout(1242, 375, 13, 0, None, None) == 0
+    assert L.dgf_pyramid_layout(0, 375, 3, 0, None, None) == 0
+    f32 = L.dgf_pyramid_layout(1242, 375, 5, 1, None, None)
+    assert f32 >= 4 * 621 * 188
+    assert L.dgf_track_workspace_bytes(1242, 375, 5, 0) >= 2 * total
+    assert L.dgf_track_workspace_bytes(1242, 375, 5, 7) == 0
+
+
+def _img(data=1 << 20, w=64, h=48, pitch=64, dtype=0):
+    return _lib.DgfImage(data, w, h, pitch, dtype)
+
+
+def test_argument_validation_before_launch():
+    """Every one of these is rejected on the host; nothing is launched (no GPU here)."""
+    L = _lib.lib()
+    bad = [_img(data=0), _img(w=0), _img(pitch=10), _img(dtype=5), _img(dtype=1, pitch=100)]
+    for im in bad:
+        assert L.dgf_detect(ctypes.byref(im), 9, 8, ctypes.c_void_p(1 << 20), None, None, 100, None) == -1
+    im = _img()
+    assert L.dgf_detect(None, 9, 8, ctypes.c_void_p(1 << 20), None, None, 100, None) == -1
+    assert L.dgf_detect(ctypes.byref(_img(dtype=1, pitch=256)), 9, 8, ctypes.c_void_p(1 << 20), None, None, 100,
+                        None) == -1
+    assert L.dgf_detect(ctypes.byref(im), 9, 0, ctypes.c_void_p(1 << 20), None, None, 100, None) == -1
+    assert L.dgf_detect(ctypes.byref(im), 129, 8, ctypes.c_void_p(1 << 20), None, None, 100, None) == -1
+    assert L.dgf_detect(ctypes.byref(im), 9, 8, ctypes.c_void_p(1 << 20), None, None, 3, None) == -2
+    assert L.dgf_detect(ctypes.byref(im), 9, 8, None, None, None, 100, None) == -1
+    # image smaller than the window: nothing to do, nothing launched
+    assert L.dgf_detect(ctypes.byref(_img(w=5, h=5, pitch=5)), 9, 8, None, None, None, 0, None) == 0
+
+    P = ctypes.c_void_p(1 << 20)
+    ws = L.dgf_track_workspace_bytes(64, 48, 3, 0)
+
+    def track(I0=im, I1=im, pts=P, n=10, levels=3, s=9, iters=10, opts=None, wsp=P, wsb=ws, flow=P, st=P):
+        return L.dgf_track(ctypes.byref(I0), ctypes.byref(I1), pts, n, levels, s, iters, opts, wsp, wsb, flow, st, None,
+                           None)
+
+    assert track(I1=_img(w=63)) == -1
+    assert track(I1=_img(dtype=1, pitch=256)) == -1
+    assert track(levels=0) == -1 and track(levels=13) == -1
+    assert track(s=8) == -1 and track(s=33) == -1 and track(s=0) == -1
+    assert track(iters=0) == -1
+    assert track(n=-1) == -1
+    assert track(pts=None) == -1 and track(flow=None) == -1 and track(st=None) == -1
+    assert track(wsp=None) == -5 and track(wsb=ws - 1) == -5
+    o = _lib.DgfTrackOpts(8, 32, 1e-2, 1e-4, 6.5, 1)
+    assert track(opts=ctypes.pointer(o)) == -3
+    o = _lib.DgfTrackOpts(float("nan"), 32, 1e-2, 1e-4, 6.5, 0)
+    assert track(opts=ctypes.pointer(o)) == -1
+    # n = 0 validates and launches nothing
+    assert track(n=0, pts=None, flow=None, st=None) == 0
+    assert L.dgf_pyramid(ctypes.byref(im), 3, None, 0, None) == -5
+    assert L.dgf_pyramid(ctypes.byref(im), 1, None, 0, None) == 0
+    assert L.dgf_track_pyramids(ctypes.byref(im), ctypes.byref(_img(h=47)), 3, P, ws, None) == -1
+    assert L.dgf_track_pyramids(ctypes.byref(im), ctypes.byref(im), 3, P, ws - 1, None) == -5
