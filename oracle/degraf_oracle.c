@@ -215,18 +215,6 @@ double or_bilinear(const double *I, int W, int H, double x, double y)
     return (1.0 - fy) * ((1.0 - fx) * i00 + fx * i10) + fy * ((1.0 - fx) * i01 + fx * i11);
 }
 
-/* Central-difference image gradient on the integer grid with replicated border. */
-static void gradients(const double *I, int W, int H, double *gx, double *gy)
-{
-    for (int y = 0; y < H; ++y)
-        for (int x = 0; x < W; ++x) {
-            int xl = clampi(x - 1, 0, W - 1), xr = clampi(x + 1, 0, W - 1);
-            int yu = clampi(y - 1, 0, H - 1), yd = clampi(y + 1, 0, H - 1);
-            gx[(int64_t)y * W + x] = 0.5 * (I[(int64_t)y * W + xr] - I[(int64_t)y * W + xl]);
-            gy[(int64_t)y * W + x] = 0.5 * (I[(int64_t)yd * W + x] - I[(int64_t)yu * W + x]);
-        }
-}
-
 /* ------------------------------------------------------------------------------------------ */
 /* Robust norm                                                                                */
 /* ------------------------------------------------------------------------------------------ */
@@ -269,22 +257,16 @@ typedef struct {
     int levels;
     int W[32], H[32];
     double *img[32]; /* level images */
-    double *gx[32], *gy[32];
 } pyr_t;
 
 static void pyr_free(pyr_t *p)
 {
-    for (int l = 0; l < p->levels; ++l) {
-        free(p->img[l]);
-        free(p->gx[l]);
-        free(p->gy[l]);
-    }
+    for (int l = 0; l < p->levels; ++l) free(p->img[l]);
 }
 
 /* dtype 0: uint8 input, levels are uint8 images (integer rounding), converted to double;
  * dtype 1: double input, levels are exact double reductions. */
-static int pyr_build(pyr_t *p, const void *src, int dtype, int W, int H, int64_t pitch, int levels,
-                     int with_grad)
+static int pyr_build(pyr_t *p, const void *src, int dtype, int W, int H, int64_t pitch, int levels)
 {
     memset(p, 0, sizeof(*p));
     p->levels = levels;
@@ -320,12 +302,6 @@ static int pyr_build(pyr_t *p, const void *src, int dtype, int W, int H, int64_t
                 or_pyr_down_f64(p->img[l - 1], dims[2 * l - 2], dims[2 * l - 1], p->img[l]);
             }
         }
-        if (with_grad) {
-            p->gx[l] = (double *)malloc(sizeof(double) * (size_t)Wl * Hl);
-            p->gy[l] = (double *)malloc(sizeof(double) * (size_t)Wl * Hl);
-            if (!p->gx[l] || !p->gy[l]) return OR_ERR_MEM;
-            gradients(p->img[l], Wl, Hl, p->gx[l], p->gy[l]);
-        }
     }
     free(u8prev);
     return OR_OK;
@@ -347,7 +323,8 @@ typedef struct {
  * Reading of the robust local flow iteration (the paper cites it without restating it):
  *   g = 0 at the coarsest level.  For l = L-1 .. 0, with p_l = p / 2^l and support offsets
  *   k in [-r, r]^2 (s = 2r + 1):
- *     T_k = B(I0_l, p_l + k), g_k = (B(Gx_l, p_l + k), B(Gy_l, p_l + k)), G0 = sum g_k g_k^T.
+ *     T_k = B(I0_l, p_l + k), g_k = (B(I0_l, p_l + k + e_x) - B(I0_l, p_l + k - e_x)) / 2 and the
+ *     same along y (central differences of the bilinear interpolant), G0 = sum g_k g_k^T.
  *     If lambda_min(G0)/s^2 < min_eig the point is ill-conditioned: u = 2^l g, stop.
  *     d = 0; repeat up to iters times:
  *        r_k = B(I1_l, p_l + k + g + d) - T_k,  w_k = psi(r_k)/r_k,
@@ -385,15 +362,17 @@ static void track_point(const pyr_t *P0, const pyr_t *P1, double px, double py, 
         const double plx = px * scale, ply = py * scale;
         const int Wl = P0->W[l], Hl = P0->H[l];
 
-        /* template and its gradient */
+        /* template and its gradient: value of the bilinear interpolant of the border-replicated
+         * level image, and central differences of that interpolant at +-1 px */
         double a = 0.0, b = 0.0, c = 0.0; /* G0 = [[a, b], [b, c]] */
+        const double *I0l = P0->img[l];
         for (int ky = -r; ky <= r; ++ky)
             for (int kx = -r; kx <= r; ++kx) {
                 int k = (ky + r) * s + (kx + r);
                 double x = plx + kx, y = ply + ky;
-                T[k] = or_bilinear(P0->img[l], Wl, Hl, x, y);
-                gxk[k] = or_bilinear(P0->gx[l], Wl, Hl, x, y);
-                gyk[k] = or_bilinear(P0->gy[l], Wl, Hl, x, y);
+                T[k] = or_bilinear(I0l, Wl, Hl, x, y);
+                gxk[k] = 0.5 * (or_bilinear(I0l, Wl, Hl, x + 1.0, y) - or_bilinear(I0l, Wl, Hl, x - 1.0, y));
+                gyk[k] = 0.5 * (or_bilinear(I0l, Wl, Hl, x, y + 1.0) - or_bilinear(I0l, Wl, Hl, x, y - 1.0));
                 a += gxk[k] * gxk[k];
                 b += gxk[k] * gyk[k];
                 c += gyk[k] * gyk[k];
@@ -503,8 +482,8 @@ int or_track(const void *I0, const void *I1, int dtype, int W, int H, int64_t pi
     if (nthreads < 1) nthreads = 1;
     or_opts o = {sigma1, sigma2, eps_coarse, eps_fine, min_eig};
     pyr_t P0, P1;
-    int rc0 = pyr_build(&P0, I0, dtype, W, H, pitch, levels, 1);
-    int rc1 = pyr_build(&P1, I1, dtype, W, H, pitch, levels, 0);
+    int rc0 = pyr_build(&P0, I0, dtype, W, H, pitch, levels);
+    int rc1 = pyr_build(&P1, I1, dtype, W, H, pitch, levels);
     if (rc0 != OR_OK || rc1 != OR_OK) {
         pyr_free(&P0);
         pyr_free(&P1);
@@ -555,8 +534,8 @@ static void bilinear_taps(int W, int H, double x, double y, int64_t idx[4], doub
  *   dL/dI1[q] = - sum_k psi'(r_k) (mu . g_k) beta_k(q)
  *   dL/dI0[q] = + sum_k psi'(r_k) (mu . g_k) alpha_k(q) - sum_k psi(r_k) mu . dg_k/dI0[q]
  * where alpha_k, beta_k are the bilinear tap weights of the template sample and of the I1
- * sample, and g_k is the bilinear sample of the central-difference gradient image, so
- * dg_k/dI0 is that difference stencil pushed through alpha_k.  Only the level-0 images
+ * sample, and g_k = (B(I0, x_k + e_x) - B(I0, x_k - e_x)) / 2 (and along y), so dg_k/dI0 is the
+ * difference of the tap weights of the two shifted samples, halved.  Only the level-0 images
  * enter: coarser levels decide which fixed point is reached but not its local dependence.
  * Results are ADDED to dI0 and dI1 ([H][W] doubles).  I0, I1 are double images, pitch W.
  */
@@ -567,14 +546,6 @@ int or_track_grad(const double *I0, const double *I1, int W, int H, const double
     if (!I0 || !I1 || W <= 0 || H <= 0 || support < 1 || (support % 2) == 0) return OR_ERR_ARG;
     if (n > 0 && (!pts || !flow || !status || !dflow || !dI0 || !dI1)) return OR_ERR_ARG;
     const int r = support / 2;
-    double *gx = (double *)malloc(sizeof(double) * (size_t)W * H);
-    double *gy = (double *)malloc(sizeof(double) * (size_t)W * H);
-    if (!gx || !gy) {
-        free(gx);
-        free(gy);
-        return OR_ERR_MEM;
-    }
-    gradients(I0, W, H, gx, gy);
 
     for (int64_t i = 0; i < n; ++i) {
         if (status[i] != OR_ST_CONVERGED) continue;
@@ -587,7 +558,8 @@ int or_track_grad(const double *I0, const double *I1, int W, int H, const double
             for (int kx = -r; kx <= r; ++kx) {
                 double x = px + kx, y = py + ky;
                 double T = or_bilinear(I0, W, H, x, y);
-                double g0 = or_bilinear(gx, W, H, x, y), g1 = or_bilinear(gy, W, H, x, y);
+                double g0 = 0.5 * (or_bilinear(I0, W, H, x + 1.0, y) - or_bilinear(I0, W, H, x - 1.0, y));
+                double g1 = 0.5 * (or_bilinear(I0, W, H, x, y + 1.0) - or_bilinear(I0, W, H, x, y - 1.0));
                 int64_t idx[4]; double wt[4]; int cx[4], cy[4]; double fx, fy;
                 bilinear_taps(W, H, x + ux, y + uy, idx, wt, cx, cy, &fx, &fy);
                 double Jv = wt[0] * I1[idx[0]] + wt[1] * I1[idx[1]] + wt[2] * I1[idx[2]] + wt[3] * I1[idx[3]];
@@ -599,11 +571,10 @@ int or_track_grad(const double *I0, const double *I1, int W, int H, const double
                 J10 += dp * g1 * djx;
                 J11 += dp * g1 * djy;
             }
-        /* J^T mu = lambda */
+        /* J^T mu = lambda, with J^T = [[J00, J10], [J01, J11]] */
         const double lx = dflow[2 * i], ly = dflow[2 * i + 1];
         const double det = J00 * J11 - J01 * J10;
         if (!(det != 0.0) || !isfinite(det)) continue;
-        /* J^T = [[J00, J10], [J01, J11]] */
         const double mux = (J11 * lx - J10 * ly) / det;
         const double muy = (J00 * ly - J01 * lx) / det;
 
@@ -612,9 +583,20 @@ int or_track_grad(const double *I0, const double *I1, int W, int H, const double
                 double x = px + kx, y = py + ky;
                 int64_t ia[4]; double wa[4]; int ax[4], ay[4]; double fxa, fya;
                 bilinear_taps(W, H, x, y, ia, wa, ax, ay, &fxa, &fya);
-                double T = wa[0] * I0[ia[0]] + wa[1] * I0[ia[1]] + wa[2] * I0[ia[2]] + wa[3] * I0[ia[3]];
-                double g0 = wa[0] * gx[ia[0]] + wa[1] * gx[ia[1]] + wa[2] * gx[ia[2]] + wa[3] * gx[ia[3]];
-                double g1 = wa[0] * gy[ia[0]] + wa[1] * gy[ia[1]] + wa[2] * gy[ia[2]] + wa[3] * gy[ia[3]];
+                /* taps of the four shifted samples that form the template gradient */
+                int64_t ixp[4], ixm[4], iyp[4], iym[4];
+                double wxp[4], wxm[4], wyp[4], wym[4];
+                int dcx[4], dcy[4]; double dfx, dfy;
+                bilinear_taps(W, H, x + 1.0, y, ixp, wxp, dcx, dcy, &dfx, &dfy);
+                bilinear_taps(W, H, x - 1.0, y, ixm, wxm, dcx, dcy, &dfx, &dfy);
+                bilinear_taps(W, H, x, y + 1.0, iyp, wyp, dcx, dcy, &dfx, &dfy);
+                bilinear_taps(W, H, x, y - 1.0, iym, wym, dcx, dcy, &dfx, &dfy);
+                double T = 0.0, g0 = 0.0, g1 = 0.0;
+                for (int t = 0; t < 4; ++t) {
+                    T += wa[t] * I0[ia[t]];
+                    g0 += 0.5 * (wxp[t] * I0[ixp[t]] - wxm[t] * I0[ixm[t]]);
+                    g1 += 0.5 * (wyp[t] * I0[iyp[t]] - wym[t] * I0[iym[t]]);
+                }
                 int64_t ib[4]; double wb[4]; int bxx[4], byy[4]; double fxb, fyb;
                 bilinear_taps(W, H, x + ux, y + uy, ib, wb, bxx, byy, &fxb, &fyb);
                 double Jv = wb[0] * I1[ib[0]] + wb[1] * I1[ib[1]] + wb[2] * I1[ib[2]] + wb[3] * I1[ib[3]];
@@ -622,22 +604,16 @@ int or_track_grad(const double *I0, const double *I1, int W, int H, const double
                 double ps = or_psi(res, sigma1, sigma2);
                 double dp = or_dpsi(res, sigma1, sigma2);
                 double mg = mux * g0 + muy * g1;
+                const double cx = -ps * mux * 0.5, cy = -ps * muy * 0.5;
                 for (int t = 0; t < 4; ++t) {
                     dI1[ib[t]] -= dp * mg * wb[t];
                     dI0[ia[t]] += dp * mg * wa[t];
-                    /* g_k.x = sum_t alpha_t Gx[tap t], Gx[y][x] = (I0[y][x+1] - I0[y][x-1]) / 2 (clamped) */
-                    int xr = clampi(ax[t] + 1, 0, W - 1), xl = clampi(ax[t] - 1, 0, W - 1);
-                    int yd = clampi(ay[t] + 1, 0, H - 1), yu = clampi(ay[t] - 1, 0, H - 1);
-                    double cxw = -ps * mux * wa[t] * 0.5;
-                    double cyw = -ps * muy * wa[t] * 0.5;
-                    dI0[(int64_t)ay[t] * W + xr] += cxw;
-                    dI0[(int64_t)ay[t] * W + xl] -= cxw;
-                    dI0[(int64_t)yd * W + ax[t]] += cyw;
-                    dI0[(int64_t)yu * W + ax[t]] -= cyw;
+                    dI0[ixp[t]] += cx * wxp[t];
+                    dI0[ixm[t]] -= cx * wxm[t];
+                    dI0[iyp[t]] += cy * wyp[t];
+                    dI0[iym[t]] -= cy * wym[t];
                 }
             }
     }
-    free(gx);
-    free(gy);
     return OR_OK;
 }

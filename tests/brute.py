@@ -8,7 +8,8 @@ Nothing here is shared with the oracle or with the HIP library:
   binomial kernel [1, 4, 6, 4, 1] and replicated borders (``mode='nearest'``).
 * ``lk_pyramidal``: textbook least-squares pyramidal Lucas-Kanade (the limit of the robust
   tracker when both robust thresholds are infinite), vectorised over points, using
-  ``scipy.ndimage.map_coordinates(order=1, mode='nearest')`` for bilinear sampling.
+  ``scipy.ndimage.map_coordinates(order=1, mode='nearest')`` for bilinear sampling; the template
+  gradient is the central difference of the sampled image at +-1 px.
 """
 from __future__ import annotations
 
@@ -55,12 +56,6 @@ def _sample(img, xs, ys):
     return ndimage.map_coordinates(img, [ys.ravel(), xs.ravel()], order=1, mode="nearest").reshape(xs.shape)
 
 
-def _grad(img):
-    gx = 0.5 * (np.concatenate([img[:, 1:], img[:, -1:]], 1) - np.concatenate([img[:, :1], img[:, :-1]], 1))
-    gy = 0.5 * (np.concatenate([img[1:], img[-1:]], 0) - np.concatenate([img[:1], img[:-1]], 0))
-    return gx, gy
-
-
 def lk_pyramidal(I0, I1, pts, levels, support, iters, eps_coarse, eps_fine):
     """Least-squares pyramidal LK: per level, template at p/2^l + k, Gauss-Newton with the
     template gradient, stop when the step norm drops below eps, propagate 2 (g + d).
@@ -83,8 +78,8 @@ def lk_pyramidal(I0, I1, pts, levels, support, iters, eps_coarse, eps_fine):
         pl = pts / 2.0 ** l
         X, Y = pl[:, :1] + kx, pl[:, 1:] + ky
         T = _sample(P0[l], X, Y)
-        gxi, gyi = _grad(P0[l])
-        GX, GY = _sample(gxi, X, Y), _sample(gyi, X, Y)
+        GX = 0.5 * (_sample(P0[l], X + 1.0, Y) - _sample(P0[l], X - 1.0, Y))
+        GY = 0.5 * (_sample(P0[l], X, Y + 1.0) - _sample(P0[l], X, Y - 1.0))
         a, b, c = (GX * GX).sum(1), (GX * GY).sum(1), (GY * GY).sum(1)
         det = a * c - b * b
         d = np.zeros((n, 2))

@@ -171,10 +171,8 @@ def _fixed_point_residual(I0, I1, p, u, s, s1, s2):
     ky, kx = np.mgrid[-r:r + 1, -r:r + 1].astype(np.float64)
     X, Y = p[0] + kx.ravel(), p[1] + ky.ravel()
     samp = lambda img, x, y: ndimage.map_coordinates(img, [y, x], order=1, mode="nearest")
-    gx = 0.5 * (np.concatenate([I0[:, 1:], I0[:, -1:]], 1) - np.concatenate([I0[:, :1], I0[:, :-1]], 1))
-    gy = 0.5 * (np.concatenate([I0[1:], I0[-1:]], 0) - np.concatenate([I0[:1], I0[:-1]], 0))
     T = samp(I0, X, Y)
-    G = np.stack([samp(gx, X, Y), samp(gy, X, Y)], 1)
+    G = np.stack([0.5 * (samp(I0, X + 1, Y) - samp(I0, X - 1, Y)), 0.5 * (samp(I0, X, Y + 1) - samp(I0, X, Y - 1))], 1)
     res = samp(I1, X + u[0], Y + u[1]) - T
     ps = _psi_np(res, s1, s2)
     return (ps[:, None] * G).sum(0), (np.abs(ps)[:, None] * np.abs(G)).sum(0)
