@@ -70,7 +70,9 @@ typedef struct {
 typedef struct {
     float sigma1;     /* inner threshold, intensity units (default 8)                   */
     float sigma2;     /* outer threshold, intensity units (default 32); both INFINITY
-                         gives plain least-squares pyramidal Lucas-Kanade                */
+                         gives plain least-squares pyramidal Lucas-Kanade; sigma1 >=
+                         sigma2 gives a hard cutoff at sigma1; a finite sigma1 with an
+                         infinite sigma2 is rejected (DGF_ERR_INVALID_ARG)               */
     float eps_coarse; /* a level > 0 stops when |step|_2 < eps_coarse px (default 1e-2) */
     float eps_fine;   /* level 0 stops when |step|_2 < eps_fine px (default 1e-4)       */
     float min_eig;    /* ill-conditioned when lambda_min(G0)/s^2 < min_eig

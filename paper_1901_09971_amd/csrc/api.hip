@@ -198,10 +198,11 @@ int dgf_track_run(const dgf_image *I0, const dgf_image *I1, const float *points,
     }
     if (!(o.sigma1 >= 0.f) || !(o.sigma2 >= 0.f) || !(o.eps_coarse >= 0.f) || !(o.eps_fine >= 0.f) || isnan(o.min_eig))
         return DGF_ERR_INVALID_ARG;
+    if (isinf(o.sigma2) && !isinf(o.sigma1)) return DGF_ERR_INVALID_ARG; // no finite inner band with infinite outer
     if (levels > 1 && (!workspace || ws_bytes < dgf_track_workspace_bytes(I0->width, I0->height, levels, I0->dtype)))
         return DGF_ERR_WORKSPACE;
     TrackTuning tune = tuning_for(support, levels, I0->dtype, n);
-    if (pick_ppl_max(support, tune.lpp) < 0) return DGF_ERR_UNSUPPORTED;
+    if (!track_shape_ok(support, tune)) return DGF_ERR_UNSUPPORTED;
     while (track_lds_bytes(support, tune) > kMaxLdsPerBlock && tune.wpb > 1) tune.wpb /= 2;
     if (track_lds_bytes(support, tune) > kMaxLdsPerBlock) return DGF_ERR_UNSUPPORTED;
     if (n == 0) return DGF_OK;
@@ -215,7 +216,7 @@ int dgf_track_run(const dgf_image *I0, const dgf_image *I1, const float *points,
     P.iters_out = iters_out;
     P.L = levels;
     P.iters = iters;
-    fill_track_geometry(P, support, tune.margin, tune.lpp);
+    fill_track_geometry(P, support, tune.margin, tune.lpp, tune.kind);
     fill_track_constants(P, o, support);
     return hip_rc(launch_track(P, tune, I0->dtype, (hipStream_t)stream));
 }

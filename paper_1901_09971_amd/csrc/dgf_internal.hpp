@@ -39,7 +39,24 @@ __device__ __forceinline__ float readlane(float v, int l)
 
 // Sum of v over the LPP-lane group the calling lane belongs to (groups are aligned blocks of
 // LPP lanes), returned to every lane of the group.  Must be called with all 64 lanes active.
-// Rows of 16 lanes are reduced with DPP butterflies; rows are combined through readlane.
+// Rows of 16 lanes are reduced with DPP butterflies; rows are then combined with the gfx950
+// row-swap permutes (v_permlane16_swap / v_permlane32_swap), whose two outputs always add up to
+// the pairwise row sums, so the result is independent of which rows the swap exchanges.
+// One cross-row step of a group sum: after the 16-lane stage, LPP = 32 adds the partner row of
+// each 32-lane half (v_permlane16_swap), LPP = 64 adds the other half (v_permlane32_swap).
+template <int LPP>
+__device__ __forceinline__ float group_sum_cross(float v)
+{
+    const unsigned u = __builtin_bit_cast(unsigned, v);
+    if constexpr (LPP == 32) {
+        const auto p = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+        return __builtin_bit_cast(float, (unsigned)p[0]) + __builtin_bit_cast(float, (unsigned)p[1]);
+    } else {
+        const auto p = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+        return __builtin_bit_cast(float, (unsigned)p[0]) + __builtin_bit_cast(float, (unsigned)p[1]);
+    }
+}
+
 template <int LPP>
 __device__ __forceinline__ float group_sum(float v)
 {
@@ -47,17 +64,54 @@ __device__ __forceinline__ float group_sum(float v)
     v += dpp<0x4E>(v);  // quad_perm [2,3,0,1]
     v += dpp<0x141>(v); // row_half_mirror
     v += dpp<0x140>(v); // row_mirror
-    if constexpr (LPP == 16) {
-        return v;
-    } else {
-        const float r0 = readlane(v, 0), r1 = readlane(v, 16), r2 = readlane(v, 32), r3 = readlane(v, 48);
-        if constexpr (LPP == 32) {
-            return (threadIdx.x & 32) ? (r2 + r3) : (r0 + r1);
-        } else {
-            return (r0 + r1) + (r2 + r3);
-        }
+    if constexpr (LPP >= 32) {
+        const unsigned u = __builtin_bit_cast(unsigned, v);
+        const auto p = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+        v = __builtin_bit_cast(float, (unsigned)p[0]) + __builtin_bit_cast(float, (unsigned)p[1]);
     }
+    if constexpr (LPP == 64) {
+        const unsigned u = __builtin_bit_cast(unsigned, v);
+        const auto p = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+        v = __builtin_bit_cast(float, (unsigned)p[0]) + __builtin_bit_cast(float, (unsigned)p[1]);
+    }
+    return v;
 }
+
+// Sums of five values over all 64 lanes, returned wave-uniform.  Transposed reduction: the
+// half- and row-swap permutes add two different values in one step (each half, then each row,
+// keeps a different value), so only two registers remain for the in-row DPP butterflies.
+__device__ __forceinline__ void wave_sum5(float &a, float &b, float &c, float &d, float &e)
+{
+    auto swap32 = [](float x, float y) {
+        const auto p = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, y),
+                                                        false, false);
+        return __builtin_bit_cast(float, (unsigned)p[0]) + __builtin_bit_cast(float, (unsigned)p[1]);
+    };
+    auto swap16 = [](float x, float y) {
+        const auto p = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, y),
+                                                        false, false);
+        return __builtin_bit_cast(float, (unsigned)p[0]) + __builtin_bit_cast(float, (unsigned)p[1]);
+    };
+    // lanes 0-31 / 32-63 now hold half-sums of (a | d), (b | e), (c | 0)
+    const float x1 = swap32(a, d), x2 = swap32(b, e), x3 = swap32(c, 0.f);
+    // rows 0..3 of y1 hold 16-lane partials of a, b, d, e; rows 0 and 2 of y2 hold c
+    float y1 = swap16(x1, x2), y2 = swap16(x3, x3);
+    y1 += dpp<0xB1>(y1);
+    y2 += dpp<0xB1>(y2);
+    y1 += dpp<0x4E>(y1);
+    y2 += dpp<0x4E>(y2);
+    y1 += dpp<0x141>(y1);
+    y2 += dpp<0x141>(y2);
+    y1 += dpp<0x140>(y1);
+    y2 += dpp<0x140>(y2);
+    a = readlane(y1, 0);
+    b = readlane(y1, 16);
+    d = readlane(y1, 32);
+    e = readlane(y1, 48);
+    c = readlane(y2, 0);
+}
+
+__device__ __forceinline__ bool wave_all(bool p) { return __builtin_amdgcn_ballot_w64(!p) == 0ull; }
 
 template <typename PixT>
 __device__ __forceinline__ float load_px(const uint8_t *base, int64_t pitch, int x, int y)
@@ -86,19 +140,30 @@ struct TrackParams {
     int32_t L, s, r, iters;
     int32_t ppl;         // pixel slots per lane actually used (ceil(s^2 / LPP))
     int32_t M;           // I1 tile margin, px on each side
-    int32_t TW;          // I1 tile width = s + 1 + 2M
+    int32_t TW;          // I1 tile width = s + 1 + 2M (row pitch in LDS: the kernel's TP)
     int32_t RW;          // raw I0 tile width = s + 3
-    int32_t tile_floats; // LDS floats per point = max(RW^2, TW^2)
+    int32_t RPP;         // LDS row pitch of the raw / resampled I0 tiles (>= RW, chosen to spread banks)
+    int32_t tile_floats; // LDS floats per point = max(RW RPP + (s+2) RPP, TW * TP)
     float invTW, invRW;
+    float invBW;         // 1 / (s + 2)
+    int32_t mode;        // ROBUST_L2, ROBUST_HAMPEL or ROBUST_HARD
     float s1, s2, cmid;  // robust thresholds and sigma1 / (sigma2 - sigma1) (0 if unused)
+    float cs2;           // cmid * sigma2
     float eps2c, eps2f;  // squared stopping thresholds
     float min_eig_s2;    // min_eig * s^2
 };
+
+// How the robust weight w = psi(r)/r is evaluated (chosen on the host from sigma1, sigma2):
+//   ROBUST_L2     both thresholds infinite: w = 1 everywhere (plain least squares)
+//   ROBUST_HAMPEL sigma1 < sigma2 finite: w = min(1, max(cmid (sigma2 - |r|), 0) / |r|)
+//   ROBUST_HARD   sigma1 >= sigma2: w = 1 for |r| <= sigma1, else 0
+enum { ROBUST_L2 = 0, ROBUST_HAMPEL = 1, ROBUST_HARD = 2 };
 
 struct TrackTuning {
     int lpp;     // lanes per point: 16, 32 or 64
     int wpb;     // waves per workgroup: 1, 2, 4
     int margin;  // I1 tile margin M
+    int kind;    // 0: row-run kernel when compiled for this support, else generic; 1: generic
 };
 
 struct PyrJob {
@@ -114,9 +179,12 @@ hipError_t launch_detect(const uint8_t *img, int64_t pitch, int W, int H, int wi
 hipError_t launch_pyr_level(const PyrJob *jobs, int njobs, int dtype, hipStream_t st);
 hipError_t launch_track(const TrackParams &P, const TrackTuning &T, int dtype, hipStream_t st);
 int pick_ppl_max(int s, int lpp);
+bool run_shape_compiled(int lpp, int s);
+// true when a kernel is compiled for this support and launch shape
+bool track_shape_ok(int s, const TrackTuning &T);
 constexpr size_t kMaxLdsPerBlock = 64 * 1024;
 // LDS bytes of one tracker workgroup for this support and launch shape
 size_t track_lds_bytes(int s, const TrackTuning &T);
-void fill_track_geometry(TrackParams &P, int s, int margin, int lpp);
+void fill_track_geometry(TrackParams &P, int s, int margin, int lpp, int kind);
 
 } // namespace dgf

@@ -1,0 +1,358 @@
+// track_run_kernel.hpp -- the tracker of track_kernel.hpp with a row-run pixel layout (device code).
+//
+// Same method, same arithmetic per support pixel; only the assignment of support pixels to
+// lanes differs.  The support rows are cut into runs of R consecutive pixels (R divides s), and
+// each lane owns SEG runs.  Consequences on CDNA4:
+//   * the I1 samples of a run come from R + 1 columns of two tile rows: R + 1 ds_read2_b32 with
+//     immediate offsets off one base address per run (vertical lerp first, then horizontal, so
+//     neighbouring pixels share their taps);
+//   * the template of a run is built in registers from a 4 x (R + 3) patch of the raw I0 tile:
+//     value and central differences at +-1 px are read off the bilinearly resampled patch;
+//   * per-pixel state is just template value and gradient (3 registers), so 16 or 32 lanes per
+//     point fit, and the per-iteration reduction and 2x2 solve are amortised over 14-28 pixels
+//     per lane instead of 7.
+#pragma once
+
+#include "track_kernel.hpp"
+
+namespace dgf {
+
+// Five group sums at once, stage by stage, so that no DPP read waits on the add just before it.
+template <int LPP>
+__device__ __forceinline__ void group_sum5(float &a, float &b, float &c, float &d, float &e)
+{
+#define DGF_STAGE(CTRL)                                                                                                \
+    {                                                                                                                  \
+        const float ta = dpp<CTRL>(a), tb = dpp<CTRL>(b), tc = dpp<CTRL>(c), td = dpp<CTRL>(d), te = dpp<CTRL>(e);     \
+        a += ta;                                                                                                       \
+        b += tb;                                                                                                       \
+        c += tc;                                                                                                       \
+        d += td;                                                                                                       \
+        e += te;                                                                                                       \
+    }
+    if constexpr (LPP == 64) {
+        wave_sum5(a, b, c, d, e);
+        return;
+    }
+    DGF_STAGE(0xB1)
+    DGF_STAGE(0x4E)
+    DGF_STAGE(0x141)
+    DGF_STAGE(0x140)
+#undef DGF_STAGE
+    if constexpr (LPP == 32) {
+        a = group_sum_cross<32>(a);
+        b = group_sum_cross<32>(b);
+        c = group_sum_cross<32>(c);
+        d = group_sum_cross<32>(d);
+        e = group_sum_cross<32>(e);
+    }
+}
+
+template <int LPP, int SEG, int R, int TP, typename PixT>
+__global__ __launch_bounds__(256) void k_track_run(TrackParams P)
+{
+    constexpr int PPW = 64 / LPP;
+    constexpr int PPL = SEG * R;
+    extern __shared__ float smem[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    const int q = lane / LPP;
+    const int li = lane - q * LPP;
+    const int64_t pidx = ((int64_t)blockIdx.x * wpb + wave) * PPW + q;
+    float *tile = smem + (size_t)(wave * PPW + q) * P.tile_floats;
+
+    const int s = P.s, r = P.r, RW = P.RW, RP = P.RPP, TW = P.TW, M = P.M;
+    const int nseg_row = s / R; // runs per support row
+    const int nseg = s * nseg_row;
+
+    const bool valid = pidx < P.n;
+    float px = 0.f, py = 0.f;
+    if (valid) {
+        const float2 pp = reinterpret_cast<const float2 *>(P.pts)[pidx];
+        px = pp.x;
+        py = pp.y;
+    }
+    const int W0 = P.lv[0].W, H0 = P.lv[0].H;
+    int status = -1;
+    float ux = 0.f, uy = 0.f;
+    if (valid && !(px >= 0.f && py >= 0.f && px <= (float)(W0 - 1) && py <= (float)(H0 - 1))) status = DGF_ST_OUT_OF_BOUNDS;
+    bool active = valid && status < 0;
+    if (!active) {
+        px = 0.f;
+        py = 0.f;
+    }
+    float gX = 0.f, gY = 0.f, dX = 0.f, dY = 0.f;
+    bool conv0 = false;
+    int it_total = 0;
+
+    // run geometry: sb = row * TP + col0 of the run's first pixel in the I1 tile, rc = row << 8 |
+    // col0; unused runs point at 0 and carry zero gradients
+    int sb[SEG], rc[SEG];
+    unsigned vmask = 0u;
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) {
+        const int g = j * LPP + li;
+        const bool vg = g < nseg;
+        const int gg = vg ? g : 0;
+        const int row = gg / nseg_row;
+        const int col0 = (gg - row * nseg_row) * R;
+        sb[j] = row * TP + col0;
+        rc[j] = (row << 8) | col0;
+        vmask |= (vg ? 1u : 0u) << j;
+    }
+
+    float T[PPL], GX[PPL], GY[PPL];
+
+    for (int l = P.L - 1; l >= 0; --l) {
+        if (!wave_any(active)) break;
+        const LevelPair LV = P.lv[l];
+        const int Wl = LV.W, Hl = LV.H;
+        const float sc = __builtin_ldexpf(1.0f, -l);
+        const float plx = px * sc, ply = py * sc;
+        const float pbx = floorf(plx), pby = floorf(ply);
+        const float pfx = plx - pbx, pfy = ply - pby;
+        const int ibx = (int)pbx - r, iby = (int)pby - r;
+
+        // ---- template: raw I0_l patch (s+3)^2 with replicated border, row pitch RP
+        wave_sync();
+        for (int c = li; c < RW * RW; c += LPP) {
+            const int ty = (int)(((float)c + 0.5f) * P.invRW);
+            const int tx = c - ty * RW;
+            tile[ty * RP + tx] =
+                load_px<PixT>(LV.p0, LV.pitch0, clampi(ibx - 1 + tx, 0, Wl - 1), clampi(iby - 1 + ty, 0, Hl - 1));
+        }
+        wave_sync();
+        // value and central differences at +-1 px of the bilinearly resampled patch
+        {
+#pragma unroll
+            for (int j = 0; j < SEG; ++j) {
+                const int row = rc[j] >> 8, col0 = rc[j] & 255;
+                const float *rp = tile + row * RP + col0; // raw rows row .. row+3, cols col0 .. col0+R+2
+                float V0[R + 3], V1[R + 3], V2[R + 3];
+#pragma unroll
+                for (int cc = 0; cc < R + 3; ++cc) {
+                    const float r0 = rp[cc], r1 = rp[RP + cc], r2 = rp[2 * RP + cc], r3 = rp[3 * RP + cc];
+                    V0[cc] = fmaf(pfy, r1 - r0, r0);
+                    V1[cc] = fmaf(pfy, r2 - r1, r1);
+                    V2[cc] = fmaf(pfy, r3 - r2, r2);
+                }
+                float B1[R + 2];
+#pragma unroll
+                for (int cc = 0; cc < R + 2; ++cc) B1[cc] = fmaf(pfx, V1[cc + 1] - V1[cc], V1[cc]);
+                const bool vg = (vmask >> j) & 1u;
+#pragma unroll
+                for (int p = 0; p < R; ++p) {
+                    const float b0 = fmaf(pfx, V0[p + 2] - V0[p + 1], V0[p + 1]);
+                    const float b2 = fmaf(pfx, V2[p + 2] - V2[p + 1], V2[p + 1]);
+                    T[j * R + p] = vg ? B1[p + 1] : 0.f;
+                    GX[j * R + p] = vg ? 0.5f * (B1[p + 2] - B1[p]) : 0.f;
+                    GY[j * R + p] = vg ? 0.5f * (b2 - b0) : 0.f;
+                }
+            }
+        }
+        float a = 0.f, b = 0.f, c = 0.f;
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+            a = fmaf(GX[j], GX[j], a);
+            b = fmaf(GX[j], GY[j], b);
+            c = fmaf(GY[j], GY[j], c);
+        }
+        {
+            float z0 = 0.f, z1 = 0.f;
+            group_sum5<LPP>(a, b, c, z0, z1);
+        }
+        const float lam = 0.5f * (a + c) - sqrtf(0.25f * (a - c) * (a - c) + b * b);
+        if (active && !(lam >= P.min_eig_s2)) {
+            status = DGF_ST_ILL_CONDITIONED;
+            ux = __builtin_ldexpf(gX, l);
+            uy = __builtin_ldexpf(gY, l);
+            active = false;
+        }
+        const float det0 = a * c - b * b;
+        const float eps2 = (l > 0) ? P.eps2c : P.eps2f;
+
+        // ---- iterations
+        dX = 0.f;
+        dY = 0.f;
+        bool lvl_active = active, lvl_conv = false;
+        int ox1 = 0, oy1 = 0;
+        for (int it = 0; it < P.iters; ++it) {
+            if (!wave_any(lvl_active)) break;
+            const float tx = pfx + (gX + dX), ty = pfy + (gY + dY);
+            float flx = floorf(tx), fly = floorf(ty);
+            const float fx = tx - flx, fy = ty - fly;
+            flx = fminf(fmaxf(flx, -1048576.f), 1048576.f);
+            fly = fminf(fmaxf(fly, -1048576.f), 1048576.f);
+            const int bx = (int)pbx + (int)flx - r, by = (int)pby + (int)fly - r;
+            int dxo = bx - ox1, dyo = by - oy1;
+            const bool inr = dxo >= 0 && dxo <= 2 * M && dyo >= 0 && dyo <= 2 * M;
+            if (wave_any((it == 0) || (lvl_active && !inr))) {
+                wave_sync();
+                ox1 = bx - M;
+                oy1 = by - M;
+                for (int cc = li; cc < TW * TW; cc += LPP) {
+                    const int yy = (int)(((float)cc + 0.5f) * P.invTW);
+                    const int xx = cc - yy * TW;
+                    tile[yy * TP + xx] =
+                        load_px<PixT>(LV.p1, LV.pitch1, clampi(ox1 + xx, 0, Wl - 1), clampi(oy1 + yy, 0, Hl - 1));
+                }
+                wave_sync();
+                dxo = M;
+                dyo = M;
+            } else if (!inr) {
+                dxo = 0;
+                dyo = 0;
+            }
+            const float *tb = tile + dyo * TP + dxo;
+
+            // residuals of every pixel of this lane's runs
+            float RES[PPL];
+#pragma unroll
+            for (int j = 0; j < SEG; ++j) {
+                const float *rp = tb + sb[j];
+                float h[R + 1];
+#pragma unroll
+                for (int cc = 0; cc < R + 1; ++cc) {
+                    const float t0 = rp[cc], t1 = rp[TP + cc];
+                    h[cc] = fmaf(fy, t1 - t0, t0);
+                }
+#pragma unroll
+                for (int p = 0; p < R; ++p) RES[j * R + p] = fmaf(fx, h[p + 1] - h[p], h[p]) - T[j * R + p];
+            }
+
+            float G11, G12, G22, B1 = 0.f, B2 = 0.f, det;
+            if (P.mode == ROBUST_L2) {
+#pragma unroll
+                for (int j = 0; j < PPL; ++j) {
+                    B1 = fmaf(RES[j], GX[j], B1);
+                    B2 = fmaf(RES[j], GY[j], B2);
+                }
+                float z0 = 0.f, z1 = 0.f, z2 = 0.f;
+                group_sum5<LPP>(B1, B2, z0, z1, z2);
+                G11 = a;
+                G12 = b;
+                G22 = c;
+                det = det0;
+            } else {
+                G11 = 0.f;
+                G12 = 0.f;
+                G22 = 0.f;
+                if (P.mode == ROBUST_HAMPEL) {
+#pragma unroll
+                    for (int j = 0; j < PPL; ++j) {
+                        const float ar = fabsf(RES[j]);
+                        const float t = fmaxf(fmaf(-P.cmid, ar, P.cs2), 0.f);
+                        const float w = fminf(1.f, t * __builtin_amdgcn_rcpf(ar));
+                        const float ps = w * RES[j];
+                        const float wgx = w * GX[j], wgy = w * GY[j];
+                        G11 = fmaf(wgx, GX[j], G11);
+                        G12 = fmaf(wgx, GY[j], G12);
+                        G22 = fmaf(wgy, GY[j], G22);
+                        B1 = fmaf(ps, GX[j], B1);
+                        B2 = fmaf(ps, GY[j], B2);
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < PPL; ++j) {
+                        const float w = (fabsf(RES[j]) <= P.s1) ? 1.f : 0.f;
+                        const float ps = w * RES[j];
+                        const float wgx = w * GX[j], wgy = w * GY[j];
+                        G11 = fmaf(wgx, GX[j], G11);
+                        G12 = fmaf(wgx, GY[j], G12);
+                        G22 = fmaf(wgy, GY[j], G22);
+                        B1 = fmaf(ps, GX[j], B1);
+                        B2 = fmaf(ps, GY[j], B2);
+                    }
+                }
+                group_sum5<LPP>(G11, G12, G22, B1, B2);
+                det = G11 * G22 - G12 * G12;
+                const bool fb = lvl_active && !(det > 1e-6f * det0);
+                if (wave_any(fb)) {
+                    float C1 = 0.f, C2 = 0.f;
+#pragma unroll
+                    for (int j = 0; j < PPL; ++j) {
+                        C1 = fmaf(RES[j], GX[j], C1);
+                        C2 = fmaf(RES[j], GY[j], C2);
+                    }
+                    float z0 = 0.f, z1 = 0.f, z2 = 0.f;
+                    group_sum5<LPP>(C1, C2, z0, z1, z2);
+                    if (fb) {
+                        G11 = a;
+                        G12 = b;
+                        G22 = c;
+                        B1 = C1;
+                        B2 = C2;
+                        det = det0;
+                    }
+                }
+            }
+            const float inv = __builtin_amdgcn_rcpf(det);
+            const float sx = (G12 * B2 - G22 * B1) * inv;
+            const float sy = (G12 * B1 - G11 * B2) * inv;
+            if (lvl_active) {
+                ++it_total;
+                if (!(isfinite(sx) && isfinite(sy))) {
+                    status = DGF_ST_NOT_CONVERGED;
+                    ux = __builtin_nanf("");
+                    uy = __builtin_nanf("");
+                    active = false;
+                    lvl_active = false;
+                } else {
+                    dX += sx;
+                    dY += sy;
+                    if (sx * sx + sy * sy < eps2) {
+                        lvl_conv = true;
+                        lvl_active = false;
+                    }
+                }
+            }
+        }
+        if (l > 0) {
+            if (active) {
+                gX = 2.f * (gX + dX);
+                gY = 2.f * (gY + dY);
+            }
+        } else {
+            conv0 = lvl_conv;
+        }
+    }
+
+    if (valid && li == 0) {
+        if (status < 0) {
+            ux = gX + dX;
+            uy = gY + dY;
+            if (!conv0) {
+                status = DGF_ST_NOT_CONVERGED;
+            } else {
+                const float qx = px + ux, qy = py + uy;
+                status = (qx >= 0.f && qy >= 0.f && qx <= (float)(W0 - 1) && qy <= (float)(H0 - 1)) ? DGF_ST_CONVERGED
+                                                                                                 : DGF_ST_OUT_OF_BOUNDS;
+            }
+        }
+        reinterpret_cast<float2 *>(P.flow)[pidx] = make_float2(ux, uy);
+        P.status[pidx] = (uint8_t)status;
+        if (P.iters_out) P.iters_out[pidx] = it_total;
+    }
+}
+
+template <int LPP, int SEG, int R, int TP, typename PixT>
+hipError_t launch_track_run_t(const TrackParams &P, int wpb, hipStream_t st)
+{
+    constexpr int PPW = 64 / LPP;
+    const int64_t waves = (P.n + PPW - 1) / PPW;
+    const int64_t blocks = (waves + wpb - 1) / wpb;
+    const size_t lds = (size_t)wpb * PPW * P.tile_floats * sizeof(float);
+    hipLaunchKernelGGL((k_track_run<LPP, SEG, R, TP, PixT>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st, P);
+    return hipGetLastError();
+}
+
+// Row-run shapes compiled per element type: (LPP, SEG, R, TP, support s).  SEG runs of R pixels
+// per lane cover the s * (s / R) runs of an s x s support.  The odd tile pitch TP = 31 spreads
+// the runs of consecutive rows over different LDS banks (a pitch of 32 maps them onto 3).
+#define DGF_TRACK_RUN_SHAPES(X, PixT)                                                                                  \
+    X(64, 1, 7, 31, 21, PixT) X(32, 2, 7, 31, 21, PixT) X(16, 4, 7, 31, 21, PixT) X(32, 1, 3, 31, 9, PixT)             \
+    X(16, 2, 3, 31, 9, PixT) X(32, 2, 5, 31, 15, PixT) X(16, 3, 5, 31, 15, PixT) X(16, 1, 11, 31, 11, PixT)           \
+    X(16, 1, 7, 31, 7, PixT) X(16, 1, 5, 31, 5, PixT)
+
+} // namespace dgf

@@ -24,9 +24,18 @@ TrackTuning heuristic(int support)
 {
     const int px = support * support;
     TrackTuning t;
-    t.lpp = px >= 200 ? 64 : (px >= 64 ? 32 : 16);
-    t.wpb = 4;
-    t.margin = 4;
+    t.wpb = 1;
+    t.margin = 2;
+    t.kind = 0;
+    if (run_shape_compiled(64, support)) {
+        t.lpp = 64;
+    } else if (run_shape_compiled(32, support)) {
+        t.lpp = 32;
+    } else if (run_shape_compiled(16, support)) {
+        t.lpp = 16;
+    } else {
+        t.lpp = px >= 200 ? 64 : (px >= 64 ? 32 : 16);
+    }
     return t;
 }
 
@@ -37,7 +46,8 @@ bool tuning_valid(const TrackTuning &t, int support)
     if (t.lpp != 16 && t.lpp != 32 && t.lpp != 64) return false;
     if (t.wpb != 1 && t.wpb != 2 && t.wpb != 4) return false;
     if (t.margin < 1 || t.margin > 16) return false;
-    return pick_ppl_max(support, t.lpp) > 0;
+    if (t.kind != 0 && t.kind != 1) return false;
+    return track_shape_ok(support, t);
 }
 
 void set_tuning(int support, int dtype, const TrackTuning &t)
@@ -69,12 +79,17 @@ TrackTuning tuning_for(int support, int levels, int dtype, int64_t n)
     TrackTuning t;
     if (get_installed(support, dtype, &t)) return t;
     t = heuristic(support);
-    // DGF_TUNE="lpp,wpb,margin" overrides the heuristic (launch-shape experiments)
+    // DGF_TUNE="lpp,wpb,margin[,kind]" overrides the heuristic (launch-shape experiments)
     if (const char *env = getenv("DGF_TUNE")) {
         TrackTuning e = t;
-        if (sscanf(env, "%d,%d,%d", &e.lpp, &e.wpb, &e.margin) == 3 && tuning_valid(e, support)) t = e;
+        e.kind = 0;
+        const int k = sscanf(env, "%d,%d,%d,%d", &e.lpp, &e.wpb, &e.margin, &e.kind);
+        if (k >= 3 && tuning_valid(e, support)) t = e;
     }
-    if (!tuning_valid(t, support)) t.lpp = 64;
+    if (!tuning_valid(t, support)) {
+        t.lpp = 64;
+        t.kind = 1;
+    }
     return t;
 }
 
@@ -82,7 +97,17 @@ void fill_track_constants(TrackParams &P, const dgf_track_opts &o, int support)
 {
     P.s1 = o.sigma1;
     P.s2 = o.sigma2;
-    P.cmid = (o.sigma2 > o.sigma1 && isfinite(o.sigma2)) ? o.sigma1 / (o.sigma2 - o.sigma1) : 0.0f;
+    if (isinf(o.sigma1)) {
+        P.mode = ROBUST_L2; // |r| <= inf always: every weight is 1
+        P.cmid = 0.0f;
+    } else if (o.sigma2 > o.sigma1 && isfinite(o.sigma2)) {
+        P.mode = ROBUST_HAMPEL;
+        P.cmid = o.sigma1 / (o.sigma2 - o.sigma1);
+    } else {
+        P.mode = ROBUST_HARD; // empty middle band: w = 1 for |r| <= sigma1, else 0
+        P.cmid = 0.0f;
+    }
+    P.cs2 = P.cmid * o.sigma2;
     P.eps2c = o.eps_coarse * o.eps_coarse;
     P.eps2f = o.eps_fine * o.eps_fine;
     P.min_eig_s2 = o.min_eig * (float)(support * support);

@@ -59,7 +59,8 @@ def test_translation_f32_1242x375():
     _run(I0, I1, pts, 3, 9, 10, 0.99)
 
 
-@pytest.mark.parametrize("tune", ["16,4,4", "32,4,4", "64,4,4", "64,1,2", "32,2,8", "16,1,1"])
+@pytest.mark.parametrize("tune", ["16,4,4,0", "32,4,4,0", "64,4,4,0", "64,1,2,0", "32,2,8,0", "16,1,1,0",
+                                  "16,4,4,1", "32,1,3,1", "64,2,5,1", "64,1,2,1"])
 def test_launch_shapes(tune, monkeypatch):
     monkeypatch.setenv("DGF_TUNE", tune)
     I0, I1, _ = synth.noise_translation_pair(200, 150, seed=5, shift=(3.7, -2.2))
@@ -70,7 +71,7 @@ def test_launch_shapes(tune, monkeypatch):
     _run(I0, I1, pts, 4, 11, 20, 0.97)
 
 
-@pytest.mark.parametrize("s", [1, 3, 5, 15, 31])
+@pytest.mark.parametrize("s", [1, 3, 5, 7, 11, 15, 21, 23, 31])
 def test_support_sizes(s):
     I0, I1, _ = synth.noise_translation_pair(160, 120, seed=6, shift=(1.2, 0.9))
     pts = oracle.detect(I0, 9, 9)[0].astype(np.float32)
@@ -110,6 +111,14 @@ def test_iteration_counts_reported():
     assert np.all(its >= 3) and np.all(its <= 30)
     # same iteration count on the vast majority of points (stopping decisions in FP32 vs FP64)
     assert np.mean(its == o_its.sum(1)) > 0.95
+
+
+@pytest.mark.parametrize("tune", ["16,1,2,0", "32,1,2,0", "64,1,2,0", "64,1,2,1", "32,4,4,1"])
+def test_driving_support21_all_kernels(tune, monkeypatch):
+    monkeypatch.setenv("DGF_TUNE", tune)
+    I0, I1, _, _ = synth.layered_pair(480, 256, seed=4, max_disp=60.0)
+    pts = oracle.detect(I0, 9, 5)[0].astype(np.float32)
+    _run(I0, I1, pts, 4, 21, 20, 0.97)
 
 
 def test_deterministic():
