@@ -155,6 +155,27 @@ int dgf_track(const dgf_image *I0, const dgf_image *I1, const float *points, int
               int32_t support, int32_t iters, const dgf_track_opts *opts, void *workspace,
               size_t ws_bytes, float *flow, uint8_t *status, int32_t *iters_out, void *stream);
 
+/* ---- gradient of the tracked flow (implicit differentiation at the converged fixed point) ---- */
+
+/* Adds dL/dI0 and dL/dI1 for an upstream gradient dflow = dL/dflow of a previous dgf_track call
+ * on the same images, points and support.  At a CONVERGED point the level-0 flow u solves
+ * F(u) = sum_k psi(r_k) g_k = 0; with J = dF/du = sum_k psi'(r_k) g_k grad I1(p+k+u)^T and
+ * J^T mu = dflow_k, the point contributes
+ *   dI1[q] -= sum_k psi'(r_k) (mu . g_k) beta_k(q)
+ *   dI0[q] += sum_k psi'(r_k) (mu . g_k) alpha_k(q) - sum_k psi(r_k) mu . dg_k/dI0[q]
+ * (alpha, beta: bilinear tap weights of the template and I1 samples; g_k: central differences at
+ * +-1 px of the bilinear interpolant of I0).  Points with any other status, or a singular J,
+ * contribute nothing.  Points are treated as constants (detection is not differentiated).
+ *   I0, I1      : DGF_F32 images (DGF_ERR_UNSUPPORTED for DGF_U8)
+ *   flow,status : outputs of dgf_track for these inputs;  dflow: float[n][2]
+ *   dI0, dI1    : float images of the same size, with the row pitch of I0 and I1 respectively;
+ *                 ACCUMULATED into (zero them first), with device float atomics, so the order
+ *                 of additions (and the last bits) is not deterministic.
+ *   opts        : the tracker constants used in the forward call (nullable = defaults). */
+int dgf_track_backward(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t support,
+                       const dgf_track_opts *opts, const float *flow, const uint8_t *status, const float *dflow,
+                       float *dI0, float *dI1, void *stream);
+
 /* The two stages of dgf_track, for callers that time or reuse them separately:
  * dgf_track_pyramids builds levels 1 .. levels-1 of both images into `workspace` (same layout
  * and size as dgf_track uses); dgf_track_run then tracks on those pyramids without rebuilding

@@ -51,6 +51,7 @@ SIGNATURES = {
     "dgf_track": (ctypes.c_int, [IMG, IMG, P, I64, I32, I32, I32, OPTS, P, SZ, P, P, P, P]),
     "dgf_track_pyramids": (ctypes.c_int, [IMG, IMG, I32, P, SZ, P]),
     "dgf_track_run": (ctypes.c_int, [IMG, IMG, P, I64, I32, I32, I32, OPTS, P, SZ, P, P, P, P]),
+    "dgf_track_backward": (ctypes.c_int, [IMG, IMG, P, I64, I32, OPTS, P, P, P, P, P, P]),
 }
 
 

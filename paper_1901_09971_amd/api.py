@@ -154,4 +154,47 @@ def track_run(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, levels: 
                               _ptr(iters_out), _stream()), "dgf_track_run")
 
 
+def track_backward(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, support: int, flow: torch.Tensor,
+                   status: torch.Tensor, dflow: torch.Tensor, dI0: torch.Tensor, dI1: torch.Tensor,
+                   opts: TrackOpts | None = None) -> None:
+    """Accumulate dL/dI0 into ``dI0`` and dL/dI1 into ``dI1`` (float32, same shape and row stride
+    as the images) for the upstream gradient ``dflow`` of a forward :func:`track` call."""
+    a, b = _image(I0, "I0"), _image(I1, "I1")
+    for t, ref, name in ((dI0, I0, "dI0"), (dI1, I1, "dI1")):
+        if t.dtype != torch.float32 or t.shape != ref.shape or t.stride() != ref.stride() or not t.is_cuda:
+            raise ValueError(f"{name}: expected float32 with the shape and strides of the image")
+    n = points.shape[0]
+    dflow = dflow.contiguous().to(torch.float32)
+    o = (opts or TrackOpts()).to_c()
+    check(lib().dgf_track_backward(ctypes.byref(a), ctypes.byref(b), _ptr(points.contiguous()), n, support,
+                                   ctypes.byref(o), _ptr(flow.contiguous()), _ptr(status.contiguous()), _ptr(dflow),
+                                   _ptr(dI0), _ptr(dI1), _stream()), "dgf_track_backward")
+
+
+class TrackFn(torch.autograd.Function):
+    """flow, status = TrackFn.apply(I0, I1, points, levels, support, iters, opts)
+
+    Differentiable tracking of float32 frames: the backward pass is the implicit-function adjoint
+    at the converged level-0 fixed point (dgf_track_backward).  ``points`` are constants; points
+    that did not converge get no gradient."""
+
+    @staticmethod
+    def forward(ctx, I0, I1, points, levels, support, iters, opts=None):
+        flow, status = track(I0, I1, points, levels, support, iters, opts=opts)
+        ctx.save_for_backward(I0, I1, points, flow, status)
+        ctx.support = support
+        ctx.opts = opts
+        ctx.mark_non_differentiable(status)
+        return flow, status
+
+    @staticmethod
+    def backward(ctx, dflow, _dstatus):
+        I0, I1, points, flow, status = ctx.saved_tensors
+        dI0 = torch.zeros_like(I0)
+        dI1 = torch.zeros_like(I1)
+        if dflow is not None:
+            track_backward(I0, I1, points, ctx.support, flow, status, dflow, dI0, dI1, ctx.opts)
+        return dI0, dI1, None, None, None, None, None
+
+
 INF = math.inf
