@@ -31,7 +31,8 @@ PEAK_FP32_VALU_TFLOPS = 78.6       # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x
 PEAK_HBM_GBPS = 8000.0
 WORKLOAD = dict(name="driving_1242x375", W=1242, H=375, window=9, stride=5, levels=5, support=21, iters=20)
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "track_driving_1242x375_counters.md")
-TRACK_SOURCES = ["paper_1901_09971_amd/csrc/track.hip", "paper_1901_09971_amd/csrc/dgf_internal.hpp"]
+TRACK_SOURCES = ["paper_1901_09971_amd/csrc/track.hip", "paper_1901_09971_amd/csrc/track_kernel.hpp",
+                 "paper_1901_09971_amd/csrc/track_run_kernel.hpp", "paper_1901_09971_amd/csrc/dgf_internal.hpp"]
 
 
 def track_source_sha() -> str:
@@ -81,6 +82,71 @@ def cpu_baseline(I0, I1, n_points, budget_s):
                       f"{el:.1f} s wall"}
 
 
+def batched_vs_plain(reps: int):
+    """Frame-pairs/s on the 64-pair mixed set (four sizes, strides 3/5/8; 5 levels, 21x21, 20
+    iterations): per-pair launches (detect, 4 pyramid levels, track for each pair in turn) vs one
+    replay of the captured batched plan.  Same tracker launch shape in both."""
+    import torch
+
+    import paper_1901_09971_amd as dgf
+    from paper_1901_09971_amd import synth
+
+    L_, s_, it_ = 5, 21, 20
+    data = synth.batch64_mixed()
+    dev = torch.device("cuda", 0)
+    pairs = [(torch.from_numpy(d["I0"]).to(dev), torch.from_numpy(d["I1"]).to(dev), 9, d["stride"]) for d in data]
+    # plain: preallocated per-pair buffers
+    bufs = []
+    for a, b, w, d in pairs:
+        n = dgf.detect_count(a.shape[1], a.shape[0], w, d)
+        bufs.append(dict(p=torch.empty((n, 2), dtype=torch.float32, device=dev),
+                         f=torch.empty((n, 2), dtype=torch.float32, device=dev),
+                         s=torch.empty(n, dtype=torch.uint8, device=dev),
+                         ws=torch.empty(dgf.track_workspace_bytes(a.shape[1], a.shape[0], L_, 0), dtype=torch.uint8,
+                                        device=dev)))
+
+    def plain():
+        for (a, b, w, d), B in zip(pairs, bufs):
+            dgf.detect(a, w, d, out=B["p"])
+            dgf.track_pyramids(a, b, L_, B["ws"])
+            dgf.track_run(a, b, B["p"], L_, s_, it_, B["ws"], B["f"], B["s"])
+
+    plan = dgf.Batch(pairs, L_, s_, it_)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        plan.run()
+        plan.capture()
+    torch.cuda.synchronize()
+
+    def timed(fn, stream):
+        with torch.cuda.stream(stream):
+            for _ in range(2):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_plain = timed(plain, side)
+    t_batch = timed(plan.replay, side)
+    # the two forms must agree exactly
+    P = torch.cat([B["p"] for B in bufs])
+    S = torch.cat([B["s"] for B in bufs])
+    identical = bool(torch.equal(P, plan.points) and torch.equal(S, plan.status))
+    npts = plan.num_points
+    plan.close()
+    return {"pairs": len(pairs), "points": npts, "reps": reps,
+            "plain_ms": t_plain, "batched_ms": t_batch,
+            "plain_pairs_per_s": len(pairs) / (t_plain * 1e-3),
+            "batched_pairs_per_s": len(pairs) / (t_batch * 1e-3),
+            "speedup": t_plain / t_batch, "identical_outputs": identical,
+            "workload": "batch64_mixed: 16 each of 1242x375, 1224x370, 640x480, 320x240, strides {3,5,8}"}
+
+
 def copy_calibration(mib: int):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -100,6 +166,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=12.0)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-pair batched vs plain measurement")
+    ap.add_argument("--batch-reps", type=int, default=10)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -217,6 +285,8 @@ def main():
         },
         "host_wall_s": t_host,
     }
+    if not args.no_batch:
+        out["batched"] = batched_vs_plain(args.batch_reps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(I0n, I1n, N, args.cpu_budget_s)
     print(json.dumps(out))

@@ -176,6 +176,45 @@ int dgf_track_backward(const dgf_image *I0, const dgf_image *I1, const float *po
                        const dgf_track_opts *opts, const float *flow, const uint8_t *status, const float *dflow,
                        float *dI0, float *dI1, void *stream);
 
+/* ---- batched form: many pairs of uneven size and point count in one pass -------------------- */
+
+/* One frame pair of a batch: both images DGF_U8 of the same size; DeGraF grid of this pair. */
+typedef struct {
+    dgf_image I0, I1;
+    int32_t window, stride;
+} dgf_pair_desc;
+
+typedef struct dgf_batch dgf_batch; /* opaque plan */
+
+/* Builds a plan for detect + pyramids + track of every pair with common levels / support /
+ * iters / opts.  The images are referenced by pointer (their contents may change between runs;
+ * the pointers may not).  This call is the only one that allocates device memory (one buffer
+ * holding every pyramid and the descriptor tables, freed by dgf_batch_destroy) and it copies the
+ * tables to the device synchronously.  DGF_ERR_UNSUPPORTED if a pair's window / stride is too
+ * large for the LDS-tiled detector or the support has no kernel. */
+int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels, int32_t support, int32_t iters,
+                     const dgf_track_opts *opts, dgf_batch **out);
+
+/* Total number of points of all pairs (-1 for a null plan); outputs are concatenated in pair
+ * order, pair i at [offsets[i], offsets[i + 1]) (offsets: host array of npairs + 1). */
+int64_t dgf_batch_num_points(const dgf_batch *b);
+int dgf_batch_point_offsets(const dgf_batch *b, int64_t *offsets);
+
+/* Runs the plan on `stream`: one launch per pyramid level for all frames, one detection launch,
+ * a counter reset and one persistent tracking launch.  points: out float[N][2]; flow: out
+ * float[N][2]; status: out uint8[N]; iters_out: nullable int32[N].  Results equal those of
+ * per-pair dgf_detect + dgf_track with the same tuning. */
+int dgf_batch_run(dgf_batch *b, float *points, float *flow, uint8_t *status, int32_t *iters_out, void *stream);
+
+/* Captures the run sequence (with these output pointers) into a HIP graph on `stream` (a created
+ * stream, not the default one); dgf_batch_replay launches it with one call.  A new capture
+ * replaces the previous graph. */
+int dgf_batch_capture(dgf_batch *b, float *points, float *flow, uint8_t *status, void *stream);
+int dgf_batch_replay(dgf_batch *b, void *stream);
+
+/* Frees the plan and its device memory (after the work using it has completed). */
+int dgf_batch_destroy(dgf_batch *b);
+
 /* The two stages of dgf_track, for callers that time or reuse them separately:
  * dgf_track_pyramids builds levels 1 .. levels-1 of both images into `workspace` (same layout
  * and size as dgf_track uses); dgf_track_run then tracks on those pyramids without rebuilding

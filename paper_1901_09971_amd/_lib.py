@@ -27,6 +27,10 @@ class DgfTrackOpts(ctypes.Structure):
                 ("eps_fine", ctypes.c_float), ("min_eig", ctypes.c_float), ("flags", ctypes.c_int32)]
 
 
+class DgfPairDesc(ctypes.Structure):
+    _fields_ = [("I0", DgfImage), ("I1", DgfImage), ("window", ctypes.c_int32), ("stride", ctypes.c_int32)]
+
+
 class DgfError(RuntimeError):
     def __init__(self, code: int, where: str):
         super().__init__(f"{where}: {strerror(code)} ({code})")
@@ -52,6 +56,14 @@ SIGNATURES = {
     "dgf_track_pyramids": (ctypes.c_int, [IMG, IMG, I32, P, SZ, P]),
     "dgf_track_run": (ctypes.c_int, [IMG, IMG, P, I64, I32, I32, I32, OPTS, P, SZ, P, P, P, P]),
     "dgf_track_backward": (ctypes.c_int, [IMG, IMG, P, I64, I32, OPTS, P, P, P, P, P, P]),
+    "dgf_batch_create": (ctypes.c_int, [ctypes.POINTER(DgfPairDesc), I32, I32, I32, I32, OPTS,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "dgf_batch_num_points": (I64, [P]),
+    "dgf_batch_point_offsets": (ctypes.c_int, [P, P]),
+    "dgf_batch_run": (ctypes.c_int, [P, P, P, P, P, P]),
+    "dgf_batch_capture": (ctypes.c_int, [P, P, P, P, P]),
+    "dgf_batch_replay": (ctypes.c_int, [P, P]),
+    "dgf_batch_destroy": (ctypes.c_int, [P]),
 }
 
 

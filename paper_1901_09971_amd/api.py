@@ -197,4 +197,57 @@ class TrackFn(torch.autograd.Function):
         return dI0, dI1, None, None, None, None, None
 
 
+class Batch:
+    """Plan for detect + pyramids + track of many uint8 frame pairs of uneven size in one pass
+    (dgf_batch_*).  ``pairs`` is a list of (I0, I1, window, stride); the tensors are kept alive
+    by the plan.  Outputs of all pairs are concatenated in pair order (see ``offsets``)."""
+
+    def __init__(self, pairs, levels: int, support: int, iters: int, opts: TrackOpts | None = None):
+        self._keep = [(a, b) for a, b, _, _ in pairs]
+        descs = (_lib.DgfPairDesc * len(pairs))()
+        for i, (a, b, window, stride) in enumerate(pairs):
+            descs[i] = _lib.DgfPairDesc(_image(a, f"pairs[{i}].I0"), _image(b, f"pairs[{i}].I1"), window, stride)
+        o = (opts or TrackOpts()).to_c()
+        h = ctypes.c_void_p()
+        check(lib().dgf_batch_create(descs, len(pairs), levels, support, iters, ctypes.byref(o), ctypes.byref(h)),
+              "dgf_batch_create")
+        self._h = h
+        self.device = pairs[0][0].device
+        self.num_points = int(lib().dgf_batch_num_points(h))
+        off = (ctypes.c_int64 * (len(pairs) + 1))()
+        check(lib().dgf_batch_point_offsets(h, off), "dgf_batch_point_offsets")
+        self.offsets = list(off)
+        n = self.num_points
+        self.points = torch.empty((n, 2), dtype=torch.float32, device=self.device)
+        self.flow = torch.empty((n, 2), dtype=torch.float32, device=self.device)
+        self.status = torch.empty(n, dtype=torch.uint8, device=self.device)
+
+    def run(self, iters_out: torch.Tensor | None = None):
+        """Eager run on the current stream; returns (points, flow, status) views of the plan's buffers."""
+        check(lib().dgf_batch_run(self._h, _ptr(self.points), _ptr(self.flow), _ptr(self.status), _ptr(iters_out),
+                                  _stream()), "dgf_batch_run")
+        return self.points, self.flow, self.status
+
+    def capture(self):
+        """Capture the run into a HIP graph on the current (non-default) stream."""
+        check(lib().dgf_batch_capture(self._h, _ptr(self.points), _ptr(self.flow), _ptr(self.status), _stream()),
+              "dgf_batch_capture")
+
+    def replay(self):
+        check(lib().dgf_batch_replay(self._h, _stream()), "dgf_batch_replay")
+        return self.points, self.flow, self.status
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            torch.cuda.synchronize(self.device)
+            check(lib().dgf_batch_destroy(self._h), "dgf_batch_destroy")
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # pragma: no cover - interpreter shutdown
+            pass
+
+
 INF = math.inf

@@ -1,0 +1,324 @@
+// batch.hip -- many frame pairs of uneven size and point count in one pass: a plan built once on
+// the host (descriptor tables and every pyramid in one device allocation), then per run
+//   * one launch per pyramid level covering all 2P frames (a job table, blockIdx.z = frame),
+//   * one detection launch covering all pairs (blockIdx.z = pair, per-pair window and stride),
+//   * a one-thread kernel that clears the work counter (no memset node, so the sequence can be
+//     captured in a graph and replayed),
+//   * one persistent tracking launch: a resident-sized grid whose wavefronts pull work items
+//     (a group of points of one pair) from the counter until it passes the item count.
+// Outputs of all pairs are concatenated in pair order.  The whole sequence can be captured once
+// into a hipGraph and replayed with a single launch.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "dgf_internal.hpp"
+#include "dgf_tuning.hpp"
+
+namespace dgf {
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v) { *p = v; }
+
+} // namespace dgf
+
+using namespace dgf;
+
+struct dgf_batch {
+    int P = 0, L = 0, s = 0, iters = 0, dtype = 0;
+    dgf_track_opts opts{};
+    TrackTuning tune{};
+    std::vector<int64_t> pt_off, item_off;
+    int64_t total_pts = 0, nitems = 0, grid_waves = 0;
+    void *dmem = nullptr;
+    LevelPair *d_lv = nullptr;
+    int64_t *d_item_off = nullptr, *d_pt_off = nullptr;
+    uint32_t *d_counter = nullptr;
+    PyrJob *d_pyr = nullptr; // [(L-1)][2P]
+    DetectJob *d_det = nullptr;
+    std::vector<int> pyr_w2, pyr_h2; // per level 1..L-1: largest output size over the frames
+    int det_tiles_x = 0, det_tiles_y = 0;
+    size_t det_lds = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+bool pair_ok(const dgf_pair_desc &d, int dtype)
+{
+    auto ok = [&](const dgf_image &im) {
+        const int e = im.dtype == DGF_U8 ? 1 : (im.dtype == DGF_F32 ? 4 : 0);
+        return im.data && im.width >= 1 && im.height >= 1 && e && im.dtype == dtype &&
+               im.pitch_bytes >= (int64_t)im.width * e && (e == 1 || (im.pitch_bytes % 4 == 0 && (uintptr_t)im.data % 4 == 0));
+    };
+    return ok(d.I0) && ok(d.I1) && d.I0.width == d.I1.width && d.I0.height == d.I1.height && d.window >= 1 &&
+           d.window <= DGF_MAX_WINDOW && d.stride >= 1;
+}
+
+int launch_all(dgf_batch *b, float *points, float *flow, uint8_t *status, int32_t *iters_out, hipStream_t st)
+{
+    for (int l = 1; l < b->L; ++l) {
+        if (launch_pyr_level_batched(b->d_pyr + (size_t)(l - 1) * 2 * b->P, 2 * b->P, b->pyr_w2[l], b->pyr_h2[l], b->dtype,
+                                     st) != hipSuccess)
+            return DGF_ERR_HIP;
+    }
+    if (launch_detect_batched(b->d_det, b->P, b->det_tiles_x, b->det_tiles_y, b->det_lds, points, st) != hipSuccess)
+        return DGF_ERR_HIP;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, st, b->d_counter, 0u);
+    if (hipGetLastError() != hipSuccess) return DGF_ERR_HIP;
+    TrackParams P{};
+    P.pts = points;
+    P.n = b->total_pts;
+    P.flow = flow;
+    P.status = status;
+    P.iters_out = iters_out;
+    P.L = b->L;
+    P.iters = b->iters;
+    fill_track_geometry(P, b->s, b->tune.margin, b->tune.lpp, b->tune.kind);
+    fill_track_constants(P, b->opts, b->s);
+    P.npairs = b->P;
+    P.persistent = 1;
+    P.blv = b->d_lv;
+    P.item_off = b->d_item_off;
+    P.pt_off = b->d_pt_off;
+    P.counter = b->d_counter;
+    P.nitems = b->nitems;
+    P.grid_waves = b->grid_waves;
+    return launch_track(P, b->tune, b->dtype, st) == hipSuccess ? DGF_OK : DGF_ERR_HIP;
+}
+
+} // namespace
+
+extern "C" {
+
+int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels, int32_t support, int32_t iters,
+                     const dgf_track_opts *opts, dgf_batch **out)
+{
+    if (!out) return DGF_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!pairs || npairs < 1 || npairs > 65535) return DGF_ERR_INVALID_ARG;
+    if (levels < 1 || levels > DGF_MAX_LEVELS || iters < 1) return DGF_ERR_INVALID_ARG;
+    if (support < 1 || (support & 1) == 0 || support > DGF_MAX_SUPPORT) return DGF_ERR_INVALID_ARG;
+    const int dtype = pairs[0].I0.dtype;
+    for (int i = 0; i < npairs; ++i)
+        if (!pair_ok(pairs[i], dtype)) return DGF_ERR_INVALID_ARG;
+    dgf_track_opts o;
+    if (opts) {
+        o = *opts;
+        if (o.flags != 0) return DGF_ERR_UNSUPPORTED;
+    } else {
+        dgf_track_opts_default(&o);
+    }
+    if (!(o.sigma1 >= 0.f) || !(o.sigma2 >= 0.f) || !(o.eps_coarse >= 0.f) || !(o.eps_fine >= 0.f) || isnan(o.min_eig))
+        return DGF_ERR_INVALID_ARG;
+    if (isinf(o.sigma2) && !isinf(o.sigma1)) return DGF_ERR_INVALID_ARG;
+    for (int i = 0; i < npairs; ++i)
+        if (detect_tile_lds(pairs[i].window, pairs[i].stride) > 48 * 1024) return DGF_ERR_UNSUPPORTED;
+
+    dgf_batch *b = new (std::nothrow) dgf_batch();
+    if (!b) return DGF_ERR_INVALID_ARG;
+    b->P = npairs;
+    b->L = levels;
+    b->s = support;
+    b->iters = iters;
+    b->dtype = dtype;
+    b->opts = o;
+    int64_t total_n = 0;
+    for (int i = 0; i < npairs; ++i)
+        total_n += dgf_detect_count(pairs[i].I0.width, pairs[i].I0.height, pairs[i].window, pairs[i].stride);
+    b->tune = tuning_for(support, levels, dtype, total_n);
+    if (!track_shape_ok(support, b->tune)) {
+        delete b;
+        return DGF_ERR_UNSUPPORTED;
+    }
+    while (track_lds_bytes(support, b->tune) > kMaxLdsPerBlock && b->tune.wpb > 1) b->tune.wpb /= 2;
+    if (track_lds_bytes(support, b->tune) > kMaxLdsPerBlock) {
+        delete b;
+        return DGF_ERR_UNSUPPORTED;
+    }
+    const int ppw = 64 / b->tune.lpp;
+
+    // point and work-item prefix sums; detection jobs
+    b->pt_off.assign(npairs + 1, 0);
+    b->item_off.assign(npairs + 1, 0);
+    std::vector<DetectJob> det(npairs);
+    for (int i = 0; i < npairs; ++i) {
+        const dgf_pair_desc &d = pairs[i];
+        const int64_t n = dgf_detect_count(d.I0.width, d.I0.height, d.window, d.stride);
+        b->pt_off[i + 1] = b->pt_off[i] + n;
+        b->item_off[i + 1] = b->item_off[i] + (n + ppw - 1) / ppw;
+        DetectJob j{};
+        j.img = (const uint8_t *)d.I0.data;
+        j.pitch = d.I0.pitch_bytes;
+        j.W = d.I0.width;
+        j.H = d.I0.height;
+        j.win = d.window;
+        j.stride = d.stride;
+        j.nx = n ? (d.I0.width - d.window) / d.stride + 1 : 0;
+        j.ny = n ? (d.I0.height - d.window) / d.stride + 1 : 0;
+        j.out_off = b->pt_off[i];
+        det[i] = j;
+        b->det_tiles_x = std::max(b->det_tiles_x, (j.nx + 15) / 16);
+        b->det_tiles_y = std::max(b->det_tiles_y, (j.ny + 15) / 16);
+        b->det_lds = std::max(b->det_lds, detect_tile_lds(d.window, d.stride));
+    }
+    b->total_pts = b->pt_off[npairs];
+    b->nitems = b->item_off[npairs];
+    if (dtype != DGF_U8) { // detection reads uint8 frames
+        delete b;
+        return DGF_ERR_UNSUPPORTED;
+    }
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        delete b;
+        return DGF_ERR_HIP;
+    }
+    // persistent grid: 32 wavefront slots per CU; waves beyond what fits start after the first
+    // ones drain the queue and exit at once
+    b->grid_waves = std::min<int64_t>(b->nitems, (int64_t)cus * 32);
+    if (b->grid_waves < 1) b->grid_waves = 1;
+
+    // device layout: [level table][item_off][pt_off][counter][pyramid jobs][detect jobs][pyramids]
+    std::vector<int64_t> pyr_bytes(npairs), pyr_base(npairs);
+    int64_t sz = 0;
+    const int64_t o_lv = sz;
+    sz = align_up(sz + (int64_t)sizeof(LevelPair) * npairs * levels, 256);
+    const int64_t o_item = sz;
+    sz = align_up(sz + 8 * (npairs + 1), 256);
+    const int64_t o_pt = sz;
+    sz = align_up(sz + 8 * (npairs + 1), 256);
+    const int64_t o_ctr = sz;
+    sz = align_up(sz + 4, 256);
+    const int64_t o_pyrjobs = sz;
+    sz = align_up(sz + (int64_t)sizeof(PyrJob) * 2 * npairs * std::max(levels - 1, 1), 256);
+    const int64_t o_det = sz;
+    sz = align_up(sz + (int64_t)sizeof(DetectJob) * npairs, 256);
+    for (int i = 0; i < npairs; ++i) {
+        pyr_bytes[i] = (int64_t)dgf_pyramid_layout(pairs[i].I0.width, pairs[i].I0.height, levels, dtype, nullptr, nullptr);
+        pyr_base[i] = sz;
+        sz = align_up(sz + 2 * pyr_bytes[i], 256);
+    }
+    if (hipMalloc(&b->dmem, (size_t)sz) != hipSuccess) {
+        b->dmem = nullptr;
+        delete b;
+        return DGF_ERR_HIP;
+    }
+    uint8_t *base = (uint8_t *)b->dmem;
+    b->d_lv = (LevelPair *)(base + o_lv);
+    b->d_item_off = (int64_t *)(base + o_item);
+    b->d_pt_off = (int64_t *)(base + o_pt);
+    b->d_counter = (uint32_t *)(base + o_ctr);
+    b->d_pyr = (PyrJob *)(base + o_pyrjobs);
+    b->d_det = (DetectJob *)(base + o_det);
+
+    // level table and pyramid jobs
+    std::vector<LevelPair> lv((size_t)npairs * levels);
+    std::vector<PyrJob> jobs((size_t)2 * npairs * std::max(levels - 1, 1));
+    b->pyr_w2.assign(levels, 0);
+    b->pyr_h2.assign(levels, 0);
+    for (int i = 0; i < npairs; ++i) {
+        int64_t off[DGF_MAX_LEVELS], pitch[DGF_MAX_LEVELS];
+        dgf_pyramid_layout(pairs[i].I0.width, pairs[i].I0.height, levels, dtype, off, pitch);
+        uint8_t *w0 = base + pyr_base[i], *w1 = w0 + pyr_bytes[i];
+        LevelPair *L = &lv[(size_t)i * levels];
+        L[0] = LevelPair{(const uint8_t *)pairs[i].I0.data, (const uint8_t *)pairs[i].I1.data, pairs[i].I0.pitch_bytes,
+                         pairs[i].I1.pitch_bytes, pairs[i].I0.width, pairs[i].I0.height};
+        int W = pairs[i].I0.width, H = pairs[i].I0.height;
+        for (int l = 1; l < levels; ++l) {
+            jobs[(size_t)(l - 1) * 2 * npairs + 2 * i] = PyrJob{L[l - 1].p0, w0 + off[l], L[l - 1].pitch0, pitch[l], W, H};
+            jobs[(size_t)(l - 1) * 2 * npairs + 2 * i + 1] = PyrJob{L[l - 1].p1, w1 + off[l], L[l - 1].pitch1, pitch[l], W, H};
+            W = (W + 1) / 2;
+            H = (H + 1) / 2;
+            b->pyr_w2[l] = std::max(b->pyr_w2[l], W);
+            b->pyr_h2[l] = std::max(b->pyr_h2[l], H);
+            L[l] = LevelPair{w0 + off[l], w1 + off[l], pitch[l], pitch[l], W, H};
+        }
+    }
+    bool ok = hipMemcpy(b->d_lv, lv.data(), sizeof(LevelPair) * lv.size(), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(b->d_item_off, b->item_off.data(), 8 * (npairs + 1), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(b->d_pt_off, b->pt_off.data(), 8 * (npairs + 1), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(b->d_pyr, jobs.data(), sizeof(PyrJob) * jobs.size(), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(b->d_det, det.data(), sizeof(DetectJob) * det.size(), hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+        hipFree(b->dmem);
+        delete b;
+        return DGF_ERR_HIP;
+    }
+    *out = b;
+    return DGF_OK;
+}
+
+int64_t dgf_batch_num_points(const dgf_batch *b) { return b ? b->total_pts : -1; }
+
+int dgf_batch_point_offsets(const dgf_batch *b, int64_t *offsets)
+{
+    if (!b || !offsets) return DGF_ERR_INVALID_ARG;
+    memcpy(offsets, b->pt_off.data(), sizeof(int64_t) * (b->P + 1));
+    return DGF_OK;
+}
+
+int dgf_batch_run(dgf_batch *b, float *points, float *flow, uint8_t *status, int32_t *iters_out, void *stream)
+{
+    if (!b) return DGF_ERR_INVALID_ARG;
+    if (b->total_pts > 0 && (!points || !flow || !status)) return DGF_ERR_INVALID_ARG;
+    if (b->total_pts == 0) return DGF_OK;
+    return launch_all(b, points, flow, status, iters_out, (hipStream_t)stream);
+}
+
+int dgf_batch_capture(dgf_batch *b, float *points, float *flow, uint8_t *status, void *stream)
+{
+    if (!b || !stream) return DGF_ERR_INVALID_ARG; // graphs are captured from a created stream
+    if (b->total_pts > 0 && (!points || !flow || !status)) return DGF_ERR_INVALID_ARG;
+    if (b->exec) {
+        hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    if (b->total_pts == 0) return DGF_OK;
+    hipStream_t st = (hipStream_t)stream;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return DGF_ERR_HIP;
+    const int rc = launch_all(b, points, flow, status, nullptr, st);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &g);
+    if (rc != DGF_OK || e != hipSuccess || !g) {
+        if (g) hipGraphDestroy(g);
+        return rc != DGF_OK ? rc : DGF_ERR_HIP;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        hipGraphDestroy(g);
+        return DGF_ERR_HIP;
+    }
+    b->graph = g;
+    b->exec = ex;
+    return DGF_OK;
+}
+
+int dgf_batch_replay(dgf_batch *b, void *stream)
+{
+    if (!b) return DGF_ERR_INVALID_ARG;
+    if (b->total_pts == 0) return DGF_OK;
+    if (!b->exec) return DGF_ERR_INVALID_ARG;
+    return hipGraphLaunch(b->exec, (hipStream_t)stream) == hipSuccess ? DGF_OK : DGF_ERR_HIP;
+}
+
+int dgf_batch_destroy(dgf_batch *b)
+{
+    if (!b) return DGF_OK;
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    int rc = DGF_OK;
+    if (b->dmem && hipFree(b->dmem) != hipSuccess) rc = DGF_ERR_HIP;
+    delete b;
+    return rc;
+}
+
+} // extern "C"

@@ -19,6 +19,8 @@ struct DetectOut {
     float *resp;
 };
 
+size_t detect_tile_lds(int win, int stride) { return (size_t)(15 * stride + win) * (size_t)(15 * stride + win); }
+
 __device__ __forceinline__ void finish_window(int S, int Mi, int Mj, int m, int win, int x0, int y0, int64_t n,
                                               DetectOut o)
 {
@@ -43,10 +45,11 @@ __device__ __forceinline__ void finish_window(int S, int Mi, int Mj, int m, int 
     if (o.resp) o.resp[n] = sqrtf((cpx - cnx) * (cpx - cnx) + (cpy - cny) * (cpy - cny));
 }
 
-// LDS-tiled form: TX x TY windows per workgroup, one lane per window.
+// LDS-tiled form: TX x TY windows per workgroup, one lane per window.  n0 offsets the output
+// (batched form: points of a pair start at its offset in the concatenated output).
 template <int TX, int TY>
-__global__ __launch_bounds__(TX *TY) void k_detect_tiled(const uint8_t *__restrict__ img, int64_t pitch, int W, int H,
-                                                          int win, int stride, int nx, int ny, DetectOut o)
+__device__ __forceinline__ void detect_tile(const uint8_t *__restrict__ img, int64_t pitch, int W, int H, int win,
+                                            int stride, int nx, int ny, int64_t n0, DetectOut o)
 {
     extern __shared__ uint8_t tile[];
     const int wx0 = blockIdx.x * TX, wy0 = blockIdx.y * TY;
@@ -76,7 +79,23 @@ __global__ __launch_bounds__(TX *TY) void k_detect_tiled(const uint8_t *__restri
         Mi += i * rs;
         Mj += rj;
     }
-    finish_window(S, Mi, Mj, m, win, kx * stride, ky * stride, (int64_t)ky * nx + kx, o);
+    finish_window(S, Mi, Mj, m, win, kx * stride, ky * stride, n0 + (int64_t)ky * nx + kx, o);
+}
+
+template <int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void k_detect_tiled(const uint8_t *__restrict__ img, int64_t pitch, int W, int H,
+                                                          int win, int stride, int nx, int ny, DetectOut o)
+{
+    detect_tile<TX, TY>(img, pitch, W, H, win, stride, nx, ny, 0, o);
+}
+
+// Batched form: blockIdx.z selects the pair; tiles beyond a pair's window grid exit at once.
+template <int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void k_detect_batched(const DetectJob *__restrict__ jobs, DetectOut o)
+{
+    const DetectJob J = jobs[blockIdx.z];
+    if ((int)blockIdx.x * TX >= J.nx || (int)blockIdx.y * TY >= J.ny) return;
+    detect_tile<TX, TY>(J.img, J.pitch, J.W, J.H, J.win, J.stride, J.nx, J.ny, J.out_off, o);
 }
 
 // Direct form for windows too large to tile: one lane per window, reads through the cache.
@@ -120,6 +139,15 @@ hipError_t launch_detect(const uint8_t *img, int64_t pitch, int W, int H, int wi
         hipLaunchKernelGGL(k_detect_direct, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, img, pitch, win,
                            stride, nx, N, o);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_detect_batched(const DetectJob *jobs, int njobs, int max_tiles_x, int max_tiles_y, size_t lds,
+                                 float *pts, hipStream_t st)
+{
+    DetectOut o{pts, nullptr, nullptr};
+    dim3 grid(max_tiles_x, max_tiles_y, njobs);
+    hipLaunchKernelGGL((k_detect_batched<16, 16>), grid, dim3(256), lds, st, jobs, o);
     return hipGetLastError();
 }
 

@@ -151,7 +151,68 @@ struct TrackParams {
     float cs2;           // cmid * sigma2
     float eps2c, eps2f;  // squared stopping thresholds
     float min_eig_s2;    // min_eig * s^2
+    // batched form (npairs = 0 for a single pair): per-pair level table, prefix sums of per-pair
+    // work items (groups of points of one pair handled by one wavefront) and of per-pair points
+    int32_t npairs;
+    int32_t persistent;  // 1: waves pull items from *counter until it passes nitems
+    const LevelPair *blv; // [npairs][L]
+    const int64_t *item_off, *pt_off; // [npairs + 1] each
+    uint32_t *counter;
+    int64_t nitems;
+    int64_t grid_waves; // batched form: wavefronts to launch (persistent: a resident-sized grid)
 };
+
+// One wavefront's unit of work: a group of up to 64 / LPP consecutive points of one pair.
+struct WorkItem {
+    int64_t pidx; // global point index of this lane's point
+    int pair;
+    bool valid;   // this lane's point exists
+    bool done;    // no work left for the wavefront
+};
+
+template <int PPW>
+__device__ __forceinline__ WorkItem work_item(const TrackParams &P, int64_t item, int q)
+{
+    WorkItem w;
+    if (P.npairs == 0) {
+        w.done = item * PPW >= P.n;
+        w.pair = 0;
+        w.pidx = item * PPW + q;
+        w.valid = w.pidx < P.n;
+        return w;
+    }
+    w.done = item >= P.nitems;
+    w.pair = 0;
+    w.pidx = 0;
+    w.valid = false;
+    if (w.done) return w;
+    int lo = 0, hi = P.npairs - 1; // last pair whose first item is <= item
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (P.item_off[mid] <= item)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int64_t local = (item - P.item_off[lo]) * PPW + q;
+    w.pair = lo;
+    w.valid = local < P.pt_off[lo + 1] - P.pt_off[lo];
+    w.pidx = P.pt_off[lo] + local;
+    return w;
+}
+
+// Next work item of a persistent wavefront: one lane bumps the counter, all lanes take its value.
+__device__ __forceinline__ int64_t next_item(uint32_t *counter)
+{
+    unsigned v = 0u;
+    if ((threadIdx.x & 63) == 0) v = atomicAdd(counter, 1u);
+    return (int64_t)__builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ LevelPair level_of(const TrackParams &P, int pair, int l)
+{
+    return P.npairs ? P.blv[pair * P.L + l] : P.lv[l];
+}
 
 // How the robust weight w = psi(r)/r is evaluated (chosen on the host from sigma1, sigma2):
 //   ROBUST_L2     both thresholds infinite: w = 1 everywhere (plain least squares)
@@ -173,7 +234,18 @@ struct PyrJob {
     int32_t W, H; // source size; destination is ceil(W/2) x ceil(H/2)
 };
 
+struct DetectJob {
+    const uint8_t *img;
+    int64_t pitch;
+    int32_t W, H, win, stride, nx, ny;
+    int64_t out_off; // index of the pair's first point in the concatenated output
+};
+
 // launchers (return hipSuccess or the launch error)
+hipError_t launch_detect_batched(const DetectJob *jobs_dev, int njobs, int max_tiles_x, int max_tiles_y, size_t lds,
+                                 float *pts, hipStream_t st);
+size_t detect_tile_lds(int win, int stride);
+hipError_t launch_pyr_level_batched(const PyrJob *jobs_dev, int njobs, int max_w2, int max_h2, int dtype, hipStream_t st);
 hipError_t launch_detect(const uint8_t *img, int64_t pitch, int W, int H, int win, int stride, float *pts,
                          uint8_t *sel, float *resp, hipStream_t st);
 hipError_t launch_pyr_level(const PyrJob *jobs, int njobs, int dtype, hipStream_t st);

@@ -59,32 +59,11 @@ __global__ __launch_bounds__(256) void k_track_run(TrackParams P)
     const int wpb = blockDim.x >> 6;
     const int q = lane / LPP;
     const int li = lane - q * LPP;
-    const int64_t pidx = ((int64_t)blockIdx.x * wpb + wave) * PPW + q;
     float *tile = smem + (size_t)(wave * PPW + q) * P.tile_floats;
 
     const int s = P.s, r = P.r, RW = P.RW, RP = P.RPP, TW = P.TW, M = P.M;
     const int nseg_row = s / R; // runs per support row
     const int nseg = s * nseg_row;
-
-    const bool valid = pidx < P.n;
-    float px = 0.f, py = 0.f;
-    if (valid) {
-        const float2 pp = reinterpret_cast<const float2 *>(P.pts)[pidx];
-        px = pp.x;
-        py = pp.y;
-    }
-    const int W0 = P.lv[0].W, H0 = P.lv[0].H;
-    int status = -1;
-    float ux = 0.f, uy = 0.f;
-    if (valid && !(px >= 0.f && py >= 0.f && px <= (float)(W0 - 1) && py <= (float)(H0 - 1))) status = DGF_ST_OUT_OF_BOUNDS;
-    bool active = valid && status < 0;
-    if (!active) {
-        px = 0.f;
-        py = 0.f;
-    }
-    float gX = 0.f, gY = 0.f, dX = 0.f, dY = 0.f;
-    bool conv0 = false;
-    int it_total = 0;
 
     // run geometry: sb = row * TP + col0 of the run's first pixel in the I1 tile, rc = row << 8 |
     // col0; unused runs point at 0 and carry zero gradients
@@ -104,9 +83,37 @@ __global__ __launch_bounds__(256) void k_track_run(TrackParams P)
 
     float T[PPL], GX[PPL], GY[PPL];
 
+    int64_t item = P.persistent ? next_item(P.counter) : (int64_t)blockIdx.x * wpb + wave;
+    for (;;) {
+    const WorkItem wi = work_item<PPW>(P, item, q);
+    if (wi.done) break;
+    const int64_t pidx = wi.pidx;
+    const int pair = wi.pair;
+    const bool valid = wi.valid;
+    float px = 0.f, py = 0.f;
+    if (valid) {
+        const float2 pp = reinterpret_cast<const float2 *>(P.pts)[pidx];
+        px = pp.x;
+        py = pp.y;
+    }
+    const LevelPair LV0 = level_of(P, pair, 0);
+    const int W0 = LV0.W, H0 = LV0.H;
+    int status = -1;
+    float ux = 0.f, uy = 0.f;
+    if (valid && !(px >= 0.f && py >= 0.f && px <= (float)(W0 - 1) && py <= (float)(H0 - 1))) status = DGF_ST_OUT_OF_BOUNDS;
+    bool active = valid && status < 0;
+    if (!active) {
+        px = 0.f;
+        py = 0.f;
+    }
+    float gX = 0.f, gY = 0.f, dX = 0.f, dY = 0.f;
+    bool conv0 = false;
+    int it_total = 0;
+
+
     for (int l = P.L - 1; l >= 0; --l) {
         if (!wave_any(active)) break;
-        const LevelPair LV = P.lv[l];
+        const LevelPair LV = level_of(P, pair, l);
         const int Wl = LV.W, Hl = LV.H;
         const float sc = __builtin_ldexpf(1.0f, -l);
         const float plx = px * sc, ply = py * sc;
@@ -334,13 +341,16 @@ __global__ __launch_bounds__(256) void k_track_run(TrackParams P)
         P.status[pidx] = (uint8_t)status;
         if (P.iters_out) P.iters_out[pidx] = it_total;
     }
+    if (!P.persistent) break;
+    item = next_item(P.counter);
+    } // work loop
 }
 
 template <int LPP, int SEG, int R, int TP, typename PixT>
 hipError_t launch_track_run_t(const TrackParams &P, int wpb, hipStream_t st)
 {
     constexpr int PPW = 64 / LPP;
-    const int64_t waves = (P.n + PPW - 1) / PPW;
+    const int64_t waves = P.npairs ? P.grid_waves : (P.n + PPW - 1) / PPW;
     const int64_t blocks = (waves + wpb - 1) / wpb;
     const size_t lds = (size_t)wpb * PPW * P.tile_floats * sizeof(float);
     hipLaunchKernelGGL((k_track_run<LPP, SEG, R, TP, PixT>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st, P);

@@ -191,17 +191,22 @@ def driving_1242x375(seed: int = 0):
     return layered_pair(1242, 375, seed=seed, max_disp=150.0)
 
 
-def batch64_mixed():
+def batch64_mixed(workers: int = 8):
     """64 pairs of four sizes (16 each), pair i uses seed i, stride per pair drawn from
-    {3, 5, 8} with rng(0).  Returns a list of dicts (I0, I1, gt, occ, stride)."""
+    {3, 5, 8} with rng(0).  Returns a list of dicts (I0, I1, gt, occ, stride).  Pairs are
+    generated on a thread pool (each pair has its own generator, so the result does not depend
+    on the scheduling)."""
+    from concurrent.futures import ThreadPoolExecutor
     sizes = [(1242, 375), (1224, 370), (640, 480), (320, 240)]
     strides = np.random.default_rng(0).choice([3, 5, 8], size=64)
-    out = []
-    for i in range(64):
+
+    def one(i):
         W, H = sizes[i % 4]
         I0, I1, gt, occ = layered_pair(W, H, seed=i, max_disp=150.0 * W / 1242.0)
-        out.append(dict(I0=I0, I1=I1, gt=gt, occ=occ, stride=int(strides[i]), W=W, H=H))
-    return out
+        return dict(I0=I0, I1=I1, gt=gt, occ=occ, stride=int(strides[i]), W=W, H=H)
+
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(one, range(64)))
 
 
 def translation_f32_1242x375(seed: int = 0):

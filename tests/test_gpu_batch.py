@@ -1,0 +1,115 @@
+"""GPU tests of the batched form (one plan for many pairs of uneven size and point count):
+its output must be bit-identical to per-pair plain detect + track calls with the same launch
+shape, and graph replays must reproduce the eager run."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1901_09971_amd as dgf
+from paper_1901_09971_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(1242, 375), (640, 480), (320, 240), (77, 41), (8, 8), (1224, 370)]
+STRIDES = [5, 8, 3, 4, 2, 7]
+
+
+def _pairs(n, max_disp=60.0):
+    out = []
+    for i in range(n):
+        W, H = SIZES[i % len(SIZES)]
+        if W < 32:
+            I0 = np.random.default_rng(i).integers(0, 256, size=(H, W), dtype=np.uint8)
+            I1 = I0.copy()
+        else:
+            I0, I1, _, _ = synth.layered_pair(W, H, seed=100 + i, max_disp=max_disp * W / 1242.0)
+        out.append((torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda(), 9, STRIDES[i % len(STRIDES)]))
+    return out
+
+
+def _plain(pairs, levels, support, iters):
+    pts, flow, st = [], [], []
+    for a, b, w, d in pairs:
+        p = dgf.detect(a, w, d)
+        f, s = dgf.track(a, b, p, levels, support, iters)
+        pts.append(p)
+        flow.append(f)
+        st.append(s)
+    return torch.cat(pts), torch.cat(flow), torch.cat(st)
+
+
+@pytest.mark.parametrize("levels,support,iters", [(5, 21, 20), (3, 9, 10)])
+def test_batched_equals_plain(levels, support, iters):
+    pairs = _pairs(12)
+    plan = dgf.Batch(pairs, levels, support, iters)
+    P, F, S = plan.run()
+    p, f, s = _plain(pairs, levels, support, iters)
+    torch.cuda.synchronize()
+    assert plan.num_points == p.shape[0]
+    assert plan.offsets[-1] == p.shape[0]
+    assert torch.equal(P, p)
+    assert torch.equal(S, s)
+    fin = torch.isfinite(f)
+    assert torch.equal(torch.isfinite(F), fin)
+    assert torch.equal(F[fin], f[fin])
+    plan.close()
+
+
+def test_graph_replay_matches_eager():
+    pairs = _pairs(8)
+    plan = dgf.Batch(pairs, 5, 21, 20)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        P0, F0, S0 = [t.clone() for t in plan.run()]
+        plan.capture()
+    torch.cuda.synchronize()
+    for rep in range(4):
+        with torch.cuda.stream(side):
+            plan.points.zero_()
+            plan.flow.zero_()
+            plan.status.fill_(255)
+            plan.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(plan.points, P0), rep
+        assert torch.equal(plan.status, S0), rep
+        fin = torch.isfinite(F0)
+        assert torch.equal(plan.flow[fin], F0[fin]), rep
+        # eager work on the default stream between replays
+        x = torch.randn(1 << 20, device="cuda")
+        _ = (x * 2).sum().item()
+    plan.close()
+
+
+def test_batched_pair_vs_oracle_sample():
+    pairs = _pairs(3)
+    plan = dgf.Batch(pairs, 4, 15, 15)
+    P, F, S = [t.cpu().numpy() for t in plan.run()]
+    for i, (a, b, w, d) in enumerate(pairs):
+        lo, hi = plan.offsets[i], plan.offsets[i + 1]
+        I0, I1 = a.cpu().numpy(), b.cpu().numpy()
+        opts, _, _ = oracle.detect(I0, w, d)
+        assert hi - lo == len(opts)
+        assert np.abs(P[lo:hi] - opts).max() <= 1e-3
+        idx = np.arange(lo, hi, 7)  # every 7th point of the pair
+        of, os_ = oracle.track(I0, I1, P[idx].astype(np.float64), 4, 15, 15)
+        both = (S[idx] == 0) & (os_ == 0)
+        assert np.mean(S[idx] == os_) > 0.97
+        if both.any():
+            assert np.abs(F[idx][both] - of[both]).max() <= 1e-3
+    plan.close()
+
+
+def test_invalid_plans():
+    a = torch.zeros((32, 32), dtype=torch.uint8, device="cuda")
+    f = torch.zeros((32, 32), dtype=torch.float32, device="cuda")
+    with pytest.raises(RuntimeError):
+        dgf.Batch([(a, f, 9, 4)], 3, 9, 10)          # mixed dtypes
+    with pytest.raises(RuntimeError):
+        dgf.Batch([(a, a, 9, 4)], 3, 8, 10)          # even support
+    with pytest.raises(RuntimeError):
+        dgf.Batch([(f, f, 9, 4)], 3, 9, 10)          # float frames cannot be detected on
+    empty = dgf.Batch([(a[:4, :4].contiguous(), a[:4, :4].contiguous(), 9, 4)], 3, 9, 10)
+    assert empty.num_points == 0
+    empty.run()
+    empty.close()
