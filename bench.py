@@ -167,6 +167,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=12.0)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-pair batched vs plain measurement")
+    ap.add_argument("--no-autotune", action="store_true", help="use the built-in launch-shape heuristic")
     ap.add_argument("--batch-reps", type=int, default=10)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
@@ -197,6 +198,14 @@ def main():
     status = torch.empty(N, dtype=torch.uint8, device=dev)
     its = torch.empty(N, dtype=torch.int32, device=dev)
     ws = torch.empty(dgf.track_workspace_bytes(w["W"], w["H"], w["levels"], 0), dtype=torch.uint8, device=dev)
+
+    # launch shape: autotuned on this pair (about a hundred timed launches, well under a second)
+    tuning = None
+    if not args.no_autotune:
+        pts0 = dgf.detect(I0, w["window"], w["stride"])
+        tuning = dgf.autotune(I0, I1, pts0, w["levels"], w["support"], w["iters"])
+    else:
+        tuning = dgf.get_tuning(w["support"], w["levels"], 0, N)
 
     def step(iters_out=None):
         dgf.detect(I0, w["window"], w["stride"], out=pts)
@@ -281,7 +290,7 @@ def main():
                        "hbm_frac": det_bytes / (t_detect * 1e-3) / (PEAK_HBM_GBPS * 1e9)},
             "pyramids": {"ms": t_pyr, "launches": w["levels"] - 1, "algorithmic_bytes": pyr_read + pyr_write,
                          "hbm_frac": (pyr_read + pyr_write) / (t_pyr * 1e-3) / (PEAK_HBM_GBPS * 1e9)},
-            "track": {"ms": t_track, "iterations": it_total, "status_counts": st_counts},
+            "track": {"ms": t_track, "iterations": it_total, "status_counts": st_counts, "tuning": tuning},
         },
         "host_wall_s": t_host,
     }

@@ -215,6 +215,36 @@ int dgf_batch_replay(dgf_batch *b, void *stream);
 /* Frees the plan and its device memory (after the work using it has completed). */
 int dgf_batch_destroy(dgf_batch *b);
 
+/* ---- launch-shape tuning ------------------------------------------------------------------- */
+
+/* Launch shape of the tracker.  It never changes results, only speed. */
+typedef struct {
+    int32_t lanes_per_point; /* 16, 32 or 64 lanes of a wavefront share one point            */
+    int32_t waves_per_group; /* wavefronts per workgroup: 1, 2 or 4                           */
+    int32_t margin;          /* I1 tile margin in pixels (clamped to what the tile allows)    */
+    int32_t kernel;          /* 0: row-run pixel layout when compiled for the support, else
+                                the generic layout; 1: generic layout                        */
+    float ms;                /* measured time of the winning shape (dgf_autotune), else -1  */
+} dgf_tuning;
+
+/* Shape the library uses for this request (installed entry for (support, dtype), else a
+ * heuristic).  Host only. */
+int dgf_get_tuning(int32_t support, int32_t levels, int32_t dtype, int64_t n, dgf_tuning *out);
+
+/* Installs a shape for (support, dtype) for the rest of the process.  Host only;
+ * DGF_ERR_UNSUPPORTED if no kernel is compiled for it. */
+int dgf_set_tuning(int32_t support, int32_t dtype, const dgf_tuning *t);
+
+/* Times every compiled launch shape on these inputs (dgf_track arguments; the pyramids are built
+ * into `workspace`, flow / status receive a valid result), installs the fastest for (support,
+ * dtype) and returns it in *out (nullable).  This is a setup call: it synchronises `stream`
+ * once per candidate.  cache_path (nullable) names a JSON file keyed by GPU architecture,
+ * support, levels, element type and the point count rounded up to a power of two: a hit installs
+ * the cached shape without timing anything; a miss appends the result. */
+int dgf_autotune(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
+                 int32_t support, int32_t iters, const dgf_track_opts *opts, void *workspace, size_t ws_bytes,
+                 float *flow, uint8_t *status, const char *cache_path, dgf_tuning *out, void *stream);
+
 /* The two stages of dgf_track, for callers that time or reuse them separately:
  * dgf_track_pyramids builds levels 1 .. levels-1 of both images into `workspace` (same layout
  * and size as dgf_track uses); dgf_track_run then tracks on those pyramids without rebuilding

@@ -31,6 +31,11 @@ class DgfPairDesc(ctypes.Structure):
     _fields_ = [("I0", DgfImage), ("I1", DgfImage), ("window", ctypes.c_int32), ("stride", ctypes.c_int32)]
 
 
+class DgfTuning(ctypes.Structure):
+    _fields_ = [("lanes_per_point", ctypes.c_int32), ("waves_per_group", ctypes.c_int32), ("margin", ctypes.c_int32),
+                ("kernel", ctypes.c_int32), ("ms", ctypes.c_float)]
+
+
 class DgfError(RuntimeError):
     def __init__(self, code: int, where: str):
         super().__init__(f"{where}: {strerror(code)} ({code})")
@@ -64,6 +69,10 @@ SIGNATURES = {
     "dgf_batch_capture": (ctypes.c_int, [P, P, P, P, P]),
     "dgf_batch_replay": (ctypes.c_int, [P, P]),
     "dgf_batch_destroy": (ctypes.c_int, [P]),
+    "dgf_get_tuning": (ctypes.c_int, [I32, I32, I32, I64, ctypes.POINTER(DgfTuning)]),
+    "dgf_set_tuning": (ctypes.c_int, [I32, I32, ctypes.POINTER(DgfTuning)]),
+    "dgf_autotune": (ctypes.c_int, [IMG, IMG, P, I64, I32, I32, I32, OPTS, P, SZ, P, P, ctypes.c_char_p,
+                                    ctypes.POINTER(DgfTuning), P]),
 }
 
 

@@ -197,6 +197,41 @@ class TrackFn(torch.autograd.Function):
         return dI0, dI1, None, None, None, None, None
 
 
+def _tuning_dict(t) -> dict:
+    return dict(lanes_per_point=t.lanes_per_point, waves_per_group=t.waves_per_group, margin=t.margin,
+                kernel=t.kernel, ms=t.ms)
+
+
+def get_tuning(support: int, levels: int, dtype: int = DGF_U8, n: int = 0) -> dict:
+    t = _lib.DgfTuning()
+    check(lib().dgf_get_tuning(support, levels, dtype, n, ctypes.byref(t)), "dgf_get_tuning")
+    return _tuning_dict(t)
+
+
+def set_tuning(support: int, dtype: int, lanes_per_point: int, waves_per_group: int, margin: int, kernel: int = 0):
+    t = _lib.DgfTuning(lanes_per_point, waves_per_group, margin, kernel, -1.0)
+    check(lib().dgf_set_tuning(support, dtype, ctypes.byref(t)), "dgf_set_tuning")
+
+
+def autotune(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, levels: int, support: int, iters: int,
+             opts: TrackOpts | None = None, cache_path: str | None = None) -> dict:
+    """Time every compiled launch shape on these inputs, install the fastest for (support,
+    dtype) and return it (dgf_autotune)."""
+    a, b = _image(I0, "I0"), _image(I1, "I1")
+    points = points.contiguous()
+    n = points.shape[0]
+    ws = torch.empty(max(track_workspace_bytes(a.width, a.height, levels, a.dtype), 1), dtype=torch.uint8,
+                     device=I0.device)
+    flow = torch.empty((n, 2), dtype=torch.float32, device=I0.device)
+    status = torch.empty(n, dtype=torch.uint8, device=I0.device)
+    o = (opts or TrackOpts()).to_c()
+    t = _lib.DgfTuning()
+    check(lib().dgf_autotune(ctypes.byref(a), ctypes.byref(b), _ptr(points), n, levels, support, iters,
+                             ctypes.byref(o), _ptr(ws), ws.numel(), _ptr(flow), _ptr(status),
+                             cache_path.encode() if cache_path else None, ctypes.byref(t), _stream()), "dgf_autotune")
+    return _tuning_dict(t)
+
+
 class Batch:
     """Plan for detect + pyramids + track of many uint8 frame pairs of uneven size in one pass
     (dgf_batch_*).  ``pairs`` is a list of (I0, I1, window, stride); the tensors are kept alive

@@ -179,9 +179,14 @@ int dgf_track_pyramids(const dgf_image *I0, const dgf_image *I1, int32_t levels,
     return DGF_OK;
 }
 
-int dgf_track_run(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
-                  int32_t support, int32_t iters, const dgf_track_opts *opts, const void *workspace, size_t ws_bytes,
-                  float *flow, uint8_t *status, int32_t *iters_out, void *stream)
+} // extern "C"
+
+namespace dgf {
+
+// Validation shared by every tracking entry point; fills the effective options.
+int validate_track(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
+                   int32_t support, int32_t iters, const dgf_track_opts *opts, const void *workspace, size_t ws_bytes,
+                   const float *flow, const uint8_t *status, dgf_track_opts *o)
 {
     int rc = check_pair(I0, I1, levels);
     if (rc != DGF_OK) return rc;
@@ -189,24 +194,30 @@ int dgf_track_run(const dgf_image *I0, const dgf_image *I1, const float *points,
     if (support < 1 || (support & 1) == 0 || support > DGF_MAX_SUPPORT) return DGF_ERR_INVALID_ARG;
     if (n < 0) return DGF_ERR_INVALID_ARG;
     if (n > 0 && (!points || !flow || !status)) return DGF_ERR_INVALID_ARG;
-    dgf_track_opts o;
     if (opts) {
-        o = *opts;
-        if (o.flags != 0) return DGF_ERR_UNSUPPORTED;
+        *o = *opts;
+        if (o->flags != 0) return DGF_ERR_UNSUPPORTED;
     } else {
-        dgf_track_opts_default(&o);
+        dgf_track_opts_default(o);
     }
-    if (!(o.sigma1 >= 0.f) || !(o.sigma2 >= 0.f) || !(o.eps_coarse >= 0.f) || !(o.eps_fine >= 0.f) || isnan(o.min_eig))
+    if (!(o->sigma1 >= 0.f) || !(o->sigma2 >= 0.f) || !(o->eps_coarse >= 0.f) || !(o->eps_fine >= 0.f) ||
+        isnan(o->min_eig))
         return DGF_ERR_INVALID_ARG;
-    if (isinf(o.sigma2) && !isinf(o.sigma1)) return DGF_ERR_INVALID_ARG; // no finite inner band with infinite outer
+    if (isinf(o->sigma2) && !isinf(o->sigma1)) return DGF_ERR_INVALID_ARG; // no finite inner band with infinite outer
     if (levels > 1 && (!workspace || ws_bytes < dgf_track_workspace_bytes(I0->width, I0->height, levels, I0->dtype)))
         return DGF_ERR_WORKSPACE;
-    TrackTuning tune = tuning_for(support, levels, I0->dtype, n);
+    return DGF_OK;
+}
+
+// Tracking on pyramids already in `workspace`, with an explicit launch shape (validated).
+int track_run_with(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
+                   int32_t support, int32_t iters, const dgf_track_opts &o, const void *workspace, float *flow,
+                   uint8_t *status, int32_t *iters_out, TrackTuning tune, hipStream_t st)
+{
     if (!track_shape_ok(support, tune)) return DGF_ERR_UNSUPPORTED;
     while (track_lds_bytes(support, tune) > kMaxLdsPerBlock && tune.wpb > 1) tune.wpb /= 2;
     if (track_lds_bytes(support, tune) > kMaxLdsPerBlock) return DGF_ERR_UNSUPPORTED;
     if (n == 0) return DGF_OK;
-
     TrackParams P{};
     pyramid_levels(I0, I1, levels, workspace, P.lv, nullptr);
     P.pts = points;
@@ -218,7 +229,22 @@ int dgf_track_run(const dgf_image *I0, const dgf_image *I1, const float *points,
     P.iters = iters;
     fill_track_geometry(P, support, tune.margin, tune.lpp, tune.kind);
     fill_track_constants(P, o, support);
-    return hip_rc(launch_track(P, tune, I0->dtype, (hipStream_t)stream));
+    return hip_rc(launch_track(P, tune, I0->dtype, st));
+}
+
+} // namespace dgf
+
+extern "C" {
+
+int dgf_track_run(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
+                  int32_t support, int32_t iters, const dgf_track_opts *opts, const void *workspace, size_t ws_bytes,
+                  float *flow, uint8_t *status, int32_t *iters_out, void *stream)
+{
+    dgf_track_opts o;
+    const int rc = validate_track(I0, I1, points, n, levels, support, iters, opts, workspace, ws_bytes, flow, status, &o);
+    if (rc != DGF_OK) return rc;
+    return track_run_with(I0, I1, points, n, levels, support, iters, o, workspace, flow, status, iters_out,
+                          tuning_for(support, levels, I0->dtype, n), (hipStream_t)stream);
 }
 
 int dgf_track(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,

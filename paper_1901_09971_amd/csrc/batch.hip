@@ -245,7 +245,7 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
     ok = ok && hipMemcpy(b->d_pyr, jobs.data(), sizeof(PyrJob) * jobs.size(), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->d_det, det.data(), sizeof(DetectJob) * det.size(), hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) {
-        hipFree(b->dmem);
+        (void)hipFree(b->dmem);
         delete b;
         return DGF_ERR_HIP;
     }
@@ -275,11 +275,11 @@ int dgf_batch_capture(dgf_batch *b, float *points, float *flow, uint8_t *status,
     if (!b || !stream) return DGF_ERR_INVALID_ARG; // graphs are captured from a created stream
     if (b->total_pts > 0 && (!points || !flow || !status)) return DGF_ERR_INVALID_ARG;
     if (b->exec) {
-        hipGraphExecDestroy(b->exec);
+        (void)hipGraphExecDestroy(b->exec);
         b->exec = nullptr;
     }
     if (b->graph) {
-        hipGraphDestroy(b->graph);
+        (void)hipGraphDestroy(b->graph);
         b->graph = nullptr;
     }
     if (b->total_pts == 0) return DGF_OK;
@@ -289,12 +289,12 @@ int dgf_batch_capture(dgf_batch *b, float *points, float *flow, uint8_t *status,
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(st, &g);
     if (rc != DGF_OK || e != hipSuccess || !g) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return rc != DGF_OK ? rc : DGF_ERR_HIP;
     }
     hipGraphExec_t ex = nullptr;
     if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         return DGF_ERR_HIP;
     }
     b->graph = g;
@@ -313,8 +313,8 @@ int dgf_batch_replay(dgf_batch *b, void *stream)
 int dgf_batch_destroy(dgf_batch *b)
 {
     if (!b) return DGF_OK;
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     int rc = DGF_OK;
     if (b->dmem && hipFree(b->dmem) != hipSuccess) rc = DGF_ERR_HIP;
     delete b;

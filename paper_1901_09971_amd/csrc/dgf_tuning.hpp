@@ -14,6 +14,15 @@ TrackTuning tuning_for(int support, int levels, int dtype, int64_t n);
 void fill_track_constants(TrackParams &P, const dgf_track_opts &o, int support);
 
 bool tuning_valid(const TrackTuning &t, int support);
+
+// Argument validation shared by the tracking entry points (fills the effective options), and
+// tracking on already-built pyramids with an explicit launch shape.
+int validate_track(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
+                   int32_t support, int32_t iters, const dgf_track_opts *opts, const void *workspace, size_t ws_bytes,
+                   const float *flow, const uint8_t *status, dgf_track_opts *o);
+int track_run_with(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
+                   int32_t support, int32_t iters, const dgf_track_opts &o, const void *workspace, float *flow,
+                   uint8_t *status, int32_t *iters_out, TrackTuning tune, hipStream_t st);
 void set_tuning(int support, int dtype, const TrackTuning &t);
 bool get_installed(int support, int dtype, TrackTuning *out);
 

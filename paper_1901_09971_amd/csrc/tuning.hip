@@ -76,16 +76,15 @@ TrackTuning tuning_for(int support, int levels, int dtype, int64_t n)
 {
     (void)levels;
     (void)n;
+    // DGF_TUNE="lpp,wpb,margin[,kind]" takes precedence (launch-shape experiments and tests)
+    if (const char *env = getenv("DGF_TUNE")) {
+        TrackTuning e{0, 0, 0, 0};
+        const int k = sscanf(env, "%d,%d,%d,%d", &e.lpp, &e.wpb, &e.margin, &e.kind);
+        if (k >= 3 && tuning_valid(e, support)) return e;
+    }
     TrackTuning t;
     if (get_installed(support, dtype, &t)) return t;
     t = heuristic(support);
-    // DGF_TUNE="lpp,wpb,margin[,kind]" overrides the heuristic (launch-shape experiments)
-    if (const char *env = getenv("DGF_TUNE")) {
-        TrackTuning e = t;
-        e.kind = 0;
-        const int k = sscanf(env, "%d,%d,%d,%d", &e.lpp, &e.wpb, &e.margin, &e.kind);
-        if (k >= 3 && tuning_valid(e, support)) t = e;
-    }
     if (!tuning_valid(t, support)) {
         t.lpp = 64;
         t.kind = 1;

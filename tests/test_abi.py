@@ -123,3 +123,20 @@ def test_argument_validation_before_launch():
     assert L.dgf_pyramid(ctypes.byref(im), 1, None, 0, None) == 0
     assert L.dgf_track_pyramids(ctypes.byref(im), ctypes.byref(_img(h=47)), 3, P, ws, None) == -1
     assert L.dgf_track_pyramids(ctypes.byref(im), ctypes.byref(im), 3, P, ws - 1, None) == -5
+
+
+def test_tuning_table_host_only():
+    L = _lib.lib()
+    t = _lib.DgfTuning()
+    assert L.dgf_get_tuning(21, 5, 0, 18278, ctypes.byref(t)) == 0
+    assert t.lanes_per_point in (16, 32, 64) and t.waves_per_group in (1, 2, 4) and t.kernel in (0, 1)
+    assert L.dgf_get_tuning(8, 5, 0, 10, ctypes.byref(t)) == -1
+    assert L.dgf_get_tuning(21, 5, 3, 10, ctypes.byref(t)) == -1
+    # install / read back / reject shapes without a kernel
+    new = _lib.DgfTuning(32, 2, 3, 1, -1.0)
+    assert L.dgf_set_tuning(13, 0, ctypes.byref(new)) == 0
+    assert L.dgf_get_tuning(13, 3, 0, 100, ctypes.byref(t)) == 0
+    assert (t.lanes_per_point, t.waves_per_group, t.margin, t.kernel) == (32, 2, 3, 1)
+    assert L.dgf_set_tuning(31, 0, ctypes.byref(_lib.DgfTuning(16, 1, 2, 1, -1.0))) == -3  # 61 slots: none compiled
+    assert L.dgf_set_tuning(13, 0, ctypes.byref(_lib.DgfTuning(24, 1, 2, 1, -1.0))) == -3
+    assert L.dgf_set_tuning(13, 0, None) == -1

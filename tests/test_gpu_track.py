@@ -52,6 +52,18 @@ def test_driving_1242x375_full():
     _run(I0, I1, pts, 5, 21, 20, 0.97)
 
 
+def test_driving_1242x375_autotuned_shape():
+    # the launch shape the benchmark times: autotuned on this pair
+    I0, I1, _, _ = synth.driving_1242x375()
+    t0, t1 = torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda()
+    before = dgf.get_tuning(21, 5, 0, 0)
+    best = dgf.autotune(t0, t1, dgf.detect(t0, 9, 5), 5, 21, 20)
+    print("autotuned:", best, flush=True)
+    pts = oracle.detect(I0, 9, 5)[0].astype(np.float32)
+    _run(I0, I1, pts, 5, 21, 20, 0.97)
+    dgf.set_tuning(21, 0, before["lanes_per_point"], before["waves_per_group"], before["margin"], before["kernel"])
+
+
 def test_translation_f32_1242x375():
     I0, I1, _ = synth.translation_f32_1242x375()
     pts = oracle.detect(np.clip(np.rint(I0), 0, 255).astype(np.uint8), 9, 8)[0].astype(np.float32)
