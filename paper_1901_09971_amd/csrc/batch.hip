@@ -2,10 +2,12 @@
 // the host (descriptor tables and every pyramid in one device allocation), then per run
 //   * one launch per pyramid level covering all 2P frames (a job table, blockIdx.z = frame),
 //   * one detection launch covering all pairs (blockIdx.z = pair, per-pair window and stride),
-//   * a one-thread kernel that clears the work counter (no memset node, so the sequence can be
+//   * a one-block kernel that clears the work counters (no memset node, so the sequence can be
 //     captured in a graph and replayed),
 //   * one persistent tracking launch: a resident-sized grid whose wavefronts pull work items
-//     (a group of points of one pair) from the counter until it passes the item count.
+//     (a group of points of one pair) from per-XCD counters over contiguous item ranges, so the
+//     pairs one XCD tracks stay in its own L2, and steal from the other ranges once theirs is
+//     drained.
 // Outputs of all pairs are concatenated in pair order.  The whole sequence can be captured once
 // into a hipGraph and replayed with a single launch.
 #include <math.h>
@@ -20,7 +22,11 @@
 
 namespace dgf {
 
-__global__ void k_fill_u32(uint32_t *p, uint32_t v) { *p = v; }
+// Clears the kNumXcd work counters (one thread each; launched as one block of kNumXcd threads).
+__global__ void k_clear_counters(uint32_t *c)
+{
+    if (threadIdx.x < kNumXcd) c[(size_t)threadIdx.x * kCounterStride] = 0u;
+}
 
 } // namespace dgf
 
@@ -69,7 +75,7 @@ int launch_all(dgf_batch *b, float *points, float *flow, uint8_t *status, int32_
     }
     if (launch_detect_batched(b->d_det, b->P, b->det_tiles_x, b->det_tiles_y, b->det_lds, points, st) != hipSuccess)
         return DGF_ERR_HIP;
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, st, b->d_counter, 0u);
+    hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(kNumXcd), 0, st, b->d_counter);
     if (hipGetLastError() != hipSuccess) return DGF_ERR_HIP;
     TrackParams P{};
     P.pts = points;
@@ -193,7 +199,7 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
     const int64_t o_pt = sz;
     sz = align_up(sz + 8 * (npairs + 1), 256);
     const int64_t o_ctr = sz;
-    sz = align_up(sz + 4, 256);
+    sz = align_up(sz + 4 * kCounterStride * kNumXcd, 256);
     const int64_t o_pyrjobs = sz;
     sz = align_up(sz + (int64_t)sizeof(PyrJob) * 2 * npairs * std::max(levels - 1, 1), 256);
     const int64_t o_det = sz;

@@ -154,7 +154,7 @@ struct TrackParams {
     // batched form (npairs = 0 for a single pair): per-pair level table, prefix sums of per-pair
     // work items (groups of points of one pair handled by one wavefront) and of per-pair points
     int32_t npairs;
-    int32_t persistent;  // 1: waves pull items from *counter until it passes nitems
+    int32_t persistent;  // 1: waves pull items from the per-XCD counters until all ranges are drained
     const LevelPair *blv; // [npairs][L]
     const int64_t *item_off, *pt_off; // [npairs + 1] each
     uint32_t *counter;
@@ -201,12 +201,30 @@ __device__ __forceinline__ WorkItem work_item(const TrackParams &P, int64_t item
     return w;
 }
 
-// Next work item of a persistent wavefront: one lane bumps the counter, all lanes take its value.
-__device__ __forceinline__ int64_t next_item(uint32_t *counter)
+// The hardware hands the blocks of a launch to the eight XCDs in turn (block b runs on XCD b mod 8)
+// and every XCD has an L2 of its own.
+constexpr int kNumXcd = 8;
+
+// Persistent form: the items are split into kNumXcd contiguous ranges, one per XCD, each with a
+// counter of its own (kCounterStride words apart, so they sit in different cache lines).  A
+// wavefront takes items from the range of the XCD it runs on and, once that range is drained, from
+// the next ones in turn; it leaves after all of them are.  Every wavefront therefore ends after at
+// most (its items + kNumXcd) counter bumps, and every item is handed out exactly once.  `visit` is
+// wavefront-uniform (all lanes take lane 0's counter value).
+constexpr int kCounterStride = 64;
+
+__device__ __forceinline__ int64_t next_item(const TrackParams &P, int home, int &visit)
 {
-    unsigned v = 0u;
-    if ((threadIdx.x & 63) == 0) v = atomicAdd(counter, 1u);
-    return (int64_t)__builtin_amdgcn_readfirstlane(v);
+    while (visit < kNumXcd) {
+        const int k = (home + visit) % kNumXcd;
+        const int64_t lo = P.nitems * k / kNumXcd, hi = P.nitems * (k + 1) / kNumXcd;
+        unsigned v = 0u;
+        if ((threadIdx.x & 63) == 0) v = atomicAdd(P.counter + (size_t)k * kCounterStride, 1u);
+        const int64_t item = lo + (int64_t)__builtin_amdgcn_readfirstlane(v);
+        if (item < hi) return item;
+        ++visit;
+    }
+    return P.nitems;
 }
 
 __device__ __forceinline__ LevelPair level_of(const TrackParams &P, int pair, int l)

@@ -75,7 +75,13 @@ __global__ __launch_bounds__(256) void k_track(TrackParams P)
 
     float T[PPL], GX[PPL], GY[PPL], GXX[PPL], GXY[PPL], GYY[PPL];
 
-    int64_t item = P.persistent ? next_item(P.counter) : (int64_t)blockIdx.x * wpb + wave;
+    // Plain launches keep the hardware's order: block b on XCD b mod 8 spreads every image band
+    // over all eight XCDs, which balances the uneven per-point work.  (Giving each XCD one band
+    // cut L2 fills 4.6x on the 1242x375 benchmark pair but made the launch 25% longer.)
+    // Persistent launches pull from the queue of their own XCD first.
+    const int home = (int)(blockIdx.x % kNumXcd);
+    int visit = 0;
+    int64_t item = P.persistent ? next_item(P, home, visit) : (int64_t)blockIdx.x * wpb + wave;
     for (;;) {
     const WorkItem wi = work_item<PPW>(P, item, q);
     if (wi.done) break;
@@ -347,7 +353,7 @@ __global__ __launch_bounds__(256) void k_track(TrackParams P)
         if (P.iters_out) P.iters_out[pidx] = it_total;
     }
     if (!P.persistent) break;
-    item = next_item(P.counter);
+    item = next_item(P, home, visit);
     } // work loop
 }
 
