@@ -58,7 +58,9 @@ typedef struct {
     const void *data;    /* device pointer to row 0                                   */
     int32_t width;       /* columns, >= 1                                             */
     int32_t height;      /* rows, >= 1                                                */
-    int64_t pitch_bytes; /* bytes between consecutive rows, >= width * element size   */
+    int64_t pitch_bytes; /* bytes between consecutive rows, >= width * element size;
+                            pitch_bytes < 2^24, height < 2^24 and pitch_bytes * height
+                            < 2^31 (2 GiB); larger images are rejected                 */
     int32_t dtype;       /* DGF_U8 or DGF_F32                                         */
 } dgf_image;
 

@@ -22,6 +22,9 @@ bool image_ok(const dgf_image *im)
     if (e == 0) return false;
     if (im->pitch_bytes < (int64_t)im->width * e) return false;
     if (im->dtype == DGF_F32 && ((uintptr_t)im->data % 4 != 0 || im->pitch_bytes % 4 != 0)) return false;
+    // kernels address pixels with 24-bit row x pitch products and 32-bit byte offsets
+    if (im->pitch_bytes >= (1 << 24) || im->height >= (1 << 24) || im->pitch_bytes > (int64_t)INT32_MAX / im->height)
+        return false;
     return true;
 }
 

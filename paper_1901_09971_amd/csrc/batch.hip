@@ -60,7 +60,9 @@ bool pair_ok(const dgf_pair_desc &d, int dtype)
     auto ok = [&](const dgf_image &im) {
         const int e = im.dtype == DGF_U8 ? 1 : (im.dtype == DGF_F32 ? 4 : 0);
         return im.data && im.width >= 1 && im.height >= 1 && e && im.dtype == dtype &&
-               im.pitch_bytes >= (int64_t)im.width * e && (e == 1 || (im.pitch_bytes % 4 == 0 && (uintptr_t)im.data % 4 == 0));
+               im.pitch_bytes >= (int64_t)im.width * e && im.pitch_bytes < (1 << 24) && im.height < (1 << 24) &&
+               im.pitch_bytes <= (int64_t)INT32_MAX / im.height &&
+               (e == 1 || (im.pitch_bytes % 4 == 0 && (uintptr_t)im.data % 4 == 0));
     };
     return ok(d.I0) && ok(d.I1) && d.I0.width == d.I1.width && d.I0.height == d.I1.height && d.window >= 1 &&
            d.window <= DGF_MAX_WINDOW && d.stride >= 1;

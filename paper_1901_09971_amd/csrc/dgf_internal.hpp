@@ -113,10 +113,63 @@ __device__ __forceinline__ void wave_sum5(float &a, float &b, float &c, float &d
 
 __device__ __forceinline__ bool wave_all(bool p) { return __builtin_amdgcn_ballot_w64(!p) == 0ull; }
 
-template <typename PixT>
-__device__ __forceinline__ float load_px(const uint8_t *base, int64_t pitch, int x, int y)
+// Lane layout for staging a rectangle `cols` floats wide with the LPP lanes of one point.  With
+// cols <= LPP, rpp = LPP / cols rows go per pass and lane li keeps column c = li mod cols of row
+// r0 = li / cols (lanes with r0 >= rpp stay idle); a wider rectangle takes one row per pass and
+// lane li keeps columns li, li + LPP, ...  `cols` is a launch constant, so this runs once per
+// launch.
+struct StageLanes {
+    int rpp, r0, c;
+};
+
+template <int LPP>
+__device__ __forceinline__ StageLanes stage_lanes(int cols, int li)
 {
-    return (float)reinterpret_cast<const PixT *>(base + (int64_t)y * pitch)[x];
+    StageLanes sl;
+    if (cols <= LPP) {
+        sl.rpp = LPP / cols;
+        sl.r0 = li / cols;
+        sl.c = li - sl.r0 * cols;
+    } else {
+        sl.rpp = 1;
+        sl.r0 = 0;
+        sl.c = li;
+    }
+    return sl;
+}
+
+// Copies the rows x cols rectangle of a level image whose top-left pixel is (ox, oy) into LDS
+// (row pitch lp floats), replicating the image border.  Every address is clamped into the image,
+// so the loads run unpredicated and kStageBatch of them are in flight before the first LDS write;
+// only the writes check the row count.  Byte offsets are 24-bit row x pitch products in 32 bits
+// off a scalar global base: the host rejects pitches of 2^24 bytes or more and images of 2 GiB or
+// more.
+constexpr int kStageBatch = 2;
+
+template <int LPP, typename PixT>
+__device__ __forceinline__ void stage_rect(float *lds, int lp, const uint8_t *base, int64_t pitch, int W, int H, int ox,
+                                           int oy, int rows, int cols, const StageLanes &sl)
+{
+    typedef const __attribute__((address_space(1))) uint8_t gbyte;
+    if (sl.r0 >= sl.rpp) return;
+    gbyte *gb = (gbyte *)base;
+    const uint32_t pb = (uint32_t)pitch, hm1 = (uint32_t)(H - 1);
+    for (int c = sl.c; c < cols; c += LPP) { // a single pass when cols <= LPP
+        const uint32_t cx = (uint32_t)clampi(ox + c, 0, W - 1) * (uint32_t)sizeof(PixT);
+        for (int y0 = sl.r0; y0 < rows; y0 += kStageBatch * sl.rpp) {
+            float v[kStageBatch];
+#pragma unroll
+            for (int k = 0; k < kStageBatch; ++k) {
+                const uint32_t cy = min((uint32_t)max(oy + y0 + k * sl.rpp, 0), hm1);
+                v[k] = (float)*reinterpret_cast<const __attribute__((address_space(1))) PixT *>(gb + (__umul24(cy, pb) + cx));
+            }
+#pragma unroll
+            for (int k = 0; k < kStageBatch; ++k) {
+                const int y = y0 + k * sl.rpp;
+                if (y < rows) lds[y * lp + c] = v[k];
+            }
+        }
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -144,7 +197,6 @@ struct TrackParams {
     int32_t RW;          // raw I0 tile width = s + 3
     int32_t RPP;         // LDS row pitch of the raw / resampled I0 tiles (>= RW, chosen to spread banks)
     int32_t tile_floats; // LDS floats per point = max(RW RPP + (s+2) RPP, TW * TP)
-    float invTW, invRW;
     float invBW;         // 1 / (s + 2)
     int32_t mode;        // ROBUST_L2, ROBUST_HAMPEL or ROBUST_HARD
     float s1, s2, cmid;  // robust thresholds and sigma1 / (sigma2 - sigma1) (0 if unused)
@@ -227,16 +279,44 @@ __device__ __forceinline__ int64_t next_item(const TrackParams &P, int home, int
     return P.nitems;
 }
 
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
+{
+    return (uint64_t)uniform_u32((uint32_t)v) | ((uint64_t)uniform_u32((uint32_t)(v >> 32)) << 32);
+}
+
+// Level descriptors of the pair a wavefront works on.  The value is the same in every lane; the
+// readfirstlanes tell the compiler so, and keep base pointers and sizes in scalar registers (the
+// table is read through a generic pointer, kernel argument or device memory, which it cannot
+// prove uniform on its own).
 __device__ __forceinline__ LevelPair level_of(const TrackParams &P, int pair, int l)
 {
-    return P.npairs ? P.blv[pair * P.L + l] : P.lv[l];
+    const LevelPair v = P.npairs ? P.blv[pair * P.L + l] : P.lv[l];
+    LevelPair u;
+    u.p0 = reinterpret_cast<const uint8_t *>(uniform_u64(reinterpret_cast<uint64_t>(v.p0)));
+    u.p1 = reinterpret_cast<const uint8_t *>(uniform_u64(reinterpret_cast<uint64_t>(v.p1)));
+    u.pitch0 = (int64_t)uniform_u64((uint64_t)v.pitch0);
+    u.pitch1 = (int64_t)uniform_u64((uint64_t)v.pitch1);
+    u.W = (int)uniform_u32((uint32_t)v.W);
+    u.H = (int)uniform_u32((uint32_t)v.H);
+    return u;
 }
 
 // How the robust weight w = psi(r)/r is evaluated (chosen on the host from sigma1, sigma2):
 //   ROBUST_L2     both thresholds infinite: w = 1 everywhere (plain least squares)
-//   ROBUST_HAMPEL sigma1 < sigma2 finite: w = min(1, max(cmid (sigma2 - |r|), 0) / |r|)
-//   ROBUST_HARD   sigma1 >= sigma2: w = 1 for |r| <= sigma1, else 0
+//   ROBUST_HAMPEL 0 < sigma1 < sigma2 finite: w = hampel_weight(r) below
+//   ROBUST_HARD   sigma1 >= sigma2, or sigma1 = 0: w = 1 for |r| <= sigma1, else 0
 enum { ROBUST_L2 = 0, ROBUST_HAMPEL = 1, ROBUST_HARD = 2 };
+
+// IRLS weight of the middle-band norm, psi(r) / r = clamp(cs2 / |r| - cmid, 0, 1) with
+// cmid = sigma1 / (sigma2 - sigma1) and cs2 = cmid sigma2: exactly 1 over the inner band
+// (cs2 / sigma1 - cmid = 1), falling to 0 at sigma2.  At r = 0 the reciprocal is infinite and the
+// clamp gives the limit 1.  Needs sigma1 > 0 (otherwise cs2 = 0 and 0 * inf is undefined).
+__device__ __forceinline__ float hampel_weight(float r, float cs2, float cmid)
+{
+    return __builtin_amdgcn_fmed3f(fmaf(cs2, __builtin_amdgcn_rcpf(fabsf(r)), -cmid), 0.f, 1.f);
+}
 
 struct TrackTuning {
     int lpp;     // lanes per point: 16, 32 or 64

@@ -74,8 +74,6 @@ void fill_track_geometry(TrackParams &P, int s, int margin, int lpp, int kind)
     const int tmpl = P.RW * P.RPP + (s + 2) * P.RPP;
     const int iter = P.TW * tp;
     P.tile_floats = tmpl > iter ? tmpl : iter;
-    P.invTW = 1.0f / (float)P.TW;
-    P.invRW = 1.0f / (float)P.RW;
     P.invBW = 1.0f / (float)(s + 2);
     P.ppl = (s * s + lpp - 1) / lpp;
 }

@@ -51,13 +51,14 @@ __global__ __launch_bounds__(256) void k_track(TrackParams P)
     constexpr int LTP = Log2<TP>::v;
     extern __shared__ float smem[];
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wpb = blockDim.x >> 6;
     const int q = lane / LPP;
     const int li = lane - q * LPP;
     float *tile = smem + (size_t)(wave * PPW + q) * P.tile_floats;
 
     const int s = P.s, r = P.r, S2 = s * s, RW = P.RW, RP = P.RPP, TW = P.TW, M = P.M;
+    const StageLanes slR = stage_lanes<LPP>(RW, li), slT = stage_lanes<LPP>(TW, li);
 
     // slot geometry: off = ky * TP + kx (kx, ky in [0, s)); unused slots read offset 0 and
     // carry zero gradients, so they add nothing to any sum
@@ -122,12 +123,7 @@ __global__ __launch_bounds__(256) void k_track(TrackParams P)
         // ---- template: stage I0_l over the support plus a one-pixel ring (RW = s + 3 square,
         //      row pitch RP), with index clamping (replicated border)
         wave_sync();
-        for (int c = li; c < RW * RW; c += LPP) {
-            const int ty = (int)(((float)c + 0.5f) * P.invRW);
-            const int tx = c - ty * RW;
-            tile[ty * RP + tx] =
-                load_px<PixT>(LV.p0, LV.pitch0, clampi(ibx - 1 + tx, 0, Wl - 1), clampi(iby - 1 + ty, 0, Hl - 1));
-        }
+        stage_rect<LPP, PixT>(tile, RP, LV.p0, LV.pitch0, Wl, Hl, ibx - 1, iby - 1, RW, RW, slR);
         wave_sync();
         const float w00 = (1.f - pfx) * (1.f - pfy), w10 = pfx * (1.f - pfy);
         const float w01 = (1.f - pfx) * pfy, w11 = pfx * pfy;
@@ -200,12 +196,7 @@ __global__ __launch_bounds__(256) void k_track(TrackParams P)
                 wave_sync();
                 ox1 = bx - M;
                 oy1 = by - M;
-                for (int cc = li; cc < TW * TW; cc += LPP) {
-                    const int yy = (int)(((float)cc + 0.5f) * P.invTW);
-                    const int xx = cc - yy * TW;
-                    tile[yy * TP + xx] =
-                        load_px<PixT>(LV.p1, LV.pitch1, clampi(ox1 + xx, 0, Wl - 1), clampi(oy1 + yy, 0, Hl - 1));
-                }
+                stage_rect<LPP, PixT>(tile, TP, LV.p1, LV.pitch1, Wl, Hl, ox1, oy1, TW, TW, slT);
                 wave_sync();
                 dxo = M;
                 dyo = M;
@@ -244,9 +235,7 @@ __global__ __launch_bounds__(256) void k_track(TrackParams P)
                     for (int j = 0; j < PPL; ++j) {
                         const float *tp = tb + off[j];
                         const float res = q00 * tp[0] + q10 * tp[1] + q01 * tp[TP] + q11 * tp[TP + 1] - T[j];
-                        const float ar = fabsf(res);
-                        const float t = fmaxf(fmaf(-P.cmid, ar, P.cs2), 0.f);
-                        const float w = fminf(1.f, t * __builtin_amdgcn_rcpf(ar));
+                        const float w = hampel_weight(res, P.cs2, P.cmid);
                         const float ps = w * res;
                         G11 = fmaf(w, GXX[j], G11);
                         G12 = fmaf(w, GXY[j], G12);

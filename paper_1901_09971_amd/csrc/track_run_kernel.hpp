@@ -55,13 +55,14 @@ __global__ __launch_bounds__(256) void k_track_run(TrackParams P)
     constexpr int PPL = SEG * R;
     extern __shared__ float smem[];
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wpb = blockDim.x >> 6;
     const int q = lane / LPP;
     const int li = lane - q * LPP;
     float *tile = smem + (size_t)(wave * PPW + q) * P.tile_floats;
 
     const int s = P.s, r = P.r, RW = P.RW, RP = P.RPP, TW = P.TW, M = P.M;
+    const StageLanes slR = stage_lanes<LPP>(RW, li), slT = stage_lanes<LPP>(TW, li);
     const int nseg_row = s / R; // runs per support row
     const int nseg = s * nseg_row;
 
@@ -129,38 +130,33 @@ __global__ __launch_bounds__(256) void k_track_run(TrackParams P)
 
         // ---- template: raw I0_l patch (s+3)^2 with replicated border, row pitch RP
         wave_sync();
-        for (int c = li; c < RW * RW; c += LPP) {
-            const int ty = (int)(((float)c + 0.5f) * P.invRW);
-            const int tx = c - ty * RW;
-            tile[ty * RP + tx] =
-                load_px<PixT>(LV.p0, LV.pitch0, clampi(ibx - 1 + tx, 0, Wl - 1), clampi(iby - 1 + ty, 0, Hl - 1));
-        }
+        stage_rect<LPP, PixT>(tile, RP, LV.p0, LV.pitch0, Wl, Hl, ibx - 1, iby - 1, RW, RW, slR);
         wave_sync();
-        // value and central differences at +-1 px of the bilinearly resampled patch
+        // value and central differences at +-1 px of the bilinearly resampled patch.  The
+        // vertical difference is resampled as one patch (bilinear sampling is linear).  Unused
+        // runs get half = 0, so their gradients vanish; they read run 0's pixels, so a
+        // non-finite pixel there reaches the sums through run 0 anyway.
         {
 #pragma unroll
             for (int j = 0; j < SEG; ++j) {
                 const int row = rc[j] >> 8, col0 = rc[j] & 255;
                 const float *rp = tile + row * RP + col0; // raw rows row .. row+3, cols col0 .. col0+R+2
-                float V0[R + 3], V1[R + 3], V2[R + 3];
+                const float half = ((vmask >> j) & 1u) ? 0.5f : 0.f;
+                float V1[R + 3], D[R + 3];
 #pragma unroll
                 for (int cc = 0; cc < R + 3; ++cc) {
                     const float r0 = rp[cc], r1 = rp[RP + cc], r2 = rp[2 * RP + cc], r3 = rp[3 * RP + cc];
-                    V0[cc] = fmaf(pfy, r1 - r0, r0);
                     V1[cc] = fmaf(pfy, r2 - r1, r1);
-                    V2[cc] = fmaf(pfy, r3 - r2, r2);
+                    D[cc] = fmaf(pfy, (r3 - r2) - (r1 - r0), r2 - r0); // row +1 minus row -1
                 }
                 float B1[R + 2];
 #pragma unroll
                 for (int cc = 0; cc < R + 2; ++cc) B1[cc] = fmaf(pfx, V1[cc + 1] - V1[cc], V1[cc]);
-                const bool vg = (vmask >> j) & 1u;
 #pragma unroll
                 for (int p = 0; p < R; ++p) {
-                    const float b0 = fmaf(pfx, V0[p + 2] - V0[p + 1], V0[p + 1]);
-                    const float b2 = fmaf(pfx, V2[p + 2] - V2[p + 1], V2[p + 1]);
-                    T[j * R + p] = vg ? B1[p + 1] : 0.f;
-                    GX[j * R + p] = vg ? 0.5f * (B1[p + 2] - B1[p]) : 0.f;
-                    GY[j * R + p] = vg ? 0.5f * (b2 - b0) : 0.f;
+                    T[j * R + p] = B1[p + 1];
+                    GX[j * R + p] = half * (B1[p + 2] - B1[p]);
+                    GY[j * R + p] = half * fmaf(pfx, D[p + 2] - D[p + 1], D[p + 1]);
                 }
             }
         }
@@ -204,12 +200,7 @@ __global__ __launch_bounds__(256) void k_track_run(TrackParams P)
                 wave_sync();
                 ox1 = bx - M;
                 oy1 = by - M;
-                for (int cc = li; cc < TW * TW; cc += LPP) {
-                    const int yy = (int)(((float)cc + 0.5f) * P.invTW);
-                    const int xx = cc - yy * TW;
-                    tile[yy * TP + xx] =
-                        load_px<PixT>(LV.p1, LV.pitch1, clampi(ox1 + xx, 0, Wl - 1), clampi(oy1 + yy, 0, Hl - 1));
-                }
+                stage_rect<LPP, PixT>(tile, TP, LV.p1, LV.pitch1, Wl, Hl, ox1, oy1, TW, TW, slT);
                 wave_sync();
                 dxo = M;
                 dyo = M;
@@ -220,18 +211,26 @@ __global__ __launch_bounds__(256) void k_track_run(TrackParams P)
             const float *tb = tile + dyo * TP + dxo;
 
             // residuals of every pixel of this lane's runs
+            // bilinear weights shared by every sample of this iteration; each residual is a chain
+            // of four FMAs started from -T
+            const float w11 = fx * fy, w10 = fx - w11, w01 = fy - w11, w00 = (1.f - fx) - w01;
             float RES[PPL];
 #pragma unroll
             for (int j = 0; j < SEG; ++j) {
                 const float *rp = tb + sb[j];
-                float h[R + 1];
+                float t0[R + 1], t1[R + 1];
 #pragma unroll
                 for (int cc = 0; cc < R + 1; ++cc) {
-                    const float t0 = rp[cc], t1 = rp[TP + cc];
-                    h[cc] = fmaf(fy, t1 - t0, t0);
+                    t0[cc] = rp[cc];
+                    t1[cc] = rp[TP + cc];
                 }
 #pragma unroll
-                for (int p = 0; p < R; ++p) RES[j * R + p] = fmaf(fx, h[p + 1] - h[p], h[p]) - T[j * R + p];
+                for (int p = 0; p < R; ++p) {
+                    float v = fmaf(w00, t0[p], -T[j * R + p]);
+                    v = fmaf(w10, t0[p + 1], v);
+                    v = fmaf(w01, t1[p], v);
+                    RES[j * R + p] = fmaf(w11, t1[p + 1], v);
+                }
             }
 
             float G11, G12, G22, B1 = 0.f, B2 = 0.f, det;
@@ -254,28 +253,24 @@ __global__ __launch_bounds__(256) void k_track_run(TrackParams P)
                 if (P.mode == ROBUST_HAMPEL) {
 #pragma unroll
                     for (int j = 0; j < PPL; ++j) {
-                        const float ar = fabsf(RES[j]);
-                        const float t = fmaxf(fmaf(-P.cmid, ar, P.cs2), 0.f);
-                        const float w = fminf(1.f, t * __builtin_amdgcn_rcpf(ar));
-                        const float ps = w * RES[j];
+                        const float w = hampel_weight(RES[j], P.cs2, P.cmid);
                         const float wgx = w * GX[j], wgy = w * GY[j];
                         G11 = fmaf(wgx, GX[j], G11);
                         G12 = fmaf(wgx, GY[j], G12);
                         G22 = fmaf(wgy, GY[j], G22);
-                        B1 = fmaf(ps, GX[j], B1);
-                        B2 = fmaf(ps, GY[j], B2);
+                        B1 = fmaf(RES[j], wgx, B1);
+                        B2 = fmaf(RES[j], wgy, B2);
                     }
                 } else {
 #pragma unroll
                     for (int j = 0; j < PPL; ++j) {
                         const float w = (fabsf(RES[j]) <= P.s1) ? 1.f : 0.f;
-                        const float ps = w * RES[j];
                         const float wgx = w * GX[j], wgy = w * GY[j];
                         G11 = fmaf(wgx, GX[j], G11);
                         G12 = fmaf(wgx, GY[j], G12);
                         G22 = fmaf(wgy, GY[j], G22);
-                        B1 = fmaf(ps, GX[j], B1);
-                        B2 = fmaf(ps, GY[j], B2);
+                        B1 = fmaf(RES[j], wgx, B1);
+                        B2 = fmaf(RES[j], wgy, B2);
                     }
                 }
                 group_sum5<LPP>(G11, G12, G22, B1, B2);

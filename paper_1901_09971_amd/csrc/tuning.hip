@@ -99,11 +99,11 @@ void fill_track_constants(TrackParams &P, const dgf_track_opts &o, int support)
     if (isinf(o.sigma1)) {
         P.mode = ROBUST_L2; // |r| <= inf always: every weight is 1
         P.cmid = 0.0f;
-    } else if (o.sigma2 > o.sigma1 && isfinite(o.sigma2)) {
+    } else if (o.sigma1 > 0.f && o.sigma2 > o.sigma1 && isfinite(o.sigma2)) {
         P.mode = ROBUST_HAMPEL;
         P.cmid = o.sigma1 / (o.sigma2 - o.sigma1);
     } else {
-        P.mode = ROBUST_HARD; // empty middle band: w = 1 for |r| <= sigma1, else 0
+        P.mode = ROBUST_HARD; // empty middle band, or sigma1 = 0 (psi is 0 off r = 0): w = 1 for |r| <= sigma1, else 0
         P.cmid = 0.0f;
     }
     P.cs2 = P.cmid * o.sigma2;

@@ -95,6 +95,10 @@ def test_argument_validation_before_launch():
     assert L.dgf_detect(ctypes.byref(im), 129, 8, ctypes.c_void_p(1 << 20), None, None, 100, None) == -1
     assert L.dgf_detect(ctypes.byref(im), 9, 8, ctypes.c_void_p(1 << 20), None, None, 3, None) == -2
     assert L.dgf_detect(ctypes.byref(im), 9, 8, None, None, None, 100, None) == -1
+    # kernels use 24-bit row x pitch products and 32-bit byte offsets: larger images are rejected
+    assert L.dgf_detect(ctypes.byref(_img(pitch=1 << 24)), 9, 8, ctypes.c_void_p(1 << 20), None, None, 100, None) == -1
+    assert L.dgf_detect(ctypes.byref(_img(h=1 << 16, pitch=1 << 15)), 9, 8, ctypes.c_void_p(1 << 20), None, None, 100,
+                        None) == -1
     # image smaller than the window: nothing to do, nothing launched
     assert L.dgf_detect(ctypes.byref(_img(w=5, h=5, pitch=5)), 9, 8, None, None, None, 0, None) == 0
 
