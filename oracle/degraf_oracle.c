@@ -325,7 +325,8 @@ typedef struct {
  *   k in [-r, r]^2 (s = 2r + 1):
  *     T_k = B(I0_l, p_l + k), g_k = (B(I0_l, p_l + k + e_x) - B(I0_l, p_l + k - e_x)) / 2 and the
  *     same along y (central differences of the bilinear interpolant), G0 = sum g_k g_k^T.
- *     If lambda_min(G0)/s^2 < min_eig the point is ill-conditioned: u = 2^l g, stop.
+ *     If lambda_min(G0)/s^2 < min_eig the level gives no update (for l > 0: g = 2 g, next
+ *     level); at level 0 the point is ill-conditioned with u = g.
  *     d = 0; repeat up to iters times:
  *        r_k = B(I1_l, p_l + k + g + d) - T_k,  w_k = psi(r_k)/r_k,
  *        Gw = sum w_k g_k g_k^T,  b = -sum w_k r_k g_k,
@@ -379,10 +380,17 @@ static void track_point(const pyr_t *P0, const pyr_t *P1, double px, double py, 
             }
         const double lam_min = 0.5 * (a + c) - sqrt(0.25 * (a - c) * (a - c) + b * b);
         if (!(lam_min / (double)npix >= o->min_eig)) {
-            *ux = ldexp(gX, l);
-            *uy = ldexp(gY, l);
-            status = OR_ST_ILL_CONDITIONED;
-            break;
+            if (l == 0) { /* the full-resolution support cannot be tracked */
+                *ux = gX;
+                *uy = gY;
+                status = OR_ST_ILL_CONDITIONED;
+                break;
+            }
+            /* a flat coarse level gives no update: the guess goes on to the next level as is */
+            if (it_count) it_count[L - 1 - l] = 0;
+            gX = 2.0 * gX;
+            gY = 2.0 * gY;
+            continue;
         }
         const double det0 = a * c - b * b;
         const double eps = (l > 0) ? o->eps_coarse : o->eps_fine;

@@ -102,3 +102,25 @@ def lk_pyramidal(I0, I1, pts, levels, support, iters, eps_coarse, eps_fine):
         if l > 0:
             g = 2.0 * (g + d)
     return g + d, conv
+
+
+def min_eig_per_level(I0, pts, levels, support):
+    """lambda_min of the template-gradient matrix G0 = sum g g^T divided by support^2, per point and
+    level (central differences at +-1 px of the bilinear interpolant).  Returns [n][levels]."""
+    P0 = [I0]
+    for _ in range(levels - 1):
+        P0.append(pyr_down_scipy(P0[-1]))
+    P0 = [p.astype(np.float64) for p in P0]
+    pts = np.asarray(pts, np.float64)
+    r = support // 2
+    ky, kx = np.mgrid[-r:r + 1, -r:r + 1].astype(np.float64)
+    kx, ky = kx.ravel()[None, :], ky.ravel()[None, :]
+    out = np.zeros((len(pts), levels))
+    for l in range(levels):
+        pl = pts / 2.0 ** l
+        X, Y = pl[:, :1] + kx, pl[:, 1:] + ky
+        GX = 0.5 * (_sample(P0[l], X + 1.0, Y) - _sample(P0[l], X - 1.0, Y))
+        GY = 0.5 * (_sample(P0[l], X, Y + 1.0) - _sample(P0[l], X, Y - 1.0))
+        a, b, c = (GX * GX).sum(1), (GX * GY).sum(1), (GY * GY).sum(1)
+        out[:, l] = (0.5 * (a + c) - np.sqrt(0.25 * (a - c) ** 2 + b * b)) / support ** 2
+    return out

@@ -6,7 +6,7 @@ import pytest
 from scipy import ndimage
 
 import oracle
-from brute import lk_pyramidal
+from brute import lk_pyramidal, min_eig_per_level
 from paper_1901_09971_amd import synth
 
 INF = float("inf")
@@ -241,6 +241,26 @@ def test_ill_conditioned_constant_image():
     flow, st = oracle.track(I0, I0, pts, 3, 9, 10)
     assert np.all(st == oracle.ST_ILL_CONDITIONED)
     assert np.all(flow == 0.0)
+
+
+def test_flat_coarse_levels_pass_the_guess_on():
+    """A coarse level whose support is too flat to invert gives no update; only level 0 can make
+    a point ill-conditioned.  With every coarse level below min_eig and level 0 above it, the
+    pyramidal result must equal the single-level tracker's (the guess reaches level 0 as zero)."""
+    I0, I1, _ = synth.noise_translation_pair(96, 80, seed=21, shift=(0.6, -0.4), sigma=0.5)
+    rng = np.random.default_rng(4)
+    pts = np.stack([rng.uniform(20, 76, 12), rng.uniform(20, 60, 12)], 1)
+    lam = min_eig_per_level(I0, pts, 3, 9)
+    thr = np.sqrt(lam[:, 0].min() * lam[:, 1:].max())
+    assert lam[:, 0].min() > thr > lam[:, 1:].max()
+    f3, s3, it3 = oracle.track(I0, I1, pts, 3, 9, 20, min_eig=thr, return_iters=True)
+    f1, s1 = oracle.track(I0, I1, pts, 1, 9, 20, min_eig=thr)
+    assert np.array_equal(s3, s1) and np.array_equal(f3, f1)
+    assert np.all(it3[:, :2] == 0) and np.all(it3[:, 2] > 0)  # columns run coarsest level first
+    assert not np.any(s3 == oracle.ST_ILL_CONDITIONED)
+    # above level 0's eigenvalue every point is ill-conditioned and keeps the zero guess
+    f, s = oracle.track(I0, I1, pts, 3, 9, 20, min_eig=2.0 * lam[:, 0].max())
+    assert np.all(s == oracle.ST_ILL_CONDITIONED) and np.all(f == 0.0)
 
 
 def test_out_of_bounds_cases():
