@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "tracked points/sec (DeGraF+RLOF) @1242x375; batched vs plain frame-pairs/sec"
-FLOPS_PER_PIXEL_ITER = 24          # see the design doc: bilinear 7, residual 1, weight 3, psi 1, sums 12
+FLOPS_PER_PIXEL_ITER = 24          # per support pixel per iteration: bilinear 7, residual 1, weight 3, psi 1, sums 12
 PEAK_FP32_VALU_TFLOPS = 78.6       # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, unpacked FP32
 PEAK_HBM_GBPS = 8000.0
 WORKLOAD = dict(name="driving_1242x375", W=1242, H=375, window=9, stride=5, levels=5, support=21, iters=20)

@@ -43,7 +43,7 @@ extern "C" {
 /* ---- per-point tracking status ----------------------------------------------------------------- */
 #define DGF_ST_CONVERGED 0       /* level 0 stopped on the step-size test, p + u inside image    */
 #define DGF_ST_NOT_CONVERGED 1   /* level 0 ran out of iterations, or a step was not finite     */
-#define DGF_ST_ILL_CONDITIONED 2 /* lambda_min(G0) / s^2 < min_eig at some level                */
+#define DGF_ST_ILL_CONDITIONED 2 /* lambda_min(G0) / s^2 < min_eig at level 0 (u = the guess) */
 #define DGF_ST_OUT_OF_BOUNDS 3   /* input point, or converged p + u, outside [0,W-1] x [0,H-1]  */
 
 /* ---- element types ------------------------------------------------------------------------------ */
@@ -77,7 +77,8 @@ typedef struct {
                          infinite sigma2 is rejected (DGF_ERR_INVALID_ARG)               */
     float eps_coarse; /* a level > 0 stops when |step|_2 < eps_coarse px (default 1e-2) */
     float eps_fine;   /* level 0 stops when |step|_2 < eps_fine px (default 1e-4)       */
-    float min_eig;    /* ill-conditioned when lambda_min(G0)/s^2 < min_eig
+    float min_eig;    /* a level with lambda_min(G0)/s^2 < min_eig runs no iteration and
+                         passes its guess on; at level 0 the point is ill-conditioned
                          (default 1e-4 * 255^2)                                          */
     int32_t flags;    /* reserved, must be 0                                            */
 } dgf_track_opts;

@@ -168,10 +168,13 @@ __global__ __launch_bounds__(256) void k_track(TrackParams P)
             c = group_sum<LPP>(c);
         }
         const float lam = 0.5f * (a + c) - sqrtf(0.25f * (a - c) * (a - c) + b * b);
-        if (active && !(lam >= P.min_eig_s2)) {
+        // too flat to invert: a coarse level runs no iteration and passes the guess on; at
+        // level 0 the point is ill-conditioned with u = g
+        const bool flat = active && !(lam >= P.min_eig_s2);
+        if (flat && l == 0) {
             status = DGF_ST_ILL_CONDITIONED;
-            ux = __builtin_ldexpf(gX, l);
-            uy = __builtin_ldexpf(gY, l);
+            ux = gX;
+            uy = gY;
             active = false;
         }
         const float det0 = a * c - b * b;
@@ -180,7 +183,7 @@ __global__ __launch_bounds__(256) void k_track(TrackParams P)
         // ---- iterations
         dX = 0.f;
         dY = 0.f;
-        bool lvl_active = active, lvl_conv = false;
+        bool lvl_active = active && !flat, lvl_conv = false;
         int ox1 = 0, oy1 = 0; // origin of the staged I1 tile
         for (int it = 0; it < P.iters; ++it) {
             if (!wave_any(lvl_active)) break;
