@@ -215,6 +215,22 @@ int dgf_batch_run(dgf_batch *b, float *points, float *flow, uint8_t *status, int
 int dgf_batch_capture(dgf_batch *b, float *points, float *flow, uint8_t *status, void *stream);
 int dgf_batch_replay(dgf_batch *b, void *stream);
 
+/* Size, in floats, of the gradient buffer dgf_batch_backward writes: every pair's dI0 then dI1,
+ * each a dense width x height float map (row pitch = width), pairs in order.  offsets
+ * (nullable, npairs + 1 entries) receives the first float of each pair's dI0; its dI1 starts
+ * width * height floats later.  Returns -1 for a null plan. */
+int64_t dgf_batch_grad_size(const dgf_batch *b, int64_t *offsets);
+
+/* Gradient for a whole batch in one launch (the adjoint of dgf_track_backward, per pair, over
+ * every point of the plan): given the points, flow and status of a dgf_batch_run / replay and an
+ * upstream gradient dflow (float[num_points][2], same order), OVERWRITES grad
+ * (dgf_batch_grad_size floats, device) with dL/dI0 and dL/dI1 of every pair, taking the uint8
+ * frames' values as reals.  grad is cleared by a kernel first; contributions are added with
+ * device float atomics, so the last bits are not deterministic.  Points that are not CONVERGED,
+ * or have a singular J, contribute nothing. */
+int dgf_batch_backward(dgf_batch *b, const float *points, const float *flow, const uint8_t *status, const float *dflow,
+                       float *grad, void *stream);
+
 /* Frees the plan and its device memory (after the work using it has completed). */
 int dgf_batch_destroy(dgf_batch *b);
 

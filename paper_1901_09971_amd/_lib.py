@@ -68,6 +68,8 @@ SIGNATURES = {
     "dgf_batch_run": (ctypes.c_int, [P, P, P, P, P, P]),
     "dgf_batch_capture": (ctypes.c_int, [P, P, P, P, P]),
     "dgf_batch_replay": (ctypes.c_int, [P, P]),
+    "dgf_batch_grad_size": (I64, [P, P]),
+    "dgf_batch_backward": (ctypes.c_int, [P, P, P, P, P, P, P]),
     "dgf_batch_destroy": (ctypes.c_int, [P]),
     "dgf_get_tuning": (ctypes.c_int, [I32, I32, I32, I64, ctypes.POINTER(DgfTuning)]),
     "dgf_set_tuning": (ctypes.c_int, [I32, I32, ctypes.POINTER(DgfTuning)]),

@@ -272,6 +272,32 @@ class Batch:
         check(lib().dgf_batch_replay(self._h, _stream()), "dgf_batch_replay")
         return self.points, self.flow, self.status
 
+    def grad_layout(self):
+        """(total floats, per-pair offsets of dI0) of the buffer :meth:`backward` writes; pair i's
+        dI1 follows its dI0, each a dense height x width float map."""
+        off = (ctypes.c_int64 * (len(self._keep) + 1))()
+        total = int(lib().dgf_batch_grad_size(self._h, off))
+        return total, list(off)
+
+    def backward(self, dflow: torch.Tensor, grad: torch.Tensor | None = None):
+        """Gradient of the last run w.r.t. every pair's frames for the upstream gradient ``dflow``
+        (float32 [num_points, 2]) in one launch (dgf_batch_backward).  Returns the flat buffer
+        and a list of (dI0, dI1) views, one per pair."""
+        total, off = self.grad_layout()
+        if grad is None or grad.numel() < total or grad.dtype != torch.float32:
+            grad = torch.empty(max(total, 1), dtype=torch.float32, device=self.device)
+        dflow = dflow.contiguous().to(torch.float32)
+        if dflow.shape != (self.num_points, 2):
+            raise ValueError("dflow: expected float32 [num_points, 2]")
+        check(lib().dgf_batch_backward(self._h, _ptr(self.points), _ptr(self.flow), _ptr(self.status), _ptr(dflow),
+                                       _ptr(grad), _stream()), "dgf_batch_backward")
+        views = []
+        for i, (a, _) in enumerate(self._keep):
+            H, W = a.shape
+            o = off[i]
+            views.append((grad[o:o + H * W].view(H, W), grad[o + H * W:o + 2 * H * W].view(H, W)))
+        return grad, views
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             torch.cuda.synchronize(self.device)

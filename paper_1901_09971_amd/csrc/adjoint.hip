@@ -11,37 +11,24 @@
 // onto border pixels).  Only the level-0 images enter: the coarser levels decide which fixed
 // point is reached, not its local dependence on the pixels.
 //
-// One point per wavefront: lanes stride over the s x s support; pass 1 accumulates the four
-// entries of J (wave reduction), every lane solves the 2x2 system, pass 2 scatters its pixels'
-// contributions with hardware float atomics into the caller's dI0 / dI1 (accumulated, so one
-// buffer can collect several pairs or calls).  Atomic order is not deterministic; the sums are
-// equal up to FP32 rounding.
+// One point per wavefront (a one-wave workgroup): lanes stride over the s x s support; pass 1
+// accumulates the four entries of J (wave reduction), every lane solves the 2x2 system, pass 2
+// adds each pixel's 24 tap contributions into LDS patches laid out by unclamped position,
+// (s+3)^2 for dI0 and (s+1)^2 for dI1, and a final pass adds every patch cell into the gradient
+// map with one device float atomic at its clamped position -- about 1,100 global atomics per
+// point instead of 24 s^2.  Atomic order is not deterministic; sums agree up to FP32 rounding.
+// The batched form runs every point of a batch plan in one launch; a wavefront finds its pair by
+// binary search over the plan's point offsets.
 #include <cmath>
 
 #include "dgf_internal.hpp"
 
 namespace dgf {
 
-struct AdjParams {
-    const uint8_t *I0, *I1;
-    int64_t pitch0, pitch1; // bytes, also the row pitch of dI0 / dI1
-    int32_t W, H, s, r;
-    const float *pts, *flow, *dflow;
-    const uint8_t *status;
-    float *dI0, *dI1;
-    int64_t n;
-    float s1, s2, dpsi_mid; // thresholds and the middle-band slope -sigma1 / (sigma2 - sigma1)
-    int32_t mode;
-};
-
-__device__ __forceinline__ float f32_at(const uint8_t *base, int64_t pitch, int x, int y)
+template <typename PixT>
+__device__ __forceinline__ float px_at(const uint8_t *base, int64_t pitch, int x, int y)
 {
-    return reinterpret_cast<const float *>(base + (int64_t)y * pitch)[x];
-}
-
-__device__ __forceinline__ void add_at(float *base, int64_t pitch, int x, int y, float v)
-{
-    unsafeAtomicAdd(reinterpret_cast<float *>(reinterpret_cast<uint8_t *>(base) + (int64_t)y * pitch) + x, v);
+    return (float)reinterpret_cast<const PixT *>(base + (int64_t)y * pitch)[x];
 }
 
 // psi(r) and psi'(r) of the robust norm, band by band
@@ -60,16 +47,32 @@ __device__ __forceinline__ void psi_and_slope(const AdjParams &A, float r, float
     }
 }
 
+template <typename PixT>
 __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
 {
+    extern __shared__ float acc[]; // dI0 patch (s+3)^2, then dI1 patch (s+1)^2
     const int li = threadIdx.x;
     const int64_t i = blockIdx.x;
     if (i >= A.n) return; // whole wave: the grid is exactly n wide
     if (A.status[i] != DGF_ST_CONVERGED) return;
+    AdjPair Pr = A.one;
+    if (A.npairs) { // last pair whose first point is <= i (uniform across the wave)
+        int lo = 0, hi = A.npairs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (A.pt_off[mid] <= i)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        Pr = A.pairs[lo];
+    }
     const float2 p = reinterpret_cast<const float2 *>(A.pts)[i];
     const float2 u = reinterpret_cast<const float2 *>(A.flow)[i];
     const float2 lam = reinterpret_cast<const float2 *>(A.dflow)[i];
-    const int W = A.W, H = A.H, s = A.s, r = A.r, S2 = s * s;
+    const int W = Pr.W, H = Pr.H, s = A.s, r = A.r, S2 = s * s;
+    const uint8_t *I0 = Pr.I0, *I1 = Pr.I1;
+    const int64_t p0 = Pr.pitch0, p1 = Pr.pitch1;
 
     // integer bases and shared fractions of the template samples (p + k) and the I1 samples
     const float pbx = floorf(p.x), pby = floorf(p.y);
@@ -86,8 +89,8 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
     auto I0s = [&](int x, int y) { // bilinear of I0 with taps at integer (x, x+1) x (y, y+1), clamped
         const int x0 = clampi(x, 0, W - 1), x1 = clampi(x + 1, 0, W - 1);
         const int y0 = clampi(y, 0, H - 1), y1 = clampi(y + 1, 0, H - 1);
-        return a00 * f32_at(A.I0, A.pitch0, x0, y0) + a10 * f32_at(A.I0, A.pitch0, x1, y0) +
-               a01 * f32_at(A.I0, A.pitch0, x0, y1) + a11 * f32_at(A.I0, A.pitch0, x1, y1);
+        return a00 * px_at<PixT>(I0, p0, x0, y0) + a10 * px_at<PixT>(I0, p0, x1, y0) +
+               a01 * px_at<PixT>(I0, p0, x0, y1) + a11 * px_at<PixT>(I0, p0, x1, y1);
     };
 
     // pass 1: J = sum psi' g (grad J)^T
@@ -100,8 +103,8 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
         const float g1 = 0.5f * (I0s(x, y + 1) - I0s(x, y - 1));
         const int x0 = clampi(jbx + kx, 0, W - 1), x1 = clampi(jbx + kx + 1, 0, W - 1);
         const int y0 = clampi(jby + ky, 0, H - 1), y1 = clampi(jby + ky + 1, 0, H - 1);
-        const float i00 = f32_at(A.I1, A.pitch1, x0, y0), i10 = f32_at(A.I1, A.pitch1, x1, y0);
-        const float i01 = f32_at(A.I1, A.pitch1, x0, y1), i11 = f32_at(A.I1, A.pitch1, x1, y1);
+        const float i00 = px_at<PixT>(I1, p1, x0, y0), i10 = px_at<PixT>(I1, p1, x1, y0);
+        const float i01 = px_at<PixT>(I1, p1, x0, y1), i11 = px_at<PixT>(I1, p1, x1, y1);
         const float J = b00 * i00 + b10 * i10 + b01 * i01 + b11 * i11;
         const float djx = (1.f - fy1) * (i10 - i00) + fy1 * (i11 - i01);
         const float djy = (1.f - fx1) * (i01 - i00) + fx1 * (i11 - i10);
@@ -120,7 +123,11 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
     const float mux = (J11 * lam.x - J10 * lam.y) / det;
     const float muy = (J00 * lam.y - J01 * lam.x) / det;
 
-    // pass 2: scatter
+    // pass 2: scatter into the LDS patches (unclamped local positions)
+    const int w0 = s + 3, w1 = s + 1, n0 = w0 * w0, n1 = w1 * w1;
+    float *acc0 = acc, *acc1 = acc + n0;
+    for (int c = li; c < n0 + n1; c += 64) acc[c] = 0.f;
+    __syncthreads();
     for (int k = li; k < S2; k += 64) {
         const int ky = k / s, kx = k - ky * s;
         const int x = ibx + kx, y = iby + ky;
@@ -129,39 +136,78 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
         const float g1 = 0.5f * (I0s(x, y + 1) - I0s(x, y - 1));
         const int x0 = clampi(jbx + kx, 0, W - 1), x1 = clampi(jbx + kx + 1, 0, W - 1);
         const int y0 = clampi(jby + ky, 0, H - 1), y1 = clampi(jby + ky + 1, 0, H - 1);
-        const float J = b00 * f32_at(A.I1, A.pitch1, x0, y0) + b10 * f32_at(A.I1, A.pitch1, x1, y0) +
-                        b01 * f32_at(A.I1, A.pitch1, x0, y1) + b11 * f32_at(A.I1, A.pitch1, x1, y1);
+        const float J = b00 * px_at<PixT>(I1, p1, x0, y0) + b10 * px_at<PixT>(I1, p1, x1, y0) +
+                        b01 * px_at<PixT>(I1, p1, x0, y1) + b11 * px_at<PixT>(I1, p1, x1, y1);
         float ps, dps;
         psi_and_slope(A, J - T, ps, dps);
         const float c1 = dps * (mux * g0 + muy * g1);
-        // dI1: - psi' (mu . g) beta
-        add_at(A.dI1, A.pitch1, x0, y0, -c1 * b00);
-        add_at(A.dI1, A.pitch1, x1, y0, -c1 * b10);
-        add_at(A.dI1, A.pitch1, x0, y1, -c1 * b01);
-        add_at(A.dI1, A.pitch1, x1, y1, -c1 * b11);
+        // dI1: - psi' (mu . g) beta, at local (kx, ky) .. (kx + 1, ky + 1)
+        float *q1 = acc1 + ky * w1 + kx;
+        atomicAdd(q1, -c1 * b00);
+        atomicAdd(q1 + 1, -c1 * b10);
+        atomicAdd(q1 + w1, -c1 * b01);
+        atomicAdd(q1 + w1 + 1, -c1 * b11);
         // dI0 on the 4 x 4 neighbourhood of the template sample: +c1 alpha at the sample, and
-        // -psi mu_x / 2 (alpha^{+x} - alpha^{-x}) - psi mu_y / 2 (alpha^{+y} - alpha^{-y})
+        // -psi mu_x / 2 (alpha^{+x} - alpha^{-x}) - psi mu_y / 2 (alpha^{+y} - alpha^{-y});
+        // local origin (ibx - 1, iby - 1)
         const float cx = -0.5f * ps * mux, cy = -0.5f * ps * muy;
         const float wa[4] = {a00, a10, a01, a11};
         const int ox[4] = {0, 1, 0, 1}, oy[4] = {0, 0, 1, 1};
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const int xt = x + ox[t], yt = y + oy[t];
+            float *q0 = acc0 + (ky + oy[t] + 1) * w0 + (kx + ox[t] + 1);
             const float w = wa[t];
-            add_at(A.dI0, A.pitch0, clampi(xt, 0, W - 1), clampi(yt, 0, H - 1), c1 * w);
-            add_at(A.dI0, A.pitch0, clampi(xt + 1, 0, W - 1), clampi(yt, 0, H - 1), cx * w);
-            add_at(A.dI0, A.pitch0, clampi(xt - 1, 0, W - 1), clampi(yt, 0, H - 1), -cx * w);
-            add_at(A.dI0, A.pitch0, clampi(xt, 0, W - 1), clampi(yt + 1, 0, H - 1), cy * w);
-            add_at(A.dI0, A.pitch0, clampi(xt, 0, W - 1), clampi(yt - 1, 0, H - 1), -cy * w);
+            atomicAdd(q0, c1 * w);
+            atomicAdd(q0 + 1, cx * w);
+            atomicAdd(q0 - 1, -cx * w);
+            atomicAdd(q0 + w0, cy * w);
+            atomicAdd(q0 - w0, -cy * w);
         }
+    }
+    __syncthreads();
+    // flush: one device atomic per patch cell, at its clamped image position
+    float *dI0 = A.grad0 + Pr.g0, *dI1 = A.grad1 + Pr.g1;
+    for (int c = li; c < n0; c += 64) {
+        const float v = acc0[c];
+        if (v == 0.f) continue;
+        const int cy = c / w0, cx = c - cy * w0;
+        unsafeAtomicAdd(dI0 + (int64_t)clampi(iby - 1 + cy, 0, H - 1) * Pr.gpitch0 + clampi(ibx - 1 + cx, 0, W - 1), v);
+    }
+    for (int c = li; c < n1; c += 64) {
+        const float v = acc1[c];
+        if (v == 0.f) continue;
+        const int cy = c / w1, cx = c - cy * w1;
+        unsafeAtomicAdd(dI1 + (int64_t)clampi(jby + cy, 0, H - 1) * Pr.gpitch1 + clampi(jbx + cx, 0, W - 1), v);
     }
 }
 
-hipError_t launch_track_adjoint(const AdjParams &A, hipStream_t st)
+size_t adjoint_lds_bytes(int s) { return sizeof(float) * (size_t)((s + 3) * (s + 3) + (s + 1) * (s + 1)); }
+
+hipError_t launch_track_adjoint(const AdjParams &A, int dtype, hipStream_t st)
 {
     if (A.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_track_adjoint, dim3((unsigned)A.n), dim3(64), 0, st, A);
+    const size_t lds = adjoint_lds_bytes(A.s);
+    if (dtype == DGF_U8)
+        hipLaunchKernelGGL(k_track_adjoint<uint8_t>, dim3((unsigned)A.n), dim3(64), lds, st, A);
+    else
+        hipLaunchKernelGGL(k_track_adjoint<float>, dim3((unsigned)A.n), dim3(64), lds, st, A);
     return hipGetLastError();
+}
+
+void fill_adjoint_constants(AdjParams &A, const dgf_track_opts &o)
+{
+    A.s1 = o.sigma1;
+    A.s2 = o.sigma2;
+    if (std::isinf(o.sigma1)) {
+        A.mode = ROBUST_L2;
+        A.dpsi_mid = 0.f;
+    } else if (o.sigma2 > o.sigma1) {
+        A.mode = ROBUST_HAMPEL;
+        A.dpsi_mid = -o.sigma1 / (o.sigma2 - o.sigma1);
+    } else {
+        A.mode = ROBUST_HARD;
+        A.dpsi_mid = 0.f;
+    }
 }
 
 } // namespace dgf
@@ -193,32 +239,17 @@ extern "C" int dgf_track_backward(const dgf_image *I0, const dgf_image *I1, cons
     if (std::isinf(o.sigma2) && !std::isinf(o.sigma1)) return DGF_ERR_INVALID_ARG;
     if (n == 0) return DGF_OK;
     AdjParams A{};
-    A.I0 = (const uint8_t *)I0->data;
-    A.I1 = (const uint8_t *)I1->data;
-    A.pitch0 = I0->pitch_bytes;
-    A.pitch1 = I1->pitch_bytes;
-    A.W = I0->width;
-    A.H = I0->height;
+    A.one = AdjPair{(const uint8_t *)I0->data, (const uint8_t *)I1->data, I0->pitch_bytes, I1->pitch_bytes, 0, 0,
+                    I0->pitch_bytes / 4, I1->pitch_bytes / 4, I0->width, I0->height};
+    A.grad0 = dI0;
+    A.grad1 = dI1;
     A.s = support;
     A.r = support / 2;
     A.pts = points;
     A.flow = flow;
     A.dflow = dflow;
     A.status = status;
-    A.dI0 = dI0;
-    A.dI1 = dI1;
     A.n = n;
-    A.s1 = o.sigma1;
-    A.s2 = o.sigma2;
-    if (std::isinf(o.sigma1)) {
-        A.mode = ROBUST_L2;
-        A.dpsi_mid = 0.f;
-    } else if (o.sigma2 > o.sigma1) {
-        A.mode = ROBUST_HAMPEL;
-        A.dpsi_mid = -o.sigma1 / (o.sigma2 - o.sigma1);
-    } else {
-        A.mode = ROBUST_HARD;
-        A.dpsi_mid = 0.f;
-    }
-    return launch_track_adjoint(A, (hipStream_t)stream) == hipSuccess ? DGF_OK : DGF_ERR_HIP;
+    fill_adjoint_constants(A, o);
+    return launch_track_adjoint(A, DGF_F32, (hipStream_t)stream) == hipSuccess ? DGF_OK : DGF_ERR_HIP;
 }

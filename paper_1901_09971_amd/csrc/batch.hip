@@ -28,6 +28,12 @@ __global__ void k_clear_counters(uint32_t *c)
     if (threadIdx.x < kNumXcd) c[(size_t)threadIdx.x * kCounterStride] = 0u;
 }
 
+// Grid-stride clear of a float buffer (a kernel, not a memset, so a captured graph can hold it).
+__global__ void k_zero_f32(float *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0.f;
+}
+
 } // namespace dgf
 
 using namespace dgf;
@@ -42,6 +48,8 @@ struct dgf_batch {
     LevelPair *d_lv = nullptr;
     int64_t *d_item_off = nullptr, *d_pt_off = nullptr;
     uint32_t *d_counter = nullptr;
+    AdjPair *d_adj = nullptr; // per-pair frames and gradient-map offsets for the adjoint
+    std::vector<int64_t> grad_off; // first float of each pair's dI0 (dI1 follows), P + 1 entries
     PyrJob *d_pyr = nullptr; // [(L-1)][2P]
     DetectJob *d_det = nullptr;
     std::vector<int> pyr_w2, pyr_h2; // per level 1..L-1: largest output size over the frames
@@ -206,6 +214,8 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
     sz = align_up(sz + (int64_t)sizeof(PyrJob) * 2 * npairs * std::max(levels - 1, 1), 256);
     const int64_t o_det = sz;
     sz = align_up(sz + (int64_t)sizeof(DetectJob) * npairs, 256);
+    const int64_t o_adj = sz;
+    sz = align_up(sz + (int64_t)sizeof(AdjPair) * npairs, 256);
     for (int i = 0; i < npairs; ++i) {
         pyr_bytes[i] = (int64_t)dgf_pyramid_layout(pairs[i].I0.width, pairs[i].I0.height, levels, dtype, nullptr, nullptr);
         pyr_base[i] = sz;
@@ -223,6 +233,7 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
     b->d_counter = (uint32_t *)(base + o_ctr);
     b->d_pyr = (PyrJob *)(base + o_pyrjobs);
     b->d_det = (DetectJob *)(base + o_det);
+    b->d_adj = (AdjPair *)(base + o_adj);
 
     // level table and pyramid jobs
     std::vector<LevelPair> lv((size_t)npairs * levels);
@@ -247,7 +258,19 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
             L[l] = LevelPair{w0 + off[l], w1 + off[l], pitch[l], pitch[l], W, H};
         }
     }
+    // adjoint table: level-0 frames, and each pair's two gradient maps (row pitch = width)
+    std::vector<AdjPair> adj(npairs);
+    b->grad_off.assign(npairs + 1, 0);
+    for (int i = 0; i < npairs; ++i) {
+        const dgf_pair_desc &d = pairs[i];
+        const int64_t wh = (int64_t)d.I0.width * d.I0.height;
+        const int64_t g0 = b->grad_off[i];
+        adj[i] = AdjPair{(const uint8_t *)d.I0.data, (const uint8_t *)d.I1.data, d.I0.pitch_bytes, d.I1.pitch_bytes,
+                         g0, g0 + wh, d.I0.width, d.I0.width, d.I0.width, d.I0.height};
+        b->grad_off[i + 1] = g0 + 2 * wh;
+    }
     bool ok = hipMemcpy(b->d_lv, lv.data(), sizeof(LevelPair) * lv.size(), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(b->d_adj, adj.data(), sizeof(AdjPair) * adj.size(), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->d_item_off, b->item_off.data(), 8 * (npairs + 1), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->d_pt_off, b->pt_off.data(), 8 * (npairs + 1), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->d_pyr, jobs.data(), sizeof(PyrJob) * jobs.size(), hipMemcpyHostToDevice) == hipSuccess;
@@ -316,6 +339,42 @@ int dgf_batch_replay(dgf_batch *b, void *stream)
     if (b->total_pts == 0) return DGF_OK;
     if (!b->exec) return DGF_ERR_INVALID_ARG;
     return hipGraphLaunch(b->exec, (hipStream_t)stream) == hipSuccess ? DGF_OK : DGF_ERR_HIP;
+}
+
+int64_t dgf_batch_grad_size(const dgf_batch *b, int64_t *offsets)
+{
+    if (!b) return -1;
+    if (offsets) memcpy(offsets, b->grad_off.data(), sizeof(int64_t) * (b->P + 1));
+    return b->grad_off[b->P];
+}
+
+int dgf_batch_backward(dgf_batch *b, const float *points, const float *flow, const uint8_t *status, const float *dflow,
+                       float *grad, void *stream)
+{
+    if (!b) return DGF_ERR_INVALID_ARG;
+    if (b->total_pts > 0 && (!points || !flow || !status || !dflow || !grad)) return DGF_ERR_INVALID_ARG;
+    if (grad && (uintptr_t)grad % 4 != 0) return DGF_ERR_INVALID_ARG;
+    if (b->total_pts == 0) return DGF_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t ng = b->grad_off[b->P];
+    const int64_t blocks = std::min<int64_t>((ng + 1023) / 1024, 8192);
+    hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)blocks), dim3(256), 0, st, grad, ng);
+    if (hipGetLastError() != hipSuccess) return DGF_ERR_HIP;
+    AdjParams A{};
+    A.pairs = b->d_adj;
+    A.pt_off = b->d_pt_off;
+    A.npairs = b->P;
+    A.grad0 = grad;
+    A.grad1 = grad;
+    A.s = b->s;
+    A.r = b->s / 2;
+    A.pts = points;
+    A.flow = flow;
+    A.dflow = dflow;
+    A.status = status;
+    A.n = b->total_pts;
+    fill_adjoint_constants(A, b->opts);
+    return launch_track_adjoint(A, b->dtype, st) == hipSuccess ? DGF_OK : DGF_ERR_HIP;
 }
 
 int dgf_batch_destroy(dgf_batch *b)

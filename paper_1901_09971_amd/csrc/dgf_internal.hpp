@@ -318,6 +318,33 @@ __device__ __forceinline__ float hampel_weight(float r, float cs2, float cmid)
     return __builtin_amdgcn_fmed3f(fmaf(cs2, __builtin_amdgcn_rcpf(fabsf(r)), -cmid), 0.f, 1.f);
 }
 
+// Level-0 frames of one pair and where its gradient maps live: dI0 = grad0 + g0 and
+// dI1 = grad1 + g1 (the kernel's base pointers), row pitch gpitch floats.
+struct AdjPair {
+    const uint8_t *I0, *I1;
+    int64_t pitch0, pitch1; // bytes
+    int64_t g0, g1;         // float offsets of the two gradient maps
+    int64_t gpitch0, gpitch1;
+    int32_t W, H;
+};
+
+struct AdjParams {
+    AdjPair one;           // single-pair form (npairs == 0)
+    const AdjPair *pairs;  // batched form: per-pair table (device)
+    const int64_t *pt_off; // batched form: first point of each pair, npairs + 1 entries (device)
+    int32_t npairs;
+    float *grad0, *grad1;  // gradient base pointers
+    int32_t s, r;
+    const float *pts, *flow, *dflow;
+    const uint8_t *status;
+    int64_t n;
+    float s1, s2, dpsi_mid; // thresholds and the middle-band slope -sigma1 / (sigma2 - sigma1)
+    int32_t mode;
+};
+
+hipError_t launch_track_adjoint(const AdjParams &A, int dtype, hipStream_t st);
+void fill_adjoint_constants(AdjParams &A, const dgf_track_opts &o);
+
 struct TrackTuning {
     int lpp;     // lanes per point: 16, 32 or 64
     int wpb;     // waves per workgroup: 1, 2, 4
