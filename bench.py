@@ -147,6 +147,79 @@ def batched_vs_plain(reps: int):
             "workload": "batch64_mixed: 16 each of 1242x375, 1224x370, 640x480, 320x240, strides {3,5,8}"}
 
 
+DENSITY = dict(name="density_2048x1024x4", W=2048, H=1024, pairs=4, window=9, stride=2, levels=6, support=21,
+               iters=20)
+
+
+def density_stress(reps: int):
+    """Density stress: four 2048x1024 uint8 pairs (layered affine motion up to 250 px, seeds 0-3),
+    DeGraF window 9 stride 2 (518,160 points each), 6 levels, 21x21 support, 20 iterations.
+    Forward: one replay of the captured batched plan (detect, pyramids, track of all four pairs).
+    Adjoint: one batched backward launch for the loss sum over converged points of |u - u_gt|^2
+    (the upstream gradient is formed outside the timed region)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+    import torch
+
+    import paper_1901_09971_amd as dgf
+    from paper_1901_09971_amd import synth
+
+    c = DENSITY
+    with ThreadPoolExecutor(c["pairs"]) as ex:
+        data = list(ex.map(synth.density_2048x1024, range(c["pairs"])))
+    dev = torch.device("cuda", 0)
+    pairs = [(torch.from_numpy(I0).to(dev), torch.from_numpy(I1).to(dev), c["window"], c["stride"])
+             for I0, I1, _, _ in data]
+    plan = dgf.Batch(pairs, c["levels"], c["support"], c["iters"])
+    n = plan.num_points
+    its = torch.empty(n, dtype=torch.int32, device=dev)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        P, F, S = plan.run(its)
+        plan.capture()
+    torch.cuda.synchronize()
+    pix_iters = int(its.to(torch.int64).sum().item()) * c["support"] ** 2
+    st_counts = np.bincount(S.cpu().numpy(), minlength=4).tolist()
+
+    # upstream gradient of sum over converged points of |u - u_gt|^2 (gt of the nearest pixel)
+    pts = P.cpu().numpy()
+    gt_pts = np.zeros((n, 2), np.float32)
+    for i, (_, _, gt, _) in enumerate(data):
+        lo, hi = plan.offsets[i], plan.offsets[i + 1]
+        xi = np.clip(np.rint(pts[lo:hi, 0]).astype(np.int64), 0, c["W"] - 1)
+        yi = np.clip(np.rint(pts[lo:hi, 1]).astype(np.int64), 0, c["H"] - 1)
+        gt_pts[lo:hi] = gt[yi, xi]
+    conv = S == 0
+    dflow = torch.zeros_like(F)
+    dflow[conv] = 2.0 * (F[conv] - torch.from_numpy(gt_pts).to(dev)[conv])
+    total, _ = plan.grad_layout()
+    grad = torch.empty(total, dtype=torch.float32, device=dev)
+
+    def timed(fn):
+        with torch.cuda.stream(side):
+            fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_fwd = timed(plan.replay)
+    t_bwd = timed(lambda: plan.backward(dflow, grad))
+    plan.close()
+    n_conv = int(conv.sum().item())
+    return {"workload": c["name"], "pairs": c["pairs"], "points": n, "levels": c["levels"],
+            "support": c["support"], "max_iters": c["iters"], "reps": reps, "status_counts": st_counts,
+            "forward_ms": t_fwd, "forward_points_per_s": n / (t_fwd * 1e-3),
+            "forward_track_tflops_lower_bound": pix_iters * FLOPS_PER_PIXEL_ITER / (t_fwd * 1e-3) / 1e12,
+            "adjoint_ms": t_bwd, "adjoint_converged_points": n_conv,
+            "adjoint_points_per_s": n_conv / (t_bwd * 1e-3)}
+
+
 def copy_calibration(mib: int):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -169,6 +242,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-pair batched vs plain measurement")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in launch-shape heuristic")
     ap.add_argument("--batch-reps", type=int, default=10)
+    ap.add_argument("--no-density", action="store_true", help="skip the 4 x 2048x1024 density stress")
+    ap.add_argument("--density-reps", type=int, default=3)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -296,6 +371,8 @@ def main():
     }
     if not args.no_batch:
         out["batched"] = batched_vs_plain(args.batch_reps)
+    if not args.no_density:
+        out["density"] = density_stress(args.density_reps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(I0n, I1n, N, args.cpu_budget_s)
     print(json.dumps(out))
