@@ -11,9 +11,11 @@
 // onto border pixels).  Only the level-0 images enter: the coarser levels decide which fixed
 // point is reached, not its local dependence on the pixels.
 //
-// One point per wavefront (a one-wave workgroup): lanes stride over the s x s support; pass 1
-// accumulates the four entries of J (wave reduction), every lane solves the 2x2 system, pass 2
-// adds each pixel's 24 tap contributions into LDS patches laid out by unclamped position,
+// One point per wavefront (a one-wave workgroup): the raw I0 patch (s+3)^2 around the template
+// and the raw I1 patch (s+1)^2 under the tracked position are staged in LDS; lanes stride over
+// the s x s support; pass 1 accumulates the four entries of J (wave reduction), every lane solves
+// the 2x2 system, pass 2 adds each pixel's 24 tap contributions into LDS patches laid out by
+// unclamped position,
 // (s+3)^2 for dI0 and (s+1)^2 for dI1, and a final pass adds every patch cell into the gradient
 // map with one device float atomic at its clamped position -- about 1,100 global atomics per
 // point instead of 24 s^2.  Atomic order is not deterministic; sums agree up to FP32 rounding.
@@ -24,12 +26,6 @@
 #include "dgf_internal.hpp"
 
 namespace dgf {
-
-template <typename PixT>
-__device__ __forceinline__ float px_at(const uint8_t *base, int64_t pitch, int x, int y)
-{
-    return (float)reinterpret_cast<const PixT *>(base + (int64_t)y * pitch)[x];
-}
 
 // psi(r) and psi'(r) of the robust norm, band by band
 __device__ __forceinline__ void psi_and_slope(const AdjParams &A, float r, float &ps, float &dps)
@@ -50,7 +46,7 @@ __device__ __forceinline__ void psi_and_slope(const AdjParams &A, float r, float
 template <typename PixT>
 __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
 {
-    extern __shared__ float acc[]; // dI0 patch (s+3)^2, then dI1 patch (s+1)^2
+    extern __shared__ float smem[];
     const int li = threadIdx.x;
     const int64_t i = blockIdx.x;
     if (i >= A.n) return; // whole wave: the grid is exactly n wide
@@ -86,25 +82,32 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
     const float a00 = (1.f - fx0) * (1.f - fy0), a10 = fx0 * (1.f - fy0), a01 = (1.f - fx0) * fy0, a11 = fx0 * fy0;
     const float b00 = (1.f - fx1) * (1.f - fy1), b10 = fx1 * (1.f - fy1), b01 = (1.f - fx1) * fy1, b11 = fx1 * fy1;
 
-    auto I0s = [&](int x, int y) { // bilinear of I0 with taps at integer (x, x+1) x (y, y+1), clamped
-        const int x0 = clampi(x, 0, W - 1), x1 = clampi(x + 1, 0, W - 1);
-        const int y0 = clampi(y, 0, H - 1), y1 = clampi(y + 1, 0, H - 1);
-        return a00 * px_at<PixT>(I0, p0, x0, y0) + a10 * px_at<PixT>(I0, p0, x1, y0) +
-               a01 * px_at<PixT>(I0, p0, x0, y1) + a11 * px_at<PixT>(I0, p0, x1, y1);
+    // LDS: raw I0 patch (s+3)^2 at (ibx - 1, iby - 1), raw I1 patch (s+1)^2 at (jbx, jby), then the
+    // two accumulation patches of the same shapes
+    const int w0 = s + 3, w1 = s + 1, n0 = w0 * w0, n1 = w1 * w1;
+    float *raw0 = smem, *raw1 = smem + n0, *acc0 = raw1 + n1, *acc1 = acc0 + n0;
+    stage_rect<64, PixT>(raw0, w0, I0, p0, W, H, ibx - 1, iby - 1, w0, w0, stage_lanes<64>(w0, li));
+    stage_rect<64, PixT>(raw1, w1, I1, p1, W, H, jbx, jby, w1, w1, stage_lanes<64>(w1, li));
+    for (int c = li; c < n0 + n1; c += 64) acc0[c] = 0.f;
+    __syncthreads();
+
+    // template value and central differences of the bilinear interpolant, from the raw I0 patch;
+    // (kx, ky) is the support offset, local tap origin (kx + 1, ky + 1)
+    auto I0s = [&](int lx, int ly) {
+        const float *q = raw0 + ly * w0 + lx;
+        return a00 * q[0] + a10 * q[1] + a01 * q[w0] + a11 * q[w0 + 1];
     };
 
     // pass 1: J = sum psi' g (grad J)^T
     float J00 = 0.f, J01 = 0.f, J10 = 0.f, J11 = 0.f;
     for (int k = li; k < S2; k += 64) {
         const int ky = k / s, kx = k - ky * s;
-        const int x = ibx + kx, y = iby + ky;
-        const float T = I0s(x, y);
-        const float g0 = 0.5f * (I0s(x + 1, y) - I0s(x - 1, y));
-        const float g1 = 0.5f * (I0s(x, y + 1) - I0s(x, y - 1));
-        const int x0 = clampi(jbx + kx, 0, W - 1), x1 = clampi(jbx + kx + 1, 0, W - 1);
-        const int y0 = clampi(jby + ky, 0, H - 1), y1 = clampi(jby + ky + 1, 0, H - 1);
-        const float i00 = px_at<PixT>(I1, p1, x0, y0), i10 = px_at<PixT>(I1, p1, x1, y0);
-        const float i01 = px_at<PixT>(I1, p1, x0, y1), i11 = px_at<PixT>(I1, p1, x1, y1);
+        const int lx = kx + 1, ly = ky + 1;
+        const float T = I0s(lx, ly);
+        const float g0 = 0.5f * (I0s(lx + 1, ly) - I0s(lx - 1, ly));
+        const float g1 = 0.5f * (I0s(lx, ly + 1) - I0s(lx, ly - 1));
+        const float *q = raw1 + ky * w1 + kx;
+        const float i00 = q[0], i10 = q[1], i01 = q[w1], i11 = q[w1 + 1];
         const float J = b00 * i00 + b10 * i10 + b01 * i01 + b11 * i11;
         const float djx = (1.f - fy1) * (i10 - i00) + fy1 * (i11 - i01);
         const float djy = (1.f - fx1) * (i01 - i00) + fx1 * (i11 - i10);
@@ -123,21 +126,15 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
     const float mux = (J11 * lam.x - J10 * lam.y) / det;
     const float muy = (J00 * lam.y - J01 * lam.x) / det;
 
-    // pass 2: scatter into the LDS patches (unclamped local positions)
-    const int w0 = s + 3, w1 = s + 1, n0 = w0 * w0, n1 = w1 * w1;
-    float *acc0 = acc, *acc1 = acc + n0;
-    for (int c = li; c < n0 + n1; c += 64) acc[c] = 0.f;
-    __syncthreads();
+    // pass 2: scatter into the LDS accumulation patches (unclamped local positions)
     for (int k = li; k < S2; k += 64) {
         const int ky = k / s, kx = k - ky * s;
-        const int x = ibx + kx, y = iby + ky;
-        const float T = I0s(x, y);
-        const float g0 = 0.5f * (I0s(x + 1, y) - I0s(x - 1, y));
-        const float g1 = 0.5f * (I0s(x, y + 1) - I0s(x, y - 1));
-        const int x0 = clampi(jbx + kx, 0, W - 1), x1 = clampi(jbx + kx + 1, 0, W - 1);
-        const int y0 = clampi(jby + ky, 0, H - 1), y1 = clampi(jby + ky + 1, 0, H - 1);
-        const float J = b00 * px_at<PixT>(I1, p1, x0, y0) + b10 * px_at<PixT>(I1, p1, x1, y0) +
-                        b01 * px_at<PixT>(I1, p1, x0, y1) + b11 * px_at<PixT>(I1, p1, x1, y1);
+        const int lx = kx + 1, ly = ky + 1;
+        const float T = I0s(lx, ly);
+        const float g0 = 0.5f * (I0s(lx + 1, ly) - I0s(lx - 1, ly));
+        const float g1 = 0.5f * (I0s(lx, ly + 1) - I0s(lx, ly - 1));
+        const float *q = raw1 + ky * w1 + kx;
+        const float J = b00 * q[0] + b10 * q[1] + b01 * q[w1] + b11 * q[w1 + 1];
         float ps, dps;
         psi_and_slope(A, J - T, ps, dps);
         const float c1 = dps * (mux * g0 + muy * g1);
@@ -148,14 +145,13 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
         atomicAdd(q1 + w1, -c1 * b01);
         atomicAdd(q1 + w1 + 1, -c1 * b11);
         // dI0 on the 4 x 4 neighbourhood of the template sample: +c1 alpha at the sample, and
-        // -psi mu_x / 2 (alpha^{+x} - alpha^{-x}) - psi mu_y / 2 (alpha^{+y} - alpha^{-y});
-        // local origin (ibx - 1, iby - 1)
+        // -psi mu_x / 2 (alpha^{+x} - alpha^{-x}) - psi mu_y / 2 (alpha^{+y} - alpha^{-y})
         const float cx = -0.5f * ps * mux, cy = -0.5f * ps * muy;
         const float wa[4] = {a00, a10, a01, a11};
         const int ox[4] = {0, 1, 0, 1}, oy[4] = {0, 0, 1, 1};
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            float *q0 = acc0 + (ky + oy[t] + 1) * w0 + (kx + ox[t] + 1);
+            float *q0 = acc0 + (ly + oy[t]) * w0 + (lx + ox[t]);
             const float w = wa[t];
             atomicAdd(q0, c1 * w);
             atomicAdd(q0 + 1, cx * w);
@@ -181,7 +177,7 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
     }
 }
 
-size_t adjoint_lds_bytes(int s) { return sizeof(float) * (size_t)((s + 3) * (s + 3) + (s + 1) * (s + 1)); }
+size_t adjoint_lds_bytes(int s) { return 2 * sizeof(float) * (size_t)((s + 3) * (s + 3) + (s + 1) * (s + 1)); }
 
 hipError_t launch_track_adjoint(const AdjParams &A, int dtype, hipStream_t st)
 {
