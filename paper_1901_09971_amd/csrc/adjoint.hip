@@ -11,16 +11,19 @@
 // onto border pixels).  Only the level-0 images enter: the coarser levels decide which fixed
 // point is reached, not its local dependence on the pixels.
 //
-// One point per wavefront (a one-wave workgroup): the raw I0 patch (s+3)^2 around the template
-// and the raw I1 patch (s+1)^2 under the tracked position are staged in LDS; lanes stride over
-// the s x s support; pass 1 accumulates the four entries of J (wave reduction), every lane solves
-// the 2x2 system, pass 2 adds each pixel's 24 tap contributions into LDS patches laid out by
-// unclamped position,
-// (s+3)^2 for dI0 and (s+1)^2 for dI1, and a final pass adds every patch cell into the gradient
-// map with one device float atomic at its clamped position -- about 1,100 global atomics per
-// point instead of 24 s^2.  Atomic order is not deterministic; sums agree up to FP32 rounding.
-// The batched form runs every point of a batch plan in one launch; a wavefront finds its pair by
-// binary search over the plan's point offsets.
+// One point per wavefront (a one-wave workgroup).  The raw I0 patch (s+3)^2 around the template
+// and the raw I1 patch (s+1)^2 under the tracked position are staged in LDS; lanes stride over the
+// s x s support.  Pass 1 accumulates the four entries of J (wave reduction) and every lane solves
+// the 2x2 system.  Pass 2 stores, per support pixel k, c1_k = psi'(r_k) (mu . g_k) and
+// cx_k, cy_k = -psi(r_k) mu_x / 2, -psi(r_k) mu_y / 2.  The image gradients are then gathered
+// rather than scattered (LDS float atomics serialise): with F(a) = c1(a) + cx(a - e_x) -
+// cx(a + e_x) + cy(a - e_y) - cy(a + e_y) on the support grid,
+//     dI0 cell X = sum over the 4 bilinear taps t of alpha_t F(X - (1, 1) - t),
+//     dI1 cell X = - sum over the 4 taps t of beta_t c1(X - t),
+// and every cell goes to the gradient map with one device float atomic at its clamped image
+// position (neighbouring points overlap, so the device atomics stay).  Atomic order is not
+// deterministic; sums agree up to FP32 rounding.  The batched form runs every point of a batch
+// plan in one launch; a wavefront finds its pair by binary search over the plan's point offsets.
 #include <cmath>
 
 #include "dgf_internal.hpp"
@@ -43,6 +46,19 @@ __device__ __forceinline__ void psi_and_slope(const AdjParams &A, float r, float
     }
 }
 
+__device__ __forceinline__ int adj_pair_of(const AdjParams &A, int64_t i)
+{
+    int lo = 0, hi = A.npairs - 1; // last pair whose first point is <= i
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (A.pt_off[mid] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 template <typename PixT>
 __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
 {
@@ -51,24 +67,11 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
     const int64_t i = blockIdx.x;
     if (i >= A.n) return; // whole wave: the grid is exactly n wide
     if (A.status[i] != DGF_ST_CONVERGED) return;
-    AdjPair Pr = A.one;
-    if (A.npairs) { // last pair whose first point is <= i (uniform across the wave)
-        int lo = 0, hi = A.npairs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (A.pt_off[mid] <= i)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        Pr = A.pairs[lo];
-    }
+    const AdjPair Pr = A.npairs ? A.pairs[adj_pair_of(A, i)] : A.one;
     const float2 p = reinterpret_cast<const float2 *>(A.pts)[i];
     const float2 u = reinterpret_cast<const float2 *>(A.flow)[i];
     const float2 lam = reinterpret_cast<const float2 *>(A.dflow)[i];
     const int W = Pr.W, H = Pr.H, s = A.s, r = A.r, S2 = s * s;
-    const uint8_t *I0 = Pr.I0, *I1 = Pr.I1;
-    const int64_t p0 = Pr.pitch0, p1 = Pr.pitch1;
 
     // integer bases and shared fractions of the template samples (p + k) and the I1 samples
     const float pbx = floorf(p.x), pby = floorf(p.y);
@@ -76,23 +79,21 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
     const float tx = fx0 + u.x, ty = fy0 + u.y;
     const float qbx = floorf(tx), qby = floorf(ty);
     const float fx1 = tx - qbx, fy1 = ty - qby;
-    const int ibx = (int)pbx - r, iby = (int)pby - r;
-    const int jbx = (int)pbx + (int)fminf(fmaxf(qbx, -1048576.f), 1048576.f) - r;
-    const int jby = (int)pby + (int)fminf(fmaxf(qby, -1048576.f), 1048576.f) - r;
+    const int ox0 = (int)pbx - r - 1, oy0 = (int)pby - r - 1; // dI0 patch origin, (s+3)^2
+    const int ox1 = (int)pbx + (int)fminf(fmaxf(qbx, -1048576.f), 1048576.f) - r;
+    const int oy1 = (int)pby + (int)fminf(fmaxf(qby, -1048576.f), 1048576.f) - r; // dI1 patch, (s+1)^2
     const float a00 = (1.f - fx0) * (1.f - fy0), a10 = fx0 * (1.f - fy0), a01 = (1.f - fx0) * fy0, a11 = fx0 * fy0;
     const float b00 = (1.f - fx1) * (1.f - fy1), b10 = fx1 * (1.f - fy1), b01 = (1.f - fx1) * fy1, b11 = fx1 * fy1;
 
-    // LDS: raw I0 patch (s+3)^2 at (ibx - 1, iby - 1), raw I1 patch (s+1)^2 at (jbx, jby), then the
-    // two accumulation patches of the same shapes
+    // LDS: raw I0 patch (later F on the (s+2)^2 grid), raw I1 patch, then c1, cx, cy on the support
     const int w0 = s + 3, w1 = s + 1, n0 = w0 * w0, n1 = w1 * w1;
-    float *raw0 = smem, *raw1 = smem + n0, *acc0 = raw1 + n1, *acc1 = acc0 + n0;
-    stage_rect<64, PixT>(raw0, w0, I0, p0, W, H, ibx - 1, iby - 1, w0, w0, stage_lanes<64>(w0, li));
-    stage_rect<64, PixT>(raw1, w1, I1, p1, W, H, jbx, jby, w1, w1, stage_lanes<64>(w1, li));
-    for (int c = li; c < n0 + n1; c += 64) acc0[c] = 0.f;
+    float *raw0 = smem, *raw1 = smem + n0, *C1 = raw1 + n1, *CX = C1 + S2, *CY = CX + S2;
+    stage_rect<64, PixT>(raw0, w0, Pr.I0, Pr.pitch0, W, H, ox0, oy0, w0, w0, stage_lanes<64>(w0, li));
+    stage_rect<64, PixT>(raw1, w1, Pr.I1, Pr.pitch1, W, H, ox1, oy1, w1, w1, stage_lanes<64>(w1, li));
     __syncthreads();
 
     // template value and central differences of the bilinear interpolant, from the raw I0 patch;
-    // (kx, ky) is the support offset, local tap origin (kx + 1, ky + 1)
+    // support offset (kx, ky) sits at local (kx + 1, ky + 1)
     auto I0s = [&](int lx, int ly) {
         const float *q = raw0 + ly * w0 + lx;
         return a00 * q[0] + a10 * q[1] + a01 * q[w0] + a11 * q[w0 + 1];
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
     const float mux = (J11 * lam.x - J10 * lam.y) / det;
     const float muy = (J00 * lam.y - J01 * lam.x) / det;
 
-    // pass 2: scatter into the LDS accumulation patches (unclamped local positions)
+    // pass 2: per support pixel, c1 = psi' (mu . g) and cx, cy = -psi mu / 2
     for (int k = li; k < S2; k += 64) {
         const int ky = k / s, kx = k - ky * s;
         const int lx = kx + 1, ly = ky + 1;
@@ -137,47 +138,46 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
         const float J = b00 * q[0] + b10 * q[1] + b01 * q[w1] + b11 * q[w1 + 1];
         float ps, dps;
         psi_and_slope(A, J - T, ps, dps);
-        const float c1 = dps * (mux * g0 + muy * g1);
-        // dI1: - psi' (mu . g) beta, at local (kx, ky) .. (kx + 1, ky + 1)
-        float *q1 = acc1 + ky * w1 + kx;
-        atomicAdd(q1, -c1 * b00);
-        atomicAdd(q1 + 1, -c1 * b10);
-        atomicAdd(q1 + w1, -c1 * b01);
-        atomicAdd(q1 + w1 + 1, -c1 * b11);
-        // dI0 on the 4 x 4 neighbourhood of the template sample: +c1 alpha at the sample, and
-        // -psi mu_x / 2 (alpha^{+x} - alpha^{-x}) - psi mu_y / 2 (alpha^{+y} - alpha^{-y})
-        const float cx = -0.5f * ps * mux, cy = -0.5f * ps * muy;
-        const float wa[4] = {a00, a10, a01, a11};
-        const int ox[4] = {0, 1, 0, 1}, oy[4] = {0, 0, 1, 1};
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            float *q0 = acc0 + (ly + oy[t]) * w0 + (lx + ox[t]);
-            const float w = wa[t];
-            atomicAdd(q0, c1 * w);
-            atomicAdd(q0 + 1, cx * w);
-            atomicAdd(q0 - 1, -cx * w);
-            atomicAdd(q0 + w0, cy * w);
-            atomicAdd(q0 - w0, -cy * w);
-        }
+        C1[k] = dps * (mux * g0 + muy * g1);
+        CX[k] = -0.5f * ps * mux;
+        CY[k] = -0.5f * ps * muy;
     }
     __syncthreads();
-    // flush: one device atomic per patch cell, at its clamped image position
-    float *dI0 = A.grad0 + Pr.g0, *dI1 = A.grad1 + Pr.g1;
-    for (int c = li; c < n0; c += 64) {
-        const float v = acc0[c];
-        if (v == 0.f) continue;
-        const int cy = c / w0, cx = c - cy * w0;
-        unsafeAtomicAdd(dI0 + (int64_t)clampi(iby - 1 + cy, 0, H - 1) * Pr.gpitch0 + clampi(ibx - 1 + cx, 0, W - 1), v);
+    auto at = [&](const float *f, int a, int b) { // field value at support (a, b), zero outside
+        return (a >= 0 && a < s && b >= 0 && b < s) ? f[b * s + a] : 0.f;
+    };
+    // F on the support grid extended by one ring, a, b in [-1, s], stored at (a + 1, b + 1) with
+    // pitch s + 2 over the raw I0 patch (no longer read)
+    const int wf = s + 2;
+    float *F = raw0;
+    for (int c = li; c < wf * wf; c += 64) {
+        const int b = c / wf - 1, a = c - (b + 1) * wf - 1;
+        F[c] = at(C1, a, b) + at(CX, a - 1, b) - at(CX, a + 1, b) + at(CY, a, b - 1) - at(CY, a, b + 1);
     }
+    // dI1 cells: - sum of the 4 taps of c1
+    float *dI1 = A.grad1 + Pr.g1;
     for (int c = li; c < n1; c += 64) {
-        const float v = acc1[c];
-        if (v == 0.f) continue;
-        const int cy = c / w1, cx = c - cy * w1;
-        unsafeAtomicAdd(dI1 + (int64_t)clampi(jby + cy, 0, H - 1) * Pr.gpitch1 + clampi(jbx + cx, 0, W - 1), v);
+        const int Y = c / w1, X = c - Y * w1;
+        const float v = -(b00 * at(C1, X, Y) + b10 * at(C1, X - 1, Y) + b01 * at(C1, X, Y - 1) + b11 * at(C1, X - 1, Y - 1));
+        if (v != 0.f)
+            unsafeAtomicAdd(dI1 + (int64_t)clampi(oy1 + Y, 0, H - 1) * Pr.gpitch1 + clampi(ox1 + X, 0, W - 1), v);
+    }
+    __syncthreads();
+    // dI0 cells: the 4 bilinear taps of F; cell X reads F at support X - (1, 1) - t, stored at X - t
+    float *dI0 = A.grad0 + Pr.g0;
+    for (int c = li; c < n0; c += 64) {
+        const int Y = c / w0, X = c - Y * w0;
+        auto f = [&](int x, int y) { return (x >= 0 && x < wf && y >= 0 && y < wf) ? F[y * wf + x] : 0.f; };
+        const float v = a00 * f(X, Y) + a10 * f(X - 1, Y) + a01 * f(X, Y - 1) + a11 * f(X - 1, Y - 1);
+        if (v != 0.f)
+            unsafeAtomicAdd(dI0 + (int64_t)clampi(oy0 + Y, 0, H - 1) * Pr.gpitch0 + clampi(ox0 + X, 0, W - 1), v);
     }
 }
 
-size_t adjoint_lds_bytes(int s) { return 2 * sizeof(float) * (size_t)((s + 3) * (s + 3) + (s + 1) * (s + 1)); }
+size_t adjoint_lds_bytes(int s)
+{
+    return sizeof(float) * (size_t)((s + 3) * (s + 3) + (s + 1) * (s + 1) + 3 * s * s);
+}
 
 hipError_t launch_track_adjoint(const AdjParams &A, int dtype, hipStream_t st)
 {
