@@ -61,6 +61,8 @@ def counter_traffic():
 
 
 def cpu_baseline(I0, I1, n_points, budget_s):
+    import numpy as np
+
     import oracle  # the CPU baseline leg is the only product-side user of the oracle
     w = WORKLOAD
     try:
@@ -77,9 +79,23 @@ def cpu_baseline(I0, I1, n_points, budget_s):
         el = time.perf_counter() - t0
         if el >= budget_s or reps >= 3:
             break
+    # one thread on a bounded sample of the same pair (every 8th point)
+    sub = np.ascontiguousarray(pts[::8])
+    t1 = time.perf_counter()
+    oracle.track(I0, I1, sub, w["levels"], w["support"], w["iters"], threads=1)
+    el1 = time.perf_counter() - t1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": reps * n_points / el, "unit": "points/s", "cores": threads, "kind": "oracle",
             "sample": f"{reps} full pass(es) of detect+track of the {n_points}-point 1242x375 pair, FP64, "
-                      f"{el:.1f} s wall"}
+                      f"{el:.1f} s wall",
+            "single_thread_value": len(sub) / el1,
+            "single_thread_sample": f"track of every 8th point ({len(sub)}), 1 thread, {el1:.1f} s",
+            "cpu_model": model}
 
 
 def batched_vs_plain(reps: int):
@@ -112,11 +128,13 @@ def batched_vs_plain(reps: int):
             dgf.track_run(a, b, B["p"], L_, s_, it_, B["ws"], B["f"], B["s"])
 
     plan = dgf.Batch(pairs, L_, s_, it_)
+    its = torch.empty(plan.num_points, dtype=torch.int32, device=dev)
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
-        plan.run()
+        plan.run(its)
         plan.capture()
     torch.cuda.synchronize()
+    pix_iters = int(its.to(torch.int64).sum().item()) * s_ ** 2
 
     def timed(fn, stream):
         with torch.cuda.stream(stream):
@@ -144,6 +162,7 @@ def batched_vs_plain(reps: int):
             "plain_pairs_per_s": len(pairs) / (t_plain * 1e-3),
             "batched_pairs_per_s": len(pairs) / (t_batch * 1e-3),
             "speedup": t_plain / t_batch, "identical_outputs": identical,
+            "batched_track_tflops_lower_bound": pix_iters * FLOPS_PER_PIXEL_ITER / (t_batch * 1e-3) / 1e12,
             "workload": "batch64_mixed: 16 each of 1242x375, 1224x370, 640x480, 320x240, strides {3,5,8}"}
 
 
@@ -321,6 +340,7 @@ def main():
     t_detect = sum(e[0].elapsed_time(e[1]) for e in ev) / K
     t_pyr = sum(e[1].elapsed_time(e[2]) for e in ev) / K
     t_track = sum(e[2].elapsed_time(e[3]) for e in ev) / K
+    ms_median = float(np.median([e[0].elapsed_time(e[3]) for e in ev]))
 
     flops = pix_iters * FLOPS_PER_PIXEL_ITER
     achieved = flops / (t_track * 1e-3) / 1e12
@@ -340,6 +360,7 @@ def main():
         "steps": K,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_median": ms_median,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
