@@ -66,7 +66,7 @@ def _load():
     lib.or_dpsi.argtypes = [f64, f64, f64]
     lib.or_dpsi.restype = f64
     lib.or_track.argtypes = [P, P, i32, i32, i32, i64, P, i64, i32, i32, i32, f64, f64, f64, f64, f64,
-                             P, P, P, i32]
+                             i32, P, P, P, P, i32]
     lib.or_track.restype = i32
     lib.or_track_grad.argtypes = [P, P, i32, i32, P, i64, i32, f64, f64, P, P, P, P, P]
     lib.or_track_grad.restype = i32
@@ -164,9 +164,10 @@ def dpsi(r: float, sigma1: float, sigma2: float) -> float:
 def track(I0: np.ndarray, I1: np.ndarray, points: np.ndarray, levels: int, support: int, iters: int,
           sigma1=DEFAULTS["sigma1"], sigma2=DEFAULTS["sigma2"], eps_coarse=DEFAULTS["eps_coarse"],
           eps_fine=DEFAULTS["eps_fine"], min_eig=DEFAULTS["min_eig"], threads: int | None = None,
-          return_iters: bool = False):
+          return_iters: bool = False, illum: bool = False, return_illum: bool = False):
     """Track points from I0 to I1.  uint8 images use the uint8 pyramid; anything else is taken
-    as real-valued (float64).  Returns (flow[n,2] float64, status[n] uint8[, iters[n,L]])."""
+    as real-valued (float64).  ``illum`` selects the gain/offset illumination model.  Returns
+    (flow[n,2] float64, status[n] uint8[, iters[n,L]][, illum[n,2] = (m, c)])."""
     if I0.shape != I1.shape:
         raise ValueError("I0 and I1 must have the same shape")
     if I0.dtype == np.uint8 and I1.dtype == np.uint8:
@@ -181,14 +182,18 @@ def track(I0: np.ndarray, I1: np.ndarray, points: np.ndarray, levels: int, suppo
     flow = np.zeros((n, 2), np.float64)
     st = np.zeros(n, np.uint8)
     its = np.zeros((n, levels), np.int32) if return_iters else None
+    mc = np.zeros((n, 2), np.float64) if return_illum else None
     rc = _load().or_track(_ptr(a0), _ptr(a1), dt, W, H, W, _ptr(pts), n, levels, support, iters,
-                          sigma1, sigma2, eps_coarse, eps_fine, min_eig, _ptr(flow), _ptr(st), _ptr(its),
-                          threads or default_threads())
+                          sigma1, sigma2, eps_coarse, eps_fine, min_eig, int(bool(illum)), _ptr(flow), _ptr(st),
+                          _ptr(its), _ptr(mc), threads or default_threads())
     if rc != 0:
         raise ValueError(f"or_track failed: {rc}")
+    out = (flow, st)
     if return_iters:
-        return flow, st, its
-    return flow, st
+        out += (its,)
+    if return_illum:
+        out += (mc,)
+    return out
 
 
 def track_grad(I0: np.ndarray, I1: np.ndarray, points: np.ndarray, support: int, flow: np.ndarray,

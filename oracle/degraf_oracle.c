@@ -473,15 +473,232 @@ static void track_point(const pyr_t *P0, const pyr_t *P1, double px, double py, 
     free(gyk);
 }
 
+/* Solves the n x n system A x = b (A row-major, both overwritten) by Gaussian elimination with
+ * partial pivoting.  Returns 0, or -1 when a pivot is zero or not a number (x is then NaN). */
+static int solve_dense(double *A, double *b, int n, double *x)
+{
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(A[r * n + c]) > fabs(A[piv * n + c])) piv = r;
+        if (!(fabs(A[piv * n + c]) > 0.0)) {
+            for (int i = 0; i < n; ++i) x[i] = NAN;
+            return -1;
+        }
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) {
+                double t = A[c * n + k];
+                A[c * n + k] = A[piv * n + k];
+                A[piv * n + k] = t;
+            }
+            double t = b[c];
+            b[c] = b[piv];
+            b[piv] = t;
+        }
+        for (int r = c + 1; r < n; ++r) {
+            double f = A[r * n + c] / A[c * n + c];
+            for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double acc = b[r];
+        for (int k = r + 1; k < n; ++k) acc -= A[r * n + k] * x[k];
+        x[r] = acc / A[r * n + r];
+    }
+    return 0;
+}
+
+/* Determinant of a 4 x 4 matrix by elimination on a copy (0 when singular). */
+static double det4(const double *M)
+{
+    double A[16], b[4] = {0, 0, 0, 0}, x[4];
+    memcpy(A, M, sizeof(A));
+    /* the elimination in solve_dense leaves U in A; its diagonal product times the sign of the
+     * row swaps is the determinant */
+    double det = 1.0;
+    for (int c = 0; c < 4; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 4; ++r)
+            if (fabs(A[r * 4 + c]) > fabs(A[piv * 4 + c])) piv = r;
+        if (!(fabs(A[piv * 4 + c]) > 0.0)) return 0.0;
+        if (piv != c) {
+            for (int k = 0; k < 4; ++k) {
+                double t = A[c * 4 + k];
+                A[c * 4 + k] = A[piv * 4 + k];
+                A[piv * 4 + k] = t;
+            }
+            det = -det;
+        }
+        det *= A[c * 4 + c];
+        for (int r = c + 1; r < 4; ++r) {
+            double f = A[r * 4 + c] / A[c * 4 + c];
+            for (int k = c; k < 4; ++k) A[r * 4 + k] -= f * A[c * 4 + k];
+        }
+    }
+    (void)b;
+    (void)x;
+    return det;
+}
+
+/*
+ * Illumination-model variant of track_point.  The paper's tracker configuration, RLOF(IM-GM)
+ * (Section 3, "Parameters"), matches the support under a linear illumination change whose
+ * definition is in the tracker's citation; the reading used here is a per-point gain and offset,
+ *   I1(p + k + u) ~ (1 + m) I0(p + k) + c,
+ * estimated jointly with u.  Per level, with theta = (d, m, c) and
+ * phi_k = ((1 + m) g_x, (1 + m) g_y, -T_k, -1) -- the derivatives of the residual below, taking
+ * the gradient of I1 at the match as the model predicts it, (1 + m) g_k:
+ *   r_k = B(I1_l, p_l + k + g + d) - (1 + m) T_k - c,   w_k = psi(r_k) / r_k,
+ *   (sum w_k phi_k phi_k^T) delta = - sum w_k r_k phi_k,   theta += delta,
+ *   least-squares step (w = 1) when the weighted determinant is <= 1e-6 of the unweighted one
+ *   (both with the current m), stop the level when |delta_d|_2 < eps_l.
+ * m and c start at 0 on the coarsest level and carry over unchanged between levels (pyramid levels
+ * are weighted averages, under which a gain and an offset stay the same).  Template, gradient,
+ * flat-level rule, level propagation of g and the statuses are those of track_point.  (m, c) of
+ * the last level are returned in illum.
+ */
+static void track_point_illum(const pyr_t *P0, const pyr_t *P1, double px, double py, int L, int s,
+                              int iters, const or_opts *o, double *ux, double *uy, uint8_t *st,
+                              int32_t *it_count, double *illum)
+{
+    const int r = s / 2;
+    const int W = P0->W[0], H = P0->H[0];
+    illum[0] = 0.0;
+    illum[1] = 0.0;
+    if (!(isfinite(px) && isfinite(py)) || px < 0.0 || py < 0.0 || px > W - 1 || py > H - 1) {
+        *ux = 0.0;
+        *uy = 0.0;
+        *st = OR_ST_OUT_OF_BOUNDS;
+        return;
+    }
+    const int npix = s * s;
+    double *T = (double *)malloc(sizeof(double) * npix);
+    double *gxk = (double *)malloc(sizeof(double) * npix);
+    double *gyk = (double *)malloc(sizeof(double) * npix);
+
+    double gX = 0.0, gY = 0.0, dX = 0.0, dY = 0.0;
+    double m = 0.0, c = 0.0; /* gain change and offset, carried across levels */
+    int conv = 0;
+    int status = -1;
+    for (int l = L - 1; l >= 0; --l) {
+        const double scale = ldexp(1.0, -l);
+        const double plx = px * scale, ply = py * scale;
+        const int Wl = P0->W[l], Hl = P0->H[l];
+        const double *I0l = P0->img[l];
+
+        /* template, its gradient, and the 2 x 2 gradient matrix for the trackability test */
+        double a2 = 0.0, b2 = 0.0, c2 = 0.0;
+        for (int ky = -r; ky <= r; ++ky)
+            for (int kx = -r; kx <= r; ++kx) {
+                int k = (ky + r) * s + (kx + r);
+                double x = plx + kx, y = ply + ky;
+                T[k] = or_bilinear(I0l, Wl, Hl, x, y);
+                gxk[k] = 0.5 * (or_bilinear(I0l, Wl, Hl, x + 1.0, y) - or_bilinear(I0l, Wl, Hl, x - 1.0, y));
+                gyk[k] = 0.5 * (or_bilinear(I0l, Wl, Hl, x, y + 1.0) - or_bilinear(I0l, Wl, Hl, x, y - 1.0));
+                a2 += gxk[k] * gxk[k];
+                b2 += gxk[k] * gyk[k];
+                c2 += gyk[k] * gyk[k];
+            }
+        const double lam_min = 0.5 * (a2 + c2) - sqrt(0.25 * (a2 - c2) * (a2 - c2) + b2 * b2);
+        if (!(lam_min / (double)npix >= o->min_eig)) {
+            if (l == 0) {
+                *ux = gX;
+                *uy = gY;
+                status = OR_ST_ILL_CONDITIONED;
+                break;
+            }
+            if (it_count) it_count[L - 1 - l] = 0;
+            gX = 2.0 * gX;
+            gY = 2.0 * gY;
+            continue;
+        }
+        const double eps = (l > 0) ? o->eps_coarse : o->eps_fine;
+
+        dX = 0.0;
+        dY = 0.0;
+        conv = 0;
+        int bad = 0;
+        int it = 0;
+        for (it = 1; it <= iters; ++it) {
+            double G[16] = {0}, G0[16] = {0}, rhs[4] = {0, 0, 0, 0}, rhs0[4] = {0, 0, 0, 0};
+            for (int ky = -r; ky <= r; ++ky)
+                for (int kx = -r; kx <= r; ++kx) {
+                    int k = (ky + r) * s + (kx + r);
+                    double J = or_bilinear(P1->img[l], Wl, Hl, plx + kx + gX + dX, ply + ky + gY + dY);
+                    double res = J - (1.0 + m) * T[k] - c;
+                    double w = irls_weight(res, o->sigma1, o->sigma2);
+                    double phi[4] = {(1.0 + m) * gxk[k], (1.0 + m) * gyk[k], -T[k], -1.0};
+                    for (int a = 0; a < 4; ++a) {
+                        for (int b = 0; b < 4; ++b) {
+                            G[a * 4 + b] += w * phi[a] * phi[b];
+                            G0[a * 4 + b] += phi[a] * phi[b];
+                        }
+                        rhs[a] -= w * res * phi[a];
+                        rhs0[a] -= res * phi[a];
+                    }
+                }
+            if (!(det4(G) > 1e-6 * det4(G0))) { /* too many down-weighted pixels: least-squares step */
+                memcpy(G, G0, sizeof(G));
+                memcpy(rhs, rhs0, sizeof(rhs));
+            }
+            double delta[4];
+            solve_dense(G, rhs, 4, delta);
+            if (!(isfinite(delta[0]) && isfinite(delta[1]) && isfinite(delta[2]) && isfinite(delta[3]))) {
+                bad = 1;
+                break;
+            }
+            dX += delta[0];
+            dY += delta[1];
+            m += delta[2];
+            c += delta[3];
+            if (sqrt(delta[0] * delta[0] + delta[1] * delta[1]) < eps) {
+                conv = 1;
+                break;
+            }
+        }
+        if (it_count) it_count[L - 1 - l] = (it > iters) ? iters : it;
+        if (bad) {
+            *ux = NAN;
+            *uy = NAN;
+            status = OR_ST_NOT_CONVERGED;
+            break;
+        }
+        if (l > 0) {
+            gX = 2.0 * (gX + dX);
+            gY = 2.0 * (gY + dY);
+        }
+    }
+    if (status < 0) {
+        *ux = gX + dX;
+        *uy = gY + dY;
+        if (!conv)
+            status = OR_ST_NOT_CONVERGED;
+        else {
+            double qx = px + *ux, qy = py + *uy;
+            status = (qx >= 0.0 && qy >= 0.0 && qx <= W - 1 && qy <= H - 1) ? OR_ST_CONVERGED
+                                                                            : OR_ST_OUT_OF_BOUNDS;
+        }
+    }
+    illum[0] = m;
+    illum[1] = c;
+    *st = (uint8_t)status;
+    free(T);
+    free(gxk);
+    free(gyk);
+}
+
 /*
  * Track n points.  I0/I1: dtype 0 = uint8 (row pitch in bytes), 1 = double (pitch in elements).
  * flow: out [n][2];  status: out [n];  iters_out: nullable [n][L], iterations run per level,
  * coarsest level first (0 where the point stopped before reaching that level).
+ * illum: 0 = plain tracker (track_point); 1 = illumination model (track_point_illum), whose
+ * final (m, c) go to illum_out (nullable, [n][2]).
  */
 int or_track(const void *I0, const void *I1, int dtype, int W, int H, int64_t pitch, const double *pts,
              int64_t n, int levels, int support, int iters, double sigma1, double sigma2,
-             double eps_coarse, double eps_fine, double min_eig, double *flow, uint8_t *status,
-             int32_t *iters_out, int nthreads)
+             double eps_coarse, double eps_fine, double min_eig, int illum, double *flow, uint8_t *status,
+             int32_t *iters_out, double *illum_out, int nthreads)
 {
     if (!I0 || !I1 || (n > 0 && (!pts || !flow || !status))) return OR_ERR_ARG;
     if (W <= 0 || H <= 0 || levels < 1 || levels > 16 || support < 1 || (support % 2) == 0 || iters < 1)
@@ -500,8 +717,18 @@ int or_track(const void *I0, const void *I1, int dtype, int W, int H, int64_t pi
     if (iters_out) memset(iters_out, 0, sizeof(int32_t) * (size_t)n * levels);
 #pragma omp parallel for num_threads(nthreads) schedule(dynamic, 16)
     for (int64_t i = 0; i < n; ++i) {
-        track_point(&P0, &P1, pts[2 * i], pts[2 * i + 1], levels, support, iters, &o, &flow[2 * i],
-                    &flow[2 * i + 1], &status[i], iters_out ? &iters_out[i * levels] : NULL);
+        if (illum) {
+            double mc[2];
+            track_point_illum(&P0, &P1, pts[2 * i], pts[2 * i + 1], levels, support, iters, &o, &flow[2 * i],
+                              &flow[2 * i + 1], &status[i], iters_out ? &iters_out[i * levels] : NULL, mc);
+            if (illum_out) {
+                illum_out[2 * i] = mc[0];
+                illum_out[2 * i + 1] = mc[1];
+            }
+        } else {
+            track_point(&P0, &P1, pts[2 * i], pts[2 * i + 1], levels, support, iters, &o, &flow[2 * i],
+                        &flow[2 * i + 1], &status[i], iters_out ? &iters_out[i * levels] : NULL);
+        }
     }
     pyr_free(&P0);
     pyr_free(&P1);

@@ -124,3 +124,53 @@ def min_eig_per_level(I0, pts, levels, support):
         a, b, c = (GX * GX).sum(1), (GX * GY).sum(1), (GY * GY).sum(1)
         out[:, l] = (0.5 * (a + c) - np.sqrt(0.25 * (a - c) ** 2 + b * b)) / support ** 2
     return out
+
+
+def lk_pyramidal_illum(I0, I1, pts, levels, support, iters, eps_coarse, eps_fine):
+    """Least-squares pyramidal LK with a per-point gain and offset, I1(p + k + u) ~ (1 + m) T_k + c:
+    per level, Gauss-Newton on (d, m, c) with residual derivatives ((1 + m) g, -T, -1), solved as a
+    4 x 4 system per point; m, c carry over between levels.  Returns (flow, converged, m, c)."""
+    P0, P1 = [I0], [I1]
+    for _ in range(levels - 1):
+        P0.append(pyr_down_scipy(P0[-1]))
+        P1.append(pyr_down_scipy(P1[-1]))
+    P0 = [p.astype(np.float64) for p in P0]
+    P1 = [p.astype(np.float64) for p in P1]
+    pts = np.asarray(pts, np.float64)
+    n = len(pts)
+    r = support // 2
+    ky, kx = np.mgrid[-r:r + 1, -r:r + 1].astype(np.float64)
+    kx, ky = kx.ravel()[None, :], ky.ravel()[None, :]
+    g = np.zeros((n, 2))
+    d = np.zeros((n, 2))
+    m = np.zeros(n)
+    c = np.zeros(n)
+    conv = np.zeros(n, bool)
+    for l in range(levels - 1, -1, -1):
+        pl = pts / 2.0 ** l
+        X, Y = pl[:, :1] + kx, pl[:, 1:] + ky
+        T = _sample(P0[l], X, Y)
+        GX = 0.5 * (_sample(P0[l], X + 1.0, Y) - _sample(P0[l], X - 1.0, Y))
+        GY = 0.5 * (_sample(P0[l], X, Y + 1.0) - _sample(P0[l], X, Y - 1.0))
+        d = np.zeros((n, 2))
+        active = np.ones(n, bool)
+        conv = np.zeros(n, bool)
+        eps = eps_coarse if l > 0 else eps_fine
+        for _ in range(iters):
+            if not active.any():
+                break
+            J = _sample(P1[l], X + (g[:, :1] + d[:, :1]), Y + (g[:, 1:] + d[:, 1:]))
+            res = J - (1.0 + m)[:, None] * T - c[:, None]
+            phi = np.stack([(1.0 + m)[:, None] * GX, (1.0 + m)[:, None] * GY, -T, -np.ones_like(T)], axis=2)
+            A = np.einsum("nka,nkb->nab", phi, phi)
+            b = -np.einsum("nk,nka->na", res, phi)
+            delta = np.linalg.solve(A, b[..., None])[..., 0]
+            d[active] += delta[active, :2]
+            m[active] += delta[active, 2]
+            c[active] += delta[active, 3]
+            done = active & (np.hypot(delta[:, 0], delta[:, 1]) < eps)
+            conv |= done
+            active &= ~done
+        if l > 0:
+            g = 2.0 * (g + d)
+    return g + d, conv, m, c
