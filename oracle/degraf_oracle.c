@@ -555,8 +555,10 @@ static double det4(const double *M)
  *   (both with the current m), stop the level when |delta_d|_2 < eps_l.
  * m and c start at 0 on the coarsest level and carry over unchanged between levels (pyramid levels
  * are weighted averages, under which a gain and an offset stay the same).  Template, gradient,
- * flat-level rule, level propagation of g and the statuses are those of track_point.  (m, c) of
- * the last level are returned in illum.
+ * flat-level rule, level propagation of g and the statuses are those of track_point, except that
+ * a point whose final gain 1 + m lies outside [1/2, 2] is NOT_CONVERGED: such a match explains the
+ * support by a contrast change (or inversion) instead of a motion.  (m, c) of the last level are
+ * returned in illum.
  */
 static void track_point_illum(const pyr_t *P0, const pyr_t *P1, double px, double py, int L, int s,
                               int iters, const or_opts *o, double *ux, double *uy, uint8_t *st,
@@ -672,7 +674,7 @@ static void track_point_illum(const pyr_t *P0, const pyr_t *P1, double px, doubl
     if (status < 0) {
         *ux = gX + dX;
         *uy = gY + dY;
-        if (!conv)
+        if (!conv || !(1.0 + m >= 0.5 && 1.0 + m <= 2.0))
             status = OR_ST_NOT_CONVERGED;
         else {
             double qx = px + *ux, qy = py + *uy;

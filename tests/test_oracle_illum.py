@@ -136,3 +136,23 @@ def test_large_offset_takes_the_least_squares_step_first():
     assert np.all(st == oracle.ST_CONVERGED)
     assert np.max(np.abs(flow - np.array(t, float))) < 1e-6
     assert np.max(np.abs(mc[:, 0] * 100.0 + mc[:, 1] - 60.0)) < 1e-3
+
+
+def test_contrast_inversion_is_not_a_match():
+    # I1 = 255 - I0 shifted: the model fits it exactly with gain -1, which is a contrast inversion,
+    # not an illumination change; such points end NOT_CONVERGED (gain outside [1/2, 2])
+    W, H, t = 100, 80, (2, -1)
+    I0 = _texture(W, H, 13)
+    I1 = 255.0 - I0
+    I1[max(t[1], 0):H + min(t[1], 0), max(t[0], 0):W + min(t[0], 0)] = \
+        255.0 - I0[max(-t[1], 0):H - max(t[1], 0), max(-t[0], 0):W - max(t[0], 0)]
+    pts = _interior(W, H, 15, 18, 14)
+    flow, st, mc = oracle.track(I0, I1, pts, 1, 9, 60, sigma1=INF, sigma2=INF, eps_fine=1e-10, min_eig=0.0,
+                                illum=True, return_illum=True)
+    exact = np.abs(1.0 + mc[:, 0] + 1.0) < 1e-6  # points that reached the exact fit, gain -1
+    assert exact.sum() >= 5 and np.max(np.abs(flow[exact] - np.array(t, float))) < 1e-6
+    assert np.all(st[exact] == oracle.ST_NOT_CONVERGED)
+    # a gain of 1.9 stays a match
+    I2 = 1.9 * I0
+    flow, st = oracle.track(I0, I2, pts, 1, 9, 60, sigma1=INF, sigma2=INF, eps_fine=1e-10, min_eig=0.0, illum=True)
+    assert np.all(st == oracle.ST_CONVERGED) and np.max(np.abs(flow)) < 1e-8
