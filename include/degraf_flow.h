@@ -80,8 +80,18 @@ typedef struct {
     float min_eig;    /* a level with lambda_min(G0)/s^2 < min_eig runs no iteration and
                          passes its guess on; at level 0 the point is ill-conditioned
                          (default 1e-4 * 255^2)                                          */
-    int32_t flags;    /* reserved, must be 0                                            */
+    int32_t flags;    /* 0, or DGF_TRACK_ILLUM                                          */
 } dgf_track_opts;
+
+/* dgf_track_opts.flags: match each support under a per-point gain and offset estimated with
+ * the flow, I1(p + k + u) ~ (1 + m) I0(p + k) + c (the illumination model of the tracker the
+ * paper runs, RLOF(IM), Section 3 "Parameters"; the model itself is defined in its citation).
+ * Each iteration then solves a 4x4 system in (d, m, c), with residual derivatives
+ * ((1 + m) g, -T, -1); m and c start at 0 and carry over between levels; a point whose final
+ * gain 1 + m lies outside [1/2, 2] is NOT_CONVERGED (a contrast change, not a match).  Supported for the
+ * supports the row-run kernel is compiled for (5, 7, 9, 11, 15, 21), else DGF_ERR_UNSUPPORTED;
+ * dgf_track_backward does not support it. */
+#define DGF_TRACK_ILLUM 1
 
 /* ---- library ----------------------------------------------------------------------------------- */
 
@@ -227,7 +237,8 @@ int64_t dgf_batch_grad_size(const dgf_batch *b, int64_t *offsets);
  * (dgf_batch_grad_size floats, device) with dL/dI0 and dL/dI1 of every pair, taking the uint8
  * frames' values as reals.  grad is cleared by a kernel first; contributions are added with
  * device float atomics, so the last bits are not deterministic.  Points that are not CONVERGED,
- * or have a singular J, contribute nothing. */
+ * or have a singular J, contribute nothing.  DGF_ERR_UNSUPPORTED for a plan made with
+ * DGF_TRACK_ILLUM. */
 int dgf_batch_backward(dgf_batch *b, const float *points, const float *flow, const uint8_t *status, const float *dflow,
                        float *grad, void *stream);
 

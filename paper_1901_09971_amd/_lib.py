@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libdegraf_flow.so")
 
 DGF_OK = 0
 DGF_U8, DGF_F32 = 0, 1
+DGF_TRACK_ILLUM = 1
 DGF_MAX_LEVELS = 12
 ST_CONVERGED, ST_NOT_CONVERGED, ST_ILL_CONDITIONED, ST_OUT_OF_BOUNDS = 0, 1, 2, 3
 

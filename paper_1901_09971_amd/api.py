@@ -9,7 +9,7 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import DGF_F32, DGF_U8, DgfImage, DgfTrackOpts, check, lib
+from ._lib import DGF_F32, DGF_TRACK_ILLUM, DGF_U8, DgfImage, DgfTrackOpts, check, lib
 
 
 @dataclass
@@ -20,9 +20,11 @@ class TrackOpts:
     eps_coarse: float = 1e-2
     eps_fine: float = 1e-4
     min_eig: float = 1e-4 * 255.0 * 255.0
+    illum: bool = False  # per-point gain and offset estimated with the flow (DGF_TRACK_ILLUM)
 
     def to_c(self) -> DgfTrackOpts:
-        return DgfTrackOpts(self.sigma1, self.sigma2, self.eps_coarse, self.eps_fine, self.min_eig, 0)
+        return DgfTrackOpts(self.sigma1, self.sigma2, self.eps_coarse, self.eps_fine, self.min_eig,
+                            DGF_TRACK_ILLUM if self.illum else 0)
 
 
 def _stream() -> ctypes.c_void_p:

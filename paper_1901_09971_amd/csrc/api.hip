@@ -199,7 +199,8 @@ int validate_track(const dgf_image *I0, const dgf_image *I1, const float *points
     if (n > 0 && (!points || !flow || !status)) return DGF_ERR_INVALID_ARG;
     if (opts) {
         *o = *opts;
-        if (o->flags != 0) return DGF_ERR_UNSUPPORTED;
+        if ((o->flags & ~DGF_TRACK_ILLUM) != 0) return DGF_ERR_UNSUPPORTED;
+        if ((o->flags & DGF_TRACK_ILLUM) && run_shape_lanes(support) == 0) return DGF_ERR_UNSUPPORTED;
     } else {
         dgf_track_opts_default(o);
     }
@@ -217,6 +218,7 @@ int track_run_with(const dgf_image *I0, const dgf_image *I1, const float *points
                    int32_t support, int32_t iters, const dgf_track_opts &o, const void *workspace, float *flow,
                    uint8_t *status, int32_t *iters_out, TrackTuning tune, hipStream_t st)
 {
+    if (o.flags & DGF_TRACK_ILLUM) tune = illum_tuning(support, tune);
     if (!track_shape_ok(support, tune)) return DGF_ERR_UNSUPPORTED;
     while (track_lds_bytes(support, tune) > kMaxLdsPerBlock && tune.wpb > 1) tune.wpb /= 2;
     if (track_lds_bytes(support, tune) > kMaxLdsPerBlock) return DGF_ERR_UNSUPPORTED;

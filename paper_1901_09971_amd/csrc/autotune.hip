@@ -138,6 +138,7 @@ int dgf_autotune(const dgf_image *I0, const dgf_image *I1, const float *points, 
                 for (int m : {1, 2, 3, 4, 6}) {
                     const TrackTuning t{lpp, wpb, m, kind};
                     if (kind == 0 && !run_shape_compiled(lpp, support)) continue;
+                    if (kind == 1 && (o.flags & DGF_TRACK_ILLUM)) continue;
                     if (!tuning_valid(t, support) || track_lds_bytes(support, t) > kMaxLdsPerBlock) continue;
                     cand.push_back(t);
                 }

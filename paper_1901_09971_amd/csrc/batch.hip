@@ -126,7 +126,8 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
     dgf_track_opts o;
     if (opts) {
         o = *opts;
-        if (o.flags != 0) return DGF_ERR_UNSUPPORTED;
+        if ((o.flags & ~DGF_TRACK_ILLUM) != 0) return DGF_ERR_UNSUPPORTED;
+        if ((o.flags & DGF_TRACK_ILLUM) && run_shape_lanes(support) == 0) return DGF_ERR_UNSUPPORTED;
     } else {
         dgf_track_opts_default(&o);
     }
@@ -148,6 +149,7 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
     for (int i = 0; i < npairs; ++i)
         total_n += dgf_detect_count(pairs[i].I0.width, pairs[i].I0.height, pairs[i].window, pairs[i].stride);
     b->tune = tuning_for(support, levels, dtype, total_n);
+    if (o.flags & DGF_TRACK_ILLUM) b->tune = illum_tuning(support, b->tune);
     if (!track_shape_ok(support, b->tune)) {
         delete b;
         return DGF_ERR_UNSUPPORTED;
@@ -354,6 +356,7 @@ int dgf_batch_backward(dgf_batch *b, const float *points, const float *flow, con
     if (!b) return DGF_ERR_INVALID_ARG;
     if (b->total_pts > 0 && (!points || !flow || !status || !dflow || !grad)) return DGF_ERR_INVALID_ARG;
     if (grad && (uintptr_t)grad % 4 != 0) return DGF_ERR_INVALID_ARG;
+    if (b->opts.flags & DGF_TRACK_ILLUM) return DGF_ERR_UNSUPPORTED; // the adjoint covers the plain model
     if (b->total_pts == 0) return DGF_OK;
     hipStream_t st = (hipStream_t)stream;
     const int64_t ng = b->grad_off[b->P];

@@ -199,6 +199,7 @@ struct TrackParams {
     int32_t tile_floats; // LDS floats per point = max(RW RPP + (s+2) RPP, TW * TP)
     float invBW;         // 1 / (s + 2)
     int32_t mode;        // ROBUST_L2, ROBUST_HAMPEL or ROBUST_HARD
+    int32_t illum;       // 1: gain / offset illumination model (4x4 system per iteration)
     float s1, s2, cmid;  // robust thresholds and sigma1 / (sigma2 - sigma1) (0 if unused)
     float cs2;           // cmid * sigma2
     float eps2c, eps2f;  // squared stopping thresholds
@@ -309,6 +310,37 @@ __device__ __forceinline__ LevelPair level_of(const TrackParams &P, int pair, in
 //   ROBUST_HARD   sigma1 >= sigma2, or sigma1 = 0: w = 1 for |r| <= sigma1, else 0
 enum { ROBUST_L2 = 0, ROBUST_HAMPEL = 1, ROBUST_HARD = 2 };
 
+// Symmetric 4x4 system M x = v by an LDL^T factorisation; m holds the upper triangle row by row
+// (m00 m01 m02 m03 m11 m12 m13 m22 m23 m33).  Returns det M (the product of the pivots); when a
+// pivot is not positive, x is not finite.  x may be null (determinant only).
+__device__ __forceinline__ float ldl4(const float *m, const float *v, float *x)
+{
+    const float d0 = m[0];
+    const float i0 = __builtin_amdgcn_rcpf(d0);
+    const float l10 = m[1] * i0, l20 = m[2] * i0, l30 = m[3] * i0;
+    const float d1 = m[4] - l10 * m[1];
+    const float i1 = __builtin_amdgcn_rcpf(d1);
+    const float l21 = (m[5] - l20 * m[1]) * i1, l31 = (m[6] - l30 * m[1]) * i1;
+    const float d2 = m[7] - l20 * m[2] - l21 * l21 * d1;
+    const float i2 = __builtin_amdgcn_rcpf(d2);
+    const float l32 = (m[8] - l30 * m[2] - l31 * l21 * d1) * i2;
+    const float d3 = m[9] - l30 * m[3] - l31 * l31 * d1 - l32 * l32 * d2;
+    const float i3 = __builtin_amdgcn_rcpf(d3);
+    if (x) {
+        const bool ok = d0 > 0.f && d1 > 0.f && d2 > 0.f && d3 > 0.f;
+        const float y0 = v[0], y1 = v[1] - l10 * y0, y2 = v[2] - l20 * y0 - l21 * y1;
+        const float y3 = v[3] - l30 * y0 - l31 * y1 - l32 * y2;
+        const float x3 = y3 * i3, x2 = y2 * i2 - l32 * x3, x1 = y1 * i1 - l21 * x2 - l31 * x3;
+        const float x0 = y0 * i0 - l10 * x1 - l20 * x2 - l30 * x3;
+        const float bad = __builtin_nanf("");
+        x[0] = ok ? x0 : bad;
+        x[1] = ok ? x1 : bad;
+        x[2] = ok ? x2 : bad;
+        x[3] = ok ? x3 : bad;
+    }
+    return d0 * d1 * d2 * d3;
+}
+
 // IRLS weight of the middle-band norm, psi(r) / r = clamp(cs2 / |r| - cmid, 0, 1) with
 // cmid = sigma1 / (sigma2 - sigma1) and cs2 = cmid sigma2: exactly 1 over the inner band
 // (cs2 / sigma1 - cmid = 1), falling to 0 at sigma2.  At r = 0 the reciprocal is infinite and the
@@ -377,6 +409,8 @@ hipError_t launch_pyr_level(const PyrJob *jobs, int njobs, int dtype, hipStream_
 hipError_t launch_track(const TrackParams &P, const TrackTuning &T, int dtype, hipStream_t st);
 int pick_ppl_max(int s, int lpp);
 bool run_shape_compiled(int lpp, int s);
+int run_shape_lanes(int s); // lanes per point of a compiled row-run shape for support s (64 preferred), 0 if none
+TrackTuning illum_tuning(int s, TrackTuning t); // t moved onto a row-run shape (the illumination model runs there)
 // true when a kernel is compiled for this support and launch shape
 bool track_shape_ok(int s, const TrackTuning &T);
 constexpr size_t kMaxLdsPerBlock = 64 * 1024;

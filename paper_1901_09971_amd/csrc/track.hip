@@ -18,6 +18,22 @@ bool run_shape_compiled(int lpp, int s)
     return false;
 }
 
+int run_shape_lanes(int s)
+{
+    for (int lpp : {64, 32, 16})
+        if (run_shape_compiled(lpp, s)) return lpp;
+    return 0;
+}
+
+TrackTuning illum_tuning(int s, TrackTuning t)
+{
+    if (t.kind != 0 || !run_shape_compiled(t.lpp, s)) {
+        t.kind = 0;
+        t.lpp = run_shape_lanes(s);
+    }
+    return t;
+}
+
 namespace {
 
 bool shape_compiled(int lpp, int ppl, int tp)

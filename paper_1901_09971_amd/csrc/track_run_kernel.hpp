@@ -48,7 +48,7 @@ __device__ __forceinline__ void group_sum5(float &a, float &b, float &c, float &
     }
 }
 
-template <int LPP, int SEG, int R, int TP, typename PixT>
+template <int LPP, int SEG, int R, int TP, typename PixT, bool IM>
 __global__ __launch_bounds__(256) void k_track_run(TrackParams P)
 {
     constexpr int PPW = 64 / LPP;
@@ -116,6 +116,7 @@ __global__ __launch_bounds__(256) void k_track_run(TrackParams P)
     float gX = 0.f, gY = 0.f, dX = 0.f, dY = 0.f;
     bool conv0 = false;
     int it_total = 0;
+    float im_m = 0.f, im_c = 0.f; // illumination model: gain change and offset, carried across levels
 
 
     for (int l = P.L - 1; l >= 0; --l) {
@@ -160,16 +161,56 @@ __global__ __launch_bounds__(256) void k_track_run(TrackParams P)
                 }
             }
         }
-        float a = 0.f, b = 0.f, c = 0.f;
+        float a = 0.f, b = 0.f, c = 0.f, sT = 0.f;
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
             a = fmaf(GX[j], GX[j], a);
             b = fmaf(GX[j], GY[j], b);
             c = fmaf(GY[j], GY[j], c);
+            if constexpr (IM) sT += ((vmask >> (j / R)) & 1u) ? T[j] : 0.f;
         }
         {
-            float z0 = 0.f, z1 = 0.f;
-            group_sum5<LPP>(a, b, c, z0, z1);
+            float z1 = 0.f;
+            group_sum5<LPP>(a, b, c, sT, z1);
+        }
+        // Illumination model: the template is centred and scaled over the support, T' = (T - Tm) / Ts,
+        // and the iteration runs in (d, ga, gb) with ga = (1 + m) Ts and gb = (1 + m) Tm + c, a linear
+        // change of the gain / offset parameters that leaves the Gauss-Newton iterates in d unchanged
+        // and conditions the 4x4 system.  M0 is its unweighted matrix for phi = (g, -T', -1).
+        float Tm = 0.f, Ts = 1.f, ga = 0.f, gb = 0.f, det0_im = 0.f;
+        float M0[10];
+        if constexpr (IM) {
+            const float nv = (float)(s * s);
+            Tm = sT / nv;
+            float S2 = 0.f, Sgxd = 0.f, Sgyd = 0.f, Sgx = 0.f, Sgy = 0.f;
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) {
+                const float dv = ((vmask >> (j / R)) & 1u) ? T[j] - Tm : 0.f;
+                S2 = fmaf(dv, dv, S2);
+                Sgxd = fmaf(GX[j], dv, Sgxd);
+                Sgyd = fmaf(GY[j], dv, Sgyd);
+                Sgx += GX[j];
+                Sgy += GY[j];
+            }
+            group_sum5<LPP>(S2, Sgxd, Sgyd, Sgx, Sgy);
+            Ts = sqrtf(S2 / nv);
+            if (!(Ts > 1e-6f)) Ts = 1.f;
+            const float iTs = 1.f / Ts;
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) T[j] = (T[j] - Tm) * iTs;
+            M0[0] = a;
+            M0[1] = b;
+            M0[2] = -Sgxd * iTs;
+            M0[3] = -Sgx;
+            M0[4] = c;
+            M0[5] = -Sgyd * iTs;
+            M0[6] = -Sgy;
+            M0[7] = S2 * iTs * iTs;
+            M0[8] = 0.f; // sum of T' over the support
+            M0[9] = nv;
+            det0_im = ldl4(M0, nullptr, nullptr);
+            ga = (1.f + im_m) * Ts;
+            gb = (1.f + im_m) * Tm + im_c;
         }
         const float lam = 0.5f * (a + c) - sqrtf(0.25f * (a - c) * (a - c) + b * b);
         // too flat to invert: a coarse level runs no iteration and passes the guess on; at
@@ -229,81 +270,182 @@ __global__ __launch_bounds__(256) void k_track_run(TrackParams P)
                 }
 #pragma unroll
                 for (int p = 0; p < R; ++p) {
-                    float v = fmaf(w00, t0[p], -T[j * R + p]);
+                    float v;
+                    if constexpr (IM)
+                        v = fmaf(w00, t0[p], -fmaf(ga, T[j * R + p], gb));
+                    else
+                        v = fmaf(w00, t0[p], -T[j * R + p]);
                     v = fmaf(w10, t0[p + 1], v);
                     v = fmaf(w01, t1[p], v);
                     RES[j * R + p] = fmaf(w11, t1[p + 1], v);
                 }
             }
 
-            float G11, G12, G22, B1 = 0.f, B2 = 0.f, det;
-            if (P.mode == ROBUST_L2) {
-#pragma unroll
-                for (int j = 0; j < PPL; ++j) {
-                    B1 = fmaf(RES[j], GX[j], B1);
-                    B2 = fmaf(RES[j], GY[j], B2);
-                }
-                float z0 = 0.f, z1 = 0.f, z2 = 0.f;
-                group_sum5<LPP>(B1, B2, z0, z1, z2);
-                G11 = a;
-                G12 = b;
-                G22 = c;
-                det = det0;
-            } else {
-                G11 = 0.f;
-                G12 = 0.f;
-                G22 = 0.f;
-                if (P.mode == ROBUST_HAMPEL) {
+            float sx, sy, sa = 0.f, sb = 0.f;
+            if constexpr (IM) {
+                // phi = (g, -T', -1) per pixel: A = sum w phi phi^T (upper triangle), V = sum w r phi
+                // with the signs applied after the reduction; invalid runs have weight 0
+                float A[10], V[4];
+                float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+                if (P.mode == ROBUST_L2) {
 #pragma unroll
                     for (int j = 0; j < PPL; ++j) {
-                        const float w = hampel_weight(RES[j], P.cs2, P.cmid);
-                        const float wgx = w * GX[j], wgy = w * GY[j];
-                        G11 = fmaf(wgx, GX[j], G11);
-                        G12 = fmaf(wgx, GY[j], G12);
-                        G22 = fmaf(wgy, GY[j], G22);
-                        B1 = fmaf(RES[j], wgx, B1);
-                        B2 = fmaf(RES[j], wgy, B2);
+                        const float w = ((vmask >> (j / R)) & 1u) ? 1.f : 0.f;
+                        const float rw = RES[j] * w;
+                        q0 = fmaf(rw, GX[j], q0);
+                        q1 = fmaf(rw, GY[j], q1);
+                        q2 = fmaf(rw, T[j], q2);
+                        q3 += rw;
                     }
+                    float z0 = 0.f;
+                    group_sum5<LPP>(q0, q1, q2, q3, z0);
+#pragma unroll
+                    for (int e = 0; e < 10; ++e) A[e] = M0[e];
                 } else {
+                    float s00 = 0.f, s01 = 0.f, s11 = 0.f, s02 = 0.f, s12 = 0.f, s03 = 0.f, s13 = 0.f, s22 = 0.f,
+                          s23 = 0.f, s33 = 0.f;
 #pragma unroll
                     for (int j = 0; j < PPL; ++j) {
-                        const float w = (fabsf(RES[j]) <= P.s1) ? 1.f : 0.f;
-                        const float wgx = w * GX[j], wgy = w * GY[j];
-                        G11 = fmaf(wgx, GX[j], G11);
-                        G12 = fmaf(wgx, GY[j], G12);
-                        G22 = fmaf(wgy, GY[j], G22);
-                        B1 = fmaf(RES[j], wgx, B1);
-                        B2 = fmaf(RES[j], wgy, B2);
+                        float w = (P.mode == ROBUST_HAMPEL) ? hampel_weight(RES[j], P.cs2, P.cmid)
+                                                            : ((fabsf(RES[j]) <= P.s1) ? 1.f : 0.f);
+                        w = ((vmask >> (j / R)) & 1u) ? w : 0.f;
+                        const float wgx = w * GX[j], wgy = w * GY[j], wt = w * T[j];
+                        s00 = fmaf(wgx, GX[j], s00);
+                        s01 = fmaf(wgx, GY[j], s01);
+                        s11 = fmaf(wgy, GY[j], s11);
+                        s02 = fmaf(wgx, T[j], s02);
+                        s12 = fmaf(wgy, T[j], s12);
+                        s03 += wgx;
+                        s13 += wgy;
+                        s22 = fmaf(wt, T[j], s22);
+                        s23 += wt;
+                        s33 += w;
+                        q0 = fmaf(RES[j], wgx, q0);
+                        q1 = fmaf(RES[j], wgy, q1);
+                        q2 = fmaf(RES[j], wt, q2);
+                        q3 = fmaf(RES[j], w, q3);
+                    }
+                    float z0 = 0.f;
+                    group_sum5<LPP>(s00, s01, s11, s02, s12);
+                    group_sum5<LPP>(s03, s13, s22, s23, s33);
+                    group_sum5<LPP>(q0, q1, q2, q3, z0);
+                    A[0] = s00;
+                    A[1] = s01;
+                    A[2] = -s02;
+                    A[3] = -s03;
+                    A[4] = s11;
+                    A[5] = -s12;
+                    A[6] = -s13;
+                    A[7] = s22;
+                    A[8] = s23;
+                    A[9] = s33;
+                    const float detw = ldl4(A, nullptr, nullptr);
+                    const bool fb = lvl_active && !(detw > 1e-6f * det0_im);
+                    if (wave_any(fb)) { // too many down-weighted pixels: least-squares step
+                        float u0 = 0.f, u1 = 0.f, u2 = 0.f, u3 = 0.f, z1 = 0.f;
+#pragma unroll
+                        for (int j = 0; j < PPL; ++j) {
+                            const float rv = ((vmask >> (j / R)) & 1u) ? RES[j] : 0.f;
+                            u0 = fmaf(rv, GX[j], u0);
+                            u1 = fmaf(rv, GY[j], u1);
+                            u2 = fmaf(rv, T[j], u2);
+                            u3 += rv;
+                        }
+                        group_sum5<LPP>(u0, u1, u2, u3, z1);
+                        if (fb) {
+#pragma unroll
+                            for (int e = 0; e < 10; ++e) A[e] = M0[e];
+                            q0 = u0;
+                            q1 = u1;
+                            q2 = u2;
+                            q3 = u3;
+                        }
                     }
                 }
-                group_sum5<LPP>(G11, G12, G22, B1, B2);
-                det = G11 * G22 - G12 * G12;
-                const bool fb = lvl_active && !(det > 1e-6f * det0);
-                if (wave_any(fb)) {
-                    float C1 = 0.f, C2 = 0.f;
-#pragma unroll
+                // step = A^-1 (-sum w r phi) with phi = (g, -T', -1)
+                V[0] = -q0;
+                V[1] = -q1;
+                V[2] = q2;
+                V[3] = q3;
+                float x[4];
+                ldl4(A, V, x);
+                // the d rows of the model's system carry (1 + m) = ga / Ts; the unscaled system
+                // solved here gives (1 + m) d
+                const float k = ga / Ts;
+                sx = x[0] / k;
+                sy = x[1] / k;
+                sa = x[2];
+                sb = x[3];
+            } else {
+                float G11, G12, G22, B1 = 0.f, B2 = 0.f, det;
+                if (P.mode == ROBUST_L2) {
+    #pragma unroll
                     for (int j = 0; j < PPL; ++j) {
-                        C1 = fmaf(RES[j], GX[j], C1);
-                        C2 = fmaf(RES[j], GY[j], C2);
+                        B1 = fmaf(RES[j], GX[j], B1);
+                        B2 = fmaf(RES[j], GY[j], B2);
                     }
                     float z0 = 0.f, z1 = 0.f, z2 = 0.f;
-                    group_sum5<LPP>(C1, C2, z0, z1, z2);
-                    if (fb) {
-                        G11 = a;
-                        G12 = b;
-                        G22 = c;
-                        B1 = C1;
-                        B2 = C2;
-                        det = det0;
+                    group_sum5<LPP>(B1, B2, z0, z1, z2);
+                    G11 = a;
+                    G12 = b;
+                    G22 = c;
+                    det = det0;
+                } else {
+                    G11 = 0.f;
+                    G12 = 0.f;
+                    G22 = 0.f;
+                    if (P.mode == ROBUST_HAMPEL) {
+    #pragma unroll
+                        for (int j = 0; j < PPL; ++j) {
+                            const float w = hampel_weight(RES[j], P.cs2, P.cmid);
+                            const float wgx = w * GX[j], wgy = w * GY[j];
+                            G11 = fmaf(wgx, GX[j], G11);
+                            G12 = fmaf(wgx, GY[j], G12);
+                            G22 = fmaf(wgy, GY[j], G22);
+                            B1 = fmaf(RES[j], wgx, B1);
+                            B2 = fmaf(RES[j], wgy, B2);
+                        }
+                    } else {
+    #pragma unroll
+                        for (int j = 0; j < PPL; ++j) {
+                            const float w = (fabsf(RES[j]) <= P.s1) ? 1.f : 0.f;
+                            const float wgx = w * GX[j], wgy = w * GY[j];
+                            G11 = fmaf(wgx, GX[j], G11);
+                            G12 = fmaf(wgx, GY[j], G12);
+                            G22 = fmaf(wgy, GY[j], G22);
+                            B1 = fmaf(RES[j], wgx, B1);
+                            B2 = fmaf(RES[j], wgy, B2);
+                        }
+                    }
+                    group_sum5<LPP>(G11, G12, G22, B1, B2);
+                    det = G11 * G22 - G12 * G12;
+                    const bool fb = lvl_active && !(det > 1e-6f * det0);
+                    if (wave_any(fb)) {
+                        float C1 = 0.f, C2 = 0.f;
+    #pragma unroll
+                        for (int j = 0; j < PPL; ++j) {
+                            C1 = fmaf(RES[j], GX[j], C1);
+                            C2 = fmaf(RES[j], GY[j], C2);
+                        }
+                        float z0 = 0.f, z1 = 0.f, z2 = 0.f;
+                        group_sum5<LPP>(C1, C2, z0, z1, z2);
+                        if (fb) {
+                            G11 = a;
+                            G12 = b;
+                            G22 = c;
+                            B1 = C1;
+                            B2 = C2;
+                            det = det0;
+                        }
                     }
                 }
+                const float inv = __builtin_amdgcn_rcpf(det);
+                sx = (G12 * B2 - G22 * B1) * inv;
+                sy = (G12 * B1 - G11 * B2) * inv;
             }
-            const float inv = __builtin_amdgcn_rcpf(det);
-            const float sx = (G12 * B2 - G22 * B1) * inv;
-            const float sy = (G12 * B1 - G11 * B2) * inv;
             if (lvl_active) {
                 ++it_total;
-                if (!(isfinite(sx) && isfinite(sy))) {
+                if (!(isfinite(sx) && isfinite(sy) && isfinite(sa) && isfinite(sb))) {
                     status = DGF_ST_NOT_CONVERGED;
                     ux = __builtin_nanf("");
                     uy = __builtin_nanf("");
@@ -312,11 +454,21 @@ __global__ __launch_bounds__(256) void k_track_run(TrackParams P)
                 } else {
                     dX += sx;
                     dY += sy;
+                    if constexpr (IM) {
+                        ga += sa;
+                        gb += sb;
+                    }
                     if (sx * sx + sy * sy < eps2) {
                         lvl_conv = true;
                         lvl_active = false;
                     }
                 }
+            }
+        }
+        if constexpr (IM) {
+            if (active && !flat) { // back to (m, c), which carry over to the next level
+                im_m = ga / Ts - 1.f;
+                im_c = gb - ga * Tm / Ts;
             }
         }
         if (l > 0) {
@@ -333,7 +485,8 @@ __global__ __launch_bounds__(256) void k_track_run(TrackParams P)
         if (status < 0) {
             ux = gX + dX;
             uy = gY + dY;
-            if (!conv0) {
+            if (!conv0 || (IM && !(1.f + im_m >= 0.5f && 1.f + im_m <= 2.f))) {
+                // (illumination model: a gain outside [1/2, 2] is a contrast change, not a match)
                 status = DGF_ST_NOT_CONVERGED;
             } else {
                 const float qx = px + ux, qy = py + uy;
@@ -350,14 +503,14 @@ __global__ __launch_bounds__(256) void k_track_run(TrackParams P)
     } // work loop
 }
 
-template <int LPP, int SEG, int R, int TP, typename PixT>
+template <int LPP, int SEG, int R, int TP, typename PixT, bool IM>
 hipError_t launch_track_run_t(const TrackParams &P, int wpb, hipStream_t st)
 {
     constexpr int PPW = 64 / LPP;
     const int64_t waves = P.npairs ? P.grid_waves : (P.n + PPW - 1) / PPW;
     const int64_t blocks = (waves + wpb - 1) / wpb;
     const size_t lds = (size_t)wpb * PPW * P.tile_floats * sizeof(float);
-    hipLaunchKernelGGL((k_track_run<LPP, SEG, R, TP, PixT>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st, P);
+    hipLaunchKernelGGL((k_track_run<LPP, SEG, R, TP, PixT, IM>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st, P);
     return hipGetLastError();
 }
 

@@ -6,7 +6,9 @@ namespace dgf {
 hipError_t launch_track_run_u8(const TrackParams &P, int lpp, int s, int wpb, hipStream_t st)
 {
 #define DGF_CASE(L_, SEG_, R_, TP_, S_, X_)                                                                            \
-    if (lpp == L_ && s == S_) return launch_track_run_t<L_, SEG_, R_, TP_, X_>(P, wpb, st);
+    if (lpp == L_ && s == S_)                                                                                          \
+        return P.illum ? launch_track_run_t<L_, SEG_, R_, TP_, X_, true>(P, wpb, st)                                   \
+                       : launch_track_run_t<L_, SEG_, R_, TP_, X_, false>(P, wpb, st);
     DGF_TRACK_RUN_SHAPES(DGF_CASE, uint8_t)
 #undef DGF_CASE
     return hipErrorInvalidValue;

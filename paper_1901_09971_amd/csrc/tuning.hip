@@ -96,6 +96,7 @@ void fill_track_constants(TrackParams &P, const dgf_track_opts &o, int support)
 {
     P.s1 = o.sigma1;
     P.s2 = o.sigma2;
+    P.illum = (o.flags & DGF_TRACK_ILLUM) ? 1 : 0;
     if (isinf(o.sigma1)) {
         P.mode = ROBUST_L2; // |r| <= inf always: every weight is 1
         P.cmid = 0.0f;

@@ -117,8 +117,10 @@ def test_argument_validation_before_launch():
     assert track(n=-1) == -1
     assert track(pts=None) == -1 and track(flow=None) == -1 and track(st=None) == -1
     assert track(wsp=None) == -5 and track(wsb=ws - 1) == -5
-    o = _lib.DgfTrackOpts(8, 32, 1e-2, 1e-4, 6.5, 1)
+    o = _lib.DgfTrackOpts(8, 32, 1e-2, 1e-4, 6.5, 2)  # unknown flag
     assert track(opts=ctypes.pointer(o)) == -3
+    o = _lib.DgfTrackOpts(8, 32, 1e-2, 1e-4, 6.5, _lib.DGF_TRACK_ILLUM)  # no row-run kernel for 13x13
+    assert track(s=13, opts=ctypes.pointer(o)) == -3
     o = _lib.DgfTrackOpts(float("nan"), 32, 1e-2, 1e-4, 6.5, 0)
     assert track(opts=ctypes.pointer(o)) == -1
     # n = 0 validates and launches nothing

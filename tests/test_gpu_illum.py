@@ -1,0 +1,123 @@
+"""GPU parity of the illumination-model tracker (DGF_TRACK_ILLUM: per-point gain and offset with
+the flow, a 4x4 system per iteration) against the FP64 oracle, through the C ABI.  Bar: flow
+within 1e-3 px on points converged on both sides; statuses agree on nearly all points."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1901_09971_amd as dgf
+from paper_1901_09971_amd import synth
+from paper_1901_09971_amd._lib import DgfError
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-3
+
+
+def _illum_u8(I1, gain, offset):
+    return np.clip(np.rint(gain * I1.astype(np.float64) + offset), 0, 255).astype(np.uint8)
+
+
+def _run(I0, I1, pts32, L, s, iters, min_agree, **kw):
+    t0, t1 = torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda()
+    P = torch.from_numpy(pts32).cuda()
+    flow, st = dgf.track(t0, t1, P, L, s, iters, opts=dgf.TrackOpts(illum=True, **kw))
+    torch.cuda.synchronize()
+    g_flow, g_st = flow.cpu().numpy().astype(np.float64), st.cpu().numpy()
+    o_flow, o_st = oracle.track(I0, I1, pts32.astype(np.float64), L, s, iters, illum=True, **kw)
+    both = (g_st == 0) & (o_st == 0)
+    agree = float(np.mean(g_st == o_st))
+    err = float(np.abs(g_flow[both] - o_flow[both]).max()) if both.any() else 0.0
+    print(f"n={len(g_st)} both_conv={int(both.sum())} agree={agree:.5f} max_err={err:.2e} "
+          f"gpu_st={np.bincount(g_st, minlength=4)} orc_st={np.bincount(o_st, minlength=4)}", flush=True)
+    assert err <= TOL, err
+    assert agree >= min_agree, agree
+    return g_flow, g_st, o_flow, o_st
+
+
+def test_translation_256x128_with_gain_and_offset():
+    I0, I1, gt = synth.translation_256x128()
+    I1 = _illum_u8(I1, 0.8, 30.0)
+    pts = oracle.detect(I0, 9, 8)[0].astype(np.float32)
+    g_flow, g_st, _, _ = _run(I0, I1, pts, 3, 9, 10, 0.98)
+    assert np.mean(g_st == 0) > 0.9
+    assert np.median(np.linalg.norm(g_flow[g_st == 0] - gt, axis=1)) < 0.1
+    # the plain tracker under the same change does worse
+    f, s = dgf.track(torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda(), torch.from_numpy(pts).cuda(), 3, 9, 10)
+    f, s = f.cpu().numpy(), s.cpu().numpy()
+    plain_ok = (s == 0) & (np.linalg.norm(f - gt, axis=1) < 0.25)
+    ill_ok = (g_st == 0) & (np.linalg.norm(g_flow - gt, axis=1) < 0.25)
+    assert ill_ok.sum() > plain_ok.sum()
+
+
+def test_driving_1242x375_with_gain_and_offset():
+    I0, I1, _, _ = synth.driving_1242x375()
+    I1 = _illum_u8(I1, 1.15, -12.0)
+    pts = oracle.detect(I0, 9, 5)[0].astype(np.float32)
+    _run(I0, I1, pts, 5, 21, 20, 0.97)
+
+
+@pytest.mark.parametrize("s", [5, 7, 9, 11, 15, 21])
+def test_supports_float_frames(s):
+    I0, I1, _ = synth.noise_translation_pair(200, 140, seed=3, shift=(1.7, -2.4), dtype="f32")
+    I1 = (0.9 * I1 + 20.0).astype(np.float32)
+    pts = oracle.detect(np.clip(np.rint(I0), 0, 255).astype(np.uint8), 9, 9)[0].astype(np.float32)
+    _run(I0, I1, pts, 3, s, 15, 0.97)
+
+
+@pytest.mark.parametrize("tune", ["16,2,2,0", "32,1,3,0", "64,4,2,0", "64,1,2,1"])
+def test_launch_shapes(tune, monkeypatch):
+    monkeypatch.setenv("DGF_TUNE", tune)
+    I0, I1, _, _ = synth.layered_pair(320, 240, seed=2, max_disp=40.0)
+    I1 = _illum_u8(I1, 1.1, -5.0)
+    pts = oracle.detect(I0, 9, 7)[0].astype(np.float32)
+    _run(I0, I1, pts, 4, 21, 20, 0.97)
+
+
+def test_exact_gain_offset_integer_translation():
+    W, H, t, m0, c0 = 160, 120, (3, -2), 0.25, -14.0
+    I0 = synth.smoothed_noise(np.random.default_rng(1), W, H, 2.0)
+    I1 = (1.0 + m0) * I0 + c0
+    I1[max(t[1], 0):H + min(t[1], 0), max(t[0], 0):W + min(t[0], 0)] = \
+        (1.0 + m0) * I0[max(-t[1], 0):H - max(t[1], 0), max(-t[0], 0):W - max(t[0], 0)] + c0
+    rng = np.random.default_rng(2)
+    pts = np.stack([rng.uniform(25, W - 26, 40), rng.uniform(25, H - 26, 40)], 1).astype(np.float32)
+    f, st = dgf.track(torch.from_numpy(I0.astype(np.float32)).cuda(), torch.from_numpy(I1.astype(np.float32)).cuda(),
+                      torch.from_numpy(pts).cuda(), 2, 9, 60, opts=dgf.TrackOpts(illum=True, eps_fine=1e-5, min_eig=0.0))
+    f, st = f.cpu().numpy(), st.cpu().numpy()
+    assert np.all(st == 0)
+    assert np.max(np.abs(f - np.array(t, np.float64))) < 1e-3
+
+
+def test_batched_equals_plain():
+    pairs = []
+    for i, (W, H) in enumerate([(640, 480), (320, 240), (1242, 375)]):
+        I0, I1, _, _ = synth.layered_pair(W, H, seed=50 + i, max_disp=60.0 * W / 1242.0)
+        pairs.append((torch.from_numpy(I0).cuda(), torch.from_numpy(_illum_u8(I1, 0.9, 14.0)).cuda(), 9, 6))
+    opts = dgf.TrackOpts(illum=True)
+    plan = dgf.Batch(pairs, 5, 21, 20, opts=opts)
+    P, F, S = plan.run()
+    for i, (a, b, w, d) in enumerate(pairs):
+        p = dgf.detect(a, w, d)
+        f, s = dgf.track(a, b, p, 5, 21, 20, opts=opts)
+        lo, hi = plan.offsets[i], plan.offsets[i + 1]
+        assert torch.equal(S[lo:hi], s)
+        fin = torch.isfinite(f)
+        assert torch.equal(F[lo:hi][fin], f[fin])
+    with pytest.raises(DgfError):
+        plan.backward(torch.zeros_like(F))
+    plan.close()
+
+
+def test_unsupported_support_and_backward():
+    I0, I1, _ = synth.noise_translation_pair(64, 48, seed=1, dtype="f32")
+    t0, t1 = torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda()
+    P = torch.tensor([[30.0, 20.0]], device="cuda")
+    with pytest.raises(DgfError) as e:
+        dgf.track(t0, t1, P, 2, 13, 10, opts=dgf.TrackOpts(illum=True))
+    assert e.value.code == -3
+    f, s = dgf.track(t0, t1, P, 2, 9, 10, opts=dgf.TrackOpts(illum=True))
+    with pytest.raises(DgfError) as e:
+        dgf.track_backward(t0, t1, P, 9, f, s, torch.ones_like(f), torch.zeros_like(t0), torch.zeros_like(t1),
+                           opts=dgf.TrackOpts(illum=True))
+    assert e.value.code == -3
