@@ -166,6 +166,58 @@ def batched_vs_plain(reps: int):
             "workload": "batch64_mixed: 16 each of 1242x375, 1224x370, 640x480, 320x240, strides {3,5,8}"}
 
 
+FLOPS_PER_PIXEL_ITER_ILLUM = 39    # illumination model: bilinear 7, residual 2, weight 3, w*(gx, gy, T') 3,
+                                   # the ten sums of the 4x4 matrix 16, the four right-hand sums 8
+
+
+def illumination(steps: int, warmup: int):
+    """The benchmark pair with the illumination model (DGF_TRACK_ILLUM) and I1 changed by a gain of
+    1.15 and an offset of -12 (rounded to uint8): detect + pyramids + track, HIP events."""
+    import numpy as np
+    import torch
+
+    import paper_1901_09971_amd as dgf
+    from paper_1901_09971_amd import synth
+
+    w = WORKLOAD
+    I0n, I1n, _, _ = synth.driving_1242x375()
+    I1n = np.clip(np.rint(1.15 * I1n.astype(np.float64) - 12.0), 0, 255).astype(np.uint8)
+    dev = torch.device("cuda", 0)
+    I0, I1 = torch.from_numpy(I0n).to(dev), torch.from_numpy(I1n).to(dev)
+    N = dgf.detect_count(w["W"], w["H"], w["window"], w["stride"])
+    pts = torch.empty((N, 2), dtype=torch.float32, device=dev)
+    flow = torch.empty((N, 2), dtype=torch.float32, device=dev)
+    status = torch.empty(N, dtype=torch.uint8, device=dev)
+    its = torch.empty(N, dtype=torch.int32, device=dev)
+    ws = torch.empty(dgf.track_workspace_bytes(w["W"], w["H"], w["levels"], 0), dtype=torch.uint8, device=dev)
+    opts = dgf.TrackOpts(illum=True)
+    dgf.detect(I0, w["window"], w["stride"], out=pts)
+    dgf.track_pyramids(I0, I1, w["levels"], ws)
+    dgf.track_run(I0, I1, pts, w["levels"], w["support"], w["iters"], ws, flow, status, its, opts=opts)
+    torch.cuda.synchronize()
+    pix_iters = int(its.to(torch.int64).sum().item()) * w["support"] ** 2
+    st_counts = np.bincount(status.cpu().numpy(), minlength=4).tolist()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    for k in range(warmup + steps):
+        e = ev[k - warmup] if k >= warmup else None
+        if e: e[0].record()
+        dgf.detect(I0, w["window"], w["stride"], out=pts)
+        if e: e[1].record()
+        dgf.track_pyramids(I0, I1, w["levels"], ws)
+        if e: e[2].record()
+        dgf.track_run(I0, I1, pts, w["levels"], w["support"], w["iters"], ws, flow, status, opts=opts)
+        if e: e[3].record()
+    torch.cuda.synchronize()
+    ms_step = sum(e[0].elapsed_time(e[3]) for e in ev) / steps
+    t_track = sum(e[2].elapsed_time(e[3]) for e in ev) / steps
+    achieved = pix_iters * FLOPS_PER_PIXEL_ITER_ILLUM / (t_track * 1e-3) / 1e12
+    return {"workload": "driving_1242x375, I1 gain 1.15 offset -12, illumination model", "points": N,
+            "points_per_s": N / (ms_step * 1e-3), "ms_per_step": ms_step, "track_ms": t_track,
+            "iterations": pix_iters // w["support"] ** 2, "status_counts": st_counts,
+            "flops_per_pixel_iteration": FLOPS_PER_PIXEL_ITER_ILLUM, "achieved_tflops": achieved,
+            "frac": achieved / PEAK_FP32_VALU_TFLOPS}
+
+
 DENSITY = dict(name="density_2048x1024x4", W=2048, H=1024, pairs=4, window=9, stride=2, levels=6, support=21,
                iters=20)
 
@@ -262,6 +314,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in launch-shape heuristic")
     ap.add_argument("--batch-reps", type=int, default=10)
     ap.add_argument("--no-density", action="store_true", help="skip the 4 x 2048x1024 density stress")
+    ap.add_argument("--no-illum", action="store_true", help="skip the illumination-model measurement")
     ap.add_argument("--density-reps", type=int, default=3)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
@@ -392,6 +445,8 @@ def main():
     }
     if not args.no_batch:
         out["batched"] = batched_vs_plain(args.batch_reps)
+    if not args.no_illum:
+        out["illumination"] = illumination(args.steps, args.warmup)
     if not args.no_density:
         out["density"] = density_stress(args.density_reps)
     if not args.no_cpu_baseline:
