@@ -68,7 +68,11 @@ def _load():
     lib.or_track.argtypes = [P, P, i32, i32, i32, i64, P, i64, i32, i32, i32, f64, f64, f64, f64, f64,
                              i32, P, P, P, P, i32]
     lib.or_track.restype = i32
-    lib.or_track_grad.argtypes = [P, P, i32, i32, P, i64, i32, f64, f64, P, P, P, P, P]
+    lib.or_track_grad.argtypes = [P, P, i32, i32, P, i64, i32, f64, f64, P, P, P, P, P, P]
+    lib.or_detect_f64.argtypes = [P, i32, i32, i64, i32, i32, P, P]
+    lib.or_detect_f64.restype = i64
+    lib.or_detect_grad.argtypes = [P, i32, i32, i64, i32, i32, P, P, P]
+    lib.or_detect_grad.restype = i32
     lib.or_track_grad.restype = i32
     _lib = lib
     return lib
@@ -196,10 +200,37 @@ def track(I0: np.ndarray, I1: np.ndarray, points: np.ndarray, levels: int, suppo
     return out
 
 
+def detect_real(img: np.ndarray, window: int, stride: int):
+    """The detector on a real-valued image.  Returns (points[N,2] float64, sel[N] uint8)."""
+    a = np.ascontiguousarray(img, dtype=np.float64)
+    H, W = a.shape
+    n = max(detect_count(W, H, window, stride), 0)
+    pts = np.zeros((max(n, 1), 2), np.float64)
+    sel = np.zeros(max(n, 1), np.uint8)
+    rc = _load().or_detect_f64(_ptr(a), W, H, W, window, stride, _ptr(pts), _ptr(sel))
+    if rc < 0:
+        raise ValueError(f"or_detect_f64 failed: {rc}")
+    return pts[:n], sel[:n]
+
+
+def detect_grad(img: np.ndarray, window: int, stride: int, sel: np.ndarray, dpoints: np.ndarray) -> np.ndarray:
+    """dL/dI of the detected points for upstream gradient dpoints = dL/dp (real-valued image)."""
+    a = np.ascontiguousarray(img, dtype=np.float64)
+    H, W = a.shape
+    s = np.ascontiguousarray(sel, dtype=np.uint8)
+    d = np.ascontiguousarray(dpoints, dtype=np.float64).reshape(-1, 2)
+    dI = np.zeros((H, W), np.float64)
+    rc = _load().or_detect_grad(_ptr(a), W, H, W, window, stride, _ptr(s), _ptr(d), _ptr(dI))
+    if rc != 0:
+        raise ValueError(f"or_detect_grad failed: {rc}")
+    return dI
+
+
 def track_grad(I0: np.ndarray, I1: np.ndarray, points: np.ndarray, support: int, flow: np.ndarray,
-               status: np.ndarray, dflow: np.ndarray, sigma1=DEFAULTS["sigma1"], sigma2=DEFAULTS["sigma2"]):
-    """Implicit gradient (dL/dI0, dL/dI1) at the converged level-0 fixed point, for upstream
-    gradient dflow = dL/du (points with status != CONVERGED contribute nothing)."""
+               status: np.ndarray, dflow: np.ndarray, sigma1=DEFAULTS["sigma1"], sigma2=DEFAULTS["sigma2"],
+               return_dpoints: bool = False):
+    """Implicit gradient (dL/dI0, dL/dI1[, dL/dp]) at the converged level-0 fixed point, for
+    upstream gradient dflow = dL/du (points with status != CONVERGED contribute nothing)."""
     a0 = np.ascontiguousarray(I0, dtype=np.float64)
     a1 = np.ascontiguousarray(I1, dtype=np.float64)
     H, W = a0.shape
@@ -209,8 +240,11 @@ def track_grad(I0: np.ndarray, I1: np.ndarray, points: np.ndarray, support: int,
     df = np.ascontiguousarray(dflow, dtype=np.float64).reshape(-1, 2)
     dI0 = np.zeros((H, W), np.float64)
     dI1 = np.zeros((H, W), np.float64)
+    dp = np.zeros((pts.shape[0], 2), np.float64) if return_dpoints else None
     rc = _load().or_track_grad(_ptr(a0), _ptr(a1), W, H, _ptr(pts), pts.shape[0], support, sigma1, sigma2,
-                               _ptr(fl), _ptr(st), _ptr(df), _ptr(dI0), _ptr(dI1))
+                               _ptr(fl), _ptr(st), _ptr(df), _ptr(dI0), _ptr(dI1), _ptr(dp))
     if rc != 0:
         raise ValueError(f"or_track_grad failed: {rc}")
+    if return_dpoints:
+        return dI0, dI1, dp
     return dI0, dI1

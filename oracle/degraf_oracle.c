@@ -136,6 +136,101 @@ int64_t or_detect(const uint8_t *img, int W, int H, int64_t pitch, int win, int 
     return N;
 }
 
+/*
+ * The same detector on a real-valued image (double, row pitch in elements): Eq. (1) and Eq. (2)
+ * with real sums and m the window maximum; the larger sum wins, a tie keeps the positive centroid.
+ * Used to define, and check by finite differences, the gradient of the points w.r.t. the image.
+ */
+int64_t or_detect_f64(const double *img, int W, int H, int64_t pitch, int win, int stride, double *pts,
+                      uint8_t *sel)
+{
+    if (!img || !pts || win <= 0 || stride <= 0 || W <= 0 || H <= 0 || pitch < W) return OR_ERR_ARG;
+    int64_t N = or_detect_count(W, H, win, stride);
+    const int nx = N ? (W - win) / stride + 1 : 1;
+    for (int64_t n = 0; n < N; ++n) {
+        const int x0 = (int)(n % nx) * stride, y0 = (int)(n / nx) * stride;
+        double m = -INFINITY;
+        for (int i = 0; i < win; ++i)
+            for (int j = 0; j < win; ++j) m = fmax(m, img[(int64_t)(y0 + i) * pitch + x0 + j]);
+        double sp = 0, ip = 0, jp = 0, sn = 0, in = 0, jn = 0;
+        for (int i = 0; i < win; ++i)
+            for (int j = 0; j < win; ++j) {
+                double v = img[(int64_t)(y0 + i) * pitch + x0 + j], vn = 1.0 + m - v;
+                sp += v;
+                ip += i * v;
+                jp += j * v;
+                sn += vn;
+                in += i * vn;
+                jn += j * vn;
+            }
+        int neg = sn > sp;
+        pts[2 * n + 0] = x0 + (neg ? jn / sn : jp / sp);
+        pts[2 * n + 1] = y0 + (neg ? in / sn : ip / sp);
+        if (sel) sel[n] = (uint8_t)neg;
+    }
+    return N;
+}
+
+/*
+ * Gradient of the detected points w.r.t. the image (the centroid ratios of Eq. 1-2 are smooth in
+ * the pixel values away from ties): for point n with upstream gradient dpoints[n] = dL/dp, ADDS
+ *   dI[q] += dL/dp . dp/dI[q]
+ * over its window.  Positive centroid C = sum c v / S: dC/dv(q) = (c(q) - C) / S.  Negative
+ * centroid with weights 1 + m - v and m the window maximum (taken at the first maximal pixel q*
+ * in row-major order): dC/dv(q) = (-(c(q) - C) + [q = q*] sum_q' (c(q') - C)) / S_neg.
+ * sel gives the centroid each point took (as or_detect_f64 returns it).
+ */
+int or_detect_grad(const double *img, int W, int H, int64_t pitch, int win, int stride, const uint8_t *sel,
+                   const double *dpoints, double *dI)
+{
+    if (!img || !sel || !dpoints || !dI || win <= 0 || stride <= 0 || W <= 0 || H <= 0 || pitch < W) return OR_ERR_ARG;
+    int64_t N = or_detect_count(W, H, win, stride);
+    const int nx = N ? (W - win) / stride + 1 : 1;
+    for (int64_t n = 0; n < N; ++n) {
+        const int x0 = (int)(n % nx) * stride, y0 = (int)(n / nx) * stride;
+        const double lx = dpoints[2 * n], ly = dpoints[2 * n + 1];
+        double m = -INFINITY;
+        int qi = 0, qj = 0;
+        for (int i = 0; i < win; ++i)
+            for (int j = 0; j < win; ++j) {
+                double v = img[(int64_t)(y0 + i) * pitch + x0 + j];
+                if (v > m) {
+                    m = v;
+                    qi = i;
+                    qj = j;
+                }
+            }
+        double S = 0, Ci = 0, Cj = 0;
+        for (int i = 0; i < win; ++i)
+            for (int j = 0; j < win; ++j) {
+                double v = img[(int64_t)(y0 + i) * pitch + x0 + j];
+                double wv = sel[n] ? 1.0 + m - v : v;
+                S += wv;
+                Ci += i * wv;
+                Cj += j * wv;
+            }
+        Ci /= S;
+        Cj /= S;
+        for (int i = 0; i < win; ++i)
+            for (int j = 0; j < win; ++j) {
+                double di, dj; /* d(Ci, Cj) / dv(i, j) */
+                if (!sel[n]) {
+                    di = (i - Ci) / S;
+                    dj = (j - Cj) / S;
+                } else {
+                    di = -(i - Ci) / S;
+                    dj = -(j - Cj) / S;
+                    if (i == qi && j == qj) { /* the maximum raises every weight */
+                        di += win * win * (0.5 * (win - 1) - Ci) / S;
+                        dj += win * win * (0.5 * (win - 1) - Cj) / S;
+                    }
+                }
+                dI[(int64_t)(y0 + i) * pitch + x0 + j] += lx * dj + ly * di;
+            }
+    }
+    return OR_OK;
+}
+
 /* ------------------------------------------------------------------------------------------ */
 /* Image pyramid (the tracker is pyramidal; the paper gives no filter, this is the reading)   */
 /* ------------------------------------------------------------------------------------------ */
@@ -764,6 +859,16 @@ static void bilinear_taps(int W, int H, double x, double y, int64_t idx[4], doub
     *fy_out = fy;
 }
 
+/* Gradient of the bilinear interpolant (inside the cell that holds (x, y); clamped taps, so it
+ * vanishes across the replicated border). */
+static void bilinear_grad(const double *I, int W, int H, double x, double y, double g[2])
+{
+    int64_t idx[4]; double wt[4]; int cx[4], cy[4]; double fx, fy;
+    bilinear_taps(W, H, x, y, idx, wt, cx, cy, &fx, &fy);
+    g[0] = (1.0 - fy) * (I[idx[1]] - I[idx[0]]) + fy * (I[idx[3]] - I[idx[2]]);
+    g[1] = (1.0 - fx) * (I[idx[2]] - I[idx[0]]) + fx * (I[idx[3]] - I[idx[1]]);
+}
+
 /*
  * For every point with status CONVERGED, with upstream gradient lambda = dflow[i] (= dL/du):
  *   J = dF/du = sum_k psi'(r_k) g_k (grad B(I1, p + k + u))^T        (2x2, not symmetric)
@@ -775,16 +880,22 @@ static void bilinear_taps(int W, int H, double x, double y, int64_t idx[4], doub
  * difference of the tap weights of the two shifted samples, halved.  Only the level-0 images
  * enter: coarser levels decide which fixed point is reached but not its local dependence.
  * Results are ADDED to dI0 and dI1 ([H][W] doubles).  I0, I1 are double images, pitch W.
+ * dpoints (nullable, [n][2]) receives dL/dp, the gradient w.r.t. the point positions (zero for
+ * points that contribute nothing).
  */
 int or_track_grad(const double *I0, const double *I1, int W, int H, const double *pts, int64_t n, int support,
                   double sigma1, double sigma2, const double *flow, const uint8_t *status,
-                  const double *dflow, double *dI0, double *dI1)
+                  const double *dflow, double *dI0, double *dI1, double *dpoints)
 {
     if (!I0 || !I1 || W <= 0 || H <= 0 || support < 1 || (support % 2) == 0) return OR_ERR_ARG;
     if (n > 0 && (!pts || !flow || !status || !dflow || !dI0 || !dI1)) return OR_ERR_ARG;
     const int r = support / 2;
 
     for (int64_t i = 0; i < n; ++i) {
+        if (dpoints) {
+            dpoints[2 * i] = 0.0;
+            dpoints[2 * i + 1] = 0.0;
+        }
         if (status[i] != OR_ST_CONVERGED) continue;
         const double px = pts[2 * i], py = pts[2 * i + 1];
         const double ux = flow[2 * i], uy = flow[2 * i + 1];
@@ -814,6 +925,36 @@ int or_track_grad(const double *I0, const double *I1, int W, int H, const double
         if (!(det != 0.0) || !isfinite(det)) continue;
         const double mux = (J11 * lx - J10 * ly) / det;
         const double muy = (J00 * ly - J01 * lx) / det;
+
+        if (dpoints) {
+            /* The flow also depends on the point: dF/dp = J + K with
+             *   K = sum_k [ -psi'(r_k) g_k (grad B(I0, p + k))^T + psi(r_k) dG/dx(p + k) ],
+             * G(x) = central differences of B(I0, .) at x, so dG/dx has rows
+             * (grad B(I0, x + e_x) - grad B(I0, x - e_x)) / 2 and the same along y; then
+             * du/dp = -J^-1 (J + K) and dL/dp = -lambda - K^T mu. */
+            double K00 = 0.0, K01 = 0.0, K10 = 0.0, K11 = 0.0;
+            for (int ky = -r; ky <= r; ++ky)
+                for (int kx = -r; kx <= r; ++kx) {
+                    double x = px + kx, y = py + ky;
+                    double T = or_bilinear(I0, W, H, x, y);
+                    double g0 = 0.5 * (or_bilinear(I0, W, H, x + 1.0, y) - or_bilinear(I0, W, H, x - 1.0, y));
+                    double g1 = 0.5 * (or_bilinear(I0, W, H, x, y + 1.0) - or_bilinear(I0, W, H, x, y - 1.0));
+                    double Jv = or_bilinear(I1, W, H, x + ux, y + uy);
+                    double ps = or_psi(Jv - T, sigma1, sigma2), dp = or_dpsi(Jv - T, sigma1, sigma2);
+                    double gT[2], gxp[2], gxm[2], gyp[2], gym[2];
+                    bilinear_grad(I0, W, H, x, y, gT);
+                    bilinear_grad(I0, W, H, x + 1.0, y, gxp);
+                    bilinear_grad(I0, W, H, x - 1.0, y, gxm);
+                    bilinear_grad(I0, W, H, x, y + 1.0, gyp);
+                    bilinear_grad(I0, W, H, x, y - 1.0, gym);
+                    K00 += -dp * g0 * gT[0] + ps * 0.5 * (gxp[0] - gxm[0]);
+                    K01 += -dp * g0 * gT[1] + ps * 0.5 * (gxp[1] - gxm[1]);
+                    K10 += -dp * g1 * gT[0] + ps * 0.5 * (gyp[0] - gym[0]);
+                    K11 += -dp * g1 * gT[1] + ps * 0.5 * (gyp[1] - gym[1]);
+                }
+            dpoints[2 * i + 0] = -lx - (K00 * mux + K10 * muy);
+            dpoints[2 * i + 1] = -ly - (K01 * mux + K11 * muy);
+        }
 
         for (int ky = -r; ky <= r; ++ky)
             for (int kx = -r; kx <= r; ++kx) {
