@@ -184,10 +184,28 @@ int dgf_track(const dgf_image *I0, const dgf_image *I1, const float *points, int
  *   dI0, dI1    : float images of the same size, with the row pitch of I0 and I1 respectively;
  *                 ACCUMULATED into (zero them first), with device float atomics, so the order
  *                 of additions (and the last bits) is not deterministic.
- *   opts        : the tracker constants used in the forward call (nullable = defaults). */
+ *   opts        : the tracker constants used in the forward call (nullable = defaults).
+ *   dpoints     : nullable, float[n][2]: WRITTEN with dL/dp, the gradient w.r.t. the point
+ *                 positions (the template moves with the point): with
+ *                 K = sum_k [-psi'(r_k) g_k grad I0(p+k)^T + psi(r_k) dg_k/dp], du/dp = -J^-1 (J + K)
+ *                 and dL/dp = -dflow - K^T mu; 0 for points that contribute nothing. */
 int dgf_track_backward(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t support,
                        const dgf_track_opts *opts, const float *flow, const uint8_t *status, const float *dflow,
-                       float *dI0, float *dI1, void *stream);
+                       float *dI0, float *dI1, float *dpoints, void *stream);
+
+/* Gradient through detection (Section 2 Eq. 1-2, the centroid ratios taken as functions of real
+ * pixel values, evaluated at the uint8 image the points were detected on): ADDS
+ *   dI0[q] += dpoints[n] . d p_n / d I0[q]
+ * over every window n.  Positive centroid C = sum c I / S: dC/dI(q) = (c(q) - C) / S; negative
+ * centroid with weights 1 + m - I (m = window maximum, at its first maximal pixel q* in row-major
+ * order): dC/dI(q) = (-(c(q) - C) + [q = q*] sum_q' (c(q') - C)) / S_neg.
+ *   I0      : the DGF_U8 frame given to dgf_detect, window / stride as there
+ *   sel     : uint8[n], the selection bits dgf_detect returned;  dpoints: float[n][2] = dL/dp
+ *   n       : must equal dgf_detect_count(width, height, window, stride)
+ *   dI0     : float map, row pitch dI0_pitch floats (>= width); accumulated with device float
+ *             atomics (windows overlap when stride < window). */
+int dgf_detect_backward(const dgf_image *I0, int32_t window, int32_t stride, const uint8_t *sel,
+                        const float *dpoints, int64_t n, float *dI0, int64_t dI0_pitch, void *stream);
 
 /* ---- batched form: many pairs of uneven size and point count in one pass -------------------- */
 

@@ -4,5 +4,6 @@ The compute path is the gfx950 HIP library ``libdegraf_flow.so`` behind the C AB
 ``include/degraf_flow.h``; this package only marshals tensors and streams into it.  Importing the
 package does not load the library; the first call does, and raises if it is not built.
 """
-from .api import (Batch, TrackFn, TrackOpts, autotune, get_tuning, set_tuning, detect, detect_count, pyramid, pyramid_layout, track,  # noqa: F401
-                  track_backward, track_pyramids, track_run, track_workspace_bytes)
+from .api import (Batch, DetectFn, TrackFn, TrackOpts, autotune, detect, detect_backward, detect_count,  # noqa: F401
+                  get_tuning, pyramid, pyramid_layout, set_tuning, track, track_backward, track_pyramids, track_run,
+                  track_workspace_bytes)

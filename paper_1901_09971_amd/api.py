@@ -158,9 +158,10 @@ def track_run(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, levels: 
 
 def track_backward(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, support: int, flow: torch.Tensor,
                    status: torch.Tensor, dflow: torch.Tensor, dI0: torch.Tensor, dI1: torch.Tensor,
-                   opts: TrackOpts | None = None) -> None:
+                   opts: TrackOpts | None = None, dpoints: torch.Tensor | None = None) -> None:
     """Accumulate dL/dI0 into ``dI0`` and dL/dI1 into ``dI1`` (float32, same shape and row stride
-    as the images) for the upstream gradient ``dflow`` of a forward :func:`track` call."""
+    as the images) for the upstream gradient ``dflow`` of a forward :func:`track` call; write
+    dL/dp into ``dpoints`` (float32 [n, 2]) when given."""
     a, b = _image(I0, "I0"), _image(I1, "I1")
     for t, ref, name in ((dI0, I0, "dI0"), (dI1, I1, "dI1")):
         if t.dtype != torch.float32 or t.shape != ref.shape or t.stride() != ref.stride() or not t.is_cuda:
@@ -168,17 +169,56 @@ def track_backward(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, sup
     n = points.shape[0]
     dflow = dflow.contiguous().to(torch.float32)
     o = (opts or TrackOpts()).to_c()
+    if dpoints is not None and (dpoints.shape != (n, 2) or dpoints.dtype != torch.float32 or not dpoints.is_contiguous()):
+        raise ValueError("dpoints: expected a contiguous float32 [n, 2] tensor")
     check(lib().dgf_track_backward(ctypes.byref(a), ctypes.byref(b), _ptr(points.contiguous()), n, support,
                                    ctypes.byref(o), _ptr(flow.contiguous()), _ptr(status.contiguous()), _ptr(dflow),
-                                   _ptr(dI0), _ptr(dI1), _stream()), "dgf_track_backward")
+                                   _ptr(dI0), _ptr(dI1), _ptr(dpoints), _stream()), "dgf_track_backward")
+
+
+def detect_backward(frame: torch.Tensor, window: int, stride: int, sel: torch.Tensor, dpoints: torch.Tensor,
+                    dI0: torch.Tensor) -> None:
+    """Accumulate into ``dI0`` (float32 [H, W]) the gradient through detection of the upstream
+    gradient ``dpoints`` = dL/dp (dgf_detect_backward); ``frame`` and ``sel`` as in :func:`detect`."""
+    a = _image(frame, "frame")
+    n = int(lib().dgf_detect_count(a.width, a.height, window, stride))
+    if dI0.dtype != torch.float32 or dI0.dim() != 2 or dI0.shape != frame.shape or dI0.stride(1) != 1:
+        raise ValueError("dI0: expected a float32 [H, W] tensor with unit column stride")
+    dpoints = dpoints.contiguous().to(torch.float32)
+    check(lib().dgf_detect_backward(ctypes.byref(a), window, stride, _ptr(sel.contiguous()), _ptr(dpoints), n,
+                                    _ptr(dI0), dI0.stride(0), _stream()), "dgf_detect_backward")
+
+
+class DetectFn(torch.autograd.Function):
+    """points = DetectFn.apply(I0, window, stride)
+
+    Differentiable DeGraF detection of a float32 frame holding grey levels: the forward pass
+    detects on the frame rounded to uint8, the backward pass is the gradient of the centroid
+    ratios at those values (dgf_detect_backward)."""
+
+    @staticmethod
+    def forward(ctx, I0, window, stride):
+        u8 = I0.detach().round().clamp(0, 255).to(torch.uint8)
+        points, sel = detect(u8, window, stride, return_sel=True)
+        ctx.save_for_backward(u8, sel)
+        ctx.window, ctx.stride = window, stride
+        return points
+
+    @staticmethod
+    def backward(ctx, dpoints):
+        u8, sel = ctx.saved_tensors
+        dI0 = torch.zeros(u8.shape, dtype=torch.float32, device=u8.device)
+        if dpoints is not None:
+            detect_backward(u8, ctx.window, ctx.stride, sel, dpoints, dI0)
+        return dI0, None, None
 
 
 class TrackFn(torch.autograd.Function):
     """flow, status = TrackFn.apply(I0, I1, points, levels, support, iters, opts)
 
     Differentiable tracking of float32 frames: the backward pass is the implicit-function adjoint
-    at the converged level-0 fixed point (dgf_track_backward).  ``points`` are constants; points
-    that did not converge get no gradient."""
+    at the converged level-0 fixed point (dgf_track_backward), w.r.t. both frames and the point
+    positions; points that did not converge get no gradient."""
 
     @staticmethod
     def forward(ctx, I0, I1, points, levels, support, iters, opts=None):
@@ -194,9 +234,10 @@ class TrackFn(torch.autograd.Function):
         I0, I1, points, flow, status = ctx.saved_tensors
         dI0 = torch.zeros_like(I0)
         dI1 = torch.zeros_like(I1)
+        dpoints = torch.zeros_like(points) if ctx.needs_input_grad[2] else None
         if dflow is not None:
-            track_backward(I0, I1, points, ctx.support, flow, status, dflow, dI0, dI1, ctx.opts)
-        return dI0, dI1, None, None, None, None, None
+            track_backward(I0, I1, points, ctx.support, flow, status, dflow, dI0, dI1, ctx.opts, dpoints)
+        return dI0, dI1, dpoints, None, None, None, None
 
 
 def _tuning_dict(t) -> dict:

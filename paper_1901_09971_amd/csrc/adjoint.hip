@@ -66,6 +66,7 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
     const int li = threadIdx.x;
     const int64_t i = blockIdx.x;
     if (i >= A.n) return; // whole wave: the grid is exactly n wide
+    if (A.dpoints && li == 0) reinterpret_cast<float2 *>(A.dpoints)[i] = make_float2(0.f, 0.f);
     if (A.status[i] != DGF_ST_CONVERGED) return;
     const AdjPair Pr = A.npairs ? A.pairs[adj_pair_of(A, i)] : A.one;
     const float2 p = reinterpret_cast<const float2 *>(A.pts)[i];
@@ -99,8 +100,18 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
         return a00 * q[0] + a10 * q[1] + a01 * q[w0] + a11 * q[w0 + 1];
     };
 
-    // pass 1: J = sum psi' g (grad J)^T
+    // gradient of the bilinear interpolant of I0 inside the cell at local (lx, ly)
+    auto I0g = [&](int lx, int ly, float &gx, float &gy) {
+        const float *q = raw0 + ly * w0 + lx;
+        gx = (1.f - fy0) * (q[1] - q[0]) + fy0 * (q[w0 + 1] - q[w0]);
+        gy = (1.f - fx0) * (q[w0] - q[0]) + fx0 * (q[w0 + 1] - q[1]);
+    };
+
+    // pass 1: J = sum psi' g (grad J)^T; with dpoints also K = sum -psi' g (grad T)^T + psi dG/dx
+    // (the dependence of F on the point: dF/dp = J + K)
+    const bool want_dp = A.dpoints != nullptr;
     float J00 = 0.f, J01 = 0.f, J10 = 0.f, J11 = 0.f;
+    float K00 = 0.f, K01 = 0.f, K10 = 0.f, K11 = 0.f;
     for (int k = li; k < S2; k += 64) {
         const int ky = k / s, kx = k - ky * s;
         const int lx = kx + 1, ly = ky + 1;
@@ -118,14 +129,31 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
         J01 = fmaf(dps * g0, djy, J01);
         J10 = fmaf(dps * g1, djx, J10);
         J11 = fmaf(dps * g1, djy, J11);
+        if (want_dp) {
+            float tgx, tgy, pxx, pxy, mxx, mxy, pyx, pyy, myx, myy;
+            I0g(lx, ly, tgx, tgy);
+            I0g(lx + 1, ly, pxx, pxy);
+            I0g(lx - 1, ly, mxx, mxy);
+            I0g(lx, ly + 1, pyx, pyy);
+            I0g(lx, ly - 1, myx, myy);
+            K00 += -dps * g0 * tgx + 0.5f * ps * (pxx - mxx);
+            K01 += -dps * g0 * tgy + 0.5f * ps * (pxy - mxy);
+            K10 += -dps * g1 * tgx + 0.5f * ps * (pyx - myx);
+            K11 += -dps * g1 * tgy + 0.5f * ps * (pyy - myy);
+        }
     }
     float z = 0.f;
     wave_sum5(J00, J01, J10, J11, z);
+    if (want_dp) wave_sum5(K00, K01, K10, K11, z);
     const float det = J00 * J11 - J01 * J10;
     if (!(det != 0.f) || !isfinite(det)) return; // uniform across the wave
     // J^T mu = lambda, J^T = [[J00, J10], [J01, J11]]
     const float mux = (J11 * lam.x - J10 * lam.y) / det;
     const float muy = (J00 * lam.y - J01 * lam.x) / det;
+    // du/dp = -J^-1 (J + K), so dL/dp = -lambda - K^T mu
+    if (want_dp && li == 0)
+        reinterpret_cast<float2 *>(A.dpoints)[i] =
+            make_float2(-lam.x - (K00 * mux + K10 * muy), -lam.y - (K01 * mux + K11 * muy));
 
     // pass 2: per support pixel, c1 = psi' (mu . g) and cx, cy = -psi mu / 2
     for (int k = li; k < S2; k += 64) {
@@ -190,6 +218,76 @@ hipError_t launch_track_adjoint(const AdjParams &A, int dtype, hipStream_t st)
     return hipGetLastError();
 }
 
+// Gradient of the DeGraF points w.r.t. the image, the centroid ratios of Eq. (1)-(2) taken as
+// functions of real pixel values: one wavefront per window; the window maximum (first maximal
+// pixel in row-major order), the weight sum and the centroid of the selected kind are reduced
+// across the wave, then every pixel gets dL/dp . dp/dI with a device float atomic (neighbouring
+// windows overlap when the stride is below the window).
+__global__ __launch_bounds__(64) void k_detect_backward(DetectGradParams G)
+{
+    const int li = threadIdx.x;
+    const int64_t n = blockIdx.x;
+    if (n >= G.n) return;
+    const float2 lam = reinterpret_cast<const float2 *>(G.dpoints)[n];
+    if (lam.x == 0.f && lam.y == 0.f) return; // uniform: nothing to add
+    const int x0 = (int)(n % G.nx) * G.stride, y0 = (int)(n / G.nx) * G.stride, w = G.win, A2 = w * w;
+    const bool neg = G.sel[n] != 0;
+    // window maximum and its first position (row-major)
+    int best = -1, bidx = 0x7fffffff;
+    for (int q = li; q < A2; q += 64) {
+        const int i = q / w, j = q - i * w;
+        const int v = G.img[(int64_t)(y0 + i) * G.pitch + x0 + j];
+        if (v > best) { // q increases, so a tie keeps the earlier index
+            best = v;
+            bidx = q;
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int ob = __shfl_xor(best, off), oi = __shfl_xor(bidx, off);
+        if (ob > best || (ob == best && oi < bidx)) {
+            best = ob;
+            bidx = oi;
+        }
+    }
+    const float m = (float)best;
+    float S = 0.f, Si = 0.f, Sj = 0.f, z0 = 0.f, z1 = 0.f;
+    for (int q = li; q < A2; q += 64) {
+        const int i = q / w, j = q - i * w;
+        const float v = (float)G.img[(int64_t)(y0 + i) * G.pitch + x0 + j];
+        const float wv = neg ? 1.f + m - v : v;
+        S += wv;
+        Si = fmaf((float)i, wv, Si);
+        Sj = fmaf((float)j, wv, Sj);
+    }
+    wave_sum5(S, Si, Sj, z0, z1);
+    if (!(S != 0.f)) return;
+    const float iS = 1.f / S, Ci = Si * iS, Cj = Sj * iS, cmid = 0.5f * (float)(w - 1);
+    for (int q = li; q < A2; q += 64) {
+        const int i = q / w, j = q - i * w;
+        float di, dj;
+        if (!neg) {
+            di = ((float)i - Ci) * iS;
+            dj = ((float)j - Cj) * iS;
+        } else {
+            di = -((float)i - Ci) * iS;
+            dj = -((float)j - Cj) * iS;
+            if (q == bidx) { // the maximum raises every weight of the negative centroid
+                di += (float)A2 * (cmid - Ci) * iS;
+                dj += (float)A2 * (cmid - Cj) * iS;
+            }
+        }
+        const float v = lam.x * dj + lam.y * di;
+        if (v != 0.f) unsafeAtomicAdd(G.dI + (int64_t)(y0 + i) * G.dpitch + x0 + j, v);
+    }
+}
+
+hipError_t launch_detect_backward(const DetectGradParams &G, hipStream_t st)
+{
+    if (G.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_detect_backward, dim3((unsigned)G.n), dim3(64), 0, st, G);
+    return hipGetLastError();
+}
+
 void fill_adjoint_constants(AdjParams &A, const dgf_track_opts &o)
 {
     A.s1 = o.sigma1;
@@ -210,7 +308,8 @@ void fill_adjoint_constants(AdjParams &A, const dgf_track_opts &o)
 
 extern "C" int dgf_track_backward(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n,
                                   int32_t support, const dgf_track_opts *opts, const float *flow,
-                                  const uint8_t *status, const float *dflow, float *dI0, float *dI1, void *stream)
+                                  const uint8_t *status, const float *dflow, float *dI0, float *dI1, float *dpoints,
+                                  void *stream)
 {
     using namespace dgf;
     auto ok = [](const dgf_image *im) {
@@ -245,7 +344,34 @@ extern "C" int dgf_track_backward(const dgf_image *I0, const dgf_image *I1, cons
     A.flow = flow;
     A.dflow = dflow;
     A.status = status;
+    A.dpoints = dpoints;
     A.n = n;
     fill_adjoint_constants(A, o);
     return launch_track_adjoint(A, DGF_F32, (hipStream_t)stream) == hipSuccess ? DGF_OK : DGF_ERR_HIP;
+}
+
+extern "C" int dgf_detect_backward(const dgf_image *I0, int32_t window, int32_t stride, const uint8_t *sel,
+                                   const float *dpoints, int64_t n, float *dI0, int64_t dI0_pitch, void *stream)
+{
+    using namespace dgf;
+    if (!I0 || !I0->data || I0->dtype != DGF_U8 || I0->width < 1 || I0->height < 1 ||
+        I0->pitch_bytes < I0->width || window < 1 || window > DGF_MAX_WINDOW || stride < 1)
+        return DGF_ERR_INVALID_ARG;
+    if (n != dgf_detect_count(I0->width, I0->height, window, stride)) return DGF_ERR_INVALID_ARG;
+    if (n == 0) return DGF_OK;
+    if (!sel || !dpoints || !dI0 || dI0_pitch < I0->width || (uintptr_t)dI0 % 4 != 0) return DGF_ERR_INVALID_ARG;
+    DetectGradParams G{};
+    G.img = (const uint8_t *)I0->data;
+    G.pitch = I0->pitch_bytes;
+    G.W = I0->width;
+    G.H = I0->height;
+    G.win = window;
+    G.stride = stride;
+    G.nx = (I0->width - window) / stride + 1;
+    G.sel = sel;
+    G.dpoints = dpoints;
+    G.dI = dI0;
+    G.dpitch = dI0_pitch;
+    G.n = n;
+    return launch_detect_backward(G, (hipStream_t)stream) == hipSuccess ? DGF_OK : DGF_ERR_HIP;
 }

@@ -369,10 +369,23 @@ struct AdjParams {
     int32_t s, r;
     const float *pts, *flow, *dflow;
     const uint8_t *status;
+    float *dpoints;        // nullable: dL/dp per point (written)
     int64_t n;
     float s1, s2, dpsi_mid; // thresholds and the middle-band slope -sigma1 / (sigma2 - sigma1)
     int32_t mode;
 };
+
+struct DetectGradParams {
+    const uint8_t *img;
+    int64_t pitch;
+    int32_t W, H, win, stride, nx;
+    const uint8_t *sel;
+    const float *dpoints;
+    float *dI;
+    int64_t dpitch; // floats
+    int64_t n;
+};
+hipError_t launch_detect_backward(const DetectGradParams &G, hipStream_t st);
 
 hipError_t launch_track_adjoint(const AdjParams &A, int dtype, hipStream_t st);
 void fill_adjoint_constants(AdjParams &A, const dgf_track_opts &o);

@@ -1,0 +1,87 @@
+"""GPU parity of the gradient through detection (dgf_detect_backward) and of dL/dp from the
+tracker's adjoint (dgf_track_backward's dpoints) against the FP64 oracle, which the CPU suite
+pins to finite differences; and the two chained by autograd (DetectFn + TrackFn)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1901_09971_amd as dgf
+from paper_1901_09971_amd import synth
+
+pytestmark = pytest.mark.gpu
+REL = 1e-4
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("case", ["translation_256x128", "driving_1242x375"])
+def test_detect_backward_vs_oracle(case):
+    if case == "translation_256x128":
+        I0, _, _ = synth.translation_256x128()
+        w, d = 9, 8
+    else:
+        I0, _, _, _ = synth.driving_1242x375()
+        w, d = 9, 5
+    t0 = torch.from_numpy(I0).cuda()
+    pts, sel = dgf.detect(t0, w, d, return_sel=True)
+    rng = np.random.default_rng(1)
+    lam = rng.normal(size=(pts.shape[0], 2)).astype(np.float32)
+    dI = torch.zeros(I0.shape, dtype=torch.float32, device="cuda")
+    dgf.detect_backward(t0, w, d, sel, torch.from_numpy(lam).cuda(), dI)
+    torch.cuda.synchronize()
+    ref = oracle.detect_grad(I0.astype(np.float64), w, d, sel.cpu().numpy(), lam.astype(np.float64))
+    e = _rel(dI.cpu().numpy().astype(np.float64), ref)
+    print(f"{case}: points {pts.shape[0]} rel-L2 {e:.2e}", flush=True)
+    assert e <= 1e-5
+
+
+def test_point_gradient_vs_oracle():
+    I0, I1, gt = synth.translation_f32_1242x375()
+    I0, I1 = np.ascontiguousarray(I0[:120, :200]), np.ascontiguousarray(I1[:120, :200])
+    pts = oracle.detect(np.clip(np.rint(I0), 0, 255).astype(np.uint8), 9, 6)[0].astype(np.float32)
+    t0, t1, P = torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda(), torch.from_numpy(pts).cuda()
+    opts = dgf.TrackOpts(eps_fine=1e-6)
+    flow, st = dgf.track(t0, t1, P, 3, 9, 100, opts=opts)
+    conv = st == 0
+    dflow = torch.zeros_like(flow)
+    dflow[conv] = 2.0 * (flow[conv] - torch.tensor(gt, dtype=torch.float32, device="cuda"))
+    dI0, dI1, dp = torch.zeros_like(t0), torch.zeros_like(t1), torch.empty_like(P)
+    dgf.track_backward(t0, t1, P, 9, flow, st, dflow, dI0, dI1, opts=opts, dpoints=dp)
+    torch.cuda.synchronize()
+    o0, o1, odp = oracle.track_grad(I0.astype(np.float64), I1.astype(np.float64), pts.astype(np.float64), 9,
+                                    flow.cpu().numpy().astype(np.float64), st.cpu().numpy(),
+                                    dflow.cpu().numpy().astype(np.float64), return_dpoints=True)
+    e0, e1, ep = _rel(dI0.cpu().numpy(), o0), _rel(dI1.cpu().numpy(), o1), _rel(dp.cpu().numpy(), odp)
+    print(f"converged {int(conv.sum())}/{len(st)}: rel dI0 {e0:.2e} dI1 {e1:.2e} dpoints {ep:.2e}", flush=True)
+    assert e0 <= REL and e1 <= REL and ep <= REL
+    assert torch.all(dp[~conv] == 0)
+
+
+def test_detect_and_track_autograd_end_to_end():
+    I0n, I1n, gt = synth.translation_f32_1242x375()
+    I0n = np.rint(np.ascontiguousarray(I0n[:120, :200])).astype(np.float32)  # grey levels
+    I1n = np.ascontiguousarray(I1n[:120, :200])
+    I0 = torch.from_numpy(I0n).cuda().requires_grad_(True)
+    I1 = torch.from_numpy(I1n).cuda().requires_grad_(True)
+    opts = dgf.TrackOpts(eps_fine=1e-6)
+    P = dgf.DetectFn.apply(I0, 9, 6)
+    flow, st = dgf.TrackFn.apply(I0, I1, P, 3, 9, 100, opts)
+    conv = (st == 0).float()[:, None]
+    g = torch.tensor(gt, dtype=torch.float32, device="cuda")
+    loss = (((flow - g) ** 2) * conv).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    # oracle: points held fixed + through the points (chain of dL/dp into the detection gradient)
+    pts = P.detach().cpu().numpy().astype(np.float64)
+    fl, s = flow.detach().cpu().numpy().astype(np.float64), st.cpu().numpy()
+    df = 2.0 * (fl - gt) * (s == 0)[:, None]
+    o0, o1, odp = oracle.track_grad(I0n.astype(np.float64), I1n.astype(np.float64), pts, 9, fl, s, df,
+                                    return_dpoints=True)
+    _, sel, _ = oracle.detect(I0n.astype(np.uint8), 9, 6)
+    o0 = o0 + oracle.detect_grad(I0n.astype(np.float64), 9, 6, sel, odp)
+    e0, e1 = _rel(I0.grad.cpu().numpy(), o0), _rel(I1.grad.cpu().numpy(), o1)
+    print(f"end to end: rel dI0 {e0:.2e} dI1 {e1:.2e}", flush=True)
+    assert e0 <= REL and e1 <= REL
