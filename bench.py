@@ -218,6 +218,63 @@ def illumination(steps: int, warmup: int):
             "frac": achieved / PEAK_FP32_VALU_TFLOPS}
 
 
+def differentiation(reps: int):
+    """The differentiation workload: the 1242x375 FP32 translation pair (shift (2.3, -1.7), 7,130
+    points at window 9 stride 8; 3 levels, 9x9 support, 10 iterations), loss = sum over converged
+    points of |u - u_gt|^2.  Forward: detect (on the frame rounded to grey levels) + track; backward:
+    the tracker adjoint w.r.t. both frames and the points, then the gradient through detection."""
+    import numpy as np
+    import torch
+
+    import paper_1901_09971_amd as dgf
+    from paper_1901_09971_amd import synth
+
+    I0n, I1n, gt = synth.translation_f32_1242x375()
+    dev = torch.device("cuda", 0)
+    I0, I1 = torch.from_numpy(I0n).to(dev), torch.from_numpy(I1n).to(dev)
+    u8 = I0.round().clamp(0, 255).to(torch.uint8)
+    L_, s_, it_, w_, d_ = 3, 9, 10, 9, 8
+    g = torch.tensor(gt, dtype=torch.float32, device=dev)
+    pts, sel = dgf.detect(u8, w_, d_, return_sel=True)
+    n = pts.shape[0]
+    ws = torch.empty(dgf.track_workspace_bytes(1242, 375, L_, 1), dtype=torch.uint8, device=dev)
+    flow = torch.empty((n, 2), dtype=torch.float32, device=dev)
+    st = torch.empty(n, dtype=torch.uint8, device=dev)
+    dI0, dI1 = torch.zeros_like(I0), torch.zeros_like(I1)
+    dp = torch.empty_like(pts)
+    dflow = torch.zeros_like(flow)
+
+    def fwd():
+        dgf.detect(u8, w_, d_, out=pts)
+        dgf.track_pyramids(I0, I1, L_, ws)
+        dgf.track_run(I0, I1, pts, L_, s_, it_, ws, flow, st)
+
+    def bwd():
+        dgf.track_backward(I0, I1, pts, s_, flow, st, dflow, dI0, dI1, dpoints=dp)
+        dgf.detect_backward(u8, w_, d_, sel, dp, dI0)
+
+    fwd()
+    conv = st == 0
+    dflow[conv] = 2.0 * (flow[conv] - g)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_f, t_b = timed(fwd), timed(bwd)
+    return {"workload": "translation_f32_1242x375, window 9 stride 8, L3 s9 it10, loss sum |u - u_gt|^2",
+            "points": n, "converged": int(conv.sum().item()), "forward_ms": t_f, "backward_ms": t_b,
+            "backward_includes": "tracker adjoint w.r.t. I0, I1 and points + gradient through detection"}
+
+
 DENSITY = dict(name="density_2048x1024x4", W=2048, H=1024, pairs=4, window=9, stride=2, levels=6, support=21,
                iters=20)
 
@@ -315,6 +372,7 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=10)
     ap.add_argument("--no-density", action="store_true", help="skip the 4 x 2048x1024 density stress")
     ap.add_argument("--no-illum", action="store_true", help="skip the illumination-model measurement")
+    ap.add_argument("--no-diff", action="store_true", help="skip the differentiation measurement")
     ap.add_argument("--density-reps", type=int, default=3)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
@@ -447,6 +505,8 @@ def main():
         out["batched"] = batched_vs_plain(args.batch_reps)
     if not args.no_illum:
         out["illumination"] = illumination(args.steps, args.warmup)
+    if not args.no_diff:
+        out["differentiation"] = differentiation(args.steps)
     if not args.no_density:
         out["density"] = density_stress(args.density_reps)
     if not args.no_cpu_baseline:
