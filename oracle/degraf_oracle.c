@@ -995,3 +995,89 @@ int or_track_grad(const double *I0, const double *I1, int W, int H, const double
     }
     return OR_OK;
 }
+
+/*
+ * Implicit gradient of the illumination-model tracker (track_point_illum).  At a converged point
+ * theta = (u, m, c) solves F(theta) = sum_k psi(r_k) phi_k = 0 with
+ * r_k = B(I1, p + k + u) - (1 + m) T_k - c and phi_k = ((1 + m) g_k, -T_k, -1).  For the upstream
+ * gradient lambda = (dL/du, 0, 0) (the loss depends on the flow only):
+ *   A = dF/dtheta = sum_k psi'(r_k) phi_k (grad B(I1, p + k + u), -T_k, -1)^T
+ *                   + sum_k psi(r_k) (g_k, 0, 0) in the column of m      (phi depends on m;
+ *                     this term is (1 + m)^-1 times the d rows of F, so it vanishes at the fixed point)
+ *   solve A^T mu = lambda,
+ *   dL/dI1[q] = - sum_k psi'(r_k) (mu . phi_k) beta_k(q)
+ *   dL/dI0[q] = sum_k [((1 + m) psi'(r_k) (mu . phi_k) + psi(r_k) mu_m) alpha_k(q)
+ *                      - (1 + m) psi(r_k) mu_d . dg_k/dI0[q]]
+ * illum holds (m, c) per point as the forward pass returned them.  Results are ADDED.
+ */
+int or_track_grad_illum(const double *I0, const double *I1, int W, int H, const double *pts, int64_t n, int support,
+                        double sigma1, double sigma2, const double *flow, const double *illum, const uint8_t *status,
+                        const double *dflow, double *dI0, double *dI1)
+{
+    if (!I0 || !I1 || W <= 0 || H <= 0 || support < 1 || (support % 2) == 0) return OR_ERR_ARG;
+    if (n > 0 && (!pts || !flow || !illum || !status || !dflow || !dI0 || !dI1)) return OR_ERR_ARG;
+    const int r = support / 2;
+    for (int64_t i = 0; i < n; ++i) {
+        if (status[i] != OR_ST_CONVERGED) continue;
+        const double px = pts[2 * i], py = pts[2 * i + 1];
+        const double ux = flow[2 * i], uy = flow[2 * i + 1];
+        const double m = illum[2 * i], c = illum[2 * i + 1];
+        double A[16] = {0};
+        for (int ky = -r; ky <= r; ++ky)
+            for (int kx = -r; kx <= r; ++kx) {
+                double x = px + kx, y = py + ky;
+                double T = or_bilinear(I0, W, H, x, y);
+                double g0 = 0.5 * (or_bilinear(I0, W, H, x + 1.0, y) - or_bilinear(I0, W, H, x - 1.0, y));
+                double g1 = 0.5 * (or_bilinear(I0, W, H, x, y + 1.0) - or_bilinear(I0, W, H, x, y - 1.0));
+                double gJ[2];
+                bilinear_grad(I1, W, H, x + ux, y + uy, gJ);
+                double res = or_bilinear(I1, W, H, x + ux, y + uy) - (1.0 + m) * T - c;
+                double ps = or_psi(res, sigma1, sigma2), dp = or_dpsi(res, sigma1, sigma2);
+                double phi[4] = {(1.0 + m) * g0, (1.0 + m) * g1, -T, -1.0};
+                double dr[4] = {gJ[0], gJ[1], -T, -1.0};
+                for (int a = 0; a < 4; ++a)
+                    for (int b = 0; b < 4; ++b) A[a * 4 + b] += dp * phi[a] * dr[b];
+                A[0 * 4 + 2] += ps * g0;
+                A[1 * 4 + 2] += ps * g1;
+            }
+        double At[16], lam[4] = {dflow[2 * i], dflow[2 * i + 1], 0.0, 0.0}, mu[4];
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) At[a * 4 + b] = A[b * 4 + a];
+        if (solve_dense(At, lam, 4, mu) != 0 || !(isfinite(mu[0]) && isfinite(mu[1]) && isfinite(mu[2]) && isfinite(mu[3])))
+            continue;
+        for (int ky = -r; ky <= r; ++ky)
+            for (int kx = -r; kx <= r; ++kx) {
+                double x = px + kx, y = py + ky;
+                int64_t ia[4], ixp[4], ixm[4], iyp[4], iym[4], ib[4];
+                double wa[4], wxp[4], wxm[4], wyp[4], wym[4], wb[4];
+                int ccx[4], ccy[4]; double ffx, ffy;
+                bilinear_taps(W, H, x, y, ia, wa, ccx, ccy, &ffx, &ffy);
+                bilinear_taps(W, H, x + 1.0, y, ixp, wxp, ccx, ccy, &ffx, &ffy);
+                bilinear_taps(W, H, x - 1.0, y, ixm, wxm, ccx, ccy, &ffx, &ffy);
+                bilinear_taps(W, H, x, y + 1.0, iyp, wyp, ccx, ccy, &ffx, &ffy);
+                bilinear_taps(W, H, x, y - 1.0, iym, wym, ccx, ccy, &ffx, &ffy);
+                bilinear_taps(W, H, x + ux, y + uy, ib, wb, ccx, ccy, &ffx, &ffy);
+                double T = 0.0, g0 = 0.0, g1 = 0.0, Jv = 0.0;
+                for (int t = 0; t < 4; ++t) {
+                    T += wa[t] * I0[ia[t]];
+                    g0 += 0.5 * (wxp[t] * I0[ixp[t]] - wxm[t] * I0[ixm[t]]);
+                    g1 += 0.5 * (wyp[t] * I0[iyp[t]] - wym[t] * I0[iym[t]]);
+                    Jv += wb[t] * I1[ib[t]];
+                }
+                double res = Jv - (1.0 + m) * T - c;
+                double ps = or_psi(res, sigma1, sigma2), dp = or_dpsi(res, sigma1, sigma2);
+                double mphi = mu[0] * (1.0 + m) * g0 + mu[1] * (1.0 + m) * g1 - mu[2] * T - mu[3];
+                double a0 = (1.0 + m) * dp * mphi + ps * mu[2];
+                double cx = -0.5 * (1.0 + m) * ps * mu[0], cy = -0.5 * (1.0 + m) * ps * mu[1];
+                for (int t = 0; t < 4; ++t) {
+                    dI1[ib[t]] -= dp * mphi * wb[t];
+                    dI0[ia[t]] += a0 * wa[t];
+                    dI0[ixp[t]] += cx * wxp[t];
+                    dI0[ixm[t]] -= cx * wxm[t];
+                    dI0[iyp[t]] += cy * wyp[t];
+                    dI0[iym[t]] -= cy * wym[t];
+                }
+            }
+    }
+    return OR_OK;
+}

@@ -156,3 +156,33 @@ def test_contrast_inversion_is_not_a_match():
     I2 = 1.9 * I0
     flow, st = oracle.track(I0, I2, pts, 1, 9, 60, sigma1=INF, sigma2=INF, eps_fine=1e-10, min_eig=0.0, illum=True)
     assert np.all(st == oracle.ST_CONVERGED) and np.max(np.abs(flow)) < 1e-8
+
+
+def test_implicit_gradient_matches_finite_differences():
+    # L = sum over converged points of lam . u for the illumination-model tracker (one level,
+    # converged to round-off), against central differences pixel by pixel on a small crop of both
+    # frames; the gain and offset differ from (0, 0) and the robust middle band is active
+    I0, I1, _ = synth.noise_translation_pair(44, 40, seed=17, shift=(0.7, -0.4), dtype="f32")
+    I0 = I0.astype(np.float64)
+    I1 = 1.1 * I1.astype(np.float64) - 9.0 + 6.0 * np.sin(np.arange(44) / 5.0)[None, :]
+    rng = np.random.default_rng(18)
+    pts = np.stack([rng.uniform(12, 31, 6), rng.uniform(12, 27, 6)], 1)
+    kw = dict(eps_fine=1e-13, min_eig=0.0, illum=True)
+    flow, st, mc = oracle.track(I0, I1, pts, 1, 9, 400, return_illum=True, **kw)
+    assert np.all(st == oracle.ST_CONVERGED)
+    lam = rng.normal(size=flow.shape)
+    g0, g1 = oracle.track_grad_illum(I0, I1, pts, 9, flow, mc, st, lam)
+    h = 1e-5
+    for img, g in ((I0, g0), (I1, g1)):
+        ys, xs = np.nonzero(np.abs(g) > 1e-9 * np.abs(g).max())
+        pick = rng.choice(len(ys), 60, replace=False)
+        for y, x in zip(ys[pick], xs[pick]):
+            vals = []
+            for sgn in (1.0, -1.0):
+                a = img.copy()
+                a[y, x] += sgn * h
+                f, s = oracle.track(a if img is I0 else I0, a if img is I1 else I1, pts, 1, 9, 400, **kw)
+                assert np.array_equal(s, st)
+                vals.append(np.sum(lam * f))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            assert abs(g[y, x] - fd) <= 1e-5 * np.abs(g).max(), (y, x, g[y, x], fd)
