@@ -89,8 +89,9 @@ typedef struct {
  * Each iteration then solves a 4x4 system in (d, m, c), with residual derivatives
  * ((1 + m) g, -T, -1); m and c start at 0 and carry over between levels; a point whose final
  * gain 1 + m lies outside [1/2, 2] is NOT_CONVERGED (a contrast change, not a match).  Supported for the
- * supports the row-run kernel is compiled for (5, 7, 9, 11, 15, 21), else DGF_ERR_UNSUPPORTED;
- * dgf_track_backward does not support it. */
+ * supports the row-run kernel is compiled for (5, 7, 9, 11, 15, 21), else DGF_ERR_UNSUPPORTED.
+ * dgf_track_backward differentiates it given the forward call's (gain, offset) (illum_out);
+ * dgf_batch_backward does not. */
 #define DGF_TRACK_ILLUM 1
 
 /* ---- library ----------------------------------------------------------------------------------- */
@@ -162,11 +163,15 @@ size_t dgf_track_workspace_bytes(int32_t width, int32_t height, int32_t levels, 
  *   workspace : device, >= dgf_track_workspace_bytes(width, height, levels, dtype) bytes
  *   flow      : out, float[n][2];   status : out, uint8[n] (DGF_ST_*)
  *   iters_out : out, nullable, int32[n]: iterations run by the point summed over levels
+ *   illum_out : out, nullable, float[n][2]: the level-0 gain m and offset c of the illumination
+ *               model (I1(p+k+u) ~ (1+m) I0(p+k) + c, offsets in grey levels of the images);
+ *               only with DGF_TRACK_ILLUM in opts->flags, else DGF_ERR_INVALID_ARG
  *   opts      : nullable (defaults)
  * n = 0 launches nothing. */
 int dgf_track(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
               int32_t support, int32_t iters, const dgf_track_opts *opts, void *workspace,
-              size_t ws_bytes, float *flow, uint8_t *status, int32_t *iters_out, void *stream);
+              size_t ws_bytes, float *flow, uint8_t *status, int32_t *iters_out, float *illum_out,
+              void *stream);
 
 /* ---- gradient of the tracked flow (implicit differentiation at the converged fixed point) ---- */
 
@@ -188,10 +193,19 @@ int dgf_track(const dgf_image *I0, const dgf_image *I1, const float *points, int
  *   dpoints     : nullable, float[n][2]: WRITTEN with dL/dp, the gradient w.r.t. the point
  *                 positions (the template moves with the point): with
  *                 K = sum_k [-psi'(r_k) g_k grad I0(p+k)^T + psi(r_k) dg_k/dp], du/dp = -J^-1 (J + K)
- *                 and dL/dp = -dflow - K^T mu; 0 for points that contribute nothing. */
+ *                 and dL/dp = -dflow - K^T mu; 0 for points that contribute nothing.
+ *   illum       : with DGF_TRACK_ILLUM in opts->flags: float[n][2], the (gain, offset) that
+ *                 dgf_track wrote to illum_out (required when n > 0); must be null otherwise.
+ *                 The adjoint is then that of the illumination model's fixed point
+ *                 F(u, m, c) = sum_k psi(r_k) phi_k = 0, r_k = I1(p+k+u) - (1+m) T_k - c,
+ *                 phi_k = ((1+m) g_k, -T_k, -1): a 4x4 J with J^T mu = (dflow, 0, 0), and
+ *   dI1[q] -= sum_k psi'(r_k) (mu . phi_k) beta_k(q)
+ *   dI0[q] += sum_k [(1+m) psi'(r_k) (mu . phi_k) + psi(r_k) mu_m] alpha_k(q)
+ *             - (1+m) sum_k psi(r_k) mu_u . dg_k/dI0[q].
+ *                 dpoints must then be null (DGF_ERR_UNSUPPORTED). */
 int dgf_track_backward(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t support,
                        const dgf_track_opts *opts, const float *flow, const uint8_t *status, const float *dflow,
-                       float *dI0, float *dI1, float *dpoints, void *stream);
+                       float *dI0, float *dI1, float *dpoints, const float *illum, void *stream);
 
 /* Gradient through detection (Section 2 Eq. 1-2, the centroid ratios taken as functions of real
  * pixel values, evaluated at the uint8 image the points were detected on): ADDS
@@ -302,7 +316,8 @@ int dgf_track_pyramids(const dgf_image *I0, const dgf_image *I1, int32_t levels,
                        void *stream);
 int dgf_track_run(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
                   int32_t support, int32_t iters, const dgf_track_opts *opts, const void *workspace,
-                  size_t ws_bytes, float *flow, uint8_t *status, int32_t *iters_out, void *stream);
+                  size_t ws_bytes, float *flow, uint8_t *status, int32_t *iters_out, float *illum_out,
+                  void *stream);
 
 #ifdef __cplusplus
 }

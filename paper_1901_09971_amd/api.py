@@ -110,9 +110,11 @@ def track_workspace_bytes(width: int, height: int, levels: int, dtype: int) -> i
 
 
 def track(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, levels: int, support: int, iters: int,
-          opts: TrackOpts | None = None, return_iters: bool = False, workspace: torch.Tensor | None = None):
+          opts: TrackOpts | None = None, return_iters: bool = False, workspace: torch.Tensor | None = None,
+          return_illum: bool = False):
     """Track ``points`` (float32 [n, 2] device) from I0 to I1.  Returns (flow float32 [n, 2],
-    status uint8 [n]) and optionally the per-point iteration count (int32 [n])."""
+    status uint8 [n]), then the per-point iteration count (int32 [n]) if ``return_iters`` and the
+    per-point (gain m, offset c) (float32 [n, 2], needs ``opts.illum``) if ``return_illum``."""
     a, b = _image(I0, "I0"), _image(I1, "I1")
     if points.dtype != torch.float32 or points.dim() != 2 or points.shape[1] != 2 or not points.is_cuda:
         raise ValueError("points: expected a float32 [n, 2] device tensor")
@@ -124,13 +126,17 @@ def track(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, levels: int,
     flow = torch.empty((n, 2), dtype=torch.float32, device=I0.device)
     status = torch.empty(n, dtype=torch.uint8, device=I0.device)
     its = torch.empty(n, dtype=torch.int32, device=I0.device) if return_iters else None
+    ill = torch.empty((n, 2), dtype=torch.float32, device=I0.device) if return_illum else None
     o = (opts or TrackOpts()).to_c()
     check(lib().dgf_track(ctypes.byref(a), ctypes.byref(b), _ptr(points), n, levels, support, iters,
                           ctypes.byref(o), _ptr(workspace), workspace.numel(), _ptr(flow), _ptr(status), _ptr(its),
-                          _stream()), "dgf_track")
+                          _ptr(ill), _stream()), "dgf_track")
+    out = (flow, status)
     if return_iters:
-        return flow, status, its
-    return flow, status
+        out += (its,)
+    if return_illum:
+        out += (ill,)
+    return out
 
 
 def track_pyramids(I0: torch.Tensor, I1: torch.Tensor, levels: int, workspace: torch.Tensor) -> None:
@@ -143,25 +149,31 @@ def track_pyramids(I0: torch.Tensor, I1: torch.Tensor, levels: int, workspace: t
 
 def track_run(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, levels: int, support: int, iters: int,
               workspace: torch.Tensor, flow: torch.Tensor, status: torch.Tensor, iters_out: torch.Tensor | None = None,
-              opts: TrackOpts | None = None) -> None:
+              opts: TrackOpts | None = None, illum_out: torch.Tensor | None = None) -> None:
     """Second stage of :func:`track` on pyramids already built by :func:`track_pyramids`;
-    writes into the caller's ``flow`` (float32 [n, 2]) and ``status`` (uint8 [n])."""
+    writes into the caller's ``flow`` (float32 [n, 2]) and ``status`` (uint8 [n]), and the
+    per-point (gain, offset) into ``illum_out`` (float32 [n, 2], with ``opts.illum``) when given."""
     a, b = _image(I0, "I0"), _image(I1, "I1")
     n = points.shape[0]
     if flow.shape != (n, 2) or flow.dtype != torch.float32 or status.shape != (n,) or status.dtype != torch.uint8:
         raise ValueError("flow/status: wrong shape or dtype")
+    if illum_out is not None and (illum_out.shape != (n, 2) or illum_out.dtype != torch.float32
+                                  or not illum_out.is_contiguous()):
+        raise ValueError("illum_out: expected a contiguous float32 [n, 2] tensor")
     o = (opts or TrackOpts()).to_c()
     check(lib().dgf_track_run(ctypes.byref(a), ctypes.byref(b), _ptr(points), n, levels, support, iters,
                               ctypes.byref(o), _ptr(workspace), workspace.numel(), _ptr(flow), _ptr(status),
-                              _ptr(iters_out), _stream()), "dgf_track_run")
+                              _ptr(iters_out), _ptr(illum_out), _stream()), "dgf_track_run")
 
 
 def track_backward(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, support: int, flow: torch.Tensor,
                    status: torch.Tensor, dflow: torch.Tensor, dI0: torch.Tensor, dI1: torch.Tensor,
-                   opts: TrackOpts | None = None, dpoints: torch.Tensor | None = None) -> None:
+                   opts: TrackOpts | None = None, dpoints: torch.Tensor | None = None,
+                   illum: torch.Tensor | None = None) -> None:
     """Accumulate dL/dI0 into ``dI0`` and dL/dI1 into ``dI1`` (float32, same shape and row stride
     as the images) for the upstream gradient ``dflow`` of a forward :func:`track` call; write
-    dL/dp into ``dpoints`` (float32 [n, 2]) when given."""
+    dL/dp into ``dpoints`` (float32 [n, 2]) when given.  With ``opts.illum`` the forward call's
+    per-point (gain, offset) go in ``illum`` (float32 [n, 2]); ``dpoints`` is then not supported."""
     a, b = _image(I0, "I0"), _image(I1, "I1")
     for t, ref, name in ((dI0, I0, "dI0"), (dI1, I1, "dI1")):
         if t.dtype != torch.float32 or t.shape != ref.shape or t.stride() != ref.stride() or not t.is_cuda:
@@ -171,9 +183,13 @@ def track_backward(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, sup
     o = (opts or TrackOpts()).to_c()
     if dpoints is not None and (dpoints.shape != (n, 2) or dpoints.dtype != torch.float32 or not dpoints.is_contiguous()):
         raise ValueError("dpoints: expected a contiguous float32 [n, 2] tensor")
+    if illum is not None:
+        if illum.shape != (n, 2) or illum.dtype != torch.float32:
+            raise ValueError("illum: expected a float32 [n, 2] tensor")
+        illum = illum.contiguous()
     check(lib().dgf_track_backward(ctypes.byref(a), ctypes.byref(b), _ptr(points.contiguous()), n, support,
                                    ctypes.byref(o), _ptr(flow.contiguous()), _ptr(status.contiguous()), _ptr(dflow),
-                                   _ptr(dI0), _ptr(dI1), _ptr(dpoints), _stream()), "dgf_track_backward")
+                                   _ptr(dI0), _ptr(dI1), _ptr(dpoints), _ptr(illum), _stream()), "dgf_track_backward")
 
 
 def detect_backward(frame: torch.Tensor, window: int, stride: int, sel: torch.Tensor, dpoints: torch.Tensor,
@@ -218,12 +234,17 @@ class TrackFn(torch.autograd.Function):
 
     Differentiable tracking of float32 frames: the backward pass is the implicit-function adjoint
     at the converged level-0 fixed point (dgf_track_backward), w.r.t. both frames and the point
-    positions; points that did not converge get no gradient."""
+    positions; points that did not converge get no gradient.  With ``opts.illum`` the adjoint
+    is that of the illumination model (frames only: the point positions get no gradient)."""
 
     @staticmethod
     def forward(ctx, I0, I1, points, levels, support, iters, opts=None):
-        flow, status = track(I0, I1, points, levels, support, iters, opts=opts)
-        ctx.save_for_backward(I0, I1, points, flow, status)
+        im = bool(opts is not None and opts.illum)
+        if im:
+            flow, status, ill = track(I0, I1, points, levels, support, iters, opts=opts, return_illum=True)
+        else:
+            (flow, status), ill = track(I0, I1, points, levels, support, iters, opts=opts), None
+        ctx.save_for_backward(I0, I1, points, flow, status, ill)
         ctx.support = support
         ctx.opts = opts
         ctx.mark_non_differentiable(status)
@@ -231,12 +252,14 @@ class TrackFn(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, dflow, _dstatus):
-        I0, I1, points, flow, status = ctx.saved_tensors
+        I0, I1, points, flow, status, ill = ctx.saved_tensors
         dI0 = torch.zeros_like(I0)
         dI1 = torch.zeros_like(I1)
+        if ill is not None and ctx.needs_input_grad[2]:
+            raise NotImplementedError("TrackFn: no point-position gradient for the illumination model")
         dpoints = torch.zeros_like(points) if ctx.needs_input_grad[2] else None
         if dflow is not None:
-            track_backward(I0, I1, points, ctx.support, flow, status, dflow, dI0, dI1, ctx.opts, dpoints)
+            track_backward(I0, I1, points, ctx.support, flow, status, dflow, dI0, dI1, ctx.opts, dpoints, ill)
         return dI0, dI1, dpoints, None, None, None, None
 
 

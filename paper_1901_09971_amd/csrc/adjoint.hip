@@ -202,16 +202,205 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
     }
 }
 
+// 4x4 system M^T x = v by Gaussian elimination with partial pivoting, fully unrolled (M row-major,
+// both copied); x is not finite when a pivot is zero.
+__device__ __forceinline__ void solve4_transposed(const float *M, const float *v, float *x)
+{
+    float a[4][5];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) a[r][c] = M[c * 4 + r];
+        a[r][4] = v[r];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        // pivot: largest |a[r][c]| for r >= c, brought to row c by selects (no dynamic indexing)
+#pragma unroll
+        for (int r = c + 1; r < 4; ++r) {
+            const bool sw = fabsf(a[r][c]) > fabsf(a[c][c]);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const float t = a[c][k];
+                a[c][k] = sw ? a[r][k] : t;
+                a[r][k] = sw ? t : a[r][k];
+            }
+        }
+        const float inv = 1.f / a[c][c];
+#pragma unroll
+        for (int r = c + 1; r < 4; ++r) {
+            const float f = a[r][c] * inv;
+#pragma unroll
+            for (int k = c; k < 5; ++k) a[r][k] = fmaf(-f, a[c][k], a[r][k]);
+        }
+    }
+#pragma unroll
+    for (int r = 3; r >= 0; --r) {
+        float acc = a[r][4];
+#pragma unroll
+        for (int k = r + 1; k < 4; ++k) acc = fmaf(-a[r][k], x[k], acc);
+        x[r] = acc / a[r][r];
+    }
+}
+
+// Adjoint of the illumination-model tracker.  At a converged point theta = (u, m, c) solves
+// F = sum_k psi(r_k) phi_k = 0, r_k = J_k - (1 + m) T_k - c, phi_k = ((1 + m) g_k, -T_k, -1).
+// The solve runs on the centred template T' = (T - Tm) / Ts on both sides -- a constant change of
+// the equations' basis (F' = R F) and of the (m, c) parameters, which leaves dL/dI unchanged at the
+// fixed point and conditions the FP32 4x4 system:
+//   A = sum_k psi'(r_k) phi'_k (grad J_k, -T'_k, -1)^T with phi'_k = ((1 + m) g_k, -T'_k, -1)
+//   (the psi g term of the m column is (1 + m)^-1 times the d rows of F and vanishes here),
+//   A^T mu = (dL/du, 0, 0),
+//   dI1 -= psi' (mu . phi') beta,
+//   dI0 += [(1 + m) psi' (mu . phi') + psi mu_m / Ts] alpha - (1 + m) psi mu_d . dg/dI0.
+// The image gradients are gathered as in k_track_adjoint, with the sample term A0 apart from c1.
+template <typename PixT>
+__global__ __launch_bounds__(64) void k_track_adjoint_illum(AdjParams A)
+{
+    extern __shared__ float smem[];
+    const int li = threadIdx.x;
+    const int64_t i = blockIdx.x;
+    if (i >= A.n) return; // whole wave: the grid is exactly n wide
+    if (A.status[i] != DGF_ST_CONVERGED) return;
+    const AdjPair Pr = A.npairs ? A.pairs[adj_pair_of(A, i)] : A.one;
+    const float2 p = reinterpret_cast<const float2 *>(A.pts)[i];
+    const float2 u = reinterpret_cast<const float2 *>(A.flow)[i];
+    const float2 lam = reinterpret_cast<const float2 *>(A.dflow)[i];
+    const float2 mc = reinterpret_cast<const float2 *>(A.illum)[i];
+    const float g1m = 1.f + mc.x;
+    const int W = Pr.W, H = Pr.H, s = A.s, r = A.r, S2 = s * s;
+
+    const float pbx = floorf(p.x), pby = floorf(p.y);
+    const float fx0 = p.x - pbx, fy0 = p.y - pby;
+    const float tx = fx0 + u.x, ty = fy0 + u.y;
+    const float qbx = floorf(tx), qby = floorf(ty);
+    const float fx1 = tx - qbx, fy1 = ty - qby;
+    const int ox0 = (int)pbx - r - 1, oy0 = (int)pby - r - 1;
+    const int ox1 = (int)pbx + (int)fminf(fmaxf(qbx, -1048576.f), 1048576.f) - r;
+    const int oy1 = (int)pby + (int)fminf(fmaxf(qby, -1048576.f), 1048576.f) - r;
+    const float a00 = (1.f - fx0) * (1.f - fy0), a10 = fx0 * (1.f - fy0), a01 = (1.f - fx0) * fy0, a11 = fx0 * fy0;
+    const float b00 = (1.f - fx1) * (1.f - fy1), b10 = fx1 * (1.f - fy1), b01 = (1.f - fx1) * fy1, b11 = fx1 * fy1;
+
+    const int w0 = s + 3, w1 = s + 1, n0 = w0 * w0, n1 = w1 * w1;
+    float *raw0 = smem, *raw1 = smem + n0, *C1 = raw1 + n1, *CX = C1 + S2, *CY = CX + S2, *A0 = CY + S2;
+    stage_rect<64, PixT>(raw0, w0, Pr.I0, Pr.pitch0, W, H, ox0, oy0, w0, w0, stage_lanes<64>(w0, li));
+    stage_rect<64, PixT>(raw1, w1, Pr.I1, Pr.pitch1, W, H, ox1, oy1, w1, w1, stage_lanes<64>(w1, li));
+    __syncthreads();
+    auto I0s = [&](int lx, int ly) {
+        const float *q = raw0 + ly * w0 + lx;
+        return a00 * q[0] + a10 * q[1] + a01 * q[w0] + a11 * q[w0 + 1];
+    };
+
+    // template mean and spread over the support
+    float sT = 0.f, sTT = 0.f, z0 = 0.f, z1 = 0.f, z2 = 0.f;
+    for (int k = li; k < S2; k += 64) {
+        const int ky = k / s, kx = k - ky * s;
+        const float T = I0s(kx + 1, ky + 1);
+        sT += T;
+        sTT = fmaf(T, T, sTT);
+    }
+    wave_sum5(sT, sTT, z0, z1, z2);
+    const float Tm = sT / (float)S2;
+    float Ts = sqrtf(fmaxf(sTT / (float)S2 - Tm * Tm, 0.f));
+    if (!(Ts > 1e-6f)) Ts = 1.f;
+    const float iTs = 1.f / Ts;
+
+    // pass 1: A = sum psi' phi' (grad J, -T', -1)^T
+    float Am[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) Am[e] = 0.f;
+    for (int k = li; k < S2; k += 64) {
+        const int ky = k / s, kx = k - ky * s;
+        const int lx = kx + 1, ly = ky + 1;
+        const float T = I0s(lx, ly);
+        const float g0 = 0.5f * (I0s(lx + 1, ly) - I0s(lx - 1, ly));
+        const float g1 = 0.5f * (I0s(lx, ly + 1) - I0s(lx, ly - 1));
+        const float *q = raw1 + ky * w1 + kx;
+        const float i00 = q[0], i10 = q[1], i01 = q[w1], i11 = q[w1 + 1];
+        const float J = b00 * i00 + b10 * i10 + b01 * i01 + b11 * i11;
+        const float djx = (1.f - fy1) * (i10 - i00) + fy1 * (i11 - i01);
+        const float djy = (1.f - fx1) * (i01 - i00) + fx1 * (i11 - i10);
+        float ps, dps;
+        psi_and_slope(A, J - g1m * T - mc.y, ps, dps);
+        const float Tp = (T - Tm) * iTs;
+        const float ph[4] = {g1m * g0, g1m * g1, -Tp, -1.f};
+        const float dr[4] = {djx, djy, -Tp, -1.f};
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) Am[a * 4 + b] = fmaf(dps * ph[a], dr[b], Am[a * 4 + b]);
+    }
+    float zz = 0.f;
+    wave_sum5(Am[0], Am[1], Am[2], Am[3], Am[4]);
+    wave_sum5(Am[5], Am[6], Am[7], Am[8], Am[9]);
+    wave_sum5(Am[10], Am[11], Am[12], Am[13], Am[14]);
+    wave_sum5(Am[15], zz, z0, z1, z2);
+    const float v[4] = {lam.x, lam.y, 0.f, 0.f};
+    float mu[4];
+    solve4_transposed(Am, v, mu);
+    if (!(isfinite(mu[0]) && isfinite(mu[1]) && isfinite(mu[2]) && isfinite(mu[3]))) return; // uniform
+
+    // pass 2: per support pixel c1 = psi' (mu . phi'), A0 = (1 + m) c1 + psi mu_m / Ts,
+    // cx, cy = -(1 + m) psi mu_d / 2
+    for (int k = li; k < S2; k += 64) {
+        const int ky = k / s, kx = k - ky * s;
+        const int lx = kx + 1, ly = ky + 1;
+        const float T = I0s(lx, ly);
+        const float g0 = 0.5f * (I0s(lx + 1, ly) - I0s(lx - 1, ly));
+        const float g1 = 0.5f * (I0s(lx, ly + 1) - I0s(lx, ly - 1));
+        const float *q = raw1 + ky * w1 + kx;
+        const float J = b00 * q[0] + b10 * q[1] + b01 * q[w1] + b11 * q[w1 + 1];
+        float ps, dps;
+        psi_and_slope(A, J - g1m * T - mc.y, ps, dps);
+        const float Tp = (T - Tm) * iTs;
+        const float mphi = g1m * (mu[0] * g0 + mu[1] * g1) - mu[2] * Tp - mu[3];
+        const float c1 = dps * mphi;
+        C1[k] = c1;
+        A0[k] = g1m * c1 + ps * mu[2] * iTs;
+        CX[k] = -0.5f * g1m * ps * mu[0];
+        CY[k] = -0.5f * g1m * ps * mu[1];
+    }
+    __syncthreads();
+    auto at = [&](const float *f, int a, int b) { return (a >= 0 && a < s && b >= 0 && b < s) ? f[b * s + a] : 0.f; };
+    const int wf = s + 2;
+    float *F = raw0;
+    for (int c = li; c < wf * wf; c += 64) {
+        const int b = c / wf - 1, a = c - (b + 1) * wf - 1;
+        F[c] = at(A0, a, b) + at(CX, a - 1, b) - at(CX, a + 1, b) + at(CY, a, b - 1) - at(CY, a, b + 1);
+    }
+    float *dI1 = A.grad1 + Pr.g1;
+    for (int c = li; c < n1; c += 64) {
+        const int Y = c / w1, X = c - Y * w1;
+        const float val = -(b00 * at(C1, X, Y) + b10 * at(C1, X - 1, Y) + b01 * at(C1, X, Y - 1) + b11 * at(C1, X - 1, Y - 1));
+        if (val != 0.f)
+            unsafeAtomicAdd(dI1 + (int64_t)clampi(oy1 + Y, 0, H - 1) * Pr.gpitch1 + clampi(ox1 + X, 0, W - 1), val);
+    }
+    __syncthreads();
+    float *dI0 = A.grad0 + Pr.g0;
+    for (int c = li; c < n0; c += 64) {
+        const int Y = c / w0, X = c - Y * w0;
+        auto f = [&](int x, int y) { return (x >= 0 && x < wf && y >= 0 && y < wf) ? F[y * wf + x] : 0.f; };
+        const float val = a00 * f(X, Y) + a10 * f(X - 1, Y) + a01 * f(X, Y - 1) + a11 * f(X - 1, Y - 1);
+        if (val != 0.f)
+            unsafeAtomicAdd(dI0 + (int64_t)clampi(oy0 + Y, 0, H - 1) * Pr.gpitch0 + clampi(ox0 + X, 0, W - 1), val);
+    }
+}
+
 size_t adjoint_lds_bytes(int s)
 {
-    return sizeof(float) * (size_t)((s + 3) * (s + 3) + (s + 1) * (s + 1) + 3 * s * s);
+    return sizeof(float) * (size_t)((s + 3) * (s + 3) + (s + 1) * (s + 1) + 4 * s * s);
 }
 
 hipError_t launch_track_adjoint(const AdjParams &A, int dtype, hipStream_t st)
 {
     if (A.n <= 0) return hipSuccess;
     const size_t lds = adjoint_lds_bytes(A.s);
-    if (dtype == DGF_U8)
+    if (A.illum) {
+        if (dtype == DGF_U8)
+            hipLaunchKernelGGL(k_track_adjoint_illum<uint8_t>, dim3((unsigned)A.n), dim3(64), lds, st, A);
+        else
+            hipLaunchKernelGGL(k_track_adjoint_illum<float>, dim3((unsigned)A.n), dim3(64), lds, st, A);
+    } else if (dtype == DGF_U8)
         hipLaunchKernelGGL(k_track_adjoint<uint8_t>, dim3((unsigned)A.n), dim3(64), lds, st, A);
     else
         hipLaunchKernelGGL(k_track_adjoint<float>, dim3((unsigned)A.n), dim3(64), lds, st, A);
@@ -309,7 +498,7 @@ void fill_adjoint_constants(AdjParams &A, const dgf_track_opts &o)
 extern "C" int dgf_track_backward(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n,
                                   int32_t support, const dgf_track_opts *opts, const float *flow,
                                   const uint8_t *status, const float *dflow, float *dI0, float *dI1, float *dpoints,
-                                  void *stream)
+                                  const float *illum, void *stream)
 {
     using namespace dgf;
     auto ok = [](const dgf_image *im) {
@@ -326,10 +515,14 @@ extern "C" int dgf_track_backward(const dgf_image *I0, const dgf_image *I1, cons
     dgf_track_opts o;
     if (opts) {
         o = *opts;
-        if (o.flags != 0) return DGF_ERR_UNSUPPORTED;
+        if ((o.flags & ~DGF_TRACK_ILLUM) != 0) return DGF_ERR_UNSUPPORTED;
     } else {
         dgf_track_opts_default(&o);
     }
+    const bool im = (o.flags & DGF_TRACK_ILLUM) != 0;
+    if (im && dpoints) return DGF_ERR_UNSUPPORTED; // the point gradient covers the plain model
+    if (im && n > 0 && !illum) return DGF_ERR_INVALID_ARG;
+    if (!im && illum) return DGF_ERR_INVALID_ARG;
     if (!(o.sigma1 >= 0.f) || !(o.sigma2 >= 0.f)) return DGF_ERR_INVALID_ARG;
     if (std::isinf(o.sigma2) && !std::isinf(o.sigma1)) return DGF_ERR_INVALID_ARG;
     if (n == 0) return DGF_OK;
@@ -345,6 +538,7 @@ extern "C" int dgf_track_backward(const dgf_image *I0, const dgf_image *I1, cons
     A.dflow = dflow;
     A.status = status;
     A.dpoints = dpoints;
+    A.illum = im ? illum : nullptr;
     A.n = n;
     fill_adjoint_constants(A, o);
     return launch_track_adjoint(A, DGF_F32, (hipStream_t)stream) == hipSuccess ? DGF_OK : DGF_ERR_HIP;

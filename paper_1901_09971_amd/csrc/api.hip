@@ -216,7 +216,7 @@ int validate_track(const dgf_image *I0, const dgf_image *I1, const float *points
 // Tracking on pyramids already in `workspace`, with an explicit launch shape (validated).
 int track_run_with(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
                    int32_t support, int32_t iters, const dgf_track_opts &o, const void *workspace, float *flow,
-                   uint8_t *status, int32_t *iters_out, TrackTuning tune, hipStream_t st)
+                   uint8_t *status, int32_t *iters_out, TrackTuning tune, hipStream_t st, float *illum_out)
 {
     if (o.flags & DGF_TRACK_ILLUM) tune = illum_tuning(support, tune);
     if (!track_shape_ok(support, tune)) return DGF_ERR_UNSUPPORTED;
@@ -230,6 +230,7 @@ int track_run_with(const dgf_image *I0, const dgf_image *I1, const float *points
     P.flow = flow;
     P.status = status;
     P.iters_out = iters_out;
+    P.illum_out = illum_out;
     P.L = levels;
     P.iters = iters;
     fill_track_geometry(P, support, tune.margin, tune.lpp, tune.kind);
@@ -243,22 +244,23 @@ extern "C" {
 
 int dgf_track_run(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
                   int32_t support, int32_t iters, const dgf_track_opts *opts, const void *workspace, size_t ws_bytes,
-                  float *flow, uint8_t *status, int32_t *iters_out, void *stream)
+                  float *flow, uint8_t *status, int32_t *iters_out, float *illum_out, void *stream)
 {
     dgf_track_opts o;
     const int rc = validate_track(I0, I1, points, n, levels, support, iters, opts, workspace, ws_bytes, flow, status, &o);
     if (rc != DGF_OK) return rc;
+    if (illum_out && !(o.flags & DGF_TRACK_ILLUM)) return DGF_ERR_INVALID_ARG;
     return track_run_with(I0, I1, points, n, levels, support, iters, o, workspace, flow, status, iters_out,
-                          tuning_for(support, levels, I0->dtype, n), (hipStream_t)stream);
+                          tuning_for(support, levels, I0->dtype, n), (hipStream_t)stream, illum_out);
 }
 
 int dgf_track(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
               int32_t support, int32_t iters, const dgf_track_opts *opts, void *workspace, size_t ws_bytes,
-              float *flow, uint8_t *status, int32_t *iters_out, void *stream)
+              float *flow, uint8_t *status, int32_t *iters_out, float *illum_out, void *stream)
 {
     // validate everything first, so that an error launches nothing
     int rc = dgf_track_run(I0, I1, points, 0, levels, support, iters, opts, workspace, ws_bytes, flow, status,
-                           iters_out, stream);
+                           iters_out, illum_out, stream);
     if (rc != DGF_OK) return rc;
     if (n < 0) return DGF_ERR_INVALID_ARG;
     if (n > 0 && (!points || !flow || !status)) return DGF_ERR_INVALID_ARG;
@@ -266,7 +268,7 @@ int dgf_track(const dgf_image *I0, const dgf_image *I1, const float *points, int
     rc = dgf_track_pyramids(I0, I1, levels, workspace, ws_bytes, stream);
     if (rc != DGF_OK) return rc;
     return dgf_track_run(I0, I1, points, n, levels, support, iters, opts, workspace, ws_bytes, flow, status,
-                         iters_out, stream);
+                         iters_out, illum_out, stream);
 }
 
 } // extern "C"

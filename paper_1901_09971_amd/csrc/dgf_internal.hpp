@@ -190,6 +190,7 @@ struct TrackParams {
     float *flow;
     uint8_t *status;
     int32_t *iters_out;
+    float *illum_out;    // illumination model: (m, c) per point (nullable)
     int32_t L, s, r, iters;
     int32_t ppl;         // pixel slots per lane actually used (ceil(s^2 / LPP))
     int32_t M;           // I1 tile margin, px on each side
@@ -370,6 +371,7 @@ struct AdjParams {
     const float *pts, *flow, *dflow;
     const uint8_t *status;
     float *dpoints;        // nullable: dL/dp per point (written)
+    const float *illum;    // illumination model: (m, c) per point from the forward pass, else null
     int64_t n;
     float s1, s2, dpsi_mid; // thresholds and the middle-band slope -sigma1 / (sigma2 - sigma1)
     int32_t mode;

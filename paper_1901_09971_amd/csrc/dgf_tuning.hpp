@@ -22,7 +22,7 @@ int validate_track(const dgf_image *I0, const dgf_image *I1, const float *points
                    const float *flow, const uint8_t *status, dgf_track_opts *o);
 int track_run_with(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
                    int32_t support, int32_t iters, const dgf_track_opts &o, const void *workspace, float *flow,
-                   uint8_t *status, int32_t *iters_out, TrackTuning tune, hipStream_t st);
+                   uint8_t *status, int32_t *iters_out, TrackTuning tune, hipStream_t st, float *illum_out = nullptr);
 void set_tuning(int support, int dtype, const TrackTuning &t);
 bool get_installed(int support, int dtype, TrackTuning *out);
 

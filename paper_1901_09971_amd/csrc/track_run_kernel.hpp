@@ -497,6 +497,9 @@ __global__ __launch_bounds__(256) void k_track_run(TrackParams P)
         reinterpret_cast<float2 *>(P.flow)[pidx] = make_float2(ux, uy);
         P.status[pidx] = (uint8_t)status;
         if (P.iters_out) P.iters_out[pidx] = it_total;
+        if constexpr (IM) {
+            if (P.illum_out) reinterpret_cast<float2 *>(P.illum_out)[pidx] = make_float2(im_m, im_c);
+        }
     }
     if (!P.persistent) break;
     item = next_item(P, home, visit);

@@ -107,7 +107,7 @@ def test_argument_validation_before_launch():
 
     def track(I0=im, I1=im, pts=P, n=10, levels=3, s=9, iters=10, opts=None, wsp=P, wsb=ws, flow=P, st=P):
         return L.dgf_track(ctypes.byref(I0), ctypes.byref(I1), pts, n, levels, s, iters, opts, wsp, wsb, flow, st, None,
-                           None)
+                           None, None)
 
     assert track(I1=_img(w=63)) == -1
     assert track(I1=_img(dtype=1, pitch=256)) == -1
