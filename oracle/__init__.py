@@ -18,10 +18,15 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "degraf_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "epic_oracle.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 ST_CONVERGED, ST_NOT_CONVERGED, ST_ILL_CONDITIONED, ST_OUT_OF_BOUNDS = 0, 1, 2, 3
+
+# Interpolation constants: k neighbours (Section 3 "Parameters"), the flat step cost kappa and
+# the weight half-distance h of the geodesic reading (both in edge-map units).
+EPIC_DEFAULTS = dict(k=128, kappa=8, h=64)
 
 # Default tracker constants on the 0..255 intensity scale (same meaning as the library's
 # default options; the values are restated here, not imported).
@@ -30,19 +35,23 @@ DEFAULTS = dict(sigma1=8.0, sigma2=32.0, eps_coarse=1e-2, eps_fine=1e-4, min_eig
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain C99, OpenMP for the loop over points)."""
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+    if force or _stale():
         tmp = _LIB_PATH + ".tmp"
-        cmd = ["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-fopenmp", "-o", tmp, _SRC, "-lm"]
+        cmd = ["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-fopenmp", "-o", tmp, *_SRCS, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
+
+
+def _stale() -> bool:
+    return not os.path.exists(_LIB_PATH) or any(os.path.getmtime(_LIB_PATH) < os.path.getmtime(f) for f in _SRCS)
 
 
 def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+    if _stale():
         build(force=True)
     lib = ctypes.CDLL(_LIB_PATH)
     P = ctypes.c_void_p
@@ -71,6 +80,14 @@ def _load():
     lib.or_track_grad.argtypes = [P, P, i32, i32, P, i64, i32, f64, f64, P, P, P, P, P, P]
     lib.or_track_grad_illum.argtypes = [P, P, i32, i32, P, i64, i32, f64, f64, P, P, P, P, P, P]
     lib.or_track_grad_illum.restype = i32
+    lib.or_epic_edges.argtypes = [P, i32, i32, i64, P]
+    lib.or_epic_edges.restype = None
+    lib.or_epic_voronoi.argtypes = [P, i32, i32, i64, P, P, i64, i32, P, P, P]
+    lib.or_epic_voronoi.restype = i32
+    lib.or_epic.argtypes = [P, i32, i32, i64, P, P, P, i64, i32, i32, i32, P, P, P, P, P, P, P]
+    lib.or_epic.restype = i32
+    lib.or_flow_error.argtypes = [P, P, P, i64, f64, P]
+    lib.or_flow_error.restype = None
     lib.or_detect_f64.argtypes = [P, i32, i32, i64, i32, i32, P, P]
     lib.or_detect_f64.restype = i64
     lib.or_detect_grad.argtypes = [P, i32, i32, i64, i32, i32, P, P, P]
@@ -272,3 +289,68 @@ def track_grad_illum(I0: np.ndarray, I1: np.ndarray, points: np.ndarray, support
     if rc != 0:
         raise ValueError(f"or_track_grad_illum failed: {rc}")
     return dI0, dI1
+
+
+# ---- dense interpolation (Section 2 "Interpolation") ------------------------------------------
+
+def epic_edges(I: np.ndarray) -> np.ndarray:
+    """Integer edge map |I(x+1)-I(x-1)| + |I(y+1)-I(y-1)| of a uint8 frame (replicated border)."""
+    a = np.ascontiguousarray(I, dtype=np.uint8)
+    H, W = a.shape
+    E = np.zeros((H, W), np.int32)
+    _load().or_epic_edges(_ptr(a), W, H, W, _ptr(E))
+    return E
+
+
+def epic_voronoi(I: np.ndarray, points: np.ndarray, status: np.ndarray, kappa=EPIC_DEFAULTS["kappa"]):
+    """Geodesic Voronoi partition of the pixels among the converged points: (D int64 [H, W],
+    L int32 [H, W], alive uint8 [n])."""
+    a = np.ascontiguousarray(I, dtype=np.uint8)
+    H, W = a.shape
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 2)
+    st = np.ascontiguousarray(status, dtype=np.uint8)
+    D = np.zeros((H, W), np.int64)
+    L = np.zeros((H, W), np.int32)
+    alive = np.zeros(pts.shape[0], np.uint8)
+    rc = _load().or_epic_voronoi(_ptr(a), W, H, W, _ptr(pts), _ptr(st), pts.shape[0], kappa, _ptr(D), _ptr(L),
+                                 _ptr(alive))
+    if rc != 0:
+        raise ValueError(f"or_epic_voronoi failed: {rc}")
+    return D, L, alive
+
+
+def epic(I: np.ndarray, points: np.ndarray, flow: np.ndarray, status: np.ndarray, k=EPIC_DEFAULTS["k"],
+         kappa=EPIC_DEFAULTS["kappa"], h=EPIC_DEFAULTS["h"], full: bool = False):
+    """Dense flow float64 [H, W, 2] interpolated from the converged points.  With ``full`` also
+    returns a dict of the intermediate results: D, L, nb [n, k], nd [n, k], model [n, 6], alive."""
+    a = np.ascontiguousarray(I, dtype=np.uint8)
+    H, W = a.shape
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 2)
+    fl = np.ascontiguousarray(flow, dtype=np.float64).reshape(-1, 2)
+    st = np.ascontiguousarray(status, dtype=np.uint8)
+    n = pts.shape[0]
+    dense = np.zeros((H, W, 2), np.float64)
+    D = np.zeros((H, W), np.int64) if full else None
+    L = np.zeros((H, W), np.int32) if full else None
+    nb = np.zeros((n, k), np.int32) if full else None
+    nd = np.zeros((n, k), np.int64) if full else None
+    model = np.zeros((n, 6), np.float64) if full else None
+    alive = np.zeros(n, np.uint8) if full else None
+    rc = _load().or_epic(_ptr(a), W, H, W, _ptr(pts), _ptr(fl), _ptr(st), n, k, kappa, h, _ptr(dense), _ptr(D),
+                         _ptr(L), _ptr(nb), _ptr(nd), _ptr(model), _ptr(alive))
+    if rc != 0:
+        raise ValueError(f"or_epic failed: {rc}")
+    if full:
+        return dense, dict(D=D, L=L, nb=nb, nd=nd, model=model, alive=alive)
+    return dense
+
+
+def flow_error(flow: np.ndarray, ref: np.ndarray, valid: np.ndarray | None = None, thresh: float = 3.0):
+    """(mean endpoint error, fraction of pixels with error > thresh px, pixel count) over ``valid``."""
+    f = np.ascontiguousarray(flow, dtype=np.float64).reshape(-1, 2)
+    r = np.ascontiguousarray(ref, dtype=np.float64).reshape(-1, 2)
+    v = None if valid is None else np.ascontiguousarray(valid, dtype=np.uint8).reshape(-1)
+    out = np.zeros(3, np.float64)
+    _load().or_flow_error(_ptr(f), _ptr(r), _ptr(v), f.shape[0], thresh, _ptr(out))
+    cnt = out[2]
+    return (out[0] / cnt if cnt else float("nan")), (out[1] / cnt if cnt else float("nan")), int(cnt)
