@@ -82,7 +82,7 @@ def _load():
     lib.or_track_grad_illum.restype = i32
     lib.or_epic_edges.argtypes = [P, i32, i32, i64, P]
     lib.or_epic_edges.restype = None
-    lib.or_epic_voronoi.argtypes = [P, i32, i32, i64, P, P, i64, i32, P, P, P]
+    lib.or_epic_voronoi.argtypes = [P, i32, i32, i64, P, P, P, i64, i32, P, P, P]
     lib.or_epic_voronoi.restype = i32
     lib.or_epic.argtypes = [P, i32, i32, i64, P, P, P, i64, i32, i32, i32, P, P, P, P, P, P, P]
     lib.or_epic.restype = i32
@@ -312,8 +312,8 @@ def epic_voronoi(I: np.ndarray, points: np.ndarray, status: np.ndarray, kappa=EP
     D = np.zeros((H, W), np.int64)
     L = np.zeros((H, W), np.int32)
     alive = np.zeros(pts.shape[0], np.uint8)
-    rc = _load().or_epic_voronoi(_ptr(a), W, H, W, _ptr(pts), _ptr(st), pts.shape[0], kappa, _ptr(D), _ptr(L),
-                                 _ptr(alive))
+    rc = _load().or_epic_voronoi(_ptr(a), W, H, W, _ptr(pts), None, _ptr(st), pts.shape[0], kappa, _ptr(D),
+                                 _ptr(L), _ptr(alive))
     if rc != 0:
         raise ValueError(f"or_epic_voronoi failed: {rc}")
     return D, L, alive

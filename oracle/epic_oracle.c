@@ -99,15 +99,16 @@ static int64_t seed_pixel(double x, double y, int W, int H)
 
 /*
  * Geodesic Voronoi partition.  Step cost between 4-neighbours p, q: kappa + E(p) + E(q) (an
- * integer, so path costs are exact).  Seeds: the points with status 0 (converged), at their seed
- * pixels; a point whose seed pixel is that of a lower-index seed is dropped.  For every pixel q:
+ * integer, so path costs are exact).  Seeds: the points with status 0 (converged) whose position
+ * and flow (nullable) are finite, at their seed pixels; a point whose seed pixel is that of a
+ * lower-index seed is dropped.  For every pixel q:
  * D(q) = the least path cost from any seed, L(q) = the lowest seed index among the seeds that
  * reach q at cost D(q) (-1 and D = -1 when there is no seed).  Dijkstra on keys (cost, label)
  * ordered lexicographically: cost and label both carry along a path, so the least key of q is
  * (D(q), L(q)) exactly.
  */
-int or_epic_voronoi(const uint8_t *I, int W, int H, int64_t pitch, const double *pts, const uint8_t *status,
-                    int64_t n, int kappa, int64_t *D, int32_t *L, uint8_t *alive)
+int or_epic_voronoi(const uint8_t *I, int W, int H, int64_t pitch, const double *pts, const double *flow,
+                    const uint8_t *status, int64_t n, int kappa, int64_t *D, int32_t *L, uint8_t *alive)
 {
     if (W <= 0 || H <= 0 || kappa < 1) return OR_ERR_ARG;
     const int64_t N = (int64_t)W * H;
@@ -122,6 +123,8 @@ int or_epic_voronoi(const uint8_t *I, int W, int H, int64_t pitch, const double 
     for (int64_t i = 0; i < n; ++i) {
         alive[i] = 0;
         if (status[i] != 0) continue;
+        if (!isfinite(pts[2 * i]) || !isfinite(pts[2 * i + 1])) continue; /* cannot be placed */
+        if (flow && (!isfinite(flow[2 * i]) || !isfinite(flow[2 * i + 1]))) continue;
         const int64_t q = seed_pixel(pts[2 * i], pts[2 * i + 1], W, H);
         if (L[q] >= 0) continue; /* pixel already seeded by a lower index */
         D[q] = 0;
@@ -336,7 +339,7 @@ int or_epic(const uint8_t *I, int W, int H, int64_t pitch, const double *pts, co
     double *model = (double *)malloc((size_t)(6 * n + 1) * sizeof(double));
     int64_t *adj_off = NULL, *adj_t = NULL, *adj_w = NULL;
     if (!D || !L || !E || !alive || !nb || !nd || !model) goto out;
-    if ((rc = or_epic_voronoi(I, W, H, pitch, pts, status, n, kappa, D, L, alive)) != OR_OK) goto out;
+    if ((rc = or_epic_voronoi(I, W, H, pitch, pts, flow, status, n, kappa, D, L, alive)) != OR_OK) goto out;
     or_epic_edges(I, W, H, pitch, E);
     if ((rc = seed_graph(E, W, H, D, L, n, kappa, &adj_off, &adj_t, &adj_w)) != OR_OK) goto out;
     const int64_t dmax = 64 * (int64_t)h;

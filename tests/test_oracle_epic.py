@@ -221,6 +221,15 @@ def test_collinear_seeds_take_the_weighted_mean():
     assert np.all(aux2["model"][:, [0, 1, 3, 4]] == 0)
 
 
+def test_non_finite_points_are_not_seeds():
+    I = np.full((10, 12), 50, np.uint8)
+    pts = np.array([[np.nan, 3.0], [4.0, 4.0], [7.0, 2.0]])
+    fl = np.array([[1.0, 1.0], [2.0, -1.0], [np.inf, 0.0]])
+    dense, aux = oracle.epic(I, pts, fl, np.zeros(3, np.uint8), full=True)
+    assert list(aux["alive"]) == [0, 1, 0]
+    assert np.all(dense[..., 0] == 2.0) and np.all(dense[..., 1] == -1.0)
+
+
 def test_single_seed_and_no_seed():
     I = np.random.default_rng(0).integers(0, 256, (12, 15)).astype(np.uint8)
     pts = np.array([[4.2, 6.7], [8.0, 3.0]])
