@@ -241,29 +241,31 @@ static int seed_graph(const int32_t *E, int W, int H, const int64_t *D, const in
 /* Weighted least-squares affine model of the flow around one seed, centred at the seed's own
  * position (sx, sy):  u(x, y) = A (x - sx, y - sy, 1)^T with A 2x3 (row-major model[6]).
  * Weights w_j = 2^(-delta_j / h).  Degenerate (fewer than 3 neighbours, or a weighted position
- * covariance C with det C <= 1e-4 (tr C)^2): the weighted mean flow, model = (0, 0, mx, 0, 0, my). */
+ * covariance C with det C <= 1e-4 (tr C)^2): the weighted mean flow, model = (0, 0, mx, 0, 0, my).
+ * Otherwise the minimiser of sum_j w_j |A (x_j, y_j, 1) - u_j|^2, computed by Householder QR of
+ * the rows sqrt(w_j) (1, x_j, y_j) (the weights can span 64 binades, far beyond what the normal
+ * equations resolve). */
 static void fit_affine(const double *pts, const double *flow, const int32_t *nb, const int64_t *nd, int cnt,
                        int64_t s, int h, double model[6])
 {
     const double sx = pts[2 * s], sy = pts[2 * s + 1];
-    double M[3][3] = {{0}}, bx[3] = {0}, by[3] = {0}, sw = 0, mx = 0, my = 0;
+    double sw = 0, sx1 = 0, sy1 = 0, sxx = 0, sxy = 0, syy = 0, mx = 0, my = 0;
     for (int j = 0; j < cnt; ++j) {
         const int64_t t = nb[j];
         const double w = exp2(-(double)nd[j] / (double)h);
         const double x = pts[2 * t] - sx, y = pts[2 * t + 1] - sy;
-        const double phi[3] = {x, y, 1.0};
-        for (int a = 0; a < 3; ++a) {
-            for (int b = 0; b < 3; ++b) M[a][b] += w * phi[a] * phi[b];
-            bx[a] += w * phi[a] * flow[2 * t];
-            by[a] += w * phi[a] * flow[2 * t + 1];
-        }
         sw += w;
+        sx1 += w * x;
+        sy1 += w * y;
+        sxx += w * x * x;
+        sxy += w * x * y;
+        syy += w * y * y;
         mx += w * flow[2 * t];
         my += w * flow[2 * t + 1];
     }
     /* weighted covariance of the positions about their weighted mean */
-    const double ex = M[0][2] / sw, ey = M[1][2] / sw;
-    const double cxx = M[0][0] / sw - ex * ex, cyy = M[1][1] / sw - ey * ey, cxy = M[0][1] / sw - ex * ey;
+    const double ex = sx1 / sw, ey = sy1 / sw;
+    const double cxx = sxx / sw - ex * ex, cyy = syy / sw - ey * ey, cxy = sxy / sw - ex * ey;
     const double tr = cxx + cyy, det = cxx * cyy - cxy * cxy;
     if (cnt < 3 || !(det > 1e-4 * tr * tr)) {
         model[0] = model[1] = model[3] = model[4] = 0.0;
@@ -271,39 +273,54 @@ static void fit_affine(const double *pts, const double *flow, const int32_t *nb,
         model[5] = my / sw;
         return;
     }
-    /* solve M a = bx and M a = by by Gaussian elimination with partial pivoting */
-    double A[3][5];
-    for (int a = 0; a < 3; ++a) {
-        for (int b = 0; b < 3; ++b) A[a][b] = M[a][b];
-        A[a][3] = bx[a];
-        A[a][4] = by[a];
+    /* rows sqrt(w) (1, x, y | u, v); Householder reflections zero each column below the diagonal */
+    double *R = (double *)malloc((size_t)cnt * 5 * sizeof(double));
+    if (!R) {
+        for (int e = 0; e < 6; ++e) model[e] = NAN;
+        return;
+    }
+    for (int j = 0; j < cnt; ++j) {
+        const int64_t t = nb[j];
+        const double r = sqrt(exp2(-(double)nd[j] / (double)h));
+        R[5 * j + 0] = r;
+        R[5 * j + 1] = r * (pts[2 * t] - sx);
+        R[5 * j + 2] = r * (pts[2 * t + 1] - sy);
+        R[5 * j + 3] = r * flow[2 * t];
+        R[5 * j + 4] = r * flow[2 * t + 1];
     }
     for (int c = 0; c < 3; ++c) {
-        int piv = c;
-        for (int r = c + 1; r < 3; ++r)
-            if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
-        if (piv != c)
-            for (int k = 0; k < 5; ++k) {
-                const double tmp = A[c][k];
-                A[c][k] = A[piv][k];
-                A[piv][k] = tmp;
+        double norm = 0;
+        for (int j = c; j < cnt; ++j) norm += R[5 * j + c] * R[5 * j + c];
+        norm = sqrt(norm);
+        const double alpha = R[5 * c + c] > 0 ? -norm : norm; /* reflect onto -sign(x0) |x| e0 */
+        /* v = x - alpha e0, applied as H = I - 2 v v^T / (v^T v) to the remaining columns */
+        const double v0 = R[5 * c + c] - alpha;
+        double vv = v0 * v0;
+        for (int j = c + 1; j < cnt; ++j) vv += R[5 * j + c] * R[5 * j + c];
+        if (vv > 0)
+            for (int e = c + 1; e < 5; ++e) {
+                double dot = v0 * R[5 * c + e];
+                for (int j = c + 1; j < cnt; ++j) dot += R[5 * j + c] * R[5 * j + e];
+                const double f = 2.0 * dot / vv;
+                R[5 * c + e] -= f * v0;
+                for (int j = c + 1; j < cnt; ++j) R[5 * j + e] -= f * R[5 * j + c];
             }
-        for (int r = c + 1; r < 3; ++r) {
-            const double f = A[r][c] / A[c][c];
-            for (int k = c; k < 5; ++k) A[r][k] -= f * A[c][k];
-        }
+        R[5 * c + c] = alpha;
+        for (int j = c + 1; j < cnt; ++j) R[5 * j + c] = 0.0;
     }
-    double sol[2][3];
-    for (int rhs = 0; rhs < 2; ++rhs)
+    /* back substitution R c = (Q^T b)[0:3] for each right-hand side; c = (offset, d/dx, d/dy) */
+    for (int rhs = 0; rhs < 2; ++rhs) {
+        double c3[3];
         for (int r = 2; r >= 0; --r) {
-            double acc = A[r][3 + rhs];
-            for (int k = r + 1; k < 3; ++k) acc -= A[r][k] * sol[rhs][k];
-            sol[rhs][r] = acc / A[r][r];
+            double acc = R[5 * r + 3 + rhs];
+            for (int e = r + 1; e < 3; ++e) acc -= R[5 * r + e] * c3[e];
+            c3[r] = acc / R[5 * r + r];
         }
-    for (int k = 0; k < 3; ++k) {
-        model[k] = sol[0][k];
-        model[3 + k] = sol[1][k];
+        model[3 * rhs + 0] = c3[1];
+        model[3 * rhs + 1] = c3[2];
+        model[3 * rhs + 2] = c3[0];
     }
+    free(R);
 }
 
 /*

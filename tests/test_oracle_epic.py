@@ -186,6 +186,32 @@ def test_fit_is_weighted_least_squares():
     assert np.allclose(dense[..., 1], M[..., 3] * rx + M[..., 4] * ry + M[..., 5], atol=1e-12)
 
 
+def test_fit_with_weights_spanning_many_binades():
+    # h = 1 with a unit step cost: neighbour weights fall to 2^-50 within a few pixels; the fit
+    # is still the weighted least-squares minimiser (numpy's SVD solver, ~cond * eps)
+    rng = np.random.default_rng(3)
+    W, H = 150, 90
+    I0 = (rng.integers(0, 30, (H, W)) + np.where(np.arange(W)[None, :] > 70, 120, 0)).astype(np.uint8)
+    n = 700
+    pts = np.stack([rng.uniform(0, W - 1, n), rng.uniform(0, H - 1, n)], 1)
+    fl = rng.normal(size=(n, 2))
+    st = np.zeros(n, np.uint8)
+    _, aux = oracle.epic(I0, pts, fl, st, k=3, kappa=1, h=1, full=True)
+    worst_cond = 0.0
+    for s in np.nonzero(aux["alive"])[0]:
+        m = aux["nb"][s] >= 0
+        nb, nd = aux["nb"][s][m], aux["nd"][s][m]
+        if np.all(aux["model"][s, [0, 1, 3, 4]] == 0):
+            continue  # weighted mean
+        sw = np.sqrt(2.0 ** (-nd / 1.0))[:, None]
+        X = np.stack([pts[nb, 0] - pts[s, 0], pts[nb, 1] - pts[s, 1], np.ones(len(nb))], 1) * sw
+        worst_cond = max(worst_cond, np.linalg.cond(X))
+        sol = np.linalg.lstsq(X, fl[nb] * sw, rcond=None)[0]
+        ref = np.concatenate([sol[:, 0], sol[:, 1]])
+        assert np.abs(aux["model"][s] - ref).max() <= 1e-6 * max(1.0, np.abs(ref).max()), s
+    assert worst_cond > 1e7
+
+
 def test_affine_motion_is_reproduced_exactly():
     # (a low-contrast texture, so that every seed has enough neighbours for a full affine fit)
     rng = np.random.default_rng(7)
