@@ -319,6 +319,60 @@ int dgf_track_run(const dgf_image *I0, const dgf_image *I1, const float *points,
                   size_t ws_bytes, float *flow, uint8_t *status, int32_t *iters_out, float *illum_out,
                   void *stream);
 
+/* ---- dense flow by edge-preserving interpolation (Section 2 "Interpolation") ---------------- */
+
+/* Interpolation constants.  k: neighbours per pixel (Section 3 "Parameters": 128), 1 .. 256.
+ * kappa: cost of one pixel step on a flat image, >= 1 (default 8).  half_dist: geodesic distance
+ * over which a neighbour's weight halves, >= 1 (default 64), in the same cost units. */
+typedef struct {
+    int32_t k;
+    int32_t kappa;
+    int32_t half_dist;
+} dgf_epic_opts;
+
+/* Fills *out with the defaults above.  DGF_ERR_INVALID_ARG for a null pointer. */
+int dgf_epic_opts_default(dgf_epic_opts *out);
+
+/* Workspace bytes dgf_epic needs for a width x height frame and n points (0 for bad sizes). */
+size_t dgf_epic_workspace_bytes(int32_t width, int32_t height, int64_t n);
+
+/* Dense flow for every pixel of I0 from the tracked points: each pixel q takes the affine motion
+ * fitted by weighted least squares to the k points geodesically nearest to it, nearness being a
+ * path cost that rises across image edges.
+ *   edge map   E(x, y) = |I0(x+1, y) - I0(x-1, y)| + |I0(x, y+1) - I0(x, y-1)| (replicated border)
+ *   step cost  between 4-neighbours p, q: kappa + E(p) + E(q); distances are exact integers
+ *   seeds      points with status DGF_ST_CONVERGED and a finite position and flow, at pixel
+ *              (floor(x + 1/2), floor(y + 1/2)) clamped into the image; a point whose pixel is
+ *              that of a lower-index seed takes no part
+ *   cells      D(q) = least path cost from any seed, L(q) = lowest seed index reaching q at D(q)
+ *   seed graph s, t joined when their cells touch (4-adjacency), edge length = least
+ *              D(p) + step(p, q) + D(q) over touching pixel pairs
+ *   neighbours of q: the k seeds t smallest in (delta(L(q), t), t), delta the seed-graph distance,
+ *              L(q) itself first, only those with delta <= 64 half_dist
+ *   fit        weights 2^(-delta / half_dist); model u(x, y) = A (x - sx, y - sy, 1)^T about the
+ *              cell seed's position (sx, sy); fewer than 3 neighbours or a weighted position
+ *              covariance C with det C <= 1e-4 (tr C)^2 give the weighted mean flow
+ *   dense(q)   the model of L(q) at q; NaN everywhere if there is no seed.
+ * Arguments (device pointers unless noted):
+ *   I0         DGF_U8 frame the points were detected on (width * height <= INT32_MAX)
+ *   points, flow : float[n][2] (level-0 positions and their tracked flow); status: uint8[n]
+ *   opts       nullable (defaults)
+ *   workspace  >= dgf_epic_workspace_bytes(width, height, n) bytes
+ *   dense      out, float rows of dense_pitch floats (even, >= 2 width), 8-byte aligned: (u, v)
+ *   labels, dist : out, nullable, int32 / uint32 [height][width]: L(q) (-1 without seeds) and
+ *              D(q) (0xFFFFFFFF without seeds)
+ *   nbr, nbr_dist : out, nullable together, int32 / uint32 [n][k]: each seed's neighbours and
+ *              graph distances in order, unused entries -1 / 0xFFFFFFFF (all for non-seeds)
+ *   model      out, nullable, float[n][6]: the row-major 2x3 A of each seed (NaN for non-seeds)
+ * Unlike the other calls this one synchronises `stream`: the geodesic relaxation runs until a
+ * pass changes nothing, which the host reads back.  Errors: DGF_ERR_UNSUPPORTED when
+ * (width + height - 2) (kappa + 1020) exceeds 2^32 - 2 (distances are 32-bit);
+ * DGF_ERR_CAPACITY when a seed's cell touches more than 32 others or a neighbour search
+ * holds more than 512 candidates (the outputs of the affected cells are then NaN). */
+int dgf_epic(const dgf_image *I0, const float *points, const float *flow, const uint8_t *status, int64_t n,
+             const dgf_epic_opts *opts, void *workspace, size_t ws_bytes, float *dense, int64_t dense_pitch,
+             int32_t *labels, uint32_t *dist, int32_t *nbr, uint32_t *nbr_dist, float *model, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -37,6 +37,10 @@ class DgfTuning(ctypes.Structure):
                 ("kernel", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
+class DgfEpicOpts(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("kappa", ctypes.c_int32), ("half_dist", ctypes.c_int32)]
+
+
 class DgfError(RuntimeError):
     def __init__(self, code: int, where: str):
         super().__init__(f"{where}: {strerror(code)} ({code})")
@@ -73,6 +77,9 @@ SIGNATURES = {
     "dgf_batch_grad_size": (I64, [P, P]),
     "dgf_batch_backward": (ctypes.c_int, [P, P, P, P, P, P, P]),
     "dgf_batch_destroy": (ctypes.c_int, [P]),
+    "dgf_epic_opts_default": (ctypes.c_int, [ctypes.POINTER(DgfEpicOpts)]),
+    "dgf_epic_workspace_bytes": (SZ, [I32, I32, I64]),
+    "dgf_epic": (ctypes.c_int, [IMG, P, P, P, I64, ctypes.POINTER(DgfEpicOpts), P, SZ, P, I64, P, P, P, P, P, P]),
     "dgf_get_tuning": (ctypes.c_int, [I32, I32, I32, I64, ctypes.POINTER(DgfTuning)]),
     "dgf_set_tuning": (ctypes.c_int, [I32, I32, ctypes.POINTER(DgfTuning)]),
     "dgf_autotune": (ctypes.c_int, [IMG, IMG, P, I64, I32, I32, I32, OPTS, P, SZ, P, P, ctypes.c_char_p,

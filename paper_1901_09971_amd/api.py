@@ -9,7 +9,7 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import DGF_F32, DGF_TRACK_ILLUM, DGF_U8, DgfImage, DgfTrackOpts, check, lib
+from ._lib import DGF_F32, DGF_TRACK_ILLUM, DGF_U8, DgfEpicOpts, DgfImage, DgfTrackOpts, check, lib
 
 
 @dataclass
@@ -261,6 +261,59 @@ class TrackFn(torch.autograd.Function):
         if dflow is not None:
             track_backward(I0, I1, points, ctx.support, flow, status, dflow, dI0, dI1, ctx.opts, dpoints, ill)
         return dI0, dI1, dpoints, None, None, None, None
+
+
+@dataclass
+class EpicOpts:
+    """Interpolation constants; see dgf_epic_opts in the C header."""
+    k: int = 128
+    kappa: int = 8
+    half_dist: int = 64
+
+    def to_c(self) -> DgfEpicOpts:
+        return DgfEpicOpts(self.k, self.kappa, self.half_dist)
+
+
+def epic_workspace_bytes(width: int, height: int, n: int) -> int:
+    return int(lib().dgf_epic_workspace_bytes(width, height, n))
+
+
+def epic(frame: torch.Tensor, points: torch.Tensor, flow: torch.Tensor, status: torch.Tensor,
+         opts: EpicOpts | None = None, return_aux: bool = False, workspace: torch.Tensor | None = None):
+    """Dense flow float32 [H, W, 2] of the uint8 ``frame`` interpolated from the tracked ``points``
+    (float32 [n, 2]) with their ``flow`` and ``status`` (dgf_epic).  With ``return_aux`` also a dict
+    of labels and dist [H, W], nbr and nbr_dist [n, k] and model [n, 6].  Synchronises the stream."""
+    a = _image(frame, "frame")
+    if a.dtype != DGF_U8:
+        raise ValueError("frame: expected uint8")
+    n = points.shape[0]
+    for t, name, dt in ((points, "points", torch.float32), (flow, "flow", torch.float32)):
+        if t.dtype != dt or t.shape != (n, 2) or not t.is_cuda:
+            raise ValueError(f"{name}: expected a float32 [n, 2] device tensor")
+    if status.dtype != torch.uint8 or status.shape != (n,) or not status.is_cuda:
+        raise ValueError("status: expected a uint8 [n] device tensor")
+    o = opts or EpicOpts()
+    H, W = frame.shape
+    ws_bytes = epic_workspace_bytes(W, H, n)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=frame.device)
+    dense = torch.empty((H, W, 2), dtype=torch.float32, device=frame.device)
+    aux = None
+    if return_aux:
+        dev = frame.device
+        aux = dict(labels=torch.empty((H, W), dtype=torch.int32, device=dev),
+                   dist=torch.empty((H, W), dtype=torch.int32, device=dev),  # holds uint32 bits
+                   nbr=torch.empty((n, o.k), dtype=torch.int32, device=dev),
+                   nbr_dist=torch.empty((n, o.k), dtype=torch.int32, device=dev),  # uint32 bits
+                   model=torch.empty((n, 6), dtype=torch.float32, device=dev))
+    g = (lambda key: _ptr(aux[key])) if aux else (lambda key: None)
+    c = o.to_c()
+    check(lib().dgf_epic(ctypes.byref(a), _ptr(points.contiguous()), _ptr(flow.contiguous()),
+                         _ptr(status.contiguous()), n, ctypes.byref(c), _ptr(workspace), workspace.numel(), _ptr(dense),
+                         2 * W, g("labels"), g("dist"), g("nbr"), g("nbr_dist"), g("model"), _stream()), "dgf_epic")
+    if return_aux:
+        return dense, aux
+    return dense
 
 
 def _tuning_dict(t) -> dict:

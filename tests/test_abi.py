@@ -146,3 +146,31 @@ def test_tuning_table_host_only():
     assert L.dgf_set_tuning(31, 0, ctypes.byref(_lib.DgfTuning(16, 1, 2, 1, -1.0))) == -3  # 61 slots: none compiled
     assert L.dgf_set_tuning(13, 0, ctypes.byref(_lib.DgfTuning(24, 1, 2, 1, -1.0))) == -3
     assert L.dgf_set_tuning(13, 0, None) == -1
+
+
+def test_epic_argument_checks_before_any_launch():
+    # every case is rejected on the host, so nothing reaches a device
+    import ctypes
+    from paper_1901_09971_amd._lib import DgfEpicOpts, DgfImage, lib
+    L = lib()
+    o = DgfEpicOpts()
+    assert L.dgf_epic_opts_default(ctypes.byref(o)) == 0 and (o.k, o.kappa, o.half_dist) == (128, 8, 64)
+    P = ctypes.c_void_p(1 << 20)
+    W, H, n = 64, 48, 10
+    ws = L.dgf_epic_workspace_bytes(W, H, n)
+    assert ws >= W * H * 10
+
+    def call(img=None, k=128, kappa=8, hd=64, n=n, wsb=ws, pitch=2 * W, dense=P, nbr=None, nbr_dist=None):
+        im = img or DgfImage(1 << 20, W, H, W, 0)
+        oo = DgfEpicOpts(k, kappa, hd)
+        return L.dgf_epic(ctypes.byref(im), P, P, P, n, ctypes.byref(oo), P, wsb, dense, pitch, None, None, nbr,
+                          nbr_dist, None, None)
+
+    assert call(img=DgfImage(1 << 20, W, H, 4 * W, 1)) == -1  # float frame
+    assert call(k=0) == -1 and call(k=257) == -1 and call(kappa=0) == -1 and call(hd=0) == -1
+    assert call(n=-1) == -1
+    assert call(pitch=2 * W - 2) == -1 and call(pitch=2 * W + 1) == -1 and call(dense=None) == -1
+    assert call(nbr=P) == -1  # nbr and nbr_dist go together
+    assert call(wsb=ws - 1) == -5
+    # distances must fit 32 bits: (W + H - 2) (kappa + 1020) <= 2^32 - 2
+    assert call(img=DgfImage(1 << 20, 8000, 10, 8000, 0), kappa=1 << 20) == -3

@@ -1,0 +1,141 @@
+"""GPU parity of the dense interpolation (dgf_epic, Section 2 "Interpolation") against the FP64
+oracle, through the C ABI.  Bar: the integer results -- geodesic distances and cells of every
+pixel, each seed's neighbour list and graph distances -- bit-exact; the affine models within
+1e-5 relative (FP64 fits on both sides, stored as float) and the dense field within 2e-4 px
+(FP32 evaluation of the float models)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1901_09971_amd as dgf
+from paper_1901_09971_amd import synth
+from paper_1901_09971_amd._lib import DgfError
+
+pytestmark = pytest.mark.gpu
+DENSE_TOL = 2e-4
+
+
+def _run_both(I0, pts, fl, st, opts=None, check_dense=True):
+    opts = opts or dgf.EpicOpts()
+    pts32, fl32 = pts.astype(np.float32), fl.astype(np.float32)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    dense, aux = dgf.epic(t(I0), t(pts32), t(fl32), t(st.astype(np.uint8)), opts=opts, return_aux=True)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in aux.items()}
+    gd = dense.cpu().numpy().astype(np.float64)
+    od, o = oracle.epic(I0, pts32.astype(np.float64), fl32.astype(np.float64), st, k=opts.k, kappa=opts.kappa,
+                        h=opts.half_dist, full=True)
+    alive = o["alive"].astype(bool)
+    print(f"{I0.shape[1]}x{I0.shape[0]} n={len(pts)} seeds={int(alive.sum())} k={opts.k}", flush=True)
+    # cells and distances: bit-exact
+    assert np.array_equal(g["labels"], o["L"])
+    assert np.array_equal(g["dist"].view(np.uint32).astype(np.int64), np.where(o["D"] < 0, 0xFFFFFFFF, o["D"]))
+    # neighbour lists and graph distances: bit-exact
+    assert np.array_equal(g["nbr"], o["nb"])
+    assert np.array_equal(g["nbr_dist"].view(np.uint32).astype(np.int64), np.where(o["nd"] < 0, 0xFFFFFFFF, o["nd"]))
+    # models
+    gm, om = g["model"].astype(np.float64), o["model"]
+    assert np.array_equal(np.isnan(gm), np.isnan(om))
+    if alive.any():
+        scale = np.maximum(np.abs(om[alive]), 1.0)
+        err = float(np.max(np.abs(gm[alive] - om[alive]) / scale))
+        assert err <= 1e-5, err
+    if check_dense:
+        assert np.array_equal(np.isnan(gd), np.isnan(od))
+        fin = ~np.isnan(od)
+        derr = float(np.abs(gd[fin] - od[fin]).max()) if fin.any() else 0.0
+        print(f"  max |dense - oracle| = {derr:.2e} px", flush=True)
+        assert derr <= DENSE_TOL, derr
+    return gd, g, od, o
+
+
+def test_layered_320x240_oracle_tracked():
+    I0, I1, gt, occ = synth.layered_pair(320, 240, seed=2, max_disp=40.0)
+    pts = oracle.detect(I0, 9, 5)[0]
+    fl, st = oracle.track(I0, I1, pts.astype(np.float32).astype(np.float64), 4, 21, 20)
+    gd, _, od, _ = _run_both(I0, pts, fl, st)
+    epe_g = oracle.flow_error(gd, gt, ~occ)
+    epe_o = oracle.flow_error(od, gt, ~occ)
+    print(f"  EPE gpu {epe_g[0]:.3f} / oracle {epe_o[0]:.3f}; >3px {epe_g[1]:.4f} / {epe_o[1]:.4f}", flush=True)
+
+
+def test_driving_1242x375_gpu_tracked():
+    # the benchmark pair: detection and tracking on the GPU, interpolation on both sides
+    I0, I1, gt, occ = synth.driving_1242x375()
+    a, b = torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda()
+    P = dgf.detect(a, 9, 5)
+    F, S = dgf.track(a, b, P, 5, 21, 20)
+    torch.cuda.synchronize()
+    _run_both(I0, P.cpu().numpy(), F.cpu().numpy(), S.cpu().numpy())
+
+
+@pytest.mark.parametrize("W,H", [(1, 1), (1, 9), (13, 1), (33, 31), (65, 40)])
+def test_small_and_ragged_images(W, H):
+    rng = np.random.default_rng(W * 100 + H)
+    I0 = rng.integers(0, 60, (H, W)).astype(np.uint8)
+    n = max(1, (W * H) // 20)
+    pts = np.stack([rng.uniform(-0.5, W - 0.5, n), rng.uniform(-0.5, H - 0.5, n)], 1)
+    fl = rng.normal(size=(n, 2)) * 4
+    st = np.zeros(n, np.uint8)
+    _run_both(I0, pts, fl, st)
+
+
+@pytest.mark.parametrize("k,kappa,h", [(1, 8, 64), (3, 1, 1), (17, 3, 200), (256, 8, 64)])
+def test_parameters(k, kappa, h):
+    rng = np.random.default_rng(k)
+    W, H = 150, 90
+    I0 = (rng.integers(0, 30, (H, W)) + np.where(np.arange(W)[None, :] > 70, 120, 0)).astype(np.uint8)
+    n = 700
+    pts = np.stack([rng.uniform(0, W - 1, n), rng.uniform(0, H - 1, n)], 1)
+    fl = np.where(pts[:, :1] > 70, [[3.0, -1.0]], [[-2.0, 0.5]]) + rng.normal(size=(n, 2)) * 0.1
+    st = (rng.uniform(size=n) < 0.1).astype(np.uint8)  # some points not converged
+    _run_both(I0, pts, fl, st, dgf.EpicOpts(k=k, kappa=kappa, half_dist=h))
+
+
+def test_seed_rules_and_degenerate_fields():
+    rng = np.random.default_rng(3)
+    W, H = 70, 50
+    I0 = rng.integers(0, 40, (H, W)).astype(np.uint8)
+    pts = np.array([[10.2, 10.4], [10.4, 9.6], [30.0, 20.0], [np.nan, 5.0], [50.0, 40.0], [60.7, 12.2]])
+    fl = np.array([[1.0, 0.0], [9.0, 9.0], [2.0, 1.0], [0.0, 0.0], [np.inf, 0.0], [-1.0, 3.0]])
+    st = np.array([0, 0, 0, 0, 0, 1], np.uint8)
+    _, g, _, o = _run_both(I0, pts, fl, st)
+    assert list(o["alive"]) == [1, 0, 1, 0, 0, 0]
+    # one seed: a constant field; none: NaN everywhere
+    gd, _, _, _ = _run_both(I0, pts[:1], fl[:1], st[:1])
+    assert np.all(gd[..., 0] == 1.0) and np.all(gd[..., 1] == 0.0)
+    gd, _, _, _ = _run_both(I0, pts[5:], fl[5:], st[5:])
+    assert np.all(np.isnan(gd))
+    t = torch.zeros((H, W), dtype=torch.uint8, device="cuda")
+    e = torch.zeros((0, 2), dtype=torch.float32, device="cuda")
+    dense = dgf.epic(t, e, e, torch.zeros(0, dtype=torch.uint8, device="cuda"))
+    assert torch.isnan(dense).all()
+
+
+def test_single_seed_long_paths():
+    # one seed in a corner of a textured frame: geodesic paths cross many relaxation tiles
+    rng = np.random.default_rng(9)
+    W, H = 700, 300
+    I0 = rng.integers(0, 50, (H, W)).astype(np.uint8)
+    I0[:, 350:353] = 255  # a wall with two gaps
+    I0[40:60, 350:353] = 20
+    I0[250:270, 350:353] = 20
+    pts = np.array([[3.0, 4.0], [690.0, 290.0]])
+    fl = np.array([[1.0, 2.0], [-3.0, 0.5]])
+    _run_both(I0, pts, fl, np.zeros(2, np.uint8))
+
+
+def test_too_many_touching_cells_is_reported():
+    # a central seed ringed by 100 seeds: its cell touches 44 cells (the oracle's partition), more
+    # than an adjacency row holds
+    W, H = 200, 200
+    I0 = np.full((H, W), 100, np.uint8)
+    ang = np.linspace(0, 2 * np.pi, 100, endpoint=False)
+    ring = np.stack([100 + 90 * np.cos(ang), 100 + 90 * np.sin(ang)], 1)
+    pts = np.concatenate([[[100.0, 100.0]], ring]).astype(np.float32)
+    fl = np.zeros_like(pts)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    with pytest.raises(DgfError) as e:
+        dgf.epic(t(I0), t(pts), t(fl), t(np.zeros(len(pts), np.uint8)))
+    assert e.value.code == -2
