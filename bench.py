@@ -60,7 +60,7 @@ def counter_traffic():
     return d
 
 
-def cpu_baseline(I0, I1, n_points, budget_s):
+def cpu_baseline(I0, I1, n_points, budget_s, seeds=None):
     import numpy as np
 
     import oracle  # the CPU baseline leg is the only product-side user of the oracle
@@ -90,12 +90,20 @@ def cpu_baseline(I0, I1, n_points, budget_s):
             model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": reps * n_points / el, "unit": "points/s", "cores": threads, "kind": "oracle",
-            "sample": f"{reps} full pass(es) of detect+track of the {n_points}-point 1242x375 pair, FP64, "
-                      f"{el:.1f} s wall",
-            "single_thread_value": len(sub) / el1,
-            "single_thread_sample": f"track of every 8th point ({len(sub)}), 1 thread, {el1:.1f} s",
-            "cpu_model": model}
+    res = {"value": reps * n_points / el, "unit": "points/s", "cores": threads, "kind": "oracle",
+           "sample": f"{reps} full pass(es) of detect+track of the {n_points}-point 1242x375 pair, FP64, "
+                     f"{el:.1f} s wall",
+           "single_thread_value": len(sub) / el1,
+           "single_thread_sample": f"track of every 8th point ({len(sub)}), 1 thread, {el1:.1f} s",
+           "cpu_model": model}
+    if seeds is not None:
+        # the dense interpolation of the GPU-tracked points of the same pair (geodesic partition
+        # single-threaded, neighbour searches and fits over the host threads)
+        P, F, S = seeds
+        t2 = time.perf_counter()
+        oracle.epic(I0, P.astype(np.float64), F.astype(np.float64), S)
+        res["interpolation_s"] = time.perf_counter() - t2
+    return res
 
 
 def batched_vs_plain(reps: int):
@@ -275,6 +283,49 @@ def differentiation(reps: int):
             "backward_includes": "tracker adjoint w.r.t. I0, I1 and points + gradient through detection"}
 
 
+def interpolation(reps: int):
+    """Dense interpolation (dgf_epic, k = 128) of the benchmark pair's tracked points: the GPU
+    detection and tracking output, then the dense field of every pixel.  The call synchronises
+    (its geodesic relaxation runs to a fixed point), so it is timed on the host clock.  Accuracy:
+    endpoint error and > 3 px rate of the dense field on the non-occluded pixels of the synthetic
+    ground truth.  Also returns the points, flows and statuses it interpolated."""
+    import numpy as np
+    import torch
+
+    import paper_1901_09971_amd as dgf
+    from paper_1901_09971_amd import synth
+
+    w = WORKLOAD
+    I0n, I1n, gt, occ = synth.driving_1242x375()
+    dev = torch.device("cuda", 0)
+    I0, I1 = torch.from_numpy(I0n).to(dev), torch.from_numpy(I1n).to(dev)
+    pts = dgf.detect(I0, w["window"], w["stride"])
+    flow, st = dgf.track(I0, I1, pts, w["levels"], w["support"], w["iters"])
+    ws = torch.empty(dgf.epic_workspace_bytes(w["W"], w["H"], pts.shape[0]), dtype=torch.uint8, device=dev)
+    dense = dgf.epic(I0, pts, flow, st, workspace=ws)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        dense = dgf.epic(I0, pts, flow, st, workspace=ws)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ms = float(np.median(times)) * 1e3
+    d = dense.cpu().numpy().astype(np.float64)
+    valid = ~occ
+    err = np.linalg.norm(d - gt, axis=-1)[valid]
+    P, F, S = pts.cpu().numpy(), flow.cpu().numpy(), st.cpu().numpy()
+    conv = S == 0
+    xi = np.clip(np.rint(P[conv, 0]).astype(np.int64), 0, w["W"] - 1)
+    yi = np.clip(np.rint(P[conv, 1]).astype(np.int64), 0, w["H"] - 1)
+    sparse_err = np.linalg.norm(F[conv] - gt[yi, xi], axis=-1)
+    return {"workload": "driving_1242x375 tracked points -> dense field, k 128, kappa 8, half-distance 64",
+            "seeds": int(conv.sum()), "pixels": w["W"] * w["H"], "reps": reps, "ms": ms,
+            "mpix_per_s": w["W"] * w["H"] / (ms * 1e-3) / 1e6,
+            "epe_noc_px": float(err.mean()), "outliers_3px_noc": float((err > 3.0).mean()),
+            "seed_epe_px": float(sparse_err.mean())}, (P, F, S)
+
+
 DENSITY = dict(name="density_2048x1024x4", W=2048, H=1024, pairs=4, window=9, stride=2, levels=6, support=21,
                iters=20)
 
@@ -374,6 +425,7 @@ def main():
     ap.add_argument("--no-illum", action="store_true", help="skip the illumination-model measurement")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation measurement")
     ap.add_argument("--density-reps", type=int, default=3)
+    ap.add_argument("--no-interp", action="store_true", help="skip the dense interpolation measurement")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -509,8 +561,11 @@ def main():
         out["differentiation"] = differentiation(args.steps)
     if not args.no_density:
         out["density"] = density_stress(args.density_reps)
+    seeds = None
+    if not args.no_interp:
+        out["interpolation"], seeds = interpolation(max(3, min(args.steps, 20)))
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(I0n, I1n, N, args.cpu_budget_s)
+        out["cpu_baseline"] = cpu_baseline(I0n, I1n, N, args.cpu_budget_s, seeds)
     print(json.dumps(out))
 
 

@@ -9,9 +9,10 @@
 // GPU structure (one pass each unless noted):
 //   k_epic_prep     edge map (uint16) and cleared tables, HBM bound
 //   k_epic_seed     one 64-bit atomicMin per converged point: key = (0 << 32) | index
-//   k_epic_relax    32x32 tiles relaxed in LDS to a local fixed point, written back with 64-bit
-//                   atomics; launched until a launch changes nothing (host checks a counter
-//                   every few launches: the one synchronisation of the call)
+//   k_epic_relax    32x32 tiles relaxed in LDS (Bellman-Ford sweeps over the tile, double
+//                   buffered), exchanging border pixels with their neighbours through 64-bit
+//                   atomics during the launch; launched until a launch changes nothing (host
+//                   checks a counter every few launches: the one synchronisation of the call)
 //   k_epic_graph    adjacent-cell pairs inserted into fixed-size per-seed adjacency rows
 //   k_epic_knn_fit  one wavefront per seed: Dijkstra on the seed graph with the frontier and a
 //                   hash index in LDS, stopped after k settles; FP64 weighted affine fit by
@@ -31,9 +32,12 @@ constexpr int kMaxDeg = 32;          // graph neighbours a seed can hold
 constexpr int kCand = 512;           // candidates one neighbour search can hold
 constexpr int kHash = 1024;          // LDS hash slots of one search (power of two, > kCand + kMaxDeg)
 constexpr int kMaxK = 256;           // largest k
-constexpr int kTile = 32;            // relaxation tile side
-constexpr int kTileThreads = 256;    // 8 rows of 32 lanes; each lane owns 4 pixels of its column
-constexpr int kLocalIters = 4 * kTile;
+constexpr int kRT = 32;              // relaxation tile side
+constexpr int kRT2 = kRT + 2;        // with the halo
+constexpr int kRelaxThreads = 256;   // each lane owns 4 pixels of one column
+constexpr int kExchange = 32;        // relaxation iterations between two halo exchanges
+constexpr int kMaxIters = 8192;      // relaxation iterations per tile and launch
+constexpr int kMaxPolls = 4096;      // halo polls of a still tile per launch
 constexpr int kChunk = 4;            // relaxation launches between two convergence checks
 constexpr int kMaxRelaxLaunches = 1 << 14;
 constexpr uint64_t kNoKey = ~0ull;
@@ -45,10 +49,11 @@ enum : uint32_t { kErrDegree = 1u, kErrCand = 2u };
 struct EpicWs {
     uint64_t *keys;  // [H*W]
     uint16_t *E;     // [H*W]
-    int32_t *adj_id; // [n][kMaxDeg], -1 = empty
-    uint32_t *adj_w; // [n][kMaxDeg]
+    uint64_t *adj;   // [n][kMaxDeg]: (edge length << 32) | neighbour, kNoKey = empty slot
     float *model;    // [n][8]: affine coefficients (6), seed position (2)
-    uint32_t *ctr;   // [kChunk] tiles changed per relaxation launch, then [1] error bits
+    uint32_t *ctr;   // [kChunk] tiles changed per relaxation launch, [1] error bits, [1] least edge,
+                     // [kChunk] busy count per relaxation launch
+    uint32_t *mail;  // [kChunk][tiles]: a neighbour published keys into this tile's halo
 };
 
 int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
@@ -62,15 +67,16 @@ int64_t ws_layout(int W, int H, int64_t n, EpicWs *ws, char *base)
         off += align256(bytes);
         return base ? base + o : nullptr;
     };
-    char *keys = take(8 * N), *E = take(2 * N), *aid = take(4 * n * kMaxDeg), *aw = take(4 * n * kMaxDeg);
-    char *model = take(32 * n), *ctr = take(4 * (kChunk + 1));
+    char *keys = take(8 * N), *E = take(2 * N), *adj = take(8 * n * kMaxDeg);
+    const int64_t tiles = (int64_t)((W + kRT - 1) / kRT) * ((H + kRT - 1) / kRT);
+    char *model = take(32 * n), *ctr = take(4 * (2 * kChunk + 2)), *mail = take(4 * kChunk * tiles);
     if (ws) {
         ws->keys = (uint64_t *)keys;
         ws->E = (uint16_t *)E;
-        ws->adj_id = (int32_t *)aid;
-        ws->adj_w = (uint32_t *)aw;
+        ws->adj = (uint64_t *)adj;
         ws->model = (float *)model;
         ws->ctr = (uint32_t *)ctr;
+        ws->mail = (uint32_t *)mail;
     }
     return off;
 }
@@ -97,11 +103,8 @@ __global__ void k_epic_prep(const uint8_t *I, int64_t pitch, int W, int H, int64
             ws.E[i] = (uint16_t)(abs(gx) + abs(gy));
             ws.keys[i] = kNoKey;
         }
-        if (i < S) {
-            ws.adj_id[i] = -1;
-            ws.adj_w[i] = 0xFFFFFFFFu;
-        }
-        if (i < kChunk + 1) ws.ctr[i] = 0u;
+        if (i < S) ws.adj[i] = kNoKey;
+        if (i < kChunk + 2) ws.ctr[i] = i == kChunk + 1 ? 0xFFFFFFFFu : 0u;
     }
 }
 
@@ -128,114 +131,270 @@ __global__ void k_epic_seed(const float *pts, const float *flow, const uint8_t *
     if (seed_pixel(pts, flow, status, i, W, H, q)) atomicMin((unsigned long long *)(keys + q), (unsigned long long)i);
 }
 
-// One relaxation round: each 32x32 tile (plus a one-pixel halo read from the current global
-// state) iterates key(p) = min(key(p), min over 4-neighbours q of key(q) + step(q, p)) in LDS until
-// nothing changes (or kLocalIters rounds), then writes its improved pixels back.  Keys only ever
-// decrease and always belong to a real path, so any interleaving of tiles converges to the exact
-// least keys; a launch in which no tile changes anything is at that fixed point.
-__global__ __launch_bounds__(kTileThreads) void k_epic_relax(int W, int H, int kappa, uint64_t *keys,
-                                                             const uint16_t *E, uint32_t *changed)
+// Key of the path that reaches a pixel from a neighbour holding key kn with a step of cost c:
+// the distance half saturates at all ones, so kNoKey stays kNoKey; a saturated distance is
+// never a least one (every least distance is below kDistCap) and is replaced in time.
+__device__ __forceinline__ uint64_t step_key(uint64_t kn, uint32_t c)
 {
-    constexpr int T2 = kTile + 2;
-    __shared__ uint64_t K[T2 * T2];
-    __shared__ uint16_t Es[T2 * T2];
-    const int x0 = (int)blockIdx.x * kTile - 1, y0 = (int)blockIdx.y * kTile - 1;
-    for (int c = threadIdx.x; c < T2 * T2; c += kTileThreads) {
-        const int ly = c / T2, lx = c - ly * T2;
+    const uint32_t hi = (uint32_t)(kn >> 32);
+    uint32_t d = hi + c;
+    d = d < hi ? 0xFFFFFFFFu : d;
+    return ((uint64_t)d << 32) | (kn & 0xFFFFFFFFull);
+}
+
+// One relaxation launch over 32x32 tiles.  Each tile holds its pixels and a one-pixel halo in
+// LDS (two buffers) and iterates key(p) = min(key(p), min over 4-neighbours q of key(q) +
+// step(q, p)) -- one barrier per iteration, each lane owning 4 pixels whose step costs stay in
+// registers.  Every kExchange iterations, and whenever it has stopped changing, a tile publishes
+// its newly improved border pixels with 64-bit atomicMin and posts mail to each neighbour tile
+// whose halo they touch; a tile with mail re-reads its halo.  Termination: `busy` counts the
+// tiles that are working plus the mail not yet taken (a publisher adds one for each mailbox it
+// fills, before it can itself go still), so it reaches zero only when no tile can change
+// anything.  A still tile (with `wait`: the whole grid resident at once) polls its mailbox and
+// the count, resuming on mail and leaving at zero; polls are bounded (kMaxPolls) so every tile
+// exits.  Keys only decrease and always belong to a real path, so any interleaving converges to
+// the exact least keys, and a launch in which no tile changes anything is at that fixed point.
+__global__ __launch_bounds__(kRelaxThreads) void k_epic_relax(int W, int H, int kappa, uint64_t *keys,
+                                                              const uint16_t *E, uint32_t *changed, uint32_t *busy,
+                                                              uint32_t *mail, int wait)
+{
+    __shared__ uint64_t K[2][kRT2 * kRT2];
+    __shared__ uint16_t Es[kRT2 * kRT2];
+    __shared__ uint32_t flags[2][kRelaxThreads / 64];
+    __shared__ uint32_t sides, got_mail, count_zero;
+    const int x0 = (int)blockIdx.x * kRT - 1, y0 = (int)blockIdx.y * kRT - 1;
+    const int me = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    const int nbr_tile[4] = {blockIdx.x > 0 ? me - 1 : -1, blockIdx.x + 1 < gridDim.x ? me + 1 : -1,
+                             blockIdx.y > 0 ? me - (int)gridDim.x : -1,
+                             blockIdx.y + 1 < gridDim.y ? me + (int)gridDim.x : -1};
+    // the halo ring: 4 kRT + 4 cells (top row, bottom row, left column, right column)
+    auto ring_cell = [&](int i) {
+        if (i < kRT2) return i;
+        if (i < 2 * kRT2) return (kRT + 1) * kRT2 + (i - kRT2);
+        i -= 2 * kRT2;
+        return i < kRT ? (i + 1) * kRT2 : (i - kRT + 1) * kRT2 + kRT + 1;
+    };
+    auto global_of = [&](int c, uint32_t &q) {
+        const int ly = c / kRT2, lx = c - ly * kRT2;
         const int gx = x0 + lx, gy = y0 + ly;
+        q = (uint32_t)gy * (uint32_t)W + (uint32_t)gx;
+        return gx >= 0 && gy >= 0 && gx < W && gy < H;
+    };
+    for (int c = threadIdx.x; c < kRT2 * kRT2; c += kRelaxThreads) {
+        uint32_t q;
         uint64_t k = kNoKey;
         uint16_t e = 0;
-        if (gx >= 0 && gy >= 0 && gx < W && gy < H) {
-            const uint32_t q = (uint32_t)gy * (uint32_t)W + (uint32_t)gx;
+        if (global_of(c, q)) {
             k = load_key(keys + q);
             e = E[q];
         }
-        K[c] = k;
+        K[0][c] = k;
+        K[1][c] = k;
         Es[c] = e;
     }
+    if (threadIdx.x == 0) sides = 0u;
     __syncthreads();
-    const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
-    int cell[4];
-    bool inside[4];
-    uint64_t orig[4];
+    const int tx = threadIdx.x % kRT, ty = threadIdx.x / kRT;
+    constexpr int kPix = kRT * kRT / kRelaxThreads;
+    int cell[kPix];
+    bool inside[kPix];
+    uint64_t own[kPix], orig[kPix], pub[kPix];
+    uint32_t cst[kPix][4]; // step costs from the left, right, upper and lower neighbour
+    uint32_t side_of[kPix]; // which neighbour tiles' halos this pixel belongs to (bit per side)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int lx = tx + 1, ly = ty + 8 * j + 1;
-        cell[j] = ly * T2 + lx;
+    for (int j = 0; j < kPix; ++j) {
+        const int lx = tx + 1, ly = ty + (kRelaxThreads / kRT) * j + 1;
+        const int c = ly * kRT2 + lx;
+        cell[j] = c;
         inside[j] = x0 + lx < W && y0 + ly < H;
-        orig[j] = K[cell[j]];
+        own[j] = orig[j] = pub[j] = K[0][c];
+        const uint32_t e = (uint32_t)kappa + Es[c];
+        cst[j][0] = e + Es[c - 1];
+        cst[j][1] = e + Es[c + 1];
+        cst[j][2] = e + Es[c - kRT2];
+        cst[j][3] = e + Es[c + kRT2];
+        side_of[j] = (lx == 1 ? 1u : 0u) | (lx == kRT ? 2u : 0u) | (ly == 1 ? 4u : 0u) | (ly == kRT ? 8u : 0u);
     }
-    for (int it = 0; it < kLocalIters; ++it) {
-        uint64_t nv[4];
-        bool imp = false;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int c = cell[j];
-            const uint64_t cur = K[c];
-            uint64_t best = cur;
-            if (inside[j]) {
-                const uint32_t ec = (uint32_t)kappa + Es[c];
-                const int nbc[4] = {c - 1, c + 1, c - T2, c + T2};
-#pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    const uint64_t kn = K[nbc[d]];
-                    if (kn == kNoKey) continue;
-                    uint64_t dist = (kn >> 32) + ec + Es[nbc[d]];
-                    dist = dist < kDistCap ? dist : kDistCap;
-                    const uint64_t cand = (dist << 32) | (kn & 0xFFFFFFFFull);
-                    best = cand < best ? cand : best;
-                }
+    // re-read the halo ring into both buffers
+    auto reload_halo = [&](int cur) {
+        for (int i = threadIdx.x; i < 4 * kRT + 4; i += kRelaxThreads) {
+            const int c = ring_cell(i);
+            uint32_t q;
+            if (!global_of(c, q)) continue;
+            const uint64_t k = load_key(keys + q);
+            if (k < K[cur][c]) {
+                K[0][c] = k;
+                K[1][c] = k;
             }
-            nv[j] = best;
-            imp |= best < cur;
         }
         __syncthreads();
+    };
+    // publish newly improved border pixels and post mail to the tiles whose halos they touch
+    auto publish = [&]() {
+        uint32_t my_sides = 0u;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) K[cell[j]] = nv[j];
-        if (!__syncthreads_or(imp)) break;
+        for (int j = 0; j < kPix; ++j) {
+            if (inside[j] && side_of[j] && own[j] < pub[j]) {
+                const int ly = ty + (kRelaxThreads / kRT) * j + 1;
+                const uint32_t q = (uint32_t)(y0 + ly) * (uint32_t)W + (uint32_t)(x0 + tx + 1);
+                atomicMin((unsigned long long *)(keys + q), (unsigned long long)own[j]);
+                pub[j] = own[j];
+                my_sides |= side_of[j];
+            }
+        }
+        if (my_sides) atomicOr(&sides, my_sides);
+        __builtin_amdgcn_s_waitcnt(0); // the key updates are performed before any mail is posted
+        __syncthreads();
+        if (threadIdx.x < 4 && ((sides >> threadIdx.x) & 1u) && nbr_tile[threadIdx.x] >= 0)
+            if (atomicExch(mail + nbr_tile[threadIdx.x], 1u) == 0u) atomicAdd(busy, 1u);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0) sides = 0u;
+    };
+    // take this tile's mail; a working tile already holds a busy count and returns the one the
+    // mail carried, a still tile takes it over
+    auto take_mail = [&](bool still_now) {
+        if (threadIdx.x == 0) {
+            uint32_t m = 0u;
+            if (__hip_atomic_load(mail + me, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) m = atomicExch(mail + me, 0u);
+            if (m && !still_now) atomicSub(busy, 1u);
+            got_mail = m;
+        }
+        __syncthreads();
+        return got_mail != 0u;
+    };
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int cur = 0, polls = 0;
+    bool still = false;
+    for (int it = 0; it < kMaxIters; ++it) {
+        // all sixteen neighbour keys first (independent LDS reads, one wait), then the minima
+        const uint64_t *Kc = K[cur];
+        uint64_t nk[kPix][4];
+#pragma unroll
+        for (int j = 0; j < kPix; ++j) {
+            const int c = cell[j];
+            nk[j][0] = Kc[c - 1];
+            nk[j][1] = Kc[c + 1];
+            nk[j][2] = Kc[c - kRT2];
+            nk[j][3] = Kc[c + kRT2];
+        }
+        bool ch = false;
+#pragma unroll
+        for (int j = 0; j < kPix; ++j) {
+            uint64_t best = own[j];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const uint64_t v = step_key(nk[j][d], cst[j][d]);
+                best = v < best ? v : best;
+            }
+            best = inside[j] ? best : own[j];
+            ch |= best < own[j];
+            own[j] = best;
+            K[cur ^ 1][cell[j]] = best;
+        }
+        // one barrier: each wavefront posts whether any of its lanes changed anything
+        const uint64_t changed_lanes = __ballot(ch);
+        if (lane == 0) flags[it & 1][wave] = changed_lanes != 0ull;
+        __syncthreads();
+        bool any = false;
+#pragma unroll
+        for (int w = 0; w < kRelaxThreads / 64; ++w) any |= flags[it & 1][w] != 0u;
+        cur ^= 1;
+        if (any && (it + 1) % kExchange != 0) continue;
+        publish();
+        if (take_mail(false)) {
+            reload_halo(cur);
+            continue;
+        }
+        if (any) continue;
+        // still
+        if (threadIdx.x == 0) atomicSub(busy, 1u);
+        still = true;
+        if (!wait) break;
+        bool resume = false;
+        while (polls < kMaxPolls) {
+            ++polls;
+            __builtin_amdgcn_s_sleep(2);
+            if (threadIdx.x == 0)
+                count_zero = __hip_atomic_load(busy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+            __syncthreads();
+            const bool zero = count_zero != 0u;
+            if (take_mail(true)) {
+                resume = true;
+                break;
+            }
+            if (zero) break;
+        }
+        if (!resume) break;
+        still = false;
+        reload_halo(cur);
     }
+    // leave: return the busy count of a working tile and of any mail not taken
     bool wrote = false;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint64_t k = K[cell[j]];
-        if (inside[j] && k < orig[j]) {
-            const uint32_t q = (uint32_t)(y0 + ty + 8 * j + 1) * (uint32_t)W + (uint32_t)(x0 + tx + 1);
-            atomicMin((unsigned long long *)(keys + q), (unsigned long long)k);
+    for (int j = 0; j < kPix; ++j) {
+        if (inside[j] && own[j] < orig[j]) {
+            const int ly = ty + (kRelaxThreads / kRT) * j + 1;
+            const uint32_t q = (uint32_t)(y0 + ly) * (uint32_t)W + (uint32_t)(x0 + tx + 1);
+            atomicMin((unsigned long long *)(keys + q), (unsigned long long)own[j]);
             wrote = true;
         }
+    }
+    if (threadIdx.x == 0) {
+        if (!still) atomicSub(busy, 1u);
+        if (atomicExch(mail + me, 0u)) atomicSub(busy, 1u);
     }
     if (__syncthreads_or(wrote) && threadIdx.x == 0) atomicAdd(changed, 1u);
 }
 
-__global__ void k_epic_clear(uint32_t *c, int m)
+__global__ void k_epic_clear_launch_counters(uint32_t *changed, uint32_t *busy, uint32_t *mail, int m,
+                                             uint32_t tiles)
 {
-    if ((int)threadIdx.x < m) c[threadIdx.x] = 0u;
+    if ((int)threadIdx.x < m) {
+        changed[threadIdx.x] = 0u;
+        busy[threadIdx.x] = tiles;
+    }
+    for (int64_t i = threadIdx.x; i < (int64_t)m * tiles; i += blockDim.x) mail[i] = 0u;
 }
 
-// Insert (or lower) the edge s -> t of length w into s's adjacency row.
-__device__ void adj_insert(const EpicWs &ws, uint32_t s, int32_t t, uint32_t w, uint32_t *err)
+// Insert (or lower) the edge s -> t of length w into s's adjacency row: a slot holds
+// (length << 32) | t, so once t owns a slot a 64-bit atomicMin keeps the least length.
+__device__ void adj_insert(const EpicWs &ws, uint32_t s, uint32_t t, uint32_t w, uint32_t *err)
 {
-    int32_t *ids = ws.adj_id + (int64_t)s * kMaxDeg;
+    unsigned long long *row = (unsigned long long *)(ws.adj + (int64_t)s * kMaxDeg);
+    const unsigned long long val = ((unsigned long long)w << 32) | t;
     for (int j = 0; j < kMaxDeg; ++j) {
-        int32_t v = __hip_atomic_load(ids + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (v == -1) {
-            const int32_t old = atomicCAS(ids + j, -1, t);
-            v = old == -1 ? t : old;
+        unsigned long long cur = __hip_atomic_load(row + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == kNoKey) {
+            cur = atomicCAS(row + j, (unsigned long long)kNoKey, val);
+            if (cur == kNoKey) return;
         }
-        if (v == t) {
-            atomicMin(ws.adj_w + (int64_t)s * kMaxDeg + j, w);
+        if ((uint32_t)cur == t) {
+            atomicMin(row + j, val);
             return;
         }
     }
     atomicOr(err, kErrDegree);
 }
 
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
 // Seed graph: every right / down pixel pair whose cells differ gives both cells an edge of
-// length D(p) + step(p, q) + D(q); each row keeps the least length per neighbour.
+// length D(p) + step(p, q) + D(q); each row keeps the least length per neighbour.  Also the
+// least edge length of the whole graph (one atomic per wavefront).
 __global__ void k_epic_graph(int W, int H, int kappa, const uint64_t *keys, const uint16_t *E, EpicWs ws,
-                             uint32_t *err)
+                             uint32_t *err, uint32_t *min_edge)
 {
     const uint32_t N = (uint32_t)W * (uint32_t)H;
+    uint32_t wmin = 0xFFFFFFFFu;
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < N; p += gridDim.x * blockDim.x) {
         const uint32_t y = p / (uint32_t)W, x = p - y * (uint32_t)W;
         const uint64_t kp = keys[p];
@@ -249,10 +408,13 @@ __global__ void k_epic_graph(int W, int H, int kappa, const uint64_t *keys, cons
             if (ls == lt) continue;
             const uint64_t w64 = (kp >> 32) + (uint64_t)kappa + E[p] + E[q] + (kq >> 32);
             const uint32_t w = w64 < 0xFFFFFFFFull ? (uint32_t)w64 : 0xFFFFFFFFu;
-            adj_insert(ws, ls, (int32_t)lt, w, err);
-            adj_insert(ws, lt, (int32_t)ls, w, err);
+            wmin = w < wmin ? w : wmin;
+            adj_insert(ws, ls, lt, w, err);
+            adj_insert(ws, lt, ls, w, err);
         }
     }
+    wmin = wave_min_u32(wmin);
+    if ((threadIdx.x & 63) == 0 && wmin != 0xFFFFFFFFu) atomicMin(min_edge, wmin);
 }
 
 struct EpicFit {
@@ -267,17 +429,8 @@ struct EpicFit {
     uint32_t *nbr_dist;
     float *model_out;
     uint32_t *err;
+    const uint32_t *min_edge;
 };
-
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint64_t w = __shfl_xor(v, o, 64);
-        v = w < v ? w : v;
-    }
-    return v;
-}
 
 __device__ __forceinline__ double wave_sum_f64(double v)
 {
@@ -289,19 +442,30 @@ __device__ __forceinline__ double wave_sum_f64(double v)
 __device__ __forceinline__ int hash_slot(int32_t t) { return (int)(((uint32_t)t * 2654435761u) >> 22); }
 
 // One wavefront per seed s: its k nearest seeds on the seed graph in increasing (distance, index)
-// order (Dijkstra from s, at graph distance <= 64 h, stopped after k settles), then the
-// weighted least-squares affine model of the flow around s, in FP64.
+// order, at graph distance <= 64 h, then the weighted least-squares affine model of the flow
+// around s, in FP64.  The search settles in batches (Dijkstra with buckets as wide as the least
+// edge length D of the graph): with dmin the least tentative distance of the frontier, every
+// frontier node below dmin + D is final, since any other path to it leaves the settled set
+// through a frontier node and adds at least D.  After each batch the settled set is exactly the
+// nodes below dmin + D, so once it holds k nodes its k smallest are the answer.  Candidates and a
+// hash index from node to candidate slot live in LDS.
 __global__ __launch_bounds__(64) void k_epic_knn_fit(EpicFit F)
 {
     static_assert(kHash == 1 << 10, "hash_slot returns 10 bits");
+    constexpr int kStageNodes = 8; // batch nodes whose adjacency rows are read together
     __shared__ int32_t hkey[kHash];
     __shared__ int16_t hval[kHash];
     __shared__ int32_t cid[kCand];
     __shared__ uint32_t cdist[kCand];
     __shared__ uint8_t cdone[kCand];
-    __shared__ int32_t sid[kMaxK];
-    __shared__ uint32_t sdist[kMaxK];
+    __shared__ int32_t sid[kCand]; // settled, in settling order
+    __shared__ uint32_t sdist[kCand];
+    __shared__ int32_t it_t[kStageNodes * kMaxDeg];
+    __shared__ uint32_t it_c[kStageNodes * kMaxDeg];
+    __shared__ int32_t oid[kMaxK]; // the k nearest, sorted
+    __shared__ uint32_t od[kMaxK];
     const int li = threadIdx.x;
+    const uint64_t below = (1ull << li) - 1ull;
     const int64_t s = blockIdx.x;
     if (s >= F.n) return; // whole wave
 
@@ -321,39 +485,69 @@ __global__ __launch_bounds__(64) void k_epic_knn_fit(EpicFit F)
             cdone[0] = 0;
         }
         int m = 1;
+        const uint64_t bucket = *F.min_edge; // >= kappa >= 1 (all ones when there is no edge)
         __syncthreads();
-        while (cnt < F.k) {
-            uint64_t best = kNoKey;
-            int bslot = -1;
-            for (int j = li; j < m; j += 64) {
-                if (cdone[j]) continue;
-                const uint64_t key = ((uint64_t)cdist[j] << 32) | (uint32_t)cid[j];
-                if (key < best) {
-                    best = key;
-                    bslot = j;
+        for (;;) {
+            uint32_t lmin = 0xFFFFFFFFu;
+            for (int j = li; j < m; j += 64)
+                if (!cdone[j]) lmin = cdist[j] < lmin ? cdist[j] : lmin;
+            const uint32_t dmin = wave_min_u32(lmin);
+            if (dmin == 0xFFFFFFFFu) break; // frontier empty
+            const uint64_t T = (uint64_t)dmin + bucket;
+            const int b0 = cnt;
+            for (int base = 0; base < m; base += 64) {
+                const int j = base + li;
+                const bool sel = j < m && !cdone[j] && (uint64_t)cdist[j] < T;
+                const uint64_t bm = __ballot(sel);
+                if (sel) {
+                    const int r = cnt + __popcll(bm & below);
+                    sid[r] = cid[j];
+                    sdist[r] = cdist[j];
+                    cdone[j] = 1;
                 }
+                cnt += __popcll(bm);
             }
-            const uint64_t wbest = wave_min_u64(best);
-            if (wbest == kNoKey) break;
-            if (bslot >= 0 && best == wbest) cdone[bslot] = 1;
-            const int32_t v = (int32_t)(uint32_t)wbest;
-            const uint32_t dv = (uint32_t)(wbest >> 32);
-            if (li == 0) {
-                sid[cnt] = v;
-                sdist[cnt] = dv;
-            }
-            ++cnt;
-            // relax v's edges, one lane per adjacency slot
-            int32_t t = -1;
-            uint32_t c = 0;
-            int hpos = -1;
-            bool is_new = false;
-            if (li < kMaxDeg) {
-                t = F.ws.adj_id[(int64_t)v * kMaxDeg + li];
-                if (t >= 0) {
-                    const uint64_t c64 = (uint64_t)dv + F.ws.adj_w[(int64_t)v * kMaxDeg + li];
-                    if (c64 <= F.dmax) {
-                        c = (uint32_t)c64;
+            __syncthreads();
+            if (cnt >= F.k) break;
+            // relax the batch's edges, kStageNodes adjacency rows at a time
+            for (int nb0 = b0; nb0 < cnt && !overflow; nb0 += kStageNodes) {
+                const int nn = cnt - nb0 < kStageNodes ? cnt - nb0 : kStageNodes;
+                uint64_t e[kStageNodes * kMaxDeg / 64];
+                uint32_t dv[kStageNodes * kMaxDeg / 64];
+#pragma unroll
+                for (int r = 0; r < kStageNodes * kMaxDeg / 64; ++r) {
+                    const int idx = li + 64 * r, node = idx / kMaxDeg, slot = idx - node * kMaxDeg;
+                    e[r] = kNoKey;
+                    dv[r] = 0u;
+                    if (node < nn) {
+                        e[r] = F.ws.adj[(int64_t)sid[nb0 + node] * kMaxDeg + slot];
+                        dv[r] = sdist[nb0 + node];
+                    }
+                }
+                int ni = 0;
+#pragma unroll
+                for (int r = 0; r < kStageNodes * kMaxDeg / 64; ++r) {
+                    const uint64_t c64 = e[r] == kNoKey ? ~0ull : (uint64_t)dv[r] + (e[r] >> 32);
+                    const bool ok = c64 <= F.dmax;
+                    const uint64_t bm = __ballot(ok);
+                    if (ok) {
+                        const int at = ni + __popcll(bm & below);
+                        it_t[at] = (int32_t)(uint32_t)e[r];
+                        it_c[at] = (uint32_t)c64;
+                    }
+                    ni += __popcll(bm);
+                }
+                __syncthreads();
+                for (int ib = 0; ib < ni; ib += 64) {
+                    const int i = ib + li;
+                    const bool has = i < ni;
+                    int32_t t = -1;
+                    uint32_t c = 0u;
+                    int hpos = -1;
+                    bool is_new = false;
+                    if (has) {
+                        t = it_t[i];
+                        c = it_c[i];
                         int hs = hash_slot(t);
                         for (int probe = 0; probe < kHash; ++probe) {
                             const int32_t old = atomicCAS(&hkey[hs], -1, t);
@@ -364,30 +558,45 @@ __global__ __launch_bounds__(64) void k_epic_knn_fit(EpicFit F)
                             }
                             hs = (hs + 1) & (kHash - 1);
                         }
-                    } else {
-                        t = -1;
                     }
+                    __syncthreads();
+                    const uint64_t nbm = __ballot(is_new);
+                    const int total = __popcll(nbm);
+                    if (m + total > kCand) {
+                        overflow = true;
+                        break;
+                    }
+                    if (is_new) {
+                        const int slot = m + __popcll(nbm & below);
+                        hval[hpos] = (int16_t)slot;
+                        cid[slot] = t;
+                        cdist[slot] = 0xFFFFFFFFu;
+                        cdone[slot] = 0;
+                    }
+                    m += total;
+                    __syncthreads();
+                    if (hpos >= 0) {
+                        const int slot = hval[hpos];
+                        if (!cdone[slot]) atomicMin(&cdist[slot], c);
+                    }
+                    __syncthreads();
                 }
             }
-            __syncthreads();
-            const uint64_t nb = __ballot(is_new);
-            const int total = __popcll(nb);
-            if (m + total > kCand) {
-                overflow = true;
-                break;
+            if (overflow) break;
+        }
+        __syncthreads();
+        if (!overflow) {
+            // the k smallest settled (distance, index) pairs, by rank
+            for (int j = li; j < cnt; j += 64) {
+                const uint64_t kj = ((uint64_t)sdist[j] << 32) | (uint32_t)sid[j];
+                int rank = 0;
+                for (int i = 0; i < cnt; ++i) rank += (((uint64_t)sdist[i] << 32) | (uint32_t)sid[i]) < kj;
+                if (rank < F.k) {
+                    oid[rank] = sid[j];
+                    od[rank] = sdist[j];
+                }
             }
-            if (is_new) {
-                const int slot = m + __popcll(nb & ((1ull << li) - 1ull));
-                hval[hpos] = (int16_t)slot;
-                cid[slot] = t;
-                cdist[slot] = c;
-                cdone[slot] = 0;
-            } else if (hpos >= 0) {
-                const int slot = hval[hpos];
-                if (!cdone[slot] && c < cdist[slot]) cdist[slot] = c;
-            }
-            m += total;
-            __syncthreads();
+            cnt = cnt < F.k ? cnt : F.k;
         }
         __syncthreads();
     }
@@ -395,8 +604,8 @@ __global__ __launch_bounds__(64) void k_epic_knn_fit(EpicFit F)
     if (!alive || overflow) cnt = 0;
     if (F.nbr)
         for (int j = li; j < F.k; j += 64) {
-            F.nbr[s * F.k + j] = j < cnt ? sid[j] : -1;
-            F.nbr_dist[s * F.k + j] = j < cnt ? sdist[j] : 0xFFFFFFFFu;
+            F.nbr[s * F.k + j] = j < cnt ? oid[j] : -1;
+            F.nbr_dist[s * F.k + j] = j < cnt ? od[j] : 0xFFFFFFFFu;
         }
     float *mo = F.ws.model + 8 * s;
     if (!alive || overflow) {
@@ -416,8 +625,8 @@ __global__ __launch_bounds__(64) void k_epic_knn_fit(EpicFit F)
         const int j = li + 64 * r;
         c1[r] = cx[r] = cy[r] = bu[r] = bv[r] = 0.0;
         if (j < cnt) {
-            const int32_t t = sid[j];
-            const double w = exp2(-(double)sdist[j] / (double)F.h);
+            const int32_t t = oid[j];
+            const double w = exp2(-(double)od[j] / (double)F.h);
             const double x = (double)F.pts[2 * t] - sx, y = (double)F.pts[2 * t + 1] - sy;
             const double u = F.flow[2 * t], v = F.flow[2 * t + 1];
             a[0] += w;
@@ -594,13 +803,23 @@ int dgf_epic(const dgf_image *I0, const float *points, const float *flow, const 
         hipLaunchKernelGGL(k_epic_seed, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, points, flow, status, n, W,
                            H, ws.keys);
         if (hipGetLastError() != hipSuccess) return DGF_ERR_HIP;
-        const dim3 tiles((unsigned)((W + kTile - 1) / kTile), (unsigned)((H + kTile - 1) / kTile));
+        const dim3 tiles((unsigned)((W + kRT - 1) / kRT), (unsigned)((H + kRT - 1) / kRT));
+        const int64_t ntiles = (int64_t)tiles.x * tiles.y;
+        // tiles may wait for each other only if the whole grid is resident at once
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_epic_relax, kRelaxThreads, 0) != hipSuccess)
+            return DGF_ERR_HIP;
+        const int wait = ntiles <= (int64_t)cus * per_cu ? 1 : 0;
+        uint32_t *busy = ws.ctr + kChunk + 2;
         bool converged = false;
         for (int base = 0; base < kMaxRelaxLaunches && !converged; base += kChunk) {
-            hipLaunchKernelGGL(k_epic_clear, dim3(1), dim3(64), 0, st, ws.ctr, kChunk);
+            hipLaunchKernelGGL(k_epic_clear_launch_counters, dim3(1), dim3(256), 0, st, ws.ctr, busy, ws.mail,
+                               kChunk, (uint32_t)ntiles);
             for (int j = 0; j < kChunk; ++j)
-                hipLaunchKernelGGL(k_epic_relax, tiles, dim3(kTileThreads), 0, st, W, H, o.kappa, ws.keys,
-                                   (const uint16_t *)ws.E, ws.ctr + j);
+                hipLaunchKernelGGL(k_epic_relax, tiles, dim3(kRelaxThreads), 0, st, W, H, o.kappa, ws.keys,
+                                   (const uint16_t *)ws.E, ws.ctr + j, busy + j, ws.mail + j * ntiles, wait);
             if (hipGetLastError() != hipSuccess) return DGF_ERR_HIP;
             uint32_t h_changed[kChunk];
             if (hipMemcpyAsync(h_changed, ws.ctr, sizeof(h_changed), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -610,7 +829,7 @@ int dgf_epic(const dgf_image *I0, const float *points, const float *flow, const 
         }
         if (!converged) return DGF_ERR_UNSUPPORTED;
         hipLaunchKernelGGL(k_epic_graph, dim3(grid_for(N, 256)), dim3(256), 0, st, W, H, o.kappa,
-                           (const uint64_t *)ws.keys, (const uint16_t *)ws.E, ws, err);
+                           (const uint64_t *)ws.keys, (const uint16_t *)ws.E, ws, err, ws.ctr + kChunk + 1);
         if (hipGetLastError() != hipSuccess) return DGF_ERR_HIP;
         EpicFit F{};
         F.pts = points;
@@ -628,6 +847,7 @@ int dgf_epic(const dgf_image *I0, const float *points, const float *flow, const 
         F.nbr_dist = nbr_dist;
         F.model_out = model;
         F.err = err;
+        F.min_edge = ws.ctr + kChunk + 1;
         hipLaunchKernelGGL(k_epic_knn_fit, dim3((unsigned)n), dim3(64), 0, st, F);
         if (hipGetLastError() != hipSuccess) return DGF_ERR_HIP;
     }
