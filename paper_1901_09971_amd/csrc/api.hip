@@ -112,6 +112,14 @@ int dgf_pyramid(const dgf_image *src, int32_t levels, void *dst, size_t dst_byte
     const uint8_t *prev = (const uint8_t *)src->data;
     int64_t prev_pitch = src->pitch_bytes;
     int W = src->width, H = src->height;
+    if (src->dtype == DGF_U8) {
+        const uint8_t *srcs[2] = {prev, nullptr};
+        const int64_t sp[2] = {prev_pitch, 0};
+        uint8_t *lvl[2][DGF_MAX_LEVELS] = {};
+        for (int l = 1; l < levels; ++l) lvl[0][l] = (uint8_t *)dst + off[l];
+        return launch_pyr_chains(srcs, sp, lvl, pitch, W, H, levels, 1, (hipStream_t)stream) == hipSuccess ? DGF_OK
+                                                                                                          : DGF_ERR_HIP;
+    }
     for (int l = 1; l < levels; ++l) {
         PyrJob j{prev, (uint8_t *)dst + off[l], prev_pitch, pitch[l], W, H};
         const hipError_t e = launch_pyr_level(&j, 1, src->dtype, (hipStream_t)stream);
@@ -175,6 +183,21 @@ int dgf_track_pyramids(const dgf_image *I0, const dgf_image *I1, int32_t levels,
     LevelPair lv[DGF_MAX_LEVELS];
     PyrJob jobs[2 * DGF_MAX_LEVELS];
     pyramid_levels(I0, I1, levels, workspace, lv, jobs);
+    if (I0->dtype == DGF_U8) {
+        const uint8_t *srcs[2] = {lv[0].p0, lv[0].p1};
+        const int64_t sp[2] = {lv[0].pitch0, lv[0].pitch1};
+        uint8_t *lvl[2][DGF_MAX_LEVELS] = {};
+        int64_t pitch[DGF_MAX_LEVELS] = {};
+        for (int l = 1; l < levels; ++l) {
+            lvl[0][l] = (uint8_t *)lv[l].p0;
+            lvl[1][l] = (uint8_t *)lv[l].p1;
+            pitch[l] = lv[l].pitch0;
+        }
+        return launch_pyr_chains(srcs, sp, lvl, pitch, I0->width, I0->height, levels, 2, (hipStream_t)stream) ==
+                       hipSuccess
+                   ? DGF_OK
+                   : DGF_ERR_HIP;
+    }
     for (int l = 1; l < levels; ++l) {
         const hipError_t e = launch_pyr_level(&jobs[2 * l], 2, I0->dtype, (hipStream_t)stream);
         if (e != hipSuccess) return DGF_ERR_HIP;

@@ -421,6 +421,22 @@ hipError_t launch_pyr_level_batched(const PyrJob *jobs_dev, int njobs, int max_w
 hipError_t launch_detect(const uint8_t *img, int64_t pitch, int W, int H, int win, int stride, float *pts,
                          uint8_t *sel, float *resp, hipStream_t st);
 hipError_t launch_pyr_level(const PyrJob *jobs, int njobs, int dtype, hipStream_t st);
+
+// Up to four consecutive uint8 levels of one or two images in one launch: level k (k = 1 .. m)
+// of image f goes to dst[k - 1][f] with row pitch dst_pitch[k - 1]; W[0] x H[0] is the source
+// level, W[k] = ceil(W[k - 1] / 2).
+struct PyrChain {
+    const uint8_t *src[2];
+    int64_t src_pitch[2];
+    uint8_t *dst[4][2];
+    int64_t dst_pitch[4];
+    int32_t W[5], H[5];
+    int32_t m;
+};
+hipError_t launch_pyr_chain_u8(const PyrChain &A, int njobs, hipStream_t st);
+hipError_t launch_pyr_chains(const uint8_t *const srcs[2], const int64_t src_pitch[2],
+                             uint8_t *const lvl[2][DGF_MAX_LEVELS], const int64_t *pitch, int W, int H, int levels,
+                             int njobs, hipStream_t st);
 hipError_t launch_track(const TrackParams &P, const TrackTuning &T, int dtype, hipStream_t st);
 int pick_ppl_max(int s, int lpp);
 bool run_shape_compiled(int lpp, int s);

@@ -1,4 +1,5 @@
-// pyramid.hip -- one pyramid reduction step on gfx950.
+// pyramid.hip -- pyramid reduction steps on gfx950 (one level per launch, or up to four uint8
+// levels per launch).
 //
 // Level l+1 = binomial [1 4 6 4 1] smoothing of level l along both axes with replicated borders,
 // sampled at even pixels (size ceil(W/2) x ceil(H/2)).  uint8 levels keep the exact integer sum
@@ -103,6 +104,129 @@ hipError_t launch_pyr_level(const PyrJob *jobs, int njobs, int dtype, hipStream_
     else
         hipLaunchKernelGGL(k_pyr_down<float>, grid, dim3(256), 0, st, J);
     return hipGetLastError();
+}
+
+// ---- several uint8 levels in one launch -----------------------------------------------------
+//
+// Levels s+1 .. s+m (m <= 4) of one or two uint8 images from level s.  A block owns a
+// PC_T x PC_T tile of the coarsest level s+m and the 2^(m-k) times larger tile of every finer
+// level s+k, which tile each level exactly; it computes each level over its owned tile plus the
+// halo the next coarser level's taps need (the needed range [lo, hi] at level k+1 needs
+// [2 lo - 2, 2 hi + 2] at level k, clamped into the level), starting from a staged rectangle of
+// level s, and writes the owned pixels.  Integer sums and the (sum + 128) >> 8 rounding at every
+// level, with the replicated border of every level, as in k_pyr_down, so the levels are
+// identical to one launch per level.
+constexpr int PC_T = 4, PC_MAXM = 4;
+constexpr int pc_width(int m) { return m == 0 ? PC_T : 2 * pc_width(m - 1) + 3; } // region width m levels finer
+constexpr int PC_N0 = pc_width(PC_MAXM);     // 109: staged source rectangle side
+constexpr int PC_N1 = pc_width(PC_MAXM - 1); // 53: first produced level
+
+__global__ __launch_bounds__(256) void k_pyr_chain_u8(PyrChain A)
+{
+    __shared__ uint8_t lvl[2][PC_N0 * PC_N0];
+    __shared__ uint16_t hs[PC_N0 * PC_N1];
+    const int f = blockIdx.z, m = A.m, tid = threadIdx.x;
+    // needed (lo, hi) at every level, coarsest first, then clamped into the level
+    int x0[PC_MAXM + 1], x1[PC_MAXM + 1], y0[PC_MAXM + 1], y1[PC_MAXM + 1];
+    int lx = (int)blockIdx.x * PC_T, hx = lx + PC_T - 1, ly = (int)blockIdx.y * PC_T, hy = ly + PC_T - 1;
+#pragma unroll
+    for (int k = PC_MAXM; k >= 0; --k) {
+        if (k <= m) {
+            if (k < m) {
+                lx = 2 * lx - 2;
+                hx = 2 * hx + 2;
+                ly = 2 * ly - 2;
+                hy = 2 * hy + 2;
+            }
+            x0[k] = lx > 0 ? lx : 0;
+            x1[k] = hx < A.W[k] - 1 ? hx : A.W[k] - 1;
+            y0[k] = ly > 0 ? ly : 0;
+            y1[k] = hy < A.H[k] - 1 ? hy : A.H[k] - 1;
+        }
+    }
+    // stage level s
+    {
+        const int w = x1[0] - x0[0] + 1, h = y1[0] - y0[0] + 1;
+        const uint8_t *src = A.src[f];
+        for (int i = tid; i < w * h; i += 256) {
+            const int y = i / w, x = i - y * w;
+            lvl[0][i] = src[(int64_t)(y0[0] + y) * A.src_pitch[f] + x0[0] + x];
+        }
+    }
+    __syncthreads();
+    for (int k = 0; k < m; ++k) {
+        const uint8_t *in = lvl[k & 1];
+        uint8_t *out = lvl[(k + 1) & 1];
+        const int wi = x1[k] - x0[k] + 1, hi = y1[k] - y0[k] + 1;
+        const int wo = x1[k + 1] - x0[k + 1] + 1, ho = y1[k + 1] - y0[k + 1] + 1;
+        const int Wk = A.W[k], Hk = A.H[k];
+        // horizontal pass: every staged row, at the output column rate
+        for (int i = tid; i < hi * wo; i += 256) {
+            const int r = i / wo, xo = i - r * wo;
+            const int c = 2 * (x0[k + 1] + xo);
+            const uint8_t *row = in + r * wi;
+            auto at = [&](int cc) { return (int)row[(cc < 0 ? 0 : (cc > Wk - 1 ? Wk - 1 : cc)) - x0[k]]; };
+            hs[i] = (uint16_t)(at(c - 2) + at(c + 2) + 4 * (at(c - 1) + at(c + 1)) + 6 * at(c));
+        }
+        __syncthreads();
+        // vertical pass, rounding, and the owned pixels to memory
+        const int sh = m - (k + 1);
+        const int ox0 = ((int)blockIdx.x * PC_T) << sh, oy0 = ((int)blockIdx.y * PC_T) << sh;
+        const int own = PC_T << sh;
+        uint8_t *dst = A.dst[k][f];
+        const int64_t dp = A.dst_pitch[k];
+        for (int i = tid; i < ho * wo; i += 256) {
+            const int yo = i / wo, xo = i - yo * wo;
+            const int gy = y0[k + 1] + yo, gx = x0[k + 1] + xo;
+            const int rr = 2 * gy;
+            auto at = [&](int r) { return (int)hs[((r < 0 ? 0 : (r > Hk - 1 ? Hk - 1 : r)) - y0[k]) * wo + xo]; };
+            const int v = at(rr - 2) + at(rr + 2) + 4 * (at(rr - 1) + at(rr + 1)) + 6 * at(rr);
+            const uint8_t q = (uint8_t)((v + 128) >> 8);
+            out[i] = q;
+            if (gx >= ox0 && gx < ox0 + own && gy >= oy0 && gy < oy0 + own) dst[(int64_t)gy * dp + gx] = q;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_pyr_chain_u8(const PyrChain &A, int njobs, hipStream_t st)
+{
+    if (A.m < 1 || A.m > PC_MAXM || njobs < 1 || njobs > 2) return hipErrorInvalidValue;
+    dim3 grid((A.W[A.m] + PC_T - 1) / PC_T, (A.H[A.m] + PC_T - 1) / PC_T, njobs);
+    hipLaunchKernelGGL(k_pyr_chain_u8, grid, dim3(256), 0, st, A);
+    return hipGetLastError();
+}
+
+// Levels 1 .. levels-1 of one or two uint8 images (level 0 = srcs) as chains of up to four
+// levels per launch; level l of image f goes to lvl[f][l], row pitch pitch[l].
+hipError_t launch_pyr_chains(const uint8_t *const srcs[2], const int64_t src_pitch[2],
+                             uint8_t *const lvl[2][DGF_MAX_LEVELS], const int64_t *pitch, int W, int H, int levels,
+                             int njobs, hipStream_t st)
+{
+    int Wl[DGF_MAX_LEVELS], Hl[DGF_MAX_LEVELS];
+    Wl[0] = W;
+    Hl[0] = H;
+    for (int l = 1; l < levels; ++l) {
+        Wl[l] = (Wl[l - 1] + 1) / 2;
+        Hl[l] = (Hl[l - 1] + 1) / 2;
+    }
+    for (int s = 0; s + 1 < levels; s += PC_MAXM) {
+        PyrChain A{};
+        A.m = levels - 1 - s < PC_MAXM ? levels - 1 - s : PC_MAXM;
+        for (int f = 0; f < njobs; ++f) {
+            A.src[f] = s == 0 ? srcs[f] : lvl[f][s];
+            A.src_pitch[f] = s == 0 ? src_pitch[f] : pitch[s];
+            for (int k = 1; k <= A.m; ++k) A.dst[k - 1][f] = lvl[f][s + k];
+        }
+        for (int k = 0; k <= A.m; ++k) {
+            A.W[k] = Wl[s + k];
+            A.H[k] = Hl[s + k];
+            if (k > 0) A.dst_pitch[k - 1] = pitch[s + k];
+        }
+        const hipError_t e = launch_pyr_chain_u8(A, njobs, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 } // namespace dgf

@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("W,H,L", [(1, 1, 3), (2, 3, 3), (5, 4, 4), (17, 9, 5), (256, 128, 3), (1242, 375, 5),
-                                   (2048, 1024, 6), (64, 16, 7), (130, 33, 8)])
+                                   (2048, 1024, 6), (64, 16, 7), (130, 33, 8), (300, 200, 12), (4000, 3, 10)])
 def test_u8_bit_exact(W, H, L):
     rng = np.random.default_rng(W * 7 + H)
     img = rng.integers(0, 256, size=(H, W), dtype=np.uint8)
