@@ -389,6 +389,18 @@ def density_stress(reps: int):
 
     t_fwd = timed(plan.replay)
     t_bwd = timed(lambda: plan.backward(dflow, grad))
+    # dense interpolation of the first pair's tracked points (the call synchronises: host clock)
+    lo, hi = plan.offsets[0], plan.offsets[1]
+    I0p = pairs[0][0]
+    e_args = (I0p, P[lo:hi].contiguous(), F[lo:hi].contiguous(), S[lo:hi].contiguous())
+    dgf.epic(*e_args)
+    torch.cuda.synchronize()
+    e_times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        dgf.epic(*e_args)
+        torch.cuda.synchronize()
+        e_times.append(time.perf_counter() - t0)
     plan.close()
     n_conv = int(conv.sum().item())
     return {"workload": c["name"], "pairs": c["pairs"], "points": n, "levels": c["levels"],
@@ -396,7 +408,9 @@ def density_stress(reps: int):
             "forward_ms": t_fwd, "forward_points_per_s": n / (t_fwd * 1e-3),
             "forward_track_tflops_lower_bound": pix_iters * FLOPS_PER_PIXEL_ITER / (t_fwd * 1e-3) / 1e12,
             "adjoint_ms": t_bwd, "adjoint_converged_points": n_conv,
-            "adjoint_points_per_s": n_conv / (t_bwd * 1e-3)}
+            "adjoint_points_per_s": n_conv / (t_bwd * 1e-3),
+            "interpolation_ms_one_pair": float(np.median(e_times)) * 1e3,
+            "interpolation_seeds_one_pair": int((S[lo:hi] == 0).sum().item())}
 
 
 def copy_calibration(mib: int):
