@@ -78,7 +78,7 @@ def _load():
                              i32, P, P, P, P, i32]
     lib.or_track.restype = i32
     lib.or_track_grad.argtypes = [P, P, i32, i32, P, i64, i32, f64, f64, P, P, P, P, P, P]
-    lib.or_track_grad_illum.argtypes = [P, P, i32, i32, P, i64, i32, f64, f64, P, P, P, P, P, P]
+    lib.or_track_grad_illum.argtypes = [P, P, i32, i32, P, i64, i32, f64, f64, P, P, P, P, P, P, P]
     lib.or_track_grad_illum.restype = i32
     lib.or_epic_edges.argtypes = [P, i32, i32, i64, P]
     lib.or_epic_edges.restype = None
@@ -271,9 +271,10 @@ def track_grad(I0: np.ndarray, I1: np.ndarray, points: np.ndarray, support: int,
 
 def track_grad_illum(I0: np.ndarray, I1: np.ndarray, points: np.ndarray, support: int, flow: np.ndarray,
                      illum: np.ndarray, status: np.ndarray, dflow: np.ndarray, sigma1=DEFAULTS["sigma1"],
-                     sigma2=DEFAULTS["sigma2"]):
+                     sigma2=DEFAULTS["sigma2"], return_dpoints: bool = False):
     """Implicit gradient (dL/dI0, dL/dI1) of the illumination-model tracker at its converged
-    level-0 fixed point (flow and illum = (m, c) as the forward pass returned them)."""
+    level-0 fixed point (flow and illum = (m, c) as the forward pass returned them), and with
+    ``return_dpoints`` also dL/dp w.r.t. the point positions."""
     a0 = np.ascontiguousarray(I0, dtype=np.float64)
     a1 = np.ascontiguousarray(I1, dtype=np.float64)
     H, W = a0.shape
@@ -284,10 +285,13 @@ def track_grad_illum(I0: np.ndarray, I1: np.ndarray, points: np.ndarray, support
     df = np.ascontiguousarray(dflow, dtype=np.float64).reshape(-1, 2)
     dI0 = np.zeros((H, W), np.float64)
     dI1 = np.zeros((H, W), np.float64)
+    dp = np.zeros((pts.shape[0], 2), np.float64) if return_dpoints else None
     rc = _load().or_track_grad_illum(_ptr(a0), _ptr(a1), W, H, _ptr(pts), pts.shape[0], support, sigma1, sigma2,
-                                     _ptr(fl), _ptr(mc), _ptr(st), _ptr(df), _ptr(dI0), _ptr(dI1))
+                                     _ptr(fl), _ptr(mc), _ptr(st), _ptr(df), _ptr(dI0), _ptr(dI1), _ptr(dp))
     if rc != 0:
         raise ValueError(f"or_track_grad_illum failed: {rc}")
+    if return_dpoints:
+        return dI0, dI1, dp
     return dI0, dI1
 
 

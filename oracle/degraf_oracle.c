@@ -1012,17 +1012,25 @@ int or_track_grad(const double *I0, const double *I1, int W, int H, const double
  */
 int or_track_grad_illum(const double *I0, const double *I1, int W, int H, const double *pts, int64_t n, int support,
                         double sigma1, double sigma2, const double *flow, const double *illum, const uint8_t *status,
-                        const double *dflow, double *dI0, double *dI1)
+                        const double *dflow, double *dI0, double *dI1, double *dpoints)
 {
     if (!I0 || !I1 || W <= 0 || H <= 0 || support < 1 || (support % 2) == 0) return OR_ERR_ARG;
     if (n > 0 && (!pts || !flow || !illum || !status || !dflow || !dI0 || !dI1)) return OR_ERR_ARG;
     const int r = support / 2;
     for (int64_t i = 0; i < n; ++i) {
+        if (dpoints) {
+            dpoints[2 * i] = 0.0;
+            dpoints[2 * i + 1] = 0.0;
+        }
         if (status[i] != OR_ST_CONVERGED) continue;
         const double px = pts[2 * i], py = pts[2 * i + 1];
         const double ux = flow[2 * i], uy = flow[2 * i + 1];
         const double m = illum[2 * i], c = illum[2 * i + 1];
         double A[16] = {0};
+        /* dependence of F on the point (the template moves with it, the images do not):
+         * dF/dp = A[:, u] + K, K = sum -(1 + m) psi' phi (grad T)^T + psi dphi/dp with
+         * dphi/dp = ((1 + m) dg/dp, -(grad T)^T, 0) */
+        double K[4][2] = {{0}};
         for (int ky = -r; ky <= r; ++ky)
             for (int kx = -r; kx <= r; ++kx) {
                 double x = px + kx, y = py + ky;
@@ -1039,12 +1047,30 @@ int or_track_grad_illum(const double *I0, const double *I1, int W, int H, const 
                     for (int b = 0; b < 4; ++b) A[a * 4 + b] += dp * phi[a] * dr[b];
                 A[0 * 4 + 2] += ps * g0;
                 A[1 * 4 + 2] += ps * g1;
+                if (dpoints) {
+                    double gT[2], gxp[2], gxm[2], gyp[2], gym[2];
+                    bilinear_grad(I0, W, H, x, y, gT);
+                    bilinear_grad(I0, W, H, x + 1.0, y, gxp);
+                    bilinear_grad(I0, W, H, x - 1.0, y, gxm);
+                    bilinear_grad(I0, W, H, x, y + 1.0, gyp);
+                    bilinear_grad(I0, W, H, x, y - 1.0, gym);
+                    for (int b = 0; b < 2; ++b) {
+                        for (int a = 0; a < 4; ++a) K[a][b] += -(1.0 + m) * dp * phi[a] * gT[b];
+                        K[0][b] += ps * (1.0 + m) * 0.5 * (gxp[b] - gxm[b]);
+                        K[1][b] += ps * (1.0 + m) * 0.5 * (gyp[b] - gym[b]);
+                        K[2][b] += -ps * gT[b];
+                    }
+                }
             }
         double At[16], lam[4] = {dflow[2 * i], dflow[2 * i + 1], 0.0, 0.0}, mu[4];
         for (int a = 0; a < 4; ++a)
             for (int b = 0; b < 4; ++b) At[a * 4 + b] = A[b * 4 + a];
         if (solve_dense(At, lam, 4, mu) != 0 || !(isfinite(mu[0]) && isfinite(mu[1]) && isfinite(mu[2]) && isfinite(mu[3])))
             continue;
+        if (dpoints) /* du/dp = -I - (A^-1 K)[u rows], so dL/dp = -lambda - K^T mu */
+            for (int b = 0; b < 2; ++b)
+                dpoints[2 * i + b] = -dflow[2 * i + b] - (K[0][b] * mu[0] + K[1][b] * mu[1] + K[2][b] * mu[2] +
+                                                          K[3][b] * mu[3]);
         for (int ky = -r; ky <= r; ++ky)
             for (int kx = -r; kx <= r; ++kx) {
                 double x = px + kx, y = py + ky;

@@ -186,3 +186,31 @@ def test_implicit_gradient_matches_finite_differences():
                 vals.append(np.sum(lam * f))
             fd = (vals[0] - vals[1]) / (2 * h)
             assert abs(g[y, x] - fd) <= 1e-5 * np.abs(g).max(), (y, x, g[y, x], fd)
+
+
+def test_point_gradient_matches_finite_differences():
+    # dL/dp of the illumination-model tracker (the template moves with the point) against central
+    # differences of the forward in the point positions; gain and offset away from (0, 0), the
+    # robust middle band active
+    I0, I1, _ = synth.noise_translation_pair(72, 60, seed=5, shift=(1.3, -0.8), dtype="f32")
+    I0 = I0.astype(np.float64)
+    I1 = 0.9 * I1.astype(np.float64) + 11.0 + 3.0 * np.sin(np.arange(72) / 7.0)[None, :]
+    rng = np.random.default_rng(16)
+    pts = np.stack([rng.uniform(15, 56, 10), rng.uniform(15, 44, 10)], 1)
+    kw = dict(eps_fine=1e-13, min_eig=0.0, illum=True)
+    flow, st, mc = oracle.track(I0, I1, pts, 1, 9, 400, return_illum=True, **kw)
+    assert np.mean(st == 0) > 0.8
+    lam = rng.normal(size=flow.shape) * (st == 0)[:, None]
+    _, _, dp = oracle.track_grad_illum(I0, I1, pts, 9, flow, mc, st, lam, return_dpoints=True)
+    h = 1e-5
+    for i in np.where(st == 0)[0]:
+        for c in range(2):
+            a = pts.copy()
+            a[i, c] += h
+            fa, _ = oracle.track(I0, I1, a[i:i + 1], 1, 9, 400, **kw)
+            b = pts.copy()
+            b[i, c] -= h
+            fb, _ = oracle.track(I0, I1, b[i:i + 1], 1, 9, 400, **kw)
+            fd = float(np.sum(lam[i] * (fa[0] - fb[0])) / (2 * h))
+            assert abs(dp[i, c] - fd) <= 1e-5 * (abs(fd) + np.abs(lam[i]).sum()), (i, c, dp[i, c], fd)
+    assert np.all(dp[st != 0] == 0.0)
