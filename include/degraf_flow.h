@@ -90,8 +90,8 @@ typedef struct {
  * ((1 + m) g, -T, -1); m and c start at 0 and carry over between levels; a point whose final
  * gain 1 + m lies outside [1/2, 2] is NOT_CONVERGED (a contrast change, not a match).  Supported for the
  * supports the row-run kernel is compiled for (5, 7, 9, 11, 15, 21), else DGF_ERR_UNSUPPORTED.
- * dgf_track_backward differentiates it given the forward call's (gain, offset) (illum_out);
- * dgf_batch_backward does not. */
+ * dgf_track_backward and dgf_batch_backward differentiate it given the forward call's
+ * (gain, offset) (illum_out). */
 #define DGF_TRACK_ILLUM 1
 
 /* ---- library ----------------------------------------------------------------------------------- */
@@ -201,8 +201,10 @@ int dgf_track(const dgf_image *I0, const dgf_image *I1, const float *points, int
  *                 phi_k = ((1+m) g_k, -T_k, -1): a 4x4 J with J^T mu = (dflow, 0, 0), and
  *   dI1[q] -= sum_k psi'(r_k) (mu . phi_k) beta_k(q)
  *   dI0[q] += sum_k [(1+m) psi'(r_k) (mu . phi_k) + psi(r_k) mu_m] alpha_k(q)
- *             - (1+m) sum_k psi(r_k) mu_u . dg_k/dI0[q].
- *                 dpoints must then be null (DGF_ERR_UNSUPPORTED). */
+ *             - (1+m) sum_k psi(r_k) mu_u . dg_k/dI0[q];
+ *                 dpoints then uses K = sum_k [-(1+m) psi'(r_k) phi_k grad I0(p+k)^T
+ *                 + psi(r_k) dphi_k/dp], dphi_k/dp = ((1+m) dg_k/dp, -grad I0(p+k)^T, 0),
+ *                 and dL/dp = -dflow - K^T mu. */
 int dgf_track_backward(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t support,
                        const dgf_track_opts *opts, const float *flow, const uint8_t *status, const float *dflow,
                        float *dI0, float *dI1, float *dpoints, const float *illum, void *stream);
@@ -247,14 +249,16 @@ int dgf_batch_point_offsets(const dgf_batch *b, int64_t *offsets);
 
 /* Runs the plan on `stream`: one launch per pyramid level for all frames, one detection launch,
  * a counter reset and one persistent tracking launch.  points: out float[N][2]; flow: out
- * float[N][2]; status: out uint8[N]; iters_out: nullable int32[N].  Results equal those of
- * per-pair dgf_detect + dgf_track with the same tuning. */
-int dgf_batch_run(dgf_batch *b, float *points, float *flow, uint8_t *status, int32_t *iters_out, void *stream);
+ * float[N][2]; status: out uint8[N]; iters_out: nullable int32[N]; illum_out: nullable
+ * float[N][2], the gain and offset of a plan made with DGF_TRACK_ILLUM (else must be null).
+ * Results equal those of per-pair dgf_detect + dgf_track with the same tuning. */
+int dgf_batch_run(dgf_batch *b, float *points, float *flow, uint8_t *status, int32_t *iters_out, float *illum_out,
+                  void *stream);
 
 /* Captures the run sequence (with these output pointers) into a HIP graph on `stream` (a created
  * stream, not the default one); dgf_batch_replay launches it with one call.  A new capture
  * replaces the previous graph. */
-int dgf_batch_capture(dgf_batch *b, float *points, float *flow, uint8_t *status, void *stream);
+int dgf_batch_capture(dgf_batch *b, float *points, float *flow, uint8_t *status, float *illum_out, void *stream);
 int dgf_batch_replay(dgf_batch *b, void *stream);
 
 /* Size, in floats, of the gradient buffer dgf_batch_backward writes: every pair's dI0 then dI1,
@@ -269,10 +273,10 @@ int64_t dgf_batch_grad_size(const dgf_batch *b, int64_t *offsets);
  * (dgf_batch_grad_size floats, device) with dL/dI0 and dL/dI1 of every pair, taking the uint8
  * frames' values as reals.  grad is cleared by a kernel first; contributions are added with
  * device float atomics, so the last bits are not deterministic.  Points that are not CONVERGED,
- * or have a singular J, contribute nothing.  DGF_ERR_UNSUPPORTED for a plan made with
- * DGF_TRACK_ILLUM. */
+ * or have a singular J, contribute nothing.  illum: for a plan made with DGF_TRACK_ILLUM, the
+ * gain and offset the run wrote (required, float[N][2]); null otherwise. */
 int dgf_batch_backward(dgf_batch *b, const float *points, const float *flow, const uint8_t *status, const float *dflow,
-                       float *grad, void *stream);
+                       const float *illum, float *grad, void *stream);
 
 /* Frees the plan and its device memory (after the work using it has completed). */
 int dgf_batch_destroy(dgf_batch *b);

@@ -71,11 +71,11 @@ SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_void_p)]),
     "dgf_batch_num_points": (I64, [P]),
     "dgf_batch_point_offsets": (ctypes.c_int, [P, P]),
-    "dgf_batch_run": (ctypes.c_int, [P, P, P, P, P, P]),
-    "dgf_batch_capture": (ctypes.c_int, [P, P, P, P, P]),
+    "dgf_batch_run": (ctypes.c_int, [P, P, P, P, P, P, P]),
+    "dgf_batch_capture": (ctypes.c_int, [P, P, P, P, P, P]),
     "dgf_batch_replay": (ctypes.c_int, [P, P]),
     "dgf_batch_grad_size": (I64, [P, P]),
-    "dgf_batch_backward": (ctypes.c_int, [P, P, P, P, P, P, P]),
+    "dgf_batch_backward": (ctypes.c_int, [P, P, P, P, P, P, P, P]),
     "dgf_batch_destroy": (ctypes.c_int, [P]),
     "dgf_epic_opts_default": (ctypes.c_int, [ctypes.POINTER(DgfEpicOpts)]),
     "dgf_epic_workspace_bytes": (SZ, [I32, I32, I64]),

@@ -173,7 +173,7 @@ def track_backward(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, sup
     """Accumulate dL/dI0 into ``dI0`` and dL/dI1 into ``dI1`` (float32, same shape and row stride
     as the images) for the upstream gradient ``dflow`` of a forward :func:`track` call; write
     dL/dp into ``dpoints`` (float32 [n, 2]) when given.  With ``opts.illum`` the forward call's
-    per-point (gain, offset) go in ``illum`` (float32 [n, 2]); ``dpoints`` is then not supported."""
+    per-point (gain, offset) go in ``illum`` (float32 [n, 2])."""
     a, b = _image(I0, "I0"), _image(I1, "I1")
     for t, ref, name in ((dI0, I0, "dI0"), (dI1, I1, "dI1")):
         if t.dtype != torch.float32 or t.shape != ref.shape or t.stride() != ref.stride() or not t.is_cuda:
@@ -235,7 +235,7 @@ class TrackFn(torch.autograd.Function):
     Differentiable tracking of float32 frames: the backward pass is the implicit-function adjoint
     at the converged level-0 fixed point (dgf_track_backward), w.r.t. both frames and the point
     positions; points that did not converge get no gradient.  With ``opts.illum`` the adjoint
-    is that of the illumination model (frames only: the point positions get no gradient)."""
+    is that of the illumination model."""
 
     @staticmethod
     def forward(ctx, I0, I1, points, levels, support, iters, opts=None):
@@ -255,8 +255,6 @@ class TrackFn(torch.autograd.Function):
         I0, I1, points, flow, status, ill = ctx.saved_tensors
         dI0 = torch.zeros_like(I0)
         dI1 = torch.zeros_like(I1)
-        if ill is not None and ctx.needs_input_grad[2]:
-            raise NotImplementedError("TrackFn: no point-position gradient for the illumination model")
         dpoints = torch.zeros_like(points) if ctx.needs_input_grad[2] else None
         if dflow is not None:
             track_backward(I0, I1, points, ctx.support, flow, status, dflow, dI0, dI1, ctx.opts, dpoints, ill)
@@ -362,6 +360,7 @@ class Batch:
         for i, (a, b, window, stride) in enumerate(pairs):
             descs[i] = _lib.DgfPairDesc(_image(a, f"pairs[{i}].I0"), _image(b, f"pairs[{i}].I1"), window, stride)
         o = (opts or TrackOpts()).to_c()
+        self.illum_model = bool(opts is not None and opts.illum)
         h = ctypes.c_void_p()
         check(lib().dgf_batch_create(descs, len(pairs), levels, support, iters, ctypes.byref(o), ctypes.byref(h)),
               "dgf_batch_create")
@@ -375,17 +374,20 @@ class Batch:
         self.points = torch.empty((n, 2), dtype=torch.float32, device=self.device)
         self.flow = torch.empty((n, 2), dtype=torch.float32, device=self.device)
         self.status = torch.empty(n, dtype=torch.uint8, device=self.device)
+        # per-point gain and offset of the illumination model (None for the plain model)
+        self.illum = torch.empty((n, 2), dtype=torch.float32, device=self.device) if self.illum_model else None
 
     def run(self, iters_out: torch.Tensor | None = None):
-        """Eager run on the current stream; returns (points, flow, status) views of the plan's buffers."""
+        """Eager run on the current stream; returns (points, flow, status) views of the plan's
+        buffers (with the illumination model, ``self.illum`` holds the gain and offset)."""
         check(lib().dgf_batch_run(self._h, _ptr(self.points), _ptr(self.flow), _ptr(self.status), _ptr(iters_out),
-                                  _stream()), "dgf_batch_run")
+                                  _ptr(self.illum), _stream()), "dgf_batch_run")
         return self.points, self.flow, self.status
 
     def capture(self):
         """Capture the run into a HIP graph on the current (non-default) stream."""
-        check(lib().dgf_batch_capture(self._h, _ptr(self.points), _ptr(self.flow), _ptr(self.status), _stream()),
-              "dgf_batch_capture")
+        check(lib().dgf_batch_capture(self._h, _ptr(self.points), _ptr(self.flow), _ptr(self.status),
+                                      _ptr(self.illum), _stream()), "dgf_batch_capture")
 
     def replay(self):
         check(lib().dgf_batch_replay(self._h, _stream()), "dgf_batch_replay")
@@ -409,7 +411,7 @@ class Batch:
         if dflow.shape != (self.num_points, 2):
             raise ValueError("dflow: expected float32 [num_points, 2]")
         check(lib().dgf_batch_backward(self._h, _ptr(self.points), _ptr(self.flow), _ptr(self.status), _ptr(dflow),
-                                       _ptr(grad), _stream()), "dgf_batch_backward")
+                                       _ptr(self.illum), _ptr(grad), _stream()), "dgf_batch_backward")
         views = []
         for i, (a, _) in enumerate(self._keep):
             H, W = a.shape

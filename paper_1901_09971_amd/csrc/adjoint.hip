@@ -261,6 +261,7 @@ __global__ __launch_bounds__(64) void k_track_adjoint_illum(AdjParams A)
     const int li = threadIdx.x;
     const int64_t i = blockIdx.x;
     if (i >= A.n) return; // whole wave: the grid is exactly n wide
+    if (A.dpoints && li == 0) reinterpret_cast<float2 *>(A.dpoints)[i] = make_float2(0.f, 0.f);
     if (A.status[i] != DGF_ST_CONVERGED) return;
     const AdjPair Pr = A.npairs ? A.pairs[adj_pair_of(A, i)] : A.one;
     const float2 p = reinterpret_cast<const float2 *>(A.pts)[i];
@@ -305,7 +306,19 @@ __global__ __launch_bounds__(64) void k_track_adjoint_illum(AdjParams A)
     if (!(Ts > 1e-6f)) Ts = 1.f;
     const float iTs = 1.f / Ts;
 
-    // pass 1: A = sum psi' phi' (grad J, -T', -1)^T
+    auto I0g = [&](int lx, int ly, float &gx, float &gy) {
+        const float *q = raw0 + ly * w0 + lx;
+        gx = (1.f - fy0) * (q[1] - q[0]) + fy0 * (q[w0 + 1] - q[w0]);
+        gy = (1.f - fx0) * (q[w0] - q[0]) + fx0 * (q[w0 + 1] - q[1]);
+    };
+
+    // pass 1: A = sum psi' phi' (grad J, -T', -1)^T; with dpoints also the point dependence
+    // K = sum -(1 + m) psi' phi' (grad T)^T + psi dphi'/dp, dphi'/dp = ((1 + m) dg/dp,
+    // -(grad T)^T / Ts, 0) (rows u_x, u_y, m, c; columns p_x, p_y)
+    const bool want_dp = A.dpoints != nullptr;
+    float Kp[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) Kp[e] = 0.f;
     float Am[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) Am[e] = 0.f;
@@ -329,16 +342,45 @@ __global__ __launch_bounds__(64) void k_track_adjoint_illum(AdjParams A)
         for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b) Am[a * 4 + b] = fmaf(dps * ph[a], dr[b], Am[a * 4 + b]);
+        if (want_dp) {
+            float tgx, tgy, pxx, pxy, mxx, mxy, pyx, pyy, myx, myy;
+            I0g(lx, ly, tgx, tgy);
+            I0g(lx + 1, ly, pxx, pxy);
+            I0g(lx - 1, ly, mxx, mxy);
+            I0g(lx, ly + 1, pyx, pyy);
+            I0g(lx, ly - 1, myx, myy);
+            const float cg = -g1m * dps, hp = 0.5f * g1m * ps;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                Kp[2 * a] = fmaf(cg * ph[a], tgx, Kp[2 * a]);
+                Kp[2 * a + 1] = fmaf(cg * ph[a], tgy, Kp[2 * a + 1]);
+            }
+            Kp[0] = fmaf(hp, pxx - mxx, Kp[0]);
+            Kp[1] = fmaf(hp, pxy - mxy, Kp[1]);
+            Kp[2] = fmaf(hp, pyx - myx, Kp[2]);
+            Kp[3] = fmaf(hp, pyy - myy, Kp[3]);
+            Kp[4] = fmaf(-ps * iTs, tgx, Kp[4]);
+            Kp[5] = fmaf(-ps * iTs, tgy, Kp[5]);
+        }
     }
     float zz = 0.f;
     wave_sum5(Am[0], Am[1], Am[2], Am[3], Am[4]);
     wave_sum5(Am[5], Am[6], Am[7], Am[8], Am[9]);
     wave_sum5(Am[10], Am[11], Am[12], Am[13], Am[14]);
     wave_sum5(Am[15], zz, z0, z1, z2);
+    if (want_dp) {
+        wave_sum5(Kp[0], Kp[1], Kp[2], Kp[3], Kp[4]);
+        wave_sum5(Kp[5], Kp[6], Kp[7], z0, z1);
+    }
     const float v[4] = {lam.x, lam.y, 0.f, 0.f};
     float mu[4];
     solve4_transposed(Am, v, mu);
     if (!(isfinite(mu[0]) && isfinite(mu[1]) && isfinite(mu[2]) && isfinite(mu[3]))) return; // uniform
+    // du/dp = -I - (A^-1 K)[u rows], so dL/dp = -lambda - K^T mu
+    if (want_dp && li == 0)
+        reinterpret_cast<float2 *>(A.dpoints)[i] =
+            make_float2(-lam.x - (Kp[0] * mu[0] + Kp[2] * mu[1] + Kp[4] * mu[2] + Kp[6] * mu[3]),
+                        -lam.y - (Kp[1] * mu[0] + Kp[3] * mu[1] + Kp[5] * mu[2] + Kp[7] * mu[3]));
 
     // pass 2: per support pixel c1 = psi' (mu . phi'), A0 = (1 + m) c1 + psi mu_m / Ts,
     // cx, cy = -(1 + m) psi mu_d / 2
@@ -520,7 +562,6 @@ extern "C" int dgf_track_backward(const dgf_image *I0, const dgf_image *I1, cons
         dgf_track_opts_default(&o);
     }
     const bool im = (o.flags & DGF_TRACK_ILLUM) != 0;
-    if (im && dpoints) return DGF_ERR_UNSUPPORTED; // the point gradient covers the plain model
     if (im && n > 0 && !illum) return DGF_ERR_INVALID_ARG;
     if (!im && illum) return DGF_ERR_INVALID_ARG;
     if (!(o.sigma1 >= 0.f) || !(o.sigma2 >= 0.f)) return DGF_ERR_INVALID_ARG;

@@ -76,7 +76,8 @@ bool pair_ok(const dgf_pair_desc &d, int dtype)
            d.window <= DGF_MAX_WINDOW && d.stride >= 1;
 }
 
-int launch_all(dgf_batch *b, float *points, float *flow, uint8_t *status, int32_t *iters_out, hipStream_t st)
+int launch_all(dgf_batch *b, float *points, float *flow, uint8_t *status, int32_t *iters_out, float *illum_out,
+               hipStream_t st)
 {
     for (int l = 1; l < b->L; ++l) {
         if (launch_pyr_level_batched(b->d_pyr + (size_t)(l - 1) * 2 * b->P, 2 * b->P, b->pyr_w2[l], b->pyr_h2[l], b->dtype,
@@ -93,6 +94,7 @@ int launch_all(dgf_batch *b, float *points, float *flow, uint8_t *status, int32_
     P.flow = flow;
     P.status = status;
     P.iters_out = iters_out;
+    P.illum_out = illum_out;
     P.L = b->L;
     P.iters = b->iters;
     fill_track_geometry(P, b->s, b->tune.margin, b->tune.lpp, b->tune.kind);
@@ -295,18 +297,21 @@ int dgf_batch_point_offsets(const dgf_batch *b, int64_t *offsets)
     return DGF_OK;
 }
 
-int dgf_batch_run(dgf_batch *b, float *points, float *flow, uint8_t *status, int32_t *iters_out, void *stream)
+int dgf_batch_run(dgf_batch *b, float *points, float *flow, uint8_t *status, int32_t *iters_out, float *illum_out,
+                  void *stream)
 {
     if (!b) return DGF_ERR_INVALID_ARG;
     if (b->total_pts > 0 && (!points || !flow || !status)) return DGF_ERR_INVALID_ARG;
+    if (illum_out && !(b->opts.flags & DGF_TRACK_ILLUM)) return DGF_ERR_INVALID_ARG;
     if (b->total_pts == 0) return DGF_OK;
-    return launch_all(b, points, flow, status, iters_out, (hipStream_t)stream);
+    return launch_all(b, points, flow, status, iters_out, illum_out, (hipStream_t)stream);
 }
 
-int dgf_batch_capture(dgf_batch *b, float *points, float *flow, uint8_t *status, void *stream)
+int dgf_batch_capture(dgf_batch *b, float *points, float *flow, uint8_t *status, float *illum_out, void *stream)
 {
     if (!b || !stream) return DGF_ERR_INVALID_ARG; // graphs are captured from a created stream
     if (b->total_pts > 0 && (!points || !flow || !status)) return DGF_ERR_INVALID_ARG;
+    if (illum_out && !(b->opts.flags & DGF_TRACK_ILLUM)) return DGF_ERR_INVALID_ARG;
     if (b->exec) {
         (void)hipGraphExecDestroy(b->exec);
         b->exec = nullptr;
@@ -318,7 +323,7 @@ int dgf_batch_capture(dgf_batch *b, float *points, float *flow, uint8_t *status,
     if (b->total_pts == 0) return DGF_OK;
     hipStream_t st = (hipStream_t)stream;
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return DGF_ERR_HIP;
-    const int rc = launch_all(b, points, flow, status, nullptr, st);
+    const int rc = launch_all(b, points, flow, status, nullptr, illum_out, st);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(st, &g);
     if (rc != DGF_OK || e != hipSuccess || !g) {
@@ -351,12 +356,14 @@ int64_t dgf_batch_grad_size(const dgf_batch *b, int64_t *offsets)
 }
 
 int dgf_batch_backward(dgf_batch *b, const float *points, const float *flow, const uint8_t *status, const float *dflow,
-                       float *grad, void *stream)
+                       const float *illum, float *grad, void *stream)
 {
     if (!b) return DGF_ERR_INVALID_ARG;
     if (b->total_pts > 0 && (!points || !flow || !status || !dflow || !grad)) return DGF_ERR_INVALID_ARG;
     if (grad && (uintptr_t)grad % 4 != 0) return DGF_ERR_INVALID_ARG;
-    if (b->opts.flags & DGF_TRACK_ILLUM) return DGF_ERR_UNSUPPORTED; // the adjoint covers the plain model
+    const bool im = (b->opts.flags & DGF_TRACK_ILLUM) != 0;
+    if (im && b->total_pts > 0 && !illum) return DGF_ERR_INVALID_ARG;
+    if (!im && illum) return DGF_ERR_INVALID_ARG;
     if (b->total_pts == 0) return DGF_OK;
     hipStream_t st = (hipStream_t)stream;
     const int64_t ng = b->grad_off[b->P];
@@ -375,6 +382,7 @@ int dgf_batch_backward(dgf_batch *b, const float *points, const float *flow, con
     A.flow = flow;
     A.dflow = dflow;
     A.status = status;
+    A.illum = im ? illum : nullptr;
     A.n = b->total_pts;
     fill_adjoint_constants(A, b->opts);
     return launch_track_adjoint(A, b->dtype, st) == hipSuccess ? DGF_OK : DGF_ERR_HIP;

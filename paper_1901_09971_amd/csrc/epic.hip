@@ -388,33 +388,57 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
 }
 
 // Seed graph: every right / down pixel pair whose cells differ gives both cells an edge of
-// length D(p) + step(p, q) + D(q); each row keeps the least length per neighbour.  Also the
-// least edge length of the whole graph (one atomic per wavefront).
+// length D(p) + step(p, q) + D(q); each row keeps the least length per neighbour.  Neighbouring
+// lanes hold neighbouring pixels of a row, so runs of lanes often carry the same cell pair (a
+// horizontal cell border seen by the down pairs): the first lane of each run inserts the run's
+// least length for all of it.  Also the least edge length of the whole graph (one atomic per
+// wavefront).
 __global__ void k_epic_graph(int W, int H, int kappa, const uint64_t *keys, const uint16_t *E, EpicWs ws,
                              uint32_t *err, uint32_t *min_edge)
 {
     const uint32_t N = (uint32_t)W * (uint32_t)H;
+    const int lane = threadIdx.x & 63;
     uint32_t wmin = 0xFFFFFFFFu;
-    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < N; p += gridDim.x * blockDim.x) {
-        const uint32_t y = p / (uint32_t)W, x = p - y * (uint32_t)W;
-        const uint64_t kp = keys[p];
-        const uint32_t nbq[2] = {x + 1 < (uint32_t)W ? p + 1 : N, y + 1 < (uint32_t)H ? p + (uint32_t)W : N};
+    // (the loop runs a whole wavefront at a time: blockDim and the stride are multiples of 64)
+    for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < N; base += gridDim.x * blockDim.x) {
+        const uint32_t p = base + lane;
+        const bool in = p < N;
+        const uint32_t y = in ? p / (uint32_t)W : 0u, x = in ? p - y * (uint32_t)W : 0u;
+        const uint64_t kp = in ? keys[p] : kNoKey;
 #pragma unroll
         for (int d = 0; d < 2; ++d) {
-            const uint32_t q = nbq[d];
-            if (q >= N) continue;
-            const uint64_t kq = keys[q];
+            const bool has = in && (d == 0 ? x + 1 < (uint32_t)W : y + 1 < (uint32_t)H);
+            const uint32_t q = d == 0 ? p + 1 : p + (uint32_t)W;
+            const uint64_t kq = has ? keys[q] : kNoKey;
             const uint32_t ls = (uint32_t)kp, lt = (uint32_t)kq;
-            if (ls == lt) continue;
-            const uint64_t w64 = (kp >> 32) + (uint64_t)kappa + E[p] + E[q] + (kq >> 32);
-            const uint32_t w = w64 < 0xFFFFFFFFull ? (uint32_t)w64 : 0xFFFFFFFFu;
-            wmin = w < wmin ? w : wmin;
-            adj_insert(ws, ls, lt, w, err);
-            adj_insert(ws, lt, ls, w, err);
+            const bool edge = has && ls != lt;
+            uint32_t w = 0xFFFFFFFFu;
+            if (edge) {
+                const uint64_t w64 = (kp >> 32) + (uint64_t)kappa + E[p] + E[q] + (kq >> 32);
+                w = w64 < 0xFFFFFFFFull ? (uint32_t)w64 : 0xFFFFFFFFu;
+            }
+            const uint64_t pair = edge ? ((uint64_t)ls << 32) | lt : kNoKey;
+            // least length over this lane's run of equal pairs (lanes lane, lane + 1, ...)
+            uint32_t wr = w;
+            bool along = edge;
+            for (int j = 1; j < 64; ++j) {
+                const uint64_t pj = __shfl_down(pair, j, 64);
+                const uint32_t wj = __shfl_down(w, j, 64);
+                along = along && lane + j < 64 && pj == pair;
+                if (along) wr = wj < wr ? wj : wr;
+                if (!__ballot(along)) break;
+            }
+            const uint64_t prev = __shfl_up(pair, 1, 64);
+            const bool head = edge && (lane == 0 || prev != pair);
+            if (head) {
+                wmin = wr < wmin ? wr : wmin;
+                adj_insert(ws, ls, lt, wr, err);
+                adj_insert(ws, lt, ls, wr, err);
+            }
         }
     }
     wmin = wave_min_u32(wmin);
-    if ((threadIdx.x & 63) == 0 && wmin != 0xFFFFFFFFu) atomicMin(min_edge, wmin);
+    if (lane == 0 && wmin != 0xFFFFFFFFu) atomicMin(min_edge, wmin);
 }
 
 struct EpicFit {
