@@ -169,18 +169,6 @@ __global__ __launch_bounds__(256) void k_track_run(TrackParams P)
             c = fmaf(GY[j], GY[j], c);
             if constexpr (IM) sT += ((vmask >> (j / R)) & 1u) ? T[j] : 0.f;
         }
-        // gradient products of the level, for the weighted sums of every iteration (few pixels
-        // per lane only: three more registers per pixel)
-        constexpr bool kPre = !IM && PPL <= 8;
-        float GXX[kPre ? PPL : 1], GXY[kPre ? PPL : 1], GYY[kPre ? PPL : 1];
-        if constexpr (kPre) {
-#pragma unroll
-            for (int j = 0; j < PPL; ++j) {
-                GXX[j] = GX[j] * GX[j];
-                GXY[j] = GX[j] * GY[j];
-                GYY[j] = GY[j] * GY[j];
-            }
-        }
         {
             float z1 = 0.f;
             group_sum5<LPP>(a, b, c, sT, z1);
@@ -407,28 +395,15 @@ __global__ __launch_bounds__(256) void k_track_run(TrackParams P)
                     G12 = 0.f;
                     G22 = 0.f;
                     if (P.mode == ROBUST_HAMPEL) {
-                        if constexpr (kPre) {
     #pragma unroll
-                            for (int j = 0; j < PPL; ++j) {
-                                const float w = hampel_weight(RES[j], P.cs2, P.cmid);
-                                const float wr = w * RES[j];
-                                G11 = fmaf(w, GXX[j], G11);
-                                G12 = fmaf(w, GXY[j], G12);
-                                G22 = fmaf(w, GYY[j], G22);
-                                B1 = fmaf(wr, GX[j], B1);
-                                B2 = fmaf(wr, GY[j], B2);
-                            }
-                        } else {
-    #pragma unroll
-                            for (int j = 0; j < PPL; ++j) {
-                                const float w = hampel_weight(RES[j], P.cs2, P.cmid);
-                                const float wgx = w * GX[j], wgy = w * GY[j];
-                                G11 = fmaf(wgx, GX[j], G11);
-                                G12 = fmaf(wgx, GY[j], G12);
-                                G22 = fmaf(wgy, GY[j], G22);
-                                B1 = fmaf(RES[j], wgx, B1);
-                                B2 = fmaf(RES[j], wgy, B2);
-                            }
+                        for (int j = 0; j < PPL; ++j) {
+                            const float w = hampel_weight(RES[j], P.cs2, P.cmid);
+                            const float wgx = w * GX[j], wgy = w * GY[j];
+                            G11 = fmaf(wgx, GX[j], G11);
+                            G12 = fmaf(wgx, GY[j], G12);
+                            G22 = fmaf(wgy, GY[j], G22);
+                            B1 = fmaf(RES[j], wgx, B1);
+                            B2 = fmaf(RES[j], wgy, B2);
                         }
                     } else {
     #pragma unroll
