@@ -7,4 +7,4 @@ package does not load the library; the first call does, and raises if it is not 
 """
 from .api import (Batch, DetectFn, EpicOpts, TrackFn, TrackOpts, autotune, detect, detect_backward,  # noqa: F401
                   detect_count, epic, epic_workspace_bytes, get_tuning, pyramid, pyramid_layout, set_tuning, track,
-                  track_backward, track_pyramids, track_run, track_workspace_bytes)
+                  track_backward, track_batched, track_pyramids, track_run, track_workspace_bytes)

@@ -432,4 +432,20 @@ class Batch:
             pass
 
 
+def track_batched(pairs, levels: int, support: int, iters: int, opts: TrackOpts | None = None):
+    """Detect and track many uint8 pairs of uneven size in one pass (a :class:`Batch` plan, run
+    once): ``pairs`` is a list of (I0, I1, window, stride); returns one (points, flow, status)
+    per pair, copies of the plan's outputs."""
+    plan = Batch(pairs, levels, support, iters, opts=opts)
+    try:
+        P, F, S = plan.run()
+        out = []
+        for i in range(len(pairs)):
+            lo, hi = plan.offsets[i], plan.offsets[i + 1]
+            out.append((P[lo:hi].clone(), F[lo:hi].clone(), S[lo:hi].clone()))
+        return out
+    finally:
+        plan.close()
+
+
 INF = math.inf

@@ -838,18 +838,21 @@ int dgf_epic(const dgf_image *I0, const float *points, const float *flow, const 
         const int wait = ntiles <= (int64_t)cus * per_cu ? 1 : 0;
         uint32_t *busy = ws.ctr + kChunk + 2;
         bool converged = false;
-        for (int base = 0; base < kMaxRelaxLaunches && !converged; base += kChunk) {
+        // when the tiles can wait for each other one launch usually reaches the fixed point, so
+        // the first check comes after two launches (work + confirmation), later ones after kChunk
+        for (int base = 0, chunk = wait ? 2 : kChunk; base < kMaxRelaxLaunches && !converged;
+             base += chunk, chunk = kChunk) {
             hipLaunchKernelGGL(k_epic_clear_launch_counters, dim3(1), dim3(256), 0, st, ws.ctr, busy, ws.mail,
-                               kChunk, (uint32_t)ntiles);
-            for (int j = 0; j < kChunk; ++j)
+                               chunk, (uint32_t)ntiles);
+            for (int j = 0; j < chunk; ++j)
                 hipLaunchKernelGGL(k_epic_relax, tiles, dim3(kRelaxThreads), 0, st, W, H, o.kappa, ws.keys,
                                    (const uint16_t *)ws.E, ws.ctr + j, busy + j, ws.mail + j * ntiles, wait);
             if (hipGetLastError() != hipSuccess) return DGF_ERR_HIP;
             uint32_t h_changed[kChunk];
-            if (hipMemcpyAsync(h_changed, ws.ctr, sizeof(h_changed), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            if (hipMemcpyAsync(h_changed, ws.ctr, sizeof(uint32_t) * chunk, hipMemcpyDeviceToHost, st) != hipSuccess ||
                 hipStreamSynchronize(st) != hipSuccess)
                 return DGF_ERR_HIP;
-            converged = h_changed[kChunk - 1] == 0u;
+            converged = h_changed[chunk - 1] == 0u;
         }
         if (!converged) return DGF_ERR_UNSUPPORTED;
         hipLaunchKernelGGL(k_epic_graph, dim3(grid_for(N, 256)), dim3(256), 0, st, W, H, o.kappa,

@@ -144,3 +144,17 @@ def test_batched_backward_equals_per_pair_backward():
     torch.cuda.synchronize()
     assert torch.allclose(grad2[:total], grad[:total], rtol=0, atol=1e-5 * float(grad[:total].abs().max()))
     plan.close()
+
+
+def test_track_batched_convenience_equals_per_pair():
+    pairs = []
+    for i, (W, H) in enumerate([(320, 240), (200, 150)]):
+        I0, I1, _, _ = synth.layered_pair(W, H, seed=70 + i, max_disp=20.0)
+        pairs.append((torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda(), 9, 7))
+    outs = dgf.track_batched(pairs, 4, 21, 20)
+    for (a, b, w, d), (P, F, S) in zip(pairs, outs):
+        p = dgf.detect(a, w, d)
+        f, s = dgf.track(a, b, p, 4, 21, 20)
+        assert torch.equal(P, p) and torch.equal(S, s)
+        fin = torch.isfinite(f)
+        assert torch.equal(F[fin], f[fin])
