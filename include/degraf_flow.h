@@ -372,7 +372,8 @@ size_t dgf_epic_workspace_bytes(int32_t width, int32_t height, int64_t n);
  * pass changes nothing, which the host reads back.  Errors: DGF_ERR_UNSUPPORTED when
  * (width + height - 2) (kappa + 1020) exceeds 2^32 - 2 (distances are 32-bit);
  * DGF_ERR_CAPACITY when a seed's cell touches more than 32 others or a neighbour search
- * holds more than 512 candidates (the outputs of the affected cells are then NaN). */
+ * holds more than 384 candidates (about 210 at k = 128 on dense grids; the outputs of the
+ * affected cells are then NaN). */
 int dgf_epic(const dgf_image *I0, const float *points, const float *flow, const uint8_t *status, int64_t n,
              const dgf_epic_opts *opts, void *workspace, size_t ws_bytes, float *dense, int64_t dense_pitch,
              int32_t *labels, uint32_t *dist, int32_t *nbr, uint32_t *nbr_dist, float *model, void *stream);

@@ -29,8 +29,8 @@ namespace dgf {
 namespace {
 
 constexpr int kMaxDeg = 32;          // graph neighbours a seed can hold
-constexpr int kCand = 512;           // candidates one neighbour search can hold
-constexpr int kHash = 1024;          // LDS hash slots of one search (power of two, > kCand + kMaxDeg)
+constexpr int kCand = 384;           // candidates one neighbour search can hold (about 210 needed at k 128)
+constexpr int kHash = 512;           // LDS hash slots of one search (power of two, > kCand + kMaxDeg)
 constexpr int kMaxK = 256;           // largest k
 constexpr int kRT = 32;              // relaxation tile side
 constexpr int kRT2 = kRT + 2;        // with the halo
@@ -463,7 +463,7 @@ __device__ __forceinline__ double wave_sum_f64(double v)
     return v;
 }
 
-__device__ __forceinline__ int hash_slot(int32_t t) { return (int)(((uint32_t)t * 2654435761u) >> 22); }
+__device__ __forceinline__ int hash_slot(int32_t t) { return (int)(((uint32_t)t * 2654435761u) >> 23); }
 
 // One wavefront per seed s: its k nearest seeds on the seed graph in increasing (distance, index)
 // order, at graph distance <= 64 h, then the weighted least-squares affine model of the flow
@@ -475,8 +475,9 @@ __device__ __forceinline__ int hash_slot(int32_t t) { return (int)(((uint32_t)t 
 // hash index from node to candidate slot live in LDS.
 __global__ __launch_bounds__(64) void k_epic_knn_fit(EpicFit F)
 {
-    static_assert(kHash == 1 << 10, "hash_slot returns 10 bits");
+    static_assert(kHash == 1 << 9, "hash_slot returns 9 bits");
     constexpr int kStageNodes = 8; // batch nodes whose adjacency rows are read together
+    static_assert(kStageNodes * kMaxDeg >= kMaxK, "the sorted output reuses the staging arrays");
     __shared__ int32_t hkey[kHash];
     __shared__ int16_t hval[kHash];
     __shared__ int32_t cid[kCand];
@@ -486,8 +487,8 @@ __global__ __launch_bounds__(64) void k_epic_knn_fit(EpicFit F)
     __shared__ uint32_t sdist[kCand];
     __shared__ int32_t it_t[kStageNodes * kMaxDeg];
     __shared__ uint32_t it_c[kStageNodes * kMaxDeg];
-    __shared__ int32_t oid[kMaxK]; // the k nearest, sorted
-    __shared__ uint32_t od[kMaxK];
+    int32_t *oid = it_t; // the k nearest, sorted (after the search, over the staging arrays)
+    uint32_t *od = it_c;
     const int li = threadIdx.x;
     const uint64_t below = (1ull << li) - 1ull;
     const int64_t s = blockIdx.x;
