@@ -120,6 +120,7 @@ __device__ __forceinline__ bool wave_all(bool p) { return __builtin_amdgcn_ballo
 // launch.
 struct StageLanes {
     int rpp, r0, c;
+    int li;
 };
 
 template <int LPP>
@@ -135,6 +136,7 @@ __device__ __forceinline__ StageLanes stage_lanes(int cols, int li)
         sl.r0 = 0;
         sl.c = li;
     }
+    sl.li = li;
     return sl;
 }
 
@@ -144,16 +146,67 @@ __device__ __forceinline__ StageLanes stage_lanes(int cols, int li)
 // only the writes check the row count.  Byte offsets are 24-bit row x pitch products in 32 bits
 // off a scalar global base: the host rejects pitches of 2^24 bytes or more and images of 2 GiB or
 // more.
+//
+// A uint8 rectangle at most 32 texels wide that lies inside the image with three columns to spare
+// on the left and four on the right (no border to replicate) goes four texels per lane: eight
+// lanes per row, lane li keeping columns 4 (li mod 8) .. + 3 of row li / 8 of each pass; two
+// aligned dword loads per lane cut out its four bytes with v_alignbyte (rows need not be dword
+// aligned), and kStageBatch4 passes' loads are in flight before the first write.  Every byte those
+// loads touch lies on an image row between columns ox - 3 and ox + 4 ceil(cols / 4) + 3.
 constexpr int kStageBatch = 2;
+constexpr int kStageBatch4 = 2;
 
 template <int LPP, typename PixT>
 __device__ __forceinline__ void stage_rect(float *lds, int lp, const uint8_t *base, int64_t pitch, int W, int H, int ox,
                                            int oy, int rows, int cols, const StageLanes &sl)
 {
     typedef const __attribute__((address_space(1))) uint8_t gbyte;
-    if (sl.r0 >= sl.rpp) return;
+    typedef const __attribute__((address_space(1))) uint32_t gword;
     gbyte *gb = (gbyte *)base;
     const uint32_t pb = (uint32_t)pitch, hm1 = (uint32_t)(H - 1);
+    if constexpr (sizeof(PixT) == 1) {
+        constexpr int rpp4 = LPP / 8;
+        if (cols <= 32 && ox >= 3 && oy >= 0 && ox + 4 * ((cols + 3) >> 2) + 4 <= W && oy + rows <= H) {
+            const int r04 = sl.li >> 3, c4 = (sl.li & 7) << 2;
+            if (c4 >= cols) return;
+            const uint32_t mis = (uint32_t)(uintptr_t)base & 3u, cx = (uint32_t)(ox + c4);
+            const bool full = c4 + 4 <= cols;
+            for (int y0 = r04; y0 < rows; y0 += kStageBatch4 * rpp4) {
+                uint32_t lo[kStageBatch4], hi[kStageBatch4], sh[kStageBatch4];
+#pragma unroll
+                for (int k = 0; k < kStageBatch4; ++k) {
+                    const int y = min(y0 + k * rpp4, rows - 1);
+                    const uint32_t off = __umul24((uint32_t)(oy + y), pb) + cx;
+                    sh[k] = (off + mis) & 3u;
+                    gword *p = (gword *)(gb + (off - sh[k]));
+                    lo[k] = p[0];
+                    hi[k] = p[1];
+                }
+#pragma unroll
+                for (int k = 0; k < kStageBatch4; ++k) {
+                    const int y = y0 + k * rpp4;
+                    if (y < rows) {
+                        const uint32_t v = __builtin_amdgcn_alignbyte(hi[k], lo[k], sh[k]);
+                        float *d = lds + y * lp + c4;
+                        const float f0 = (float)(v & 255u), f1 = (float)((v >> 8) & 255u),
+                                    f2 = (float)((v >> 16) & 255u), f3 = (float)(v >> 24);
+                        if (full) {
+                            d[0] = f0;
+                            d[1] = f1;
+                            d[2] = f2;
+                            d[3] = f3;
+                        } else {
+                            d[0] = f0;
+                            if (c4 + 1 < cols) d[1] = f1;
+                            if (c4 + 2 < cols) d[2] = f2;
+                        }
+                    }
+                }
+            }
+            return;
+        }
+    }
+    if (sl.r0 >= sl.rpp) return;
     for (int c = sl.c; c < cols; c += LPP) { // a single pass when cols <= LPP
         const uint32_t cx = (uint32_t)clampi(ox + c, 0, W - 1) * (uint32_t)sizeof(PixT);
         for (int y0 = sl.r0; y0 < rows; y0 += kStageBatch * sl.rpp) {
