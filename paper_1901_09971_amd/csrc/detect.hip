@@ -6,8 +6,8 @@
 // weight sum is kept (strictly larger for the negative one).
 //
 // The image is read once from HBM: a workgroup owns a TX x TY block of windows, stages the
-// pixel rectangle they cover into LDS with coalesced row loads, and each lane then reduces its
-// own window from LDS.  Only the positive moments are accumulated; the negative ones follow
+// pixel rectangle they cover into LDS four bytes per lane (aligned dword pairs), and each lane
+// then reduces its own window from LDS.  Only the positive moments are accumulated; the negative ones follow
 // exactly from sum (1 + m - I) = (1 + m) w h - sum I (and likewise for the moments).
 #include "dgf_internal.hpp"
 
@@ -19,7 +19,11 @@ struct DetectOut {
     float *resp;
 };
 
-size_t detect_tile_lds(int win, int stride) { return (size_t)(15 * stride + win) * (size_t)(15 * stride + win); }
+// LDS of one 16 x 16-window tile: rows of (15 stride + win) bytes at a pitch rounded up to 4
+size_t detect_tile_lds(int win, int stride)
+{
+    return (size_t)((15 * stride + win + 3) & ~3) * (size_t)(15 * stride + win);
+}
 
 __device__ __forceinline__ void finish_window(int S, int Mi, int Mj, int m, int win, int x0, int y0, int64_t n,
                                               DetectOut o)
@@ -51,26 +55,22 @@ template <int TX, int TY>
 __device__ __forceinline__ void detect_tile(const uint8_t *__restrict__ img, int64_t pitch, int W, int H, int win,
                                             int stride, int nx, int ny, int64_t n0, DetectOut o)
 {
-    extern __shared__ uint8_t tile[];
+    extern __shared__ __align__(16) uint8_t tile[];
     const int wx0 = blockIdx.x * TX, wy0 = blockIdx.y * TY;
     const int ox = wx0 * stride, oy = wy0 * stride;
-    const int RW = (TX - 1) * stride + win, RH = (TY - 1) * stride + win;
+    const int RW = (TX - 1) * stride + win, RH = (TY - 1) * stride + win, RP = (RW + 3) & ~3;
     const int rw = min(RW, W - ox), rh = min(RH, H - oy);
-    // coalesced staging: consecutive lanes read consecutive bytes of a row
-    for (int i = threadIdx.x; i < rw * rh; i += blockDim.x) {
-        const int y = i / rw, x = i - y * rw;
-        tile[y * RW + x] = img[(int64_t)(oy + y) * pitch + ox + x];
-    }
+    stage_u8_block<4>(tile, RP, img, pitch, W, ox, oy, rw, rh);
     __syncthreads();
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int kx = wx0 + tx, ky = wy0 + ty;
     if (kx >= nx || ky >= ny) return;
-    const uint8_t *w0 = tile + ty * stride * RW + tx * stride;
+    const uint8_t *w0 = tile + ty * stride * RP + tx * stride;
     int S = 0, Mi = 0, Mj = 0, m = 0;
     for (int i = 0; i < win; ++i) {
         int rs = 0, rj = 0;
         for (int j = 0; j < win; ++j) {
-            const int v = w0[i * RW + j];
+            const int v = w0[i * RP + j];
             rs += v;
             rj += j * v;
             m = max(m, v);
@@ -130,9 +130,10 @@ hipError_t launch_detect(const uint8_t *img, int64_t pitch, int W, int H, int wi
     DetectOut o{pts, sel, resp};
     constexpr int TX = 16, TY = 16;
     const int64_t RW = (int64_t)(TX - 1) * stride + win, RH = (int64_t)(TY - 1) * stride + win;
-    if (RW * RH <= 48 * 1024) {
+    const int64_t RP = (RW + 3) & ~(int64_t)3;
+    if (RP * RH <= 48 * 1024) {
         dim3 grid((nx + TX - 1) / TX, (ny + TY - 1) / TY);
-        hipLaunchKernelGGL((k_detect_tiled<TX, TY>), grid, dim3(TX * TY), (size_t)(RW * RH), st, img, pitch, W, H, win,
+        hipLaunchKernelGGL((k_detect_tiled<TX, TY>), grid, dim3(TX * TY), (size_t)(RP * RH), st, img, pitch, W, H, win,
                            stride, nx, ny, o);
     } else {
         const int64_t N = (int64_t)nx * ny;

@@ -225,6 +225,82 @@ __device__ __forceinline__ void stage_rect(float *lds, int lp, const uint8_t *ba
     }
 }
 
+// i / d for 0 <= i < 2^16 and 1 <= d < 2^8, with inv = 1 / d: (i + 1/2) / d is at least 1 / (2 d)
+// away from the next integer and the float product errs by far less, so the truncation is exact.
+__device__ __forceinline__ int div_small(int i, float inv) { return (int)(((float)i + 0.5f) * inv); }
+
+// Block-wide copy of the w x h byte rectangle whose top-left pixel is (x, y) of a uint8 image
+// (row pitch `pitch` bytes, width W; the rectangle lies inside the image) into LDS with row pitch
+// lp, a multiple of 4 at least 4 ceil(w / 4), from a 4-byte aligned base.  Four bytes per lane
+// and step, from two aligned dwords of the image row cut by v_alignbyte; kB steps' loads are
+// issued before the first LDS write.  A group whose dword pair would leave the row loads an
+// in-row pair instead (branch-free, so no load waits on another) and is redone byte by byte
+// afterwards; rows narrower than 11 bytes go byte by byte throughout.  Bytes w .. 4 ceil(w / 4) - 1
+// of an LDS row receive copies of row bytes (clamped).
+template <int kB>
+__device__ __forceinline__ void stage_u8_block(uint8_t *lds, int lp, const uint8_t *img, int64_t pitch, int W, int x,
+                                              int y, int w, int h)
+{
+    typedef const __attribute__((address_space(1))) uint8_t gbyte;
+    typedef const __attribute__((address_space(1))) uint32_t gword;
+    const int n4 = (w + 3) >> 2, G = n4 * h, nt = (int)blockDim.x;
+    const float inv = 1.0f / (float)n4;
+    const uint32_t mis = (uint32_t)(uintptr_t)img & 3u;
+    gbyte *gb = (gbyte *)img;
+    auto bytes = [&](int64_t row, int c) {
+        uint32_t t = 0u;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) t |= (uint32_t)gb[row + min(x + c + b, W - 1)] << (8 * b);
+        return t;
+    };
+    if (W < 11) {
+        for (int g = (int)threadIdx.x; g < G; g += nt) {
+            const int r = div_small(g, inv), c = 4 * (g - r * n4);
+            *reinterpret_cast<uint32_t *>(lds + r * lp + c) = bytes((int64_t)(y + r) * pitch, c);
+        }
+        return;
+    }
+    for (int g0 = (int)threadIdx.x; g0 < G; g0 += kB * nt) {
+        uint32_t lo[kB], hi[kB], sh[kB];
+        unsigned edge = 0u;
+#pragma unroll
+        for (int k = 0; k < kB; ++k) {
+            const int g = min(g0 + k * nt, G - 1);
+            const int r = div_small(g, inv), c = 4 * (g - r * n4);
+            const int64_t row = (int64_t)(y + r) * pitch;
+            const int s = (int)((row + x + c + mis) & 3);
+            int a = x + c - s; // image column of the first aligned dword: a is in [-3, W - 1]
+            const bool fits = a >= 0 && a + 8 <= W;
+            // else the nearest aligned pair inside the row (one exists when W >= 11)
+            a = a < 0 ? a + 4 : a;
+            a = a + 8 > W ? a - 4 * ((a + 11 - W) >> 2) : a;
+            gword *p = (gword *)(gb + (row + a));
+            lo[k] = p[0];
+            hi[k] = p[1];
+            sh[k] = (uint32_t)s;
+            edge |= (fits ? 0u : 1u) << k;
+        }
+#pragma unroll
+        for (int k = 0; k < kB; ++k) {
+            const int g = g0 + k * nt;
+            if (g < G) {
+                const int r = div_small(g, inv), c = 4 * (g - r * n4);
+                *reinterpret_cast<uint32_t *>(lds + r * lp + c) = __builtin_amdgcn_alignbyte(hi[k], lo[k], sh[k]);
+            }
+        }
+        if (edge) {
+#pragma unroll
+            for (int k = 0; k < kB; ++k) {
+                const int g = g0 + k * nt;
+                if (g < G && ((edge >> k) & 1u)) {
+                    const int r = div_small(g, inv), c = 4 * (g - r * n4);
+                    *reinterpret_cast<uint32_t *>(lds + r * lp + c) = bytes((int64_t)(y + r) * pitch, c);
+                }
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // launch descriptors
 // ------------------------------------------------------------------------------------------

@@ -120,10 +120,11 @@ constexpr int PC_T = 4, PC_MAXM = 4;
 constexpr int pc_width(int m) { return m == 0 ? PC_T : 2 * pc_width(m - 1) + 3; } // region width m levels finer
 constexpr int PC_N0 = pc_width(PC_MAXM);     // 109: staged source rectangle side
 constexpr int PC_N1 = pc_width(PC_MAXM - 1); // 53: first produced level
+constexpr int PC_N0P = (PC_N0 + 3) & ~3;     // 112: row pitch of the staged source rectangle
 
 __global__ __launch_bounds__(256) void k_pyr_chain_u8(PyrChain A)
 {
-    __shared__ uint8_t lvl[2][PC_N0 * PC_N0];
+    __shared__ __align__(16) uint8_t lvl[2][PC_N0P * PC_N0];
     __shared__ uint16_t hs[PC_N0 * PC_N1];
     const int f = blockIdx.z, m = A.m, tid = threadIdx.x;
     // needed (lo, hi) at every level, coarsest first, then clamped into the level
@@ -144,27 +145,22 @@ __global__ __launch_bounds__(256) void k_pyr_chain_u8(PyrChain A)
             y1[k] = hy < A.H[k] - 1 ? hy : A.H[k] - 1;
         }
     }
-    // stage level s
-    {
-        const int w = x1[0] - x0[0] + 1, h = y1[0] - y0[0] + 1;
-        const uint8_t *src = A.src[f];
-        for (int i = tid; i < w * h; i += 256) {
-            const int y = i / w, x = i - y * w;
-            lvl[0][i] = src[(int64_t)(y0[0] + y) * A.src_pitch[f] + x0[0] + x];
-        }
-    }
+    // stage level s (row pitch 4 ceil(w / 4); the produced levels use their own width)
+    const int w0 = x1[0] - x0[0] + 1, p0 = (w0 + 3) & ~3;
+    stage_u8_block<4>(lvl[0], p0, A.src[f], A.src_pitch[f], A.W[0], x0[0], y0[0], w0, y1[0] - y0[0] + 1);
     __syncthreads();
     for (int k = 0; k < m; ++k) {
         const uint8_t *in = lvl[k & 1];
         uint8_t *out = lvl[(k + 1) & 1];
-        const int wi = x1[k] - x0[k] + 1, hi = y1[k] - y0[k] + 1;
+        const int wi = x1[k] - x0[k] + 1, hi = y1[k] - y0[k] + 1, pin = k == 0 ? p0 : wi;
         const int wo = x1[k + 1] - x0[k + 1] + 1, ho = y1[k + 1] - y0[k + 1] + 1;
+        const float inv_wo = 1.0f / (float)wo;
         const int Wk = A.W[k], Hk = A.H[k];
         // horizontal pass: every staged row, at the output column rate
         for (int i = tid; i < hi * wo; i += 256) {
-            const int r = i / wo, xo = i - r * wo;
+            const int r = div_small(i, inv_wo), xo = i - r * wo;
             const int c = 2 * (x0[k + 1] + xo);
-            const uint8_t *row = in + r * wi;
+            const uint8_t *row = in + r * pin;
             auto at = [&](int cc) { return (int)row[(cc < 0 ? 0 : (cc > Wk - 1 ? Wk - 1 : cc)) - x0[k]]; };
             hs[i] = (uint16_t)(at(c - 2) + at(c + 2) + 4 * (at(c - 1) + at(c + 1)) + 6 * at(c));
         }
@@ -176,7 +172,7 @@ __global__ __launch_bounds__(256) void k_pyr_chain_u8(PyrChain A)
         uint8_t *dst = A.dst[k][f];
         const int64_t dp = A.dst_pitch[k];
         for (int i = tid; i < ho * wo; i += 256) {
-            const int yo = i / wo, xo = i - yo * wo;
+            const int yo = div_small(i, inv_wo), xo = i - yo * wo;
             const int gy = y0[k + 1] + yo, gx = x0[k + 1] + xo;
             const int rr = 2 * gy;
             auto at = [&](int r) { return (int)hs[((r < 0 ? 0 : (r > Hk - 1 ? Hk - 1 : r)) - y0[k]) * wo + xo]; };
