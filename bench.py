@@ -4,7 +4,9 @@
 One step = DeGraF key-point detection on I0, the pyramids of both frames, and robust tracking of
 every detected point, on one 1242x375 driving-shaped uint8 pair (window 9, stride 5: 18,278
 points; 5 pyramid levels, 21x21 support, at most 20 iterations per level).  The frames are
-resident in device memory before the timed region; every step recomputes everything.
+resident in device memory before the timed region; every step recomputes everything, in two
+launches: detection beside both pyramids (dgf_detect_pyramids), then tracking
+(``--separate-detect``: detection, pyramids and tracking as three launches).
 
 Prints ONE JSON line.  ``value`` is tracked points per second over the timed steps.  The
 ``roofline`` object describes the dominant kernel (the tracker): its algorithmic FP32 work per
@@ -440,6 +442,8 @@ def main():
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation measurement")
     ap.add_argument("--density-reps", type=int, default=3)
     ap.add_argument("--no-interp", action="store_true", help="skip the dense interpolation measurement")
+    ap.add_argument("--separate-detect", action="store_true",
+                    help="step as three launches (detect, pyramids, track) instead of detect+pyramids, track")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -478,9 +482,17 @@ def main():
     else:
         tuning = dgf.get_tuning(w["support"], w["levels"], 0, N)
 
+    fused = not args.separate_detect
+
+    def front():
+        if fused:
+            dgf.detect_pyramids(I0, I1, w["window"], w["stride"], w["levels"], ws, pts)
+        else:
+            dgf.detect(I0, w["window"], w["stride"], out=pts)
+            dgf.track_pyramids(I0, I1, w["levels"], ws)
+
     def step(iters_out=None):
-        dgf.detect(I0, w["window"], w["stride"], out=pts)
-        dgf.track_pyramids(I0, I1, w["levels"], ws)
+        front()
         dgf.track_run(I0, I1, pts, w["levels"], w["support"], w["iters"], ws, flow, status, iters_out)
 
     # work accounting (not timed): executed iterations of every point
@@ -503,9 +515,13 @@ def main():
     for k in range(K):
         e = ev[k]
         e[0].record()
-        dgf.detect(I0, w["window"], w["stride"], out=pts)
-        e[1].record()
-        dgf.track_pyramids(I0, I1, w["levels"], ws)
+        if fused:  # one launch: e[0] .. e[2] spans detection and pyramids together
+            e[1].record()
+            dgf.detect_pyramids(I0, I1, w["window"], w["stride"], w["levels"], ws, pts)
+        else:
+            dgf.detect(I0, w["window"], w["stride"], out=pts)
+            e[1].record()
+            dgf.track_pyramids(I0, I1, w["levels"], ws)
         e[2].record()
         dgf.track_run(I0, I1, pts, w["levels"], w["support"], w["iters"], ws, flow, status)
         e[3].record()
@@ -559,10 +575,13 @@ def main():
             "track_ms": t_track,
         },
         "kernels": {
-            "detect": {"ms": t_detect, "algorithmic_bytes": det_bytes,
-                       "hbm_frac": det_bytes / (t_detect * 1e-3) / (PEAK_HBM_GBPS * 1e9)},
-            "pyramids": {"ms": t_pyr, "launches": w["levels"] - 1, "algorithmic_bytes": pyr_read + pyr_write,
-                         "hbm_frac": (pyr_read + pyr_write) / (t_pyr * 1e-3) / (PEAK_HBM_GBPS * 1e9)},
+            "detect": ({"fused_with": "pyramids", "algorithmic_bytes": det_bytes} if fused else
+                       {"ms": t_detect, "algorithmic_bytes": det_bytes,
+                        "hbm_frac": det_bytes / (t_detect * 1e-3) / (PEAK_HBM_GBPS * 1e9)}),
+            "pyramids": {"ms": t_pyr, "launches": (w["levels"] + 2) // 4, "includes_detection": fused,
+                         "algorithmic_bytes": pyr_read + pyr_write + (det_bytes if fused else 0),
+                         "hbm_frac": (pyr_read + pyr_write + (det_bytes if fused else 0)) / (t_pyr * 1e-3)
+                         / (PEAK_HBM_GBPS * 1e9)},
             "track": {"ms": t_track, "iterations": it_total, "status_counts": st_counts, "tuning": tuning},
         },
         "host_wall_s": t_host,

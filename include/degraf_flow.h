@@ -323,6 +323,24 @@ int dgf_track_run(const dgf_image *I0, const dgf_image *I1, const float *points,
                   size_t ws_bytes, float *flow, uint8_t *status, int32_t *iters_out, float *illum_out,
                   void *stream);
 
+/* dgf_detect on I0 and dgf_track_pyramids on (I0, I1) in one launch where they fit one
+ * (Section 2 "Point detection"; the pyramids serve "Point tracking"): the detection tiles run
+ * beside the tiles of the first pyramid-chain launch, so the two independent, latency-bound jobs
+ * overlap.  Outputs are identical to the two separate calls: points / sel / response as from
+ * dgf_detect(I0, window, stride, points, sel, response, capacity), and the pyramids in
+ * `workspace` as from dgf_track_pyramids(I0, I1, levels, workspace, ws_bytes), ready for
+ * dgf_track_run.  With levels == 1, no points, or a detection tile larger than the chain's LDS
+ * (about 24 KB: (15 stride + window) rows of that many bytes), the two calls are made one after
+ * the other on `stream`.
+ *   I0, I1   : DGF_U8 frames of equal size (else DGF_ERR_INVALID_ARG)
+ *   window, stride, points, sel, response, capacity : as for dgf_detect
+ *   levels, workspace, ws_bytes : as for dgf_track_pyramids
+ * Every argument is validated before anything is launched; no host synchronisation, no
+ * allocation.  The caller owns every buffer. */
+int dgf_detect_pyramids(const dgf_image *I0, const dgf_image *I1, int32_t window, int32_t stride, int32_t levels,
+                        void *workspace, size_t ws_bytes, float *points, uint8_t *sel, float *response,
+                        int64_t capacity, void *stream);
+
 /* ---- dense flow by edge-preserving interpolation (Section 2 "Interpolation") ---------------- */
 
 /* Interpolation constants.  k: neighbours per pixel (Section 3 "Parameters": 128), 1 .. 256.

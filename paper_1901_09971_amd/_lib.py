@@ -65,6 +65,7 @@ SIGNATURES = {
     "dgf_track": (ctypes.c_int, [IMG, IMG, P, I64, I32, I32, I32, OPTS, P, SZ, P, P, P, P, P]),
     "dgf_track_pyramids": (ctypes.c_int, [IMG, IMG, I32, P, SZ, P]),
     "dgf_track_run": (ctypes.c_int, [IMG, IMG, P, I64, I32, I32, I32, OPTS, P, SZ, P, P, P, P, P]),
+    "dgf_detect_pyramids": (ctypes.c_int, [IMG, IMG, I32, I32, I32, P, SZ, P, P, P, I64, P]),
     "dgf_track_backward": (ctypes.c_int, [IMG, IMG, P, I64, I32, OPTS, P, P, P, P, P, P, P, P]),
     "dgf_detect_backward": (ctypes.c_int, [IMG, I32, I32, P, P, I64, P, I64, P]),
     "dgf_batch_create": (ctypes.c_int, [ctypes.POINTER(DgfPairDesc), I32, I32, I32, I32, OPTS,

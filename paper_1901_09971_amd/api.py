@@ -147,6 +147,24 @@ def track_pyramids(I0: torch.Tensor, I1: torch.Tensor, levels: int, workspace: t
                                    _stream()), "dgf_track_pyramids")
 
 
+def detect_pyramids(I0: torch.Tensor, I1: torch.Tensor, window: int, stride: int, levels: int,
+                    workspace: torch.Tensor, points: torch.Tensor, sel: torch.Tensor | None = None,
+                    response: torch.Tensor | None = None) -> None:
+    """:func:`detect` on ``I0`` into ``points`` (float32 [n, 2], n = :func:`detect_count`; optional
+    ``sel`` uint8 [n] and ``response`` float32 [n]) and :func:`track_pyramids` of the pair into
+    ``workspace``, in one launch where they fit one (dgf_detect_pyramids)."""
+    a, b = _image(I0, "I0"), _image(I1, "I1")
+    n = detect_count(I0.shape[1], I0.shape[0], window, stride)
+    if points.shape != (n, 2) or points.dtype != torch.float32 or not points.is_contiguous():
+        raise ValueError(f"points: expected a contiguous float32 tensor of shape {(n, 2)}")
+    for t, dt, name in ((sel, torch.uint8, "sel"), (response, torch.float32, "response")):
+        if t is not None and (t.shape != (n,) or t.dtype != dt or not t.is_contiguous()):
+            raise ValueError(f"{name}: expected a contiguous {dt} tensor of shape {(n,)}")
+    check(lib().dgf_detect_pyramids(ctypes.byref(a), ctypes.byref(b), window, stride, levels, _ptr(workspace),
+                                    workspace.numel(), _ptr(points), _ptr(sel), _ptr(response), n, _stream()),
+          "dgf_detect_pyramids")
+
+
 def track_run(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, levels: int, support: int, iters: int,
               workspace: torch.Tensor, flow: torch.Tensor, status: torch.Tensor, iters_out: torch.Tensor | None = None,
               opts: TrackOpts | None = None, illum_out: torch.Tensor | None = None) -> None:

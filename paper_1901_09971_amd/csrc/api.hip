@@ -205,6 +205,54 @@ int dgf_track_pyramids(const dgf_image *I0, const dgf_image *I1, int32_t levels,
     return DGF_OK;
 }
 
+int dgf_detect_pyramids(const dgf_image *I0, const dgf_image *I1, int32_t window, int32_t stride, int32_t levels,
+                        void *workspace, size_t ws_bytes, float *points, uint8_t *sel, float *response,
+                        int64_t capacity, void *stream)
+{
+    // everything both parts check, before anything is launched
+    int rc = check_pair(I0, I1, levels);
+    if (rc != DGF_OK) return rc;
+    if (I0->dtype != DGF_U8) return DGF_ERR_INVALID_ARG;
+    if (window < 1 || window > DGF_MAX_WINDOW || stride < 1) return DGF_ERR_INVALID_ARG;
+    const int64_t n = dgf_detect_count(I0->width, I0->height, window, stride);
+    if (n > 0 && !points) return DGF_ERR_INVALID_ARG;
+    if (n > capacity) return DGF_ERR_CAPACITY;
+    if (levels > 1 && (!workspace || ws_bytes < dgf_track_workspace_bytes(I0->width, I0->height, levels, I0->dtype)))
+        return DGF_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    if (levels == 1 || n == 0 || !front_detect_fits(window, stride)) {
+        if (n > 0) {
+            rc = dgf_detect(I0, window, stride, points, sel, response, capacity, stream);
+            if (rc != DGF_OK) return rc;
+        }
+        return dgf_track_pyramids(I0, I1, levels, workspace, ws_bytes, stream);
+    }
+    LevelPair lv[DGF_MAX_LEVELS];
+    pyramid_levels(I0, I1, levels, workspace, lv, nullptr);
+    const uint8_t *srcs[2] = {lv[0].p0, lv[0].p1};
+    const int64_t sp[2] = {lv[0].pitch0, lv[0].pitch1};
+    uint8_t *lvl[2][DGF_MAX_LEVELS] = {};
+    int64_t pitch[DGF_MAX_LEVELS] = {};
+    for (int l = 1; l < levels; ++l) {
+        lvl[0][l] = (uint8_t *)lv[l].p0;
+        lvl[1][l] = (uint8_t *)lv[l].p1;
+        pitch[l] = lv[l].pitch0;
+    }
+    FrontDetect D{};
+    D.img = (const uint8_t *)I0->data;
+    D.pitch = I0->pitch_bytes;
+    D.W = I0->width;
+    D.H = I0->height;
+    D.win = window;
+    D.stride = stride;
+    D.nx = (D.W - window) / stride + 1;
+    D.ny = (D.H - window) / stride + 1;
+    D.tiles_x = (D.nx + 15) / 16;
+    D.tiles_y = (D.ny + 15) / 16;
+    D.o = DetectOut{points, sel, response};
+    return hip_rc(launch_pyr_chains(srcs, sp, lvl, pitch, I0->width, I0->height, levels, 2, st, &D));
+}
+
 } // extern "C"
 
 namespace dgf {

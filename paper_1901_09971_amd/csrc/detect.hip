@@ -13,80 +13,18 @@
 
 namespace dgf {
 
-struct DetectOut {
-    float *pts;
-    uint8_t *sel;
-    float *resp;
-};
-
 // LDS of one 16 x 16-window tile: rows of (15 stride + win) bytes at a pitch rounded up to 4
 size_t detect_tile_lds(int win, int stride)
 {
     return (size_t)((15 * stride + win + 3) & ~3) * (size_t)(15 * stride + win);
 }
 
-__device__ __forceinline__ void finish_window(int S, int Mi, int Mj, int m, int win, int x0, int y0, int64_t n,
-                                              DetectOut o)
-{
-    const int wh = win * win;
-    const int mom = win * (win * (win - 1) / 2); // sum over the window of a row (or column) index
-    const int S_neg = (1 + m) * wh - S;
-    const int Mi_neg = (1 + m) * mom - Mi;
-    const int Mj_neg = (1 + m) * mom - Mj;
-    const bool neg = S_neg > S;
-    const float cnx = (float)Mj_neg / (float)S_neg, cny = (float)Mi_neg / (float)S_neg;
-    float cpx, cpy;
-    if (S > 0) {
-        cpx = (float)Mj / (float)S;
-        cpy = (float)Mi / (float)S;
-    } else {
-        cpx = 0.5f * (float)(win - 1);
-        cpy = cpx;
-    }
-    const float ox = neg ? cnx : cpx, oy = neg ? cny : cpy;
-    reinterpret_cast<float2 *>(o.pts)[n] = make_float2((float)x0 + ox, (float)y0 + oy);
-    if (o.sel) o.sel[n] = (uint8_t)neg;
-    if (o.resp) o.resp[n] = sqrtf((cpx - cnx) * (cpx - cnx) + (cpy - cny) * (cpy - cny));
-}
-
-// LDS-tiled form: TX x TY windows per workgroup, one lane per window.  n0 offsets the output
-// (batched form: points of a pair start at its offset in the concatenated output).
-template <int TX, int TY>
-__device__ __forceinline__ void detect_tile(const uint8_t *__restrict__ img, int64_t pitch, int W, int H, int win,
-                                            int stride, int nx, int ny, int64_t n0, DetectOut o)
-{
-    extern __shared__ __align__(16) uint8_t tile[];
-    const int wx0 = blockIdx.x * TX, wy0 = blockIdx.y * TY;
-    const int ox = wx0 * stride, oy = wy0 * stride;
-    const int RW = (TX - 1) * stride + win, RH = (TY - 1) * stride + win, RP = (RW + 3) & ~3;
-    const int rw = min(RW, W - ox), rh = min(RH, H - oy);
-    stage_u8_block<4>(tile, RP, img, pitch, W, ox, oy, rw, rh);
-    __syncthreads();
-    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-    const int kx = wx0 + tx, ky = wy0 + ty;
-    if (kx >= nx || ky >= ny) return;
-    const uint8_t *w0 = tile + ty * stride * RP + tx * stride;
-    int S = 0, Mi = 0, Mj = 0, m = 0;
-    for (int i = 0; i < win; ++i) {
-        int rs = 0, rj = 0;
-        for (int j = 0; j < win; ++j) {
-            const int v = w0[i * RP + j];
-            rs += v;
-            rj += j * v;
-            m = max(m, v);
-        }
-        S += rs;
-        Mi += i * rs;
-        Mj += rj;
-    }
-    finish_window(S, Mi, Mj, m, win, kx * stride, ky * stride, n0 + (int64_t)ky * nx + kx, o);
-}
-
 template <int TX, int TY>
 __global__ __launch_bounds__(TX *TY) void k_detect_tiled(const uint8_t *__restrict__ img, int64_t pitch, int W, int H,
                                                           int win, int stride, int nx, int ny, DetectOut o)
 {
-    detect_tile<TX, TY>(img, pitch, W, H, win, stride, nx, ny, 0, o);
+    extern __shared__ __align__(16) uint8_t tile[];
+    detect_tile<TX, TY>(tile, (int)blockIdx.x, (int)blockIdx.y, img, pitch, W, H, win, stride, nx, ny, 0, o);
 }
 
 // Batched form: blockIdx.z selects the pair; tiles beyond a pair's window grid exit at once.
@@ -95,7 +33,9 @@ __global__ __launch_bounds__(TX *TY) void k_detect_batched(const DetectJob *__re
 {
     const DetectJob J = jobs[blockIdx.z];
     if ((int)blockIdx.x * TX >= J.nx || (int)blockIdx.y * TY >= J.ny) return;
-    detect_tile<TX, TY>(J.img, J.pitch, J.W, J.H, J.win, J.stride, J.nx, J.ny, J.out_off, o);
+    extern __shared__ __align__(16) uint8_t tile[];
+    detect_tile<TX, TY>(tile, (int)blockIdx.x, (int)blockIdx.y, J.img, J.pitch, J.W, J.H, J.win, J.stride, J.nx, J.ny,
+                        J.out_off, o);
 }
 
 // Direct form for windows too large to tile: one lane per window, reads through the cache.

@@ -113,6 +113,41 @@ __device__ __forceinline__ void wave_sum5(float &a, float &b, float &c, float &d
 
 __device__ __forceinline__ bool wave_all(bool p) { return __builtin_amdgcn_ballot_w64(!p) == 0ull; }
 
+// DeGraF centroid of one w x w window from its integer sums (Section 2 "Point detection", Eq. 1
+// and 2): S = sum I, Mi = sum i I, Mj = sum j I (i row, j column within the window), m = max I.
+// The negative weights 1 + m - I give S- = (1 + m) w^2 - S and moments (1 + m) w (w(w-1)/2) - M;
+// the negative centroid is taken when S- > S.  (ox, oy) is the chosen centroid within the window,
+// resp the distance between the two centroids.
+struct DgfCentroid {
+    float ox, oy, resp;
+    bool neg;
+};
+
+__device__ __forceinline__ DgfCentroid degraf_centroid(int S, int Mi, int Mj, int m, int win)
+{
+    const int wh = win * win;
+    const int mom = win * (win * (win - 1) / 2); // sum over the window of a row (or column) index
+    const int S_neg = (1 + m) * wh - S;
+    const int Mi_neg = (1 + m) * mom - Mi;
+    const int Mj_neg = (1 + m) * mom - Mj;
+    const bool neg = S_neg > S;
+    const float cnx = (float)Mj_neg / (float)S_neg, cny = (float)Mi_neg / (float)S_neg;
+    float cpx, cpy;
+    if (S > 0) {
+        cpx = (float)Mj / (float)S;
+        cpy = (float)Mi / (float)S;
+    } else {
+        cpx = 0.5f * (float)(win - 1);
+        cpy = cpx;
+    }
+    DgfCentroid d;
+    d.ox = neg ? cnx : cpx;
+    d.oy = neg ? cny : cpy;
+    d.neg = neg;
+    d.resp = sqrtf((cpx - cnx) * (cpx - cnx) + (cpy - cny) * (cpy - cny));
+    return d;
+}
+
 // Lane layout for staging a rectangle `cols` floats wide with the LPP lanes of one point.  With
 // cols <= LPP, rpp = LPP / cols rows go per pass and lane li keeps column c = li mod cols of row
 // r0 = li / cols (lanes with r0 >= rpp stay idle); a wider rectangle takes one row per pass and
@@ -299,6 +334,58 @@ __device__ __forceinline__ void stage_u8_block(uint8_t *lds, int lp, const uint8
             }
         }
     }
+}
+
+// ---- detection tiles (shared by the detection launches and the fused front-end launch) -------
+
+struct DetectOut {
+    float *pts;
+    uint8_t *sel;
+    float *resp;
+};
+
+__device__ __forceinline__ void finish_window(int S, int Mi, int Mj, int m, int win, int x0, int y0, int64_t n,
+                                              DetectOut o)
+{
+    const DgfCentroid d = degraf_centroid(S, Mi, Mj, m, win);
+    reinterpret_cast<float2 *>(o.pts)[n] = make_float2((float)x0 + d.ox, (float)y0 + d.oy);
+    if (o.sel) o.sel[n] = (uint8_t)d.neg;
+    if (o.resp) o.resp[n] = d.resp;
+}
+
+// LDS-tiled form: TX x TY windows per workgroup (tile (tile_x, tile_y) of the window grid), one
+// lane per window, the covered pixels staged in `tile` (row pitch rounded up to 4 bytes, 4-byte
+// aligned).  n0 offsets the output (batched form: points of a pair start at its offset in the
+// concatenated output).
+template <int TX, int TY>
+__device__ __forceinline__ void detect_tile(uint8_t *tile, int tile_x, int tile_y, const uint8_t *__restrict__ img,
+                                            int64_t pitch, int W, int H, int win, int stride, int nx, int ny, int64_t n0,
+                                            DetectOut o)
+{
+    const int wx0 = tile_x * TX, wy0 = tile_y * TY;
+    const int ox = wx0 * stride, oy = wy0 * stride;
+    const int RW = (TX - 1) * stride + win, RH = (TY - 1) * stride + win, RP = (RW + 3) & ~3;
+    const int rw = min(RW, W - ox), rh = min(RH, H - oy);
+    stage_u8_block<4>(tile, RP, img, pitch, W, ox, oy, rw, rh);
+    __syncthreads();
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int kx = wx0 + tx, ky = wy0 + ty;
+    if (kx >= nx || ky >= ny) return;
+    const uint8_t *w0 = tile + ty * stride * RP + tx * stride;
+    int S = 0, Mi = 0, Mj = 0, m = 0;
+    for (int i = 0; i < win; ++i) {
+        int rs = 0, rj = 0;
+        for (int j = 0; j < win; ++j) {
+            const int v = w0[i * RP + j];
+            rs += v;
+            rj += j * v;
+            m = max(m, v);
+        }
+        S += rs;
+        Mi += i * rs;
+        Mj += rj;
+    }
+    finish_window(S, Mi, Mj, m, win, kx * stride, ky * stride, n0 + (int64_t)ky * nx + kx, o);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -562,10 +649,20 @@ struct PyrChain {
     int32_t W[5], H[5];
     int32_t m;
 };
-hipError_t launch_pyr_chain_u8(const PyrChain &A, int njobs, hipStream_t st);
+// Detection of one uint8 frame run beside the first pyramid-chain launch (dgf_detect_pyramids):
+// tiles_x x tiles_y tiles of 16 x 16 windows; front_detect_fits tells whether a tile's pixels fit
+// the chain's LDS.
+struct FrontDetect {
+    const uint8_t *img;
+    int64_t pitch;
+    int32_t W, H, win, stride, nx, ny, tiles_x, tiles_y;
+    DetectOut o;
+};
+bool front_detect_fits(int win, int stride);
+hipError_t launch_pyr_chain_u8(const PyrChain &A, int njobs, hipStream_t st, const FrontDetect *det = nullptr);
 hipError_t launch_pyr_chains(const uint8_t *const srcs[2], const int64_t src_pitch[2],
                              uint8_t *const lvl[2][DGF_MAX_LEVELS], const int64_t *pitch, int W, int H, int levels,
-                             int njobs, hipStream_t st);
+                             int njobs, hipStream_t st, const FrontDetect *det = nullptr);
 hipError_t launch_track(const TrackParams &P, const TrackTuning &T, int dtype, hipStream_t st);
 int pick_ppl_max(int s, int lpp);
 bool run_shape_compiled(int lpp, int s);

@@ -122,14 +122,15 @@ constexpr int PC_N0 = pc_width(PC_MAXM);     // 109: staged source rectangle sid
 constexpr int PC_N1 = pc_width(PC_MAXM - 1); // 53: first produced level
 constexpr int PC_N0P = (PC_N0 + 3) & ~3;     // 112: row pitch of the staged source rectangle
 
-__global__ __launch_bounds__(256) void k_pyr_chain_u8(PyrChain A)
+// One block of a chain launch: tile (bx, by) of the coarsest level of image f, with the LDS
+// buffers the kernel provides.
+__device__ __forceinline__ void pyr_chain_block(const PyrChain &A, int bx, int by, int f,
+                                                uint8_t (*lvl)[PC_N0P * PC_N0], uint16_t *hs)
 {
-    __shared__ __align__(16) uint8_t lvl[2][PC_N0P * PC_N0];
-    __shared__ uint16_t hs[PC_N0 * PC_N1];
-    const int f = blockIdx.z, m = A.m, tid = threadIdx.x;
+    const int m = A.m, tid = threadIdx.x;
     // needed (lo, hi) at every level, coarsest first, then clamped into the level
     int x0[PC_MAXM + 1], x1[PC_MAXM + 1], y0[PC_MAXM + 1], y1[PC_MAXM + 1];
-    int lx = (int)blockIdx.x * PC_T, hx = lx + PC_T - 1, ly = (int)blockIdx.y * PC_T, hy = ly + PC_T - 1;
+    int lx = bx * PC_T, hx = lx + PC_T - 1, ly = by * PC_T, hy = ly + PC_T - 1;
 #pragma unroll
     for (int k = PC_MAXM; k >= 0; --k) {
         if (k <= m) {
@@ -167,7 +168,7 @@ __global__ __launch_bounds__(256) void k_pyr_chain_u8(PyrChain A)
         __syncthreads();
         // vertical pass, rounding, and the owned pixels to memory
         const int sh = m - (k + 1);
-        const int ox0 = ((int)blockIdx.x * PC_T) << sh, oy0 = ((int)blockIdx.y * PC_T) << sh;
+        const int ox0 = (bx * PC_T) << sh, oy0 = (by * PC_T) << sh;
         const int own = PC_T << sh;
         uint8_t *dst = A.dst[k][f];
         const int64_t dp = A.dst_pitch[k];
@@ -185,19 +186,56 @@ __global__ __launch_bounds__(256) void k_pyr_chain_u8(PyrChain A)
     }
 }
 
-hipError_t launch_pyr_chain_u8(const PyrChain &A, int njobs, hipStream_t st)
+__global__ __launch_bounds__(256) void k_pyr_chain_u8(PyrChain A)
+{
+    __shared__ __align__(16) uint8_t lvl[2][PC_N0P * PC_N0];
+    __shared__ uint16_t hs[PC_N0 * PC_N1];
+    pyr_chain_block(A, (int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z, lvl, hs);
+}
+
+// The chain launch with the detection tiles of one uint8 frame beside it: blocks 0 .. nchain - 1
+// build pyramid tiles (x fastest, then y, then image), the rest are 16 x 16-window detection
+// tiles staged in the chain's level buffer.  The two kinds of work are independent, so one
+// launch runs both in about the time of the longer.
+__global__ __launch_bounds__(256) void k_front_u8(PyrChain A, FrontDetect D, int chain_x, int chain_y, int nchain)
+{
+    __shared__ __align__(16) uint8_t lvl[2][PC_N0P * PC_N0];
+    __shared__ uint16_t hs[PC_N0 * PC_N1];
+    const int b = (int)blockIdx.x;
+    if (b < nchain) {
+        const int per = chain_x * chain_y, f = b / per, t = b - f * per, by = t / chain_x;
+        pyr_chain_block(A, t - by * chain_x, by, f, lvl, hs);
+        return;
+    }
+    const int t = b - nchain, ty = t / D.tiles_x;
+    detect_tile<16, 16>(&lvl[0][0], t - ty * D.tiles_x, ty, D.img, D.pitch, D.W, D.H, D.win, D.stride, D.nx, D.ny, 0,
+                        D.o);
+}
+
+// Largest detection tile the fused launch can stage (the chain's two level buffers).
+constexpr size_t kFrontDetectLds = 2 * (size_t)PC_N0P * PC_N0;
+
+hipError_t launch_pyr_chain_u8(const PyrChain &A, int njobs, hipStream_t st, const FrontDetect *det)
 {
     if (A.m < 1 || A.m > PC_MAXM || njobs < 1 || njobs > 2) return hipErrorInvalidValue;
     dim3 grid((A.W[A.m] + PC_T - 1) / PC_T, (A.H[A.m] + PC_T - 1) / PC_T, njobs);
-    hipLaunchKernelGGL(k_pyr_chain_u8, grid, dim3(256), 0, st, A);
+    if (!det) {
+        hipLaunchKernelGGL(k_pyr_chain_u8, grid, dim3(256), 0, st, A);
+        return hipGetLastError();
+    }
+    const int nchain = (int)(grid.x * grid.y * grid.z);
+    const int blocks = nchain + det->tiles_x * det->tiles_y;
+    hipLaunchKernelGGL(k_front_u8, dim3((unsigned)blocks), dim3(256), 0, st, A, *det, (int)grid.x, (int)grid.y, nchain);
     return hipGetLastError();
 }
+
+bool front_detect_fits(int win, int stride) { return detect_tile_lds(win, stride) <= kFrontDetectLds; }
 
 // Levels 1 .. levels-1 of one or two uint8 images (level 0 = srcs) as chains of up to four
 // levels per launch; level l of image f goes to lvl[f][l], row pitch pitch[l].
 hipError_t launch_pyr_chains(const uint8_t *const srcs[2], const int64_t src_pitch[2],
                              uint8_t *const lvl[2][DGF_MAX_LEVELS], const int64_t *pitch, int W, int H, int levels,
-                             int njobs, hipStream_t st)
+                             int njobs, hipStream_t st, const FrontDetect *det)
 {
     int Wl[DGF_MAX_LEVELS], Hl[DGF_MAX_LEVELS];
     Wl[0] = W;
@@ -219,7 +257,7 @@ hipError_t launch_pyr_chains(const uint8_t *const srcs[2], const int64_t src_pit
             A.H[k] = Hl[s + k];
             if (k > 0) A.dst_pitch[k - 1] = pitch[s + k];
         }
-        const hipError_t e = launch_pyr_chain_u8(A, njobs, st);
+        const hipError_t e = launch_pyr_chain_u8(A, njobs, st, s == 0 ? det : nullptr);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

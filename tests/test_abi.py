@@ -131,6 +131,28 @@ def test_argument_validation_before_launch():
     assert L.dgf_track_pyramids(ctypes.byref(im), ctypes.byref(im), 3, P, ws - 1, None) == -5
 
 
+def test_detect_pyramids_argument_checks_before_launch():
+    """dgf_detect_pyramids: every rejection happens on the host, before any launch."""
+    L = _lib.lib()
+    P = ctypes.c_void_p(1 << 20)
+    im = _img()
+    ws = L.dgf_track_workspace_bytes(64, 48, 3, 0)
+    n = L.dgf_detect_count(64, 48, 9, 8)
+    assert n == 35
+
+    def run(I0=im, I1=im, window=9, stride=8, levels=3, wsp=P, wsb=ws, pts=P, cap=n):
+        return L.dgf_detect_pyramids(ctypes.byref(I0), ctypes.byref(I1), window, stride, levels, wsp, wsb, pts, None,
+                                     None, cap, None)
+
+    f32 = _img(dtype=1, pitch=256)
+    assert run(I0=f32, I1=f32) == -1 and run(I1=f32) == -1 and run(I1=_img(w=63)) == -1
+    assert run(window=0) == -1 and run(window=129) == -1 and run(stride=0) == -1
+    assert run(levels=0) == -1 and run(levels=13) == -1
+    assert run(pts=None) == -1
+    assert run(cap=n - 1) == -2
+    assert run(wsp=None) == -5 and run(wsb=ws - 1) == -5
+
+
 def test_tuning_table_host_only():
     L = _lib.lib()
     t = _lib.DgfTuning()
