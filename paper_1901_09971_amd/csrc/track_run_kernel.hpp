@@ -287,7 +287,7 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
             if constexpr (IM) {
                 // phi = (g, -T', -1) per pixel: A = sum w phi phi^T (upper triangle), V = sum w r phi
                 // with the signs applied after the reduction; invalid runs have weight 0
-                float A[10], V[4];
+                float A[10], V[4], x[4]; // step = A^-1 (-sum w r phi) with phi = (g, -T', -1)
                 float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
                 if (P.mode == ROBUST_L2) {
 #pragma unroll
@@ -303,6 +303,11 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
                     group_sum5<LPP>(q0, q1, q2, q3, z0);
 #pragma unroll
                     for (int e = 0; e < 10; ++e) A[e] = M0[e];
+                    V[0] = -q0;
+                    V[1] = -q1;
+                    V[2] = q2;
+                    V[3] = q3;
+                    ldl4(A, V, x);
                 } else {
                     float s00 = 0.f, s01 = 0.f, s11 = 0.f, s02 = 0.f, s12 = 0.f, s03 = 0.f, s13 = 0.f, s22 = 0.f,
                           s23 = 0.f, s33 = 0.f;
@@ -341,7 +346,13 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
                     A[7] = s22;
                     A[8] = s23;
                     A[9] = s33;
-                    const float detw = ldl4(A, nullptr, nullptr);
+                    // the factorisation that gives det A also solves for the step; only lanes
+                    // that fall back need a second one
+                    V[0] = -q0;
+                    V[1] = -q1;
+                    V[2] = q2;
+                    V[3] = q3;
+                    const float detw = ldl4(A, V, x);
                     const bool fb = lvl_active && !(detw > 1e-6f * det0_im);
                     if (wave_any(fb)) { // too many down-weighted pixels: least-squares step
                         float u0 = 0.f, u1 = 0.f, u2 = 0.f, u3 = 0.f, z1 = 0.f;
@@ -357,20 +368,14 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
                         if (fb) {
 #pragma unroll
                             for (int e = 0; e < 10; ++e) A[e] = M0[e];
-                            q0 = u0;
-                            q1 = u1;
-                            q2 = u2;
-                            q3 = u3;
+                            V[0] = -u0;
+                            V[1] = -u1;
+                            V[2] = u2;
+                            V[3] = u3;
                         }
+                        ldl4(A, V, x);
                     }
                 }
-                // step = A^-1 (-sum w r phi) with phi = (g, -T', -1)
-                V[0] = -q0;
-                V[1] = -q1;
-                V[2] = q2;
-                V[3] = q3;
-                float x[4];
-                ldl4(A, V, x);
                 // the d rows of the model's system carry (1 + m) = ga / Ts; the unscaled system
                 // solved here gives (1 + m) d
                 const float k = ga / Ts;
