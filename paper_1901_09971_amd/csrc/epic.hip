@@ -9,7 +9,7 @@
 // GPU structure (one pass each unless noted):
 //   k_epic_prep     edge map (uint16) and cleared tables, HBM bound
 //   k_epic_seed     one 64-bit atomicMin per converged point: key = (0 << 32) | index
-//   k_epic_relax    32x32 tiles relaxed in LDS (Bellman-Ford sweeps over the tile, double
+//   k_epic_relax    32x64 tiles relaxed in LDS (Bellman-Ford sweeps over the tile, double
 //                   buffered), exchanging border pixels with their neighbours through 64-bit
 //                   atomics during the launch; launched until a launch changes nothing (host
 //                   checks a counter every few launches: the one synchronisation of the call)
@@ -32,9 +32,15 @@ constexpr int kMaxDeg = 32;          // graph neighbours a seed can hold
 constexpr int kCand = 384;           // candidates one neighbour search can hold (about 210 needed at k 128)
 constexpr int kHash = 512;           // LDS hash slots of one search (power of two, > kCand + kMaxDeg)
 constexpr int kMaxK = 256;           // largest k
-constexpr int kRT = 32;              // relaxation tile side
-constexpr int kRT2 = kRT + 2;        // with the halo
-constexpr int kRelaxThreads = 256;   // each lane owns 4 pixels of one column
+// relaxation tile: 32 x 64 crossed fewer tile borders than 32 x 32 on the benchmark frames
+// (0.755 against 0.792 ms per 1242x375 frame); 64 x 64 tiles put 16 wavefronts behind each
+// barrier and were slower (0.816 ms)
+constexpr int kRTX = 32;             // relaxation tile width
+constexpr int kRTY = 64;             // relaxation tile height
+constexpr int kRTX2 = kRTX + 2;      // with the halo
+constexpr int kRTY2 = kRTY + 2;
+constexpr int kRelaxThreads = kRTX * kRTY / 4; // each lane owns 4 pixels of one column
+static_assert(kRelaxThreads % 64 == 0 && kRelaxThreads <= 1024 && kRTY % (kRelaxThreads / kRTX) == 0, "tile shape");
 constexpr int kExchange = 32;        // relaxation iterations between two halo exchanges
 constexpr int kMaxIters = 8192;      // relaxation iterations per tile and launch
 constexpr int kMaxPolls = 4096;      // halo polls of a still tile per launch
@@ -68,7 +74,7 @@ int64_t ws_layout(int W, int H, int64_t n, EpicWs *ws, char *base)
         return base ? base + o : nullptr;
     };
     char *keys = take(8 * N), *E = take(2 * N), *adj = take(8 * n * kMaxDeg);
-    const int64_t tiles = (int64_t)((W + kRT - 1) / kRT) * ((H + kRT - 1) / kRT);
+    const int64_t tiles = (int64_t)((W + kRTX - 1) / kRTX) * ((H + kRTY - 1) / kRTY);
     char *model = take(32 * n), *ctr = take(4 * (2 * kChunk + 2)), *mail = take(4 * kChunk * tiles);
     if (ws) {
         ws->keys = (uint64_t *)keys;
@@ -142,7 +148,7 @@ __device__ __forceinline__ uint64_t step_key(uint64_t kn, uint32_t c)
     return ((uint64_t)d << 32) | (kn & 0xFFFFFFFFull);
 }
 
-// One relaxation launch over 32x32 tiles.  Each tile holds its pixels and a one-pixel halo in
+// One relaxation launch over 32x64 tiles.  Each tile holds its pixels and a one-pixel halo in
 // LDS (two buffers) and iterates key(p) = min(key(p), min over 4-neighbours q of key(q) +
 // step(q, p)) -- one barrier per iteration, each lane owning 4 pixels whose step costs stay in
 // registers.  Every kExchange iterations, and whenever it has stopped changing, a tile publishes
@@ -158,29 +164,29 @@ __global__ __launch_bounds__(kRelaxThreads) void k_epic_relax(int W, int H, int 
                                                               const uint16_t *E, uint32_t *changed, uint32_t *busy,
                                                               uint32_t *mail, int wait)
 {
-    __shared__ uint64_t K[2][kRT2 * kRT2];
-    __shared__ uint16_t Es[kRT2 * kRT2];
+    __shared__ uint64_t K[2][kRTX2 * kRTY2];
+    __shared__ uint16_t Es[kRTX2 * kRTY2];
     __shared__ uint32_t flags[2][kRelaxThreads / 64];
     __shared__ uint32_t sides, got_mail, count_zero;
-    const int x0 = (int)blockIdx.x * kRT - 1, y0 = (int)blockIdx.y * kRT - 1;
+    const int x0 = (int)blockIdx.x * kRTX - 1, y0 = (int)blockIdx.y * kRTY - 1;
     const int me = (int)(blockIdx.y * gridDim.x + blockIdx.x);
     const int nbr_tile[4] = {blockIdx.x > 0 ? me - 1 : -1, blockIdx.x + 1 < gridDim.x ? me + 1 : -1,
                              blockIdx.y > 0 ? me - (int)gridDim.x : -1,
                              blockIdx.y + 1 < gridDim.y ? me + (int)gridDim.x : -1};
-    // the halo ring: 4 kRT + 4 cells (top row, bottom row, left column, right column)
+    // the halo ring: 2 (kRTX + 2) + 2 kRTY cells (top row, bottom row, left column, right column)
     auto ring_cell = [&](int i) {
-        if (i < kRT2) return i;
-        if (i < 2 * kRT2) return (kRT + 1) * kRT2 + (i - kRT2);
-        i -= 2 * kRT2;
-        return i < kRT ? (i + 1) * kRT2 : (i - kRT + 1) * kRT2 + kRT + 1;
+        if (i < kRTX2) return i;
+        if (i < 2 * kRTX2) return (kRTY + 1) * kRTX2 + (i - kRTX2);
+        i -= 2 * kRTX2;
+        return i < kRTY ? (i + 1) * kRTX2 : (i - kRTY + 1) * kRTX2 + kRTX + 1;
     };
     auto global_of = [&](int c, uint32_t &q) {
-        const int ly = c / kRT2, lx = c - ly * kRT2;
+        const int ly = c / kRTX2, lx = c - ly * kRTX2;
         const int gx = x0 + lx, gy = y0 + ly;
         q = (uint32_t)gy * (uint32_t)W + (uint32_t)gx;
         return gx >= 0 && gy >= 0 && gx < W && gy < H;
     };
-    for (int c = threadIdx.x; c < kRT2 * kRT2; c += kRelaxThreads) {
+    for (int c = threadIdx.x; c < kRTX2 * kRTY2; c += kRelaxThreads) {
         uint32_t q;
         uint64_t k = kNoKey;
         uint16_t e = 0;
@@ -194,8 +200,9 @@ __global__ __launch_bounds__(kRelaxThreads) void k_epic_relax(int W, int H, int 
     }
     if (threadIdx.x == 0) sides = 0u;
     __syncthreads();
-    const int tx = threadIdx.x % kRT, ty = threadIdx.x / kRT;
-    constexpr int kPix = kRT * kRT / kRelaxThreads;
+    const int tx = threadIdx.x % kRTX, ty = threadIdx.x / kRTX;
+    constexpr int kPix = kRTX * kRTY / kRelaxThreads;
+    constexpr int kRowStep = kRelaxThreads / kRTX; // rows between a lane's pixels
     int cell[kPix];
     bool inside[kPix];
     uint64_t own[kPix], orig[kPix], pub[kPix];
@@ -203,21 +210,21 @@ __global__ __launch_bounds__(kRelaxThreads) void k_epic_relax(int W, int H, int 
     uint32_t side_of[kPix]; // which neighbour tiles' halos this pixel belongs to (bit per side)
 #pragma unroll
     for (int j = 0; j < kPix; ++j) {
-        const int lx = tx + 1, ly = ty + (kRelaxThreads / kRT) * j + 1;
-        const int c = ly * kRT2 + lx;
+        const int lx = tx + 1, ly = ty + kRowStep * j + 1;
+        const int c = ly * kRTX2 + lx;
         cell[j] = c;
         inside[j] = x0 + lx < W && y0 + ly < H;
         own[j] = orig[j] = pub[j] = K[0][c];
         const uint32_t e = (uint32_t)kappa + Es[c];
         cst[j][0] = e + Es[c - 1];
         cst[j][1] = e + Es[c + 1];
-        cst[j][2] = e + Es[c - kRT2];
-        cst[j][3] = e + Es[c + kRT2];
-        side_of[j] = (lx == 1 ? 1u : 0u) | (lx == kRT ? 2u : 0u) | (ly == 1 ? 4u : 0u) | (ly == kRT ? 8u : 0u);
+        cst[j][2] = e + Es[c - kRTX2];
+        cst[j][3] = e + Es[c + kRTX2];
+        side_of[j] = (lx == 1 ? 1u : 0u) | (lx == kRTX ? 2u : 0u) | (ly == 1 ? 4u : 0u) | (ly == kRTY ? 8u : 0u);
     }
     // re-read the halo ring into both buffers
     auto reload_halo = [&](int cur) {
-        for (int i = threadIdx.x; i < 4 * kRT + 4; i += kRelaxThreads) {
+        for (int i = threadIdx.x; i < 2 * kRTX2 + 2 * kRTY; i += kRelaxThreads) {
             const int c = ring_cell(i);
             uint32_t q;
             if (!global_of(c, q)) continue;
@@ -235,7 +242,7 @@ __global__ __launch_bounds__(kRelaxThreads) void k_epic_relax(int W, int H, int 
 #pragma unroll
         for (int j = 0; j < kPix; ++j) {
             if (inside[j] && side_of[j] && own[j] < pub[j]) {
-                const int ly = ty + (kRelaxThreads / kRT) * j + 1;
+                const int ly = ty + kRowStep * j + 1;
                 const uint32_t q = (uint32_t)(y0 + ly) * (uint32_t)W + (uint32_t)(x0 + tx + 1);
                 atomicMin((unsigned long long *)(keys + q), (unsigned long long)own[j]);
                 pub[j] = own[j];
@@ -275,8 +282,8 @@ __global__ __launch_bounds__(kRelaxThreads) void k_epic_relax(int W, int H, int 
             const int c = cell[j];
             nk[j][0] = Kc[c - 1];
             nk[j][1] = Kc[c + 1];
-            nk[j][2] = Kc[c - kRT2];
-            nk[j][3] = Kc[c + kRT2];
+            nk[j][2] = Kc[c - kRTX2];
+            nk[j][3] = Kc[c + kRTX2];
         }
         bool ch = false;
 #pragma unroll
@@ -334,7 +341,7 @@ __global__ __launch_bounds__(kRelaxThreads) void k_epic_relax(int W, int H, int 
 #pragma unroll
     for (int j = 0; j < kPix; ++j) {
         if (inside[j] && own[j] < orig[j]) {
-            const int ly = ty + (kRelaxThreads / kRT) * j + 1;
+            const int ly = ty + kRowStep * j + 1;
             const uint32_t q = (uint32_t)(y0 + ly) * (uint32_t)W + (uint32_t)(x0 + tx + 1);
             atomicMin((unsigned long long *)(keys + q), (unsigned long long)own[j]);
             wrote = true;
@@ -828,7 +835,7 @@ int dgf_epic(const dgf_image *I0, const float *points, const float *flow, const 
         hipLaunchKernelGGL(k_epic_seed, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, points, flow, status, n, W,
                            H, ws.keys);
         if (hipGetLastError() != hipSuccess) return DGF_ERR_HIP;
-        const dim3 tiles((unsigned)((W + kRT - 1) / kRT), (unsigned)((H + kRT - 1) / kRT));
+        const dim3 tiles((unsigned)((W + kRTX - 1) / kRTX), (unsigned)((H + kRTY - 1) / kRTY));
         const int64_t ntiles = (int64_t)tiles.x * tiles.y;
         // tiles may wait for each other only if the whole grid is resident at once
         int dev = 0, cus = 0, per_cu = 0;
