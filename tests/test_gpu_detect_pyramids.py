@@ -3,6 +3,7 @@ calls, dgf_detect and dgf_track_pyramids, through the C ABI: points, selections 
 bit-identical, every pyramid level of both frames byte-identical, for ragged grids, window sizes
 up to the largest the fused launch stages, one and two chain launches, and the fallbacks (one
 level, no points, a detection tile too large to fuse)."""
+import numpy as np
 import pytest
 import torch
 
@@ -61,3 +62,33 @@ def test_fallbacks():
     _both(I0, I1, 9, 5, 1)        # one level: detection alone
     _both(I0, I1, 128, 60, 4)     # tile of 1028 x 1028 bytes: two launches
     _both(I0[:8, :8].copy(), I1[:8, :8].copy(), 9, 1, 3)  # no points: pyramids alone
+
+
+def test_odd_pitch_misaligned_frames_through_tracking():
+    # frames as views with an odd row pitch (1249 bytes) and bases 3 and 6 bytes into their
+    # buffers, so every image row starts at a different dword alignment; detection beside the
+    # pyramids and tracking on them must equal the same frames stored contiguously, bit for bit
+    I0, I1, _, _ = synth.driving_1242x375()
+    H, W = I0.shape
+    big0 = np.zeros((H, W + 7), np.uint8)
+    big1 = np.zeros((H, W + 7), np.uint8)
+    big0[:, 3:3 + W] = I0
+    big1[:, 6:6 + W] = I1
+    v0, v1 = torch.from_numpy(big0).cuda()[:, 3:3 + W], torch.from_numpy(big1).cuda()[:, 6:6 + W]
+    c0, c1 = torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda()
+    assert v0.stride(0) == W + 7 and v0.data_ptr() % 4 == 3
+    n = dgf.detect_count(W, H, 9, 5)
+    out = []
+    for a, b in ((c0, c1), (v0, v1)):
+        ws = torch.empty(dgf.track_workspace_bytes(W, H, 5, 0), dtype=torch.uint8, device="cuda")
+        P = torch.empty((n, 2), dtype=torch.float32, device="cuda")
+        F = torch.empty((n, 2), dtype=torch.float32, device="cuda")
+        S = torch.empty(n, dtype=torch.uint8, device="cuda")
+        dgf.detect_pyramids(a, b, 9, 5, 5, ws, P)
+        dgf.track_run(a, b, P, 5, 21, 20, ws, F, S)
+        torch.cuda.synchronize()
+        out.append((P, F, S))
+    (P1, F1, S1), (P2, F2, S2) = out
+    assert torch.equal(P1.view(torch.int32), P2.view(torch.int32))
+    assert torch.equal(F1.view(torch.int32), F2.view(torch.int32))
+    assert torch.equal(S1, S2)
