@@ -478,8 +478,9 @@ __device__ __forceinline__ int hash_slot(int32_t t) { return (int)(((uint32_t)t 
 // edge length D of the graph): with dmin the least tentative distance of the frontier, every
 // frontier node below dmin + D is final, since any other path to it leaves the settled set
 // through a frontier node and adds at least D.  After each batch the settled set is exactly the
-// nodes below dmin + D, so once it holds k nodes its k smallest are the answer.  Candidates and a
-// hash index from node to candidate slot live in LDS.
+// nodes below dmin + D, so once it holds k nodes its k smallest are the answer.  Candidates, a
+// hash index from node to candidate slot and the settled candidates' slots (16-bit) live in LDS:
+// 9.3 KB per search, so 17 searches share a CU.
 __global__ __launch_bounds__(64) void k_epic_knn_fit(EpicFit F)
 {
     static_assert(kHash == 1 << 9, "hash_slot returns 9 bits");
@@ -490,8 +491,7 @@ __global__ __launch_bounds__(64) void k_epic_knn_fit(EpicFit F)
     __shared__ int32_t cid[kCand];
     __shared__ uint32_t cdist[kCand];
     __shared__ uint8_t cdone[kCand];
-    __shared__ int32_t sid[kCand]; // settled, in settling order
-    __shared__ uint32_t sdist[kCand];
+    __shared__ int16_t sslot[kCand]; // candidate slots of the settled nodes, in settling order
     __shared__ int32_t it_t[kStageNodes * kMaxDeg];
     __shared__ uint32_t it_c[kStageNodes * kMaxDeg];
     int32_t *oid = it_t; // the k nearest, sorted (after the search, over the staging arrays)
@@ -532,9 +532,7 @@ __global__ __launch_bounds__(64) void k_epic_knn_fit(EpicFit F)
                 const bool sel = j < m && !cdone[j] && (uint64_t)cdist[j] < T;
                 const uint64_t bm = __ballot(sel);
                 if (sel) {
-                    const int r = cnt + __popcll(bm & below);
-                    sid[r] = cid[j];
-                    sdist[r] = cdist[j];
+                    sslot[cnt + __popcll(bm & below)] = (int16_t)j;
                     cdone[j] = 1;
                 }
                 cnt += __popcll(bm);
@@ -552,8 +550,9 @@ __global__ __launch_bounds__(64) void k_epic_knn_fit(EpicFit F)
                     e[r] = kNoKey;
                     dv[r] = 0u;
                     if (node < nn) {
-                        e[r] = F.ws.adj[(int64_t)sid[nb0 + node] * kMaxDeg + slot];
-                        dv[r] = sdist[nb0 + node];
+                        const int cs = sslot[nb0 + node];
+                        e[r] = F.ws.adj[(int64_t)cid[cs] * kMaxDeg + slot];
+                        dv[r] = cdist[cs];
                     }
                 }
                 int ni = 0;
@@ -620,12 +619,16 @@ __global__ __launch_bounds__(64) void k_epic_knn_fit(EpicFit F)
         if (!overflow) {
             // the k smallest settled (distance, index) pairs, by rank
             for (int j = li; j < cnt; j += 64) {
-                const uint64_t kj = ((uint64_t)sdist[j] << 32) | (uint32_t)sid[j];
+                const int cj = sslot[j];
+                const uint64_t kj = ((uint64_t)cdist[cj] << 32) | (uint32_t)cid[cj];
                 int rank = 0;
-                for (int i = 0; i < cnt; ++i) rank += (((uint64_t)sdist[i] << 32) | (uint32_t)sid[i]) < kj;
+                for (int i = 0; i < cnt; ++i) {
+                    const int ci = sslot[i];
+                    rank += (((uint64_t)cdist[ci] << 32) | (uint32_t)cid[ci]) < kj;
+                }
                 if (rank < F.k) {
-                    oid[rank] = sid[j];
-                    od[rank] = sdist[j];
+                    oid[rank] = cid[cj];
+                    od[rank] = cdist[cj];
                 }
             }
             cnt = cnt < F.k ? cnt : F.k;
