@@ -1,0 +1,143 @@
+"""Randomised sweep of the batched form and of the adjoint through the C ABI (fixed seeds).
+  * batched: 60 plans of 1 to 8 pairs of random size (8 x 8 up to 400 x 300), window, stride,
+    levels, support, iteration limit, robust mode and illumination model: points, statuses and
+    finite flows bit-identical to per-pair detect + track calls, and a graph replay reproduces
+    the eager run;
+  * adjoint: 60 float32 pairs, random everything as above, random upstream gradient on the
+    converged points, against the oracle's implicit gradient at the GPU's fixed point.  A point
+    with a support residual within 1e-3 of a threshold (sigma1 or sigma2) takes psi' from either
+    band (the derivative does not exist there; flat regions of integer frames put residuals exactly
+    on it) and is left out on both sides.  Bar: relative L2 error <= 1e-4 on dI0 and dI1, and
+    <= 1e-3 with the illumination model, whose 4 x 4 system on small supports carries more FP32
+    rounding (a 3,300-trial run of the same generator: none above 1e-4 without it, the worst
+    7.8e-4 with it)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1901_09971_amd as dgf
+from paper_1901_09971_amd import synth
+
+pytestmark = pytest.mark.gpu
+RUN = [5, 7, 9, 11, 15, 21]
+GEN = [3, 13, 17, 19, 23, 25, 27, 29, 31]
+MODES = [dict(sigma1=8.0, sigma2=32.0), dict(sigma1=float("inf"), sigma2=float("inf")),
+         dict(sigma1=12.0, sigma2=12.0)]
+
+
+def _config(rng):
+    levels, iters = int(rng.integers(1, 7)), int(rng.integers(1, 21))
+    illum = bool(rng.random() < 0.25)
+    mode = int(rng.integers(3))
+    s = int(rng.choice(RUN)) if illum or rng.random() < 0.6 else int(rng.choice(GEN))
+    return levels, iters, illum, mode, s
+
+
+def test_batched_random_plans():
+    rng = np.random.default_rng(9)
+    for t in range(60):
+        levels, iters, illum, mode, s = _config(rng)
+        opts = dgf.TrackOpts(illum=illum, **MODES[mode])
+        pairs = []
+        for _ in range(int(rng.integers(1, 9))):
+            W, H = int(rng.integers(8, 400)), int(rng.integers(8, 300))
+            I0, I1, _, _ = synth.layered_pair(max(W, 16), max(H, 16), seed=int(rng.integers(1 << 30)),
+                                              max_disp=float(rng.uniform(0, 20)))
+            I0, I1 = np.ascontiguousarray(I0[:H, :W]), np.ascontiguousarray(I1[:H, :W])
+            win, d = int(rng.integers(1, min(W, H, 15) + 1)), int(rng.integers(2, 11))
+            pairs.append((torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda(), win, d))
+        tag = f"#{t} pairs={len(pairs)} L{levels} s{s} it{iters} mode{mode}{' IM' if illum else ''}"
+        print(tag, flush=True)
+        plan = dgf.Batch(pairs, levels, s, iters, opts=opts)
+        P, F, S = [x.clone() for x in plan.run()]
+        pp, ff, ss = [], [], []
+        for a, b, w, d in pairs:
+            p = dgf.detect(a, w, d)
+            f, st = dgf.track(a, b, p, levels, s, iters, opts=opts)
+            pp.append(p)
+            ff.append(f)
+            ss.append(st)
+        p, f, st = torch.cat(pp), torch.cat(ff), torch.cat(ss)
+        torch.cuda.synchronize()
+        fin = torch.isfinite(f)
+        assert torch.equal(P, p) and torch.equal(S, st), tag
+        assert torch.equal(torch.isfinite(F), fin) and torch.equal(F[fin], f[fin]), tag
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            plan.capture()
+            plan.status.fill_(255)
+            plan.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(plan.status, S) and torch.equal(plan.points, P), tag
+        plan.close()
+
+
+def _bilinear(I, x, y):
+    x0, y0 = np.floor(x).astype(int), np.floor(y).astype(int)
+    fx, fy = x - x0, y - y0
+    H, W = I.shape
+    at = lambda yy, xx: I[np.clip(yy, 0, H - 1), np.clip(xx, 0, W - 1)]
+    return ((1 - fy) * ((1 - fx) * at(y0, x0) + fx * at(y0, x0 + 1))
+            + fy * ((1 - fx) * at(y0 + 1, x0) + fx * at(y0 + 1, x0 + 1)))
+
+
+def _rel(a, b):
+    n = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / n) if n > 0 else float(np.linalg.norm(a))
+
+
+def test_adjoint_random_pairs():
+    rng = np.random.default_rng(11)
+    done = 0
+    for t in range(200):
+        if done == 60:
+            break
+        levels, iters, illum, mode, s = _config(rng)
+        W, H = int(rng.integers(40, 300)), int(rng.integers(40, 220))
+        I0u, I1u, _, _ = synth.layered_pair(W, H, seed=int(rng.integers(1 << 30)), max_disp=float(rng.uniform(0, 12)))
+        win, d = int(rng.integers(3, 16)), int(rng.integers(3, 12))
+        pts = oracle.detect(I0u, win, d)[0].astype(np.float32)
+        if len(pts) == 0:
+            continue
+        done += 1
+        opts = dgf.TrackOpts(illum=illum, **MODES[mode])
+        I0, I1 = I0u.astype(np.float32), I1u.astype(np.float32)
+        t0, t1, P = torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda(), torch.from_numpy(pts).cuda()
+        if illum:
+            flow, st, mc = dgf.track(t0, t1, P, levels, s, iters, opts=opts, return_illum=True)
+        else:
+            flow, st = dgf.track(t0, t1, P, levels, s, iters, opts=opts)
+            mc = None
+        torch.cuda.synchronize()
+        Fn, Sn = flow.cpu().numpy().astype(np.float64), st.cpu().numpy()
+        tie = np.zeros(len(pts), bool)
+        if mode != 1:
+            r = s // 2
+            ky, kx = np.mgrid[-r:r + 1, -r:r + 1]
+            mcn = mc.cpu().numpy().astype(np.float64) if illum else None
+            for i in np.where(Sn == 0)[0]:
+                px, py = pts[i].astype(np.float64)
+                T = _bilinear(I0.astype(np.float64), px + kx, py + ky)
+                J = _bilinear(I1.astype(np.float64), px + Fn[i, 0] + kx, py + Fn[i, 1] + ky)
+                res = np.abs(J - (1 + mcn[i, 0]) * T - mcn[i, 1]) if illum else np.abs(J - T)
+                tie[i] = any(np.any(np.abs(res - th) < 1e-3) for th in (opts.sigma1, opts.sigma2))
+        keep = (Sn == 0) & ~tie
+        g = torch.Generator(device="cpu").manual_seed(t)
+        dflow = torch.randn(flow.shape, generator=g).cuda() * torch.from_numpy(keep).cuda()[:, None]
+        dI0, dI1 = torch.zeros_like(t0), torch.zeros_like(t1)
+        dgf.track_backward(t0, t1, P, s, flow, st, dflow, dI0, dI1, opts=opts, illum=mc)
+        torch.cuda.synchronize()
+        f64 = lambda x: x.cpu().numpy().astype(np.float64)
+        args = (I0.astype(np.float64), I1.astype(np.float64), pts.astype(np.float64), s)
+        if illum:
+            o0, o1 = oracle.track_grad_illum(*args, Fn, f64(mc), Sn, f64(dflow), sigma1=opts.sigma1,
+                                             sigma2=opts.sigma2)
+        else:
+            o0, o1 = oracle.track_grad(*args, Fn, Sn, f64(dflow), sigma1=opts.sigma1, sigma2=opts.sigma2)
+        e0, e1 = _rel(f64(dI0), o0), _rel(f64(dI1), o1)
+        bar = 1e-3 if illum else 1e-4
+        print(f"#{t} {W}x{H} L{levels} s{s} it{iters} mode{mode}{' IM' if illum else ''} "
+              f"kept={int(keep.sum())} ties={int(tie.sum())} rel={e0:.1e}/{e1:.1e}", flush=True)
+        assert e0 <= bar and e1 <= bar, (t, e0, e1)
+    assert done == 60
