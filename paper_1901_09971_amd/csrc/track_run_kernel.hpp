@@ -48,12 +48,10 @@ __device__ __forceinline__ void group_sum5(float &a, float &b, float &c, float &
     }
 }
 
-// The 64-lane forms are held to six waves per SIMD without the illumination model (80 VGPRs, two
-// values spilled outside the pixel loops) and five with it (96 VGPRs, from 119 and four waves):
-// they are issue bound, and the extra wave pays (330 vs 333 us and 679 vs 686 us on the
-// benchmark pair, results unchanged).
+// The 64-lane form without the illumination model is held to 80 VGPRs (six waves per SIMD, two
+// values spilled outside the pixel loops): it is issue bound, and the sixth wave pays.
 template <int LPP, int SEG, int R, int TP, typename PixT, bool IM>
-__global__ __launch_bounds__(256, LPP == 64 ? (IM ? 5 : 6) : 1) void k_track_run(TrackParams P)
+__global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(TrackParams P)
 {
     constexpr int PPW = 64 / LPP;
     constexpr int PPL = SEG * R;
