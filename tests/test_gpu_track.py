@@ -95,6 +95,9 @@ def test_least_squares_limit_and_many_levels():
     pts = oracle.detect(I0, 9, 8)[0].astype(np.float32)
     _run(I0, I1, pts, 3, 9, 20, 0.99, sigma1=INF, sigma2=INF, min_eig=0.0)
     _run(I0, I1, pts, 8, 9, 20, 0.98)  # coarse levels down to 2 x 1 pixels
+    # the largest level count: levels 8 .. 11 are 1 x 1 (flat, so they pass the guess on) and the
+    # pyramids take three chain launches
+    _run(I0, I1, pts, 12, 9, 20, 0.98)
 
 
 def test_edge_points_and_empty():
