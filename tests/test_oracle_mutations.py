@@ -1,0 +1,90 @@
+"""The oracle's pins must catch plausible mistakes in the oracle itself.
+
+Each case plants one mistake in a private copy of the oracle's C source (a flipped sign, a wrong
+or transposed operand, a dropped term or factor, a changed comparison or filter tap), rebuilds
+that copy with gcc and runs the oracle pin tests against it: at least one pin must fail.  The
+working tree is never touched; every copy lives in a temporary directory."""
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PIN_FILES = ["tests/test_oracle_degraf.py", "tests/test_oracle_pyramid.py", "tests/test_oracle_rlof.py",
+             "tests/test_oracle_illum.py", "tests/test_oracle_grad.py", "tests/test_oracle_detect_grad.py"]
+
+# (name, original text, planted text): the first occurrence in degraf_oracle.c is replaced
+MUTATIONS = [
+    ("selection tie goes to the negative centroid (Eq. 2 rule)",
+     "int neg = s_neg > s_pos;", "int neg = s_neg >= s_pos;"),
+    ("row moment takes the column index (Eq. 1)",
+     "i_pos += (int64_t)i * v;", "i_pos += (int64_t)j * v;"),
+    ("pyramid taps 1 5 4 5 1 (same sum)",
+     "static const int k5[5] = {1, 4, 6, 4, 1};", "static const int k5[5] = {1, 5, 4, 5, 1};"),
+    ("bilinear interpolation with the two off-diagonal taps swapped",
+     "(1.0 - fy) * ((1.0 - fx) * i00 + fx * i10) + fy * ((1.0 - fx) * i01 + fx * i11)",
+     "(1.0 - fy) * ((1.0 - fx) * i00 + fx * i01) + fy * ((1.0 - fx) * i10 + fx * i11)"),
+    ("psi without its sigma1 factor in the middle band",
+     "return copysign(s1 * (s2 - a) / (s2 - s1), r);", "return copysign((s2 - a) / (s2 - s1), r);"),
+    ("off-diagonal of the structure tensor with the wrong sign",
+     "b += gxk[k] * gyk[k];", "b -= gxk[k] * gyk[k];"),
+    ("vertical template gradient taken along x",
+     "gyk[k] = 0.5 * (or_bilinear(I0l, Wl, Hl, x, y + 1.0) - or_bilinear(I0l, Wl, Hl, x, y - 1.0));",
+     "gyk[k] = 0.5 * (or_bilinear(I0l, Wl, Hl, x + 1.0, y) - or_bilinear(I0l, Wl, Hl, x - 1.0, y));"),
+    ("2x2 solve with the right-hand side transposed",
+     "double stepX = (C * bx - B * by) / det;", "double stepX = (C * by - B * bx) / det;"),
+    ("no least-squares fallback when the weighted system is near singular",
+     "if (!(det > 1e-6 * det0)) {", "if (0) {"),
+    ("guess not doubled from one level to the next",
+     "gX = 2.0 * (gX + dX);", "gX = (gX + dX);"),
+    ("illumination offset entering the residual with the wrong sign",
+     "double res = J - (1.0 + m) * T[k] - c;", "double res = J - (1.0 + m) * T[k] + c;"),
+    ("adjoint without the template-gradient term of dI0",
+     "dI0[ixp[t]] += cx * wxp[t];", "(void)cx;"),
+]
+
+
+def _copy_tree(dst):
+    ign = shutil.ignore_patterns("__pycache__", "*.so", "*.o", "_build", "*.tmp", "csrc")
+    for d in ("oracle", "tests", "paper_1901_09971_amd"):
+        shutil.copytree(os.path.join(ROOT, d), os.path.join(dst, d), ignore=ign)
+
+
+def _run_mutant(tmp, old, new):
+    src_path = os.path.join(tmp, "oracle", "degraf_oracle.c")
+    if old is not None:
+        src = open(src_path).read()
+        assert src.count(old) >= 1, f"mutation target not found: {old}"
+        open(src_path, "w").write(src.replace(old, new, 1))
+    env = dict(os.environ, OMP_NUM_THREADS="2", PYTHONDONTWRITEBYTECODE="1")
+    p = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *PIN_FILES],
+                       cwd=tmp, env=env, capture_output=True, text=True, timeout=900)
+    return p.returncode, (p.stdout + p.stderr).strip().splitlines()
+
+
+def test_every_planted_mistake_fails_a_pin(tmp_path):
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    dirs = []
+    for i in range(len(MUTATIONS) + 1):
+        d = str(tmp_path / f"m{i}")
+        _copy_tree(d)
+        dirs.append(d)
+    with cf.ThreadPoolExecutor(max_workers=4) as ex:
+        # the unchanged copy is the control: its pins must all pass
+        control = ex.submit(_run_mutant, dirs[-1], None, None)
+        futs = [ex.submit(_run_mutant, d, old, new) for d, (_, old, new) in zip(dirs, MUTATIONS)]
+        results = [f.result() for f in futs]
+        rc0, lines0 = control.result()
+    assert rc0 == 0, lines0[-5:]
+    survivors = []
+    for (name, _, _), (rc, lines) in zip(MUTATIONS, results):
+        last = lines[-1] if lines else ""
+        print(f"{name}: rc={rc} {last}", flush=True)
+        # a pin must fail (not a build or collection error)
+        if not (rc == 1 and " failed" in last and "error" not in last):
+            survivors.append((name, rc, last))
+    assert not survivors, survivors
