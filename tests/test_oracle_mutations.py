@@ -1,6 +1,6 @@
 """The oracle's pins must catch plausible mistakes in the oracle itself.
 
-Each case plants one mistake in a private copy of the oracle's C source (a flipped sign, a wrong
+Each case plants one mistake in a private copy of one of the oracle's C sources (a flipped sign, a wrong
 or transposed operand, a dropped term or factor, a changed comparison or filter tap), rebuilds
 that copy with gcc and runs the oracle pin tests against it: at least one pin must fail.  The
 working tree is never touched; every copy lives in a temporary directory."""
@@ -46,6 +46,21 @@ MUTATIONS = [
      "dI0[ixp[t]] += cx * wxp[t];", "(void)cx;"),
 ]
 
+# the same for the dense interpolation's oracle, checked by its own pins
+EPIC_PIN_FILES = ["tests/test_oracle_epic.py"]
+EPIC_MUTATIONS = [
+    ("edge map without its vertical term",
+     "E[(int64_t)y * W + x] = abs(gx) + abs(gy);", "E[(int64_t)y * W + x] = abs(gx);"),
+    ("geodesic step cost without the edge value of the pixel entered",
+     "const int64_t c = it.k0 + kappa + E[p] + E[q];", "const int64_t c = it.k0 + kappa + E[p];"),
+    ("equal distances go to the higher seed index",
+     "(c == D[q] && it.k1 < L[q])", "(c == D[q] && it.k1 > L[q])"),
+    ("seed-graph edge length without the far side's distance",
+     "const int64_t w = D[p] + kappa + E[p] + E[q] + D[q];", "const int64_t w = D[p] + kappa + E[p] + E[q];"),
+    ("affine fit rows scaled by the weight instead of its square root",
+     "const double r = sqrt(exp2(-(double)nd[j] / (double)h));", "const double r = exp2(-(double)nd[j] / (double)h);"),
+]
+
 
 def _copy_tree(dst):
     ign = shutil.ignore_patterns("__pycache__", "*.so", "*.o", "_build", "*.tmp", "csrc")
@@ -53,14 +68,14 @@ def _copy_tree(dst):
         shutil.copytree(os.path.join(ROOT, d), os.path.join(dst, d), ignore=ign)
 
 
-def _run_mutant(tmp, old, new):
-    src_path = os.path.join(tmp, "oracle", "degraf_oracle.c")
+def _run_mutant(tmp, old, new, source="degraf_oracle.c", pins=PIN_FILES):
+    src_path = os.path.join(tmp, "oracle", source)
     if old is not None:
         src = open(src_path).read()
         assert src.count(old) >= 1, f"mutation target not found: {old}"
         open(src_path, "w").write(src.replace(old, new, 1))
     env = dict(os.environ, OMP_NUM_THREADS="2", PYTHONDONTWRITEBYTECODE="1")
-    p = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *PIN_FILES],
+    p = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *pins],
                        cwd=tmp, env=env, capture_output=True, text=True, timeout=900)
     return p.returncode, (p.stdout + p.stderr).strip().splitlines()
 
@@ -68,20 +83,23 @@ def _run_mutant(tmp, old, new):
 def test_every_planted_mistake_fails_a_pin(tmp_path):
     if shutil.which("gcc") is None:
         pytest.skip("gcc not available")
+    cases = [(m, "degraf_oracle.c", PIN_FILES) for m in MUTATIONS]
+    cases += [(m, "epic_oracle.c", EPIC_PIN_FILES) for m in EPIC_MUTATIONS]
     dirs = []
-    for i in range(len(MUTATIONS) + 1):
+    for i in range(len(cases) + 1):
         d = str(tmp_path / f"m{i}")
         _copy_tree(d)
         dirs.append(d)
     with cf.ThreadPoolExecutor(max_workers=4) as ex:
-        # the unchanged copy is the control: its pins must all pass
-        control = ex.submit(_run_mutant, dirs[-1], None, None)
-        futs = [ex.submit(_run_mutant, d, old, new) for d, (_, old, new) in zip(dirs, MUTATIONS)]
+        # the unchanged copy is the control: all its pins must pass
+        control = ex.submit(_run_mutant, dirs[-1], None, None, "degraf_oracle.c", PIN_FILES + EPIC_PIN_FILES)
+        futs = [ex.submit(_run_mutant, d, old, new, src, pins)
+                for d, ((_, old, new), src, pins) in zip(dirs, cases)]
         results = [f.result() for f in futs]
         rc0, lines0 = control.result()
     assert rc0 == 0, lines0[-5:]
     survivors = []
-    for (name, _, _), (rc, lines) in zip(MUTATIONS, results):
+    for ((name, _, _), _, _), (rc, lines) in zip(cases, results):
         last = lines[-1] if lines else ""
         print(f"{name}: rc={rc} {last}", flush=True)
         # a pin must fail (not a build or collection error)
