@@ -298,15 +298,18 @@ typedef struct {
 int dgf_get_tuning(int32_t support, int32_t levels, int32_t dtype, int64_t n, dgf_tuning *out);
 
 /* Installs a shape for (support, dtype) for the rest of the process.  Host only;
- * DGF_ERR_UNSUPPORTED if no kernel is compiled for it. */
+ * DGF_ERR_UNSUPPORTED if no kernel is compiled for it.  One shape serves both the plain tracker
+ * and the illumination model (DGF_TRACK_ILLUM) of that support and element type. */
 int dgf_set_tuning(int32_t support, int32_t dtype, const dgf_tuning *t);
 
 /* Times every compiled launch shape on these inputs (dgf_track arguments; the pyramids are built
  * into `workspace`, flow / status receive a valid result), installs the fastest for (support,
  * dtype) and returns it in *out (nullable).  This is a setup call: it synchronises `stream`
  * once per candidate.  cache_path (nullable) names a JSON file keyed by GPU architecture,
- * support, levels, element type and the point count rounded up to a power of two: a hit installs
- * the cached shape without timing anything; a miss appends the result. */
+ * support, levels, element type, the point count rounded up to a power of two and whether
+ * DGF_TRACK_ILLUM is set: a hit installs the cached shape without timing anything; a miss appends
+ * the result.  The installed shape serves both models (see dgf_set_tuning), so tuning with
+ * DGF_TRACK_ILLUM also sets the plain tracker's shape for this support and element type. */
 int dgf_autotune(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
                  int32_t support, int32_t iters, const dgf_track_opts *opts, void *workspace, size_t ws_bytes,
                  float *flow, uint8_t *status, const char *cache_path, dgf_tuning *out, void *stream);

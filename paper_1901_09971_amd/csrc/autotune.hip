@@ -21,7 +21,7 @@ using namespace dgf;
 
 namespace {
 
-std::string cache_key(int support, int levels, int dtype, int64_t n)
+std::string cache_key(int support, int levels, int dtype, int64_t n, bool illum)
 {
     hipDeviceProp_t prop{};
     int dev = 0;
@@ -34,8 +34,8 @@ std::string cache_key(int support, int levels, int dtype, int64_t n)
     int64_t bucket = 1;
     while (bucket < n) bucket <<= 1;
     char buf[160];
-    snprintf(buf, sizeof buf, "%s:s%d:L%d:%s:n%lld", arch.c_str(), support, levels, dtype == DGF_U8 ? "u8" : "f32",
-             (long long)bucket);
+    snprintf(buf, sizeof buf, "%s:s%d:L%d:%s:n%lld%s", arch.c_str(), support, levels, dtype == DGF_U8 ? "u8" : "f32",
+             (long long)bucket, illum ? ":illum" : "");
     return buf;
 }
 
@@ -115,7 +115,8 @@ int dgf_autotune(const dgf_image *I0, const dgf_image *I1, const float *points, 
     int rc = validate_track(I0, I1, points, n, levels, support, iters, opts, workspace, ws_bytes, flow, status, &o);
     if (rc != DGF_OK) return rc;
     if (n < 1) return DGF_ERR_INVALID_ARG;
-    const std::string key = cache_key(support, levels, I0->dtype, n);
+    // the illumination model's timings are cached under their own key
+    const std::string key = cache_key(support, levels, I0->dtype, n, (o.flags & DGF_TRACK_ILLUM) != 0);
     std::map<std::string, dgf_tuning> cache;
     if (cache_path) {
         cache = read_cache(cache_path);

@@ -40,3 +40,19 @@ def test_autotune_installs_and_caches(tmp_path):
     assert np.mean(g_st == ost) > 0.97
     assert np.abs(flow.cpu().numpy()[both] - of[both]).max() <= 1e-3
     dgf.set_tuning(21, 0, before["lanes_per_point"], before["waves_per_group"], before["margin"], before["kernel"])
+
+
+def test_illumination_model_cached_under_its_own_key(tmp_path):
+    before = dgf.get_tuning(21, 4, 0, 0)
+    I0, I1, _, _ = synth.layered_pair(320, 200, seed=9, max_disp=20.0)
+    t0, t1 = torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda()
+    pts = dgf.detect(t0, 9, 8)
+    cache = str(tmp_path / "tune.json")
+    dgf.autotune(t0, t1, pts, 3, 21, 10, cache_path=cache)
+    # the same request with the illumination model is a miss, timed and stored beside the first
+    im = dgf.autotune(t0, t1, pts, 3, 21, 10, opts=dgf.TrackOpts(illum=True), cache_path=cache)
+    assert im["lanes_per_point"] in (16, 32, 64) and im["ms"] > 0
+    with open(cache) as f:
+        keys = sorted(json.load(f))
+    assert len(keys) == 2 and keys[1] == keys[0] + ":illum", keys
+    dgf.set_tuning(21, 0, before["lanes_per_point"], before["waves_per_group"], before["margin"], before["kernel"])
