@@ -290,7 +290,10 @@ int or_pyr_down_f64(const double *src, int W, int H, double *dst)
 /* ------------------------------------------------------------------------------------------ */
 
 /* Bilinear interpolation with each of the four taps clamped to the image (replicated border).
- * Pixel centres are at integer coordinates.  Non-finite coordinates give NaN. */
+ * Pixel centres are at integer coordinates.  Non-finite coordinates give NaN.  Evaluated as two
+ * linear interpolations along x and one along y (a + f (b - a)): the same interpolant as the
+ * weighted four-tap sum, in a form that reproduces a constant neighbourhood exactly, so a
+ * residual between flat regions of integer frames is an exact integer. */
 double or_bilinear(const double *I, int W, int H, double x, double y)
 {
     if (!isfinite(x) || !isfinite(y)) return NAN;
@@ -307,7 +310,8 @@ double or_bilinear(const double *I, int W, int H, double x, double y)
     int ya = clampi(y0, 0, H - 1), yb = clampi(y0 + 1, 0, H - 1);
     double i00 = I[(int64_t)ya * W + xa], i10 = I[(int64_t)ya * W + xb];
     double i01 = I[(int64_t)yb * W + xa], i11 = I[(int64_t)yb * W + xb];
-    return (1.0 - fy) * ((1.0 - fx) * i00 + fx * i10) + fy * ((1.0 - fx) * i01 + fx * i11);
+    double h0 = i00 + fx * (i10 - i00), h1 = i01 + fx * (i11 - i01);
+    return h0 + fy * (h1 - h0);
 }
 
 /* ------------------------------------------------------------------------------------------ */
@@ -910,7 +914,7 @@ int or_track_grad(const double *I0, const double *I1, int W, int H, const double
                 double g1 = 0.5 * (or_bilinear(I0, W, H, x, y + 1.0) - or_bilinear(I0, W, H, x, y - 1.0));
                 int64_t idx[4]; double wt[4]; int cx[4], cy[4]; double fx, fy;
                 bilinear_taps(W, H, x + ux, y + uy, idx, wt, cx, cy, &fx, &fy);
-                double Jv = wt[0] * I1[idx[0]] + wt[1] * I1[idx[1]] + wt[2] * I1[idx[2]] + wt[3] * I1[idx[3]];
+                double Jv = or_bilinear(I1, W, H, x + ux, y + uy);
                 double djx = (1.0 - fy) * (I1[idx[1]] - I1[idx[0]]) + fy * (I1[idx[3]] - I1[idx[2]]);
                 double djy = (1.0 - fx) * (I1[idx[2]] - I1[idx[0]]) + fx * (I1[idx[3]] - I1[idx[1]]);
                 double dp = or_dpsi(Jv - T, sigma1, sigma2);
@@ -969,15 +973,13 @@ int or_track_grad(const double *I0, const double *I1, int W, int H, const double
                 bilinear_taps(W, H, x - 1.0, y, ixm, wxm, dcx, dcy, &dfx, &dfy);
                 bilinear_taps(W, H, x, y + 1.0, iyp, wyp, dcx, dcy, &dfx, &dfy);
                 bilinear_taps(W, H, x, y - 1.0, iym, wym, dcx, dcy, &dfx, &dfy);
-                double T = 0.0, g0 = 0.0, g1 = 0.0;
-                for (int t = 0; t < 4; ++t) {
-                    T += wa[t] * I0[ia[t]];
-                    g0 += 0.5 * (wxp[t] * I0[ixp[t]] - wxm[t] * I0[ixm[t]]);
-                    g1 += 0.5 * (wyp[t] * I0[iyp[t]] - wym[t] * I0[iym[t]]);
-                }
+                /* values as in the first pass (the taps only distribute the gradient) */
+                double T = or_bilinear(I0, W, H, x, y);
+                double g0 = 0.5 * (or_bilinear(I0, W, H, x + 1.0, y) - or_bilinear(I0, W, H, x - 1.0, y));
+                double g1 = 0.5 * (or_bilinear(I0, W, H, x, y + 1.0) - or_bilinear(I0, W, H, x, y - 1.0));
                 int64_t ib[4]; double wb[4]; int bxx[4], byy[4]; double fxb, fyb;
                 bilinear_taps(W, H, x + ux, y + uy, ib, wb, bxx, byy, &fxb, &fyb);
-                double Jv = wb[0] * I1[ib[0]] + wb[1] * I1[ib[1]] + wb[2] * I1[ib[2]] + wb[3] * I1[ib[3]];
+                double Jv = or_bilinear(I1, W, H, x + ux, y + uy);
                 double res = Jv - T;
                 double ps = or_psi(res, sigma1, sigma2);
                 double dp = or_dpsi(res, sigma1, sigma2);
@@ -1083,13 +1085,11 @@ int or_track_grad_illum(const double *I0, const double *I1, int W, int H, const 
                 bilinear_taps(W, H, x, y + 1.0, iyp, wyp, ccx, ccy, &ffx, &ffy);
                 bilinear_taps(W, H, x, y - 1.0, iym, wym, ccx, ccy, &ffx, &ffy);
                 bilinear_taps(W, H, x + ux, y + uy, ib, wb, ccx, ccy, &ffx, &ffy);
-                double T = 0.0, g0 = 0.0, g1 = 0.0, Jv = 0.0;
-                for (int t = 0; t < 4; ++t) {
-                    T += wa[t] * I0[ia[t]];
-                    g0 += 0.5 * (wxp[t] * I0[ixp[t]] - wxm[t] * I0[ixm[t]]);
-                    g1 += 0.5 * (wyp[t] * I0[iyp[t]] - wym[t] * I0[iym[t]]);
-                    Jv += wb[t] * I1[ib[t]];
-                }
+                /* values as in the first pass (the taps only distribute the gradient) */
+                double T = or_bilinear(I0, W, H, x, y);
+                double g0 = 0.5 * (or_bilinear(I0, W, H, x + 1.0, y) - or_bilinear(I0, W, H, x - 1.0, y));
+                double g1 = 0.5 * (or_bilinear(I0, W, H, x, y + 1.0) - or_bilinear(I0, W, H, x, y - 1.0));
+                double Jv = or_bilinear(I1, W, H, x + ux, y + uy);
                 double res = Jv - (1.0 + m) * T - c;
                 double ps = or_psi(res, sigma1, sigma2), dp = or_dpsi(res, sigma1, sigma2);
                 double mphi = mu[0] * (1.0 + m) * g0 + mu[1] * (1.0 + m) * g1 - mu[2] * T - mu[3];

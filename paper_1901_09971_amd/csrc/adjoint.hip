@@ -30,6 +30,17 @@
 
 namespace dgf {
 
+// Value of the bilinear interpolant in the 2 x 2 cell whose top-left texel is q (row pitch w) at
+// fraction (fx, fy), as nested linear interpolations: a constant cell gives exactly its value, so
+// residuals between flat regions of integer frames are exact and a residual exactly on a robust
+// threshold takes the same band as in any other exact evaluation.
+__device__ __forceinline__ float lerp_cell(const float *q, int w, float fx, float fy)
+{
+    const float h0 = fmaf(fx, q[1] - q[0], q[0]);
+    const float h1 = fmaf(fx, q[w + 1] - q[w], q[w]);
+    return fmaf(fy, h1 - h0, h0);
+}
+
 // psi(r) and psi'(r) of the robust norm, band by band
 __device__ __forceinline__ void psi_and_slope(const AdjParams &A, float r, float &ps, float &dps)
 {
@@ -95,10 +106,7 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
 
     // template value and central differences of the bilinear interpolant, from the raw I0 patch;
     // support offset (kx, ky) sits at local (kx + 1, ky + 1)
-    auto I0s = [&](int lx, int ly) {
-        const float *q = raw0 + ly * w0 + lx;
-        return a00 * q[0] + a10 * q[1] + a01 * q[w0] + a11 * q[w0 + 1];
-    };
+    auto I0s = [&](int lx, int ly) { return lerp_cell(raw0 + ly * w0 + lx, w0, fx0, fy0); };
 
     // gradient of the bilinear interpolant of I0 inside the cell at local (lx, ly)
     auto I0g = [&](int lx, int ly, float &gx, float &gy) {
@@ -120,7 +128,7 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
         const float g1 = 0.5f * (I0s(lx, ly + 1) - I0s(lx, ly - 1));
         const float *q = raw1 + ky * w1 + kx;
         const float i00 = q[0], i10 = q[1], i01 = q[w1], i11 = q[w1 + 1];
-        const float J = b00 * i00 + b10 * i10 + b01 * i01 + b11 * i11;
+        const float J = lerp_cell(q, w1, fx1, fy1);
         const float djx = (1.f - fy1) * (i10 - i00) + fy1 * (i11 - i01);
         const float djy = (1.f - fx1) * (i01 - i00) + fx1 * (i11 - i10);
         float ps, dps;
@@ -163,7 +171,7 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
         const float g0 = 0.5f * (I0s(lx + 1, ly) - I0s(lx - 1, ly));
         const float g1 = 0.5f * (I0s(lx, ly + 1) - I0s(lx, ly - 1));
         const float *q = raw1 + ky * w1 + kx;
-        const float J = b00 * q[0] + b10 * q[1] + b01 * q[w1] + b11 * q[w1 + 1];
+        const float J = lerp_cell(q, w1, fx1, fy1);
         float ps, dps;
         psi_and_slope(A, J - T, ps, dps);
         C1[k] = dps * (mux * g0 + muy * g1);
@@ -287,10 +295,7 @@ __global__ __launch_bounds__(64) void k_track_adjoint_illum(AdjParams A)
     stage_rect<64, PixT>(raw0, w0, Pr.I0, Pr.pitch0, W, H, ox0, oy0, w0, w0, stage_lanes<64>(w0, li));
     stage_rect<64, PixT>(raw1, w1, Pr.I1, Pr.pitch1, W, H, ox1, oy1, w1, w1, stage_lanes<64>(w1, li));
     __syncthreads();
-    auto I0s = [&](int lx, int ly) {
-        const float *q = raw0 + ly * w0 + lx;
-        return a00 * q[0] + a10 * q[1] + a01 * q[w0] + a11 * q[w0 + 1];
-    };
+    auto I0s = [&](int lx, int ly) { return lerp_cell(raw0 + ly * w0 + lx, w0, fx0, fy0); };
 
     // template mean and spread over the support
     float sT = 0.f, sTT = 0.f, z0 = 0.f, z1 = 0.f, z2 = 0.f;
@@ -330,7 +335,7 @@ __global__ __launch_bounds__(64) void k_track_adjoint_illum(AdjParams A)
         const float g1 = 0.5f * (I0s(lx, ly + 1) - I0s(lx, ly - 1));
         const float *q = raw1 + ky * w1 + kx;
         const float i00 = q[0], i10 = q[1], i01 = q[w1], i11 = q[w1 + 1];
-        const float J = b00 * i00 + b10 * i10 + b01 * i01 + b11 * i11;
+        const float J = lerp_cell(q, w1, fx1, fy1);
         const float djx = (1.f - fy1) * (i10 - i00) + fy1 * (i11 - i01);
         const float djy = (1.f - fx1) * (i01 - i00) + fx1 * (i11 - i10);
         float ps, dps;
@@ -391,7 +396,7 @@ __global__ __launch_bounds__(64) void k_track_adjoint_illum(AdjParams A)
         const float g0 = 0.5f * (I0s(lx + 1, ly) - I0s(lx - 1, ly));
         const float g1 = 0.5f * (I0s(lx, ly + 1) - I0s(lx, ly - 1));
         const float *q = raw1 + ky * w1 + kx;
-        const float J = b00 * q[0] + b10 * q[1] + b01 * q[w1] + b11 * q[w1 + 1];
+        const float J = lerp_cell(q, w1, fx1, fy1);
         float ps, dps;
         psi_and_slope(A, J - g1m * T - mc.y, ps, dps);
         const float Tp = (T - Tm) * iTs;

@@ -12,6 +12,7 @@ import torch
 import oracle
 import paper_1901_09971_amd as dgf
 from paper_1901_09971_amd import synth
+from parity import compare_tracks
 
 pytestmark = pytest.mark.gpu
 L, S_, IT, WIN, STRIDE, NPAIRS, SAMPLE = 6, 21, 20, 9, 2, 4, 300
@@ -44,18 +45,19 @@ def test_every_point_detected(batch):
 def test_tracking_sample(batch):
     data, plan, P, F, S, samples = batch
     Pn, Fn, Sn = P.cpu().numpy(), F.cpu().numpy().astype(np.float64), S.cpu().numpy()
+    g_all, o_all = [], []
     for i, (I0, I1, _, _) in enumerate(data):
         idx = plan.offsets[i] + samples[i]
         pts = Pn[idx].astype(np.float64)
         of, os_ = oracle.track(I0, I1, pts, L, S_, IT)
-        agree = np.mean(os_ == Sn[idx])
-        both = (os_ == 0) & (Sn[idx] == 0)
-        err = np.max(np.abs(Fn[idx][both] - of[both])) if both.any() else 0.0
-        print(f"pair {i}: status agreement {agree:.4f}, both converged {int(both.sum())}, max err {err:.2e}",
-              flush=True)
-        assert agree >= 0.97
-        assert both.sum() >= 0.2 * SAMPLE
-        assert err <= 1e-3
+        r = compare_tracks(Fn[idx], Sn[idx], of, os_, 0.99, 1e-3, label=f"pair {i}")
+        assert r["conv"] >= 0.2 * SAMPLE
+        g_all.append(Sn[idx])
+        o_all.append(os_)
+    # over the whole sample (1,200 points) at most one status may differ
+    agree = float(np.mean(np.concatenate(g_all) == np.concatenate(o_all)))
+    print(f"status agreement over the sample {agree:.5f}", flush=True)
+    assert agree >= 0.999
 
 
 def test_adjoint_sample(batch):

@@ -6,13 +6,15 @@ pairs.  Bars:
   * detection beside the pyramids: points and every pyramid level bit-identical to the separate
     calls;
   * tracking, Hampel and L2 without the illumination model, supports 5 x 5 and larger: every
-    point both sides report CONVERGED within 1e-3 px; statuses differ on at most max(2, 3 %);
+    point both sides report CONVERGED within 1e-3 px; statuses differ on at most max(1, 0.1 %)
+    per trial, and agree on at least 99.9 % of all such points over the sweep;
   * tracking with hard thresholding, the illumination model or a 3 x 3 support: at most
     max(3, 1 %) of the points both sides report CONVERGED lie further apart, statuses differ on
-    at most max(5, 10 %).  A discontinuous weight, a gain near its acceptance bound trading off
-    against the motion, or a nine-pixel system lets FP32 and FP64 iterations settle at different
-    fixed points (a 5,000-trial sweep found at most 9 such points in one trial, none with Hampel
-    or L2 alone at supports of 5 and up; this sweep found one at a 3 x 3 support);
+    at most max(3, 2 %) per trial; over the sweep statuses agree on at least 99.9 % (99.8 % for
+    hard thresholding with the illumination model).  A discontinuous weight, a gain near its
+    acceptance bound trading off against the motion, or a nine-pixel system lets FP32 and FP64
+    iterations settle at different fixed points (a 5,000-trial sweep found at most 9 such points
+    in one trial, none with Hampel or L2 alone at supports of 5 and up);
   * dense interpolation (frames up to 60,000 pixels): cells and neighbour lists exact."""
 import numpy as np
 import pytest
@@ -29,7 +31,7 @@ MODES = [dict(sigma1=8.0, sigma2=32.0), dict(sigma1=float("inf"), sigma2=float("
          dict(sigma1=12.0, sigma2=12.0)]
 
 
-def _trial(rng, t):
+def _trial(rng, t, tally):
     W, H = int(rng.integers(12, 400)), int(rng.integers(12, 300))
     disp = float(rng.uniform(0, 25))
     I0, I1, _, _ = synth.layered_pair(W, H, seed=int(rng.integers(1 << 30)), max_disp=disp)
@@ -77,12 +79,16 @@ def _trial(rng, t):
     bad = int((np.abs(gF[both] - oF[both]).max(1) > 1e-3).sum()) if both.any() else 0
     differ = int((gS != oS).sum())
     print(f"  n={n} both={int(both.sum())} far={bad} status_differ={differ}", flush=True)
+    cls = ("illum " if illum else "") + ("hard" if mode == 2 else ("s3" if s == 3 else "smooth"))
+    tot = tally.setdefault(cls, [0, 0])
+    tot[0] += n
+    tot[1] += differ
     if illum or mode == 2 or s == 3:
         assert bad <= max(3, 0.01 * both.sum()), tag
-        assert differ <= max(5, 0.10 * n), tag
+        assert differ <= max(3, 0.02 * n), tag
     else:
         assert bad == 0, tag
-        assert differ <= max(2, 0.03 * n), tag
+        assert differ <= max(1, 0.001 * n), tag
     if W * H <= 60000:
         _, aux = dgf.epic(a, P, F, S, opts=dgf.EpicOpts(k=kk), return_aux=True)
         torch.cuda.synchronize()
@@ -93,5 +99,10 @@ def _trial(rng, t):
 
 def test_randomised_sweep():
     rng = np.random.default_rng(20190125)
+    tally = {}
     for t in range(300):
-        _trial(rng, t)
+        _trial(rng, t, tally)
+    for cls, (n, differ) in sorted(tally.items()):
+        agree = 1.0 - differ / max(n, 1)
+        print(f"{cls}: {n} points, statuses agree on {agree:.5f}", flush=True)
+        assert agree >= (0.998 if cls == "illum hard" else 0.999), cls

@@ -78,8 +78,9 @@ def _bilinear(I, x, y):
     fx, fy = x - x0, y - y0
     H, W = I.shape
     at = lambda yy, xx: I[np.clip(yy, 0, H - 1), np.clip(xx, 0, W - 1)]
-    return ((1 - fy) * ((1 - fx) * at(y0, x0) + fx * at(y0, x0 + 1))
-            + fy * ((1 - fx) * at(y0 + 1, x0) + fx * at(y0 + 1, x0 + 1)))
+    h0 = at(y0, x0) + fx * (at(y0, x0 + 1) - at(y0, x0))
+    h1 = at(y0 + 1, x0) + fx * (at(y0 + 1, x0 + 1) - at(y0 + 1, x0))
+    return h0 + fy * (h1 - h0)
 
 
 def _rel(a, b):
@@ -90,6 +91,7 @@ def _rel(a, b):
 def test_adjoint_random_pairs():
     rng = np.random.default_rng(11)
     done = 0
+    failed = []
     for t in range(200):
         if done == 60:
             break
@@ -111,7 +113,12 @@ def test_adjoint_random_pairs():
             mc = None
         torch.cuda.synchronize()
         Fn, Sn = flow.cpu().numpy().astype(np.float64), st.cpu().numpy()
-        tie = np.zeros(len(pts), bool)
+        # A residual within the FP32 evaluation error of a robust threshold (a sample of values
+        # <= 255 through three FMAs, minus another: < 1e-4) takes its psi' band by rounding, so the
+        # gradient of such a point is not fixed by FP32 arithmetic; those points are left out.
+        # Residuals exactly on a threshold (flat regions of integer frames) are exact on both
+        # sides (nested-lerp interpolation) and stay in.
+        near = np.zeros(len(pts), bool)
         if mode != 1:
             r = s // 2
             ky, kx = np.mgrid[-r:r + 1, -r:r + 1]
@@ -121,8 +128,8 @@ def test_adjoint_random_pairs():
                 T = _bilinear(I0.astype(np.float64), px + kx, py + ky)
                 J = _bilinear(I1.astype(np.float64), px + Fn[i, 0] + kx, py + Fn[i, 1] + ky)
                 res = np.abs(J - (1 + mcn[i, 0]) * T - mcn[i, 1]) if illum else np.abs(J - T)
-                tie[i] = any(np.any(np.abs(res - th) < 1e-3) for th in (opts.sigma1, opts.sigma2))
-        keep = (Sn == 0) & ~tie
+                near[i] = any(np.any((np.abs(res - th) < 1e-4) & (res != th)) for th in (opts.sigma1, opts.sigma2))
+        keep = (Sn == 0) & ~near
         g = torch.Generator(device="cpu").manual_seed(t)
         dflow = torch.randn(flow.shape, generator=g).cuda() * torch.from_numpy(keep).cuda()[:, None]
         dI0, dI1 = torch.zeros_like(t0), torch.zeros_like(t1)
@@ -136,8 +143,10 @@ def test_adjoint_random_pairs():
         else:
             o0, o1 = oracle.track_grad(*args, Fn, Sn, f64(dflow), sigma1=opts.sigma1, sigma2=opts.sigma2)
         e0, e1 = _rel(f64(dI0), o0), _rel(f64(dI1), o1)
-        bar = 1e-3 if illum else 1e-4
         print(f"#{t} {W}x{H} L{levels} s{s} it{iters} mode{mode}{' IM' if illum else ''} "
-              f"kept={int(keep.sum())} ties={int(tie.sum())} rel={e0:.1e}/{e1:.1e}", flush=True)
-        assert e0 <= bar and e1 <= bar, (t, e0, e1)
+              f"conv={int((Sn == 0).sum())} near_ties={int(near.sum())} rel={e0:.1e}/{e1:.1e}", flush=True)
+        if not (e0 <= 1e-4 and e1 <= 1e-4):
+            failed.append((t, s, mode, illum, e0, e1))
+    print("failed:", failed, flush=True)
+    assert not failed, failed
     assert done == 60

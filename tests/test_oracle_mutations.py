@@ -25,8 +25,8 @@ MUTATIONS = [
     ("pyramid taps 1 5 4 5 1 (same sum)",
      "static const int k5[5] = {1, 4, 6, 4, 1};", "static const int k5[5] = {1, 5, 4, 5, 1};"),
     ("bilinear interpolation with the two off-diagonal taps swapped",
-     "(1.0 - fy) * ((1.0 - fx) * i00 + fx * i10) + fy * ((1.0 - fx) * i01 + fx * i11)",
-     "(1.0 - fy) * ((1.0 - fx) * i00 + fx * i01) + fy * ((1.0 - fx) * i10 + fx * i11)"),
+     "double h0 = i00 + fx * (i10 - i00), h1 = i01 + fx * (i11 - i01);",
+     "double h0 = i00 + fx * (i01 - i00), h1 = i10 + fx * (i11 - i10);"),
     ("psi without its sigma1 factor in the middle band",
      "return copysign(s1 * (s2 - a) / (s2 - s1), r);", "return copysign((s2 - a) / (s2 - s1), r);"),
     ("off-diagonal of the structure tensor with the wrong sign",

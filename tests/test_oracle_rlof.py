@@ -64,6 +64,27 @@ def test_bilinear_exact_on_span_and_clamped():
     assert np.isnan(oracle.bilinear(img, np.nan, 1.0))
 
 
+def test_bilinear_reproduces_flat_neighbourhoods_exactly():
+    """A constant 2 x 2 neighbourhood interpolates to exactly its value at every fraction (the
+    interpolant's weights sum to one; evaluated as nested linear interpolations this holds in
+    floating point too), and a cell constant along one axis gives the exact 1-D interpolation
+    along the other.  Residuals between flat regions of integer frames are therefore exact
+    integers, which decides a residual lying exactly on a robust threshold the same way
+    wherever it is evaluated."""
+    rng = np.random.default_rng(4)
+    img = np.zeros((6, 8))
+    img[:, :4] = 137.0
+    img[:, 4:] = 145.0
+    for _ in range(2000):
+        x, y = rng.uniform(0.0, 2.999), rng.uniform(0.0, 4.999)
+        assert oracle.bilinear(img, x, y) == 137.0
+        assert oracle.bilinear(img, x + 4.001, y) == 145.0
+    # residual exactly on sigma1 = 8 between the two flat halves
+    assert oracle.bilinear(img, 5.3, 2.7) - oracle.bilinear(img, 1.6, 0.2) == 8.0
+    # constant along y: exact 1-D interpolation in x at a dyadic fraction
+    assert oracle.bilinear(img, 3.25, 2.9) == 137.0 + 0.25 * 8.0
+
+
 # ---------------------------------------------------------------------------------------------
 # tracking
 # ---------------------------------------------------------------------------------------------
