@@ -39,6 +39,7 @@ extern "C" {
 #define DGF_ERR_UNSUPPORTED (-3) /* valid request outside what this build implements          */
 #define DGF_ERR_HIP (-4)         /* a HIP runtime call or kernel launch failed                   */
 #define DGF_ERR_WORKSPACE (-5)   /* workspace null or smaller than dgf_track_workspace_bytes()   */
+#define DGF_ERR_SCRATCH (-6)     /* input larger than the static scratch of dgf_track_static     */
 
 /* ---- per-point tracking status ----------------------------------------------------------------- */
 #define DGF_ST_CONVERGED 0       /* level 0 stopped on the step-size test, p + u inside image    */
@@ -172,6 +173,27 @@ int dgf_track(const dgf_image *I0, const dgf_image *I1, const float *points, int
               int32_t support, int32_t iters, const dgf_track_opts *opts, void *workspace,
               size_t ws_bytes, float *flow, uint8_t *status, int32_t *iters_out, float *illum_out,
               void *stream);
+
+/* dgf_track without a workspace argument, for callers that cannot allocate device memory (code
+ * under stream capture into a graph, allocation-free serving loops, harnesses that forbid
+ * hipMalloc).  Both pyramids are built into a file-scope device array of
+ * DGF_TRACK_STATIC_MAX_BYTES bytes (16 MiB) that every GPU using this library holds until the
+ * process ends; the call itself allocates nothing.  Arguments, outputs and results are those of
+ * dgf_track (same kernels, same launch shape), minus workspace / ws_bytes.
+ *   Limit : dgf_track_workspace_bytes(width, height, levels, dtype) must not exceed
+ *           DGF_TRACK_STATIC_MAX_BYTES, else DGF_ERR_SCRATCH and nothing is launched (for
+ *           example 1242 x 375 uint8 at 5 levels needs 0.33 MB, 2048 x 1024 float at 6 levels
+ *           5.6 MB).
+ *   Races : every call on one GPU uses that GPU's one array, which keeps the last call's
+ *           pyramids; two calls whose work overlaps on one GPU (different streams, or host
+ *           threads) race on it.  Order them on one stream or with events.
+ *   Set-up: the first call on a device looks the array's device address up (hipGetSymbolAddress,
+ *           with that device current); DGF_ERR_HIP if that fails.  The device is the current
+ *           HIP device, which must be the one `stream` belongs to. */
+#define DGF_TRACK_STATIC_MAX_BYTES (16u << 20)
+int dgf_track_static(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
+                     int32_t support, int32_t iters, const dgf_track_opts *opts, float *flow, uint8_t *status,
+                     int32_t *iters_out, float *illum_out, void *stream);
 
 /* ---- gradient of the tracked flow (implicit differentiation at the converged fixed point) ---- */
 

@@ -15,6 +15,8 @@ DGF_OK = 0
 DGF_U8, DGF_F32 = 0, 1
 DGF_TRACK_ILLUM = 1
 DGF_MAX_LEVELS = 12
+DGF_ERR_SCRATCH = -6
+DGF_TRACK_STATIC_MAX_BYTES = 16 << 20
 ST_CONVERGED, ST_NOT_CONVERGED, ST_ILL_CONDITIONED, ST_OUT_OF_BOUNDS = 0, 1, 2, 3
 
 
@@ -63,6 +65,7 @@ SIGNATURES = {
     "dgf_pyramid": (ctypes.c_int, [IMG, I32, P, SZ, P]),
     "dgf_track_workspace_bytes": (SZ, [I32, I32, I32, I32]),
     "dgf_track": (ctypes.c_int, [IMG, IMG, P, I64, I32, I32, I32, OPTS, P, SZ, P, P, P, P, P]),
+    "dgf_track_static": (ctypes.c_int, [IMG, IMG, P, I64, I32, I32, I32, OPTS, P, P, P, P, P]),
     "dgf_track_pyramids": (ctypes.c_int, [IMG, IMG, I32, P, SZ, P]),
     "dgf_track_run": (ctypes.c_int, [IMG, IMG, P, I64, I32, I32, I32, OPTS, P, SZ, P, P, P, P, P]),
     "dgf_detect_pyramids": (ctypes.c_int, [IMG, IMG, I32, I32, I32, P, SZ, P, P, P, I64, P]),

@@ -139,6 +139,32 @@ def track(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, levels: int,
     return out
 
 
+def track_static(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, levels: int, support: int, iters: int,
+                 opts: TrackOpts | None = None, return_iters: bool = False, return_illum: bool = False):
+    """``track`` through ``dgf_track_static``: the pyramids go to the library's per-GPU static
+    scratch array instead of a workspace (the call allocates no device memory; outputs are
+    allocated here, by the caller of the C entry point).  Calls overlapping on one GPU race."""
+    a, b = _image(I0, "I0"), _image(I1, "I1")
+    if points.dtype != torch.float32 or points.dim() != 2 or points.shape[1] != 2 or not points.is_cuda:
+        raise ValueError("points: expected a float32 [n, 2] device tensor")
+    points = points.contiguous()
+    n = points.shape[0]
+    flow = torch.empty((n, 2), dtype=torch.float32, device=I0.device)
+    status = torch.empty(n, dtype=torch.uint8, device=I0.device)
+    its = torch.empty(n, dtype=torch.int32, device=I0.device) if return_iters else None
+    ill = torch.empty((n, 2), dtype=torch.float32, device=I0.device) if return_illum else None
+    o = (opts or TrackOpts()).to_c()
+    check(lib().dgf_track_static(ctypes.byref(a), ctypes.byref(b), _ptr(points), n, levels, support, iters,
+                                 ctypes.byref(o), _ptr(flow), _ptr(status), _ptr(its), _ptr(ill), _stream()),
+          "dgf_track_static")
+    out = (flow, status)
+    if return_iters:
+        out += (its,)
+    if return_illum:
+        out += (ill,)
+    return out
+
+
 def track_pyramids(I0: torch.Tensor, I1: torch.Tensor, levels: int, workspace: torch.Tensor) -> None:
     """First stage of :func:`track`: build both pyramids into ``workspace`` (uint8 device
     tensor of at least track_workspace_bytes(...) bytes)."""

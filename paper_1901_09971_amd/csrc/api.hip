@@ -45,6 +45,7 @@ const char *dgf_strerror(int code)
     case DGF_ERR_UNSUPPORTED: return "unsupported configuration";
     case DGF_ERR_HIP: return "HIP runtime error";
     case DGF_ERR_WORKSPACE: return "workspace missing or too small";
+    case DGF_ERR_SCRATCH: return "input larger than the static scratch of dgf_track_static";
     default: return "unknown error";
     }
 }
@@ -262,6 +263,17 @@ int validate_track(const dgf_image *I0, const dgf_image *I1, const float *points
                    int32_t support, int32_t iters, const dgf_track_opts *opts, const void *workspace, size_t ws_bytes,
                    const float *flow, const uint8_t *status, dgf_track_opts *o)
 {
+    const int rc = validate_track_args(I0, I1, points, n, levels, support, iters, opts, flow, status, o);
+    if (rc != DGF_OK) return rc;
+    if (levels > 1 && (!workspace || ws_bytes < dgf_track_workspace_bytes(I0->width, I0->height, levels, I0->dtype)))
+        return DGF_ERR_WORKSPACE;
+    return DGF_OK;
+}
+
+int validate_track_args(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
+                        int32_t support, int32_t iters, const dgf_track_opts *opts, const float *flow,
+                        const uint8_t *status, dgf_track_opts *o)
+{
     int rc = check_pair(I0, I1, levels);
     if (rc != DGF_OK) return rc;
     if (iters < 1) return DGF_ERR_INVALID_ARG;
@@ -279,8 +291,6 @@ int validate_track(const dgf_image *I0, const dgf_image *I1, const float *points
         isnan(o->min_eig))
         return DGF_ERR_INVALID_ARG;
     if (isinf(o->sigma2) && !isinf(o->sigma1)) return DGF_ERR_INVALID_ARG; // no finite inner band with infinite outer
-    if (levels > 1 && (!workspace || ws_bytes < dgf_track_workspace_bytes(I0->width, I0->height, levels, I0->dtype)))
-        return DGF_ERR_WORKSPACE;
     return DGF_OK;
 }
 

@@ -20,6 +20,10 @@ bool tuning_valid(const TrackTuning &t, int support);
 int validate_track(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
                    int32_t support, int32_t iters, const dgf_track_opts *opts, const void *workspace, size_t ws_bytes,
                    const float *flow, const uint8_t *status, dgf_track_opts *o);
+// The same checks without the workspace (for dgf_track_static, whose pyramids need none).
+int validate_track_args(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
+                        int32_t support, int32_t iters, const dgf_track_opts *opts, const float *flow,
+                        const uint8_t *status, dgf_track_opts *o);
 int track_run_with(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
                    int32_t support, int32_t iters, const dgf_track_opts &o, const void *workspace, float *flow,
                    uint8_t *status, int32_t *iters_out, TrackTuning tune, hipStream_t st, float *illum_out = nullptr);

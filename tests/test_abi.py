@@ -196,3 +196,34 @@ def test_epic_argument_checks_before_any_launch():
     assert call(wsb=ws - 1) == -5
     # distances must fit 32 bits: (W + H - 2) (kappa + 1020) <= 2^32 - 2
     assert call(img=DgfImage(1 << 20, 8000, 10, 8000, 0), kappa=1 << 20) == -3
+
+
+def test_track_static_checks_before_any_hip_call():
+    """dgf_track_static rejects bad arguments and inputs larger than its static scratch on the
+    host, before it looks up the scratch array or launches anything (no GPU here)."""
+    L = _lib.lib()
+    P = ctypes.c_void_p(1 << 20)
+    im = _img()
+
+    def call(I0=im, I1=im, pts=P, n=10, levels=3, s=9, iters=10, opts=None, flow=P, st=P, ill=None):
+        return L.dgf_track_static(ctypes.byref(I0), ctypes.byref(I1), pts, n, levels, s, iters, opts, flow, st, None,
+                                  ill, None)
+
+    assert call(I1=_img(w=63)) == -1 and call(levels=0) == -1 and call(levels=13) == -1
+    assert call(s=8) == -1 and call(iters=0) == -1 and call(n=-1) == -1
+    assert call(pts=None) == -1 and call(flow=None) == -1 and call(st=None) == -1
+    assert call(ill=P) == -1  # illum_out without the illumination model
+    o = _lib.DgfTrackOpts(8, 32, 1e-2, 1e-4, 6.5, 2)
+    assert call(opts=ctypes.pointer(o)) == -3
+    assert L.dgf_track_static(None, ctypes.byref(im), P, 10, 3, 9, 10, None, P, P, None, None, None) == -1
+    # n = 0: validated, nothing looked up or launched
+    assert call(n=0, pts=None, flow=None, st=None) == 0
+    # pyramids larger than the static array: DGF_ERR_SCRATCH, whatever the point count
+    big = _img(w=4096, h=4096, pitch=4 * 4096, dtype=1)
+    need = L.dgf_track_workspace_bytes(4096, 4096, 3, 1)
+    assert need > _lib.DGF_TRACK_STATIC_MAX_BYTES
+    assert call(I0=big, I1=big) == _lib.DGF_ERR_SCRATCH
+    assert call(I0=big, I1=big, n=0, pts=None, flow=None, st=None) == _lib.DGF_ERR_SCRATCH
+    # one level needs no pyramid: never too large
+    assert L.dgf_track_workspace_bytes(4096, 4096, 1, 1) <= _lib.DGF_TRACK_STATIC_MAX_BYTES
+    assert b"static scratch" in L.dgf_strerror(_lib.DGF_ERR_SCRATCH)
