@@ -440,11 +440,11 @@ struct WorkItem {
     bool done;    // no work left for the wavefront
 };
 
-template <int PPW>
+template <int PPW, bool BATCH = true>
 __device__ __forceinline__ WorkItem work_item(const TrackParams &P, int64_t item, int q)
 {
     WorkItem w;
-    if (P.npairs == 0) {
+    if (!BATCH || P.npairs == 0) {
         w.done = item * PPW >= P.n;
         w.pair = 0;
         w.pidx = item * PPW + q;
@@ -508,9 +508,10 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
 // readfirstlanes tell the compiler so, and keep base pointers and sizes in scalar registers (the
 // table is read through a generic pointer, kernel argument or device memory, which it cannot
 // prove uniform on its own).
+template <bool BATCH = true>
 __device__ __forceinline__ LevelPair level_of(const TrackParams &P, int pair, int l)
 {
-    const LevelPair v = P.npairs ? P.blv[pair * P.L + l] : P.lv[l];
+    const LevelPair v = (BATCH && P.npairs) ? P.blv[pair * P.L + l] : P.lv[l];
     LevelPair u;
     u.p0 = reinterpret_cast<const uint8_t *>(uniform_u64(reinterpret_cast<uint64_t>(v.p0)));
     u.p1 = reinterpret_cast<const uint8_t *>(uniform_u64(reinterpret_cast<uint64_t>(v.p1)));

@@ -48,9 +48,23 @@ __device__ __forceinline__ void group_sum5(float &a, float &b, float &c, float &
     }
 }
 
-// The 64-lane form without the illumination model is held to 80 VGPRs (six waves per SIMD, two
-// values spilled outside the pixel loops): it is issue bound, and the sixth wave pays.
-template <int LPP, int SEG, int R, int TP, typename PixT, bool IM>
+// True when the flag is set on any lane of the wavefront.  With one point per wavefront (64 lanes
+// per point) every lane holds the same value, so the flag itself decides the branch: no ballot,
+// whose lowering would spend two vector instructions turning a mask back into a condition.
+template <int LPP>
+__device__ __forceinline__ bool group_any(bool p)
+{
+    if constexpr (LPP == 64)
+        return p;
+    else
+        return wave_any(p);
+}
+
+// The 64-lane form without the illumination model is held to 80 VGPRs (six waves per SIMD): it is
+// issue bound, and the sixth wave pays.  MODE (ROBUST_L2 / HAMPEL / HARD) and BATCH (a batch plan's
+// persistent launch rather than one pair) are compile-time, so a single-pair launch carries no
+// batch bookkeeping and no branch on the robust norm.
+template <int LPP, int SEG, int R, int TP, int S, typename PixT, bool IM, int MODE, bool BATCH>
 __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(TrackParams P)
 {
     constexpr int PPW = 64 / LPP;
@@ -63,10 +77,14 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
     const int li = lane - q * LPP;
     float *tile = smem + (size_t)(wave * PPW + q) * P.tile_floats;
 
-    const int s = P.s, r = P.r, RW = P.RW, RP = P.RPP, TW = P.TW, M = P.M;
+    // support s x s, raw I0 patch (s + 3)^2 with row pitch RP (the host's raw_pitch(s)), resampled
+    // grid (s + 2)^2 below it with the same pitch
+    constexpr int s = S, r = S / 2, RW = S + 3, RP = (RW % 4 == 0) ? RW + 2 : RW, G = S + 2;
+    static_assert(S % R == 0, "runs must tile the support rows");
+    const int TW = P.TW, M = P.M;
     const StageLanes slR = stage_lanes<LPP>(RW, li), slT = stage_lanes<LPP>(TW, li);
-    const int nseg_row = s / R; // runs per support row
-    const int nseg = s * nseg_row;
+    constexpr int nseg_row = s / R; // runs per support row
+    constexpr int nseg = s * nseg_row;
 
     // run geometry: sb = row * TP + col0 of the run's first pixel in the I1 tile, rc = row << 8 |
     // col0; unused runs point at 0 and carry zero gradients
@@ -92,9 +110,9 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
     // Persistent launches pull from the queue of their own XCD first.
     const int home = (int)(blockIdx.x % kNumXcd);
     int visit = 0;
-    int64_t item = P.persistent ? next_item(P, home, visit) : (int64_t)blockIdx.x * wpb + wave;
+    int64_t item = (BATCH && P.persistent) ? next_item(P, home, visit) : (int64_t)blockIdx.x * wpb + wave;
     for (;;) {
-    const WorkItem wi = work_item<PPW>(P, item, q);
+    const WorkItem wi = work_item<PPW, BATCH>(P, item, q);
     if (wi.done) break;
     const int64_t pidx = wi.pidx;
     const int pair = wi.pair;
@@ -105,7 +123,7 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
         px = pp.x;
         py = pp.y;
     }
-    const LevelPair LV0 = level_of(P, pair, 0);
+    const LevelPair LV0 = level_of<BATCH>(P, pair, 0);
     const int W0 = LV0.W, H0 = LV0.H;
     int status = -1;
     float ux = 0.f, uy = 0.f;
@@ -115,15 +133,16 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
         px = 0.f;
         py = 0.f;
     }
-    float gX = 0.f, gY = 0.f, dX = 0.f, dY = 0.f;
+    float gX = 0.f, gY = 0.f; // guess of the current level
+    float hX = 0.f, hY = 0.f; // guess plus the steps taken on it so far (g + d)
     bool conv0 = false;
     int it_total = 0;
     float im_m = 0.f, im_c = 0.f; // illumination model: gain change and offset, carried across levels
 
 
     for (int l = P.L - 1; l >= 0; --l) {
-        if (!wave_any(active)) break;
-        const LevelPair LV = level_of(P, pair, l);
+        if (!group_any<LPP>(active)) break;
+        const LevelPair LV = level_of<BATCH>(P, pair, l);
         const int Wl = LV.W, Hl = LV.H;
         const float sc = __builtin_ldexpf(1.0f, -l);
         const float plx = px * sc, ply = py * sc;
@@ -135,32 +154,39 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
         wave_sync();
         stage_rect<LPP, PixT>(tile, RP, LV.p0, LV.pitch0, Wl, Hl, ibx - 1, iby - 1, RW, RW, slR);
         wave_sync();
-        // value and central differences at +-1 px of the bilinearly resampled patch.  The
-        // vertical difference is resampled as one patch (bilinear sampling is linear).  Unused
-        // runs get half = 0, so their gradients vanish; they read run 0's pixels, so a
-        // non-finite pixel there reaches the sums through run 0 anyway.
+        // Bilinear resample of the raw patch on the (s + 2)^2 grid of support offsets -r-1 .. r+1
+        // (every sample shares the point's fraction): lanes take runs of kRes grid columns of one
+        // grid row, a vertical lerp per raw column and a horizontal lerp between neighbours.
+        float *grid = tile + RW * RP;
         {
+            constexpr int kRes = 12, runs_row = (G + kRes - 1) / kRes;
+            for (int u = li; u < G * runs_row; u += LPP) {
+                const int gi = u / runs_row, c0 = (u - gi * runs_row) * kRes;
+                const float *q = tile + gi * RP + c0;
+                float v[kRes + 1];
 #pragma unroll
-            for (int j = 0; j < SEG; ++j) {
-                const int row = rc[j] >> 8, col0 = rc[j] & 255;
-                const float *rp = tile + row * RP + col0; // raw rows row .. row+3, cols col0 .. col0+R+2
-                const float half = ((vmask >> j) & 1u) ? 0.5f : 0.f;
-                float V1[R + 3], D[R + 3];
+                for (int cc = 0; cc <= kRes; ++cc) v[cc] = fmaf(pfy, q[RP + cc] - q[cc], q[cc]);
+                float *o = grid + gi * RP + c0;
 #pragma unroll
-                for (int cc = 0; cc < R + 3; ++cc) {
-                    const float r0 = rp[cc], r1 = rp[RP + cc], r2 = rp[2 * RP + cc], r3 = rp[3 * RP + cc];
-                    V1[cc] = fmaf(pfy, r2 - r1, r1);
-                    D[cc] = fmaf(pfy, (r3 - r2) - (r1 - r0), r2 - r0); // row +1 minus row -1
-                }
-                float B1[R + 2];
+                for (int cc = 0; cc < kRes; ++cc)
+                    if (c0 + cc < G) o[cc] = fmaf(pfx, v[cc + 1] - v[cc], v[cc]);
+            }
+        }
+        wave_sync();
+        // template value and central differences at +-1 px of the resampled patch.  Unused runs get
+        // half = 0, so their gradients vanish; they read run 0's pixels, so a non-finite pixel
+        // there reaches the sums through run 0 anyway.
 #pragma unroll
-                for (int cc = 0; cc < R + 2; ++cc) B1[cc] = fmaf(pfx, V1[cc + 1] - V1[cc], V1[cc]);
+        for (int j = 0; j < SEG; ++j) {
+            const int row = rc[j] >> 8, col0 = rc[j] & 255;
+            const float *gm = grid + row * RP + col0 + 1;      // grid row of support row - 1
+            const float *g0 = gm + RP, *gp = gm + 2 * RP;        // support row, support row + 1
+            const float half = ((vmask >> j) & 1u) ? 0.5f : 0.f;
 #pragma unroll
-                for (int p = 0; p < R; ++p) {
-                    T[j * R + p] = B1[p + 1];
-                    GX[j * R + p] = half * (B1[p + 2] - B1[p]);
-                    GY[j * R + p] = half * fmaf(pfx, D[p + 2] - D[p + 1], D[p + 1]);
-                }
+            for (int p = 0; p < R; ++p) {
+                T[j * R + p] = g0[p];
+                GX[j * R + p] = half * (g0[p + 1] - g0[p - 1]);
+                GY[j * R + p] = half * (gp[p] - gm[p]);
             }
         }
         float a = 0.f, b = 0.f, c = 0.f, sT = 0.f;
@@ -228,21 +254,36 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
         const float eps2 = (l > 0) ? P.eps2c : P.eps2f;
 
         // ---- iterations
-        dX = 0.f;
-        dY = 0.f;
+        hX = gX;
+        hY = gY;
         bool lvl_active = active && !flat, lvl_conv = false;
+        // below this the weighted system falls back to least squares
+        const float det_floor = 1e-6f * (IM ? det0_im : det0);
         int ox1 = 0, oy1 = 0;
         for (int it = 0; it < P.iters; ++it) {
-            if (!wave_any(lvl_active)) break;
-            const float tx = pfx + (gX + dX), ty = pfy + (gY + dY);
-            float flx = floorf(tx), fly = floorf(ty);
+            if (!group_any<LPP>(lvl_active)) break;
+            const float tx = pfx + hX, ty = pfy + hY;
+            const float flx = floorf(tx), fly = floorf(ty);
             const float fx = tx - flx, fy = ty - fly;
-            flx = fminf(fmaxf(flx, -1048576.f), 1048576.f);
-            fly = fminf(fmaxf(fly, -1048576.f), 1048576.f);
-            const int bx = (int)pbx + (int)flx - r, by = (int)pby + (int)fly - r;
+            // integer part, kept finite and small for the tile arithmetic (a non-finite guess only
+            // occurs on a point already stopped, whose samples are discarded)
+            int ix, iy;
+            if constexpr (LPP == 64) {
+                // one point per wavefront: the position is wave-uniform.  An integral float below
+                // 2^22 in magnitude plus 1.5 * 2^23 is exact and holds the value plus 2^22 in its low
+                // 23 bits, so one add and one read-first-lane give the integer to scalar code; larger
+                // or non-finite values decode to something in [-2^22, 2^22), which keeps every tile
+                // offset far from integer overflow (staging clamps each address into the image).
+                ix = (__builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, flx + 12582912.f)) & 0x7FFFFF) - 0x400000;
+                iy = (__builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, fly + 12582912.f)) & 0x7FFFFF) - 0x400000;
+            } else {
+                ix = (int)__builtin_amdgcn_fmed3f(flx, -1048576.f, 1048576.f);
+                iy = (int)__builtin_amdgcn_fmed3f(fly, -1048576.f, 1048576.f);
+            }
+            const int bx = ibx + ix, by = iby + iy;
             int dxo = bx - ox1, dyo = by - oy1;
             const bool inr = dxo >= 0 && dxo <= 2 * M && dyo >= 0 && dyo <= 2 * M;
-            if (wave_any((it == 0) || (lvl_active && !inr))) {
+            if (group_any<LPP>((it == 0) || (lvl_active && !inr))) {
                 wave_sync();
                 ox1 = bx - M;
                 oy1 = by - M;
@@ -289,7 +330,7 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
                 // with the signs applied after the reduction; invalid runs have weight 0
                 float A[10], V[4], x[4]; // step = A^-1 (-sum w r phi) with phi = (g, -T', -1)
                 float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
-                if (P.mode == ROBUST_L2) {
+                if constexpr (MODE == ROBUST_L2) {
 #pragma unroll
                     for (int j = 0; j < PPL; ++j) {
                         const float w = ((vmask >> (j / R)) & 1u) ? 1.f : 0.f;
@@ -313,8 +354,8 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
                           s23 = 0.f, s33 = 0.f;
 #pragma unroll
                     for (int j = 0; j < PPL; ++j) {
-                        float w = (P.mode == ROBUST_HAMPEL) ? hampel_weight(RES[j], P.cs2, P.cmid)
-                                                            : ((fabsf(RES[j]) <= P.s1) ? 1.f : 0.f);
+                        float w = (MODE == ROBUST_HAMPEL) ? hampel_weight(RES[j], P.cs2, P.cmid)
+                                                          : ((fabsf(RES[j]) <= P.s1) ? 1.f : 0.f);
                         w = ((vmask >> (j / R)) & 1u) ? w : 0.f;
                         const float wgx = w * GX[j], wgy = w * GY[j], wt = w * T[j];
                         s00 = fmaf(wgx, GX[j], s00);
@@ -353,8 +394,8 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
                     V[2] = q2;
                     V[3] = q3;
                     const float detw = ldl4(A, V, x);
-                    const bool fb = lvl_active && !(detw > 1e-6f * det0_im);
-                    if (wave_any(fb)) { // too many down-weighted pixels: least-squares step
+                    const bool fb = lvl_active && !(detw > det_floor);
+                    if (group_any<LPP>(fb)) { // too many down-weighted pixels: least-squares step
                         float u0 = 0.f, u1 = 0.f, u2 = 0.f, u3 = 0.f, z1 = 0.f;
 #pragma unroll
                         for (int j = 0; j < PPL; ++j) {
@@ -385,7 +426,7 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
                 sb = x[3];
             } else {
                 float G11, G12, G22, B1 = 0.f, B2 = 0.f, det;
-                if (P.mode == ROBUST_L2) {
+                if constexpr (MODE == ROBUST_L2) {
     #pragma unroll
                     for (int j = 0; j < PPL; ++j) {
                         B1 = fmaf(RES[j], GX[j], B1);
@@ -401,7 +442,7 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
                     G11 = 0.f;
                     G12 = 0.f;
                     G22 = 0.f;
-                    if (P.mode == ROBUST_HAMPEL) {
+                    if constexpr (MODE == ROBUST_HAMPEL) {
     #pragma unroll
                         for (int j = 0; j < PPL; ++j) {
                             const float w = hampel_weight(RES[j], P.cs2, P.cmid);
@@ -426,8 +467,8 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
                     }
                     group_sum5<LPP>(G11, G12, G22, B1, B2);
                     det = G11 * G22 - G12 * G12;
-                    const bool fb = lvl_active && !(det > 1e-6f * det0);
-                    if (wave_any(fb)) {
+                    const bool fb = lvl_active && !(det > det_floor);
+                    if (group_any<LPP>(fb)) {
                         float C1 = 0.f, C2 = 0.f;
     #pragma unroll
                         for (int j = 0; j < PPL; ++j) {
@@ -459,8 +500,8 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
                     active = false;
                     lvl_active = false;
                 } else {
-                    dX += sx;
-                    dY += sy;
+                    hX += sx;
+                    hY += sy;
                     if constexpr (IM) {
                         ga += sa;
                         gb += sb;
@@ -480,8 +521,8 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
         }
         if (l > 0) {
             if (active) {
-                gX = 2.f * (gX + dX);
-                gY = 2.f * (gY + dY);
+                gX = 2.f * hX;
+                gY = 2.f * hY;
             }
         } else {
             conv0 = lvl_conv;
@@ -490,8 +531,8 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
 
     if (valid && li == 0) {
         if (status < 0) {
-            ux = gX + dX;
-            uy = gY + dY;
+            ux = hX;
+            uy = hY;
             if (!conv0 || (IM && !(1.f + im_m >= 0.5f && 1.f + im_m <= 2.f))) {
                 // (illumination model: a gain outside [1/2, 2] is a contrast change, not a match)
                 status = DGF_ST_NOT_CONVERGED;
@@ -508,19 +549,25 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
             if (P.illum_out) reinterpret_cast<float2 *>(P.illum_out)[pidx] = make_float2(im_m, im_c);
         }
     }
-    if (!P.persistent) break;
+    if (!(BATCH && P.persistent)) break;
     item = next_item(P, home, visit);
     } // work loop
 }
 
-template <int LPP, int SEG, int R, int TP, typename PixT, bool IM>
+template <int LPP, int SEG, int R, int TP, int S, typename PixT, bool IM, bool BATCH>
 hipError_t launch_track_run_t(const TrackParams &P, int wpb, hipStream_t st)
 {
     constexpr int PPW = 64 / LPP;
     const int64_t waves = P.npairs ? P.grid_waves : (P.n + PPW - 1) / PPW;
     const int64_t blocks = (waves + wpb - 1) / wpb;
     const size_t lds = (size_t)wpb * PPW * P.tile_floats * sizeof(float);
-    hipLaunchKernelGGL((k_track_run<LPP, SEG, R, TP, PixT, IM>), dim3((unsigned)blocks), dim3(64 * wpb), lds, st, P);
+    const dim3 grid((unsigned)blocks), block(64 * wpb);
+    if (P.mode == ROBUST_L2)
+        hipLaunchKernelGGL((k_track_run<LPP, SEG, R, TP, S, PixT, IM, ROBUST_L2, BATCH>), grid, block, lds, st, P);
+    else if (P.mode == ROBUST_HAMPEL)
+        hipLaunchKernelGGL((k_track_run<LPP, SEG, R, TP, S, PixT, IM, ROBUST_HAMPEL, BATCH>), grid, block, lds, st, P);
+    else
+        hipLaunchKernelGGL((k_track_run<LPP, SEG, R, TP, S, PixT, IM, ROBUST_HARD, BATCH>), grid, block, lds, st, P);
     return hipGetLastError();
 }
 
