@@ -418,6 +418,62 @@ def density_stress(reps: int):
             "interpolation_seeds_one_pair": int((S[lo:hi] == 0).sum().item())}
 
 
+def achievable_peaks():
+    """On-box probes of what the chip delivers (libdgf_peaks.so, built beside the package): HBM
+    stream copy and stream read over 1 GiB buffers (four times the 256 MB Infinity Cache, so the
+    stream comes from HBM), LDS read bandwidth (conflict-free 16-byte reads), and the FP32 issue
+    rates of unpacked FMA and of the reciprocal, each over ~5 ms launches, HIP events, best of 5."""
+    import ctypes
+
+    import torch
+
+    L = ctypes.CDLL(os.path.join(ROOT, "paper_1901_09971_amd", "probes", "libdgf_peaks.so"))
+    dev = torch.device("cuda", 0)
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    n16 = (1 << 30) // 16
+    a = torch.ones(n16 * 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    blocks = cus * 8
+    out = torch.empty(max(blocks * 256, cus * 32 * 256), dtype=torch.float32, device=dev)
+
+    def best(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return min(ts)
+
+    mem_blocks = cus * 32
+    t_copy = best(lambda: L.pk_copy(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                    ctypes.c_int64(n16), mem_blocks, st))
+    t_read = best(lambda: L.pk_read(ctypes.c_void_p(a.data_ptr()), ctypes.c_int64(n16),
+                                    ctypes.c_void_p(out.data_ptr()), mem_blocks, st))
+    it_lds, it_fma, it_rcp = 6000, 6000, 1500
+    t_lds = best(lambda: L.pk_lds(it_lds, ctypes.c_void_p(out.data_ptr()), blocks, st))
+    t_fma = best(lambda: L.pk_fma(it_fma, ctypes.c_void_p(out.data_ptr()), blocks, st))
+    t_rcp = best(lambda: L.pk_rcp(it_rcp, ctypes.c_void_p(out.data_ptr()), blocks, st))
+    threads = blocks * 256
+    fma_rate = threads * it_fma * 64 / (t_fma * 1e-3)
+    rcp_rate = threads * it_rcp * 64 / (t_rcp * 1e-3)
+    del a, b, out
+    torch.cuda.empty_cache()
+    return {"hbm_copy_gbps": 2 * (1 << 30) / (t_copy * 1e-3) / 1e9,
+            "hbm_read_gbps": (1 << 30) / (t_read * 1e-3) / 1e9,
+            "lds_read_tbps": threads * it_lds * 8 * 16 / (t_lds * 1e-3) / 1e12,
+            "fp32_fma_tflops": 2 * fma_rate / 1e12,
+            "rcp_per_fma_rate": rcp_rate / fma_rate,
+            "compute_units": cus,
+            "what": "1 GiB copy (read + write bytes) and read; LDS conflict-free 16-byte reads; "
+                    "unpacked FP32 FMA and v_rcp_f32, 8 independent chains per lane"}
+
+
 def copy_calibration(mib: int):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -447,6 +503,8 @@ def main():
     ap.add_argument("--no-interp", action="store_true", help="skip the dense interpolation measurement")
     ap.add_argument("--separate-detect", action="store_true",
                     help="step as three launches (detect, pyramids, track) instead of detect+pyramids, track")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the achievable-peak probes")
+    ap.add_argument("--peaks-only", action="store_true", help="only run the achievable-peak probes")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -457,6 +515,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration_mib:
         copy_calibration(args.copy_calibration_mib)
+        return
+    if args.peaks_only:
+        print(json.dumps({"achievable": achievable_peaks()}))
         return
 
     import numpy as np
