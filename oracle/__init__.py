@@ -31,6 +31,8 @@ EPIC_DEFAULTS = dict(k=128, kappa=8, h=64)
 # Default tracker constants on the 0..255 intensity scale (same meaning as the library's
 # default options; the values are restated here, not imported).
 DEFAULTS = dict(sigma1=8.0, sigma2=32.0, eps_coarse=1e-2, eps_fine=1e-4, min_eig=1e-4 * 255.0 * 255.0)
+# Intensity threshold of the adaptive cross-based supports (grey levels).
+CROSS_TAU = 25.0
 
 
 def build(force: bool = True) -> str:
@@ -75,7 +77,11 @@ def _load():
     lib.or_dpsi.argtypes = [f64, f64, f64]
     lib.or_dpsi.restype = f64
     lib.or_track.argtypes = [P, P, i32, i32, i32, i64, P, i64, i32, i32, i32, f64, f64, f64, f64, f64,
-                             i32, P, P, P, P, i32]
+                             i32, i32, f64, i32, P, P, P, P, P, i32]
+    lib.or_cross_mask.argtypes = [P, i32, f64, P]
+    lib.or_cross_mask.restype = i32
+    lib.or_gm_fit.argtypes = [P, P, P, i64, f64, f64, f64, i32, P]
+    lib.or_gm_fit.restype = i32
     lib.or_track.restype = i32
     lib.or_track_grad.argtypes = [P, P, i32, i32, P, i64, i32, f64, f64, P, P, P, P, P, P]
     lib.or_track_grad_illum.argtypes = [P, P, i32, i32, P, i64, i32, f64, f64, P, P, P, P, P, P, P]
@@ -187,10 +193,12 @@ def dpsi(r: float, sigma1: float, sigma2: float) -> float:
 def track(I0: np.ndarray, I1: np.ndarray, points: np.ndarray, levels: int, support: int, iters: int,
           sigma1=DEFAULTS["sigma1"], sigma2=DEFAULTS["sigma2"], eps_coarse=DEFAULTS["eps_coarse"],
           eps_fine=DEFAULTS["eps_fine"], min_eig=DEFAULTS["min_eig"], threads: int | None = None,
-          return_iters: bool = False, illum: bool = False, return_illum: bool = False):
+          return_iters: bool = False, illum: bool = False, return_illum: bool = False,
+          cross: bool = False, tau: float = CROSS_TAU, gm: bool = False, return_gm: bool = False):
     """Track points from I0 to I1.  uint8 images use the uint8 pyramid; anything else is taken
-    as real-valued (float64).  ``illum`` selects the gain/offset illumination model.  Returns
-    (flow[n,2] float64, status[n] uint8[, iters[n,L]][, illum[n,2] = (m, c)])."""
+    as real-valued (float64).  ``illum`` selects the gain/offset illumination model, ``cross`` the
+    adaptive cross-based supports (threshold ``tau``), ``gm`` the global-motion prior.  Returns
+    (flow[n,2] float64, status[n] uint8[, iters[n,L]][, illum[n,2] = (m, c)][, gm model[2,3]])."""
     if I0.shape != I1.shape:
         raise ValueError("I0 and I1 must have the same shape")
     if I0.dtype == np.uint8 and I1.dtype == np.uint8:
@@ -206,9 +214,11 @@ def track(I0: np.ndarray, I1: np.ndarray, points: np.ndarray, levels: int, suppo
     st = np.zeros(n, np.uint8)
     its = np.zeros((n, levels), np.int32) if return_iters else None
     mc = np.zeros((n, 2), np.float64) if return_illum else None
+    A = np.zeros(6, np.float64)
     rc = _load().or_track(_ptr(a0), _ptr(a1), dt, W, H, W, _ptr(pts), n, levels, support, iters,
-                          sigma1, sigma2, eps_coarse, eps_fine, min_eig, int(bool(illum)), _ptr(flow), _ptr(st),
-                          _ptr(its), _ptr(mc), threads or default_threads())
+                          sigma1, sigma2, eps_coarse, eps_fine, min_eig, int(bool(illum)), int(bool(cross)),
+                          float(tau), int(bool(gm)), _ptr(flow), _ptr(st), _ptr(its), _ptr(mc), _ptr(A),
+                          threads or default_threads())
     if rc != 0:
         raise ValueError(f"or_track failed: {rc}")
     out = (flow, st)
@@ -216,7 +226,33 @@ def track(I0: np.ndarray, I1: np.ndarray, points: np.ndarray, levels: int, suppo
         out += (its,)
     if return_illum:
         out += (mc,)
+    if return_gm:
+        out += (A.reshape(2, 3),)
     return out
+
+
+def cross_mask(Tx: np.ndarray, tau: float = None) -> np.ndarray:
+    """Adaptive cross-based support of a template given on its (s+2) x (s+2) extension (offsets
+    -r-1 .. r+1): uint8 s x s mask, 1 = in the support."""
+    Tx = np.ascontiguousarray(Tx, dtype=np.float64)
+    e = Tx.shape[0]
+    s = e - 2
+    assert Tx.shape == (e, e) and s % 2 == 1 and s >= 1
+    m = np.zeros((s, s), np.uint8)
+    _load().or_cross_mask(_ptr(Tx), s, CROSS_TAU if tau is None else float(tau), _ptr(m))
+    return m
+
+
+def gm_fit(points: np.ndarray, motions: np.ndarray, use: np.ndarray, center, scale: float, iters: int = 10):
+    """Robust global affine motion of the samples: (A[2,3], kind) with kind 2 affine, 1
+    translation, 0 none; motion ~ A (x - cx, y - cy, 1)."""
+    p = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 2)
+    v = np.ascontiguousarray(motions, dtype=np.float64).reshape(-1, 2)
+    u = np.ascontiguousarray(use, dtype=np.uint8).reshape(-1)
+    A = np.zeros(6, np.float64)
+    kind = _load().or_gm_fit(_ptr(p), _ptr(v), _ptr(u), len(p), float(center[0]), float(center[1]), float(scale),
+                             int(iters), _ptr(A))
+    return A.reshape(2, 3), int(kind)
 
 
 def detect_real(img: np.ndarray, window: int, stride: int):

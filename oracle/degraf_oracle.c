@@ -414,8 +414,54 @@ typedef struct {
     double sigma1, sigma2;   /* robust-norm thresholds, intensity units */
     double eps_coarse;       /* stop a level > 0 when |delta| < eps_coarse (px of that level) */
     double eps_fine;         /* stop level 0 when |delta| < eps_fine */
-    double min_eig;          /* ill-conditioned when lambda_min(G0) / s^2 < min_eig */
+    double min_eig;          /* ill-conditioned when lambda_min(G0) / |support| < min_eig */
+    int cross;               /* adaptive cross-based support (or_cross_mask) instead of the square */
+    double tau;              /* its intensity threshold */
 } or_opts;
+
+/*
+ * Adaptive cross-based support region of a template (the support RLOF(IM-GM) uses, Section 3
+ * "Parameters"; defined in the tracker's citation).  Reading: the classic cross construction, on
+ * the template extended by one pixel, Tx of size (s + 2) x (s + 2) (offsets -r-1 .. r+1 from the
+ * point, index (ky + r + 1) (s + 2) + (kx + r + 1), s = 2r + 1):
+ *   the vertical arm of the centre runs up and down from it while each next pixel of the centre
+ *   column stays within tau of the centre value; every row the vertical arm covers gets a
+ *   horizontal arm, anchored on that row's centre-column pixel, running left and right while
+ *   each next pixel stays within tau of the anchor; the region is the union of the horizontal
+ *   arms (the anchors and the centre are always in; |difference| <= tau, so a non-finite value
+ *   ends an arm).
+ * The support (mask, s x s, 1 = in) keeps a support pixel when it and its four neighbours -- the
+ * stencil of its central-difference gradient -- all lie in the region, so no template gradient
+ * in the support straddles the region's edge.  Returns the number of support pixels.
+ */
+int or_cross_mask(const double *Tx, int s, double tau, uint8_t *mask)
+{
+    const int r = s / 2, e = s + 2, re = r + 1;
+    uint8_t *R = (uint8_t *)calloc((size_t)e * e, 1);
+    if (!R) return 0;
+    const double c = Tx[re * e + re];
+    int up = 0, down = 0;
+    while (up < re && fabs(Tx[(re - up - 1) * e + re] - c) <= tau) ++up;
+    while (down < re && fabs(Tx[(re + down + 1) * e + re] - c) <= tau) ++down;
+    for (int ky = -up; ky <= down; ++ky) {
+        const double *row = Tx + (ky + re) * e;
+        const double a = row[re];
+        int left = 0, right = 0;
+        while (left < re && fabs(row[re - left - 1] - a) <= tau) ++left;
+        while (right < re && fabs(row[re + right + 1] - a) <= tau) ++right;
+        for (int kx = -left; kx <= right; ++kx) R[(ky + re) * e + (kx + re)] = 1;
+    }
+    int count = 0;
+    for (int ky = -r; ky <= r; ++ky)
+        for (int kx = -r; kx <= r; ++kx) {
+            const int q = (ky + re) * e + (kx + re);
+            const uint8_t in = R[q] & R[q - 1] & R[q + 1] & R[q - e] & R[q + e];
+            mask[(ky + r) * s + (kx + r)] = in;
+            count += in;
+        }
+    free(R);
+    return count;
+}
 
 /*
  * Track one point p (level-0 pixel coordinates) from I0 to I1.
@@ -437,8 +483,8 @@ typedef struct {
  * Points outside the image (or not finite) are out of bounds with u = 0.
  */
 static void track_point(const pyr_t *P0, const pyr_t *P1, double px, double py, int L, int s,
-                        int iters, const or_opts *o, double *ux, double *uy, uint8_t *st,
-                        int32_t *it_count)
+                        int iters, const or_opts *o, double g0x, double g0y, int lstop, double *ux,
+                        double *uy, uint8_t *st, int32_t *it_count)
 {
     const int r = s / 2;
     const int W = P0->W[0], H = P0->H[0];
@@ -452,19 +498,21 @@ static void track_point(const pyr_t *P0, const pyr_t *P1, double px, double py, 
     double *T = (double *)malloc(sizeof(double) * npix);
     double *gxk = (double *)malloc(sizeof(double) * npix);
     double *gyk = (double *)malloc(sizeof(double) * npix);
+    uint8_t *M = (uint8_t *)malloc((size_t)npix);
+    double *Tx = (double *)malloc(sizeof(double) * (size_t)(s + 2) * (s + 2));
 
-    double gX = 0.0, gY = 0.0; /* guess carried from the coarser level, in level-l pixels */
+    double gX = g0x, gY = g0y; /* guess carried from the coarser level, in level-l pixels */
     double dX = 0.0, dY = 0.0;
     int conv = 0;
     int status = -1;
-    for (int l = L - 1; l >= 0; --l) {
+    for (int l = L - 1; l >= lstop; --l) {
         const double scale = ldexp(1.0, -l);
         const double plx = px * scale, ply = py * scale;
         const int Wl = P0->W[l], Hl = P0->H[l];
 
         /* template and its gradient: value of the bilinear interpolant of the border-replicated
          * level image, and central differences of that interpolant at +-1 px */
-        double a = 0.0, b = 0.0, c = 0.0; /* G0 = [[a, b], [b, c]] */
+        double a = 0.0, b = 0.0, c = 0.0; /* G0 = [[a, b], [b, c]] over the support */
         const double *I0l = P0->img[l];
         for (int ky = -r; ky <= r; ++ky)
             for (int kx = -r; kx <= r; ++kx) {
@@ -473,13 +521,26 @@ static void track_point(const pyr_t *P0, const pyr_t *P1, double px, double py, 
                 T[k] = or_bilinear(I0l, Wl, Hl, x, y);
                 gxk[k] = 0.5 * (or_bilinear(I0l, Wl, Hl, x + 1.0, y) - or_bilinear(I0l, Wl, Hl, x - 1.0, y));
                 gyk[k] = 0.5 * (or_bilinear(I0l, Wl, Hl, x, y + 1.0) - or_bilinear(I0l, Wl, Hl, x, y - 1.0));
+            }
+        /* support of this level: the square window, or its adaptive cross-based part */
+        int nsup = npix;
+        if (o->cross) {
+            for (int ky = -r - 1; ky <= r + 1; ++ky)
+                for (int kx = -r - 1; kx <= r + 1; ++kx)
+                    Tx[(ky + r + 1) * (s + 2) + (kx + r + 1)] = or_bilinear(I0l, Wl, Hl, plx + kx, ply + ky);
+            nsup = or_cross_mask(Tx, s, o->tau, M);
+        } else {
+            memset(M, 1, (size_t)npix);
+        }
+        for (int k = 0; k < npix; ++k)
+            if (M[k]) {
                 a += gxk[k] * gxk[k];
                 b += gxk[k] * gyk[k];
                 c += gyk[k] * gyk[k];
             }
         const double lam_min = 0.5 * (a + c) - sqrt(0.25 * (a - c) * (a - c) + b * b);
-        if (!(lam_min / (double)npix >= o->min_eig)) {
-            if (l == 0) { /* the full-resolution support cannot be tracked */
+        if (!(lam_min / (double)nsup >= o->min_eig)) {
+            if (l == lstop) { /* the last level's support cannot be tracked */
                 *ux = gX;
                 *uy = gY;
                 status = OR_ST_ILL_CONDITIONED;
@@ -504,6 +565,7 @@ static void track_point(const pyr_t *P0, const pyr_t *P1, double px, double py, 
             for (int ky = -r; ky <= r; ++ky)
                 for (int kx = -r; kx <= r; ++kx) {
                     int k = (ky + r) * s + (kx + r);
+                    if (!M[k]) continue;
                     double J = or_bilinear(P1->img[l], Wl, Hl, plx + kx + gX + dX, ply + ky + gY + dY);
                     double res = J - T[k];
                     double w = irls_weight(res, o->sigma1, o->sigma2);
@@ -523,6 +585,7 @@ static void track_point(const pyr_t *P0, const pyr_t *P1, double px, double py, 
                 for (int ky = -r; ky <= r; ++ky)
                     for (int kx = -r; kx <= r; ++kx) {
                         int k = (ky + r) * s + (kx + r);
+                        if (!M[k]) continue;
                         double J = or_bilinear(P1->img[l], Wl, Hl, plx + kx + gX + dX, ply + ky + gY + dY);
                         double res = J - T[k];
                         bx -= res * gxk[k];
@@ -550,7 +613,7 @@ static void track_point(const pyr_t *P0, const pyr_t *P1, double px, double py, 
             status = OR_ST_NOT_CONVERGED;
             break;
         }
-        if (l > 0) {
+        if (l > lstop) {
             gX = 2.0 * (gX + dX);
             gY = 2.0 * (gY + dY);
         }
@@ -560,6 +623,8 @@ static void track_point(const pyr_t *P0, const pyr_t *P1, double px, double py, 
         *uy = gY + dY;
         if (!conv)
             status = OR_ST_NOT_CONVERGED;
+        else if (lstop > 0) /* a pass that stops above level 0 reports the step test only */
+            status = OR_ST_CONVERGED;
         else {
             double qx = px + *ux, qy = py + *uy;
             status = (qx >= 0.0 && qy >= 0.0 && qx <= W - 1 && qy <= H - 1) ? OR_ST_CONVERGED
@@ -570,6 +635,8 @@ static void track_point(const pyr_t *P0, const pyr_t *P1, double px, double py, 
     free(T);
     free(gxk);
     free(gyk);
+    free(M);
+    free(Tx);
 }
 
 /* Solves the n x n system A x = b (A row-major, both overwritten) by Gaussian elimination with
@@ -660,8 +727,8 @@ static double det4(const double *M)
  * returned in illum.
  */
 static void track_point_illum(const pyr_t *P0, const pyr_t *P1, double px, double py, int L, int s,
-                              int iters, const or_opts *o, double *ux, double *uy, uint8_t *st,
-                              int32_t *it_count, double *illum)
+                              int iters, const or_opts *o, double g0x, double g0y, int lstop, double *ux,
+                              double *uy, uint8_t *st, int32_t *it_count, double *illum)
 {
     const int r = s / 2;
     const int W = P0->W[0], H = P0->H[0];
@@ -677,12 +744,14 @@ static void track_point_illum(const pyr_t *P0, const pyr_t *P1, double px, doubl
     double *T = (double *)malloc(sizeof(double) * npix);
     double *gxk = (double *)malloc(sizeof(double) * npix);
     double *gyk = (double *)malloc(sizeof(double) * npix);
+    uint8_t *M = (uint8_t *)malloc((size_t)npix);
+    double *Tx = (double *)malloc(sizeof(double) * (size_t)(s + 2) * (s + 2));
 
-    double gX = 0.0, gY = 0.0, dX = 0.0, dY = 0.0;
+    double gX = g0x, gY = g0y, dX = 0.0, dY = 0.0;
     double m = 0.0, c = 0.0; /* gain change and offset, carried across levels */
     int conv = 0;
     int status = -1;
-    for (int l = L - 1; l >= 0; --l) {
+    for (int l = L - 1; l >= lstop; --l) {
         const double scale = ldexp(1.0, -l);
         const double plx = px * scale, ply = py * scale;
         const int Wl = P0->W[l], Hl = P0->H[l];
@@ -697,13 +766,25 @@ static void track_point_illum(const pyr_t *P0, const pyr_t *P1, double px, doubl
                 T[k] = or_bilinear(I0l, Wl, Hl, x, y);
                 gxk[k] = 0.5 * (or_bilinear(I0l, Wl, Hl, x + 1.0, y) - or_bilinear(I0l, Wl, Hl, x - 1.0, y));
                 gyk[k] = 0.5 * (or_bilinear(I0l, Wl, Hl, x, y + 1.0) - or_bilinear(I0l, Wl, Hl, x, y - 1.0));
+            }
+        int nsup = npix;
+        if (o->cross) {
+            for (int ky = -r - 1; ky <= r + 1; ++ky)
+                for (int kx = -r - 1; kx <= r + 1; ++kx)
+                    Tx[(ky + r + 1) * (s + 2) + (kx + r + 1)] = or_bilinear(I0l, Wl, Hl, plx + kx, ply + ky);
+            nsup = or_cross_mask(Tx, s, o->tau, M);
+        } else {
+            memset(M, 1, (size_t)npix);
+        }
+        for (int k = 0; k < npix; ++k)
+            if (M[k]) {
                 a2 += gxk[k] * gxk[k];
                 b2 += gxk[k] * gyk[k];
                 c2 += gyk[k] * gyk[k];
             }
         const double lam_min = 0.5 * (a2 + c2) - sqrt(0.25 * (a2 - c2) * (a2 - c2) + b2 * b2);
-        if (!(lam_min / (double)npix >= o->min_eig)) {
-            if (l == 0) {
+        if (!(lam_min / (double)nsup >= o->min_eig)) {
+            if (l == lstop) {
                 *ux = gX;
                 *uy = gY;
                 status = OR_ST_ILL_CONDITIONED;
@@ -726,6 +807,7 @@ static void track_point_illum(const pyr_t *P0, const pyr_t *P1, double px, doubl
             for (int ky = -r; ky <= r; ++ky)
                 for (int kx = -r; kx <= r; ++kx) {
                     int k = (ky + r) * s + (kx + r);
+                    if (!M[k]) continue;
                     double J = or_bilinear(P1->img[l], Wl, Hl, plx + kx + gX + dX, ply + ky + gY + dY);
                     double res = J - (1.0 + m) * T[k] - c;
                     double w = irls_weight(res, o->sigma1, o->sigma2);
@@ -765,7 +847,7 @@ static void track_point_illum(const pyr_t *P0, const pyr_t *P1, double px, doubl
             status = OR_ST_NOT_CONVERGED;
             break;
         }
-        if (l > 0) {
+        if (l > lstop) {
             gX = 2.0 * (gX + dX);
             gY = 2.0 * (gY + dY);
         }
@@ -775,6 +857,8 @@ static void track_point_illum(const pyr_t *P0, const pyr_t *P1, double px, doubl
         *uy = gY + dY;
         if (!conv || !(1.0 + m >= 0.5 && 1.0 + m <= 2.0))
             status = OR_ST_NOT_CONVERGED;
+        else if (lstop > 0)
+            status = OR_ST_CONVERGED;
         else {
             double qx = px + *ux, qy = py + *uy;
             status = (qx >= 0.0 && qy >= 0.0 && qx <= W - 1 && qy <= H - 1) ? OR_ST_CONVERGED
@@ -787,6 +871,87 @@ static void track_point_illum(const pyr_t *P0, const pyr_t *P1, double px, doubl
     free(T);
     free(gxk);
     free(gyk);
+    free(M);
+    free(Tx);
+}
+
+/*
+ * Global motion prior (the "GM" of RLOF(IM-GM), Section 3 "Parameters"; defined in the tracker's
+ * citation).  Reading: one global affine motion of the frame, fitted robustly to sample motions
+ * v_i at positions p_i (level-0 pixels), v ~ A (x - cx, y - cy, 1)^T with A 2 x 3:
+ *   weighted least squares with weights w_i (1 for every sample to start), then `iters` times:
+ *   residual e_i = |v_i - A p~_i|_2, Tukey biweight w_i = (1 - (e_i / c)^2)^2 for e_i < c, else 0,
+ *   c = 4.685 scale, and the weighted least squares again.
+ *   When fewer than 3 samples carry weight, or the weighted position covariance C has
+ *   det C <= 1e-4 (tr C)^2, the model is the weighted mean motion (a translation); with no
+ *   sample of positive weight the previous model stays (none at the start: A = 0).
+ * pts, mot: [n][2]; use: [n], nonzero for a sample.  A: out [2][3] row-major.
+ * Returns 2 (affine), 1 (translation) or 0 (no model, A = 0).
+ */
+int or_gm_fit(const double *pts, const double *mot, const uint8_t *use, int64_t n, double cx, double cy,
+              double scale, int iters, double *A)
+{
+    for (int k = 0; k < 6; ++k) A[k] = 0.0;
+    double *w = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!w) return 0;
+    for (int64_t i = 0; i < n; ++i) w[i] = use[i] ? 1.0 : 0.0;
+    const double c = 4.685 * scale;
+    int kind = 0;
+    for (int pass = 0; pass <= iters; ++pass) {
+        if (pass > 0)
+            for (int64_t i = 0; i < n; ++i) {
+                if (!use[i]) continue;
+                const double x = pts[2 * i] - cx, y = pts[2 * i + 1] - cy;
+                const double ex = mot[2 * i] - (A[0] * x + A[1] * y + A[2]);
+                const double ey = mot[2 * i + 1] - (A[3] * x + A[4] * y + A[5]);
+                const double e = sqrt(ex * ex + ey * ey);
+                const double t = e / c;
+                w[i] = (e < c) ? (1.0 - t * t) * (1.0 - t * t) : 0.0;
+            }
+        double S = 0, Sx = 0, Sy = 0, Sxx = 0, Sxy = 0, Syy = 0;
+        double Su = 0, Sxu = 0, Syu = 0, Sv = 0, Sxv = 0, Syv = 0;
+        int64_t nz = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (!(w[i] > 0.0)) continue;
+            const double x = pts[2 * i] - cx, y = pts[2 * i + 1] - cy, u = mot[2 * i], v = mot[2 * i + 1];
+            ++nz;
+            S += w[i];
+            Sx += w[i] * x;
+            Sy += w[i] * y;
+            Sxx += w[i] * x * x;
+            Sxy += w[i] * x * y;
+            Syy += w[i] * y * y;
+            Su += w[i] * u;
+            Sxu += w[i] * x * u;
+            Syu += w[i] * y * u;
+            Sv += w[i] * v;
+            Sxv += w[i] * x * v;
+            Syv += w[i] * y * v;
+        }
+        if (nz == 0) break; /* keep the previous model */
+        const double mx = Sx / S, my = Sy / S;
+        const double Cxx = Sxx / S - mx * mx, Cxy = Sxy / S - mx * my, Cyy = Syy / S - my * my;
+        const double trC = Cxx + Cyy, detC = Cxx * Cyy - Cxy * Cxy;
+        if (nz < 3 || !(detC > 1e-4 * trC * trC)) {
+            A[0] = A[1] = A[3] = A[4] = 0.0;
+            A[2] = Su / S;
+            A[5] = Sv / S;
+            kind = 1;
+            continue;
+        }
+        double N[9] = {Sxx, Sxy, Sx, Sxy, Syy, Sy, Sx, Sy, S}, N2[9];
+        double bu[3] = {Sxu, Syu, Su}, bv[3] = {Sxv, Syv, Sv}, au[3], av[3];
+        memcpy(N2, N, sizeof(N));
+        const int e1 = solve_dense(N, bu, 3, au), e2 = solve_dense(N2, bv, 3, av);
+        if (e1 != 0 || e2 != 0) break;
+        for (int k = 0; k < 3; ++k) {
+            A[k] = au[k];
+            A[3 + k] = av[k];
+        }
+        kind = 2;
+    }
+    free(w);
+    return kind;
 }
 
 /*
@@ -795,18 +960,25 @@ static void track_point_illum(const pyr_t *P0, const pyr_t *P1, double px, doubl
  * coarsest level first (0 where the point stopped before reaching that level).
  * illum: 0 = plain tracker (track_point); 1 = illumination model (track_point_illum), whose
  * final (m, c) go to illum_out (nullable, [n][2]).
+ * cross: adaptive cross-based supports with threshold tau (or_cross_mask) at every level.
+ * gm: global motion prior.  A first pass tracks every point on the coarsest level alone from zero
+ * motion (same tracker, options and iteration limit); the points it reports converged there give
+ * the samples (motion times 2^(L-1), at their level-0 positions) of or_gm_fit about the image
+ * centre ((W-1)/2, (H-1)/2), scale 2^(L-1) px (one coarsest-level pixel), 10 reweightings; the
+ * tracking proper then starts every point on the coarsest level from the model's motion at its
+ * position (divided by 2^(L-1)) instead of zero.  gm_out (nullable, [6]) receives the model.
  */
 int or_track(const void *I0, const void *I1, int dtype, int W, int H, int64_t pitch, const double *pts,
              int64_t n, int levels, int support, int iters, double sigma1, double sigma2,
-             double eps_coarse, double eps_fine, double min_eig, int illum, double *flow, uint8_t *status,
-             int32_t *iters_out, double *illum_out, int nthreads)
+             double eps_coarse, double eps_fine, double min_eig, int illum, int cross, double tau, int gm,
+             double *flow, uint8_t *status, int32_t *iters_out, double *illum_out, double *gm_out, int nthreads)
 {
     if (!I0 || !I1 || (n > 0 && (!pts || !flow || !status))) return OR_ERR_ARG;
     if (W <= 0 || H <= 0 || levels < 1 || levels > 16 || support < 1 || (support % 2) == 0 || iters < 1)
         return OR_ERR_ARG;
     if (dtype != 0 && dtype != 1) return OR_ERR_ARG;
     if (nthreads < 1) nthreads = 1;
-    or_opts o = {sigma1, sigma2, eps_coarse, eps_fine, min_eig};
+    or_opts o = {sigma1, sigma2, eps_coarse, eps_fine, min_eig, cross, tau};
     pyr_t P0, P1;
     int rc0 = pyr_build(&P0, I0, dtype, W, H, pitch, levels);
     int rc1 = pyr_build(&P1, I1, dtype, W, H, pitch, levels);
@@ -816,21 +988,56 @@ int or_track(const void *I0, const void *I1, int dtype, int W, int H, int64_t pi
         return OR_ERR_MEM;
     }
     if (iters_out) memset(iters_out, 0, sizeof(int32_t) * (size_t)n * levels);
+    const double top = ldexp(1.0, levels - 1); /* level-0 pixels per coarsest-level pixel */
+    double *init = (double *)calloc((size_t)(n > 0 ? 2 * n : 2), sizeof(double));
+    double A[6] = {0, 0, 0, 0, 0, 0};
+    if (gm && n > 0) {
+        double *mot = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+        uint8_t *st1 = (uint8_t *)malloc((size_t)n);
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 16)
+        for (int64_t i = 0; i < n; ++i) {
+            double mc[2];
+            if (illum)
+                track_point_illum(&P0, &P1, pts[2 * i], pts[2 * i + 1], levels, support, iters, &o, 0.0, 0.0,
+                                  levels - 1, &mot[2 * i], &mot[2 * i + 1], &st1[i], NULL, mc);
+            else
+                track_point(&P0, &P1, pts[2 * i], pts[2 * i + 1], levels, support, iters, &o, 0.0, 0.0,
+                            levels - 1, &mot[2 * i], &mot[2 * i + 1], &st1[i], NULL);
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            st1[i] = (st1[i] == OR_ST_CONVERGED && isfinite(mot[2 * i]) && isfinite(mot[2 * i + 1])) ? 1 : 0;
+            mot[2 * i] *= top;
+            mot[2 * i + 1] *= top;
+        }
+        or_gm_fit(pts, mot, st1, n, 0.5 * (W - 1), 0.5 * (H - 1), top, 10, A);
+        for (int64_t i = 0; i < n; ++i) {
+            const double x = pts[2 * i] - 0.5 * (W - 1), y = pts[2 * i + 1] - 0.5 * (H - 1);
+            init[2 * i] = (A[0] * x + A[1] * y + A[2]) / top;
+            init[2 * i + 1] = (A[3] * x + A[4] * y + A[5]) / top;
+        }
+        free(mot);
+        free(st1);
+    }
+    if (gm_out)
+        for (int k = 0; k < 6; ++k) gm_out[k] = A[k];
 #pragma omp parallel for num_threads(nthreads) schedule(dynamic, 16)
     for (int64_t i = 0; i < n; ++i) {
         if (illum) {
             double mc[2];
-            track_point_illum(&P0, &P1, pts[2 * i], pts[2 * i + 1], levels, support, iters, &o, &flow[2 * i],
-                              &flow[2 * i + 1], &status[i], iters_out ? &iters_out[i * levels] : NULL, mc);
+            track_point_illum(&P0, &P1, pts[2 * i], pts[2 * i + 1], levels, support, iters, &o, init[2 * i],
+                              init[2 * i + 1], 0, &flow[2 * i], &flow[2 * i + 1], &status[i],
+                              iters_out ? &iters_out[i * levels] : NULL, mc);
             if (illum_out) {
                 illum_out[2 * i] = mc[0];
                 illum_out[2 * i + 1] = mc[1];
             }
         } else {
-            track_point(&P0, &P1, pts[2 * i], pts[2 * i + 1], levels, support, iters, &o, &flow[2 * i],
-                        &flow[2 * i + 1], &status[i], iters_out ? &iters_out[i * levels] : NULL);
+            track_point(&P0, &P1, pts[2 * i], pts[2 * i + 1], levels, support, iters, &o, init[2 * i],
+                        init[2 * i + 1], 0, &flow[2 * i], &flow[2 * i + 1], &status[i],
+                        iters_out ? &iters_out[i * levels] : NULL);
         }
     }
+    free(init);
     pyr_free(&P0);
     pyr_free(&P1);
     return OR_OK;

@@ -14,7 +14,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PIN_FILES = ["tests/test_oracle_degraf.py", "tests/test_oracle_pyramid.py", "tests/test_oracle_rlof.py",
-             "tests/test_oracle_illum.py", "tests/test_oracle_grad.py", "tests/test_oracle_detect_grad.py"]
+             "tests/test_oracle_illum.py", "tests/test_oracle_grad.py", "tests/test_oracle_detect_grad.py",
+             "tests/test_oracle_next3.py"]
 
 # (name, original text, planted text): the first occurrence in degraf_oracle.c is replaced
 MUTATIONS = [
@@ -44,6 +45,17 @@ MUTATIONS = [
      "double res = J - (1.0 + m) * T[k] - c;", "double res = J - (1.0 + m) * T[k] + c;"),
     ("adjoint without the template-gradient term of dI0",
      "dI0[ixp[t]] += cx * wxp[t];", "(void)cx;"),
+    ("cross arms that stop at a difference equal to the threshold",
+     "while (left < re && fabs(row[re - left - 1] - a) <= tau) ++left;",
+     "while (left < re && fabs(row[re - left - 1] - a) < tau) ++left;"),
+    ("cross support without the erosion by the gradient stencil",
+     "const uint8_t in = R[q] & R[q - 1] & R[q + 1] & R[q - e] & R[q + e];", "const uint8_t in = R[q];"),
+    ("trackability divided by the window instead of the support",
+     "if (!(lam_min / (double)nsup >= o->min_eig)) {", "if (!(lam_min / (double)npix >= o->min_eig)) {"),
+    ("global fit weights without the square of the Tukey factor",
+     "w[i] = (e < c) ? (1.0 - t * t) * (1.0 - t * t) : 0.0;", "w[i] = (e < c) ? (1.0 - t * t) : 0.0;"),
+    ("global prior start not scaled to the coarsest level",
+     "init[2 * i] = (A[0] * x + A[1] * y + A[2]) / top;", "init[2 * i] = (A[0] * x + A[1] * y + A[2]);"),
 ]
 
 # the same for the dense interpolation's oracle, checked by its own pins
