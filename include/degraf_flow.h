@@ -6,7 +6,8 @@
  * and efficient sparse-to-dense optical flow estimation" (2019), Section 2: points are detected
  * on a uniform grid of gradient centroids in the first frame ("Point detection", Eq. 1-2 and the
  * selection rule) and tracked into the next frame with robust local optical flow ("Sparse point
- * tracking").  The dense interpolation stage of that pipeline is not part of this library.
+ * tracking"; the RLOF(IM-GM) options of Section 3 "Parameters" as flags), and the tracked points
+ * can be interpolated into a dense field ("Interpolation", dgf_epic).
  *
  * Conventions shared by every call:
  *   - Every data pointer is a DEVICE pointer owned by the caller.  The library never allocates
@@ -78,10 +79,11 @@ typedef struct {
                          infinite sigma2 is rejected (DGF_ERR_INVALID_ARG)               */
     float eps_coarse; /* a level > 0 stops when |step|_2 < eps_coarse px (default 1e-2) */
     float eps_fine;   /* level 0 stops when |step|_2 < eps_fine px (default 1e-4)       */
-    float min_eig;    /* a level with lambda_min(G0)/s^2 < min_eig runs no iteration and
-                         passes its guess on; at level 0 the point is ill-conditioned
-                         (default 1e-4 * 255^2)                                          */
-    int32_t flags;    /* 0, or DGF_TRACK_ILLUM                                          */
+    float min_eig;    /* a level with lambda_min(G0)/|support| < min_eig runs no iteration
+                         and passes its guess on; at level 0 the point is ill-conditioned
+                         (default 1e-4 * 255^2); |support| = s^2 for the square window  */
+    int32_t flags;    /* 0, or any of DGF_TRACK_ILLUM, DGF_TRACK_CROSS, DGF_TRACK_GLOBAL  */
+    float cross_tau;  /* DGF_TRACK_CROSS: arm threshold, intensity units (default 25)   */
 } dgf_track_opts;
 
 /* dgf_track_opts.flags: match each support under a per-point gain and offset estimated with
@@ -94,6 +96,53 @@ typedef struct {
  * dgf_track_backward and dgf_batch_backward differentiate it given the forward call's
  * (gain, offset) (illum_out). */
 #define DGF_TRACK_ILLUM 1
+
+/* dgf_track_opts.flags: adaptive cross-based supports (the support region RLOF(IM-GM) uses,
+ * Section 3 "Parameters"; defined in its citation).  At every level the region is decided on the
+ * level image's own pixels at floor(p_l) + k, k in [-r-1, r+1]^2 (border replicated): the vertical
+ * arm of the centre runs up and down while each next centre-column pixel stays within cross_tau
+ * of the centre, every row it covers gets a horizontal arm around its centre-column pixel (within
+ * cross_tau of that pixel), and the support keeps the window offsets that lie, with their four
+ * neighbours (the stencil of the template gradient), in the union of those arms.  Every support sum runs over the kept pixels
+ * and the trackability test divides by their number.  Supports of the row-run kernel only
+ * (5, 7, 9, 11, 15, 21; else DGF_ERR_UNSUPPORTED); not differentiated (dgf_track_backward and
+ * dgf_batch_backward reject it). */
+#define DGF_TRACK_CROSS 2
+
+/* dgf_track_opts.flags: global-motion prior (the "GM" of RLOF(IM-GM), Section 3 "Parameters";
+ * defined in its citation).  A first pass tracks every point on the coarsest level alone from zero
+ * motion; the points that stop there on the step test give samples (their motion at their
+ * level-0 position) of one global affine motion v = A (x - (W-1)/2, y - (H-1)/2, 1)^T, fitted by
+ * least squares and then ten Tukey-biweight reweightings (scale 4.685 coarsest-level pixels);
+ * with fewer than 3 samples or collinear positions the model is their weighted mean motion, with
+ * none it is zero.  The tracking proper then starts each point on the coarsest level from
+ * A p~ / 2^(levels-1) instead of zero.  All of it runs on the stream (no host synchronisation);
+ * the model lives in the workspace (dgf_track_workspace_bytes covers it, also for levels = 1).
+ * Row-run supports only, as DGF_TRACK_CROSS.  After the call the fitted model (6 doubles, A
+ * row-major) sits at byte offset 2 * dgf_pyramid_layout(width, height, levels, dtype) of the
+ * workspace (batch plans keep theirs inside the plan).  The gradient at a converged point does not
+ * depend on where the iteration started, so the adjoint accepts the flag. */
+#define DGF_TRACK_GLOBAL 4
+
+/* Workspace bytes of dgf_gm_fit (a constant: the fit keeps at most 256 partial-sum slots). */
+size_t dgf_gm_workspace_bytes(void);
+
+/* Global affine motion of one frame from tracked points: the fit of the DGF_TRACK_GLOBAL prior
+ * (Section 3 "Parameters", the "GM" of RLOF(IM-GM); defined in its citation), on any tracking result.
+ * Samples are the points with status DGF_ST_CONVERGED and finite flow; v = A p~ with
+ * p~ = (x - (width-1)/2, y - (height-1)/2, 1), fitted by least squares and then ten Tukey-biweight
+ * reweightings, w = (1 - (e / c)^2)^2 for a residual norm e < c = 4.685 scale, else 0.  With fewer
+ * than 3 weighted samples, or weighted positions whose covariance C has det C <= 1e-4 (tr C)^2, a
+ * pass's model is the weighted mean motion; a pass with no weighted sample (or a singular system)
+ * keeps the model before it, and with no sample at all A = 0.  FP64 throughout.
+ *   points, flow  device, [n][2] float (flow in the same pixels as the points)
+ *   status        device, [n]
+ *   scale         > 0, finite: the Tukey scale in pixels (the tracker uses 2^(levels-1))
+ *   workspace     device, >= dgf_gm_workspace_bytes() bytes
+ *   model         device, 6 doubles: A row-major (2 x 3), written on `stream`
+ * Errors: DGF_ERR_INVALID_ARG, DGF_ERR_WORKSPACE, DGF_ERR_HIP.  Nothing is launched on an error. */
+int dgf_gm_fit(const float *points, const float *flow, const uint8_t *status, int64_t n, int32_t width,
+               int32_t height, double scale, void *workspace, size_t ws_bytes, double *model, void *stream);
 
 /* ---- library ----------------------------------------------------------------------------------- */
 

@@ -422,8 +422,9 @@ typedef struct {
 /*
  * Adaptive cross-based support region of a template (the support RLOF(IM-GM) uses, Section 3
  * "Parameters"; defined in the tracker's citation).  Reading: the classic cross construction, on
- * the template extended by one pixel, Tx of size (s + 2) x (s + 2) (offsets -r-1 .. r+1 from the
- * point, index (ky + r + 1) (s + 2) + (kx + r + 1), s = 2r + 1):
+ * a patch one pixel wider than the support on each side, Tx of size (s + 2) x (s + 2) (offsets
+ * -r-1 .. r+1 from the point, index (ky + r + 1) (s + 2) + (kx + r + 1), s = 2r + 1; the tracker
+ * fills it with cross_pixels):
  *   the vertical arm of the centre runs up and down from it while each next pixel of the centre
  *   column stays within tau of the centre value; every row the vertical arm covers gets a
  *   horizontal arm, anchored on that row's centre-column pixel, running left and right while
@@ -461,6 +462,24 @@ int or_cross_mask(const double *Tx, int s, double tau, uint8_t *mask)
         }
     free(R);
     return count;
+}
+
+/*
+ * The (s + 2)^2 values the cross construction runs on: the level image's own pixels at
+ * floor(p_l) + k, k in [-r-1, r+1]^2, border replicated (the pixel at the top-left of the cell each
+ * template sample interpolates in).  Reading: the cross region is a segmentation of the image
+ * around the point, so it is taken on the image's pixel grid; for integer frames every comparison
+ * with tau is then exact, where differences of interpolated samples that share one set of bilinear
+ * weights land exactly on an integer tau wherever the four underlying pixel differences agree, and
+ * rounding would decide.
+ */
+static void cross_pixels(const double *I, int W, int H, double plx, double ply, int r, double *Tx)
+{
+    const int x0 = (int)floor(plx), y0 = (int)floor(ply), e = 2 * r + 3;
+    for (int ky = -r - 1; ky <= r + 1; ++ky)
+        for (int kx = -r - 1; kx <= r + 1; ++kx)
+            Tx[(ky + r + 1) * e + (kx + r + 1)] =
+                I[(int64_t)clampi(y0 + ky, 0, H - 1) * W + clampi(x0 + kx, 0, W - 1)];
 }
 
 /*
@@ -525,9 +544,7 @@ static void track_point(const pyr_t *P0, const pyr_t *P1, double px, double py, 
         /* support of this level: the square window, or its adaptive cross-based part */
         int nsup = npix;
         if (o->cross) {
-            for (int ky = -r - 1; ky <= r + 1; ++ky)
-                for (int kx = -r - 1; kx <= r + 1; ++kx)
-                    Tx[(ky + r + 1) * (s + 2) + (kx + r + 1)] = or_bilinear(I0l, Wl, Hl, plx + kx, ply + ky);
+            cross_pixels(I0l, Wl, Hl, plx, ply, r, Tx);
             nsup = or_cross_mask(Tx, s, o->tau, M);
         } else {
             memset(M, 1, (size_t)npix);
@@ -721,9 +738,14 @@ static double det4(const double *M)
  *   (both with the current m), stop the level when |delta_d|_2 < eps_l.
  * m and c start at 0 on the coarsest level and carry over unchanged between levels (pyramid levels
  * are weighted averages, under which a gain and an offset stay the same).  Template, gradient,
- * flat-level rule, level propagation of g and the statuses are those of track_point, except that
- * a point whose final gain 1 + m lies outside [1/2, 2] is NOT_CONVERGED: such a match explains the
- * support by a contrast change (or inversion) instead of a motion.  (m, c) of the last level are
+ * level propagation of g and the statuses are those of track_point, except that
+ *   - a support of fewer than four pixels (fewer than the unknowns) is flat as well;
+ *   - a point whose gain 1 + m has left [1/4, 4] at the end of a coarse level (one it iterated
+ *     on) ends NOT_CONVERGED with a NaN flow, as after a non-finite step: carried on, such
+ *     iterates drift towards gain 0, where the motion drops out of the model and the steps in d
+ *     grow without bound;
+ *   - a point whose final gain lies outside [1/2, 2] is NOT_CONVERGED: such a match explains the
+ *     support by a contrast change (or inversion) instead of a motion.  (m, c) of the last level are
  * returned in illum.
  */
 static void track_point_illum(const pyr_t *P0, const pyr_t *P1, double px, double py, int L, int s,
@@ -769,9 +791,7 @@ static void track_point_illum(const pyr_t *P0, const pyr_t *P1, double px, doubl
             }
         int nsup = npix;
         if (o->cross) {
-            for (int ky = -r - 1; ky <= r + 1; ++ky)
-                for (int kx = -r - 1; kx <= r + 1; ++kx)
-                    Tx[(ky + r + 1) * (s + 2) + (kx + r + 1)] = or_bilinear(I0l, Wl, Hl, plx + kx, ply + ky);
+            cross_pixels(I0l, Wl, Hl, plx, ply, r, Tx);
             nsup = or_cross_mask(Tx, s, o->tau, M);
         } else {
             memset(M, 1, (size_t)npix);
@@ -783,7 +803,8 @@ static void track_point_illum(const pyr_t *P0, const pyr_t *P1, double px, doubl
                 c2 += gyk[k] * gyk[k];
             }
         const double lam_min = 0.5 * (a2 + c2) - sqrt(0.25 * (a2 - c2) * (a2 - c2) + b2 * b2);
-        if (!(lam_min / (double)nsup >= o->min_eig)) {
+        /* four unknowns need at least four support pixels (fewer make the 4 x 4 system singular) */
+        if (!(lam_min / (double)nsup >= o->min_eig) || nsup < 4) {
             if (l == lstop) {
                 *ux = gX;
                 *uy = gY;
@@ -841,6 +862,7 @@ static void track_point_illum(const pyr_t *P0, const pyr_t *P1, double px, doubl
             }
         }
         if (it_count) it_count[L - 1 - l] = (it > iters) ? iters : it;
+        if (!bad && l > lstop && !(1.0 + m >= 0.25 && 1.0 + m <= 4.0)) bad = 1; /* runaway gain */
         if (bad) {
             *ux = NAN;
             *uy = NAN;

@@ -14,6 +14,8 @@ LIB_PATH = os.path.join(HERE, "libdegraf_flow.so")
 DGF_OK = 0
 DGF_U8, DGF_F32 = 0, 1
 DGF_TRACK_ILLUM = 1
+DGF_TRACK_CROSS = 2
+DGF_TRACK_GLOBAL = 4
 DGF_MAX_LEVELS = 12
 DGF_ERR_SCRATCH = -6
 DGF_TRACK_STATIC_MAX_BYTES = 16 << 20
@@ -27,7 +29,8 @@ class DgfImage(ctypes.Structure):
 
 class DgfTrackOpts(ctypes.Structure):
     _fields_ = [("sigma1", ctypes.c_float), ("sigma2", ctypes.c_float), ("eps_coarse", ctypes.c_float),
-                ("eps_fine", ctypes.c_float), ("min_eig", ctypes.c_float), ("flags", ctypes.c_int32)]
+                ("eps_fine", ctypes.c_float), ("min_eig", ctypes.c_float), ("flags", ctypes.c_int32),
+                ("cross_tau", ctypes.c_float)]
 
 
 class DgfPairDesc(ctypes.Structure):
@@ -64,6 +67,8 @@ SIGNATURES = {
     "dgf_pyramid_layout": (SZ, [I32, I32, I32, I32, P, P]),
     "dgf_pyramid": (ctypes.c_int, [IMG, I32, P, SZ, P]),
     "dgf_track_workspace_bytes": (SZ, [I32, I32, I32, I32]),
+    "dgf_gm_workspace_bytes": (SZ, []),
+    "dgf_gm_fit": (ctypes.c_int, [P, P, P, I64, I32, I32, ctypes.c_double, P, SZ, P, P]),
     "dgf_track": (ctypes.c_int, [IMG, IMG, P, I64, I32, I32, I32, OPTS, P, SZ, P, P, P, P, P]),
     "dgf_track_static": (ctypes.c_int, [IMG, IMG, P, I64, I32, I32, I32, OPTS, P, P, P, P, P]),
     "dgf_track_pyramids": (ctypes.c_int, [IMG, IMG, I32, P, SZ, P]),

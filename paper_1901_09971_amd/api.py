@@ -9,7 +9,7 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import DGF_F32, DGF_TRACK_ILLUM, DGF_U8, DgfEpicOpts, DgfImage, DgfTrackOpts, check, lib
+from ._lib import DGF_F32, DGF_TRACK_CROSS, DGF_TRACK_GLOBAL, DGF_TRACK_ILLUM, DGF_U8, DgfEpicOpts, DgfImage, DgfTrackOpts, check, lib
 
 
 @dataclass
@@ -21,10 +21,17 @@ class TrackOpts:
     eps_fine: float = 1e-4
     min_eig: float = 1e-4 * 255.0 * 255.0
     illum: bool = False  # per-point gain and offset estimated with the flow (DGF_TRACK_ILLUM)
+    cross: bool = False  # adaptive cross-based supports (DGF_TRACK_CROSS)
+    global_motion: bool = False  # global affine prior for the coarsest level (DGF_TRACK_GLOBAL)
+    cross_tau: float = 25.0  # arm threshold of the cross-based supports, intensity units
+
+    def flags(self) -> int:
+        return ((DGF_TRACK_ILLUM if self.illum else 0) | (DGF_TRACK_CROSS if self.cross else 0)
+                | (DGF_TRACK_GLOBAL if self.global_motion else 0))
 
     def to_c(self) -> DgfTrackOpts:
-        return DgfTrackOpts(self.sigma1, self.sigma2, self.eps_coarse, self.eps_fine, self.min_eig,
-                            DGF_TRACK_ILLUM if self.illum else 0)
+        return DgfTrackOpts(self.sigma1, self.sigma2, self.eps_coarse, self.eps_fine, self.min_eig, self.flags(),
+                            self.cross_tau)
 
 
 def _stream() -> ctypes.c_void_p:
@@ -111,10 +118,14 @@ def track_workspace_bytes(width: int, height: int, levels: int, dtype: int) -> i
 
 def track(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, levels: int, support: int, iters: int,
           opts: TrackOpts | None = None, return_iters: bool = False, workspace: torch.Tensor | None = None,
-          return_illum: bool = False):
+          return_illum: bool = False, return_gm: bool = False):
     """Track ``points`` (float32 [n, 2] device) from I0 to I1.  Returns (flow float32 [n, 2],
-    status uint8 [n]), then the per-point iteration count (int32 [n]) if ``return_iters`` and the
-    per-point (gain m, offset c) (float32 [n, 2], needs ``opts.illum``) if ``return_illum``."""
+    status uint8 [n]), then the per-point iteration count (int32 [n]) if ``return_iters``, the
+    per-point (gain m, offset c) (float32 [n, 2], needs ``opts.illum``) if ``return_illum`` and the
+    fitted global affine motion (float64 [2, 3] device, needs ``opts.global_motion``) if
+    ``return_gm``."""
+    if return_gm and not (opts is not None and opts.global_motion):
+        raise ValueError("return_gm needs opts.global_motion")
     a, b = _image(I0, "I0"), _image(I1, "I1")
     if points.dtype != torch.float32 or points.dim() != 2 or points.shape[1] != 2 or not points.is_cuda:
         raise ValueError("points: expected a float32 [n, 2] device tensor")
@@ -136,7 +147,27 @@ def track(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, levels: int,
         out += (its,)
     if return_illum:
         out += (ill,)
+    if return_gm:
+        # the model sits right after both pyramids in the workspace
+        at = 2 * pyramid_layout(a.width, a.height, levels, a.dtype)[0]
+        out += (workspace[at:at + 48].clone().view(torch.float64).view(2, 3),)
     return out
+
+
+def gm_fit(points: torch.Tensor, flow: torch.Tensor, status: torch.Tensor, width: int, height: int,
+           scale: float) -> torch.Tensor:
+    """Robust global affine motion (float64 [2, 3] device, v = A (x - (width-1)/2, y - (height-1)/2,
+    1)) of the converged points of a tracking result (dgf_gm_fit; Tukey scale ``scale`` pixels)."""
+    n = points.shape[0]
+    for t, shape, dt, name in ((points, (n, 2), torch.float32, "points"), (flow, (n, 2), torch.float32, "flow"),
+                               (status, (n,), torch.uint8, "status")):
+        if t.shape != shape or t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name}: expected a contiguous {dt} device tensor of shape {shape}")
+    ws = torch.empty(int(lib().dgf_gm_workspace_bytes()), dtype=torch.uint8, device=points.device)
+    model = torch.empty((2, 3), dtype=torch.float64, device=points.device)
+    check(lib().dgf_gm_fit(_ptr(points), _ptr(flow), _ptr(status), n, width, height, float(scale), _ptr(ws),
+                           ws.numel(), _ptr(model), _stream()), "dgf_gm_fit")
+    return model
 
 
 def track_static(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, levels: int, support: int, iters: int,

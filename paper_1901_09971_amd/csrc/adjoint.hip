@@ -562,7 +562,8 @@ extern "C" int dgf_track_backward(const dgf_image *I0, const dgf_image *I1, cons
     dgf_track_opts o;
     if (opts) {
         o = *opts;
-        if ((o.flags & ~DGF_TRACK_ILLUM) != 0) return DGF_ERR_UNSUPPORTED;
+        // the global prior only moves where the iteration starts; cross-based supports are not differentiated
+        if ((o.flags & ~(DGF_TRACK_ILLUM | DGF_TRACK_GLOBAL)) != 0) return DGF_ERR_UNSUPPORTED;
     } else {
         dgf_track_opts_default(&o);
     }

@@ -61,6 +61,7 @@ int dgf_track_opts_default(dgf_track_opts *o)
     o->eps_fine = 1e-4f;
     o->min_eig = 1e-4f * 255.0f * 255.0f;
     o->flags = 0;
+    o->cross_tau = 25.0f;
     return DGF_OK;
 }
 
@@ -136,7 +137,8 @@ int dgf_pyramid(const dgf_image *src, int32_t levels, void *dst, size_t dst_byte
 size_t dgf_track_workspace_bytes(int32_t W, int32_t H, int32_t levels, int32_t dtype)
 {
     if (W < 1 || H < 1 || levels < 1 || levels > DGF_MAX_LEVELS || esize(dtype) == 0) return 0;
-    return 2 * dgf_pyramid_layout(W, H, levels, dtype, nullptr, nullptr) + 256;
+    // both pyramids, then the global-motion fit's state
+    return 2 * dgf_pyramid_layout(W, H, levels, dtype, nullptr, nullptr) + gm_state_bytes(1, kGmMaxBlocks);
 }
 
 namespace {
@@ -265,7 +267,8 @@ int validate_track(const dgf_image *I0, const dgf_image *I1, const float *points
 {
     const int rc = validate_track_args(I0, I1, points, n, levels, support, iters, opts, flow, status, o);
     if (rc != DGF_OK) return rc;
-    if (levels > 1 && (!workspace || ws_bytes < dgf_track_workspace_bytes(I0->width, I0->height, levels, I0->dtype)))
+    if ((levels > 1 || (o->flags & DGF_TRACK_GLOBAL)) &&
+        (!workspace || ws_bytes < dgf_track_workspace_bytes(I0->width, I0->height, levels, I0->dtype)))
         return DGF_ERR_WORKSPACE;
     return DGF_OK;
 }
@@ -280,10 +283,15 @@ int validate_track_args(const dgf_image *I0, const dgf_image *I1, const float *p
     if (support < 1 || (support & 1) == 0 || support > DGF_MAX_SUPPORT) return DGF_ERR_INVALID_ARG;
     if (n < 0) return DGF_ERR_INVALID_ARG;
     if (n > 0 && (!points || !flow || !status)) return DGF_ERR_INVALID_ARG;
+    return effective_track_opts(opts, support, o);
+}
+
+int effective_track_opts(const dgf_track_opts *opts, int32_t support, dgf_track_opts *o)
+{
     if (opts) {
         *o = *opts;
-        if ((o->flags & ~DGF_TRACK_ILLUM) != 0) return DGF_ERR_UNSUPPORTED;
-        if ((o->flags & DGF_TRACK_ILLUM) && run_shape_lanes(support) == 0) return DGF_ERR_UNSUPPORTED;
+        if ((o->flags & ~kTrackFlags) != 0) return DGF_ERR_UNSUPPORTED;
+        if ((o->flags & kRowRunFlags) && run_shape_lanes(support) == 0) return DGF_ERR_UNSUPPORTED;
     } else {
         dgf_track_opts_default(o);
     }
@@ -291,7 +299,30 @@ int validate_track_args(const dgf_image *I0, const dgf_image *I1, const float *p
         isnan(o->min_eig))
         return DGF_ERR_INVALID_ARG;
     if (isinf(o->sigma2) && !isinf(o->sigma1)) return DGF_ERR_INVALID_ARG; // no finite inner band with infinite outer
+    if ((o->flags & DGF_TRACK_CROSS) && !(o->cross_tau >= 0.f && isfinite(o->cross_tau))) return DGF_ERR_INVALID_ARG;
     return DGF_OK;
+}
+
+// Global-motion fit state in a track workspace: after both pyramids.
+GmFit gm_fit_for(const dgf_image *I0, int32_t levels, const void *workspace, const float *points,
+                 const float *flow, const uint8_t *status, int64_t n)
+{
+    const size_t pyr = dgf_pyramid_layout(I0->width, I0->height, levels, I0->dtype, nullptr, nullptr);
+    uint8_t *base = (uint8_t *)workspace + 2 * pyr;
+    GmFit g{};
+    g.pts = reinterpret_cast<const float2 *>(points);
+    g.flow = reinterpret_cast<const float2 *>(flow);
+    g.status = status;
+    g.n = n;
+    g.W = I0->width;
+    g.H = I0->height;
+    g.L = levels;
+    g.npairs = 1;
+    g.nblk = gm_blocks(n);
+    g.c = kTukeyC * ldexp(1.0, levels - 1);
+    g.models = reinterpret_cast<double *>(base);
+    g.part = reinterpret_cast<double *>(base + gm_models_bytes(1));
+    return g;
 }
 
 // Tracking on pyramids already in `workspace`, with an explicit launch shape (validated).
@@ -299,7 +330,7 @@ int track_run_with(const dgf_image *I0, const dgf_image *I1, const float *points
                    int32_t support, int32_t iters, const dgf_track_opts &o, const void *workspace, float *flow,
                    uint8_t *status, int32_t *iters_out, TrackTuning tune, hipStream_t st, float *illum_out)
 {
-    if (o.flags & DGF_TRACK_ILLUM) tune = illum_tuning(support, tune);
+    if (o.flags & kRowRunFlags) tune = illum_tuning(support, tune);
     if (!track_shape_ok(support, tune)) return DGF_ERR_UNSUPPORTED;
     while (track_lds_bytes(support, tune) > kMaxLdsPerBlock && tune.wpb > 1) tune.wpb /= 2;
     if (track_lds_bytes(support, tune) > kMaxLdsPerBlock) return DGF_ERR_UNSUPPORTED;
@@ -316,6 +347,20 @@ int track_run_with(const dgf_image *I0, const dgf_image *I1, const float *points
     P.iters = iters;
     fill_track_geometry(P, support, tune.margin, tune.lpp, tune.kind);
     fill_track_constants(P, o, support);
+    if (o.flags & DGF_TRACK_GLOBAL) {
+        // first pass on the coarsest level alone (into the outputs), the global fit into the
+        // workspace, then the tracking proper from the fitted motion
+        const GmFit g = gm_fit_for(I0, levels, workspace, points, flow, status, n);
+        P.lstop = levels - 1;
+        P.iters_out = nullptr;
+        P.illum_out = nullptr;
+        if (launch_track(P, tune, I0->dtype, st) != hipSuccess) return DGF_ERR_HIP;
+        if (launch_gm_fit(g, st) != hipSuccess) return DGF_ERR_HIP;
+        P.lstop = 0;
+        P.gm_model = g.models;
+        P.iters_out = iters_out;
+        P.illum_out = illum_out;
+    }
     return hip_rc(launch_track(P, tune, I0->dtype, st));
 }
 

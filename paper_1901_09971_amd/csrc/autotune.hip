@@ -21,7 +21,7 @@ using namespace dgf;
 
 namespace {
 
-std::string cache_key(int support, int levels, int dtype, int64_t n, bool illum)
+std::string cache_key(int support, int levels, int dtype, int64_t n, int32_t flags)
 {
     hipDeviceProp_t prop{};
     int dev = 0;
@@ -34,8 +34,9 @@ std::string cache_key(int support, int levels, int dtype, int64_t n, bool illum)
     int64_t bucket = 1;
     while (bucket < n) bucket <<= 1;
     char buf[160];
-    snprintf(buf, sizeof buf, "%s:s%d:L%d:%s:n%lld%s", arch.c_str(), support, levels, dtype == DGF_U8 ? "u8" : "f32",
-             (long long)bucket, illum ? ":illum" : "");
+    snprintf(buf, sizeof buf, "%s:s%d:L%d:%s:n%lld%s%s%s", arch.c_str(), support, levels, dtype == DGF_U8 ? "u8" : "f32",
+             (long long)bucket, (flags & DGF_TRACK_ILLUM) ? ":illum" : "", (flags & DGF_TRACK_CROSS) ? ":cross" : "",
+             (flags & DGF_TRACK_GLOBAL) ? ":gm" : "");
     return buf;
 }
 
@@ -115,8 +116,8 @@ int dgf_autotune(const dgf_image *I0, const dgf_image *I1, const float *points, 
     int rc = validate_track(I0, I1, points, n, levels, support, iters, opts, workspace, ws_bytes, flow, status, &o);
     if (rc != DGF_OK) return rc;
     if (n < 1) return DGF_ERR_INVALID_ARG;
-    // the illumination model's timings are cached under their own key
-    const std::string key = cache_key(support, levels, I0->dtype, n, (o.flags & DGF_TRACK_ILLUM) != 0);
+    // the illumination model, cross-based supports and the global prior are cached under their own keys
+    const std::string key = cache_key(support, levels, I0->dtype, n, o.flags);
     std::map<std::string, dgf_tuning> cache;
     if (cache_path) {
         cache = read_cache(cache_path);
@@ -139,7 +140,7 @@ int dgf_autotune(const dgf_image *I0, const dgf_image *I1, const float *points, 
                 for (int m : {1, 2, 3, 4, 6}) {
                     const TrackTuning t{lpp, wpb, m, kind};
                     if (kind == 0 && !run_shape_compiled(lpp, support)) continue;
-                    if (kind == 1 && (o.flags & DGF_TRACK_ILLUM)) continue;
+                    if (kind == 1 && (o.flags & kRowRunFlags)) continue;
                     if (!tuning_valid(t, support) || track_lds_bytes(support, t) > kMaxLdsPerBlock) continue;
                     cand.push_back(t);
                 }

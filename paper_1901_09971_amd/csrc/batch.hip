@@ -51,6 +51,8 @@ struct dgf_batch {
     AdjPair *d_adj = nullptr; // per-pair frames and gradient-map offsets for the adjoint
     std::vector<int64_t> grad_off; // first float of each pair's dI0 (dI1 follows), P + 1 entries
     PyrJob *d_pyr = nullptr; // [(L-1)][2P]
+    double *d_gm = nullptr;  // global-motion fit state (models, then partial sums), DGF_TRACK_GLOBAL only
+    int gm_nblk = 0;
     DetectJob *d_det = nullptr;
     std::vector<int> pyr_w2, pyr_h2; // per level 1..L-1: largest output size over the frames
     int det_tiles_x = 0, det_tiles_y = 0;
@@ -107,6 +109,33 @@ int launch_all(dgf_batch *b, float *points, float *flow, uint8_t *status, int32_
     P.counter = b->d_counter;
     P.nitems = b->nitems;
     P.grid_waves = b->grid_waves;
+    if (b->opts.flags & DGF_TRACK_GLOBAL) {
+        // every pair's coarsest-level pass, every pair's global fit, fresh work counters, then the
+        // tracking proper from each pair's fitted motion
+        GmFit g{};
+        g.pts = reinterpret_cast<const float2 *>(points);
+        g.flow = reinterpret_cast<const float2 *>(flow);
+        g.status = status;
+        g.pt_off = b->d_pt_off;
+        g.blv = b->d_lv;
+        g.L = b->L;
+        g.npairs = b->P;
+        g.nblk = b->gm_nblk;
+        g.c = kTukeyC * ldexp(1.0, b->L - 1);
+        g.models = b->d_gm;
+        g.part = (double *)((uint8_t *)b->d_gm + gm_models_bytes(b->P));
+        P.lstop = b->L - 1;
+        P.iters_out = nullptr;
+        P.illum_out = nullptr;
+        if (launch_track(P, b->tune, b->dtype, st) != hipSuccess) return DGF_ERR_HIP;
+        if (launch_gm_fit(g, st) != hipSuccess) return DGF_ERR_HIP;
+        hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(kNumXcd), 0, st, b->d_counter);
+        if (hipGetLastError() != hipSuccess) return DGF_ERR_HIP;
+        P.lstop = 0;
+        P.gm_model = g.models;
+        P.iters_out = iters_out;
+        P.illum_out = illum_out;
+    }
     return launch_track(P, b->tune, b->dtype, st) == hipSuccess ? DGF_OK : DGF_ERR_HIP;
 }
 
@@ -126,16 +155,8 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
     for (int i = 0; i < npairs; ++i)
         if (!pair_ok(pairs[i], dtype)) return DGF_ERR_INVALID_ARG;
     dgf_track_opts o;
-    if (opts) {
-        o = *opts;
-        if ((o.flags & ~DGF_TRACK_ILLUM) != 0) return DGF_ERR_UNSUPPORTED;
-        if ((o.flags & DGF_TRACK_ILLUM) && run_shape_lanes(support) == 0) return DGF_ERR_UNSUPPORTED;
-    } else {
-        dgf_track_opts_default(&o);
-    }
-    if (!(o.sigma1 >= 0.f) || !(o.sigma2 >= 0.f) || !(o.eps_coarse >= 0.f) || !(o.eps_fine >= 0.f) || isnan(o.min_eig))
-        return DGF_ERR_INVALID_ARG;
-    if (isinf(o.sigma2) && !isinf(o.sigma1)) return DGF_ERR_INVALID_ARG;
+    const int orc = effective_track_opts(opts, support, &o);
+    if (orc != DGF_OK) return orc;
     for (int i = 0; i < npairs; ++i)
         if (detect_tile_lds(pairs[i].window, pairs[i].stride) > 48 * 1024) return DGF_ERR_UNSUPPORTED;
 
@@ -151,7 +172,7 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
     for (int i = 0; i < npairs; ++i)
         total_n += dgf_detect_count(pairs[i].I0.width, pairs[i].I0.height, pairs[i].window, pairs[i].stride);
     b->tune = tuning_for(support, levels, dtype, total_n);
-    if (o.flags & DGF_TRACK_ILLUM) b->tune = illum_tuning(support, b->tune);
+    if (o.flags & kRowRunFlags) b->tune = illum_tuning(support, b->tune);
     if (!track_shape_ok(support, b->tune)) {
         delete b;
         return DGF_ERR_UNSUPPORTED;
@@ -220,6 +241,11 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
     sz = align_up(sz + (int64_t)sizeof(DetectJob) * npairs, 256);
     const int64_t o_adj = sz;
     sz = align_up(sz + (int64_t)sizeof(AdjPair) * npairs, 256);
+    int64_t max_n = 0;
+    for (int i = 0; i < npairs; ++i) max_n = std::max(max_n, b->pt_off[i + 1] - b->pt_off[i]);
+    b->gm_nblk = gm_blocks(max_n);
+    const int64_t o_gm = sz;
+    if (o.flags & DGF_TRACK_GLOBAL) sz = align_up(sz + (int64_t)gm_state_bytes(npairs, b->gm_nblk), 256);
     for (int i = 0; i < npairs; ++i) {
         pyr_bytes[i] = (int64_t)dgf_pyramid_layout(pairs[i].I0.width, pairs[i].I0.height, levels, dtype, nullptr, nullptr);
         pyr_base[i] = sz;
@@ -238,6 +264,7 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
     b->d_pyr = (PyrJob *)(base + o_pyrjobs);
     b->d_det = (DetectJob *)(base + o_det);
     b->d_adj = (AdjPair *)(base + o_adj);
+    if (o.flags & DGF_TRACK_GLOBAL) b->d_gm = (double *)(base + o_gm);
 
     // level table and pyramid jobs
     std::vector<LevelPair> lv((size_t)npairs * levels);
@@ -361,6 +388,7 @@ int dgf_batch_backward(dgf_batch *b, const float *points, const float *flow, con
     if (!b) return DGF_ERR_INVALID_ARG;
     if (b->total_pts > 0 && (!points || !flow || !status || !dflow || !grad)) return DGF_ERR_INVALID_ARG;
     if (grad && (uintptr_t)grad % 4 != 0) return DGF_ERR_INVALID_ARG;
+    if (b->opts.flags & DGF_TRACK_CROSS) return DGF_ERR_UNSUPPORTED; // cross-based supports are not differentiated
     const bool im = (b->opts.flags & DGF_TRACK_ILLUM) != 0;
     if (im && b->total_pts > 0 && !illum) return DGF_ERR_INVALID_ARG;
     if (!im && illum) return DGF_ERR_INVALID_ARG;

@@ -77,6 +77,32 @@ __device__ __forceinline__ float group_sum(float v)
     return v;
 }
 
+// Bitwise OR of v over the LPP-lane group of the calling lane (the pattern of group_sum).  Must be
+// called with all 64 lanes active.
+template <int CTRL>
+__device__ __forceinline__ unsigned dppu(unsigned v)
+{
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+template <int LPP>
+__device__ __forceinline__ unsigned group_or(unsigned v)
+{
+    v |= dppu<0xB1>(v);
+    v |= dppu<0x4E>(v);
+    v |= dppu<0x141>(v);
+    v |= dppu<0x140>(v);
+    if constexpr (LPP >= 32) {
+        const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        v = (unsigned)p[0] | (unsigned)p[1];
+    }
+    if constexpr (LPP == 64) {
+        const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        v = (unsigned)p[0] | (unsigned)p[1];
+    }
+    return v;
+}
+
 // Sums of five values over all 64 lanes, returned wave-uniform.  Transposed reduction: the
 // half- and row-swap permutes add two different values in one step (each half, then each row,
 // keeps a different value), so only two registers remain for the in-row DPP butterflies.
@@ -421,6 +447,11 @@ struct TrackParams {
     float cs2;           // cmid * sigma2
     float eps2c, eps2f;  // squared stopping thresholds
     float min_eig_s2;    // min_eig * s^2
+    float min_eig;       // per support pixel (cross-based supports divide by their own size)
+    int32_t cross;       // 1: adaptive cross-based supports with threshold tau
+    float tau;
+    int32_t lstop;       // last (finest) level run: 0, or L - 1 for the global prior's first pass
+    const double *gm_model; // nullable: global affine motion per pair, [npairs or 1][6], starts the coarsest level
     // batched form (npairs = 0 for a single pair): per-pair level table, prefix sums of per-pair
     // work items (groups of points of one pair handled by one wavefront) and of per-pair points
     int32_t npairs;
@@ -608,6 +639,42 @@ hipError_t launch_detect_backward(const DetectGradParams &G, hipStream_t st);
 
 hipError_t launch_track_adjoint(const AdjParams &A, int dtype, hipStream_t st);
 void fill_adjoint_constants(AdjParams &A, const dgf_track_opts &o);
+
+// Tracker flags this build implements, and those that need the row-run kernel.
+constexpr int32_t kTrackFlags = DGF_TRACK_ILLUM | DGF_TRACK_CROSS | DGF_TRACK_GLOBAL;
+constexpr int32_t kRowRunFlags = DGF_TRACK_ILLUM | DGF_TRACK_CROSS | DGF_TRACK_GLOBAL;
+
+// Global-motion fit of the tracker's first pass (gm.hip): least squares, then ten Tukey
+// reweightings, one launch each, plus one that finishes the last model.
+constexpr int kGmSums = 13;      // weighted sums of one pass
+constexpr int kGmPasses = 11;    // weighting passes
+constexpr int kGmMaxBlocks = 256; // workgroups per pair and pass
+constexpr double kTukeyC = 4.685;  // Tukey biweight constant, in coarsest-level pixels
+
+struct GmFit {
+    const float2 *pts, *flow;  // points and first-pass motion (level-0 pixels)
+    const uint8_t *status;     // first-pass status: CONVERGED marks a sample
+    int64_t n;                 // single pair: points [0, n) of a W x H frame
+    int W, H;
+    const int64_t *pt_off;     // batched: pair p holds points pt_off[p] .. pt_off[p + 1] (else null)
+    const LevelPair *blv;      // batched: level table [npairs][L] (level 0 gives the frame size)
+    int L;
+    int npairs, nblk;          // nblk: largest gm_blocks over the pairs (the grid's x extent)
+    double c;                  // Tukey constant, level-0 pixels
+    double *models;            // [2][npairs][6]; the fitted model ends in the first half
+    double *part;              // [2][npairs][nblk][kGmSums]
+};
+
+// Workgroups per pass for a pair of n points (about 2048 points each): a function of the pair's
+// own count, so that a pair fitted in a batch plan is reduced exactly as it is on its own.
+__host__ __device__ inline int gm_blocks(int64_t n)
+{
+    const int64_t b = (n + 2047) / 2048;
+    return (int)(b < 1 ? 1 : (b > kGmMaxBlocks ? kGmMaxBlocks : b));
+}
+size_t gm_models_bytes(int npairs);
+size_t gm_state_bytes(int npairs, int nblk); // models, then partials (at gm_models_bytes)
+hipError_t launch_gm_fit(const GmFit &g, hipStream_t st);
 
 struct TrackTuning {
     int lpp;     // lanes per point: 16, 32 or 64

@@ -24,10 +24,14 @@ int validate_track(const dgf_image *I0, const dgf_image *I1, const float *points
 int validate_track_args(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
                         int32_t support, int32_t iters, const dgf_track_opts *opts, const float *flow,
                         const uint8_t *status, dgf_track_opts *o);
+// Options in effect for a tracking call (defaults when opts is null), checked against the support.
+int effective_track_opts(const dgf_track_opts *opts, int32_t support, dgf_track_opts *o);
 int track_run_with(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
                    int32_t support, int32_t iters, const dgf_track_opts &o, const void *workspace, float *flow,
                    uint8_t *status, int32_t *iters_out, TrackTuning tune, hipStream_t st, float *illum_out = nullptr);
 void set_tuning(int support, int dtype, const TrackTuning &t);
+GmFit gm_fit_for(const dgf_image *I0, int32_t levels, const void *workspace, const float *points,
+                 const float *flow, const uint8_t *status, int64_t n);
 bool get_installed(int support, int dtype, TrackTuning *out);
 
 } // namespace dgf

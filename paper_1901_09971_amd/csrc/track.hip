@@ -1,13 +1,22 @@
 // track.hip -- host side of the tracker: launch geometry, shape selection and dispatch to the
-// kernel instantiations in track_u8.hip / track_f32.hip (kernel: track_kernel.hpp).
+// kernel instantiations in track_u8.hip / track_f32.hip (generic kernel: track_kernel.hpp) and
+// track_run_*.hip (row-run kernel: track_run_kernel.hpp).
 #include "track_run_kernel.hpp"
 
 namespace dgf {
 
 hipError_t launch_track_u8(const TrackParams &P, int lpp, int ppl, int tp, int wpb, hipStream_t st);
 hipError_t launch_track_f32(const TrackParams &P, int lpp, int ppl, int tp, int wpb, hipStream_t st);
+// row-run instantiations, one file per (element type, cross-based supports, batch plan)
+using RunLaunch = hipError_t (*)(const TrackParams &, int, int, int, hipStream_t);
 hipError_t launch_track_run_u8(const TrackParams &P, int lpp, int s, int wpb, hipStream_t st);
+hipError_t launch_track_run_u8_batch(const TrackParams &P, int lpp, int s, int wpb, hipStream_t st);
+hipError_t launch_track_run_u8_cross(const TrackParams &P, int lpp, int s, int wpb, hipStream_t st);
+hipError_t launch_track_run_u8_cross_batch(const TrackParams &P, int lpp, int s, int wpb, hipStream_t st);
 hipError_t launch_track_run_f32(const TrackParams &P, int lpp, int s, int wpb, hipStream_t st);
+hipError_t launch_track_run_f32_batch(const TrackParams &P, int lpp, int s, int wpb, hipStream_t st);
+hipError_t launch_track_run_f32_cross(const TrackParams &P, int lpp, int s, int wpb, hipStream_t st);
+hipError_t launch_track_run_f32_cross_batch(const TrackParams &P, int lpp, int s, int wpb, hipStream_t st);
 
 bool run_shape_compiled(int lpp, int s)
 {
@@ -87,7 +96,8 @@ void fill_track_geometry(TrackParams &P, int s, int margin, int lpp, int kind)
     P.TW = s + 1 + 2 * P.M;
     P.RW = s + 3;
     P.RPP = raw_pitch(s);
-    const int tmpl = P.RW * P.RPP + (s + 2) * P.RPP;
+    // raw patch, resampled (s + 2)^2 grid, and the cross-based support's arms (2 (s + 2) + 2 ints)
+    const int tmpl = P.RW * P.RPP + (s + 2) * P.RPP + 2 * (s + 2) + 2;
     const int iter = P.TW * tp;
     P.tile_floats = tmpl > iter ? tmpl : iter;
     P.invBW = 1.0f / (float)(s + 2);
@@ -105,8 +115,11 @@ hipError_t launch_track(const TrackParams &P, const TrackTuning &T, int dtype, h
 {
     if (P.n <= 0) return hipSuccess;
     if (T.kind == 0 && run_shape_compiled(T.lpp, P.s)) {
-        if (dtype == DGF_U8) return launch_track_run_u8(P, T.lpp, P.s, T.wpb, st);
-        return launch_track_run_f32(P, T.lpp, P.s, T.wpb, st);
+        static const RunLaunch run[2][2][2] = {
+            {{launch_track_run_u8, launch_track_run_u8_batch}, {launch_track_run_u8_cross, launch_track_run_u8_cross_batch}},
+            {{launch_track_run_f32, launch_track_run_f32_batch},
+             {launch_track_run_f32_cross, launch_track_run_f32_cross_batch}}};
+        return run[dtype == DGF_U8 ? 0 : 1][P.cross ? 1 : 0][P.npairs ? 1 : 0](P, T.lpp, P.s, T.wpb, st);
     }
     const int tp = tile_pitch(P.s);
     if (!shape_compiled(T.lpp, P.ppl, tp)) return hipErrorInvalidValue;

@@ -1,21 +1,10 @@
-// track_run_f32.hip -- single-pair instantiations of the row-run tracker kernel for float images
-// (batch plans: track_run_f32_batch.hip).
+// track_run_f32.hip -- single-pair, square-window instantiations of the row-run tracker kernel for
+// float images (kernel: track_run_kernel.hpp; the other forms have files of their own, so that they
+// compile in parallel).
 #include "track_run_kernel.hpp"
 
 namespace dgf {
 
-hipError_t launch_track_run_f32_batch(const TrackParams &P, int lpp, int s, int wpb, hipStream_t st);
-
-hipError_t launch_track_run_f32(const TrackParams &P, int lpp, int s, int wpb, hipStream_t st)
-{
-    if (P.npairs) return launch_track_run_f32_batch(P, lpp, s, wpb, st);
-#define DGF_CASE(L_, SEG_, R_, TP_, S_, X_)                                                                            \
-    if (lpp == L_ && s == S_)                                                                                          \
-        return P.illum ? launch_track_run_t<L_, SEG_, R_, TP_, S_, X_, true, false>(P, wpb, st)                            \
-                       : launch_track_run_t<L_, SEG_, R_, TP_, S_, X_, false, false>(P, wpb, st);
-    DGF_TRACK_RUN_SHAPES(DGF_CASE, float)
-#undef DGF_CASE
-    return hipErrorInvalidValue;
-}
+DGF_DEFINE_TRACK_RUN_LAUNCH(launch_track_run_f32, float, false, false)
 
 } // namespace dgf

@@ -48,6 +48,40 @@ __device__ __forceinline__ void group_sum5(float &a, float &b, float &c, float &
     }
 }
 
+// Adaptive cross-based support, decided on the level image's own pixels at floor(p) + k for the
+// support offsets extended by one, k in [-r-1, r+1]^2 (the first G = s + 2 rows and columns of the
+// raw patch, pitch RP; centre c = G / 2): exact comparisons for integer frames, where the
+// interpolated template would put many differences exactly on tau.  Per row the horizontal arm
+// around the row's centre-column pixel (pixels within tau of it, run outward until the first that
+// is not), and the vertical arm of the centre.  Rows are shared out over the group's lanes; the
+// arms go to `arms` in LDS: left[y], right[y] as arms[2 y], arms[2 y + 1] (0 .. c), up and down in
+// arms[2 G], arms[2 G + 1].  Needs G <= 32 (row flags as a 32-bit mask).
+template <int LPP, int G, int RP>
+__device__ __forceinline__ void cross_arms(const float *raw, int *arms, float tau, int li)
+{
+    static_assert(G <= 32, "cross-based supports need s + 2 <= 32");
+    constexpr int c = G / 2;
+    const float centre = raw[c * RP + c];
+    unsigned vbits = 0u; // bit y: centre-column pixel of row y within tau of the centre
+    for (int y = li; y < G; y += LPP) {
+        const float *row = raw + y * RP;
+        const float a = row[c];
+        unsigned ok = 0u;
+#pragma unroll
+        for (int x = 0; x < G; ++x) ok |= (fabsf(row[x] - a) <= tau ? 1u : 0u) << x;
+        const unsigned above = ok >> (c + 1), below = ok << (32 - c);
+        arms[2 * y] = min(__builtin_clz(~below), c);
+        arms[2 * y + 1] = min(__builtin_ctz(~above), c);
+        vbits |= (fabsf(a - centre) <= tau ? 1u : 0u) << y;
+    }
+    // the vertical arm from the group's row flags
+    const unsigned all = (unsigned)group_or<LPP>(vbits);
+    if (li == 0) {
+        arms[2 * G] = min(__builtin_clz(~(all << (32 - c))), c);
+        arms[2 * G + 1] = min(__builtin_ctz(~(all >> (c + 1))), c);
+    }
+}
+
 // True when the flag is set on any lane of the wavefront.  With one point per wavefront (64 lanes
 // per point) every lane holds the same value, so the flag itself decides the branch: no ballot,
 // whose lowering would spend two vector instructions turning a mask back into a condition.
@@ -61,10 +95,11 @@ __device__ __forceinline__ bool group_any(bool p)
 }
 
 // The 64-lane form without the illumination model is held to 80 VGPRs (six waves per SIMD): it is
-// issue bound, and the sixth wave pays.  MODE (ROBUST_L2 / HAMPEL / HARD) and BATCH (a batch plan's
-// persistent launch rather than one pair) are compile-time, so a single-pair launch carries no
-// batch bookkeeping and no branch on the robust norm.
-template <int LPP, int SEG, int R, int TP, int S, typename PixT, bool IM, int MODE, bool BATCH>
+// issue bound, and the sixth wave pays.  MODE (ROBUST_L2 / HAMPEL / HARD), CROSS (adaptive
+// cross-based supports) and BATCH (a batch plan's persistent launch rather than one pair) are
+// compile-time, so a single-pair square-window launch carries no batch bookkeeping, no per-pixel
+// support mask and no branch on the robust norm.
+template <int LPP, int SEG, int R, int TP, int S, typename PixT, bool IM, int MODE, bool CROSS, bool BATCH>
 __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(TrackParams P)
 {
     constexpr int PPW = 64 / LPP;
@@ -135,12 +170,20 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
     }
     float gX = 0.f, gY = 0.f; // guess of the current level
     float hX = 0.f, hY = 0.f; // guess plus the steps taken on it so far (g + d)
+    if (P.gm_model && active) {
+        // global-motion prior: the coarsest level starts from the fitted affine motion at the point
+        const double *A = P.gm_model + (BATCH ? 6 * pair : 0);
+        const double x = (double)px - 0.5 * (W0 - 1), y = (double)py - 0.5 * (H0 - 1);
+        const double itop = __builtin_ldexp(1.0, 1 - P.L); // coarsest-level pixels per level-0 pixel
+        gX = (float)((A[0] * x + A[1] * y + A[2]) * itop);
+        gY = (float)((A[3] * x + A[4] * y + A[5]) * itop);
+    }
     bool conv0 = false;
     int it_total = 0;
     float im_m = 0.f, im_c = 0.f; // illumination model: gain change and offset, carried across levels
 
 
-    for (int l = P.L - 1; l >= 0; --l) {
+    for (int l = P.L - 1; l >= P.lstop; --l) {
         if (!group_any<LPP>(active)) break;
         const LevelPair LV = level_of<BATCH>(P, pair, l);
         const int Wl = LV.W, Hl = LV.H;
@@ -173,34 +216,64 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
             }
         }
         wave_sync();
-        // template value and central differences at +-1 px of the resampled patch.  Unused runs get
-        // half = 0, so their gradients vanish; they read run 0's pixels, so a non-finite pixel
-        // there reaches the sums through run 0 anyway.
+        // support of this level: bit j*R+p of pm for pixel p of run j (unused runs are out); the
+        // square window is every pixel of the used runs
+        unsigned pm = 0u;
+#pragma unroll
+        for (int j = 0; j < SEG; ++j)
+            if ((vmask >> j) & 1u) pm |= ((1u << R) - 1u) << (j * R);
+        auto in_support = [&](int j) -> bool {
+            if constexpr (CROSS)
+                return (pm >> j) & 1u;
+            else
+                return (vmask >> (j / R)) & 1u;
+        };
+        if constexpr (CROSS) {
+            // adaptive cross-based support: a pixel stays when it and its four neighbours lie in
+            // the cross region (no template gradient straddles the region's edge)
+            int *arms = reinterpret_cast<int *>(grid + G * RP);
+            cross_arms<LPP, G, RP>(tile, arms, P.tau, li);
+            wave_sync();
+            constexpr int c = G / 2;
+            const int up = arms[2 * G], down = arms[2 * G + 1];
+#pragma unroll
+            for (int j = 0; j < SEG; ++j) {
+                const int y = (rc[j] >> 8) + 1, x0 = (rc[j] & 255) + 1;
+                const bool rowok = (y - 1 >= c - up) && (y + 1 <= c + down);
+                const int lo = max(c - arms[2 * y] + 1, max(c - arms[2 * y - 2], c - arms[2 * y + 2]));
+                const int hi = min(c + arms[2 * y + 1] - 1, min(c + arms[2 * y - 1], c + arms[2 * y + 3]));
+#pragma unroll
+                for (int p = 0; p < R; ++p)
+                    if (!(rowok && x0 + p >= lo && x0 + p <= hi)) pm &= ~(1u << (j * R + p));
+            }
+        }
+        // template value and central differences at +-1 px of the resampled patch.  Pixels out of
+        // the support get half = 0, so their gradients vanish (unused runs read run 0's pixels,
+        // so a non-finite pixel there reaches the sums through run 0 anyway).
 #pragma unroll
         for (int j = 0; j < SEG; ++j) {
             const int row = rc[j] >> 8, col0 = rc[j] & 255;
             const float *gm = grid + row * RP + col0 + 1;      // grid row of support row - 1
             const float *g0 = gm + RP, *gp = gm + 2 * RP;        // support row, support row + 1
-            const float half = ((vmask >> j) & 1u) ? 0.5f : 0.f;
 #pragma unroll
             for (int p = 0; p < R; ++p) {
+                const float half = in_support(j * R + p) ? 0.5f : 0.f;
                 T[j * R + p] = g0[p];
                 GX[j * R + p] = half * (g0[p + 1] - g0[p - 1]);
                 GY[j * R + p] = half * (gp[p] - gm[p]);
             }
         }
-        float a = 0.f, b = 0.f, c = 0.f, sT = 0.f;
+        float a = 0.f, b = 0.f, c = 0.f, sT = 0.f, nsup = 0.f;
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
             a = fmaf(GX[j], GX[j], a);
             b = fmaf(GX[j], GY[j], b);
             c = fmaf(GY[j], GY[j], c);
-            if constexpr (IM) sT += ((vmask >> (j / R)) & 1u) ? T[j] : 0.f;
+            if constexpr (IM) sT += in_support(j) ? T[j] : 0.f;
         }
-        {
-            float z1 = 0.f;
-            group_sum5<LPP>(a, b, c, sT, z1);
-        }
+        if constexpr (CROSS) nsup = (float)__builtin_popcount(pm);
+        group_sum5<LPP>(a, b, c, sT, nsup);
+        if constexpr (!CROSS) nsup = (float)(s * s);
         // Illumination model: the template is centred and scaled over the support, T' = (T - Tm) / Ts,
         // and the iteration runs in (d, ga, gb) with ga = (1 + m) Ts and gb = (1 + m) Tm + c, a linear
         // change of the gain / offset parameters that leaves the Gauss-Newton iterates in d unchanged
@@ -208,12 +281,12 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
         float Tm = 0.f, Ts = 1.f, ga = 0.f, gb = 0.f, det0_im = 0.f;
         float M0[10];
         if constexpr (IM) {
-            const float nv = (float)(s * s);
+            const float nv = nsup;
             Tm = sT / nv;
             float S2 = 0.f, Sgxd = 0.f, Sgyd = 0.f, Sgx = 0.f, Sgy = 0.f;
 #pragma unroll
             for (int j = 0; j < PPL; ++j) {
-                const float dv = ((vmask >> (j / R)) & 1u) ? T[j] - Tm : 0.f;
+                const float dv = in_support(j) ? T[j] - Tm : 0.f;
                 S2 = fmaf(dv, dv, S2);
                 Sgxd = fmaf(GX[j], dv, Sgxd);
                 Sgyd = fmaf(GY[j], dv, Sgyd);
@@ -242,9 +315,11 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
         }
         const float lam = 0.5f * (a + c) - sqrtf(0.25f * (a - c) * (a - c) + b * b);
         // too flat to invert: a coarse level runs no iteration and passes the guess on; at
-        // level 0 the point is ill-conditioned with u = g
-        const bool flat = active && !(lam >= P.min_eig_s2);
-        if (flat && l == 0) {
+        // level 0 the point is ill-conditioned with u = g.  (An empty cross-based support is flat,
+        // and with the illumination model one of fewer than four pixels: four unknowns.)
+        const bool flat = active && !(CROSS ? (nsup >= (IM ? 4.f : 1.f) && lam >= P.min_eig * nsup)
+                                            : lam >= P.min_eig_s2);
+        if (flat && l == P.lstop) {
             status = DGF_ST_ILL_CONDITIONED;
             ux = gX;
             uy = gY;
@@ -333,7 +408,7 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
                 if constexpr (MODE == ROBUST_L2) {
 #pragma unroll
                     for (int j = 0; j < PPL; ++j) {
-                        const float w = ((vmask >> (j / R)) & 1u) ? 1.f : 0.f;
+                        const float w = in_support(j) ? 1.f : 0.f;
                         const float rw = RES[j] * w;
                         q0 = fmaf(rw, GX[j], q0);
                         q1 = fmaf(rw, GY[j], q1);
@@ -356,7 +431,7 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
                     for (int j = 0; j < PPL; ++j) {
                         float w = (MODE == ROBUST_HAMPEL) ? hampel_weight(RES[j], P.cs2, P.cmid)
                                                           : ((fabsf(RES[j]) <= P.s1) ? 1.f : 0.f);
-                        w = ((vmask >> (j / R)) & 1u) ? w : 0.f;
+                        w = in_support(j) ? w : 0.f;
                         const float wgx = w * GX[j], wgy = w * GY[j], wt = w * T[j];
                         s00 = fmaf(wgx, GX[j], s00);
                         s01 = fmaf(wgx, GY[j], s01);
@@ -399,7 +474,7 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
                         float u0 = 0.f, u1 = 0.f, u2 = 0.f, u3 = 0.f, z1 = 0.f;
 #pragma unroll
                         for (int j = 0; j < PPL; ++j) {
-                            const float rv = ((vmask >> (j / R)) & 1u) ? RES[j] : 0.f;
+                            const float rv = in_support(j) ? RES[j] : 0.f;
                             u0 = fmaf(rv, GX[j], u0);
                             u1 = fmaf(rv, GY[j], u1);
                             u2 = fmaf(rv, T[j], u2);
@@ -517,9 +592,16 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
             if (active && !flat) { // back to (m, c), which carry over to the next level
                 im_m = ga / Ts - 1.f;
                 im_c = gb - ga * Tm / Ts;
+                if (l > P.lstop && !(1.f + im_m >= 0.25f && 1.f + im_m <= 4.f)) {
+                    // a runaway gain (towards 0, where the motion drops out of the model) ends the point
+                    status = DGF_ST_NOT_CONVERGED;
+                    ux = __builtin_nanf("");
+                    uy = __builtin_nanf("");
+                    active = false;
+                }
             }
         }
-        if (l > 0) {
+        if (l > P.lstop) {
             if (active) {
                 gX = 2.f * hX;
                 gY = 2.f * hY;
@@ -536,6 +618,12 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
             if (!conv0 || (IM && !(1.f + im_m >= 0.5f && 1.f + im_m <= 2.f))) {
                 // (illumination model: a gain outside [1/2, 2] is a contrast change, not a match)
                 status = DGF_ST_NOT_CONVERGED;
+            } else if (P.lstop > 0) {
+                // a pass that stops above level 0 (the global prior's first pass) reports the
+                // step test only, with the motion in level-0 pixels
+                status = DGF_ST_CONVERGED;
+                ux = ldexpf(ux, P.lstop);
+                uy = ldexpf(uy, P.lstop);
             } else {
                 const float qx = px + ux, qy = py + uy;
                 status = (qx >= 0.f && qy >= 0.f && qx <= (float)(W0 - 1) && qy <= (float)(H0 - 1)) ? DGF_ST_CONVERGED
@@ -554,7 +642,7 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
     } // work loop
 }
 
-template <int LPP, int SEG, int R, int TP, int S, typename PixT, bool IM, bool BATCH>
+template <int LPP, int SEG, int R, int TP, int S, typename PixT, bool IM, bool CROSS, bool BATCH>
 hipError_t launch_track_run_t(const TrackParams &P, int wpb, hipStream_t st)
 {
     constexpr int PPW = 64 / LPP;
@@ -563,17 +651,35 @@ hipError_t launch_track_run_t(const TrackParams &P, int wpb, hipStream_t st)
     const size_t lds = (size_t)wpb * PPW * P.tile_floats * sizeof(float);
     const dim3 grid((unsigned)blocks), block(64 * wpb);
     if (P.mode == ROBUST_L2)
-        hipLaunchKernelGGL((k_track_run<LPP, SEG, R, TP, S, PixT, IM, ROBUST_L2, BATCH>), grid, block, lds, st, P);
+        hipLaunchKernelGGL((k_track_run<LPP, SEG, R, TP, S, PixT, IM, ROBUST_L2, CROSS, BATCH>), grid, block, lds, st, P);
     else if (P.mode == ROBUST_HAMPEL)
-        hipLaunchKernelGGL((k_track_run<LPP, SEG, R, TP, S, PixT, IM, ROBUST_HAMPEL, BATCH>), grid, block, lds, st, P);
+        hipLaunchKernelGGL((k_track_run<LPP, SEG, R, TP, S, PixT, IM, ROBUST_HAMPEL, CROSS, BATCH>), grid, block, lds, st,
+                           P);
     else
-        hipLaunchKernelGGL((k_track_run<LPP, SEG, R, TP, S, PixT, IM, ROBUST_HARD, BATCH>), grid, block, lds, st, P);
+        hipLaunchKernelGGL((k_track_run<LPP, SEG, R, TP, S, PixT, IM, ROBUST_HARD, CROSS, BATCH>), grid, block, lds, st, P);
     return hipGetLastError();
 }
 
 // Row-run shapes compiled per element type: (LPP, SEG, R, TP, support s).  SEG runs of R pixels
 // per lane cover the s * (s / R) runs of an s x s support.  The odd tile pitch TP = 31 spreads
 // the runs of consecutive rows over different LDS banks (a pitch of 32 maps them onto 3).
+// Dispatcher of one instantiation file: element type, cross-based supports or not, single pair
+// or batch plan; the support shape and the illumination model are picked at run time.
+#define DGF_DEFINE_TRACK_RUN_LAUNCH(NAME, PIXT, CROSS, BATCH)                                                          \
+    hipError_t NAME(const TrackParams &P, int lpp, int s, int wpb, hipStream_t st)                                     \
+    {                                                                                                                  \
+        DGF_TRACK_RUN_SHAPES(DGF_TRACK_RUN_CASE_##CROSS##_##BATCH, PIXT)                                               \
+        return hipErrorInvalidValue;                                                                                   \
+    }
+#define DGF_TRACK_RUN_CASE(L_, SEG_, R_, TP_, S_, X_, C_, B_)                                                          \
+    if (lpp == L_ && s == S_)                                                                                          \
+        return P.illum ? launch_track_run_t<L_, SEG_, R_, TP_, S_, X_, true, C_, B_>(P, wpb, st)                       \
+                       : launch_track_run_t<L_, SEG_, R_, TP_, S_, X_, false, C_, B_>(P, wpb, st);
+#define DGF_TRACK_RUN_CASE_false_false(L_, SEG_, R_, TP_, S_, X_) DGF_TRACK_RUN_CASE(L_, SEG_, R_, TP_, S_, X_, false, false)
+#define DGF_TRACK_RUN_CASE_false_true(L_, SEG_, R_, TP_, S_, X_) DGF_TRACK_RUN_CASE(L_, SEG_, R_, TP_, S_, X_, false, true)
+#define DGF_TRACK_RUN_CASE_true_false(L_, SEG_, R_, TP_, S_, X_) DGF_TRACK_RUN_CASE(L_, SEG_, R_, TP_, S_, X_, true, false)
+#define DGF_TRACK_RUN_CASE_true_true(L_, SEG_, R_, TP_, S_, X_) DGF_TRACK_RUN_CASE(L_, SEG_, R_, TP_, S_, X_, true, true)
+
 #define DGF_TRACK_RUN_SHAPES(X, PixT)                                                                                  \
     X(64, 1, 7, 31, 21, PixT) X(32, 2, 7, 31, 21, PixT) X(16, 4, 7, 31, 21, PixT) X(32, 1, 3, 31, 9, PixT)             \
     X(16, 2, 3, 31, 9, PixT) X(32, 2, 5, 31, 15, PixT) X(16, 3, 5, 31, 15, PixT) X(16, 1, 11, 31, 11, PixT)           \

@@ -1,0 +1,10 @@
+// track_run_u8_cross_batch.hip -- batch-plan (persistent), cross-based-support instantiations of
+// the row-run tracker kernel for uint8_t images (kernel: track_run_kernel.hpp; the other forms have
+// files of their own, so that they compile in parallel).
+#include "track_run_kernel.hpp"
+
+namespace dgf {
+
+DGF_DEFINE_TRACK_RUN_LAUNCH(launch_track_run_u8_cross_batch, uint8_t, true, true)
+
+} // namespace dgf

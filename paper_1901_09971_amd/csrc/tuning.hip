@@ -111,6 +111,11 @@ void fill_track_constants(TrackParams &P, const dgf_track_opts &o, int support)
     P.eps2c = o.eps_coarse * o.eps_coarse;
     P.eps2f = o.eps_fine * o.eps_fine;
     P.min_eig_s2 = o.min_eig * (float)(support * support);
+    P.min_eig = o.min_eig;
+    P.cross = (o.flags & DGF_TRACK_CROSS) ? 1 : 0;
+    P.tau = o.cross_tau;
+    P.lstop = 0;
+    P.gm_model = nullptr;
 }
 
 } // namespace dgf

@@ -46,7 +46,7 @@ def test_strerror_version_defaults():
     assert L.dgf_track_opts_default(ctypes.byref(o)) == 0
     assert (o.sigma1, o.sigma2) == (8.0, 32.0)
     assert abs(o.eps_coarse - 1e-2) < 1e-9 and abs(o.eps_fine - 1e-4) < 1e-10
-    assert abs(o.min_eig - 6.5025) < 1e-4 and o.flags == 0
+    assert abs(o.min_eig - 6.5025) < 1e-4 and o.flags == 0 and o.cross_tau == 25.0
     assert L.dgf_track_opts_default(None) == -1
 
 
@@ -117,10 +117,21 @@ def test_argument_validation_before_launch():
     assert track(n=-1) == -1
     assert track(pts=None) == -1 and track(flow=None) == -1 and track(st=None) == -1
     assert track(wsp=None) == -5 and track(wsb=ws - 1) == -5
-    o = _lib.DgfTrackOpts(8, 32, 1e-2, 1e-4, 6.5, 2)  # unknown flag
+    o = _lib.DgfTrackOpts(8, 32, 1e-2, 1e-4, 6.5, 8)  # unknown flag
     assert track(opts=ctypes.pointer(o)) == -3
-    o = _lib.DgfTrackOpts(8, 32, 1e-2, 1e-4, 6.5, _lib.DGF_TRACK_ILLUM)  # no row-run kernel for 13x13
-    assert track(s=13, opts=ctypes.pointer(o)) == -3
+    for fl in (_lib.DGF_TRACK_ILLUM, _lib.DGF_TRACK_CROSS, _lib.DGF_TRACK_GLOBAL):  # no row-run kernel for 13x13
+        o = _lib.DgfTrackOpts(8, 32, 1e-2, 1e-4, 6.5, fl, 25.0)
+        assert track(s=13, opts=ctypes.pointer(o)) == -3
+    for tau in (float("nan"), -1.0, float("inf")):  # cross-based supports need a finite threshold >= 0
+        o = _lib.DgfTrackOpts(8, 32, 1e-2, 1e-4, 6.5, _lib.DGF_TRACK_CROSS, tau)
+        assert track(opts=ctypes.pointer(o)) == -1
+    o = _lib.DgfTrackOpts(8, 32, 1e-2, 1e-4, 6.5, 0, float("nan"))  # the threshold is unused without the flag
+    assert track(n=0, pts=None, flow=None, st=None, opts=ctypes.pointer(o)) == 0
+    # the global prior keeps its fit in the workspace, so it needs one even for a single level
+    o = _lib.DgfTrackOpts(8, 32, 1e-2, 1e-4, 6.5, _lib.DGF_TRACK_GLOBAL, 25.0)
+    assert track(levels=1, wsp=None, wsb=0, opts=ctypes.pointer(o)) == -5
+    assert track(levels=1, wsp=None, wsb=0, n=0, pts=None, flow=None, st=None) == 0
+    assert track(levels=1, wsp=None, wsb=0, n=0, pts=None, flow=None, st=None, opts=ctypes.pointer(o)) == -5
     o = _lib.DgfTrackOpts(float("nan"), 32, 1e-2, 1e-4, 6.5, 0)
     assert track(opts=ctypes.pointer(o)) == -1
     # n = 0 validates and launches nothing
@@ -213,7 +224,7 @@ def test_track_static_checks_before_any_hip_call():
     assert call(s=8) == -1 and call(iters=0) == -1 and call(n=-1) == -1
     assert call(pts=None) == -1 and call(flow=None) == -1 and call(st=None) == -1
     assert call(ill=P) == -1  # illum_out without the illumination model
-    o = _lib.DgfTrackOpts(8, 32, 1e-2, 1e-4, 6.5, 2)
+    o = _lib.DgfTrackOpts(8, 32, 1e-2, 1e-4, 6.5, 8)
     assert call(opts=ctypes.pointer(o)) == -3
     assert L.dgf_track_static(None, ctypes.byref(im), P, 10, 3, 9, 10, None, P, P, None, None, None) == -1
     # n = 0: validated, nothing looked up or launched

@@ -214,3 +214,42 @@ def test_point_gradient_matches_finite_differences():
             fd = float(np.sum(lam[i] * (fa[0] - fb[0])) / (2 * h))
             assert abs(dp[i, c] - fd) <= 1e-5 * (abs(fd) + np.abs(lam[i]).sum()), (i, c, dp[i, c], fd)
     assert np.all(dp[st != 0] == 0.0)
+
+
+def test_coarse_level_with_a_runaway_gain_ends_the_point():
+    # the contrast-inverted pair on two levels: the coarse level already fits gain -1, outside
+    # [1/4, 4], so the point ends there (NOT_CONVERGED, NaN flow) instead of carrying an inverted
+    # model to the finer level
+    W, H, t = 100, 80, (2, -1)
+    I0 = _texture(W, H, 13)
+    I1 = 255.0 - I0
+    I1[max(t[1], 0):H + min(t[1], 0), max(t[0], 0):W + min(t[0], 0)] = \
+        255.0 - I0[max(-t[1], 0):H - max(t[1], 0), max(-t[0], 0):W - max(t[0], 0)]
+    pts = _interior(W, H, 15, 18, 14)
+    kw = dict(sigma1=INF, sigma2=INF, eps_fine=1e-10, min_eig=0.0, illum=True)
+    flow, st, its, mc = oracle.track(I0, I1, pts, 2, 9, 60, return_iters=True, return_illum=True, **kw)
+    ended = np.isnan(flow).all(1)
+    assert ended.sum() >= 10 and np.all(st[ended] == oracle.ST_NOT_CONVERGED)
+    assert np.all(its[ended, 1] == 0) and np.all(1.0 + mc[ended, 0] < 0.25)  # stopped before level 0
+    # a gain of 1.9 stays a match through both levels
+    flow, st = oracle.track(I0, 1.9 * I0, pts, 2, 9, 60, **kw)
+    assert np.all(st == oracle.ST_CONVERGED) and np.max(np.abs(flow)) < 1e-8
+
+
+def test_cross_support_of_fewer_than_four_pixels_is_flat_for_the_illumination_model():
+    # a 3 x 4 block of mutually similar values on a far brighter frame: the cross region at the
+    # block's centre is the block, and the gradient-stencil erosion keeps two pixels -- enough for
+    # the 2 x 2 system of the plain tracker, too few for the four unknowns of the illumination model
+    W = H = 40
+    I0 = np.full((H, W), 200.0)
+    I0[19:22, 19:23] = np.array([[100.0, 108.0, 95.0, 104.0], [112.0, 99.0, 110.0, 93.0], [97.0, 115.0, 102.0, 109.0]])
+    I1 = np.roll(I0, (1, 1), axis=(0, 1))
+    p = np.array([[20.3, 20.2]])
+    ys, xs = np.arange(20 - 11, 20 + 12), np.arange(20 - 11, 20 + 12)
+    m = oracle.cross_mask(I0[np.ix_(np.clip(ys, 0, H - 1), np.clip(xs, 0, W - 1))])
+    assert m.sum() == 2 and m[10, 10] and m[10, 11]
+    kw = dict(cross=True, min_eig=0.0)
+    f, st = oracle.track(I0, I1, p, 1, 21, 20, **kw)
+    assert st[0] != oracle.ST_ILL_CONDITIONED
+    f, st = oracle.track(I0, I1, p, 1, 21, 20, illum=True, **kw)
+    assert st[0] == oracle.ST_ILL_CONDITIONED

@@ -48,6 +48,13 @@ MUTATIONS = [
     ("cross arms that stop at a difference equal to the threshold",
      "while (left < re && fabs(row[re - left - 1] - a) <= tau) ++left;",
      "while (left < re && fabs(row[re - left - 1] - a) < tau) ++left;"),
+    ("illumination model on supports of fewer than four pixels",
+     "if (!(lam_min / (double)nsup >= o->min_eig) || nsup < 4) {", "if (!(lam_min / (double)nsup >= o->min_eig)) {"),
+    ("illumination model carrying a runaway gain to the next level",
+     "if (!bad && l > lstop && !(1.0 + m >= 0.25 && 1.0 + m <= 4.0)) bad = 1;", "(void)0;"),
+    ("cross region decided one pixel to the right of the point's cell",
+     "I[(int64_t)clampi(y0 + ky, 0, H - 1) * W + clampi(x0 + kx, 0, W - 1)];",
+     "I[(int64_t)clampi(y0 + ky, 0, H - 1) * W + clampi(x0 + kx + 1, 0, W - 1)];"),
     ("cross support without the erosion by the gradient stencil",
      "const uint8_t in = R[q] & R[q - 1] & R[q + 1] & R[q - e] & R[q + e];", "const uint8_t in = R[q];"),
     ("trackability divided by the window instead of the support",

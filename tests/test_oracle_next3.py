@@ -150,9 +150,13 @@ def _occluder_pair(t=(2, 1)):
 
 
 def _template_ext(I, p, s):
+    """The patch the tracker decides the cross region on: pixels at floor(p) + k, k in [-r-1, r+1]^2,
+    border replicated."""
     r = s // 2
-    return np.array([[oracle.bilinear(I.astype(np.float64), p[0] + kx, p[1] + ky) for kx in range(-r - 1, r + 2)]
-                     for ky in range(-r - 1, r + 2)])
+    H, W = I.shape
+    ys = np.clip(int(np.floor(p[1])) + np.arange(-r - 1, r + 2), 0, H - 1)
+    xs = np.clip(int(np.floor(p[0])) + np.arange(-r - 1, r + 2), 0, W - 1)
+    return I.astype(np.float64)[np.ix_(ys, xs)]
 
 
 def test_cross_support_excludes_a_changing_block_exactly():
