@@ -12,7 +12,11 @@ Prints ONE JSON line.  ``value`` is tracked points per second over the timed ste
 ``roofline`` object describes the dominant kernel (the tracker): its algorithmic FP32 work per
 launch (24 flops per executed support-pixel iteration, counted from the per-point iteration
 numbers the kernel reports) over its average duration measured with HIP events on the stream it
-runs on.  ``cpu_baseline`` times the FP64 CPU oracle on the same pair on the host cores.
+runs on.  ``achievable`` holds the on-box peak probes; ``kernels`` gives every kernel of every
+workload (the small translation pair, the benchmark pair, the 64-pair batch, the density stress)
+its roofline time from algorithmic counts against the nominal and the achievable peak, and each
+workload a sum-of-rooflines over measured time.  ``cpu_baseline`` times the FP64 CPU oracle on
+the host cores: the benchmark pair, and bounded samples of the other workloads.
 """
 from __future__ import annotations
 
@@ -31,6 +35,10 @@ METRIC = "tracked points/sec (DeGraF+RLOF) @1242x375; batched vs plain frame-pai
 FLOPS_PER_PIXEL_ITER = 24          # per support pixel per iteration: bilinear 7, residual 1, weight 3, psi 1, sums 12
 PEAK_FP32_VALU_TFLOPS = 78.6       # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, unpacked FP32
 PEAK_HBM_GBPS = 8000.0
+PEAK_LANE_INSTR = 39.3e12          # unpacked FP32 VALU issue: 256 CU x 64 lanes x 2.4 GHz
+INSTR_PER_PIXEL_ITER = 16          # algorithmic lane-instructions per pixel-iteration: bilinear 4 FMA (residual
+                                   # folded in), robust weight 4, w*g 2 mul, five accumulations 5 FMA, +1 slack
+C1 = dict(name="translation_256x128", W=256, H=128, window=9, stride=8, levels=3, support=9, iters=10)
 WORKLOAD = dict(name="driving_1242x375", W=1242, H=375, window=9, stride=5, levels=5, support=21, iters=20)
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "track_driving_1242x375_counters.md")
 TRACK_SOURCES = ["paper_1901_09971_amd/csrc/track.hip", "paper_1901_09971_amd/csrc/track_kernel.hpp",
@@ -79,7 +87,7 @@ def cpu_baseline(I0, I1, n_points, budget_s, seeds=None):
         oracle.track(I0, I1, pts, w["levels"], w["support"], w["iters"], threads=threads)
         reps += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or reps >= 3:
+        if el >= budget_s or reps >= 100:
             break
     # one thread on a bounded sample of the same pair (every 8th point)
     sub = np.ascontiguousarray(pts[::8])
@@ -108,10 +116,11 @@ def cpu_baseline(I0, I1, n_points, budget_s, seeds=None):
     return res
 
 
-def batched_vs_plain(reps: int):
+def batched_vs_plain(reps: int, peaks: dict | None = None):
     """Frame-pairs/s on the 64-pair mixed set (four sizes, strides 3/5/8; 5 levels, 21x21, 20
     iterations): per-pair launches (detect, 4 pyramid levels, track for each pair in turn) vs one
-    replay of the captured batched plan.  Same tracker launch shape in both."""
+    replay of the captured batched plan.  Same tracker launch shape in both.  The plan's two
+    halves (pyramids + detection, tracking) are also timed on their own for their rooflines."""
     import torch
 
     import paper_1901_09971_amd as dgf
@@ -161,18 +170,26 @@ def batched_vs_plain(reps: int):
 
     t_plain = timed(plain, side)
     t_batch = timed(plan.replay, side)
+    t_front = timed(plan.front, side)
+    t_track = timed(plan.track, side)
     # the two forms must agree exactly
     P = torch.cat([B["p"] for B in bufs])
     S = torch.cat([B["s"] for B in bufs])
     identical = bool(torch.equal(P, plan.points) and torch.equal(S, plan.status))
     npts = plan.num_points
     plan.close()
+    fb = sum(front_bytes(a.shape[1], a.shape[0], L_, B["p"].shape[0]) for (a, _, _, _), B in zip(pairs, bufs))
+    kern = {"front": roof("hbm", fb, t_front, peaks),
+            "track": roof("alu", pix_iters * FLOPS_PER_PIXEL_ITER, t_track, peaks, pix_iters)}
+    kern["front"]["kernels"] = "k_pyr_down_batched<u8> x 4 levels, k_detect_batched<16,16>"
+    kern["track"]["kernel"] = "k_track_run<64,1,7,31,21,u8,IM=0,HAMPEL,CROSS=0,BATCH=1> (persistent)"
     return {"pairs": len(pairs), "points": npts, "reps": reps,
             "plain_ms": t_plain, "batched_ms": t_batch,
             "plain_pairs_per_s": len(pairs) / (t_plain * 1e-3),
             "batched_pairs_per_s": len(pairs) / (t_batch * 1e-3),
             "speedup": t_plain / t_batch, "identical_outputs": identical,
             "batched_track_tflops_lower_bound": pix_iters * FLOPS_PER_PIXEL_ITER / (t_batch * 1e-3) / 1e12,
+            "kernels": kern, "sigma_roofline": sigma_roofline(kern, t_batch),
             "workload": "batch64_mixed: 16 each of 1242x375, 1224x370, 640x480, 320x240, strides {3,5,8}"}
 
 
@@ -335,7 +352,7 @@ DENSITY = dict(name="density_2048x1024x4", W=2048, H=1024, pairs=4, window=9, st
                iters=20)
 
 
-def density_stress(reps: int):
+def density_stress(reps: int, peaks: dict | None = None):
     """Density stress: four 2048x1024 uint8 pairs (layered affine motion up to 250 px, seeds 0-3),
     DeGraF window 9 stride 2 (518,160 points each), 6 levels, 21x21 support, 20 iterations.
     Forward: one replay of the captured batched plan (detect, pyramids, track of all four pairs).
@@ -393,6 +410,8 @@ def density_stress(reps: int):
         return e0.elapsed_time(e1) / reps
 
     t_fwd = timed(plan.replay)
+    t_front = timed(plan.front)
+    t_track = timed(plan.track)
     t_bwd = timed(lambda: plan.backward(dflow, grad))
     # dense interpolation of the first pair's tracked points (the call synchronises: host clock)
     lo, hi = plan.offsets[0], plan.offsets[1]
@@ -408,7 +427,17 @@ def density_stress(reps: int):
         e_times.append(time.perf_counter() - t0)
     plan.close()
     n_conv = int(conv.sum().item())
+    per_pair = n // c["pairs"]
+    kern = {"front": roof("hbm", c["pairs"] * front_bytes(c["W"], c["H"], c["levels"], per_pair), t_front, peaks),
+            "track": roof("alu", pix_iters * FLOPS_PER_PIXEL_ITER, t_track, peaks, pix_iters)}
+    # adjoint: reads both frames and the point data, writes both gradient maps (cleared first)
+    adj_bytes = c["pairs"] * (2 * c["W"] * c["H"] + 2 * 2 * 4 * c["W"] * c["H"]) + n * (8 + 8 + 8 + 1)
+    adj = roof("hbm", adj_bytes, t_bwd, peaks)
+    adj["tap_adds_per_s"] = n_conv * c["support"] ** 2 * 10 / (t_bwd * 1e-3)
+    adj["what"] = ("bytes: frames read, both gradient maps cleared and written, points/flow/dflow/status read; "
+                   "tap adds: 10 per support pixel per converged point (the scatter)")
     return {"workload": c["name"], "pairs": c["pairs"], "points": n, "levels": c["levels"],
+            "kernels": dict(kern, adjoint=adj), "sigma_roofline_forward": sigma_roofline(kern, t_fwd),
             "support": c["support"], "max_iters": c["iters"], "reps": reps, "status_counts": st_counts,
             "forward_ms": t_fwd, "forward_points_per_s": n / (t_fwd * 1e-3),
             "forward_track_tflops_lower_bound": pix_iters * FLOPS_PER_PIXEL_ITER / (t_fwd * 1e-3) / 1e12,
@@ -486,6 +515,280 @@ def copy_calibration(mib: int):
     print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 3}))
 
 
+def front_bytes(W: int, H: int, levels: int, n_points: int) -> int:
+    """Algorithmic HBM bytes of detection and both pyramids of one pair (per-kernel counts: the
+    detector reads the frame and writes 8 B per point; each pyramid reads every level but the
+    coarsest and writes every level but the finest)."""
+    pyr = 0
+    Wl, Hl = W, H
+    for _ in range(levels - 1):
+        pyr += Wl * Hl
+        Wl, Hl = (Wl + 1) // 2, (Hl + 1) // 2
+        pyr += Wl * Hl
+    return W * H + 8 * n_points + 2 * pyr
+
+
+def roof(bound: str, amount: float, ms: float, peaks: dict | None, pixel_iters: int | None = None) -> dict:
+    """One kernel against its roof: ``amount`` algorithmic bytes (hbm) or flops (alu) per launch
+    over ``ms`` per launch, with the roofline time at the nominal and the achievable peak."""
+    if bound == "hbm":
+        nominal, achievable = PEAK_HBM_GBPS * 1e9, (peaks["hbm_copy_gbps"] * 1e9 if peaks else None)
+        unit = "bytes"
+    else:
+        nominal, achievable = PEAK_FP32_VALU_TFLOPS * 1e12, (peaks["fp32_fma_tflops"] * 1e12 if peaks else None)
+        unit = "flops"
+    r = {"bound": bound, "ms": ms, "algorithmic": amount, "unit": unit,
+         "roofline_ms_nominal": amount / nominal * 1e3, "frac_nominal": amount / nominal * 1e3 / ms}
+    if achievable:
+        r["roofline_ms_achievable"] = amount / achievable * 1e3
+        r["frac_achievable"] = amount / achievable * 1e3 / ms
+    if pixel_iters is not None:
+        # instruction-issue form: the algorithmic lane-instructions at the unpacked issue rate
+        r["issue_frac_nominal"] = pixel_iters * INSTR_PER_PIXEL_ITER / PEAK_LANE_INSTR * 1e3 / ms
+        if peaks:
+            r["issue_frac_achievable"] = (pixel_iters * INSTR_PER_PIXEL_ITER / (peaks["fp32_fma_tflops"] * 1e12 / 2)
+                                          * 1e3 / ms)
+    return r
+
+
+def sigma_roofline(kernels: dict, total_ms: float) -> dict:
+    """Sum over kernels of their roofline times, over the measured total."""
+    out = {"measured_ms": total_ms}
+    for key in ("nominal", "achievable"):
+        vals = [k.get("roofline_ms_" + key) for k in kernels.values()]
+        if all(v is not None for v in vals):
+            out["sum_roofline_ms_" + key] = sum(vals)
+            out["frac_" + key] = sum(vals) / total_ms
+    return out
+
+
+def track_kernel_name(tuning: dict | None, support: int, dtype: str = "u8", illum: bool = False,
+                      cross: bool = False, batch: bool = False) -> str:
+    """The instantiation that runs for a tuning: row-run k_track_run<lanes, runs per lane, run length,
+    tile pitch, support, pixel type, illum, robust norm, cross, batch> or the generic k_track."""
+    t = tuning or {}
+    lpp = int(t.get("lanes_per_point", 64))
+    if int(t.get("kernel", 0)) == 0 and support == 21:
+        seg = {64: 1, 32: 2, 16: 4}[lpp]
+        return (f"k_track_run<{lpp},{seg},7,31,21,{dtype},IM={int(illum)},HAMPEL,CROSS={int(cross)},"
+                f"BATCH={int(batch)}>")
+    return f"k_track<{lpp},...,{dtype}>"
+
+
+def lscpu_info() -> dict:
+    import subprocess
+    info = {}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return info
+    keys = {"Model name": "cpu_model", "CPU(s)": "logical_cpus", "Thread(s) per core": "threads_per_core",
+            "Core(s) per socket": "cores_per_socket", "Socket(s)": "sockets"}
+    for ln in txt.splitlines():
+        k, _, v = ln.partition(":")
+        if k.strip() in keys:
+            info[keys[k.strip()]] = v.strip()
+    return info
+
+
+def c1_step(steps: int, warmup: int, peaks: dict | None):
+    """The small translation pair (256x128, window 9 stride 8: 465 points; 3 levels, 9x9, 10
+    iterations): the same two-launch step as the benchmark pair, HIP events."""
+    import numpy as np
+    import torch
+
+    import paper_1901_09971_amd as dgf
+    from paper_1901_09971_amd import synth
+
+    c = C1
+    I0n, I1n, _ = synth.translation_256x128()
+    dev = torch.device("cuda", 0)
+    I0, I1 = torch.from_numpy(I0n).to(dev), torch.from_numpy(I1n).to(dev)
+    N = dgf.detect_count(c["W"], c["H"], c["window"], c["stride"])
+    pts = torch.empty((N, 2), dtype=torch.float32, device=dev)
+    flow = torch.empty((N, 2), dtype=torch.float32, device=dev)
+    status = torch.empty(N, dtype=torch.uint8, device=dev)
+    its = torch.empty(N, dtype=torch.int32, device=dev)
+    ws = torch.empty(dgf.track_workspace_bytes(c["W"], c["H"], c["levels"], 0), dtype=torch.uint8, device=dev)
+
+    def front():
+        dgf.detect_pyramids(I0, I1, c["window"], c["stride"], c["levels"], ws, pts)
+
+    def track(io=None):
+        dgf.track_run(I0, I1, pts, c["levels"], c["support"], c["iters"], ws, flow, status, io)
+
+    front()
+    track(its)
+    torch.cuda.synchronize()
+    pix_iters = int(its.to(torch.int64).sum().item()) * c["support"] ** 2
+    for _ in range(warmup):
+        front()
+        track()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for e in ev:
+        front()
+        e[0].record()
+        track()
+        e[1].record()
+    end.record()
+    torch.cuda.synchronize()
+    ms_step = start.elapsed_time(end) / steps
+    t_track = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
+    t_front = (start.elapsed_time(ev[0][0]) + sum(ev[k - 1][1].elapsed_time(ev[k][0]) for k in range(1, steps))) / steps
+    kern = {"front": roof("hbm", front_bytes(c["W"], c["H"], c["levels"], N), t_front, peaks),
+            "track": roof("alu", pix_iters * FLOPS_PER_PIXEL_ITER, t_track, peaks, pix_iters)}
+    return {"workload": c["name"], "points": N, "steps": steps, "ms_per_step": ms_step,
+            "points_per_s": N / (ms_step * 1e-3), "status_counts": np.bincount(status.cpu().numpy(),
+                                                                                minlength=4).tolist(),
+            "kernels": kern, "sigma_roofline": sigma_roofline(kern, ms_step)}
+
+
+def im_gm(steps: int, warmup: int, plain: dict | None):
+    """RLOF(IM-GM) on the benchmark pair (illumination model, cross-based supports, global prior):
+    detection with the pyramids, then tracking (its coarsest-level pass, the global fit and the
+    tracking proper), HIP events; status counts, the error of the converged points and of their
+    dense interpolation against the synthetic ground truth, beside the plain tracker's."""
+    import numpy as np
+    import torch
+
+    import paper_1901_09971_amd as dgf
+    from paper_1901_09971_amd import synth
+
+    w = WORKLOAD
+    I0n, I1n, gt, occ = synth.driving_1242x375()
+    dev = torch.device("cuda", 0)
+    I0, I1 = torch.from_numpy(I0n).to(dev), torch.from_numpy(I1n).to(dev)
+    N = dgf.detect_count(w["W"], w["H"], w["window"], w["stride"])
+    pts = torch.empty((N, 2), dtype=torch.float32, device=dev)
+    flow = torch.empty((N, 2), dtype=torch.float32, device=dev)
+    status = torch.empty(N, dtype=torch.uint8, device=dev)
+    ws = torch.empty(dgf.track_workspace_bytes(w["W"], w["H"], w["levels"], 0), dtype=torch.uint8, device=dev)
+    opts = dgf.TrackOpts(illum=True, cross=True, global_motion=True)
+
+    def step():
+        dgf.detect_pyramids(I0, I1, w["window"], w["stride"], w["levels"], ws, pts)
+        e0.record()
+        dgf.track_run(I0, I1, pts, w["levels"], w["support"], w["iters"], ws, flow, status, opts=opts)
+        e1.record()
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    tt, ts = [], []
+    for _ in range(steps):
+        s0 = torch.cuda.Event(enable_timing=True)
+        s0.record()
+        step()
+        torch.cuda.synchronize()
+        tt.append(e0.elapsed_time(e1))
+        ts.append(s0.elapsed_time(e1))
+    P, F, S = pts.cpu().numpy(), flow.cpu().numpy(), status.cpu().numpy()
+    conv = S == 0
+    xi = np.clip(np.rint(P[conv, 0]).astype(np.int64), 0, w["W"] - 1)
+    yi = np.clip(np.rint(P[conv, 1]).astype(np.int64), 0, w["H"] - 1)
+    sparse_err = np.linalg.norm(F[conv] - gt[yi, xi], axis=-1)
+    dense = dgf.epic(I0, pts, flow, status).cpu().numpy().astype(np.float64)
+    err = np.linalg.norm(dense - gt, axis=-1)[~occ]
+    out = {"workload": "driving_1242x375, illumination model + cross-based supports + global prior",
+           "points": N, "ms_per_step": float(np.median(ts)), "track_ms": float(np.median(tt)),
+           "points_per_s": N / (float(np.median(ts)) * 1e-3),
+           "status_counts": np.bincount(S, minlength=4).tolist(),
+           "seed_epe_px": float(sparse_err.mean()), "seed_median_err_px": float(np.median(sparse_err)),
+           "dense_epe_noc_px": float(err.mean()), "dense_outliers_3px_noc": float((err > 3.0).mean())}
+    if plain:
+        out["plain"] = plain
+    # each option on its own (status counts and the converged points' error, untimed)
+    variants = {}
+    for name, o in (("global_motion", dgf.TrackOpts(global_motion=True)), ("cross", dgf.TrackOpts(cross=True)),
+                    ("illum", dgf.TrackOpts(illum=True))):
+        dgf.track_run(I0, I1, pts, w["levels"], w["support"], w["iters"], ws, flow, status, opts=o)
+        F, S = flow.cpu().numpy(), status.cpu().numpy()
+        ok = S == 0
+        e = np.linalg.norm(F[ok] - gt[np.clip(np.rint(P[ok, 1]).astype(np.int64), 0, w["H"] - 1),
+                                      np.clip(np.rint(P[ok, 0]).astype(np.int64), 0, w["W"] - 1)], axis=-1)
+        variants[name] = {"status_counts": np.bincount(S, minlength=4).tolist(), "seed_epe_px": float(e.mean()),
+                          "seeds_within_1px": int((e < 1.0).sum())}
+    out["single_options"] = variants
+    return out
+
+
+def oracle_timings(budget_s: float):
+    """The FP64 oracle on the host cores beside the GPU workloads: the small translation pair
+    (median of 5), one pair of each size of the 64-pair batch, the differentiation crop (forward
+    and gradient, median of 5) and a strided sample of one density-stress pair (1 run), each as
+    points per second.  Bounded: every entry is a sample of a few seconds at most."""
+    import numpy as np
+
+    import oracle
+    from paper_1901_09971_amd import synth
+
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    thr = min(int(os.environ.get("OMP_NUM_THREADS", cores)), cores)
+    res = {"threads": thr}
+    c = C1
+    I0, I1, _ = synth.translation_256x128()
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        pts = oracle.detect(I0, c["window"], c["stride"], threads=thr)[0]
+        oracle.track(I0, I1, pts, c["levels"], c["support"], c["iters"], threads=thr)
+        ts.append(time.perf_counter() - t0)
+    res["translation_256x128"] = {"points": len(pts), "median_s": float(np.median(ts)),
+                                  "points_per_s": len(pts) / float(np.median(ts)), "runs": 5}
+    # one pair of each size of the 64-pair set (pairs 0-3), detect + track, one run
+    strides = np.random.default_rng(0).choice([3, 5, 8], size=64)  # as synth.batch64_mixed draws them
+    data = []
+    for i, (W, H) in enumerate([(1242, 375), (1224, 370), (640, 480), (320, 240)]):
+        a, b, _, _ = synth.layered_pair(W, H, seed=i, max_disp=150.0 * W / 1242.0)
+        data.append(dict(I0=a, I1=b, stride=int(strides[i])))
+    t0 = time.perf_counter()
+    n = 0
+    for d in data:
+        p = oracle.detect(d["I0"], 9, d["stride"], threads=thr)[0]
+        oracle.track(d["I0"], d["I1"], p, 5, 21, 20, threads=thr)
+        n += len(p)
+    el = time.perf_counter() - t0
+    res["batch64_mixed_sample"] = {"sample": "pairs 0-3 (one of each size), detect + track", "points": n,
+                                   "s": el, "points_per_s": n / el}
+    # differentiation crop: 128x64 at (0, 0), window 9 stride 6 (200 points), forward + gradient
+    I0f, I1f, gt = synth.translation_f32_1242x375()
+    a0, a1 = np.ascontiguousarray(I0f[:64, :128]), np.ascontiguousarray(I1f[:64, :128])
+    u8 = np.clip(np.rint(a0), 0, 255).astype(np.uint8)
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        p = oracle.detect(u8, 9, 6, threads=thr)[0]
+        f, st = oracle.track(a0, a1, p, 3, 9, 10, threads=thr)
+        df = np.where((st == 0)[:, None], 2.0 * (f - np.asarray(gt, np.float64)), 0.0)
+        oracle.track_grad(a0, a1, p, 9, f, st, df)
+        ts.append(time.perf_counter() - t0)
+    res["differentiation_crop_128x64"] = {"points": len(p), "median_s": float(np.median(ts)),
+                                          "points_per_s": len(p) / float(np.median(ts)), "runs": 5,
+                                          "what": "detect + track + implicit gradient (FP64)"}
+    # density stress: every 64th point of pair 0, one run
+    D0, D1, _, _ = synth.density_2048x1024(0)
+    t0 = time.perf_counter()
+    p = oracle.detect(D0, 9, 2, threads=thr)[0]
+    t_det = time.perf_counter() - t0
+    sub = np.ascontiguousarray(p[::64])
+    t1 = time.perf_counter()
+    oracle.track(D0, D1, sub, 6, 21, 20, threads=thr)
+    t_trk = time.perf_counter() - t1
+    res["density_2048x1024_sample"] = {"sample": f"detect all {len(p)} windows of pair 0, track every 64th point "
+                                                 f"({len(sub)}), one run",
+                                       "detect_s": t_det, "track_s": t_trk,
+                                       "track_points_per_s": len(sub) / t_trk,
+                                       "detect_points_per_s": len(p) / t_det}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -501,6 +804,10 @@ def main():
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation measurement")
     ap.add_argument("--density-reps", type=int, default=3)
     ap.add_argument("--no-interp", action="store_true", help="skip the dense interpolation measurement")
+    ap.add_argument("--no-c1", action="store_true", help="skip the small translation pair")
+    ap.add_argument("--no-imgm", action="store_true", help="skip the RLOF(IM-GM) measurement")
+    ap.add_argument("--no-oracle-timings", action="store_true",
+                    help="skip the oracle samples of the other workloads (the benchmark pair's stays)")
     ap.add_argument("--separate-detect", action="store_true",
                     help="step as three launches (detect, pyramids, track) instead of detect+pyramids, track")
     ap.add_argument("--no-peaks", action="store_true", help="skip the achievable-peak probes")
@@ -526,6 +833,7 @@ def main():
     import paper_1901_09971_amd as dgf
     from paper_1901_09971_amd import synth
 
+    peaks = None if args.no_peaks else achievable_peaks()
     w = WORKLOAD
     I0n, I1n, _, _ = synth.driving_1242x375()
     dev = torch.device("cuda", 0)
@@ -598,13 +906,16 @@ def main():
     flops = pix_iters * FLOPS_PER_PIXEL_ITER
     achieved = flops / (t_track * 1e-3) / 1e12
     traffic = counter_traffic()
-    det_bytes = w["W"] * w["H"] + 8 * N
-    pyr_read = pyr_write = 0
-    Wl, Hl = w["W"], w["H"]
-    for _ in range(w["levels"] - 1):
-        pyr_read += 2 * Wl * Hl
-        Wl, Hl = (Wl + 1) // 2, (Hl + 1) // 2
-        pyr_write += 2 * Wl * Hl
+    fbytes = front_bytes(w["W"], w["H"], w["levels"], N)
+    kname = track_kernel_name(tuning, w["support"])
+    k_front = roof("hbm", fbytes, t_front, peaks)
+    k_front.update({"what": ("detection beside both pyramids, one launch (k_front_u8) and the chain launch of the "
+                             "last level" if fused else "detection, then both pyramids"),
+                    "timed_as": "previous tracking end to tracking start (launch gaps included)",
+                    "chain_launches": (w["levels"] + 2) // 4})
+    k_track = roof("alu", flops, t_track, peaks, pix_iters)
+    k_track.update({"kernel": kname, "iterations": it_total, "status_counts": st_counts, "tuning": tuning})
+    c2_kernels = {"front": k_front, "track": k_track}
     out = {
         "metric": METRIC,
         "value": N / (ms_step * 1e-3),
@@ -624,7 +935,7 @@ def main():
                    "max_iters": w["iters"], "input": "uint8 pair, layered affine motion up to 150 px"},
         "roofline": {
             "bound": "alu",
-            "kernel": "k_track",
+            "kernel": kname,
             "achieved": achieved,
             "peak": PEAK_FP32_VALU_TFLOPS,
             "unit": "TFLOP/s",
@@ -633,31 +944,37 @@ def main():
             "algorithmic_flops_per_launch": flops,
             "pixel_iterations_per_launch": pix_iters,
             "track_ms": t_track,
+            "frac_of_achievable": k_track.get("frac_achievable"),
+            "issue_frac": k_track["issue_frac_nominal"],
         },
-        "kernels": {
-            "front": {"ms": t_front, "what": ("detection beside both pyramids, one launch" if fused else
-                                              "detection, then both pyramids: two launches"),
-                      "timed_as": "previous tracking end to tracking start (launch gaps included)",
-                      "chain_launches": (w["levels"] + 2) // 4,
-                      "algorithmic_bytes": pyr_read + pyr_write + det_bytes,
-                      "hbm_frac": (pyr_read + pyr_write + det_bytes) / (t_front * 1e-3) / (PEAK_HBM_GBPS * 1e9)},
-            "track": {"ms": t_track, "iterations": it_total, "status_counts": st_counts, "tuning": tuning},
-        },
+        "achievable": peaks,
+        "kernels": {"driving_1242x375": dict(c2_kernels, sigma_roofline=sigma_roofline(c2_kernels, ms_step))},
         "host_wall_s": t_host,
     }
+    if not args.no_c1:
+        out["kernels"]["translation_256x128"] = c1_step(args.steps, args.warmup, peaks)
     if not args.no_batch:
-        out["batched"] = batched_vs_plain(args.batch_reps)
+        out["batched"] = batched_vs_plain(args.batch_reps, peaks)
     if not args.no_illum:
         out["illumination"] = illumination(args.steps, args.warmup)
     if not args.no_diff:
         out["differentiation"] = differentiation(args.steps)
     if not args.no_density:
-        out["density"] = density_stress(args.density_reps)
+        out["density"] = density_stress(args.density_reps, peaks)
     seeds = None
+    plain_acc = None
     if not args.no_interp:
         out["interpolation"], seeds = interpolation(max(3, min(args.steps, 20)))
+        plain_acc = {"status_counts": st_counts, "seed_epe_px": out["interpolation"]["seed_epe_px"],
+                     "dense_epe_noc_px": out["interpolation"]["epe_noc_px"],
+                     "dense_outliers_3px_noc": out["interpolation"]["outliers_3px_noc"]}
+    if not args.no_imgm:
+        out["rlof_im_gm"] = im_gm(max(5, min(args.steps, 20)), 3, plain_acc)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(I0n, I1n, N, args.cpu_budget_s, seeds)
+        out["cpu_baseline"].update(lscpu_info())
+        if not args.no_oracle_timings:
+            out["cpu_baseline"]["other_workloads"] = oracle_timings(args.cpu_budget_s)
     print(json.dumps(out))
 
 

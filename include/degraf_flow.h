@@ -326,6 +326,16 @@ int dgf_batch_point_offsets(const dgf_batch *b, int64_t *offsets);
 int dgf_batch_run(dgf_batch *b, float *points, float *flow, uint8_t *status, int32_t *iters_out, float *illum_out,
                   void *stream);
 
+/* The two halves of dgf_batch_run, for callers that time, overlap or separate them (same
+ * arguments; dgf_batch_run is exactly dgf_batch_front then dgf_batch_track on one stream):
+ * dgf_batch_front builds every pair's pyramids into the plan and detects every pair's points
+ * (Section 2 "Point detection"); dgf_batch_track tracks the points it is given from the pyramids
+ * the last front call built (Section 2 "Sparse point tracking"), and may be given other points of
+ * the same count (the plan's per-pair point ranges). */
+int dgf_batch_front(dgf_batch *b, float *points, void *stream);
+int dgf_batch_track(dgf_batch *b, const float *points, float *flow, uint8_t *status, int32_t *iters_out,
+                    float *illum_out, void *stream);
+
 /* Captures the run sequence (with these output pointers) into a HIP graph on `stream` (a created
  * stream, not the default one); dgf_batch_replay launches it with one call.  A new capture
  * replaces the previous graph. */

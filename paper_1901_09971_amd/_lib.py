@@ -81,6 +81,8 @@ SIGNATURES = {
     "dgf_batch_num_points": (I64, [P]),
     "dgf_batch_point_offsets": (ctypes.c_int, [P, P]),
     "dgf_batch_run": (ctypes.c_int, [P, P, P, P, P, P, P]),
+    "dgf_batch_front": (ctypes.c_int, [P, P, P]),
+    "dgf_batch_track": (ctypes.c_int, [P, P, P, P, P, P, P]),
     "dgf_batch_capture": (ctypes.c_int, [P, P, P, P, P, P]),
     "dgf_batch_replay": (ctypes.c_int, [P, P]),
     "dgf_batch_grad_size": (I64, [P, P]),

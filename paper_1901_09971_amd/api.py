@@ -459,6 +459,21 @@ class Batch:
                                   _ptr(self.illum), _stream()), "dgf_batch_run")
         return self.points, self.flow, self.status
 
+    def front(self):
+        """First half of :meth:`run`: every pair's pyramids and points (into ``self.points``)."""
+        check(lib().dgf_batch_front(self._h, _ptr(self.points), _stream()), "dgf_batch_front")
+        return self.points
+
+    def track(self, points: torch.Tensor | None = None, iters_out: torch.Tensor | None = None):
+        """Second half of :meth:`run`: track ``points`` (default: the plan's own, as the last
+        :meth:`front` detected them) on the pyramids of the last :meth:`front`."""
+        p = self.points if points is None else points
+        if p.shape != self.points.shape or p.dtype != torch.float32 or not p.is_contiguous():
+            raise ValueError("points: expected a contiguous float32 tensor of the plan's point count")
+        check(lib().dgf_batch_track(self._h, _ptr(p), _ptr(self.flow), _ptr(self.status), _ptr(iters_out),
+                                    _ptr(self.illum), _stream()), "dgf_batch_track")
+        return self.flow, self.status
+
     def capture(self):
         """Capture the run into a HIP graph on the current (non-default) stream."""
         check(lib().dgf_batch_capture(self._h, _ptr(self.points), _ptr(self.flow), _ptr(self.status),

@@ -78,8 +78,8 @@ bool pair_ok(const dgf_pair_desc &d, int dtype)
            d.window <= DGF_MAX_WINDOW && d.stride >= 1;
 }
 
-int launch_all(dgf_batch *b, float *points, float *flow, uint8_t *status, int32_t *iters_out, float *illum_out,
-               hipStream_t st)
+// Pyramids of every frame, then detection of every pair.
+int launch_front(dgf_batch *b, float *points, hipStream_t st)
 {
     for (int l = 1; l < b->L; ++l) {
         if (launch_pyr_level_batched(b->d_pyr + (size_t)(l - 1) * 2 * b->P, 2 * b->P, b->pyr_w2[l], b->pyr_h2[l], b->dtype,
@@ -88,6 +88,14 @@ int launch_all(dgf_batch *b, float *points, float *flow, uint8_t *status, int32_
     }
     if (launch_detect_batched(b->d_det, b->P, b->det_tiles_x, b->det_tiles_y, b->det_lds, points, st) != hipSuccess)
         return DGF_ERR_HIP;
+    return DGF_OK;
+}
+
+// Work counters, then the persistent tracking launch (with the global prior: its first pass, the
+// fit and fresh counters before it).
+int launch_track_all(dgf_batch *b, const float *points, float *flow, uint8_t *status, int32_t *iters_out,
+                     float *illum_out, hipStream_t st)
+{
     hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(kNumXcd), 0, st, b->d_counter);
     if (hipGetLastError() != hipSuccess) return DGF_ERR_HIP;
     TrackParams P{};
@@ -137,6 +145,21 @@ int launch_all(dgf_batch *b, float *points, float *flow, uint8_t *status, int32_
         P.illum_out = illum_out;
     }
     return launch_track(P, b->tune, b->dtype, st) == hipSuccess ? DGF_OK : DGF_ERR_HIP;
+}
+
+int launch_all(dgf_batch *b, float *points, float *flow, uint8_t *status, int32_t *iters_out, float *illum_out,
+               hipStream_t st)
+{
+    const int rc = launch_front(b, points, st);
+    return rc != DGF_OK ? rc : launch_track_all(b, points, flow, status, iters_out, illum_out, st);
+}
+
+int check_run(const dgf_batch *b, const float *points, const float *flow, const uint8_t *status, const float *illum_out)
+{
+    if (!b) return DGF_ERR_INVALID_ARG;
+    if (b->total_pts > 0 && (!points || !flow || !status)) return DGF_ERR_INVALID_ARG;
+    if (illum_out && !(b->opts.flags & DGF_TRACK_ILLUM)) return DGF_ERR_INVALID_ARG;
+    return DGF_OK;
 }
 
 } // namespace
@@ -327,18 +350,32 @@ int dgf_batch_point_offsets(const dgf_batch *b, int64_t *offsets)
 int dgf_batch_run(dgf_batch *b, float *points, float *flow, uint8_t *status, int32_t *iters_out, float *illum_out,
                   void *stream)
 {
-    if (!b) return DGF_ERR_INVALID_ARG;
-    if (b->total_pts > 0 && (!points || !flow || !status)) return DGF_ERR_INVALID_ARG;
-    if (illum_out && !(b->opts.flags & DGF_TRACK_ILLUM)) return DGF_ERR_INVALID_ARG;
-    if (b->total_pts == 0) return DGF_OK;
+    const int rc = check_run(b, points, flow, status, illum_out);
+    if (rc != DGF_OK || b->total_pts == 0) return rc;
     return launch_all(b, points, flow, status, iters_out, illum_out, (hipStream_t)stream);
+}
+
+int dgf_batch_front(dgf_batch *b, float *points, void *stream)
+{
+    if (!b) return DGF_ERR_INVALID_ARG;
+    if (b->total_pts > 0 && !points) return DGF_ERR_INVALID_ARG;
+    if (b->total_pts == 0) return DGF_OK;
+    return launch_front(b, points, (hipStream_t)stream);
+}
+
+int dgf_batch_track(dgf_batch *b, const float *points, float *flow, uint8_t *status, int32_t *iters_out,
+                    float *illum_out, void *stream)
+{
+    const int rc = check_run(b, points, flow, status, illum_out);
+    if (rc != DGF_OK || b->total_pts == 0) return rc;
+    return launch_track_all(b, points, flow, status, iters_out, illum_out, (hipStream_t)stream);
 }
 
 int dgf_batch_capture(dgf_batch *b, float *points, float *flow, uint8_t *status, float *illum_out, void *stream)
 {
     if (!b || !stream) return DGF_ERR_INVALID_ARG; // graphs are captured from a created stream
-    if (b->total_pts > 0 && (!points || !flow || !status)) return DGF_ERR_INVALID_ARG;
-    if (illum_out && !(b->opts.flags & DGF_TRACK_ILLUM)) return DGF_ERR_INVALID_ARG;
+    const int crc = check_run(b, points, flow, status, illum_out);
+    if (crc != DGF_OK) return crc;
     if (b->exec) {
         (void)hipGraphExecDestroy(b->exec);
         b->exec = nullptr;

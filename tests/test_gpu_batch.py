@@ -156,3 +156,19 @@ def test_track_batched_convenience_equals_per_pair():
         assert torch.equal(P, p) and torch.equal(S, s)
         fin = torch.isfinite(f)
         assert torch.equal(F[fin], f[fin])
+
+
+def test_front_then_track_equals_run():
+    pairs = _pairs(6)
+    plan = dgf.Batch(pairs, 4, 21, 20)
+    P, F, S = [t.clone() for t in plan.run()]
+    plan.points.zero_()
+    plan.flow.zero_()
+    plan.status.fill_(255)
+    plan.front()
+    plan.track()
+    torch.cuda.synchronize()
+    assert torch.equal(plan.points, P) and torch.equal(plan.status, S)
+    fin = torch.isfinite(F)
+    assert torch.equal(torch.isfinite(plan.flow), fin) and torch.equal(plan.flow[fin], F[fin])
+    plan.close()
