@@ -58,8 +58,15 @@ bool shape_compiled(int lpp, int ppl, int tp)
 
 int tile_pitch(int s) { return s <= 21 ? 32 : 64; }
 
-// I1 tile pitch of the row-run kernel (odd, see DGF_TRACK_RUN_SHAPES)
-constexpr int kRunPitch = 31;
+// I1 tile pitch of a row-run shape (see DGF_TRACK_RUN_SHAPES)
+int run_shape_pitch(int lpp, int s)
+{
+#define DGF_HAS(L_, SEG_, R_, TP_, S_, X_)                                                                             \
+    if (lpp == L_ && s == S_) return TP_;
+    DGF_TRACK_RUN_SHAPES(DGF_HAS, float)
+#undef DGF_HAS
+    return 0;
+}
 
 // Row pitch of the raw / resampled I0 tiles: s + 3, moved off multiples of 4 so that the rows
 // touched by one wavefront land in different LDS banks.
@@ -89,7 +96,7 @@ int clamp_margin(int s, int margin, int tp)
 
 void fill_track_geometry(TrackParams &P, int s, int margin, int lpp, int kind)
 {
-    const int tp = (kind == 0 && run_shape_compiled(lpp, s)) ? kRunPitch : tile_pitch(s);
+    const int tp = (kind == 0 && run_shape_compiled(lpp, s)) ? run_shape_pitch(lpp, s) : tile_pitch(s);
     P.s = s;
     P.r = s / 2;
     P.M = clamp_margin(s, margin, tp);

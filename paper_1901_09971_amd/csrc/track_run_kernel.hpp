@@ -660,9 +660,6 @@ hipError_t launch_track_run_t(const TrackParams &P, int wpb, hipStream_t st)
     return hipGetLastError();
 }
 
-// Row-run shapes compiled per element type: (LPP, SEG, R, TP, support s).  SEG runs of R pixels
-// per lane cover the s * (s / R) runs of an s x s support.  The odd tile pitch TP = 31 spreads
-// the runs of consecutive rows over different LDS banks (a pitch of 32 maps them onto 3).
 // Dispatcher of one instantiation file: element type, cross-based supports or not, single pair
 // or batch plan; the support shape and the illumination model are picked at run time.
 #define DGF_DEFINE_TRACK_RUN_LAUNCH(NAME, PIXT, CROSS, BATCH)                                                          \
@@ -680,6 +677,11 @@ hipError_t launch_track_run_t(const TrackParams &P, int wpb, hipStream_t st)
 #define DGF_TRACK_RUN_CASE_true_false(L_, SEG_, R_, TP_, S_, X_) DGF_TRACK_RUN_CASE(L_, SEG_, R_, TP_, S_, X_, true, false)
 #define DGF_TRACK_RUN_CASE_true_true(L_, SEG_, R_, TP_, S_, X_) DGF_TRACK_RUN_CASE(L_, SEG_, R_, TP_, S_, X_, true, true)
 
+// Row-run shapes compiled per element type: (LPP, SEG, R, TP, support s).  SEG runs of R pixels
+// per lane cover the s * (s / R) runs of an s x s support.  The odd tile pitch TP = 31 spreads
+// the runs of consecutive rows over different LDS banks (a pitch of 32 maps them onto 3;
+// a pitch of 43, conflict-free for the 64-lane form in a bank model, measured slower and no fewer
+// conflict cycles).
 #define DGF_TRACK_RUN_SHAPES(X, PixT)                                                                                  \
     X(64, 1, 7, 31, 21, PixT) X(32, 2, 7, 31, 21, PixT) X(16, 4, 7, 31, 21, PixT) X(32, 1, 3, 31, 9, PixT)             \
     X(16, 2, 3, 31, 9, PixT) X(32, 2, 5, 31, 15, PixT) X(16, 3, 5, 31, 15, PixT) X(16, 1, 11, 31, 11, PixT)           \
