@@ -181,7 +181,7 @@ def batched_vs_plain(reps: int, peaks: dict | None = None):
     fb = sum(front_bytes(a.shape[1], a.shape[0], L_, B["p"].shape[0]) for (a, _, _, _), B in zip(pairs, bufs))
     kern = {"front": roof("hbm", fb, t_front, peaks),
             "track": roof("alu", pix_iters * FLOPS_PER_PIXEL_ITER, t_track, peaks, pix_iters)}
-    kern["front"]["kernels"] = "k_pyr_down_batched<u8> x 4 levels, k_detect_batched<16,16>"
+    kern["front"]["kernels"] = "k_front_batched (level 1 of every frame beside every pair's detection), k_pyr_level_batched x 3"
     kern["track"]["kernel"] = "k_track_run<64,1,7,31,21,u8,IM=0,HAMPEL,CROSS=0,BATCH=1> (persistent)"
     return {"pairs": len(pairs), "points": npts, "reps": reps,
             "plain_ms": t_plain, "batched_ms": t_batch,
@@ -432,6 +432,7 @@ def density_stress(reps: int, peaks: dict | None = None):
             "track": roof("alu", pix_iters * FLOPS_PER_PIXEL_ITER, t_track, peaks, pix_iters)}
     # adjoint: reads both frames and the point data, writes both gradient maps (cleared first)
     adj_bytes = c["pairs"] * (2 * c["W"] * c["H"] + 2 * 2 * 4 * c["W"] * c["H"]) + n * (8 + 8 + 8 + 1)
+    kern["front"]["kernels"] = "k_front_batched (level 1 of every frame beside every pair's detection), k_pyr_level_batched x 4"
     adj = roof("hbm", adj_bytes, t_bwd, peaks)
     adj["tap_adds_per_s"] = n_conv * c["support"] ** 2 * 10 / (t_bwd * 1e-3)
     adj["what"] = ("bytes: frames read, both gradient maps cleared and written, points/flow/dflow/status read; "

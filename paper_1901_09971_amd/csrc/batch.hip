@@ -78,17 +78,23 @@ bool pair_ok(const dgf_pair_desc &d, int dtype)
            d.window <= DGF_MAX_WINDOW && d.stride >= 1;
 }
 
-// Pyramids of every frame, then detection of every pair.
+// Level 1 of every frame beside every pair's detection, then the coarser levels.
 int launch_front(dgf_batch *b, float *points, hipStream_t st)
 {
+    BatchFront F{};
+    F.pyr = b->d_pyr;
+    F.det = b->d_det;
+    F.nframes = 2 * b->P;
+    F.npairs = b->P;
+    F.L = b->L;
     for (int l = 1; l < b->L; ++l) {
-        if (launch_pyr_level_batched(b->d_pyr + (size_t)(l - 1) * 2 * b->P, 2 * b->P, b->pyr_w2[l], b->pyr_h2[l], b->dtype,
-                                     st) != hipSuccess)
-            return DGF_ERR_HIP;
+        F.max_w2[l] = b->pyr_w2[l];
+        F.max_h2[l] = b->pyr_h2[l];
     }
-    if (launch_detect_batched(b->d_det, b->P, b->det_tiles_x, b->det_tiles_y, b->det_lds, points, st) != hipSuccess)
-        return DGF_ERR_HIP;
-    return DGF_OK;
+    F.det_tx = b->det_tiles_x;
+    F.det_ty = b->det_tiles_y;
+    F.det_lds = b->det_lds;
+    return launch_front_batched(F, points, st) == hipSuccess ? DGF_OK : DGF_ERR_HIP;
 }
 
 // Work counters, then the persistent tracking launch (with the global prior: its first pass, the
@@ -181,7 +187,7 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
     const int orc = effective_track_opts(opts, support, &o);
     if (orc != DGF_OK) return orc;
     for (int i = 0; i < npairs; ++i)
-        if (detect_tile_lds(pairs[i].window, pairs[i].stride) > 48 * 1024) return DGF_ERR_UNSUPPORTED;
+        if (front_detect_lds(pairs[i].window, pairs[i].stride) > kMaxLdsPerBlock) return DGF_ERR_UNSUPPORTED;
 
     dgf_batch *b = new (std::nothrow) dgf_batch();
     if (!b) return DGF_ERR_INVALID_ARG;
@@ -229,7 +235,7 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
         det[i] = j;
         b->det_tiles_x = std::max(b->det_tiles_x, (j.nx + 15) / 16);
         b->det_tiles_y = std::max(b->det_tiles_y, (j.ny + 15) / 16);
-        b->det_lds = std::max(b->det_lds, detect_tile_lds(d.window, d.stride));
+        b->det_lds = std::max(b->det_lds, front_detect_lds(d.window, d.stride));
     }
     b->total_pts = b->pt_off[npairs];
     b->nitems = b->item_off[npairs];

@@ -27,17 +27,6 @@ __global__ __launch_bounds__(TX *TY) void k_detect_tiled(const uint8_t *__restri
     detect_tile<TX, TY>(tile, (int)blockIdx.x, (int)blockIdx.y, img, pitch, W, H, win, stride, nx, ny, 0, o);
 }
 
-// Batched form: blockIdx.z selects the pair; tiles beyond a pair's window grid exit at once.
-template <int TX, int TY>
-__global__ __launch_bounds__(TX *TY) void k_detect_batched(const DetectJob *__restrict__ jobs, DetectOut o)
-{
-    const DetectJob J = jobs[blockIdx.z];
-    if ((int)blockIdx.x * TX >= J.nx || (int)blockIdx.y * TY >= J.ny) return;
-    extern __shared__ __align__(16) uint8_t tile[];
-    detect_tile<TX, TY>(tile, (int)blockIdx.x, (int)blockIdx.y, J.img, J.pitch, J.W, J.H, J.win, J.stride, J.nx, J.ny,
-                        J.out_off, o);
-}
-
 // Direct form for windows too large to tile: one lane per window, reads through the cache.
 __global__ __launch_bounds__(256) void k_detect_direct(const uint8_t *__restrict__ img, int64_t pitch, int win,
                                                         int stride, int nx, int64_t N, DetectOut o)
@@ -80,15 +69,6 @@ hipError_t launch_detect(const uint8_t *img, int64_t pitch, int W, int H, int wi
         hipLaunchKernelGGL(k_detect_direct, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, img, pitch, win,
                            stride, nx, N, o);
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_detect_batched(const DetectJob *jobs, int njobs, int max_tiles_x, int max_tiles_y, size_t lds,
-                                 float *pts, hipStream_t st)
-{
-    DetectOut o{pts, nullptr, nullptr};
-    dim3 grid(max_tiles_x, max_tiles_y, njobs);
-    hipLaunchKernelGGL((k_detect_batched<16, 16>), grid, dim3(256), lds, st, jobs, o);
     return hipGetLastError();
 }
 

@@ -698,10 +698,7 @@ struct DetectJob {
 };
 
 // launchers (return hipSuccess or the launch error)
-hipError_t launch_detect_batched(const DetectJob *jobs_dev, int njobs, int max_tiles_x, int max_tiles_y, size_t lds,
-                                 float *pts, hipStream_t st);
 size_t detect_tile_lds(int win, int stride);
-hipError_t launch_pyr_level_batched(const PyrJob *jobs_dev, int njobs, int max_w2, int max_h2, int dtype, hipStream_t st);
 hipError_t launch_detect(const uint8_t *img, int64_t pitch, int W, int H, int win, int stride, float *pts,
                          uint8_t *sel, float *resp, hipStream_t st);
 hipError_t launch_pyr_level(const PyrJob *jobs, int njobs, int dtype, hipStream_t st);
@@ -726,6 +723,19 @@ struct FrontDetect {
     int32_t W, H, win, stride, nx, ny, tiles_x, tiles_y;
     DetectOut o;
 };
+// The front end of a batch plan (front_batch.hip): level 1 of every frame beside every pair's
+// detection in one launch, then one launch per coarser level.
+struct BatchFront {
+    const PyrJob *pyr;    // device: [(L - 1)][nframes] level jobs, frame 2p = I0 of pair p, 2p + 1 its I1
+    const DetectJob *det; // device: [npairs]
+    int nframes, npairs, L;
+    int max_w2[DGF_MAX_LEVELS], max_h2[DGF_MAX_LEVELS]; // largest level-l size over the frames
+    int det_tx, det_ty;   // tiles of 16 x 16 windows covering the largest window grid
+    size_t det_lds;       // largest front_detect_lds over the pairs
+};
+hipError_t launch_front_batched(const BatchFront &F, float *pts, hipStream_t st);
+size_t front_detect_lds(int win, int stride); // LDS of one pair's detection tile in that launch
+
 bool front_detect_fits(int win, int stride);
 hipError_t launch_pyr_chain_u8(const PyrChain &A, int njobs, hipStream_t st, const FrontDetect *det = nullptr);
 hipError_t launch_pyr_chains(const uint8_t *const srcs[2], const int64_t src_pitch[2],

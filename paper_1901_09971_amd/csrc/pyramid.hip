@@ -10,7 +10,7 @@
 // runs the horizontal 5-tap pass into a second LDS buffer at the decimated column rate, then the
 // vertical pass at the decimated row rate.  Every input byte is read from HBM once per tile
 // (plus a 3-pixel halo), every output byte written once.  blockIdx.z selects the job (image), so
-// both frames of a pair, or a whole batch, go in one launch.
+// both frames of a pair go in one launch.  (Batch plans use front_batch.hip.)
 #include "dgf_internal.hpp"
 
 namespace dgf {
@@ -66,26 +66,6 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_pyr_down(PyrJobs2 jobs)
 {
     pyr_tile<T>(jobs.j[blockIdx.z], blockIdx.x, blockIdx.y);
-}
-
-// Batched form: blockIdx.z selects the job in a device table; tiles beyond a job's output exit
-// before staging.
-template <typename T>
-__global__ __launch_bounds__(256) void k_pyr_down_batched(const PyrJob *__restrict__ jobs)
-{
-    const PyrJob J = jobs[blockIdx.z];
-    if ((int)blockIdx.x * PYR_TX >= ((J.W + 1) >> 1) || (int)blockIdx.y * PYR_TY >= ((J.H + 1) >> 1)) return;
-    pyr_tile<T>(J, blockIdx.x, blockIdx.y);
-}
-
-hipError_t launch_pyr_level_batched(const PyrJob *jobs_dev, int njobs, int max_w2, int max_h2, int dtype, hipStream_t st)
-{
-    dim3 grid((max_w2 + PYR_TX - 1) / PYR_TX, (max_h2 + PYR_TY - 1) / PYR_TY, njobs);
-    if (dtype == DGF_U8)
-        hipLaunchKernelGGL(k_pyr_down_batched<uint8_t>, grid, dim3(256), 0, st, jobs_dev);
-    else
-        hipLaunchKernelGGL(k_pyr_down_batched<float>, grid, dim3(256), 0, st, jobs_dev);
-    return hipGetLastError();
 }
 
 hipError_t launch_pyr_level(const PyrJob *jobs, int njobs, int dtype, hipStream_t st)
