@@ -387,9 +387,10 @@ int dgf_set_tuning(int32_t support, int32_t dtype, const dgf_tuning *t);
  * into `workspace`, flow / status receive a valid result), installs the fastest for (support,
  * dtype) and returns it in *out (nullable).  This is a setup call: it synchronises `stream`
  * once per candidate.  cache_path (nullable) names a JSON file keyed by GPU architecture,
- * support, levels, element type, the point count rounded up to a power of two and whether
- * DGF_TRACK_ILLUM is set: a hit installs the cached shape without timing anything; a miss appends
- * the result.  The installed shape serves both models (see dgf_set_tuning), so tuning with
+ * support, levels, element type, the point count rounded up to a power of two and the flags
+ * (DGF_TRACK_ILLUM / CROSS / GLOBAL): a hit installs the cached shape without timing anything
+ * (the pyramids, flow and status are still written, by one tracking pass with that shape); a miss
+ * appends the result.  The installed shape serves both models (see dgf_set_tuning), so tuning with
  * DGF_TRACK_ILLUM also sets the plain tracker's shape for this support and element type. */
 int dgf_autotune(const dgf_image *I0, const dgf_image *I1, const float *points, int64_t n, int32_t levels,
                  int32_t support, int32_t iters, const dgf_track_opts *opts, void *workspace, size_t ws_bytes,
@@ -472,7 +473,9 @@ size_t dgf_epic_workspace_bytes(int32_t width, int32_t height, int64_t n);
  *   model      out, nullable, float[n][6]: the row-major 2x3 A of each seed (NaN for non-seeds)
  * Unlike the other calls this one synchronises `stream`: the geodesic relaxation runs until a
  * pass changes nothing, which the host reads back.  Errors: DGF_ERR_UNSUPPORTED when
- * (width + height - 2) (kappa + 1020) exceeds 2^32 - 2 (distances are 32-bit);
+ * (width + height - 2) (kappa + 1020) exceeds 2^32 - 2 (distances are 32-bit), or when the
+ * relaxation has not reached its fixed point after 16,384 launches (nothing is written then;
+ * every launch moves the distance front across whole tiles, so real frames need a handful);
  * DGF_ERR_CAPACITY when a seed's cell touches more than 32 others or a neighbour search
  * holds more than 384 candidates (about 210 at k = 128 on dense grids; the outputs of the
  * affected cells are then NaN). */

@@ -406,9 +406,10 @@ def set_tuning(support: int, dtype: int, lanes_per_point: int, waves_per_group: 
 
 
 def autotune(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, levels: int, support: int, iters: int,
-             opts: TrackOpts | None = None, cache_path: str | None = None) -> dict:
+             opts: TrackOpts | None = None, cache_path: str | None = None, return_result: bool = False):
     """Time every compiled launch shape on these inputs, install the fastest for (support,
-    dtype) and return it (dgf_autotune)."""
+    dtype) and return it (dgf_autotune); with ``return_result`` also the (flow, status) the call
+    leaves, a tracking result made with the installed shape."""
     a, b = _image(I0, "I0"), _image(I1, "I1")
     points = points.contiguous()
     n = points.shape[0]
@@ -421,6 +422,8 @@ def autotune(I0: torch.Tensor, I1: torch.Tensor, points: torch.Tensor, levels: i
     check(lib().dgf_autotune(ctypes.byref(a), ctypes.byref(b), _ptr(points), n, levels, support, iters,
                              ctypes.byref(o), _ptr(ws), ws.numel(), _ptr(flow), _ptr(status),
                              cache_path.encode() if cache_path else None, ctypes.byref(t), _stream()), "dgf_autotune")
+    if return_result:
+        return _tuning_dict(t), flow, status
     return _tuning_dict(t)
 
 

@@ -123,9 +123,14 @@ int dgf_autotune(const dgf_image *I0, const dgf_image *I1, const float *points, 
         cache = read_cache(cache_path);
         auto it = cache.find(key);
         if (it != cache.end() && tuning_valid(to_internal(it->second), support)) {
+            // a cache hit installs the stored shape and still leaves what a timed call leaves:
+            // the pyramids in the workspace and a tracking result made with that shape
             set_tuning(support, I0->dtype, to_internal(it->second));
             if (out) *out = it->second;
-            return DGF_OK;
+            rc = dgf_track_pyramids(I0, I1, levels, workspace, ws_bytes, stream);
+            if (rc != DGF_OK) return rc;
+            return track_run_with(I0, I1, points, n, levels, support, iters, o, workspace, flow, status, nullptr,
+                                  to_internal(it->second), (hipStream_t)stream);
         }
     }
     hipStream_t st = (hipStream_t)stream;

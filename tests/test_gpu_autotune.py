@@ -34,6 +34,11 @@ def test_autotune_installs_and_caches(tmp_path):
         all(again[k] == best[k] for k in ("lanes_per_point", "waves_per_group", "margin", "kernel"))
     # tracking with the installed shape is still within parity of the oracle
     flow, st = dgf.track(t0, t1, pts, 4, 21, 20)
+    # a cache hit still leaves a tracking result made with the installed shape
+    _, hf, hs = dgf.autotune(t0, t1, pts, 4, 21, 20, cache_path=cache, return_result=True)
+    torch.cuda.synchronize()
+    fin = torch.isfinite(flow)
+    assert torch.equal(hs, st) and torch.equal(torch.isfinite(hf), fin) and torch.equal(hf[fin], flow[fin])
     P = pts.cpu().numpy().astype(np.float64)
     of, ost = oracle.track(I0, I1, P, 4, 21, 20)
     compare_tracks(flow.cpu().numpy(), st.cpu().numpy(), of, ost, 0.999, 1e-3, label="autotuned shape")
