@@ -70,7 +70,7 @@ def counter_traffic():
     return d
 
 
-def cpu_baseline(I0, I1, n_points, budget_s, seeds=None):
+def cpu_baseline(I0, I1, n_points, budget_s, interp=False):
     import numpy as np
 
     import oracle  # the CPU baseline leg is the only product-side user of the oracle
@@ -84,7 +84,7 @@ def cpu_baseline(I0, I1, n_points, budget_s, seeds=None):
     reps = 0
     while True:
         pts, _, _ = oracle.detect(I0, w["window"], w["stride"], threads=threads)
-        oracle.track(I0, I1, pts, w["levels"], w["support"], w["iters"], threads=threads)
+        flow, st = oracle.track(I0, I1, pts, w["levels"], w["support"], w["iters"], threads=threads)
         reps += 1
         el = time.perf_counter() - t0
         if el >= budget_s or reps >= 100:
@@ -106,12 +106,11 @@ def cpu_baseline(I0, I1, n_points, budget_s, seeds=None):
            "single_thread_value": len(sub) / el1,
            "single_thread_sample": f"track of every 8th point ({len(sub)}), 1 thread, {el1:.1f} s",
            "cpu_model": model}
-    if seeds is not None:
-        # the dense interpolation of the GPU-tracked points of the same pair (geodesic partition
+    if interp:
+        # the dense interpolation of the oracle's own tracks of the same pair (geodesic partition
         # single-threaded, neighbour searches and fits over the host threads)
-        P, F, S = seeds
         t2 = time.perf_counter()
-        oracle.epic(I0, P.astype(np.float64), F.astype(np.float64), S)
+        oracle.epic(I0, pts, flow, st)
         res["interpolation_s"] = time.perf_counter() - t2
     return res
 
@@ -310,7 +309,7 @@ def interpolation(reps: int):
     detection and tracking output, then the dense field of every pixel.  The call synchronises
     (its geodesic relaxation runs to a fixed point), so it is timed on the host clock.  Accuracy:
     endpoint error and > 3 px rate of the dense field on the non-occluded pixels of the synthetic
-    ground truth.  Also returns the points, flows and statuses it interpolated."""
+    ground truth."""
     import numpy as np
     import torch
 
@@ -345,7 +344,7 @@ def interpolation(reps: int):
             "seeds": int(conv.sum()), "pixels": w["W"] * w["H"], "reps": reps, "ms": ms,
             "mpix_per_s": w["W"] * w["H"] / (ms * 1e-3) / 1e6,
             "epe_noc_px": float(err.mean()), "outliers_3px_noc": float((err > 3.0).mean()),
-            "seed_epe_px": float(sparse_err.mean())}, (P, F, S)
+            "seed_epe_px": float(sparse_err.mean())}
 
 
 DENSITY = dict(name="density_2048x1024x4", W=2048, H=1024, pairs=4, window=9, stride=2, levels=6, support=21,
@@ -962,17 +961,16 @@ def main():
         out["differentiation"] = differentiation(args.steps)
     if not args.no_density:
         out["density"] = density_stress(args.density_reps, peaks)
-    seeds = None
     plain_acc = None
     if not args.no_interp:
-        out["interpolation"], seeds = interpolation(max(3, min(args.steps, 20)))
+        out["interpolation"] = interpolation(max(3, min(args.steps, 20)))
         plain_acc = {"status_counts": st_counts, "seed_epe_px": out["interpolation"]["seed_epe_px"],
                      "dense_epe_noc_px": out["interpolation"]["epe_noc_px"],
                      "dense_outliers_3px_noc": out["interpolation"]["outliers_3px_noc"]}
     if not args.no_imgm:
         out["rlof_im_gm"] = im_gm(max(5, min(args.steps, 20)), 3, plain_acc)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(I0n, I1n, N, args.cpu_budget_s, seeds)
+        out["cpu_baseline"] = cpu_baseline(I0n, I1n, N, args.cpu_budget_s, interp=not args.no_interp)
         out["cpu_baseline"].update(lscpu_info())
         if not args.no_oracle_timings:
             out["cpu_baseline"]["other_workloads"] = oracle_timings(args.cpu_budget_s)

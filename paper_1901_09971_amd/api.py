@@ -493,18 +493,31 @@ class Batch:
         total = int(lib().dgf_batch_grad_size(self._h, off))
         return total, list(off)
 
-    def backward(self, dflow: torch.Tensor, grad: torch.Tensor | None = None):
-        """Gradient of the last run w.r.t. every pair's frames for the upstream gradient ``dflow``
-        (float32 [num_points, 2]) in one launch (dgf_batch_backward).  Returns the flat buffer
-        and a list of (dI0, dI1) views, one per pair."""
+    def backward(self, dflow: torch.Tensor, grad: torch.Tensor | None = None, points: torch.Tensor | None = None,
+                 flow: torch.Tensor | None = None, status: torch.Tensor | None = None,
+                 illum: torch.Tensor | None = None):
+        """Gradient w.r.t. every pair's frames for the upstream gradient ``dflow`` (float32
+        [num_points, 2]) in one launch (dgf_batch_backward), at the last run's points, flow,
+        status (and gain / offset) unless others of the same shapes are given.  Returns the flat
+        buffer and a list of (dI0, dI1) views, one per pair."""
         total, off = self.grad_layout()
         if grad is None or grad.numel() < total or grad.dtype != torch.float32:
             grad = torch.empty(max(total, 1), dtype=torch.float32, device=self.device)
         dflow = dflow.contiguous().to(torch.float32)
         if dflow.shape != (self.num_points, 2):
             raise ValueError("dflow: expected float32 [num_points, 2]")
-        check(lib().dgf_batch_backward(self._h, _ptr(self.points), _ptr(self.flow), _ptr(self.status), _ptr(dflow),
-                                       _ptr(self.illum), _ptr(grad), _stream()), "dgf_batch_backward")
+        state = []
+        for name, given, own in (("points", points, self.points), ("flow", flow, self.flow),
+                                 ("status", status, self.status), ("illum", illum, self.illum)):
+            if given is None or own is None:
+                state.append(own)
+                continue
+            if given.shape != own.shape or given.dtype != own.dtype or not given.is_contiguous():
+                raise ValueError(f"{name}: expected a contiguous {own.dtype} tensor of shape {tuple(own.shape)}")
+            state.append(given)
+        p, f, st, ill = state
+        check(lib().dgf_batch_backward(self._h, _ptr(p), _ptr(f), _ptr(st), _ptr(dflow), _ptr(ill), _ptr(grad),
+                                       _stream()), "dgf_batch_backward")
         views = []
         for i, (a, _) in enumerate(self._keep):
             H, W = a.shape

@@ -1,7 +1,8 @@
 """GPU parity of the implicit adjoint d(flow)/d(I0, I1) (HIP kernel through the C ABI) against
 the FP64 oracle gradient, which the CPU suite pins to central finite differences.
 
-Loss: L = sum over points CONVERGED in the forward pass of |u_k - u_gt|^2, points fixed.
+Loss: L = sum over points CONVERGED in the forward pass of |u_k - u_gt|^2, points fixed.  Both
+adjoints take the oracle's forward result (flow, statuses, dflow) as their input.
 Bar: relative L2 error <= 1e-4 on dI0 and on dI1 separately."""
 import numpy as np
 import pytest
@@ -19,67 +20,44 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def _gpu_fwd_bwd(I0, I1, pts, gt, levels, support, iters, opts):
+def _check_against_oracle(I0, I1, pts, gt, levels, support, iters, opts, min_conv=0.9):
+    """Both adjoints at the oracle's forward result: the FP64 tracker converged to 1e-12 gives the
+    flow (rounded to FP32, the type the kernel takes) and the statuses, and dflow follows from
+    that flow (the forward kernels are held to the oracle in the tracking tests).  Returns the
+    oracle's statuses and the GPU gradients."""
+    I0d, I1d = I0.astype(np.float64), I1.astype(np.float64)
+    P32 = pts.astype(np.float32)
+    P = P32.astype(np.float64)
+    oflow, ost = oracle.track(I0d, I1d, P, levels, support, iters, sigma1=opts.sigma1, sigma2=opts.sigma2,
+                              min_eig=opts.min_eig, eps_fine=1e-12)
+    conv = ost == 0
+    assert conv.mean() > min_conv
+    fl32 = np.where(conv[:, None], oflow, 0.0).astype(np.float32)
+    df32 = np.where(conv[:, None], 2.0 * (fl32.astype(np.float64) - gt), 0.0).astype(np.float32)
     t0 = torch.from_numpy(np.ascontiguousarray(I0, np.float32)).cuda()
     t1 = torch.from_numpy(np.ascontiguousarray(I1, np.float32)).cuda()
-    P = torch.from_numpy(pts.astype(np.float32)).cuda()
-    flow, st = dgf.track(t0, t1, P, levels, support, iters, opts=opts)
-    conv = st == 0
-    dflow = torch.zeros_like(flow)
-    g = torch.tensor(gt, dtype=torch.float32, device="cuda")
-    dflow[conv] = 2.0 * (flow[conv] - g)
-    dI0 = torch.zeros_like(t0)
-    dI1 = torch.zeros_like(t1)
-    dgf.track_backward(t0, t1, P, support, flow, st, dflow, dI0, dI1, opts=opts)
+    dI0, dI1 = torch.zeros_like(t0), torch.zeros_like(t1)
+    dgf.track_backward(t0, t1, torch.from_numpy(P32).cuda(), support, torch.from_numpy(fl32).cuda(),
+                       torch.from_numpy(ost).cuda(), torch.from_numpy(df32).cuda(), dI0, dI1, opts=opts)
     torch.cuda.synchronize()
-    return (flow.cpu().numpy().astype(np.float64), st.cpu().numpy(), dflow.cpu().numpy().astype(np.float64),
-            dI0.cpu().numpy().astype(np.float64), dI1.cpu().numpy().astype(np.float64))
-
-
-def _check_against_oracle(I0, I1, pts, gt, levels, support, iters, opts):
-    flow, st, dflow, dI0, dI1 = _gpu_fwd_bwd(I0, I1, pts, gt, levels, support, iters, opts)
-    I0d, I1d = I0.astype(np.float64), I1.astype(np.float64)
-    P = pts.astype(np.float32).astype(np.float64)
-    # oracle gradient at the GPU's converged flow (same points, same fixed points)
-    o0, o1 = oracle.track_grad(I0d, I1d, P, support, flow, st, dflow, sigma1=opts.sigma1, sigma2=opts.sigma2)
+    o0, o1 = oracle.track_grad(I0d, I1d, P, support, fl32.astype(np.float64), ost, df32.astype(np.float64),
+                               sigma1=opts.sigma1, sigma2=opts.sigma2)
+    dI0, dI1 = dI0.cpu().numpy().astype(np.float64), dI1.cpu().numpy().astype(np.float64)
     e0, e1 = _rel(dI0, o0), _rel(dI1, o1)
-    print(f"converged={int((st == 0).sum())}/{len(st)} rel(dI0)={e0:.2e} rel(dI1)={e1:.2e}", flush=True)
+    print(f"converged={int(conv.sum())}/{len(ost)} rel(dI0)={e0:.2e} rel(dI1)={e1:.2e}", flush=True)
     assert e0 <= REL and e1 <= REL
-    return flow, st, dI0, dI1
+    return ost, dI0, dI1
 
 
-def test_crop_128x64_200_points_vs_oracle_and_fd():
+def test_crop_128x64_200_points_vs_oracle():
+    # the CPU suite checks the oracle gradient pixel by pixel against central finite differences
+    # on this same crop
     I0, I1, gt = synth.translation_f32_1242x375()
     I0 = np.ascontiguousarray(I0[:64, :128])
     I1 = np.ascontiguousarray(I1[:64, :128])
     pts = oracle.detect(np.clip(np.rint(I0), 0, 255).astype(np.uint8), 9, 6)[0]
     assert len(pts) == 200
-    opts = dgf.TrackOpts(eps_fine=1e-6)
-    flow, st, dI0, dI1 = _check_against_oracle(I0, I1, pts, gt, 3, 9, 100, opts)
-    # against the oracle's own forward (FP64, converged to 1e-12) and its gradient, which the CPU
-    # suite checks pixel by pixel against central finite differences on this same crop
-    P = pts.astype(np.float32).astype(np.float64)
-    oflow, ost = oracle.track(I0.astype(np.float64), I1.astype(np.float64), P, 3, 9, 100, eps_fine=1e-12)
-    both = (st == 0) & (ost == 0)
-    assert both.mean() > 0.9
-    odf = np.zeros_like(oflow)
-    odf[both] = 2.0 * (oflow[both] - gt)
-    st_both = np.where(both, 0, 1).astype(np.uint8)  # CONVERGED on both sides, else excluded
-    o0, o1 = oracle.track_grad(I0.astype(np.float64), I1.astype(np.float64), P, 9, oflow, st_both, odf)
-    gdf = np.zeros_like(flow)
-    gdf[both] = 2.0 * (flow[both] - gt)
-    t0 = torch.from_numpy(I0).cuda()
-    t1 = torch.from_numpy(I1).cuda()
-    g0 = torch.zeros_like(t0)
-    g1 = torch.zeros_like(t1)
-    dgf.track_backward(t0, t1, torch.from_numpy(pts.astype(np.float32)).cuda(), 9,
-                       torch.from_numpy(flow.astype(np.float32)).cuda(),
-                       torch.from_numpy(np.where(both, 0, 1).astype(np.uint8)).cuda(),
-                       torch.from_numpy(gdf.astype(np.float32)).cuda(), g0, g1, opts=opts)
-    e0 = _rel(g0.cpu().numpy().astype(np.float64), o0)
-    e1 = _rel(g1.cpu().numpy().astype(np.float64), o1)
-    print(f"vs oracle forward: rel(dI0)={e0:.2e} rel(dI1)={e1:.2e}", flush=True)
-    assert e0 <= REL and e1 <= REL
+    _check_against_oracle(I0, I1, pts, gt, 3, 9, 100, dgf.TrackOpts(eps_fine=1e-6))
 
 
 def test_full_1242x375_and_random_direction_fd():
@@ -87,11 +65,11 @@ def test_full_1242x375_and_random_direction_fd():
     pts = oracle.detect(np.clip(np.rint(I0), 0, 255).astype(np.uint8), 9, 8)[0]
     assert len(pts) == 7130
     opts = dgf.TrackOpts(eps_fine=1e-6)
-    flow, st, dI0, dI1 = _check_against_oracle(I0, I1, pts, gt, 3, 9, 100, opts)
+    ost, dI0, dI1 = _check_against_oracle(I0, I1, pts, gt, 3, 9, 100, opts)
     # directional derivative <grad L, v> against FP64 central differences of the oracle forward,
-    # restricted to the points converged on the GPU
+    # over the points the oracle's forward converged
     P = pts.astype(np.float32).astype(np.float64)
-    conv = st == 0
+    conv = ost == 0
     rng = np.random.default_rng(0)
     v0 = rng.normal(size=I0.shape)
     v1 = rng.normal(size=I1.shape)
@@ -117,7 +95,8 @@ def test_robust_layered_scene():
     I0, I1, _, _ = synth.layered_pair(400, 240, seed=5, max_disp=30.0, dtype="f32")
     pts = oracle.detect(np.clip(np.rint(I0), 0, 255).astype(np.uint8), 9, 6)[0]
     gt = np.zeros(2)
-    _check_against_oracle(I0, I1, pts, gt, 3, 11, 50, dgf.TrackOpts(eps_fine=1e-6))
+    # occlusions and 50 iterations: about half the points reach the 1e-12 step test
+    _check_against_oracle(I0, I1, pts, gt, 3, 11, 50, dgf.TrackOpts(eps_fine=1e-6), min_conv=0.5)
 
 
 def test_least_squares_limit():

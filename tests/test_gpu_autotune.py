@@ -19,7 +19,8 @@ def test_autotune_installs_and_caches(tmp_path):
     before = dgf.get_tuning(21, 4, 0, 0)
     I0, I1, _, _ = synth.layered_pair(480, 256, seed=7, max_disp=50.0)
     t0, t1 = torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda()
-    pts = dgf.detect(t0, 9, 6)
+    P = oracle.detect(I0, 9, 6)[0].astype(np.float32)
+    pts = torch.from_numpy(P).cuda()
     cache = str(tmp_path / "tune.json")
     best = dgf.autotune(t0, t1, pts, 4, 21, 20, cache_path=cache)
     assert best["lanes_per_point"] in (16, 32, 64) and best["ms"] > 0
@@ -39,8 +40,7 @@ def test_autotune_installs_and_caches(tmp_path):
     torch.cuda.synchronize()
     fin = torch.isfinite(flow)
     assert torch.equal(hs, st) and torch.equal(torch.isfinite(hf), fin) and torch.equal(hf[fin], flow[fin])
-    P = pts.cpu().numpy().astype(np.float64)
-    of, ost = oracle.track(I0, I1, P, 4, 21, 20)
+    of, ost = oracle.track(I0, I1, P.astype(np.float64), 4, 21, 20)
     compare_tracks(flow.cpu().numpy(), st.cpu().numpy(), of, ost, 0.999, 1e-3, label="autotuned shape")
     dgf.set_tuning(21, 0, before["lanes_per_point"], before["waves_per_group"], before["margin"], before["kernel"])
 

@@ -85,15 +85,17 @@ def test_graph_replay_matches_eager():
 def test_batched_pair_vs_oracle_sample():
     pairs = _pairs(3)
     plan = dgf.Batch(pairs, 4, 15, 15)
-    P, F, S = [t.cpu().numpy() for t in plan.run()]
-    for i, (a, b, w, d) in enumerate(pairs):
+    P = plan.front().cpu().numpy()
+    frames = [(a.cpu().numpy(), b.cpu().numpy()) for a, b, _, _ in pairs]
+    oP = np.concatenate([oracle.detect(I0, w, d)[0] for (I0, _), (_, _, w, d) in zip(frames, pairs)])
+    assert P.shape == oP.shape and np.abs(P - oP).max() <= 1e-3
+    # the plan tracks the oracle's points (FP32) on its own pyramids; the oracle tracks the same
+    oP = oP.astype(np.float32)
+    F, S = [t.cpu().numpy() for t in plan.track(torch.from_numpy(oP).cuda())]
+    for i, (I0, I1) in enumerate(frames):
         lo, hi = plan.offsets[i], plan.offsets[i + 1]
-        I0, I1 = a.cpu().numpy(), b.cpu().numpy()
-        opts, _, _ = oracle.detect(I0, w, d)
-        assert hi - lo == len(opts)
-        assert np.abs(P[lo:hi] - opts).max() <= 1e-3
         idx = np.arange(lo, hi, 7)  # every 7th point of the pair
-        of, os_ = oracle.track(I0, I1, P[idx].astype(np.float64), 4, 15, 15)
+        of, os_ = oracle.track(I0, I1, oP[idx].astype(np.float64), 4, 15, 15)
         compare_tracks(F[idx], S[idx], of, os_, 0.999, 1e-3, label=f"batched pair {i}")
     plan.close()
 

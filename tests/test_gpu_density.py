@@ -1,8 +1,9 @@
 """Parity at the density-stress size, in the launch configuration the benchmark times: four
 2048x1024 uint8 pairs (layered affine motion up to 250 px, seeds 0-3), DeGraF window 9 stride 2
 (518,160 points each), 6 levels, 21x21 support, 20 iterations, one batched plan.  The FP64 oracle
-checks every detected point, and the tracking and the adjoint on a seeded sample of points of
-every pair (the oracle tracks points one by one)."""
+checks every detected point; the plan then tracks the oracle's points, and the oracle checks the
+tracking and the adjoint on a seeded sample of points of every pair (it tracks points one by
+one)."""
 from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
@@ -18,38 +19,50 @@ pytestmark = pytest.mark.gpu
 L, S_, IT, WIN, STRIDE, NPAIRS, SAMPLE = 6, 21, 20, 9, 2, 4, 300
 
 
+def _oracle_points(pair):
+    return oracle.detect(pair[0], WIN, STRIDE)[0]
+
+
 @pytest.fixture(scope="module")
 def batch():
     with ThreadPoolExecutor(NPAIRS) as ex:
         data = list(ex.map(synth.density_2048x1024, range(NPAIRS)))
+        opts = list(ex.map(_oracle_points, data))
     pairs = [(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), WIN, STRIDE) for a, b, _, _ in data]
     plan = dgf.Batch(pairs, L, S_, IT)
-    P, F, S = plan.run()
+    # the two halves of the run: detection and pyramids of every pair, then tracking of the
+    # oracle's points (FP32) on those pyramids, so that both sides track the same points
+    P = plan.front().clone()
+    oP = np.concatenate(opts).astype(np.float32)
+    F, S = plan.track(torch.from_numpy(oP).cuda())
     torch.cuda.synchronize()
     rng = np.random.default_rng(0)
     samples = [rng.choice(plan.offsets[i + 1] - plan.offsets[i], SAMPLE, replace=False) for i in range(NPAIRS)]
-    yield data, plan, P, F, S, samples
+    # the oracle's tracks of the sampled points, one pair after the other
+    tracks = []
+    for i, (I0, I1, _, _) in enumerate(data):
+        idx = plan.offsets[i] + samples[i]
+        tracks.append(oracle.track(I0, I1, oP[idx].astype(np.float64), L, S_, IT))
+    yield data, plan, P, oP, F, S, samples, tracks
     plan.close()
 
 
 def test_every_point_detected(batch):
-    data, plan, P, _, _, _ = batch
+    data, plan, P, oP, _, _, _, _ = batch
     Pn = P.cpu().numpy().astype(np.float64)
-    for i, (I0, _, _, _) in enumerate(data):
-        ref = oracle.detect(I0, WIN, STRIDE)[0]
+    for i in range(NPAIRS):
         lo, hi = plan.offsets[i], plan.offsets[i + 1]
-        assert hi - lo == len(ref) == 518160
-        assert np.max(np.abs(Pn[lo:hi] - ref)) <= 1e-3
+        assert hi - lo == 518160
+        assert np.max(np.abs(Pn[lo:hi] - oP[lo:hi].astype(np.float64))) <= 1e-3
 
 
 def test_tracking_sample(batch):
-    data, plan, P, F, S, samples = batch
-    Pn, Fn, Sn = P.cpu().numpy(), F.cpu().numpy().astype(np.float64), S.cpu().numpy()
+    data, plan, P, oP, F, S, samples, tracks = batch
+    Fn, Sn = F.cpu().numpy().astype(np.float64), S.cpu().numpy()
     g_all, o_all = [], []
-    for i, (I0, I1, _, _) in enumerate(data):
+    for i in range(NPAIRS):
         idx = plan.offsets[i] + samples[i]
-        pts = Pn[idx].astype(np.float64)
-        of, os_ = oracle.track(I0, I1, pts, L, S_, IT)
+        of, os_ = tracks[i]
         r = compare_tracks(Fn[idx], Sn[idx], of, os_, 0.99, 1e-3, label=f"pair {i}")
         assert r["conv"] >= 0.2 * SAMPLE
         g_all.append(Sn[idx])
@@ -61,21 +74,29 @@ def test_tracking_sample(batch):
 
 
 def test_adjoint_sample(batch):
-    data, plan, P, F, S, samples = batch
-    Sn = S.cpu().numpy()
+    """The batched adjoint at the oracle's tracks of the sampled points (every other point is
+    given a non-converged status and contributes nothing), against the oracle's gradient at the
+    same input."""
+    data, plan, P, oP, F, S, samples, tracks = batch
+    n = oP.shape[0]
+    flow_in = np.zeros((n, 2), np.float32)
+    st_in = np.ones(n, np.uint8)
+    dflow = np.zeros((n, 2), np.float32)
     g = np.random.default_rng(1)
-    dflow = torch.zeros_like(F)
     for i in range(NPAIRS):
         idx = plan.offsets[i] + samples[i]
-        idx = idx[Sn[idx] == 0]
-        dflow[torch.from_numpy(idx).cuda()] = torch.from_numpy(g.normal(size=(len(idx), 2)).astype(np.float32)).cuda()
-    _, views = plan.backward(dflow)
+        of, os_ = tracks[i]
+        conv = os_ == 0
+        flow_in[idx] = np.where(conv[:, None], of, 0.0)
+        st_in[idx] = os_
+        dflow[idx] = g.normal(size=(len(idx), 2)) * conv[:, None]
+    dev = lambda a: torch.from_numpy(a).cuda()
+    _, views = plan.backward(dev(dflow), points=dev(oP), flow=dev(flow_in), status=dev(st_in))
     torch.cuda.synchronize()
-    Pn, Fn, Dn = P.cpu().numpy(), F.cpu().numpy(), dflow.cpu().numpy()
     for i, (I0, I1, _, _) in enumerate(data):
         idx = plan.offsets[i] + samples[i]
-        o0, o1 = oracle.track_grad(I0.astype(np.float64), I1.astype(np.float64), Pn[idx].astype(np.float64), S_,
-                                   Fn[idx].astype(np.float64), Sn[idx], Dn[idx].astype(np.float64))
+        o0, o1 = oracle.track_grad(I0.astype(np.float64), I1.astype(np.float64), oP[idx].astype(np.float64), S_,
+                                   flow_in[idx].astype(np.float64), st_in[idx], dflow[idx].astype(np.float64))
         for got, ref in ((views[i][0], o0), (views[i][1], o1)):
             got = got.cpu().numpy().astype(np.float64)
             rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)

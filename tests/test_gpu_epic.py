@@ -70,14 +70,26 @@ def test_layered_320x240_oracle_tracked():
     print(f"  EPE gpu {epe_g[0]:.3f} / oracle {epe_o[0]:.3f}; >3px {epe_g[1]:.4f} / {epe_o[1]:.4f}", flush=True)
 
 
-def test_driving_1242x375_gpu_tracked():
-    # the benchmark pair: detection and tracking on the GPU, interpolation on both sides
+def test_driving_1242x375_oracle_tracked():
+    # the benchmark pair in its benchmark configuration (window 9, stride 5, 5 levels, 21 x 21,
+    # 20 iterations), tracked by the oracle, interpolated on both sides
     I0, I1, gt, occ = synth.driving_1242x375()
-    a, b = torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda()
-    P = dgf.detect(a, 9, 5)
-    F, S = dgf.track(a, b, P, 5, 21, 20)
-    torch.cuda.synchronize()
-    _run_both(I0, P.cpu().numpy(), F.cpu().numpy(), S.cpu().numpy())
+    pts = oracle.detect(I0, 9, 5)[0]
+    fl, st = oracle.track(I0, I1, pts.astype(np.float32).astype(np.float64), 5, 21, 20)
+    _run_both(I0, pts, fl, st)
+
+
+def _seeded_tracks(pts, gt, occ, seed):
+    """A tracker-like result made by the input generator alone: the true motion at each point's
+    nearest pixel plus N(0, 0.2 px) noise; occluded points and a random 5 % of the others are not
+    converged (statuses 1 and 2)."""
+    rng = np.random.default_rng(seed)
+    H, W = occ.shape
+    ix = np.clip(np.rint(pts[:, 0]).astype(int), 0, W - 1)
+    iy = np.clip(np.rint(pts[:, 1]).astype(int), 0, H - 1)
+    fl = gt[iy, ix] + rng.normal(0, 0.2, (len(pts), 2))
+    st = np.where(occ[iy, ix], 1, np.where(rng.random(len(pts)) < 0.05, 2, 0)).astype(np.uint8)
+    return fl, st
 
 
 @pytest.mark.parametrize("W,H", [(1, 1), (1, 9), (13, 1), (33, 31), (65, 40)])
@@ -151,13 +163,11 @@ def test_too_many_touching_cells_is_reported():
     assert e.value.code == -2
 
 
-def test_density_2048x1024_gpu_tracked():
-    # the largest workload: 518,160 points at stride 2, tracked on the GPU; more relaxation tiles
+def test_density_2048x1024_seeded_tracks():
+    # the largest workload: 518,160 points at stride 2 with seeded tracks; more relaxation tiles
     # than the GPU holds at once (tiles then leave as soon as they are still)
-    I0, I1, _, _ = synth.density_2048x1024(0)
-    a, b = torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda()
-    P = dgf.detect(a, 9, 2)
-    F, S = dgf.track(a, b, P, 6, 21, 20)
-    torch.cuda.synchronize()
-    assert P.shape[0] == 518160
-    _run_both(I0, P.cpu().numpy(), F.cpu().numpy(), S.cpu().numpy())
+    I0, _, gt, occ = synth.density_2048x1024(0)
+    pts = oracle.detect(I0, 9, 2)[0]
+    assert pts.shape[0] == 518160
+    fl, st = _seeded_tracks(pts, gt, occ, 0)
+    _run_both(I0, pts, fl, st)

@@ -2,7 +2,7 @@
 the flow, a 4x4 system per iteration) against the FP64 oracle, through the C ABI.  Bar: flow
 within 1e-3 px on points converged on both sides; statuses agree on nearly all points.  Its
 adjoint (dgf_track_backward with the forward call's gain and offset) against the oracle's
-implicit gradient: relative L2 error <= 1e-4 on dI0 and dI1."""
+implicit gradient, both at the oracle's forward result: relative L2 error <= 1e-4 on dI0 and dI1."""
 import numpy as np
 import pytest
 import torch
@@ -153,29 +153,39 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def _oracle_forward_illum(I0, I1, pts32, L, s, iters, sigma1, sigma2):
+    """The oracle's illumination-model forward (FP64, converged to 1e-12), in the FP32 form the
+    backward kernel takes: (flow, (m, c), statuses, converged mask)."""
+    f, st, mc = oracle.track(np.asarray(I0, np.float64), np.asarray(I1, np.float64), pts32.astype(np.float64), L,
+                             s, iters, illum=True, return_illum=True, eps_fine=1e-12, sigma1=sigma1, sigma2=sigma2)
+    conv = st == 0
+    return (np.where(conv[:, None], f, 0.0).astype(np.float32), np.where(conv[:, None], mc, 0.0).astype(np.float32),
+            st, conv)
+
+
 def _adjoint_vs_oracle(I0, I1, pts, L, s, iters, seed, min_conv=0.8, **kw):
+    """Both adjoints at the oracle's forward result (flow, gain and offset, statuses) with a
+    seeded upstream gradient on its converged points."""
     opts = dgf.TrackOpts(illum=True, **kw)
+    pts32 = pts.astype(np.float32)
+    fl32, mc32, st, conv = _oracle_forward_illum(I0, I1, pts32, L, s, iters, opts.sigma1, opts.sigma2)
+    g = np.random.default_rng(seed)
+    df32 = (g.normal(size=fl32.shape) * conv[:, None]).astype(np.float32)
     t0 = torch.from_numpy(np.ascontiguousarray(I0, np.float32)).cuda()
     t1 = torch.from_numpy(np.ascontiguousarray(I1, np.float32)).cuda()
-    P = torch.from_numpy(pts.astype(np.float32)).cuda()
-    flow, st, mc = dgf.track(t0, t1, P, L, s, iters, opts=opts, return_illum=True)
-    conv = st == 0
-    g = torch.Generator(device="cpu").manual_seed(seed)
-    dflow = torch.randn(flow.shape, generator=g).cuda() * conv[:, None]
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     dI0, dI1 = torch.zeros_like(t0), torch.zeros_like(t1)
-    dgf.track_backward(t0, t1, P, s, flow, st, dflow, dI0, dI1, opts=opts, illum=mc)
+    dgf.track_backward(t0, t1, dev(pts32), s, dev(fl32), dev(st), dev(df32), dI0, dI1, opts=opts, illum=dev(mc32))
     torch.cuda.synchronize()
-    f64 = lambda t: t.cpu().numpy().astype(np.float64)
-    o0, o1 = oracle.track_grad_illum(np.asarray(I0, np.float64), np.asarray(I1, np.float64),
-                                     pts.astype(np.float32).astype(np.float64), s, f64(flow), f64(mc),
-                                     st.cpu().numpy(), f64(dflow), sigma1=opts.sigma1, sigma2=opts.sigma2)
-    e0, e1 = _rel(f64(dI0), o0), _rel(f64(dI1), o1)
-    mcn = mc.cpu().numpy()[conv.cpu().numpy()]
+    f64 = lambda a: np.asarray(a, np.float64)
+    o0, o1 = oracle.track_grad_illum(f64(I0), f64(I1), f64(pts32), s, f64(fl32), f64(mc32), st, f64(df32),
+                                     sigma1=opts.sigma1, sigma2=opts.sigma2)
+    e0, e1 = _rel(f64(dI0.cpu().numpy()), o0), _rel(f64(dI1.cpu().numpy()), o1)
+    mcn = mc32[conv]
     print(f"n={len(pts)} converged={int(conv.sum())} gain=[{1 + mcn[:, 0].min():.3f}, {1 + mcn[:, 0].max():.3f}] "
           f"rel(dI0)={e0:.2e} rel(dI1)={e1:.2e}", flush=True)
     assert int(conv.sum()) > min_conv * len(pts)
     assert e0 <= ADJ_REL and e1 <= ADJ_REL
-    return flow, st, mc, dflow, dI0, dI1
 
 
 def test_adjoint_noise_pair_with_gain_and_offset():
@@ -185,10 +195,10 @@ def test_adjoint_noise_pair_with_gain_and_offset():
     _adjoint_vs_oracle(I0, I1, pts, 3, 9, 100, 0, eps_fine=1e-6)
 
 
-@pytest.mark.parametrize("s,min_conv", [(5, 0.15), (21, 0.4)])
+@pytest.mark.parametrize("s,min_conv", [(5, 0.15), (21, 0.3)])
 def test_adjoint_layered_scene(s, min_conv):
     # (occlusions, and at 5x5 a support that fixes four unknowns poorly, leave many points short
-    # of convergence to 1e-6 px in 60 iterations; the converged ones are compared)
+    # of convergence to 1e-12 px in 60 iterations; the converged ones are compared)
     I0, I1, _, _ = synth.layered_pair(320, 240, seed=2, max_disp=40.0, dtype="f32")
     I1 = (1.1 * I1 - 5.0).astype(np.float32)
     pts = oracle.detect(np.clip(np.rint(I0), 0, 255).astype(np.uint8), 9, 7)[0]
@@ -233,22 +243,21 @@ def test_adjoint_autograd_function():
 def test_adjoint_point_gradient_vs_oracle():
     I0, I1, _ = synth.noise_translation_pair(200, 140, seed=3, shift=(1.7, -2.4), dtype="f32")
     I1 = (0.9 * I1 + 20.0 + 5.0 * np.sin(np.arange(200) / 7.0)[None, :]).astype(np.float32)
-    pts = oracle.detect(np.clip(np.rint(I0), 0, 255).astype(np.uint8), 9, 6)[0]
+    pts32 = oracle.detect(np.clip(np.rint(I0), 0, 255).astype(np.uint8), 9, 6)[0].astype(np.float32)
     opts = dgf.TrackOpts(illum=True, eps_fine=1e-6)
-    t0, t1 = torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda()
-    P = torch.from_numpy(pts.astype(np.float32)).cuda()
-    flow, st, mc = dgf.track(t0, t1, P, 3, 9, 100, opts=opts, return_illum=True)
-    conv = st == 0
-    g = torch.Generator(device="cpu").manual_seed(7)
-    dflow = torch.randn(flow.shape, generator=g).cuda() * conv[:, None]
+    fl32, mc32, st, conv = _oracle_forward_illum(I0, I1, pts32, 3, 9, 100, opts.sigma1, opts.sigma2)
+    df32 = (np.random.default_rng(7).normal(size=fl32.shape) * conv[:, None]).astype(np.float32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    t0, t1, P = dev(I0), dev(I1), dev(pts32)
     dI0, dI1, dp = torch.zeros_like(t0), torch.zeros_like(t1), torch.zeros_like(P)
-    dgf.track_backward(t0, t1, P, 9, flow, st, dflow, dI0, dI1, opts=opts, dpoints=dp, illum=mc)
+    dgf.track_backward(t0, t1, P, 9, dev(fl32), dev(st), dev(df32), dI0, dI1, opts=opts, dpoints=dp, illum=dev(mc32))
     torch.cuda.synchronize()
-    f64 = lambda t: t.cpu().numpy().astype(np.float64)
-    o0, o1, odp = oracle.track_grad_illum(I0.astype(np.float64), I1.astype(np.float64),
-                                          pts.astype(np.float32).astype(np.float64), 9, f64(flow), f64(mc),
-                                          st.cpu().numpy(), f64(dflow), return_dpoints=True)
-    e0, e1, ep = _rel(f64(dI0), o0), _rel(f64(dI1), o1), _rel(f64(dp), odp)
-    print(f"converged={int(conv.sum())}/{len(pts)} rel(dI0)={e0:.2e} rel(dI1)={e1:.2e} rel(dp)={ep:.2e}", flush=True)
+    f64 = lambda a: np.asarray(a, np.float64)
+    o0, o1, odp = oracle.track_grad_illum(f64(I0), f64(I1), f64(pts32), 9, f64(fl32), f64(mc32), st, f64(df32),
+                                          return_dpoints=True)
+    e0, e1, ep = (_rel(f64(dI0.cpu().numpy()), o0), _rel(f64(dI1.cpu().numpy()), o1),
+                  _rel(f64(dp.cpu().numpy()), odp))
+    print(f"converged={int(conv.sum())}/{len(pts32)} rel(dI0)={e0:.2e} rel(dI1)={e1:.2e} rel(dp)={ep:.2e}", flush=True)
+    assert conv.mean() > 0.9
     assert e0 <= ADJ_REL and e1 <= ADJ_REL and ep <= ADJ_REL
-    assert torch.all(dp[~conv] == 0)
+    assert torch.all(dp[dev(~conv)] == 0)

@@ -116,10 +116,11 @@ def test_constant_image_ill_conditioned():
 
 def test_iteration_counts_reported():
     I0, I1, _ = synth.translation_256x128()
-    pts = torch.from_numpy(oracle.detect(I0, 9, 8)[0].astype(np.float32)).cuda()
-    _, st, its = dgf.track(torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda(), pts, 3, 9, 10, return_iters=True)
+    P = oracle.detect(I0, 9, 8)[0].astype(np.float32)
+    _, st, its = dgf.track(torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda(), torch.from_numpy(P).cuda(), 3, 9,
+                           10, return_iters=True)
     its = its.cpu().numpy()
-    _, _, o_its = oracle.track(I0, I1, pts.cpu().numpy().astype(np.float64), 3, 9, 10, return_iters=True)
+    _, _, o_its = oracle.track(I0, I1, P.astype(np.float64), 3, 9, 10, return_iters=True)
     assert np.all(its >= 3) and np.all(its <= 30)
     # same iteration count on the vast majority of points (stopping decisions in FP32 vs FP64)
     assert np.mean(its == o_its.sum(1)) > 0.95
