@@ -139,8 +139,9 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
 
     float T[PPL], GX[PPL], GY[PPL];
 
-    // Plain launches keep the hardware's order: block b on XCD b mod 8 spreads every image band
-    // over all eight XCDs, which balances the uneven per-point work.  (Giving each XCD one band
+    // Plain launches keep the hardware's order of blocks (taking the points from the last one
+    // back, see work_item): block b on XCD b mod 8 spreads every image band over all eight XCDs,
+    // which balances the uneven per-point work.  (Giving each XCD one band
     // cut L2 fills 4.6x on the 1242x375 benchmark pair but made the launch 25% longer.)
     // Persistent launches pull from the queue of their own XCD first.
     const int home = (int)(blockIdx.x % kNumXcd);
