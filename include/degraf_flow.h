@@ -336,6 +336,15 @@ int dgf_batch_front(dgf_batch *b, float *points, void *stream);
 int dgf_batch_track(dgf_batch *b, const float *points, float *flow, uint8_t *status, int32_t *iters_out,
                     float *illum_out, void *stream);
 
+/* Where the plan keeps pyramid level `level` (0 .. levels - 1) of frame `frame` (0 = I0, 1 = I1)
+ * of pair `pair`, as dgf_batch_front builds it (the tracker's pyramid, Section 2 "Sparse point
+ * tracking"): device pointer, row pitch in bytes, width and height; level 0 is the caller's
+ * frame.  A query only (no device work).  The memory belongs to the plan, stays valid until
+ * dgf_batch_destroy and is rewritten by every front or run call.  DGF_ERR_INVALID_ARG for a null
+ * plan or output, or an index out of range. */
+int dgf_batch_level(const dgf_batch *b, int pair, int frame, int level, const uint8_t **data, int64_t *pitch_bytes,
+                    int32_t *width, int32_t *height);
+
 /* Captures the run sequence (with these output pointers) into a HIP graph on `stream` (a created
  * stream, not the default one); dgf_batch_replay launches it with one call.  A new capture
  * replaces the previous graph. */

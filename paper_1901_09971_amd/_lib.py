@@ -85,6 +85,8 @@ SIGNATURES = {
     "dgf_batch_track": (ctypes.c_int, [P, P, P, P, P, P, P]),
     "dgf_batch_capture": (ctypes.c_int, [P, P, P, P, P, P]),
     "dgf_batch_replay": (ctypes.c_int, [P, P]),
+    "dgf_batch_level": (ctypes.c_int, [P, I32, I32, I32, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(I64),
+                                       ctypes.POINTER(I32), ctypes.POINTER(I32)]),
     "dgf_batch_grad_size": (I64, [P, P]),
     "dgf_batch_backward": (ctypes.c_int, [P, P, P, P, P, P, P, P]),
     "dgf_batch_destroy": (ctypes.c_int, [P]),

@@ -486,6 +486,16 @@ class Batch:
         check(lib().dgf_batch_replay(self._h, _stream()), "dgf_batch_replay")
         return self.points, self.flow, self.status
 
+    def level(self, pair: int, frame: int, level: int):
+        """Where the plan keeps pyramid level ``level`` of frame ``frame`` (0 = I0, 1 = I1) of pair
+        ``pair`` (dgf_batch_level): (device address, row pitch in bytes, width, height).  The
+        bytes are the plan's and are rewritten by the next front or run."""
+        data, pitch = ctypes.c_void_p(), ctypes.c_int64()
+        w, h = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().dgf_batch_level(self._h, pair, frame, level, ctypes.byref(data), ctypes.byref(pitch),
+                                    ctypes.byref(w), ctypes.byref(h)), "dgf_batch_level")
+        return int(data.value or 0), pitch.value, w.value, h.value
+
     def grad_layout(self):
         """(total floats, per-pair offsets of dI0) of the buffer :meth:`backward` writes; pair i's
         dI1 follows its dI0, each a dense height x width float map."""

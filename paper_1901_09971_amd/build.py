@@ -23,6 +23,16 @@ ARCH = "gfx950"
 CFLAGS = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I" + INCLUDE, "-I" + CSRC]
+# The tracker's batched and single-pair forms are separate template instantiations whose outputs
+# are bit-identical.  With implicit contraction the optimiser may fuse a * b + c in one of them and
+# not in the other, so these sources are built with -ffp-contract=off and write every fused
+# multiply-add out (fmaf / fma): the same operations in every instantiation by construction.
+NO_CONTRACT_PREFIX = "track"
+
+
+def _flags(src: str) -> list:
+    extra = ["-ffp-contract=off"] if os.path.basename(src).startswith(NO_CONTRACT_PREFIX) else []
+    return CFLAGS + extra
 
 
 def sources():
@@ -31,7 +41,7 @@ def sources():
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *_flags(src), "-c", src, "-o", obj]
     p = subprocess.run(cmd, capture_output=True, text=True)
     out = "\n".join(l for l in (p.stdout + p.stderr).splitlines() if "packed-fp32-ops" not in l)
     if p.returncode != 0:

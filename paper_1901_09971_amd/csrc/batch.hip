@@ -1,7 +1,7 @@
 // batch.hip -- many frame pairs of uneven size and point count in one pass: a plan built once on
 // the host (descriptor tables and every pyramid in one device allocation), then per run
-//   * one launch per pyramid level covering all 2P frames (a job table, blockIdx.z = frame),
-//   * one detection launch covering all pairs (blockIdx.z = pair, per-pair window and stride),
+//   * one launch making level 1 of all 2P frames beside the detection of all pairs (job tables,
+//     per-pair window and stride), then one launch making every coarser level of every frame,
 //   * a one-block kernel that clears the work counters (no memset node, so the sequence can be
 //     captured in a graph and replayed),
 //   * one persistent tracking launch: a resident-sized grid whose wavefronts pull work items
@@ -46,6 +46,7 @@ struct dgf_batch {
     int64_t total_pts = 0, nitems = 0, grid_waves = 0;
     void *dmem = nullptr;
     LevelPair *d_lv = nullptr;
+    std::vector<LevelPair> h_lv; // host copy of the level table
     int64_t *d_item_off = nullptr, *d_pt_off = nullptr;
     uint32_t *d_counter = nullptr;
     AdjPair *d_adj = nullptr; // per-pair frames and gradient-map offsets for the adjoint
@@ -57,6 +58,8 @@ struct dgf_batch {
     std::vector<int> pyr_w2, pyr_h2; // per level 1..L-1: largest output size over the frames
     int det_tiles_x = 0, det_tiles_y = 0;
     size_t det_lds = 0;
+    LevelCounters lvcnt{}; // tile counters of the coarse-level launch
+    int64_t nlvcnt = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -94,6 +97,8 @@ int launch_front(dgf_batch *b, float *points, hipStream_t st)
     F.det_tx = b->det_tiles_x;
     F.det_ty = b->det_tiles_y;
     F.det_lds = b->det_lds;
+    F.lvcnt = b->lvcnt;
+    F.nlvcnt = b->nlvcnt;
     return launch_front_batched(F, points, st) == hipSuccess ? DGF_OK : DGF_ERR_HIP;
 }
 
@@ -253,7 +258,22 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
     b->grid_waves = std::min<int64_t>(b->nitems, (int64_t)cus * 32);
     if (b->grid_waves < 1) b->grid_waves = 1;
 
-    // device layout: [level table][item_off][pt_off][counter][pyramid jobs][detect jobs][pyramids]
+    // largest size of every level over the frames, and the coarse-level launch's tile counters
+    b->pyr_w2.assign(levels, 0);
+    b->pyr_h2.assign(levels, 0);
+    for (int i = 0; i < npairs; ++i) {
+        int W = pairs[i].I0.width, H = pairs[i].I0.height;
+        for (int l = 1; l < levels; ++l) {
+            W = (W + 1) / 2;
+            H = (H + 1) / 2;
+            b->pyr_w2[l] = std::max(b->pyr_w2[l], W);
+            b->pyr_h2[l] = std::max(b->pyr_h2[l], H);
+        }
+    }
+    b->lvcnt = level_counters(b->pyr_w2.data(), b->pyr_h2.data(), levels, 2 * npairs, nullptr, &b->nlvcnt);
+
+    // device layout: [level table][item_off][pt_off][counter][level counters][pyramid jobs]
+    // [detect jobs][adjoint table][global-motion state][pyramids]
     std::vector<int64_t> pyr_bytes(npairs), pyr_base(npairs);
     int64_t sz = 0;
     const int64_t o_lv = sz;
@@ -264,6 +284,8 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
     sz = align_up(sz + 8 * (npairs + 1), 256);
     const int64_t o_ctr = sz;
     sz = align_up(sz + 4 * kCounterStride * kNumXcd, 256);
+    const int64_t o_lvcnt = sz;
+    sz = align_up(sz + 4 * std::max<int64_t>(b->nlvcnt, 1), 256);
     const int64_t o_pyrjobs = sz;
     sz = align_up(sz + (int64_t)sizeof(PyrJob) * 2 * npairs * std::max(levels - 1, 1), 256);
     const int64_t o_det = sz;
@@ -290,6 +312,7 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
     b->d_item_off = (int64_t *)(base + o_item);
     b->d_pt_off = (int64_t *)(base + o_pt);
     b->d_counter = (uint32_t *)(base + o_ctr);
+    b->lvcnt.cnt = (uint32_t *)(base + o_lvcnt);
     b->d_pyr = (PyrJob *)(base + o_pyrjobs);
     b->d_det = (DetectJob *)(base + o_det);
     b->d_adj = (AdjPair *)(base + o_adj);
@@ -298,8 +321,6 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
     // level table and pyramid jobs
     std::vector<LevelPair> lv((size_t)npairs * levels);
     std::vector<PyrJob> jobs((size_t)2 * npairs * std::max(levels - 1, 1));
-    b->pyr_w2.assign(levels, 0);
-    b->pyr_h2.assign(levels, 0);
     for (int i = 0; i < npairs; ++i) {
         int64_t off[DGF_MAX_LEVELS], pitch[DGF_MAX_LEVELS];
         dgf_pyramid_layout(pairs[i].I0.width, pairs[i].I0.height, levels, dtype, off, pitch);
@@ -313,8 +334,6 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
             jobs[(size_t)(l - 1) * 2 * npairs + 2 * i + 1] = PyrJob{L[l - 1].p1, w1 + off[l], L[l - 1].pitch1, pitch[l], W, H};
             W = (W + 1) / 2;
             H = (H + 1) / 2;
-            b->pyr_w2[l] = std::max(b->pyr_w2[l], W);
-            b->pyr_h2[l] = std::max(b->pyr_h2[l], H);
             L[l] = LevelPair{w0 + off[l], w1 + off[l], pitch[l], pitch[l], W, H};
         }
     }
@@ -329,6 +348,7 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
                          g0, g0 + wh, d.I0.width, d.I0.width, d.I0.width, d.I0.height};
         b->grad_off[i + 1] = g0 + 2 * wh;
     }
+    b->h_lv = lv;
     bool ok = hipMemcpy(b->d_lv, lv.data(), sizeof(LevelPair) * lv.size(), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->d_adj, adj.data(), sizeof(AdjPair) * adj.size(), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->d_item_off, b->item_off.data(), 8 * (npairs + 1), hipMemcpyHostToDevice) == hipSuccess;
@@ -416,6 +436,19 @@ int dgf_batch_replay(dgf_batch *b, void *stream)
     if (b->total_pts == 0) return DGF_OK;
     if (!b->exec) return DGF_ERR_INVALID_ARG;
     return hipGraphLaunch(b->exec, (hipStream_t)stream) == hipSuccess ? DGF_OK : DGF_ERR_HIP;
+}
+
+int dgf_batch_level(const dgf_batch *b, int pair, int frame, int level, const uint8_t **data, int64_t *pitch_bytes,
+                    int32_t *width, int32_t *height)
+{
+    if (!b || !data || !pitch_bytes || !width || !height) return DGF_ERR_INVALID_ARG;
+    if (pair < 0 || pair >= b->P || (frame != 0 && frame != 1) || level < 0 || level >= b->L) return DGF_ERR_INVALID_ARG;
+    const LevelPair &v = b->h_lv[(size_t)pair * b->L + level];
+    *data = frame ? v.p1 : v.p0;
+    *pitch_bytes = frame ? v.pitch1 : v.pitch0;
+    *width = v.W;
+    *height = v.H;
+    return DGF_OK;
 }
 
 int64_t dgf_batch_grad_size(const dgf_batch *b, int64_t *offsets)

@@ -572,20 +572,21 @@ __device__ __forceinline__ float ldl4(const float *m, const float *v, float *x)
     const float d0 = m[0];
     const float i0 = __builtin_amdgcn_rcpf(d0);
     const float l10 = m[1] * i0, l20 = m[2] * i0, l30 = m[3] * i0;
-    const float d1 = m[4] - l10 * m[1];
+    const float d1 = fmaf(-l10, m[1], m[4]);
     const float i1 = __builtin_amdgcn_rcpf(d1);
-    const float l21 = (m[5] - l20 * m[1]) * i1, l31 = (m[6] - l30 * m[1]) * i1;
-    const float d2 = m[7] - l20 * m[2] - l21 * l21 * d1;
+    const float l21 = fmaf(-l20, m[1], m[5]) * i1, l31 = fmaf(-l30, m[1], m[6]) * i1;
+    const float d2 = fmaf(-l21 * l21, d1, fmaf(-l20, m[2], m[7]));
     const float i2 = __builtin_amdgcn_rcpf(d2);
-    const float l32 = (m[8] - l30 * m[2] - l31 * l21 * d1) * i2;
-    const float d3 = m[9] - l30 * m[3] - l31 * l31 * d1 - l32 * l32 * d2;
+    const float l32 = fmaf(-l31 * l21, d1, fmaf(-l30, m[2], m[8])) * i2;
+    const float d3 = fmaf(-l32 * l32, d2, fmaf(-l31 * l31, d1, fmaf(-l30, m[3], m[9])));
     const float i3 = __builtin_amdgcn_rcpf(d3);
     if (x) {
         const bool ok = d0 > 0.f && d1 > 0.f && d2 > 0.f && d3 > 0.f;
-        const float y0 = v[0], y1 = v[1] - l10 * y0, y2 = v[2] - l20 * y0 - l21 * y1;
-        const float y3 = v[3] - l30 * y0 - l31 * y1 - l32 * y2;
-        const float x3 = y3 * i3, x2 = y2 * i2 - l32 * x3, x1 = y1 * i1 - l21 * x2 - l31 * x3;
-        const float x0 = y0 * i0 - l10 * x1 - l20 * x2 - l30 * x3;
+        const float y0 = v[0], y1 = fmaf(-l10, y0, v[1]), y2 = fmaf(-l21, y1, fmaf(-l20, y0, v[2]));
+        const float y3 = fmaf(-l32, y2, fmaf(-l31, y1, fmaf(-l30, y0, v[3])));
+        const float x3 = y3 * i3, x2 = fmaf(-l32, x3, y2 * i2);
+        const float x1 = fmaf(-l31, x3, fmaf(-l21, x2, y1 * i1));
+        const float x0 = fmaf(-l30, x3, fmaf(-l20, x2, fmaf(-l10, x1, y0 * i0)));
         const float bad = __builtin_nanf("");
         x[0] = ok ? x0 : bad;
         x[1] = ok ? x1 : bad;
@@ -730,6 +731,18 @@ struct FrontDetect {
 };
 // The front end of a batch plan (front_batch.hip): level 1 of every frame beside every pair's
 // detection in one launch, then one launch per coarser level.
+// Tile counters of the batched coarse-level launch: level m >= 3 of frame f, tile (X, Y) of
+// 128 x 16 pixels, at cnt[off[m] + (f * ty[m] + Y) * tx[m] + X] (tx, ty: the largest tile grid of
+// level m over the frames).
+struct LevelCounters {
+    uint32_t *cnt;
+    int tx[DGF_MAX_LEVELS], ty[DGF_MAX_LEVELS];
+    int64_t off[DGF_MAX_LEVELS];
+};
+// Counter layout for levels of the given largest sizes (max_w2 / max_h2 indexed by level);
+// *total receives the number of counters.
+LevelCounters level_counters(const int *max_w2, const int *max_h2, int L, int nframes, uint32_t *cnt, int64_t *total);
+
 struct BatchFront {
     const PyrJob *pyr;    // device: [(L - 1)][nframes] level jobs, frame 2p = I0 of pair p, 2p + 1 its I1
     const DetectJob *det; // device: [npairs]
@@ -737,6 +750,8 @@ struct BatchFront {
     int max_w2[DGF_MAX_LEVELS], max_h2[DGF_MAX_LEVELS]; // largest level-l size over the frames
     int det_tx, det_ty;   // tiles of 16 x 16 windows covering the largest window grid
     size_t det_lds;       // largest front_detect_lds over the pairs
+    LevelCounters lvcnt;  // device counters of the coarse-level launch (levels 3 .. L - 1)
+    int64_t nlvcnt;
 };
 hipError_t launch_front_batched(const BatchFront &F, float *pts, hipStream_t st);
 size_t front_detect_lds(int win, int stride); // LDS of one pair's detection tile in that launch

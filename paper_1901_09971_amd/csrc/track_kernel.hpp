@@ -167,7 +167,7 @@ __global__ __launch_bounds__(256) void k_track(TrackParams P)
             b = group_sum<LPP>(b);
             c = group_sum<LPP>(c);
         }
-        const float lam = 0.5f * (a + c) - sqrtf(0.25f * (a - c) * (a - c) + b * b);
+        const float lam = 0.5f * (a + c) - sqrtf(fmaf(b, b, 0.25f * (a - c) * (a - c)));
         // too flat to invert: a coarse level runs no iteration and passes the guess on; at
         // level 0 the point is ill-conditioned with u = g
         const bool flat = active && !(lam >= P.min_eig_s2);
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(256) void k_track(TrackParams P)
             uy = gY;
             active = false;
         }
-        const float det0 = a * c - b * b;
+        const float det0 = fmaf(a, c, -b * b);
         const float eps2 = (l > 0) ? P.eps2c : P.eps2f;
 
         // ---- iterations
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void k_track(TrackParams P)
 #pragma unroll
                 for (int j = 0; j < PPL; ++j) {
                     const float *tp = tb + off[j];
-                    const float res = q00 * tp[0] + q10 * tp[1] + q01 * tp[TP] + q11 * tp[TP + 1] - T[j];
+                    const float res = fmaf(q11, tp[TP + 1], fmaf(q01, tp[TP], fmaf(q10, tp[1], fmaf(q00, tp[0], -T[j]))));
                     B1 = fmaf(res, GX[j], B1);
                     B2 = fmaf(res, GY[j], B2);
                 }
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(256) void k_track(TrackParams P)
 #pragma unroll
                     for (int j = 0; j < PPL; ++j) {
                         const float *tp = tb + off[j];
-                        const float res = q00 * tp[0] + q10 * tp[1] + q01 * tp[TP] + q11 * tp[TP + 1] - T[j];
+                        const float res = fmaf(q11, tp[TP + 1], fmaf(q01, tp[TP], fmaf(q10, tp[1], fmaf(q00, tp[0], -T[j]))));
                         const float w = hampel_weight(res, P.cs2, P.cmid);
                         const float ps = w * res;
                         G11 = fmaf(w, GXX[j], G11);
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256) void k_track(TrackParams P)
 #pragma unroll
                     for (int j = 0; j < PPL; ++j) {
                         const float *tp = tb + off[j];
-                        const float res = q00 * tp[0] + q10 * tp[1] + q01 * tp[TP] + q11 * tp[TP + 1] - T[j];
+                        const float res = fmaf(q11, tp[TP + 1], fmaf(q01, tp[TP], fmaf(q10, tp[1], fmaf(q00, tp[0], -T[j]))));
                         const float w = (fabsf(res) <= P.s1) ? 1.f : 0.f;
                         const float ps = w * res;
                         G11 = fmaf(w, GXX[j], G11);
@@ -269,14 +269,14 @@ __global__ __launch_bounds__(256) void k_track(TrackParams P)
                     B1 = group_sum<LPP>(B1);
                     B2 = group_sum<LPP>(B2);
                 }
-                det = G11 * G22 - G12 * G12;
+                det = fmaf(G11, G22, -G12 * G12);
                 const bool fb = lvl_active && !(det > 1e-6f * det0);
                 if (wave_any(fb)) { // too many down-weighted pixels: least-squares step for those points
                     float C1 = 0.f, C2 = 0.f;
 #pragma unroll
                     for (int j = 0; j < PPL; ++j) {
                         const float *tp = tb + off[j];
-                        const float res = q00 * tp[0] + q10 * tp[1] + q01 * tp[TP] + q11 * tp[TP + 1] - T[j];
+                        const float res = fmaf(q11, tp[TP + 1], fmaf(q01, tp[TP], fmaf(q10, tp[1], fmaf(q00, tp[0], -T[j]))));
                         C1 = fmaf(res, GX[j], C1);
                         C2 = fmaf(res, GY[j], C2);
                     }
@@ -298,8 +298,8 @@ __global__ __launch_bounds__(256) void k_track(TrackParams P)
                 }
             }
             const float inv = __builtin_amdgcn_rcpf(det);
-            const float sx = (G12 * B2 - G22 * B1) * inv;
-            const float sy = (G12 * B1 - G11 * B2) * inv;
+            const float sx = fmaf(G12, B2, -G22 * B1) * inv;
+            const float sy = fmaf(G12, B1, -G11 * B2) * inv;
             if (lvl_active) {
                 ++it_total;
                 if (!(isfinite(sx) && isfinite(sy))) {
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(256) void k_track(TrackParams P)
                 } else {
                     dX += sx;
                     dY += sy;
-                    if (sx * sx + sy * sy < eps2) {
+                    if (fmaf(sx, sx, sy * sy) < eps2) {
                         lvl_conv = true;
                         lvl_active = false;
                     }

@@ -176,8 +176,8 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
         const double *A = P.gm_model + (BATCH ? 6 * pair : 0);
         const double x = (double)px - 0.5 * (W0 - 1), y = (double)py - 0.5 * (H0 - 1);
         const double itop = __builtin_ldexp(1.0, 1 - P.L); // coarsest-level pixels per level-0 pixel
-        gX = (float)((A[0] * x + A[1] * y + A[2]) * itop);
-        gY = (float)((A[3] * x + A[4] * y + A[5]) * itop);
+        gX = (float)(fma(A[0], x, fma(A[1], y, A[2])) * itop);
+        gY = (float)(fma(A[3], x, fma(A[4], y, A[5])) * itop);
     }
     bool conv0 = false;
     int it_total = 0;
@@ -312,9 +312,9 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
             M0[9] = nv;
             det0_im = ldl4(M0, nullptr, nullptr);
             ga = (1.f + im_m) * Ts;
-            gb = (1.f + im_m) * Tm + im_c;
+            gb = fmaf(1.f + im_m, Tm, im_c);
         }
-        const float lam = 0.5f * (a + c) - sqrtf(0.25f * (a - c) * (a - c) + b * b);
+        const float lam = 0.5f * (a + c) - sqrtf(fmaf(b, b, 0.25f * (a - c) * (a - c)));
         // too flat to invert: a coarse level runs no iteration and passes the guess on; at
         // level 0 the point is ill-conditioned with u = g.  (An empty cross-based support is flat,
         // and with the illumination model one of fewer than four pixels: four unknowns.)
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
             uy = gY;
             active = false;
         }
-        const float det0 = a * c - b * b;
+        const float det0 = fmaf(a, c, -b * b);
         const float eps2 = (l > 0) ? P.eps2c : P.eps2f;
 
         // ---- iterations
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
             // residuals of every pixel of this lane's runs
             // bilinear weights shared by every sample of this iteration; each residual is a chain
             // of four FMAs started from -T
-            const float w11 = fx * fy, w10 = fx - w11, w01 = fy - w11, w00 = (1.f - fx) - w01;
+            const float w11 = fx * fy, w10 = fmaf(-fx, fy, fx), w01 = fmaf(-fx, fy, fy), w00 = (1.f - fx) - w01;
             float RES[PPL];
 #pragma unroll
             for (int j = 0; j < SEG; ++j) {
@@ -542,7 +542,7 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
                         }
                     }
                     group_sum5<LPP>(G11, G12, G22, B1, B2);
-                    det = G11 * G22 - G12 * G12;
+                    det = fmaf(G11, G22, -G12 * G12);
                     const bool fb = lvl_active && !(det > det_floor);
                     if (group_any<LPP>(fb)) {
                         float C1 = 0.f, C2 = 0.f;
@@ -564,8 +564,8 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
                     }
                 }
                 const float inv = __builtin_amdgcn_rcpf(det);
-                sx = (G12 * B2 - G22 * B1) * inv;
-                sy = (G12 * B1 - G11 * B2) * inv;
+                sx = fmaf(G12, B2, -G22 * B1) * inv;
+                sy = fmaf(G12, B1, -G11 * B2) * inv;
             }
             if (lvl_active) {
                 ++it_total;
@@ -582,7 +582,7 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
                         ga += sa;
                         gb += sb;
                     }
-                    if (sx * sx + sy * sy < eps2) {
+                    if (fmaf(sx, sx, sy * sy) < eps2) {
                         lvl_conv = true;
                         lvl_active = false;
                     }

@@ -174,3 +174,45 @@ def test_front_then_track_equals_run():
     fin = torch.isfinite(F)
     assert torch.equal(torch.isfinite(plan.flow), fin) and torch.equal(plan.flow[fin], F[fin])
     plan.close()
+
+
+def _device_level(addr, pitch, w, h):
+    """Copy a uint8 device image (address, row pitch) into a new [h, w] tensor (hipMemcpy2D)."""
+    import ctypes
+    # the HIP runtime this process already uses (torch's), not a second copy
+    with open("/proc/self/maps") as f:
+        path = next(ln.split()[-1] for ln in f if "libamdhip64" in ln)
+    hip = ctypes.CDLL(path)
+    out = torch.empty((h, w), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    rc = hip.hipMemcpy2D(ctypes.c_void_p(out.data_ptr()), ctypes.c_size_t(w), ctypes.c_void_p(addr),
+                         ctypes.c_size_t(pitch), ctypes.c_size_t(w), ctypes.c_size_t(h), 3)  # device to device
+    assert rc == 0
+    return out
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_plan_pyramids_equal_per_frame_pyramids(seed):
+    # every level of every frame the batched front end builds (level 1 beside detection, the
+    # coarser levels in one launch) equals dgf_pyramid of that frame, bit for bit
+    rng = np.random.default_rng(1000 + seed)
+    pairs = []
+    for _ in range(int(rng.integers(1, 9))):
+        W, H = int(rng.integers(8, 2100)), int(rng.integers(8, 1100))
+        a = rng.integers(0, 256, size=(H, W), dtype=np.uint8)
+        b = rng.integers(0, 256, size=(H, W), dtype=np.uint8)
+        pairs.append((torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), 9, int(rng.integers(2, 9))))
+    levels = int(rng.integers(2, 9))
+    plan = dgf.Batch(pairs, levels, 9, 10)
+    for rep in range(2):  # a second front reuses the counters the first one left
+        plan.front()
+        torch.cuda.synchronize()
+        for i, (a, b, _, _) in enumerate(pairs):
+            for f, img in enumerate((a, b)):
+                ref = dgf.pyramid(img, levels)
+                for l in range(1, levels):
+                    got = _device_level(*plan.level(i, f, l))
+                    assert torch.equal(got, ref[l]), (seed, rep, i, f, l, tuple(img.shape))
+    with pytest.raises(RuntimeError):
+        plan.level(len(pairs), 0, 1)
+    plan.close()
