@@ -1,7 +1,7 @@
 // batch.hip -- many frame pairs of uneven size and point count in one pass: a plan built once on
 // the host (descriptor tables and every pyramid in one device allocation), then per run
 //   * one launch making level 1 of all 2P frames beside the detection of all pairs (job tables,
-//     per-pair window and stride), then one launch making every coarser level of every frame,
+//     per-pair window and stride), then one launch per coarser level covering all frames,
 //   * a one-block kernel that clears the work counters (no memset node, so the sequence can be
 //     captured in a graph and replayed),
 //   * one persistent tracking launch: a resident-sized grid whose wavefronts pull work items
@@ -58,8 +58,6 @@ struct dgf_batch {
     std::vector<int> pyr_w2, pyr_h2; // per level 1..L-1: largest output size over the frames
     int det_tiles_x = 0, det_tiles_y = 0;
     size_t det_lds = 0;
-    LevelCounters lvcnt{}; // tile counters of the coarse-level launch
-    int64_t nlvcnt = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -97,8 +95,6 @@ int launch_front(dgf_batch *b, float *points, hipStream_t st)
     F.det_tx = b->det_tiles_x;
     F.det_ty = b->det_tiles_y;
     F.det_lds = b->det_lds;
-    F.lvcnt = b->lvcnt;
-    F.nlvcnt = b->nlvcnt;
     return launch_front_batched(F, points, st) == hipSuccess ? DGF_OK : DGF_ERR_HIP;
 }
 
@@ -258,7 +254,7 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
     b->grid_waves = std::min<int64_t>(b->nitems, (int64_t)cus * 32);
     if (b->grid_waves < 1) b->grid_waves = 1;
 
-    // largest size of every level over the frames, and the coarse-level launch's tile counters
+    // largest size of every level over the frames
     b->pyr_w2.assign(levels, 0);
     b->pyr_h2.assign(levels, 0);
     for (int i = 0; i < npairs; ++i) {
@@ -270,10 +266,9 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
             b->pyr_h2[l] = std::max(b->pyr_h2[l], H);
         }
     }
-    b->lvcnt = level_counters(b->pyr_w2.data(), b->pyr_h2.data(), levels, 2 * npairs, nullptr, &b->nlvcnt);
 
-    // device layout: [level table][item_off][pt_off][counter][level counters][pyramid jobs]
-    // [detect jobs][adjoint table][global-motion state][pyramids]
+    // device layout: [level table][item_off][pt_off][counter][pyramid jobs][detect jobs]
+    // [adjoint table][global-motion state][pyramids]
     std::vector<int64_t> pyr_bytes(npairs), pyr_base(npairs);
     int64_t sz = 0;
     const int64_t o_lv = sz;
@@ -284,8 +279,6 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
     sz = align_up(sz + 8 * (npairs + 1), 256);
     const int64_t o_ctr = sz;
     sz = align_up(sz + 4 * kCounterStride * kNumXcd, 256);
-    const int64_t o_lvcnt = sz;
-    sz = align_up(sz + 4 * std::max<int64_t>(b->nlvcnt, 1), 256);
     const int64_t o_pyrjobs = sz;
     sz = align_up(sz + (int64_t)sizeof(PyrJob) * 2 * npairs * std::max(levels - 1, 1), 256);
     const int64_t o_det = sz;
@@ -312,7 +305,6 @@ int dgf_batch_create(const dgf_pair_desc *pairs, int32_t npairs, int32_t levels,
     b->d_item_off = (int64_t *)(base + o_item);
     b->d_pt_off = (int64_t *)(base + o_pt);
     b->d_counter = (uint32_t *)(base + o_ctr);
-    b->lvcnt.cnt = (uint32_t *)(base + o_lvcnt);
     b->d_pyr = (PyrJob *)(base + o_pyrjobs);
     b->d_det = (DetectJob *)(base + o_det);
     b->d_adj = (AdjPair *)(base + o_adj);

@@ -731,18 +731,6 @@ struct FrontDetect {
 };
 // The front end of a batch plan (front_batch.hip): level 1 of every frame beside every pair's
 // detection in one launch, then one launch per coarser level.
-// Tile counters of the batched coarse-level launch: level m >= 3 of frame f, tile (X, Y) of
-// 128 x 16 pixels, at cnt[off[m] + (f * ty[m] + Y) * tx[m] + X] (tx, ty: the largest tile grid of
-// level m over the frames).
-struct LevelCounters {
-    uint32_t *cnt;
-    int tx[DGF_MAX_LEVELS], ty[DGF_MAX_LEVELS];
-    int64_t off[DGF_MAX_LEVELS];
-};
-// Counter layout for levels of the given largest sizes (max_w2 / max_h2 indexed by level);
-// *total receives the number of counters.
-LevelCounters level_counters(const int *max_w2, const int *max_h2, int L, int nframes, uint32_t *cnt, int64_t *total);
-
 struct BatchFront {
     const PyrJob *pyr;    // device: [(L - 1)][nframes] level jobs, frame 2p = I0 of pair p, 2p + 1 its I1
     const DetectJob *det; // device: [npairs]
@@ -750,8 +738,6 @@ struct BatchFront {
     int max_w2[DGF_MAX_LEVELS], max_h2[DGF_MAX_LEVELS]; // largest level-l size over the frames
     int det_tx, det_ty;   // tiles of 16 x 16 windows covering the largest window grid
     size_t det_lds;       // largest front_detect_lds over the pairs
-    LevelCounters lvcnt;  // device counters of the coarse-level launch (levels 3 .. L - 1)
-    int64_t nlvcnt;
 };
 hipError_t launch_front_batched(const BatchFront &F, float *pts, hipStream_t st);
 size_t front_detect_lds(int win, int stride); // LDS of one pair's detection tile in that launch

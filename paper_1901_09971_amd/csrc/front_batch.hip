@@ -2,13 +2,10 @@
 // points of every pair (Section 2, "Point detection" and the tracker's image pyramid).
 //
 // One launch holds level 1 of every frame beside the detection of every pair (two independent
-// kinds of workgroup in one grid, so neither runs alone on a half-empty chip); a second one makes
-// every coarser level of every frame: its workgroups make the level-2 tiles, and each tile of a
-// coarser level is made by the workgroup that finishes the last of the tiles it reads (counters
-// per tile, no workgroup ever waits).  (Chains of four levels per workgroup, as the single-pair
-// front end uses, measured 5x slower here: tens of thousands of small latency-bound workgroups;
-// one launch per level costs a launch's latency, ~7 us, for each level.)  The uint8 arithmetic
-// is that of
+// kinds of workgroup in one grid, so neither runs alone on a half-empty chip); each coarser level
+// is one launch over all frames.  (Chains of four levels per launch, as the single-pair front end
+// uses, measured 5x slower here: tens of thousands of small latency-bound workgroups.)  The
+// uint8 arithmetic is that of
 // k_pyr_down and of detect_tile -- exact integer sums, (sum + 128) >> 8 per level, replicated
 // borders -- so the outputs are bit-identical to theirs; only the data movement and the
 // instruction count differ:
@@ -130,18 +127,6 @@ __device__ void pyr_tile_fast(const PyrJob &J, int tile_x, int tile_y, uint32_t 
     }
 }
 
-// The level-(m-1) tiles (PF_OW x PF_OH pixels) holding what the level-m tile (X, Y) reads:
-// columns 2 PF_OW X - 2 .. 2 PF_OW (X + 1) and rows 2 PF_OH Y - 2 .. 2 PF_OH (Y + 1), clamped to
-// the source (J is the level-m job, W x H its source); the bytes staged beyond those columns lie
-// in the same tiles.
-__device__ __forceinline__ void tile_inputs(const PyrJob &J, int X, int Y, int &c0, int &c1, int &r0, int &r1)
-{
-    c0 = max(0, 2 * PF_OW * X - 2) / PF_OW;
-    c1 = min(J.W - 1, 2 * PF_OW * (X + 1)) / PF_OW;
-    r0 = max(0, 2 * PF_OH * Y - 2) / PF_OH;
-    r1 = min(J.H - 1, 2 * PF_OH * (Y + 1)) / PF_OH;
-}
-
 // Separable detection of one tile of 16 x 32 windows (same windows, sums and outputs as
 // detect_tile; two windows per lane).  lds: the staged pixels (row pitch RP bytes, RH rows), then
 // three [RH][16] int arrays of row sums over each window column.
@@ -218,15 +203,12 @@ __device__ void detect_tile_rows(uint8_t *lds, int tile_x, int tile_y, const Det
 // Level 1 of every frame (blocks 0 .. npyr - 1: frame b / per_frame, tile b mod per_frame of a
 // tiles_x-wide grid) beside every pair's detection (the rest: pair, then tile of a det_tx-wide
 // grid).  Tiles beyond a frame's or a pair's extent exit at once.
-// Block 0 also clears the tile counters of the coarse-level launch that follows.
 __global__ __launch_bounds__(256) void k_front_batched(const PyrJob *__restrict__ pyr, const DetectJob *__restrict__ det,
                                                        int tiles_x, int per_frame, int npyr, int det_tx, int per_pair,
-                                                       float *pts, uint32_t *lvcnt, int64_t nlvcnt)
+                                                       float *pts)
 {
     extern __shared__ __align__(16) uint8_t smem[];
     const int b = (int)blockIdx.x;
-    if (b == 0)
-        for (int64_t i = threadIdx.x; i < nlvcnt; i += blockDim.x) lvcnt[i] = 0u;
     if (b < npyr) {
         const int f = b / per_frame, t = b - f * per_frame, ty = t / tiles_x, tx = t - ty * tiles_x;
         const PyrJob J = pyr[f];
@@ -252,60 +234,13 @@ __global__ __launch_bounds__(256) void k_front_batched(const PyrJob *__restrict_
         detect_tile_rows<0>(smem, tx, ty >> 1, J, o, J.win);
 }
 
-// Levels 2 .. L - 1 of every frame (blockIdx.z = frame, blockIdx.x / y = level-2 tile).  After
-// making a tile of level m, the workgroup fences its stores and bumps the counter of each
-// level-(m + 1) tile that reads it (at most four); the bump that brings a counter to the number
-// of tiles feeding that tile hands it to this workgroup, which makes it after a fence of its own
-// (so it sees what the other workgroups stored).  Tiles to make wait on a stack in LDS: each tile
-// pushes at most four, so 4 (L - 2) entries bound it.  No workgroup waits for another, so the
-// launch needs no co-residency; every counter a tile bumps reaches its count (each of its input
-// tiles exists and is made exactly once), and k_front_batched zeroes them before each front.
-__global__ __launch_bounds__(256) void k_pyr_levels_batched(const PyrJob *__restrict__ pyr, LevelCounters C, int nframes,
-                                                            int L)
+// One coarser level of every frame (blockIdx.z = frame).
+__global__ __launch_bounds__(256) void k_pyr_level_batched(const PyrJob *__restrict__ pyr)
 {
     __shared__ __align__(16) uint32_t lds[kPyrLds / 4];
-    __shared__ int stk[4 * DGF_MAX_LEVELS][3];
-    __shared__ int nstk;
-    const int f = (int)blockIdx.z;
-    int m = 2, X = (int)blockIdx.x, Y = (int)blockIdx.y;
-    {
-        const PyrJob J = pyr[(size_t)nframes + f];
-        if (X * PF_OW >= ((J.W + 1) >> 1) || Y * PF_OH >= ((J.H + 1) >> 1)) return;
-    }
-    if (threadIdx.x == 0) nstk = 0;
-    for (;;) {
-        pyr_tile_fast(pyr[(size_t)(m - 1) * nframes + f], X, Y, lds);
-        __threadfence(); // this tile's bytes before any counter announces them
-        __syncthreads();
-        if (m + 1 < L && threadIdx.x < 9) {
-            const PyrJob N = pyr[(size_t)m * nframes + f]; // level m + 1 from level m
-            const int Xn = (X >> 1) - 1 + (int)threadIdx.x % 3, Yn = (Y >> 1) - 1 + (int)threadIdx.x / 3;
-            const int txn = (((N.W + 1) >> 1) + PF_OW - 1) / PF_OW, tyn = (((N.H + 1) >> 1) + PF_OH - 1) / PF_OH;
-            if (Xn >= 0 && Yn >= 0 && Xn < txn && Yn < tyn) {
-                int c0, c1, r0, r1;
-                tile_inputs(N, Xn, Yn, c0, c1, r0, r1);
-                if (c0 <= X && X <= c1 && r0 <= Y && Y <= r1) {
-                    uint32_t *cnt = C.cnt + C.off[m + 1] + ((int64_t)f * C.ty[m + 1] + Yn) * C.tx[m + 1] + Xn;
-                    const uint32_t need = (uint32_t)((c1 - c0 + 1) * (r1 - r0 + 1));
-                    if (atomicAdd(cnt, 1u) + 1u == need) {
-                        const int k = atomicAdd(&nstk, 1);
-                        stk[k][0] = m + 1;
-                        stk[k][1] = Xn;
-                        stk[k][2] = Yn;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        const int n = nstk;
-        if (n == 0) break;
-        m = stk[n - 1][0];
-        X = stk[n - 1][1];
-        Y = stk[n - 1][2];
-        __syncthreads(); // every lane has the top before it is popped
-        if (threadIdx.x == 0) nstk = n - 1;
-        __threadfence(); // the input tiles the other workgroups stored
-    }
+    const PyrJob J = pyr[blockIdx.z];
+    if ((int)blockIdx.x * PF_OW >= ((J.W + 1) >> 1) || (int)blockIdx.y * PF_OH >= ((J.H + 1) >> 1)) return;
+    pyr_tile_fast(J, blockIdx.x, blockIdx.y, lds);
 }
 
 } // namespace
@@ -318,21 +253,6 @@ size_t front_detect_lds(int win, int stride)
     return ((RP * RH + 15) & ~(size_t)15) + 3 * RH * 16 * sizeof(int);
 }
 
-LevelCounters level_counters(const int *max_w2, const int *max_h2, int L, int nframes, uint32_t *cnt, int64_t *total)
-{
-    LevelCounters C{};
-    C.cnt = cnt;
-    int64_t n = 0;
-    for (int m = 3; m < L; ++m) {
-        C.tx[m] = (max_w2[m] + PF_OW - 1) / PF_OW;
-        C.ty[m] = (max_h2[m] + PF_OH - 1) / PF_OH;
-        C.off[m] = n;
-        n += (int64_t)nframes * C.tx[m] * C.ty[m];
-    }
-    if (total) *total = n;
-    return C;
-}
-
 hipError_t launch_front_batched(const BatchFront &F, float *pts, hipStream_t st)
 {
     const int tx1 = (F.max_w2[1] + PF_OW - 1) / PF_OW, ty1 = (F.max_h2[1] + PF_OH - 1) / PF_OH;
@@ -341,11 +261,11 @@ hipError_t launch_front_batched(const BatchFront &F, float *pts, hipStream_t st)
     const int64_t blocks = (int64_t)npyr + (int64_t)per_pair * F.npairs;
     const size_t lds = F.det_lds > kPyrLds ? F.det_lds : kPyrLds;
     hipLaunchKernelGGL(k_front_batched, dim3((unsigned)blocks), dim3(256), lds, st, F.pyr, F.det, tx1, per_frame, npyr,
-                       F.det_tx, per_pair, pts, F.lvcnt.cnt, F.nlvcnt);
+                       F.det_tx, per_pair, pts);
     hipError_t e = hipGetLastError();
-    if (F.L > 2 && e == hipSuccess) {
-        const dim3 grid((F.max_w2[2] + PF_OW - 1) / PF_OW, (F.max_h2[2] + PF_OH - 1) / PF_OH, F.nframes);
-        hipLaunchKernelGGL(k_pyr_levels_batched, grid, dim3(256), 0, st, F.pyr, F.lvcnt, F.nframes, F.L);
+    for (int l = 2; l < F.L && e == hipSuccess; ++l) {
+        const dim3 grid((F.max_w2[l] + PF_OW - 1) / PF_OW, (F.max_h2[l] + PF_OH - 1) / PF_OH, F.nframes);
+        hipLaunchKernelGGL(k_pyr_level_batched, grid, dim3(256), 0, st, F.pyr + (size_t)(l - 1) * F.nframes);
         e = hipGetLastError();
     }
     return e;
