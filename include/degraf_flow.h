@@ -253,8 +253,12 @@ int dgf_track_static(const dgf_image *I0, const dgf_image *I1, const float *poin
  *   dI1[q] -= sum_k psi'(r_k) (mu . g_k) beta_k(q)
  *   dI0[q] += sum_k psi'(r_k) (mu . g_k) alpha_k(q) - sum_k psi(r_k) mu . dg_k/dI0[q]
  * (alpha, beta: bilinear tap weights of the template and I1 samples; g_k: central differences at
- * +-1 px of the bilinear interpolant of I0).  Points with any other status, or a singular J,
- * contribute nothing.  Points are treated as constants (detection is not differentiated).
+ * +-1 px of the bilinear interpolant of I0).  Where the tracker's weighted system falls back to
+ * least squares at the converged flow (its rule: det of sum w_k g_k g_k^T, w = psi(r)/r, at most
+ * 1e-6 of the unweighted one's, or not a number), the fixed point solves sum_k r_k g_k = 0
+ * instead, and the point is differentiated with psi(r) = r, psi' = 1 (for the illumination model
+ * the same test on its 4x4 systems).  Points with any other status, or a singular J, contribute
+ * nothing.  Points are treated as constants (detection is not differentiated).
  *   I0, I1      : DGF_F32 images (DGF_ERR_UNSUPPORTED for DGF_U8)
  *   flow,status : outputs of dgf_track for these inputs;  dflow: float[n][2]
  *   dI0, dI1    : float images of the same size, with the row pitch of I0 and I1 respectively;

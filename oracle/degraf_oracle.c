@@ -1103,6 +1103,58 @@ static void bilinear_grad(const double *I, int W, int H, double x, double y, dou
 }
 
 /*
+ * Whether the step the tracker takes at the converged flow u is its least-squares one: the
+ * fallback rule of track_point (weighted 2 x 2 matrix sum w g g^T, w = psi(r)/r, with a
+ * determinant at most 1e-6 of the unweighted one's, or not a number) evaluated at u.  The forward
+ * pass stopped on a step of that system there, so its fixed point solves the least-squares
+ * equation sum r g = 0, and that is the equation the gradient differentiates (psi(r) = r).
+ */
+static int ls_regime(const double *I0, const double *I1, int W, int H, double px, double py, int r, double ux,
+                     double uy, double sigma1, double sigma2)
+{
+    double a = 0.0, b = 0.0, c = 0.0, a0 = 0.0, b0 = 0.0, c0 = 0.0;
+    for (int ky = -r; ky <= r; ++ky)
+        for (int kx = -r; kx <= r; ++kx) {
+            const double x = px + kx, y = py + ky;
+            const double T = or_bilinear(I0, W, H, x, y);
+            const double g0 = 0.5 * (or_bilinear(I0, W, H, x + 1.0, y) - or_bilinear(I0, W, H, x - 1.0, y));
+            const double g1 = 0.5 * (or_bilinear(I0, W, H, x, y + 1.0) - or_bilinear(I0, W, H, x, y - 1.0));
+            const double w = irls_weight(or_bilinear(I1, W, H, x + ux, y + uy) - T, sigma1, sigma2);
+            a += w * g0 * g0;
+            b += w * g0 * g1;
+            c += w * g1 * g1;
+            a0 += g0 * g0;
+            b0 += g0 * g1;
+            c0 += g1 * g1;
+        }
+    return !(a * c - b * b > 1e-6 * (a0 * c0 - b0 * b0));
+}
+
+/* The same for the illumination model (track_point_illum's rule: the weighted and unweighted
+ * 4 x 4 systems with phi = ((1 + m) g, -T, -1) at the converged (u, m, c)). */
+static int ls_regime_illum(const double *I0, const double *I1, int W, int H, double px, double py, int r,
+                           double ux, double uy, double m, double c, double sigma1, double sigma2)
+{
+    double G[16] = {0}, G0[16] = {0};
+    for (int ky = -r; ky <= r; ++ky)
+        for (int kx = -r; kx <= r; ++kx) {
+            const double x = px + kx, y = py + ky;
+            const double T = or_bilinear(I0, W, H, x, y);
+            const double g0 = 0.5 * (or_bilinear(I0, W, H, x + 1.0, y) - or_bilinear(I0, W, H, x - 1.0, y));
+            const double g1 = 0.5 * (or_bilinear(I0, W, H, x, y + 1.0) - or_bilinear(I0, W, H, x, y - 1.0));
+            const double res = or_bilinear(I1, W, H, x + ux, y + uy) - (1.0 + m) * T - c;
+            const double w = irls_weight(res, sigma1, sigma2);
+            const double phi[4] = {(1.0 + m) * g0, (1.0 + m) * g1, -T, -1.0};
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b) {
+                    G[a * 4 + b] += w * phi[a] * phi[b];
+                    G0[a * 4 + b] += phi[a] * phi[b];
+                }
+        }
+    return !(det4(G) > 1e-6 * det4(G0));
+}
+
+/*
  * For every point with status CONVERGED, with upstream gradient lambda = dflow[i] (= dL/du):
  *   J = dF/du = sum_k psi'(r_k) g_k (grad B(I1, p + k + u))^T        (2x2, not symmetric)
  *   solve J^T mu = lambda
@@ -1132,6 +1184,9 @@ int or_track_grad(const double *I0, const double *I1, int W, int H, const double
         if (status[i] != OR_ST_CONVERGED) continue;
         const double px = pts[2 * i], py = pts[2 * i + 1];
         const double ux = flow[2 * i], uy = flow[2 * i + 1];
+        /* the norm of the equation the forward pass stopped on (least squares in its fallback regime) */
+        const int ls = ls_regime(I0, I1, W, H, px, py, r, ux, uy, sigma1, sigma2);
+        const double s1 = ls ? INFINITY : sigma1, s2 = ls ? INFINITY : sigma2;
 
         /* J = sum psi' g (grad J)^T */
         double J00 = 0.0, J01 = 0.0, J10 = 0.0, J11 = 0.0;
@@ -1146,7 +1201,7 @@ int or_track_grad(const double *I0, const double *I1, int W, int H, const double
                 double Jv = or_bilinear(I1, W, H, x + ux, y + uy);
                 double djx = (1.0 - fy) * (I1[idx[1]] - I1[idx[0]]) + fy * (I1[idx[3]] - I1[idx[2]]);
                 double djy = (1.0 - fx) * (I1[idx[2]] - I1[idx[0]]) + fx * (I1[idx[3]] - I1[idx[1]]);
-                double dp = or_dpsi(Jv - T, sigma1, sigma2);
+                double dp = or_dpsi(Jv - T, s1, s2);
                 J00 += dp * g0 * djx;
                 J01 += dp * g0 * djy;
                 J10 += dp * g1 * djx;
@@ -1173,7 +1228,7 @@ int or_track_grad(const double *I0, const double *I1, int W, int H, const double
                     double g0 = 0.5 * (or_bilinear(I0, W, H, x + 1.0, y) - or_bilinear(I0, W, H, x - 1.0, y));
                     double g1 = 0.5 * (or_bilinear(I0, W, H, x, y + 1.0) - or_bilinear(I0, W, H, x, y - 1.0));
                     double Jv = or_bilinear(I1, W, H, x + ux, y + uy);
-                    double ps = or_psi(Jv - T, sigma1, sigma2), dp = or_dpsi(Jv - T, sigma1, sigma2);
+                    double ps = or_psi(Jv - T, s1, s2), dp = or_dpsi(Jv - T, s1, s2);
                     double gT[2], gxp[2], gxm[2], gyp[2], gym[2];
                     bilinear_grad(I0, W, H, x, y, gT);
                     bilinear_grad(I0, W, H, x + 1.0, y, gxp);
@@ -1210,8 +1265,8 @@ int or_track_grad(const double *I0, const double *I1, int W, int H, const double
                 bilinear_taps(W, H, x + ux, y + uy, ib, wb, bxx, byy, &fxb, &fyb);
                 double Jv = or_bilinear(I1, W, H, x + ux, y + uy);
                 double res = Jv - T;
-                double ps = or_psi(res, sigma1, sigma2);
-                double dp = or_dpsi(res, sigma1, sigma2);
+                double ps = or_psi(res, s1, s2);
+                double dp = or_dpsi(res, s1, s2);
                 double mg = mux * g0 + muy * g1;
                 const double cx = -ps * mux * 0.5, cy = -ps * muy * 0.5;
                 for (int t = 0; t < 4; ++t) {
@@ -1257,6 +1312,9 @@ int or_track_grad_illum(const double *I0, const double *I1, int W, int H, const 
         const double px = pts[2 * i], py = pts[2 * i + 1];
         const double ux = flow[2 * i], uy = flow[2 * i + 1];
         const double m = illum[2 * i], c = illum[2 * i + 1];
+        /* the norm of the equation the forward pass stopped on (least squares in its fallback regime) */
+        const int ls = ls_regime_illum(I0, I1, W, H, px, py, r, ux, uy, m, c, sigma1, sigma2);
+        const double s1 = ls ? INFINITY : sigma1, s2 = ls ? INFINITY : sigma2;
         double A[16] = {0};
         /* dependence of F on the point (the template moves with it, the images do not):
          * dF/dp = A[:, u] + K, K = sum -(1 + m) psi' phi (grad T)^T + psi dphi/dp with
@@ -1271,7 +1329,7 @@ int or_track_grad_illum(const double *I0, const double *I1, int W, int H, const 
                 double gJ[2];
                 bilinear_grad(I1, W, H, x + ux, y + uy, gJ);
                 double res = or_bilinear(I1, W, H, x + ux, y + uy) - (1.0 + m) * T - c;
-                double ps = or_psi(res, sigma1, sigma2), dp = or_dpsi(res, sigma1, sigma2);
+                double ps = or_psi(res, s1, s2), dp = or_dpsi(res, s1, s2);
                 double phi[4] = {(1.0 + m) * g0, (1.0 + m) * g1, -T, -1.0};
                 double dr[4] = {gJ[0], gJ[1], -T, -1.0};
                 for (int a = 0; a < 4; ++a)
@@ -1320,7 +1378,7 @@ int or_track_grad_illum(const double *I0, const double *I1, int W, int H, const 
                 double g1 = 0.5 * (or_bilinear(I0, W, H, x, y + 1.0) - or_bilinear(I0, W, H, x, y - 1.0));
                 double Jv = or_bilinear(I1, W, H, x + ux, y + uy);
                 double res = Jv - (1.0 + m) * T - c;
-                double ps = or_psi(res, sigma1, sigma2), dp = or_dpsi(res, sigma1, sigma2);
+                double ps = or_psi(res, s1, s2), dp = or_dpsi(res, s1, s2);
                 double mphi = mu[0] * (1.0 + m) * g0 + mu[1] * (1.0 + m) * g1 - mu[2] * T - mu[3];
                 double a0 = (1.0 + m) * dp * mphi + ps * mu[2];
                 double cx = -0.5 * (1.0 + m) * ps * mu[0], cy = -0.5 * (1.0 + m) * ps * mu[1];

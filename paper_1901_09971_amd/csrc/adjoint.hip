@@ -115,6 +115,42 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
         gy = (1.f - fx0) * (q[w0] - q[0]) + fx0 * (q[w0 + 1] - q[1]);
     };
 
+    // the norm of the equation the forward pass stopped on: where its weighted 2 x 2 system falls
+    // back at the converged flow (det of sum w g g^T, w = psi(r) / r, at most 1e-6 of the
+    // unweighted one's, or not a number) the fixed point solves sum r g = 0, so psi(r) = r
+    bool ls = false;
+    if (A.mode != ROBUST_L2) {
+        float a = 0.f, b = 0.f, c = 0.f, a0 = 0.f, b0 = 0.f, c0 = 0.f;
+        for (int k = li; k < S2; k += 64) {
+            const int ky = k / s, kx = k - ky * s;
+            const int lx = kx + 1, ly = ky + 1;
+            const float g0 = 0.5f * (I0s(lx + 1, ly) - I0s(lx - 1, ly));
+            const float g1 = 0.5f * (I0s(lx, ly + 1) - I0s(lx, ly - 1));
+            const float res = lerp_cell(raw1 + ky * w1 + kx, w1, fx1, fy1) - I0s(lx, ly);
+            float ps, dps;
+            psi_and_slope(A, res, ps, dps);
+            const float w = res != 0.f ? ps / res : 1.f;
+            a = fmaf(w * g0, g0, a);
+            b = fmaf(w * g0, g1, b);
+            c = fmaf(w * g1, g1, c);
+            a0 = fmaf(g0, g0, a0);
+            b0 = fmaf(g0, g1, b0);
+            c0 = fmaf(g1, g1, c0);
+        }
+        float z = 0.f;
+        wave_sum5(a, b, c, a0, b0);
+        wave_sum5(c0, z, z, z, z);
+        ls = !(fmaf(a, c, -b * b) > 1e-6f * fmaf(a0, c0, -b0 * b0));
+    }
+    auto psi_at = [&](float res, float &ps, float &dps) {
+        if (ls) {
+            ps = res;
+            dps = 1.f;
+        } else {
+            psi_and_slope(A, res, ps, dps);
+        }
+    };
+
     // pass 1: J = sum psi' g (grad J)^T; with dpoints also K = sum -psi' g (grad T)^T + psi dG/dx
     // (the dependence of F on the point: dF/dp = J + K)
     const bool want_dp = A.dpoints != nullptr;
@@ -132,7 +168,7 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
         const float djx = (1.f - fy1) * (i10 - i00) + fy1 * (i11 - i01);
         const float djy = (1.f - fx1) * (i01 - i00) + fx1 * (i11 - i10);
         float ps, dps;
-        psi_and_slope(A, J - T, ps, dps);
+        psi_at(J - T, ps, dps);
         J00 = fmaf(dps * g0, djx, J00);
         J01 = fmaf(dps * g0, djy, J01);
         J10 = fmaf(dps * g1, djx, J10);
@@ -173,7 +209,7 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
         const float *q = raw1 + ky * w1 + kx;
         const float J = lerp_cell(q, w1, fx1, fy1);
         float ps, dps;
-        psi_and_slope(A, J - T, ps, dps);
+        psi_at(J - T, ps, dps);
         C1[k] = dps * (mux * g0 + muy * g1);
         CX[k] = -0.5f * ps * mux;
         CY[k] = -0.5f * ps * muy;
@@ -317,6 +353,55 @@ __global__ __launch_bounds__(64) void k_track_adjoint_illum(AdjParams A)
         gy = (1.f - fx0) * (q[w0] - q[0]) + fx0 * (q[w0 + 1] - q[1]);
     };
 
+    // the norm of the equations the forward pass stopped on: where its weighted 4 x 4 system falls
+    // back at the converged (u, m, c) (det of sum w phi phi^T at most 1e-6 of the unweighted one's,
+    // or not a number; the ratio is the same in the centred and scaled template used here) the
+    // fixed point solves the least-squares equations, so psi(r) = r
+    bool ls = false;
+    if (A.mode != ROBUST_L2) {
+        float G[10], G0[10];
+#pragma unroll
+        for (int e = 0; e < 10; ++e) {
+            G[e] = 0.f;
+            G0[e] = 0.f;
+        }
+        for (int k = li; k < S2; k += 64) {
+            const int ky = k / s, kx = k - ky * s;
+            const int lx = kx + 1, ly = ky + 1;
+            const float T = I0s(lx, ly);
+            const float g0 = 0.5f * (I0s(lx + 1, ly) - I0s(lx - 1, ly));
+            const float g1 = 0.5f * (I0s(lx, ly + 1) - I0s(lx, ly - 1));
+            const float res = lerp_cell(raw1 + ky * w1 + kx, w1, fx1, fy1) - g1m * T - mc.y;
+            float ps, dps;
+            psi_and_slope(A, res, ps, dps);
+            const float w = res != 0.f ? ps / res : 1.f;
+            const float ph[4] = {g1m * g0, g1m * g1, -(T - Tm) * iTs, -1.f};
+            int e = 0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = a; b < 4; ++b, ++e) {
+                    G[e] = fmaf(w * ph[a], ph[b], G[e]);
+                    G0[e] = fmaf(ph[a], ph[b], G0[e]);
+                }
+        }
+        float z = 0.f;
+        wave_sum5(G[0], G[1], G[2], G[3], G[4]);
+        wave_sum5(G[5], G[6], G[7], G[8], G[9]);
+        wave_sum5(G0[0], G0[1], G0[2], G0[3], G0[4]);
+        wave_sum5(G0[5], G0[6], G0[7], G0[8], G0[9]);
+        (void)z;
+        ls = !(ldl4(G, nullptr, nullptr) > 1e-6f * ldl4(G0, nullptr, nullptr));
+    }
+    auto psi_at = [&](float res, float &ps, float &dps) {
+        if (ls) {
+            ps = res;
+            dps = 1.f;
+        } else {
+            psi_and_slope(A, res, ps, dps);
+        }
+    };
+
     // pass 1: A = sum psi' phi' (grad J, -T', -1)^T; with dpoints also the point dependence
     // K = sum -(1 + m) psi' phi' (grad T)^T + psi dphi'/dp, dphi'/dp = ((1 + m) dg/dp,
     // -(grad T)^T / Ts, 0) (rows u_x, u_y, m, c; columns p_x, p_y)
@@ -339,7 +424,7 @@ __global__ __launch_bounds__(64) void k_track_adjoint_illum(AdjParams A)
         const float djx = (1.f - fy1) * (i10 - i00) + fy1 * (i11 - i01);
         const float djy = (1.f - fx1) * (i01 - i00) + fx1 * (i11 - i10);
         float ps, dps;
-        psi_and_slope(A, J - g1m * T - mc.y, ps, dps);
+        psi_at(J - g1m * T - mc.y, ps, dps);
         const float Tp = (T - Tm) * iTs;
         const float ph[4] = {g1m * g0, g1m * g1, -Tp, -1.f};
         const float dr[4] = {djx, djy, -Tp, -1.f};
@@ -398,7 +483,7 @@ __global__ __launch_bounds__(64) void k_track_adjoint_illum(AdjParams A)
         const float *q = raw1 + ky * w1 + kx;
         const float J = lerp_cell(q, w1, fx1, fy1);
         float ps, dps;
-        psi_and_slope(A, J - g1m * T - mc.y, ps, dps);
+        psi_at(J - g1m * T - mc.y, ps, dps);
         const float Tp = (T - Tm) * iTs;
         const float mphi = g1m * (mu[0] * g0 + mu[1] * g1) - mu[2] * Tp - mu[3];
         const float c1 = dps * mphi;

@@ -139,3 +139,14 @@ def test_non_converged_points_contribute_nothing():
     # u8 frames have no gradient
     with pytest.raises(RuntimeError):
         dgf.track_backward(t0.to(torch.uint8), t1.to(torch.uint8), pts, 9, flow, st, flow, d0, d1)
+
+
+def test_least_squares_fallback_regime():
+    # hard thresholding at sigma 0.5 on a pair with N(0, 20) noise: many points converge in the
+    # tracker's least-squares fallback regime, where the gradient differentiates sum r g = 0
+    # (the CPU suite pins the oracle there to central differences)
+    I0, I1, gt = synth.noise_translation_pair(64, 48, seed=21, dtype="f32")
+    I1 = (I1.astype(np.float64) + np.random.default_rng(5).normal(0, 20.0, I1.shape)).astype(np.float32)
+    pts = oracle.detect(np.clip(np.rint(I0), 0, 255).astype(np.uint8), 9, 6)[0]
+    _check_against_oracle(I0, I1, pts, gt, 3, 9, 100, dgf.TrackOpts(sigma1=0.5, sigma2=0.5, eps_fine=1e-6),
+                          min_conv=0.4)

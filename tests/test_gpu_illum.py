@@ -261,3 +261,12 @@ def test_adjoint_point_gradient_vs_oracle():
     assert conv.mean() > 0.9
     assert e0 <= ADJ_REL and e1 <= ADJ_REL and ep <= ADJ_REL
     assert torch.all(dp[dev(~conv)] == 0)
+
+
+def test_adjoint_least_squares_fallback_regime():
+    # as for the plain tracker: hard thresholding at sigma 0.5 with N(0, 20) noise, gain 0.9 and
+    # offset 10 leave most converged points in the least-squares fallback regime of the 4 x 4 system
+    I0, I1, _ = synth.noise_translation_pair(64, 48, seed=21, dtype="f32")
+    I1 = (0.9 * I1.astype(np.float64) + 10.0 + np.random.default_rng(5).normal(0, 20.0, I1.shape)).astype(np.float32)
+    pts = oracle.detect(np.clip(np.rint(I0), 0, 255).astype(np.uint8), 9, 6)[0]
+    _adjoint_vs_oracle(I0, I1, pts, 3, 9, 100, 4, min_conv=0.5, eps_fine=1e-6, sigma1=0.5, sigma2=0.5)

@@ -6,12 +6,10 @@
   * adjoint: 60 float32 pairs, random everything as above, random upstream gradient on the
     converged points, against the oracle's implicit gradient, both at the oracle's forward result
     (flow, gain and offset rounded to FP32, statuses) as their input.  A point
-    with a support residual within 1e-3 of a threshold (sigma1 or sigma2) takes psi' from either
+    with a support residual within 1e-4 of a threshold (sigma1 or sigma2) takes psi' from either
     band (the derivative does not exist there; flat regions of integer frames put residuals exactly
-    on it) and is left out on both sides.  Bar: relative L2 error <= 1e-4 on dI0 and dI1, and
-    <= 1e-3 with the illumination model, whose 4 x 4 system on small supports carries more FP32
-    rounding (a 3,300-trial run of the same generator: none above 1e-4 without it, the worst
-    7.8e-4 with it)."""
+    on it) and is left out on both sides.  Bar: relative L2 error <= 1e-4 on dI0 and dI1, with
+    and without the illumination model."""
 import numpy as np
 import pytest
 import torch

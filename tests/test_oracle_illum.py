@@ -253,3 +253,13 @@ def test_cross_support_of_fewer_than_four_pixels_is_flat_for_the_illumination_mo
     assert st[0] != oracle.ST_ILL_CONDITIONED
     f, st = oracle.track(I0, I1, p, 1, 21, 20, illum=True, **kw)
     assert st[0] == oracle.ST_ILL_CONDITIONED
+
+
+def test_grad_illum_least_squares_fallback_regime():
+    # as for the plain tracker: in the least-squares fallback regime of the 4 x 4 system at the
+    # converged (u, m, c) the gradient differentiates the least-squares equations (49 of these 54
+    # points had a wrong gradient of the robust equations)
+    from test_oracle_grad import _directional_checks, _fallback_case
+    I0, I1, pts = _fallback_case(True)
+    checked, worst = _directional_checks(I0, I1, pts, True, dict(sigma1=0.5, sigma2=0.5))
+    assert checked >= 40 and worst < 1e-6, (checked, worst)

@@ -59,6 +59,12 @@ MUTATIONS = [
      "const uint8_t in = R[q] & R[q - 1] & R[q + 1] & R[q - e] & R[q + e];", "const uint8_t in = R[q];"),
     ("trackability divided by the window instead of the support",
      "if (!(lam_min / (double)nsup >= o->min_eig)) {", "if (!(lam_min / (double)npix >= o->min_eig)) {"),
+    ("gradient of the robust equation at a point the tracker stopped on its least-squares step",
+     "const double s1 = ls ? INFINITY : sigma1, s2 = ls ? INFINITY : sigma2;\n\n        /* J = sum psi' g (grad J)^T */",
+     "const double s1 = sigma1, s2 = sigma2;\n        (void)ls;\n\n        /* J = sum psi' g (grad J)^T */"),
+    ("illumination-model gradient of the robust equations in the least-squares regime",
+     "const int ls = ls_regime_illum(I0, I1, W, H, px, py, r, ux, uy, m, c, sigma1, sigma2);",
+     "const int ls = 0;"),
     ("global fit weights without the square of the Tukey factor",
      "w[i] = (e < c) ? (1.0 - t * t) * (1.0 - t * t) : 0.0;", "w[i] = (e < c) ? (1.0 - t * t) : 0.0;"),
     ("global prior start not scaled to the coarsest level",
