@@ -485,7 +485,7 @@ size_t dgf_epic_workspace_bytes(int32_t width, int32_t height, int64_t n);
  *              graph distances in order, unused entries -1 / 0xFFFFFFFF (all for non-seeds)
  *   model      out, nullable, float[n][6]: the row-major 2x3 A of each seed (NaN for non-seeds)
  * Unlike the other calls this one synchronises `stream`: the geodesic relaxation runs until a
- * pass changes nothing, which the host reads back.  Errors: DGF_ERR_UNSUPPORTED when
+ * pass changes nothing, which the host reads back (dgf_epic_async below does not).  Errors: DGF_ERR_UNSUPPORTED when
  * (width + height - 2) (kappa + 1020) exceeds 2^32 - 2 (distances are 32-bit), or when the
  * relaxation has not reached its fixed point after 16,384 launches (nothing is written then;
  * every launch moves the distance front across whole tiles, so real frames need a handful);
@@ -495,6 +495,21 @@ size_t dgf_epic_workspace_bytes(int32_t width, int32_t height, int64_t n);
 int dgf_epic(const dgf_image *I0, const float *points, const float *flow, const uint8_t *status, int64_t n,
              const dgf_epic_opts *opts, void *workspace, size_t ws_bytes, float *dense, int64_t dense_pitch,
              int32_t *labels, uint32_t *dist, int32_t *nbr, uint32_t *nbr_dist, float *model, void *stream);
+
+/* dgf_epic without host synchronisation, for graph capture and pipelines that must not stall the
+ * host: the same computation and outputs, enqueued on `stream` with a fixed number of geodesic
+ * relaxation launches, max_relax (0 = 32; at most 16,384).  A launch after one that changed
+ * nothing returns at once, so launches beyond the fixed point cost a few microseconds each; the
+ * ones dgf_epic needs are those a frame needs here (two to a dozen on 2048 x 1024 frames).
+ * status_out (device uint32, 4-byte aligned) is written by the last kernel of the call: 0 done;
+ * 1 the relaxation had not reached its fixed point after max_relax launches (the outputs are not
+ * written: run again with more launches); 2 a capacity limit (DGF_ERR_CAPACITY of dgf_epic, with
+ * its outputs).  The host-checked conditions of dgf_epic are returned as there
+ * (DGF_ERR_INVALID_ARG also for a null or misaligned status_out or max_relax out of range). */
+int dgf_epic_async(const dgf_image *I0, const float *points, const float *flow, const uint8_t *status, int64_t n,
+                   const dgf_epic_opts *opts, void *workspace, size_t ws_bytes, float *dense, int64_t dense_pitch,
+                   int32_t *labels, uint32_t *dist, int32_t *nbr, uint32_t *nbr_dist, float *model,
+                   int32_t max_relax, uint32_t *status_out, void *stream);
 
 #ifdef __cplusplus
 }

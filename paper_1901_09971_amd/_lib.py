@@ -93,6 +93,8 @@ SIGNATURES = {
     "dgf_epic_opts_default": (ctypes.c_int, [ctypes.POINTER(DgfEpicOpts)]),
     "dgf_epic_workspace_bytes": (SZ, [I32, I32, I64]),
     "dgf_epic": (ctypes.c_int, [IMG, P, P, P, I64, ctypes.POINTER(DgfEpicOpts), P, SZ, P, I64, P, P, P, P, P, P]),
+    "dgf_epic_async": (ctypes.c_int, [IMG, P, P, P, I64, ctypes.POINTER(DgfEpicOpts), P, SZ, P, I64, P, P, P, P, P, I32,
+                                      P, P]),
     "dgf_get_tuning": (ctypes.c_int, [I32, I32, I32, I64, ctypes.POINTER(DgfTuning)]),
     "dgf_set_tuning": (ctypes.c_int, [I32, I32, ctypes.POINTER(DgfTuning)]),
     "dgf_autotune": (ctypes.c_int, [IMG, IMG, P, I64, I32, I32, I32, OPTS, P, SZ, P, P, ctypes.c_char_p,

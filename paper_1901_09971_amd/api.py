@@ -351,11 +351,7 @@ def epic_workspace_bytes(width: int, height: int, n: int) -> int:
     return int(lib().dgf_epic_workspace_bytes(width, height, n))
 
 
-def epic(frame: torch.Tensor, points: torch.Tensor, flow: torch.Tensor, status: torch.Tensor,
-         opts: EpicOpts | None = None, return_aux: bool = False, workspace: torch.Tensor | None = None):
-    """Dense flow float32 [H, W, 2] of the uint8 ``frame`` interpolated from the tracked ``points``
-    (float32 [n, 2]) with their ``flow`` and ``status`` (dgf_epic).  With ``return_aux`` also a dict
-    of labels and dist [H, W], nbr and nbr_dist [n, k] and model [n, 6].  Synchronises the stream."""
+def _epic_buffers(frame, points, flow, status, opts, return_aux, workspace, dense):
     a = _image(frame, "frame")
     if a.dtype != DGF_U8:
         raise ValueError("frame: expected uint8")
@@ -370,7 +366,10 @@ def epic(frame: torch.Tensor, points: torch.Tensor, flow: torch.Tensor, status: 
     ws_bytes = epic_workspace_bytes(W, H, n)
     if workspace is None or workspace.numel() < ws_bytes:
         workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=frame.device)
-    dense = torch.empty((H, W, 2), dtype=torch.float32, device=frame.device)
+    if dense is None:
+        dense = torch.empty((H, W, 2), dtype=torch.float32, device=frame.device)
+    elif dense.shape != (H, W, 2) or dense.dtype != torch.float32 or not dense.is_contiguous():
+        raise ValueError("dense: expected a contiguous float32 [H, W, 2] tensor")
     aux = None
     if return_aux:
         dev = frame.device
@@ -380,13 +379,41 @@ def epic(frame: torch.Tensor, points: torch.Tensor, flow: torch.Tensor, status: 
                    nbr_dist=torch.empty((n, o.k), dtype=torch.int32, device=dev),  # uint32 bits
                    model=torch.empty((n, 6), dtype=torch.float32, device=dev))
     g = (lambda key: _ptr(aux[key])) if aux else (lambda key: None)
-    c = o.to_c()
-    check(lib().dgf_epic(ctypes.byref(a), _ptr(points.contiguous()), _ptr(flow.contiguous()),
-                         _ptr(status.contiguous()), n, ctypes.byref(c), _ptr(workspace), workspace.numel(), _ptr(dense),
-                         2 * W, g("labels"), g("dist"), g("nbr"), g("nbr_dist"), g("model"), _stream()), "dgf_epic")
+    args = (ctypes.byref(a), _ptr(points.contiguous()), _ptr(flow.contiguous()), _ptr(status.contiguous()), n,
+            ctypes.byref(o.to_c()), _ptr(workspace), workspace.numel(), _ptr(dense), 2 * W, g("labels"), g("dist"),
+            g("nbr"), g("nbr_dist"), g("model"))
+    return args, dense, aux
+
+
+def epic(frame: torch.Tensor, points: torch.Tensor, flow: torch.Tensor, status: torch.Tensor,
+         opts: EpicOpts | None = None, return_aux: bool = False, workspace: torch.Tensor | None = None):
+    """Dense flow float32 [H, W, 2] of the uint8 ``frame`` interpolated from the tracked ``points``
+    (float32 [n, 2]) with their ``flow`` and ``status`` (dgf_epic).  With ``return_aux`` also a dict
+    of labels and dist [H, W], nbr and nbr_dist [n, k] and model [n, 6].  Synchronises the stream."""
+    args, dense, aux = _epic_buffers(frame, points, flow, status, opts, return_aux, workspace, None)
+    check(lib().dgf_epic(*args, _stream()), "dgf_epic")
     if return_aux:
         return dense, aux
     return dense
+
+
+def epic_async(frame: torch.Tensor, points: torch.Tensor, flow: torch.Tensor, status: torch.Tensor,
+               opts: EpicOpts | None = None, max_relax: int = 0, return_aux: bool = False,
+               workspace: torch.Tensor | None = None, dense: torch.Tensor | None = None,
+               status_out: torch.Tensor | None = None):
+    """:func:`epic` without synchronising the stream (dgf_epic_async), so it can be captured in a
+    graph: ``max_relax`` geodesic relaxation launches (0 = the library default).  Returns
+    (dense, status_out[, aux]); status_out, an int32 [1] device tensor, holds 0 when done, 1 when
+    the relaxation needed more launches (nothing written), 2 on a capacity limit."""
+    args, dense, aux = _epic_buffers(frame, points, flow, status, opts, return_aux, workspace, dense)
+    if status_out is None:
+        status_out = torch.empty(1, dtype=torch.int32, device=frame.device)
+    elif status_out.dtype != torch.int32 or status_out.numel() < 1 or not status_out.is_cuda:
+        raise ValueError("status_out: expected an int32 device tensor")
+    check(lib().dgf_epic_async(*args, int(max_relax), _ptr(status_out), _stream()), "dgf_epic_async")
+    if return_aux:
+        return dense, status_out, aux
+    return dense, status_out
 
 
 def _tuning_dict(t) -> dict:

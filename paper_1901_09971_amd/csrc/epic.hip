@@ -46,6 +46,7 @@ constexpr int kMaxIters = 8192;      // relaxation iterations per tile and launc
 constexpr int kMaxPolls = 4096;      // halo polls of a still tile per launch
 constexpr int kChunk = 4;            // relaxation launches between two convergence checks
 constexpr int kMaxRelaxLaunches = 1 << 14;
+constexpr int kDefaultAsyncRelax = 32; // dgf_epic_async's relaxation launches when given 0
 constexpr uint64_t kNoKey = ~0ull;
 constexpr uint64_t kDistCap = 0xFFFFFFFEull;
 constexpr int kMaxEdge = 510;        // largest edge-map value
@@ -58,7 +59,8 @@ struct EpicWs {
     uint64_t *adj;   // [n][kMaxDeg]: (edge length << 32) | neighbour, kNoKey = empty slot
     float *model;    // [n][8]: affine coefficients (6), seed position (2)
     uint32_t *ctr;   // [kChunk] tiles changed per relaxation launch, [1] error bits, [1] least edge,
-                     // [kChunk] busy count per relaxation launch
+                     // [kChunk] busy count per relaxation launch, [1] the changed count of the
+                     // launch before the current group of kChunk
     uint32_t *mail;  // [kChunk][tiles]: a neighbour published keys into this tile's halo
 };
 
@@ -75,7 +77,7 @@ int64_t ws_layout(int W, int H, int64_t n, EpicWs *ws, char *base)
     };
     char *keys = take(8 * N), *E = take(2 * N), *adj = take(8 * n * kMaxDeg);
     const int64_t tiles = (int64_t)((W + kRTX - 1) / kRTX) * ((H + kRTY - 1) / kRTY);
-    char *model = take(32 * n), *ctr = take(4 * (2 * kChunk + 2)), *mail = take(4 * kChunk * tiles);
+    char *model = take(32 * n), *ctr = take(4 * (2 * kChunk + 3)), *mail = take(4 * kChunk * tiles);
     if (ws) {
         ws->keys = (uint64_t *)keys;
         ws->E = (uint16_t *)E;
@@ -160,10 +162,14 @@ __device__ __forceinline__ uint64_t step_key(uint64_t kn, uint32_t c)
 // the count, resuming on mail and leaving at zero; polls are bounded (kMaxPolls) so every tile
 // exits.  Keys only decrease and always belong to a real path, so any interleaving converges to
 // the exact least keys, and a launch in which no tile changes anything is at that fixed point.
+// prev (nullable): the changed count of the launch before; when it is zero the distances are
+// already at the fixed point and the launch returns at once (so a fixed number of launches can be
+// enqueued without reading anything back).
 __global__ __launch_bounds__(kRelaxThreads) void k_epic_relax(int W, int H, int kappa, uint64_t *keys,
                                                               const uint16_t *E, uint32_t *changed, uint32_t *busy,
-                                                              uint32_t *mail, int wait)
+                                                              uint32_t *mail, int wait, const uint32_t *prev)
 {
+    if (prev && *prev == 0u) return; // the same value in every block (an earlier kernel wrote it)
     __shared__ uint64_t K[2][kRTX2 * kRTY2];
     __shared__ uint16_t Es[kRTX2 * kRTY2];
     __shared__ uint32_t flags[2][kRelaxThreads / 64];
@@ -354,9 +360,13 @@ __global__ __launch_bounds__(kRelaxThreads) void k_epic_relax(int W, int H, int 
     if (__syncthreads_or(wrote) && threadIdx.x == 0) atomicAdd(changed, 1u);
 }
 
+// (one block) Keeps the changed count of the previous group's last launch (prev_last >= 0) in
+// carry, then clears the counters of the next m launches.
 __global__ void k_epic_clear_launch_counters(uint32_t *changed, uint32_t *busy, uint32_t *mail, int m,
-                                             uint32_t tiles)
+                                             uint32_t tiles, uint32_t *carry, int prev_last)
 {
+    if (prev_last >= 0 && threadIdx.x == 0) *carry = changed[prev_last];
+    __syncthreads();
     if ((int)threadIdx.x < m) {
         changed[threadIdx.x] = 0u;
         busy[threadIdx.x] = tiles;
@@ -401,8 +411,9 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
 // least length for all of it.  Also the least edge length of the whole graph (one atomic per
 // wavefront).
 __global__ void k_epic_graph(int W, int H, int kappa, const uint64_t *keys, const uint16_t *E, EpicWs ws,
-                             uint32_t *err, uint32_t *min_edge)
+                             uint32_t *err, uint32_t *min_edge, const uint32_t *unsettled)
 {
+    if (unsettled && *unsettled) return; // the partition did not reach its fixed point
     const uint32_t N = (uint32_t)W * (uint32_t)H;
     const int lane = threadIdx.x & 63;
     uint32_t wmin = 0xFFFFFFFFu;
@@ -461,6 +472,7 @@ struct EpicFit {
     float *model_out;
     uint32_t *err;
     const uint32_t *min_edge;
+    const uint32_t *unsettled; // nullable: nonzero when the partition did not reach its fixed point
 };
 
 __device__ __forceinline__ double wave_sum_f64(double v)
@@ -483,6 +495,7 @@ __device__ __forceinline__ int hash_slot(int32_t t) { return (int)(((uint32_t)t 
 // 9.3 KB per search, so 17 searches share a CU.
 __global__ __launch_bounds__(64) void k_epic_knn_fit(EpicFit F)
 {
+    if (F.unsettled && *F.unsettled) return; // the partition did not reach its fixed point
     static_assert(kHash == 1 << 9, "hash_slot returns 9 bits");
     constexpr int kStageNodes = 8; // batch nodes whose adjacency rows are read together
     static_assert(kStageNodes * kMaxDeg >= kMaxK, "the sorted output reuses the staging arrays");
@@ -745,8 +758,9 @@ __global__ __launch_bounds__(64) void k_epic_knn_fit(EpicFit F)
 
 // Every pixel evaluates the model of its cell's seed at its own coordinates.
 __global__ void k_epic_dense(int W, int H, const uint64_t *keys, const float *model, float *dense, int64_t dpitch,
-                             int32_t *labels, uint32_t *dist)
+                             int32_t *labels, uint32_t *dist, const uint32_t *unsettled)
 {
+    if (unsettled && *unsettled) return; // the partition did not reach its fixed point
     const uint32_t N = (uint32_t)W * (uint32_t)H;
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < N; p += gridDim.x * blockDim.x) {
         const uint32_t y = p / (uint32_t)W, x = p - y * (uint32_t)W;
@@ -787,6 +801,17 @@ using namespace dgf;
 
 extern "C" {
 
+namespace dgf {
+namespace {
+// (one thread) The outcome of a call without host synchronisation: 0 done, 1 the partition did
+// not reach its fixed point within the launches given, 2 a capacity limit (see dgf_epic).
+__global__ void k_epic_status(uint32_t *out, const uint32_t *unsettled, const uint32_t *err)
+{
+    *out = (unsettled && *unsettled) ? 1u : (*err ? 2u : 0u);
+}
+} // namespace
+} // namespace dgf
+
 int dgf_epic_opts_default(dgf_epic_opts *o)
 {
     if (!o) return DGF_ERR_INVALID_ARG;
@@ -802,9 +827,15 @@ size_t dgf_epic_workspace_bytes(int32_t width, int32_t height, int64_t n)
     return (size_t)ws_layout(width, height, n, nullptr, nullptr);
 }
 
-int dgf_epic(const dgf_image *I0, const float *points, const float *flow, const uint8_t *status, int64_t n,
+namespace {
+
+// The body of dgf_epic (max_relax == 0: relaxation checked from the host until it settles, the
+// outcome returned) and of dgf_epic_async (max_relax > 0 launches, the outcome left in
+// *status_out on the device).
+int epic_run(const dgf_image *I0, const float *points, const float *flow, const uint8_t *status, int64_t n,
              const dgf_epic_opts *opts, void *workspace, size_t ws_bytes, float *dense, int64_t dense_pitch,
-             int32_t *labels, uint32_t *dist, int32_t *nbr, uint32_t *nbr_dist, float *model, void *stream)
+             int32_t *labels, uint32_t *dist, int32_t *nbr, uint32_t *nbr_dist, float *model, void *stream,
+             int max_relax, uint32_t *status_out)
 {
     if (!epic_image_ok(I0)) return DGF_ERR_INVALID_ARG;
     const int W = I0->width, H = I0->height;
@@ -834,6 +865,7 @@ int dgf_epic(const dgf_image *I0, const float *points, const float *flow, const 
                        I0->pitch_bytes, W, H, n, ws);
     if (hipGetLastError() != hipSuccess) return DGF_ERR_HIP;
     uint32_t *err = ws.ctr + kChunk;
+    const uint32_t *unsettled = nullptr; // (the async form) the last relaxation launch's changed count
     if (n > 0) {
         hipLaunchKernelGGL(k_epic_seed, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, points, flow, status, n, W,
                            H, ws.keys);
@@ -847,27 +879,37 @@ int dgf_epic(const dgf_image *I0, const float *points, const float *flow, const 
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_epic_relax, kRelaxThreads, 0) != hipSuccess)
             return DGF_ERR_HIP;
         const int wait = ntiles <= (int64_t)cus * per_cu ? 1 : 0;
-        uint32_t *busy = ws.ctr + kChunk + 2;
+        uint32_t *busy = ws.ctr + kChunk + 2, *carry = ws.ctr + 2 * kChunk + 2;
+        const bool sync = max_relax == 0;
+        const int limit = sync ? kMaxRelaxLaunches : max_relax;
         bool converged = false;
+        int last = 0; // the index of the last launch of the last group
         // when the tiles can wait for each other one launch usually reaches the fixed point, so
-        // the first check comes after two launches (work + confirmation), later ones after kChunk
-        for (int base = 0, chunk = wait ? 2 : kChunk; base < kMaxRelaxLaunches && !converged;
-             base += chunk, chunk = kChunk) {
+        // the first check comes after two launches (work + confirmation), later ones after kChunk;
+        // a launch after one that changed nothing returns at once
+        for (int base = 0, chunk = wait ? 2 : kChunk; base < limit && !converged; base += chunk, chunk = kChunk) {
+            chunk = chunk < limit - base ? chunk : limit - base;
             hipLaunchKernelGGL(k_epic_clear_launch_counters, dim3(1), dim3(256), 0, st, ws.ctr, busy, ws.mail,
-                               chunk, (uint32_t)ntiles);
+                               chunk, (uint32_t)ntiles, carry, base > 0 ? last : -1);
             for (int j = 0; j < chunk; ++j)
                 hipLaunchKernelGGL(k_epic_relax, tiles, dim3(kRelaxThreads), 0, st, W, H, o.kappa, ws.keys,
-                                   (const uint16_t *)ws.E, ws.ctr + j, busy + j, ws.mail + j * ntiles, wait);
+                                   (const uint16_t *)ws.E, ws.ctr + j, busy + j, ws.mail + j * ntiles, wait,
+                                   j > 0 ? (const uint32_t *)(ws.ctr + j - 1) : (base > 0 ? (const uint32_t *)carry : nullptr));
             if (hipGetLastError() != hipSuccess) return DGF_ERR_HIP;
-            uint32_t h_changed[kChunk];
-            if (hipMemcpyAsync(h_changed, ws.ctr, sizeof(uint32_t) * chunk, hipMemcpyDeviceToHost, st) != hipSuccess ||
-                hipStreamSynchronize(st) != hipSuccess)
-                return DGF_ERR_HIP;
-            converged = h_changed[chunk - 1] == 0u;
+            last = chunk - 1;
+            if (sync) {
+                uint32_t h_changed[kChunk];
+                if (hipMemcpyAsync(h_changed, ws.ctr, sizeof(uint32_t) * chunk, hipMemcpyDeviceToHost, st) !=
+                        hipSuccess ||
+                    hipStreamSynchronize(st) != hipSuccess)
+                    return DGF_ERR_HIP;
+                converged = h_changed[chunk - 1] == 0u;
+            }
         }
-        if (!converged) return DGF_ERR_UNSUPPORTED;
+        if (sync && !converged) return DGF_ERR_UNSUPPORTED;
+        unsettled = sync ? nullptr : ws.ctr + last;
         hipLaunchKernelGGL(k_epic_graph, dim3(grid_for(N, 256)), dim3(256), 0, st, W, H, o.kappa,
-                           (const uint64_t *)ws.keys, (const uint16_t *)ws.E, ws, err, ws.ctr + kChunk + 1);
+                           (const uint64_t *)ws.keys, (const uint16_t *)ws.E, ws, err, ws.ctr + kChunk + 1, unsettled);
         if (hipGetLastError() != hipSuccess) return DGF_ERR_HIP;
         EpicFit F{};
         F.pts = points;
@@ -886,17 +928,43 @@ int dgf_epic(const dgf_image *I0, const float *points, const float *flow, const 
         F.model_out = model;
         F.err = err;
         F.min_edge = ws.ctr + kChunk + 1;
+        F.unsettled = unsettled;
         hipLaunchKernelGGL(k_epic_knn_fit, dim3((unsigned)n), dim3(64), 0, st, F);
         if (hipGetLastError() != hipSuccess) return DGF_ERR_HIP;
     }
     hipLaunchKernelGGL(k_epic_dense, dim3(grid_for(N, 256)), dim3(256), 0, st, W, H, (const uint64_t *)ws.keys,
-                       (const float *)ws.model, dense, dense_pitch, labels, dist);
+                       (const float *)ws.model, dense, dense_pitch, labels, dist, unsettled);
     if (hipGetLastError() != hipSuccess) return DGF_ERR_HIP;
+    if (max_relax > 0) {
+        hipLaunchKernelGGL(k_epic_status, dim3(1), dim3(1), 0, st, status_out, unsettled, (const uint32_t *)err);
+        return hipGetLastError() == hipSuccess ? DGF_OK : DGF_ERR_HIP;
+    }
     uint32_t h_err = 0;
     if (hipMemcpyAsync(&h_err, err, sizeof(h_err), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return DGF_ERR_HIP;
     return h_err ? DGF_ERR_CAPACITY : DGF_OK;
+}
+
+} // namespace
+
+int dgf_epic(const dgf_image *I0, const float *points, const float *flow, const uint8_t *status, int64_t n,
+             const dgf_epic_opts *opts, void *workspace, size_t ws_bytes, float *dense, int64_t dense_pitch,
+             int32_t *labels, uint32_t *dist, int32_t *nbr, uint32_t *nbr_dist, float *model, void *stream)
+{
+    return epic_run(I0, points, flow, status, n, opts, workspace, ws_bytes, dense, dense_pitch, labels, dist, nbr,
+                    nbr_dist, model, stream, 0, nullptr);
+}
+
+int dgf_epic_async(const dgf_image *I0, const float *points, const float *flow, const uint8_t *status, int64_t n,
+                   const dgf_epic_opts *opts, void *workspace, size_t ws_bytes, float *dense, int64_t dense_pitch,
+                   int32_t *labels, uint32_t *dist, int32_t *nbr, uint32_t *nbr_dist, float *model,
+                   int32_t max_relax, uint32_t *status_out, void *stream)
+{
+    if (max_relax < 0 || max_relax > kMaxRelaxLaunches || !status_out || (uintptr_t)status_out % 4 != 0)
+        return DGF_ERR_INVALID_ARG;
+    return epic_run(I0, points, flow, status, n, opts, workspace, ws_bytes, dense, dense_pitch, labels, dist, nbr,
+                    nbr_dist, model, stream, max_relax ? max_relax : kDefaultAsyncRelax, status_out);
 }
 
 } // extern "C"

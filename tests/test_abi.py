@@ -208,6 +208,17 @@ def test_epic_argument_checks_before_any_launch():
     # distances must fit 32 bits: (W + H - 2) (kappa + 1020) <= 2^32 - 2
     assert call(img=DgfImage(1 << 20, 8000, 10, 8000, 0), kappa=1 << 20) == -3
 
+    # the form without host synchronisation: the same checks, and a status word and a launch count
+    def call_async(max_relax=0, status_out=P, **kw):
+        im = DgfImage(1 << 20, W, H, W, 0)
+        oo = DgfEpicOpts(128, 8, 64)
+        return L.dgf_epic_async(ctypes.byref(im), P, P, P, kw.get("n", n), ctypes.byref(oo), P, kw.get("wsb", ws),
+                                P, 2 * W, None, None, None, None, None, max_relax, status_out, None)
+
+    assert call_async(status_out=None) == -1 and call_async(status_out=ctypes.c_void_p((1 << 20) + 2)) == -1
+    assert call_async(max_relax=-1) == -1 and call_async(max_relax=(1 << 14) + 1) == -1
+    assert call_async(n=-1) == -1 and call_async(wsb=ws - 1) == -5
+
 
 def test_track_static_checks_before_any_hip_call():
     """dgf_track_static rejects bad arguments and inputs larger than its static scratch on the

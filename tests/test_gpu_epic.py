@@ -171,3 +171,94 @@ def test_density_2048x1024_seeded_tracks():
     assert pts.shape[0] == 518160
     fl, st = _seeded_tracks(pts, gt, occ, 0)
     _run_both(I0, pts, fl, st)
+
+
+def _outputs(dense, aux):
+    return [dense.view(torch.int32)] + [aux[k] for k in ("labels", "dist", "nbr", "nbr_dist")] + \
+        [aux["model"].view(torch.int32)]
+
+
+@pytest.mark.parametrize("scene", ["layered_320x240", "driving_1242x375", "density_2048x1024"])
+def test_async_equals_sync(scene):
+    # dgf_epic_async: the same outputs bit for bit as dgf_epic, without reading anything back
+    if scene == "layered_320x240":
+        I0, I1, _, _ = synth.layered_pair(320, 240, seed=2, max_disp=40.0)
+        pts = oracle.detect(I0, 9, 5)[0]
+        fl, st = oracle.track(I0, I1, pts.astype(np.float32).astype(np.float64), 4, 21, 20)
+    elif scene == "driving_1242x375":
+        I0, I1, _, _ = synth.driving_1242x375()
+        pts = oracle.detect(I0, 9, 5)[0]
+        fl, st = oracle.track(I0, I1, pts.astype(np.float32).astype(np.float64), 5, 21, 20)
+    else:
+        I0, _, gt, occ = synth.density_2048x1024(0)
+        pts = oracle.detect(I0, 9, 2)[0]
+        fl, st = _seeded_tracks(pts, gt, occ, 0)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    args = (t(I0), t(pts.astype(np.float32)), t(fl.astype(np.float32)), t(st.astype(np.uint8)))
+    d1, a1 = dgf.epic(*args, return_aux=True)
+    d2, s2, a2 = dgf.epic_async(*args, return_aux=True)
+    torch.cuda.synchronize()
+    assert int(s2.item()) == 0
+    for x, y in zip(_outputs(d1, a1), _outputs(d2, a2)):
+        assert torch.equal(x, y)
+
+
+def test_async_too_few_launches_reported():
+    # one relaxation launch cannot confirm a fixed point: status 1, and the outputs are not written
+    I0, I1, _, _ = synth.layered_pair(320, 240, seed=2, max_disp=40.0)
+    pts = oracle.detect(I0, 9, 5)[0]
+    fl, st = oracle.track(I0, I1, pts.astype(np.float32).astype(np.float64), 4, 21, 20)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    args = (t(I0), t(pts.astype(np.float32)), t(fl.astype(np.float32)), t(st.astype(np.uint8)))
+    dense = torch.full((240, 320, 2), 7.0, device="cuda")
+    _, s = dgf.epic_async(*args, max_relax=1, dense=dense)
+    torch.cuda.synchronize()
+    assert int(s.item()) == 1
+    assert torch.all(dense == 7.0)
+    _, s = dgf.epic_async(*args, max_relax=64, dense=dense)
+    torch.cuda.synchronize()
+    assert int(s.item()) == 0 and not torch.all(dense == 7.0)
+    with pytest.raises(RuntimeError):
+        dgf.epic_async(*args, max_relax=-1)
+
+
+def test_async_in_a_captured_graph():
+    # tracking and interpolation of the driving pair captured into one graph (the tracker's
+    # pyramids and points, then dgf_epic_async), replayed three times with other work between the
+    # replays; every replay equals the eager, synchronising call on the same tracks
+    I0, I1, _, _ = synth.driving_1242x375()
+    W, H = 1242, 375
+    a, b = torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda()
+    n = dgf.detect_count(W, H, 9, 5)
+    pts = torch.empty((n, 2), dtype=torch.float32, device="cuda")
+    flow = torch.empty((n, 2), dtype=torch.float32, device="cuda")
+    st = torch.empty(n, dtype=torch.uint8, device="cuda")
+    ws = torch.empty(dgf.track_workspace_bytes(W, H, 5, 0), dtype=torch.uint8, device="cuda")
+    ews = torch.empty(dgf.epic_workspace_bytes(W, H, n), dtype=torch.uint8, device="cuda")
+    dense = torch.empty((H, W, 2), dtype=torch.float32, device="cuda")
+    status = torch.empty(1, dtype=torch.int32, device="cuda")
+
+    def pipeline():
+        dgf.detect_pyramids(a, b, 9, 5, 5, ws, pts)
+        dgf.track_run(a, b, pts, 5, 21, 20, ws, flow, st)
+        dgf.epic_async(a, pts, flow, st, workspace=ews, dense=dense, status_out=status)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        pipeline()  # warm-up outside the capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    ref = dgf.epic(a, pts, flow, st).clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pipeline()
+    for rep in range(3):
+        dense.fill_(0.0)
+        status.fill_(-1)
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(status.item()) == 0, rep
+        assert torch.equal(dense.view(torch.int32), ref.view(torch.int32)), rep
+        x = torch.randn(1 << 20, device="cuda")
+        _ = (x * 2).sum().item()
