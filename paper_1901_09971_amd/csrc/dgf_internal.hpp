@@ -396,7 +396,7 @@ __device__ __forceinline__ void detect_tile(uint8_t *tile, int tile_x, int tile_
     __syncthreads();
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int kx = wx0 + tx, ky = wy0 + ty;
-    if (kx >= nx || ky >= ny) return;
+    if (ty >= TY || kx >= nx || ky >= ny) return; // (blocks may have more lanes than windows)
     const uint8_t *w0 = tile + ty * stride * RP + tx * stride;
     int S = 0, Mi = 0, Mj = 0, m = 0;
     for (int i = 0; i < win; ++i) {
