@@ -103,9 +103,11 @@ __device__ __forceinline__ unsigned group_or(unsigned v)
     return v;
 }
 
-// Sums of five values over all 64 lanes, returned wave-uniform.  Transposed reduction: the
-// half- and row-swap permutes add two different values in one step (each half, then each row,
-// keeps a different value), so only two registers remain for the in-row DPP butterflies.
+// Sums of five values over all 64 lanes, returned wave-uniform.  Transposed reduction for four of
+// them: the half- and row-swap permutes add two different values in one step (each half, then
+// each row, keeps a different value), so one register remains for the in-row DPP butterflies.
+// The fifth takes the in-row butterflies and then two row broadcasts (row 0 into row 1 and row
+// 2 into row 3, then row 1 into rows 2 and 3), which leave its sum in lane 63.
 __device__ __forceinline__ void wave_sum5(float &a, float &b, float &c, float &d, float &e)
 {
     auto swap32 = [](float x, float y) {
@@ -118,10 +120,10 @@ __device__ __forceinline__ void wave_sum5(float &a, float &b, float &c, float &d
                                                         false, false);
         return __builtin_bit_cast(float, (unsigned)p[0]) + __builtin_bit_cast(float, (unsigned)p[1]);
     };
-    // lanes 0-31 / 32-63 now hold half-sums of (a | d), (b | e), (c | 0)
-    const float x1 = swap32(a, d), x2 = swap32(b, e), x3 = swap32(c, 0.f);
-    // rows 0..3 of y1 hold 16-lane partials of a, b, d, e; rows 0 and 2 of y2 hold c
-    float y1 = swap16(x1, x2), y2 = swap16(x3, x3);
+    // lanes 0-31 / 32-63 now hold half-sums of (a | d), (b | e)
+    const float x1 = swap32(a, d), x2 = swap32(b, e);
+    // rows 0..3 of y1 hold 16-lane partials of a, b, d, e
+    float y1 = swap16(x1, x2), y2 = c;
     y1 += dpp<0xB1>(y1);
     y2 += dpp<0xB1>(y2);
     y1 += dpp<0x4E>(y1);
@@ -130,11 +132,22 @@ __device__ __forceinline__ void wave_sum5(float &a, float &b, float &c, float &d
     y2 += dpp<0x141>(y2);
     y1 += dpp<0x140>(y1);
     y2 += dpp<0x140>(y2);
+    // rows 1 and 3 add lane 15 / 47 (row_bcast:15), rows 2 and 3 then lane 31 (row_bcast:31); the
+    // other rows keep their value.  Written out because the compiler turns a DPP add on some rows
+    // into a zeroed copy, a DPP move and an add.  The s_nops give the two wait states a DPP read
+    // needs after a vector write of its source (also for a DPP read of the result after the
+    // block, which the compiler's hazard check cannot see); the block touches registers only.
+    asm("s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+        "s_nop 1"
+        : "+v"(y2));
     a = readlane(y1, 0);
     b = readlane(y1, 16);
     d = readlane(y1, 32);
     e = readlane(y1, 48);
-    c = readlane(y2, 0);
+    c = readlane(y2, 63);
 }
 
 __device__ __forceinline__ bool wave_all(bool p) { return __builtin_amdgcn_ballot_w64(!p) == 0ull; }
@@ -284,6 +297,85 @@ __device__ __forceinline__ void stage_rect(float *lds, int lp, const uint8_t *ba
             }
         }
     }
+}
+
+// Steps of stage_u8_w64 (below) for one lane: NS steps of 8 rows from byte offset a0 (aligned)
+// with shift sh off the aligned base gb, B steps' loads in flight.  WHOLE: every group writes
+// all four words (the row's last group fits the LDS row); otherwise the row's last group writes
+// only the words it owns.
+template <int NS, int B, bool EXACT, bool WHOLE>
+__device__ __forceinline__ void stage_u8_w64_steps(float *lds, int lp, const __attribute__((address_space(1))) uint8_t *gb,
+                                                   uint32_t pb, uint32_t a0, uint32_t alast, uint32_t sh, int r0,
+                                                   int c4, int rows, int cols)
+{
+    typedef const __attribute__((address_space(1))) uint32_t gword;
+#pragma unroll
+    for (int k0 = 0; k0 < NS; k0 += B) {
+        uint32_t lo[B], hi[B];
+#pragma unroll
+        for (int k = k0; k < k0 + B && k < NS; ++k) {
+            uint32_t a = a0 + (uint32_t)(8 * k) * pb;
+            if (!EXACT) a = min(a, alast);
+            gword *p = (gword *)(gb + a);
+            lo[k - k0] = p[0];
+            hi[k - k0] = p[1];
+        }
+#pragma unroll
+        for (int k = k0; k < k0 + B && k < NS; ++k) {
+            if (EXACT || r0 + 8 * k < rows) {
+                const uint32_t v = __builtin_amdgcn_alignbyte(hi[k - k0], lo[k - k0], sh);
+                float *d = lds + (r0 + 8 * k) * lp + c4;
+                const float f0 = (float)(v & 255u), f1 = (float)((v >> 8) & 255u), f2 = (float)((v >> 16) & 255u),
+                            f3 = (float)(v >> 24);
+                if (WHOLE || c4 + 4 <= cols) {
+                    d[0] = f0;
+                    d[1] = f1;
+                    d[2] = f2;
+                    d[3] = f3;
+                } else {
+                    d[0] = f0;
+                    if (c4 + 1 < cols) d[1] = f1;
+                    if (c4 + 2 < cols) d[2] = f2;
+                }
+            }
+        }
+    }
+}
+
+// stage_rect's interior case for a rectangle staged by a whole wavefront (64 lanes) from a uint8
+// image: the same values, with the steps unrolled.  Qualifies when rows <= 8 NS, cols <= 32 and
+// the rectangle lies inside the image with every row's dword pairs inside the row (stage_rect's
+// own interior test); returns false, staging nothing, otherwise.  Eight lanes per row, four bytes
+// per lane, row r0 + 8 k in step k.  The base pointer is moved back to a 4-byte boundary once;
+// 8 k rows further on the byte shift is the same (8 pitch is a multiple of 4), so a step costs an
+// offset add, one v_alignbyte and four conversions.  The loads are unpredicated and go out B steps
+// at a time, all of a batch before its first LDS write: a step past the rectangle's last row loads
+// that row again and writes nothing.  When the row's last group of four fits the LDS row pitch it
+// writes all four words (the extra ones land in the row's padding, which no reader looks at).
+// CROWS = 8 NS tells that rows always equals it (no clamp, no write test).
+template <int NS, int B, int CROWS = 0>
+__device__ __forceinline__ bool stage_u8_w64(float *lds, int lp, const uint8_t *base, int64_t pitch, int W, int H,
+                                             int ox, int oy, int rows, int cols, int li)
+{
+    constexpr bool exact = CROWS == 8 * NS;
+    if (!(rows <= 8 * NS && cols <= 32 && ox >= 3 && oy >= 0 && ox + 4 * ((cols + 3) >> 2) + 4 <= W && oy + rows <= H))
+        return false;
+    typedef const __attribute__((address_space(1))) uint8_t gbyte;
+    const int r0 = li >> 3, c4 = (li & 7) << 2;
+    if (c4 >= cols || r0 >= rows) return true;
+    const uint32_t mis = (uint32_t)(uintptr_t)base & 3u;
+    gbyte *gb = (gbyte *)(base - mis); // 4-byte aligned
+    const uint32_t pb = (uint32_t)pitch;
+    // byte offset of the lane's first pixel off the aligned base (step 0), its shift and the
+    // aligned offset; then the aligned offset of the lane's pixel in the rectangle's last row
+    const uint32_t o0 = __umul24((uint32_t)(oy + r0), pb) + (uint32_t)(ox + c4) + mis;
+    const uint32_t sh = o0 & 3u, a0 = o0 - sh;
+    const uint32_t alast = exact ? 0u : a0 + __umul24((uint32_t)(rows - 1 - r0), pb);
+    if (4 * ((cols + 3) >> 2) <= lp)
+        stage_u8_w64_steps<NS, B, exact, true>(lds, lp, gb, pb, a0, alast, sh, r0, c4, rows, cols);
+    else
+        stage_u8_w64_steps<NS, B, exact, false>(lds, lp, gb, pb, a0, alast, sh, r0, c4, rows, cols);
+    return true;
 }
 
 // i / d for 0 <= i < 2^16 and 1 <= d < 2^8, with inv = 1 / d: (i + 1/2) / d is at least 1 / (2 d)

@@ -82,6 +82,31 @@ __device__ __forceinline__ void cross_arms(const float *raw, int *arms, float ta
     }
 }
 
+// The integer value of a wave-uniform integral float (a floor), decoded from its bits by scalar
+// instructions (one vector read-first-lane): exact below 2^23 in magnitude, +-2^23 beyond and for
+// non-finite values, which keeps every tile offset far from integer overflow (staging clamps each
+// address into the image).
+__device__ __forceinline__ int uniform_floor_int(float f)
+{
+    const int b = __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, f));
+    const int e = ((b >> 23) & 0xFF) - 127; // unbiased exponent; -127 for +-0
+    const int mag = e < 0 ? 0 : e >= 23 ? (1 << 23) : (((b & 0x7FFFFF) | 0x800000) >> (23 - e));
+    return b < 0 ? -mag : mag;
+}
+
+// A square rectangle (rows = cols) of at most 8 NS rows into LDS (B steps' loads in flight;
+// CROWS: its row count when fixed at compile time): the unrolled whole-wavefront form for uint8
+// images where it qualifies, stage_rect otherwise, its lane layout worked out there and then
+// (border tiles are rare, and the layout would otherwise hold registers for the whole launch).
+template <int LPP, typename PixT, int NS, int B, int CROWS = 0>
+__device__ __forceinline__ void stage_tile(float *lds, int lp, const uint8_t *base, int64_t pitch, int W, int H, int ox,
+                                           int oy, int rows, int cols, int li)
+{
+    if constexpr (LPP == 64 && sizeof(PixT) == 1)
+        if (stage_u8_w64<NS, B, CROWS>(lds, lp, base, pitch, W, H, ox, oy, rows, cols, li)) return;
+    stage_rect<LPP, PixT>(lds, lp, base, pitch, W, H, ox, oy, rows, cols, stage_lanes<LPP>(cols, li));
+}
+
 // True when the flag is set on any lane of the wavefront.  With one point per wavefront (64 lanes
 // per point) every lane holds the same value, so the flag itself decides the branch: no ballot,
 // whose lowering would spend two vector instructions turning a mask back into a condition.
@@ -117,7 +142,6 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
     constexpr int s = S, r = S / 2, RW = S + 3, RP = (RW % 4 == 0) ? RW + 2 : RW, G = S + 2;
     static_assert(S % R == 0, "runs must tile the support rows");
     const int TW = P.TW, M = P.M;
-    const StageLanes slR = stage_lanes<LPP>(RW, li), slT = stage_lanes<LPP>(TW, li);
     constexpr int nseg_row = s / R; // runs per support row
     constexpr int nseg = s * nseg_row;
 
@@ -133,6 +157,10 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
         const int row = gg / nseg_row;
         const int col0 = (gg - row * nseg_row) * R;
         sb[j] = row * TP + col0;
+        // one register holding the whole offset: the run's tile address is then a single
+        // shift-and-add off the wave's tile origin (the compiler would otherwise keep the row
+        // and column terms apart and add them in every iteration)
+        asm("" : "+v"(sb[j]));
         rc[j] = (row << 8) | col0;
         vmask |= (vg ? 1u : 0u) << j;
     }
@@ -196,7 +224,7 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
 
         // ---- template: raw I0_l patch (s+3)^2 with replicated border, row pitch RP
         wave_sync();
-        stage_rect<LPP, PixT>(tile, RP, LV.p0, LV.pitch0, Wl, Hl, ibx - 1, iby - 1, RW, RW, slR);
+        stage_tile<LPP, PixT, (RW + 7) / 8, (RW + 7) / 8, RW>(tile, RP, LV.p0, LV.pitch0, Wl, Hl, ibx - 1, iby - 1, RW, RW, li);
         wave_sync();
         // Bilinear resample of the raw patch on the (s + 2)^2 grid of support offsets -r-1 .. r+1
         // (every sample shares the point's fraction): lanes take runs of kRes grid columns of one
@@ -345,13 +373,10 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
             // occurs on a point already stopped, whose samples are discarded)
             int ix, iy;
             if constexpr (LPP == 64) {
-                // one point per wavefront: the position is wave-uniform.  An integral float below
-                // 2^22 in magnitude plus 1.5 * 2^23 is exact and holds the value plus 2^22 in its low
-                // 23 bits, so one add and one read-first-lane give the integer to scalar code; larger
-                // or non-finite values decode to something in [-2^22, 2^22), which keeps every tile
-                // offset far from integer overflow (staging clamps each address into the image).
-                ix = (__builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, flx + 12582912.f)) & 0x7FFFFF) - 0x400000;
-                iy = (__builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, fly + 12582912.f)) & 0x7FFFFF) - 0x400000;
+                // one point per wavefront: the position is wave-uniform, and scalar code decodes
+                // the integer from the floor's bits
+                ix = uniform_floor_int(flx);
+                iy = uniform_floor_int(fly);
             } else {
                 ix = (int)__builtin_amdgcn_fmed3f(flx, -1048576.f, 1048576.f);
                 iy = (int)__builtin_amdgcn_fmed3f(fly, -1048576.f, 1048576.f);
@@ -363,7 +388,7 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
                 wave_sync();
                 ox1 = bx - M;
                 oy1 = by - M;
-                stage_rect<LPP, PixT>(tile, TP, LV.p1, LV.pitch1, Wl, Hl, ox1, oy1, TW, TW, slT);
+                stage_tile<LPP, PixT, (TP + 7) / 8, 2>(tile, TP, LV.p1, LV.pitch1, Wl, Hl, ox1, oy1, TW, TW, li);
                 wave_sync();
                 dxo = M;
                 dyo = M;
