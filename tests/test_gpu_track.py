@@ -140,3 +140,29 @@ def test_deterministic():
     a = dgf.track(torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda(), pts, 4, 21, 20)
     b = dgf.track(torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda(), pts, 4, 21, 20)
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("offset,extra", [(1, 5), (2, 3), (3, 7)])
+def test_pitched_unaligned_frames_match_contiguous(offset, extra):
+    # The frames are views into larger buffers: the first pixel `offset` bytes past a 4-byte
+    # boundary and rows `extra` bytes longer than the image, so level-0 tiles are staged from
+    # dword pairs at every byte shift.  Same pixels, so flow and status must be bit-identical to
+    # the contiguous frames'.
+    I0, I1, _, _ = synth.driving_1242x375()
+    H, W = I0.shape
+    pts = torch.from_numpy(oracle.detect(I0, 9, 5)[0].astype(np.float32)).cuda()
+    t0, t1 = torch.from_numpy(I0).cuda(), torch.from_numpy(I1).cuda()
+    f_ref, s_ref = dgf.track(t0, t1, pts, 5, 21, 20)
+
+    def view(img):
+        buf = torch.zeros(offset + H * (W + extra), dtype=torch.uint8, device="cuda")
+        v = buf[offset:].view(H, W + extra)[:, :W]
+        v.copy_(torch.from_numpy(img).cuda())
+        assert v.data_ptr() % 4 == offset % 4 and v.stride(0) == W + extra
+        return v
+
+    v0, v1 = view(I0), view(I1)
+    f, s = dgf.track(v0, v1, pts, 5, 21, 20)
+    torch.cuda.synchronize()
+    assert torch.equal(s, s_ref)
+    assert torch.equal(f.view(torch.int32), f_ref.view(torch.int32))
