@@ -603,6 +603,30 @@ __device__ __forceinline__ WorkItem work_item(const TrackParams &P, int64_t item
 // and every XCD has an L2 of its own.
 constexpr int kNumXcd = 8;
 
+// Plain row-run launches hand each XCD runs of kXcdRun consecutive points: the blocks of XCD x
+// take runs x, x + 8, x + 16, ... in their launch order, so a point's flow and status lines are
+// written back from one L2 rather than from up to eight, and the launch order still takes the
+// points from the last one back in steps of 8 kXcdRun.  The grid is a whole number of such groups
+// of 8 runs (plain_blocks); waves past the last point find nothing to do.  PPW points per wave,
+// wpb waves per block, both powers of two with wpb PPW <= kXcdRun.
+constexpr int kXcdRun = 64;
+
+template <int PPW>
+__device__ __forceinline__ int64_t plain_item(unsigned b, int wave, int wpb)
+{
+    const int ppb = wpb * PPW;                         // points per block
+    const int kb_log = __builtin_ctz(kXcdRun / ppb);    // blocks per run, log2
+    const unsigned x = b % kNumXcd, j = b / kNumXcd;    // XCD, and the block's rank on it
+    const int64_t run = (int64_t)(j >> kb_log) * kNumXcd + x;
+    return (run * kXcdRun + (int64_t)(j & ((1u << kb_log) - 1)) * ppb) / PPW + wave;
+}
+
+inline int64_t plain_blocks(int64_t blocks, int wpb, int ppw)
+{
+    const int64_t group = (int64_t)kNumXcd * (kXcdRun / (wpb * ppw));
+    return (blocks + group - 1) / group * group;
+}
+
 // Persistent form: the items are split into kNumXcd contiguous ranges, one per XCD, each with a
 // counter of its own (kCounterStride words apart, so they sit in different cache lines).  A
 // wavefront takes items from the range of the XCD it runs on and, once that range is drained, from

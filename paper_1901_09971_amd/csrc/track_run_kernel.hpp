@@ -167,14 +167,17 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
 
     float T[PPL], GX[PPL], GY[PPL];
 
-    // Plain launches keep the hardware's order of blocks (taking the points from the last one
-    // back, see work_item): block b on XCD b mod 8 spreads every image band over all eight XCDs,
-    // which balances the uneven per-point work.  (Giving each XCD one band
-    // cut L2 fills 4.6x on the 1242x375 benchmark pair but made the launch 25% longer.)
-    // Persistent launches pull from the queue of their own XCD first.
+    // Plain launches give each XCD runs of 64 consecutive points in turn (plain_item; the points
+    // are taken from the last one back, see work_item): every image band is still spread over all
+    // eight XCDs, which balances the uneven per-point work, while each point's output lines are
+    // written from one L2.  (Giving each XCD one band cut L2 fills 4.6x on the 1242x375 benchmark
+    // pair but made the launch 25% longer.)  Persistent launches pull from the queue of their own
+    // XCD first.
     const int home = (int)(blockIdx.x % kNumXcd);
     int visit = 0;
-    int64_t item = (BATCH && P.persistent) ? next_item(P, home, visit) : (int64_t)blockIdx.x * wpb + wave;
+    int64_t item = (BATCH && P.persistent) ? next_item(P, home, visit)
+                   : (!BATCH || P.npairs == 0) ? plain_item<PPW>(blockIdx.x, wave, wpb)
+                                               : (int64_t)blockIdx.x * wpb + wave;
     for (;;) {
     const WorkItem wi = work_item<PPW, BATCH>(P, item, q);
     if (wi.done) break;
@@ -673,7 +676,7 @@ hipError_t launch_track_run_t(const TrackParams &P, int wpb, hipStream_t st)
 {
     constexpr int PPW = 64 / LPP;
     const int64_t waves = P.npairs ? P.grid_waves : (P.n + PPW - 1) / PPW;
-    const int64_t blocks = (waves + wpb - 1) / wpb;
+    const int64_t blocks = P.npairs ? (waves + wpb - 1) / wpb : plain_blocks((waves + wpb - 1) / wpb, wpb, PPW);
     const size_t lds = (size_t)wpb * PPW * P.tile_floats * sizeof(float);
     const dim3 grid((unsigned)blocks), block(64 * wpb);
     if (P.mode == ROBUST_L2)
