@@ -24,7 +24,9 @@
 // position (neighbouring points overlap, so the device atomics stay).  Atomic order is not
 // deterministic; sums agree up to FP32 rounding.  The batched form runs every point of a batch
 // plan in one launch; a wavefront finds its pair by binary search over the plan's point offsets.
+#include <algorithm>
 #include <cmath>
+#include <numeric>
 
 #include "dgf_internal.hpp"
 
@@ -75,8 +77,7 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
 {
     extern __shared__ float smem[];
     const int li = threadIdx.x;
-    const int64_t i = blockIdx.x;
-    if (i >= A.n) return; // whole wave: the grid is exactly n wide
+    const int64_t i = (int64_t)(((uint64_t)blockIdx.x * (uint64_t)A.perm_mul) % (uint64_t)A.n);
     if (A.dpoints && li == 0) reinterpret_cast<float2 *>(A.dpoints)[i] = make_float2(0.f, 0.f);
     if (A.status[i] != DGF_ST_CONVERGED) return;
     const AdjPair Pr = A.npairs ? A.pairs[adj_pair_of(A, i)] : A.one;
@@ -246,6 +247,199 @@ __global__ __launch_bounds__(64) void k_track_adjoint(AdjParams A)
     }
 }
 
+// k_track_adjoint for a support size fixed at compile time (no illumination model): the same
+// quantities by the same formulas, arranged for fewer instructions.  The bilinearly resampled I0
+// patch on the (S + 2)^2 grid of support offsets -r-1 .. r+1 is built once in LDS, and every
+// lane computes its pixels' template gradient, I1 sample and gradient, residual and psi band once
+// (NS slots of 64 pixels) and keeps them in registers for the fallback-regime test and both
+// passes; the fields c1, cx, cy and F sit in LDS arrays with a zero border, so the gathers read
+// them without bounds tests; divisions by the support size are by a constant.
+template <typename PixT, int S>
+__global__ __launch_bounds__(64) void k_track_adjoint_fixed(AdjParams A)
+{
+    constexpr int r = S / 2, S2 = S * S, NS = (S2 + 63) / 64;
+    constexpr int w0 = S + 3, w1 = S + 1, n0 = w0 * w0, n1 = w1 * w1;
+    constexpr int G = S + 2;      // resampled grid: support offsets -r-1 .. r+1
+    constexpr int PC = S + 4;     // c1, cx, cy with a zero border of 2: support (a, b) at (a + 2, b + 2)
+    constexpr int PF = S + 4;     // F with a zero border of 1: grid (x, y) at (x + 1, y + 1)
+    extern __shared__ float smem[];
+    const int li = threadIdx.x;
+    const int64_t i = (int64_t)(((uint64_t)blockIdx.x * (uint64_t)A.perm_mul) % (uint64_t)A.n);
+    if (A.dpoints && li == 0) reinterpret_cast<float2 *>(A.dpoints)[i] = make_float2(0.f, 0.f);
+    if (A.status[i] != DGF_ST_CONVERGED) return;
+    const AdjPair Pr = A.npairs ? A.pairs[adj_pair_of(A, i)] : A.one;
+    const float2 p = reinterpret_cast<const float2 *>(A.pts)[i];
+    const float2 u = reinterpret_cast<const float2 *>(A.flow)[i];
+    const float2 lam = reinterpret_cast<const float2 *>(A.dflow)[i];
+    const int W = Pr.W, H = Pr.H;
+
+    const float pbx = floorf(p.x), pby = floorf(p.y);
+    const float fx0 = p.x - pbx, fy0 = p.y - pby;
+    const float tx = fx0 + u.x, ty = fy0 + u.y;
+    const float qbx = floorf(tx), qby = floorf(ty);
+    const float fx1 = tx - qbx, fy1 = ty - qby;
+    const int ox0 = (int)pbx - r - 1, oy0 = (int)pby - r - 1;
+    const int ox1 = (int)pbx + (int)fminf(fmaxf(qbx, -1048576.f), 1048576.f) - r;
+    const int oy1 = (int)pby + (int)fminf(fmaxf(qby, -1048576.f), 1048576.f) - r;
+    const float a00 = (1.f - fx0) * (1.f - fy0), a10 = fx0 * (1.f - fy0), a01 = (1.f - fx0) * fy0, a11 = fx0 * fy0;
+    const float b00 = (1.f - fx1) * (1.f - fy1), b10 = fx1 * (1.f - fy1), b01 = (1.f - fx1) * fy1, b11 = fx1 * fy1;
+
+    // LDS: region 0 holds the raw patches, then c1, cx, cy; region 1 the grid, then F
+    float *raw0 = smem, *raw1 = smem + n0;
+    float *C1 = smem, *CX = C1 + PC * PC, *CY = CX + PC * PC;
+    float *grid = smem + 3 * PC * PC, *F = grid;
+    stage_rect<64, PixT>(raw0, w0, Pr.I0, Pr.pitch0, W, H, ox0, oy0, w0, w0, stage_lanes<64>(w0, li));
+    stage_rect<64, PixT>(raw1, w1, Pr.I1, Pr.pitch1, W, H, ox1, oy1, w1, w1, stage_lanes<64>(w1, li));
+    __syncthreads();
+    for (int c = li; c < G * G; c += 64) {
+        const int y = c / G, x = c - y * G;
+        grid[c] = lerp_cell(raw0 + y * w0 + x, w0, fx0, fy0);
+    }
+    __syncthreads();
+
+    // per slot: the pixel's template central differences, I1 gradient, residual and psi band
+    float g0[NS], g1[NS], djx[NS], djy[NS], res[NS], ps[NS], dps[NS];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        const int k = li + 64 * t;
+        const bool in = k < S2;
+        const int kk = in ? k : 0;
+        const int ky = kk / S, kx = kk - ky * S;
+        const float *gc = grid + (ky + 1) * G + kx + 1;
+        const float T = gc[0];
+        g0[t] = in ? 0.5f * (gc[1] - gc[-1]) : 0.f;
+        g1[t] = in ? 0.5f * (gc[G] - gc[-G]) : 0.f;
+        const float *q = raw1 + ky * w1 + kx;
+        const float i00 = q[0], i10 = q[1], i01 = q[w1], i11 = q[w1 + 1];
+        const float J = lerp_cell(q, w1, fx1, fy1);
+        djx[t] = (1.f - fy1) * (i10 - i00) + fy1 * (i11 - i01);
+        djy[t] = (1.f - fx1) * (i01 - i00) + fx1 * (i11 - i10);
+        res[t] = J - T;
+        psi_and_slope(A, res[t], ps[t], dps[t]);
+        if (!in) {
+            ps[t] = 0.f;
+            dps[t] = 0.f;
+        }
+    }
+    // the norm of the equation the forward pass stopped on (as in k_track_adjoint)
+    if (A.mode != ROBUST_L2) {
+        float a = 0.f, b = 0.f, c = 0.f, a0 = 0.f, b0 = 0.f, c0 = 0.f;
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            const float w = res[t] != 0.f ? ps[t] / res[t] : 1.f;
+            a = fmaf(w * g0[t], g0[t], a);
+            b = fmaf(w * g0[t], g1[t], b);
+            c = fmaf(w * g1[t], g1[t], c);
+            a0 = fmaf(g0[t], g0[t], a0);
+            b0 = fmaf(g0[t], g1[t], b0);
+            c0 = fmaf(g1[t], g1[t], c0);
+        }
+        float z = 0.f;
+        wave_sum5(a, b, c, a0, b0);
+        wave_sum5(c0, z, z, z, z);
+        if (!(fmaf(a, c, -b * b) > 1e-6f * fmaf(a0, c0, -b0 * b0))) {
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+                const bool in = li + 64 * t < S2;
+                ps[t] = in ? res[t] : 0.f;
+                dps[t] = in ? 1.f : 0.f;
+            }
+        }
+    }
+
+    // pass 1: J = sum psi' g (grad J)^T; with dpoints also K (see k_track_adjoint)
+    const bool want_dp = A.dpoints != nullptr;
+    float J00 = 0.f, J01 = 0.f, J10 = 0.f, J11 = 0.f;
+    float K00 = 0.f, K01 = 0.f, K10 = 0.f, K11 = 0.f;
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        J00 = fmaf(dps[t] * g0[t], djx[t], J00);
+        J01 = fmaf(dps[t] * g0[t], djy[t], J01);
+        J10 = fmaf(dps[t] * g1[t], djx[t], J10);
+        J11 = fmaf(dps[t] * g1[t], djy[t], J11);
+    }
+    if (want_dp) {
+        auto I0g = [&](int lx, int ly, float &gx, float &gy) {
+            const float *q = raw0 + ly * w0 + lx;
+            gx = (1.f - fy0) * (q[1] - q[0]) + fy0 * (q[w0 + 1] - q[w0]);
+            gy = (1.f - fx0) * (q[w0] - q[0]) + fx0 * (q[w0 + 1] - q[1]);
+        };
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            const int k = li + 64 * t;
+            if (k < S2) {
+                const int ky = k / S, kx = k - ky * S, lx = kx + 1, ly = ky + 1;
+                float tgx, tgy, pxx, pxy, mxx, mxy, pyx, pyy, myx, myy;
+                I0g(lx, ly, tgx, tgy);
+                I0g(lx + 1, ly, pxx, pxy);
+                I0g(lx - 1, ly, mxx, mxy);
+                I0g(lx, ly + 1, pyx, pyy);
+                I0g(lx, ly - 1, myx, myy);
+                K00 += -dps[t] * g0[t] * tgx + 0.5f * ps[t] * (pxx - mxx);
+                K01 += -dps[t] * g0[t] * tgy + 0.5f * ps[t] * (pxy - mxy);
+                K10 += -dps[t] * g1[t] * tgx + 0.5f * ps[t] * (pyx - myx);
+                K11 += -dps[t] * g1[t] * tgy + 0.5f * ps[t] * (pyy - myy);
+            }
+        }
+    }
+    float z = 0.f;
+    wave_sum5(J00, J01, J10, J11, z);
+    if (want_dp) wave_sum5(K00, K01, K10, K11, z);
+    const float det = J00 * J11 - J01 * J10;
+    if (!(det != 0.f) || !isfinite(det)) return; // uniform across the wave
+    const float mux = (J11 * lam.x - J10 * lam.y) / det;
+    const float muy = (J00 * lam.y - J01 * lam.x) / det;
+    if (want_dp && li == 0)
+        reinterpret_cast<float2 *>(A.dpoints)[i] =
+            make_float2(-lam.x - (K00 * mux + K10 * muy), -lam.y - (K01 * mux + K11 * muy));
+
+    // pass 2: c1, cx, cy on the support, zero around it (the raw patches are no longer read)
+    __syncthreads();
+    for (int c = li; c < 3 * PC * PC; c += 64) C1[c] = 0.f;
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        const int k = li + 64 * t;
+        if (k < S2) {
+            const int ky = k / S, kx = k - ky * S, e = (ky + 2) * PC + kx + 2;
+            C1[e] = dps[t] * (mux * g0[t] + muy * g1[t]);
+            CX[e] = -0.5f * ps[t] * mux;
+            CY[e] = -0.5f * ps[t] * muy;
+        }
+    }
+    __syncthreads();
+    // F on the support grid extended by one ring (a, b in [-1, S]), zero around it; the grid is no
+    // longer read
+    for (int c = li; c < PF * PF; c += 64) {
+        const int y = c / PF, x = c - y * PF; // F index (x - 1, y - 1) = support (x - 2, y - 2)
+        float v = 0.f;
+        if (x >= 1 && x <= G && y >= 1 && y <= G) {
+            const float *e = C1 + y * PC + x; // support (x - 2, y - 2) sits at (x, y)
+            v = e[0] + CX[y * PC + x - 1] - CX[y * PC + x + 1] + CY[(y - 1) * PC + x] - CY[(y + 1) * PC + x];
+        }
+        F[c] = v;
+    }
+    // dI1 cells: - sum of the 4 taps of c1 (cell X reads support X - t at padded X - t + 2)
+    float *dI1 = A.grad1 + Pr.g1;
+    for (int c = li; c < n1; c += 64) {
+        const int Y = c / w1, X = c - Y * w1;
+        const float *e = C1 + (Y + 2) * PC + X + 2;
+        const float v = -(b00 * e[0] + b10 * e[-1] + b01 * e[-PC] + b11 * e[-PC - 1]);
+        if (v != 0.f)
+            unsafeAtomicAdd(dI1 + (int64_t)clampi(oy1 + Y, 0, H - 1) * Pr.gpitch1 + clampi(ox1 + X, 0, W - 1), v);
+    }
+    __syncthreads();
+    // dI0 cells: the 4 bilinear taps of F; cell X reads F index X - t, padded at X - t + 1
+    float *dI0 = A.grad0 + Pr.g0;
+    for (int c = li; c < n0; c += 64) {
+        const int Y = c / w0, X = c - Y * w0;
+        const float *f = F + (Y + 1) * PF + X + 1;
+        const float v = a00 * f[0] + a10 * f[-1] + a01 * f[-PF] + a11 * f[-PF - 1];
+        if (v != 0.f)
+            unsafeAtomicAdd(dI0 + (int64_t)clampi(oy0 + Y, 0, H - 1) * Pr.gpitch0 + clampi(ox0 + X, 0, W - 1), v);
+    }
+}
+
 // 4x4 system M^T x = v by Gaussian elimination with partial pivoting, fully unrolled (M row-major,
 // both copied); x is not finite when a pivot is zero.
 __device__ __forceinline__ void solve4_transposed(const float *M, const float *v, float *x)
@@ -303,8 +497,7 @@ __global__ __launch_bounds__(64) void k_track_adjoint_illum(AdjParams A)
 {
     extern __shared__ float smem[];
     const int li = threadIdx.x;
-    const int64_t i = blockIdx.x;
-    if (i >= A.n) return; // whole wave: the grid is exactly n wide
+    const int64_t i = (int64_t)(((uint64_t)blockIdx.x * (uint64_t)A.perm_mul) % (uint64_t)A.n);
     if (A.dpoints && li == 0) reinterpret_cast<float2 *>(A.dpoints)[i] = make_float2(0.f, 0.f);
     if (A.status[i] != DGF_ST_CONVERGED) return;
     const AdjPair Pr = A.npairs ? A.pairs[adj_pair_of(A, i)] : A.one;
@@ -523,15 +716,42 @@ size_t adjoint_lds_bytes(int s)
     return sizeof(float) * (size_t)((s + 3) * (s + 3) + (s + 1) * (s + 1) + 4 * s * s);
 }
 
-hipError_t launch_track_adjoint(const AdjParams &A, int dtype, hipStream_t st)
+// Blocks take the points in a scattered order, point (b M) mod n for M coprime to n near 0.618 n:
+// the waves in flight at any time then lie spread over the frames instead of covering a band a few
+// point rows high, whose windows overlap tens of times and would queue their gradient atomics on
+// the same addresses.  Each point is still taken exactly once.
+static int64_t scatter_multiplier(int64_t n)
 {
-    if (A.n <= 0) return hipSuccess;
+    int64_t m = std::max<int64_t>(1, (int64_t)llround(0.6180339887498949 * (double)n));
+    while (std::gcd(m, n) != 1) ++m;
+    return m;
+}
+
+hipError_t launch_track_adjoint(const AdjParams &A0, int dtype, hipStream_t st)
+{
+    if (A0.n <= 0) return hipSuccess;
+    AdjParams A = A0;
+    A.perm_mul = scatter_multiplier(A.n);
     const size_t lds = adjoint_lds_bytes(A.s);
     if (A.illum) {
         if (dtype == DGF_U8)
             hipLaunchKernelGGL(k_track_adjoint_illum<uint8_t>, dim3((unsigned)A.n), dim3(64), lds, st, A);
         else
             hipLaunchKernelGGL(k_track_adjoint_illum<float>, dim3((unsigned)A.n), dim3(64), lds, st, A);
+    } else if (A.s == 21 || A.s == 9) {
+        // the support sizes of the benchmark workloads: the fixed-size form
+        const size_t lds_fixed = sizeof(float) * 4 * (size_t)(A.s + 4) * (A.s + 4);
+        if (A.s == 21) {
+            if (dtype == DGF_U8)
+                hipLaunchKernelGGL((k_track_adjoint_fixed<uint8_t, 21>), dim3((unsigned)A.n), dim3(64), lds_fixed, st, A);
+            else
+                hipLaunchKernelGGL((k_track_adjoint_fixed<float, 21>), dim3((unsigned)A.n), dim3(64), lds_fixed, st, A);
+        } else {
+            if (dtype == DGF_U8)
+                hipLaunchKernelGGL((k_track_adjoint_fixed<uint8_t, 9>), dim3((unsigned)A.n), dim3(64), lds_fixed, st, A);
+            else
+                hipLaunchKernelGGL((k_track_adjoint_fixed<float, 9>), dim3((unsigned)A.n), dim3(64), lds_fixed, st, A);
+        }
     } else if (dtype == DGF_U8)
         hipLaunchKernelGGL(k_track_adjoint<uint8_t>, dim3((unsigned)A.n), dim3(64), lds, st, A);
     else

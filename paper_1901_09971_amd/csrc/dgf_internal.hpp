@@ -745,6 +745,7 @@ struct AdjParams {
     int64_t n;
     float s1, s2, dpsi_mid; // thresholds and the middle-band slope -sigma1 / (sigma2 - sigma1)
     int32_t mode;
+    int64_t perm_mul;       // block b takes point (b perm_mul) mod n; set by the launch
 };
 
 struct DetectGradParams {
