@@ -522,10 +522,12 @@ __global__ __launch_bounds__(256, (LPP == 64 && !IM) ? 6 : 1) void k_track_run(T
                     }
                 }
                 // the d rows of the model's system carry (1 + m) = ga / Ts; the unscaled system
-                // solved here gives (1 + m) d
-                const float k = ga / Ts;
-                sx = x[0] / k;
-                sy = x[1] / k;
+                // solved here gives (1 + m) d, scaled back by Ts / ga (one reciprocal: correctly
+                // rounded divisions cost about ten instructions each; ga = 0 still gives a
+                // non-finite step)
+                const float ik = Ts * __builtin_amdgcn_rcpf(ga);
+                sx = x[0] * ik;
+                sy = x[1] * ik;
                 sa = x[2];
                 sb = x[3];
             } else {
