@@ -833,7 +833,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the tracker shards by pairs or point ranges with no "
-              "exchange in the forward pass, and this build runs on a single MI355X (use --gpus 1).",
+              "exchange in the forward pass, and the benchmark runs on a single MI355X (use --gpus 1).",
               file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration_mib:

@@ -37,7 +37,7 @@ extern "C" {
 #define DGF_OK 0
 #define DGF_ERR_INVALID_ARG (-1) /* null pointer, bad size, bad dtype, bad pitch, ...          */
 #define DGF_ERR_CAPACITY (-2)    /* output capacity smaller than the number of results          */
-#define DGF_ERR_UNSUPPORTED (-3) /* valid request outside what this build implements          */
+#define DGF_ERR_UNSUPPORTED (-3) /* valid request outside what the library implements         */
 #define DGF_ERR_HIP (-4)         /* a HIP runtime call or kernel launch failed                   */
 #define DGF_ERR_WORKSPACE (-5)   /* workspace null or smaller than dgf_track_workspace_bytes()   */
 #define DGF_ERR_SCRATCH (-6)     /* input larger than the static scratch of dgf_track_static     */

@@ -763,7 +763,7 @@ hipError_t launch_detect_backward(const DetectGradParams &G, hipStream_t st);
 hipError_t launch_track_adjoint(const AdjParams &A, int dtype, hipStream_t st);
 void fill_adjoint_constants(AdjParams &A, const dgf_track_opts &o);
 
-// Tracker flags this build implements, and those that need the row-run kernel.
+// Tracker flags the library implements, and those that need the row-run kernel.
 constexpr int32_t kTrackFlags = DGF_TRACK_ILLUM | DGF_TRACK_CROSS | DGF_TRACK_GLOBAL;
 constexpr int32_t kRowRunFlags = DGF_TRACK_ILLUM | DGF_TRACK_CROSS | DGF_TRACK_GLOBAL;
 
