@@ -9,12 +9,16 @@ pairs.  Both sides track the oracle's points and interpolate the oracle's tracks
     point both sides report CONVERGED within 1e-3 px; statuses differ on at most max(1, 0.1 %)
     per trial, and agree on at least 99.9 % of all such points over the sweep;
   * tracking with hard thresholding, the illumination model or a 3 x 3 support: at most
-    max(3, 1 %) of the points both sides report CONVERGED lie further apart, statuses differ on
-    at most max(3, 2 %) per trial; over the sweep statuses agree on at least 99.9 % (99.8 % for
-    hard thresholding with the illumination model).  A discontinuous weight, a gain near its
-    acceptance bound trading off against the motion, or a nine-pixel system lets FP32 and FP64
-    iterations settle at different fixed points (a 5,000-trial sweep found at most 9 such points
-    in one trial, none with Hampel or L2 alone at supports of 5 and up);
+    max(3, 1 %) of the points both sides report CONVERGED lie further apart; statuses differ on
+    at most max(3, 2 %) of the points whose coarse levels all stopped on the step test in the
+    oracle (determined paths, as in tests/parity.py) and on at most 5 % of all points per trial;
+    over the sweep statuses agree on at least 99.9 % of the determined paths (99.8 % for hard
+    thresholding with the illumination model) and on at least 99.5 % of all points.  A discontinuous weight, a gain near its acceptance bound trading off
+    against the motion, or a nine-pixel system lets FP32 and FP64 iterations settle at different
+    fixed points (a 5,000-trial sweep found at most 9 such points in one trial, none with Hampel
+    or L2 alone at supports of 5 and up), and a coarse level that runs out of iterations hands on
+    an iterate that then depends on rounding (with the illumination model on a 5 x 5 support and
+    15 iterations, 15 of 179 such points settled differently, 2 of the 437 others);
   * dense interpolation (frames up to 60,000 pixels): cells and neighbour lists exact.
 A second sweep (120 trials) covers the RLOF(IM-GM) options; its bars are at _trial_options."""
 import numpy as np
@@ -77,18 +81,26 @@ def _trial(rng, t, tally):
     F, S = dgf.track(a, b, Pg, levels, s, iters, opts=dgf.TrackOpts(illum=illum, **MODES[mode]))
     torch.cuda.synchronize()
     gF, gS = F.cpu().numpy().astype(np.float64), S.cpu().numpy()
-    oF, oS = oracle.track(I0, I1, Pn.astype(np.float64), levels, s, iters, illum=illum, **MODES[mode])[:2]
+    oF, oS, oIt = oracle.track(I0, I1, Pn.astype(np.float64), levels, s, iters, illum=illum, return_iters=True,
+                               **MODES[mode])[:3]
     both = (gS == 0) & (oS == 0)
     bad = int((np.abs(gF[both] - oF[both]).max(1) > 1e-3).sum()) if both.any() else 0
     differ = int((gS != oS).sum())
-    print(f"  n={n} both={int(both.sum())} far={bad} status_differ={differ}", flush=True)
+    # determined paths: every coarse level stopped on the step test in the oracle
+    det = np.all(np.asarray(oIt).reshape(n, -1)[:, :-1] < iters, axis=1)
+    differ_det = int(((gS != oS) & det).sum())
+    print(f"  n={n} both={int(both.sum())} far={bad} status_differ={differ} "
+          f"(determined paths {int(det.sum())}: {differ_det})", flush=True)
     cls = ("illum " if illum else "") + ("hard" if mode == 2 else ("s3" if s == 3 else "smooth"))
-    tot = tally.setdefault(cls, [0, 0])
+    tot = tally.setdefault(cls, [0, 0, 0, 0])
     tot[0] += n
     tot[1] += differ
+    tot[2] += int(det.sum())
+    tot[3] += differ_det
     if illum or mode == 2 or s == 3:
         assert bad <= max(3, 0.01 * both.sum()), tag
-        assert differ <= max(3, 0.02 * n), tag
+        assert differ_det <= max(3, 0.02 * int(det.sum())), tag
+        assert differ <= max(3, 0.05 * n), tag
     else:
         assert bad == 0, tag
         assert differ <= max(1, 0.001 * n), tag
@@ -108,10 +120,16 @@ def test_randomised_sweep():
     tally = {}
     for t in range(300):
         _trial(rng, t, tally)
-    for cls, (n, differ) in sorted(tally.items()):
+    for cls, (n, differ, n_det, differ_det) in sorted(tally.items()):
         agree = 1.0 - differ / max(n, 1)
-        print(f"{cls}: {n} points, statuses agree on {agree:.5f}", flush=True)
-        assert agree >= (0.998 if cls == "illum hard" else 0.999), cls
+        agree_det = 1.0 - differ_det / max(n_det, 1)
+        print(f"{cls}: {n} points, statuses agree on {agree:.5f} ({agree_det:.5f} on {n_det} determined paths)",
+              flush=True)
+        if cls == "smooth":
+            assert agree >= 0.999, cls
+        else:
+            assert agree_det >= (0.998 if cls == "illum hard" else 0.999), cls
+            assert agree >= 0.995, cls
 
 
 def _corner_motion(A, W, H):
